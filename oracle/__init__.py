@@ -1,0 +1,139 @@
+"""Reference oracle for the overdecomposed 3D Jacobi hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package.  The product library
+(``paper_2605_12734_amd``) never imports it and shares no code with it.
+
+It wraps ``jacobi_oracle.c`` (plain C, fp64/fp32, no fusion, no blocking):
+the undecomposed Jacobi iteration over one global padded grid that every
+overdecomposition of the grid must reproduce exactly (Section III: chares
+only change how the work is mapped, not what it computes; Section V,
+Jacobi2D: Jacobi iterations with halo exchange).  ``brute.py`` holds a
+pure-Python version of the same definition for tiny grids.
+
+Layout of every field handled here: a numpy array of shape
+(nz+2, ny+2, nx+2), x fastest, the ghost shell holding the Dirichlet values.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "jacobi_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libjacobi_oracle.so")
+_lib = None
+
+DEFAULT_BC = (1.0, 0.0, 0.0, 0.0, 0.0, 0.0)
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle in-tree with the flags its bit-exactness needs."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+               "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    u64, i64, dp = ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p
+    lib.oracle_splitmix64.argtypes = [u64, u64]
+    lib.oracle_splitmix64.restype = u64
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
+    lib.oracle_max_threads.restype = ctypes.c_int
+    for suf, ct in (("f64", ctypes.c_double), ("f32", ctypes.c_float)):
+        f = getattr(lib, "oracle_init_" + suf)
+        f.argtypes = [dp, i64, i64, i64, u64, ctypes.POINTER(ctypes.c_double)]
+        f.restype = None
+        f = getattr(lib, "oracle_sweep_" + suf)
+        f.argtypes = [dp, dp, i64, i64, i64]
+        f.restype = ct
+        f = getattr(lib, "oracle_jacobi_" + suf)
+        f.argtypes = [dp, dp, i64, i64, i64, i64, ctypes.c_double, i64,
+                      ctypes.POINTER(ctypes.c_double)]
+        f.restype = i64
+    _lib = lib
+    return lib
+
+
+def _suffix(dtype) -> str:
+    dt = np.dtype(dtype)
+    if dt == np.float64:
+        return "f64"
+    if dt == np.float32:
+        return "f32"
+    raise ValueError(f"oracle supports float64/float32, not {dt}")
+
+
+def _dims(n):
+    if np.isscalar(n):
+        return int(n), int(n), int(n)
+    nx, ny, nz = (int(v) for v in n)
+    return nx, ny, nz
+
+
+def splitmix64(seed: int, idx: int) -> int:
+    """idx-th output (0-based) of the SplitMix64 stream seeded with seed."""
+    return int(_load().oracle_splitmix64(seed & (2**64 - 1), idx))
+
+
+def set_threads(n: int) -> None:
+    _load().oracle_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(_load().oracle_max_threads())
+
+
+def init_field(n, dtype=np.float64, seed: int = 12734, bc=DEFAULT_BC) -> np.ndarray:
+    """Padded global field: SplitMix64 interior, Dirichlet ghost faces."""
+    nx, ny, nz = _dims(n)
+    U = np.empty((nz + 2, ny + 2, nx + 2), dtype=dtype)
+    bcarr = (ctypes.c_double * 6)(*[float(b) for b in bc])
+    getattr(_load(), "oracle_init_" + _suffix(dtype))(
+        U.ctypes.data, nx, ny, nz, seed & (2**64 - 1), bcarr)
+    return U
+
+
+def sweep(U: np.ndarray):
+    """One sweep of the padded field U; returns (V, residual)."""
+    U = np.ascontiguousarray(U)
+    nz, ny, nx = (s - 2 for s in U.shape)
+    V = U.copy()
+    r = getattr(_load(), "oracle_sweep_" + _suffix(U.dtype))(U.ctypes.data, V.ctypes.data, nx, ny, nz)
+    return V, float(r)
+
+
+def jacobi(U: np.ndarray, max_iters: int, tol: float = 0.0, check_every: int = 0):
+    """Iterate a copy of the padded field U.
+
+    Stops after iteration ``it`` when ``check_every > 0``,
+    ``it % check_every == 0`` and the residual is strictly below ``tol``,
+    or after ``max_iters``.  Returns (field, iterations, residual).
+    """
+    A = np.array(U, copy=True, order="C")
+    B = np.empty_like(A)
+    nz, ny, nx = (s - 2 for s in A.shape)
+    r = ctypes.c_double(0.0)
+    it = getattr(_load(), "oracle_jacobi_" + _suffix(A.dtype))(
+        A.ctypes.data, B.ctypes.data, nx, ny, nz, int(max_iters), float(tol),
+        int(check_every), ctypes.byref(r))
+    return A, int(it), float(r.value)
+
+
+def solve(n, dtype=np.float64, seed: int = 12734, iters: int = 100, bc=DEFAULT_BC,
+          tol: float = 0.0, check_every: int = 0):
+    """init_field + jacobi in one call: (field, iterations, residual)."""
+    return jacobi(init_field(n, dtype, seed, bc), iters, tol, check_every)
