@@ -1,0 +1,206 @@
+"""Benchmark: overdecomposed 3D 7-point Jacobi on one MI355X.
+
+Default workload (one "step" = one pass of the whole hot path):
+512^3 fp64 interior split into 4096 chares of 32^3 (16^3 chares), 200 Jacobi
+iterations with in-kernel halo exchange, graph-captured fused sweeps, residual
+of the last sweep read back.  value = GLUP/s (10^9 lattice-site updates/s).
+
+Prints ONE JSON line (metric, value, roofline of the sweep kernel measured
+live with HIP events on the grid's stream, the CPU oracle on a bounded sample
+of the same workload).  Extra legs (--sweep) add the ODF sweep, fp32, and the
+per-chare baseline.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--sweep]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBPS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2605_12734_amd", "csrc", "kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str, per_launch_alg_bytes: float):
+    """HBM bytes per sweep launch from committed rocprofv3 counter runs, if
+    they were taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "sweep_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    e = d.get(workload)
+    if not e or e.get("kernel_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def run_grid_leg(n, odf, dtype, exec_, iters, steps, warmup, tile=None):
+    import torch
+    import paper_2605_12734_amd as od
+
+    g = od.Grid(n, odf=odf, dtype=dtype, exec=exec_, tile=tile)
+    try:
+        plan = g.plan()
+        for _ in range(warmup):
+            g.iterate(iters)
+        g.residual()
+        torch.cuda.synchronize()
+        st = g.stream
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(st)
+        for _ in range(steps):
+            g.iterate(iters)
+        ev1.record(st)
+        r = g.residual()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dev_s = ev0.elapsed_time(ev1) * 1e-3
+    finally:
+        g.close()
+    lups = plan["interior"] * iters * steps
+    return {"wall_s": t1 - t0, "dev_s": dev_s, "glups": lups / (t1 - t0) / 1e9, "residual": r, "plan": plan,
+            "launch_s": dev_s / (iters * steps)}
+
+
+def cpu_baseline(n, dtype, budget_s=12.0, max_iters=12):
+    import numpy as np
+    import oracle
+
+    oracle.build(force=False)
+    nt = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    oracle.set_threads(nt)
+    U = oracle.init_field(n, np.float64 if dtype == "f64" else np.float32, 12734)
+    t = time.perf_counter()
+    oracle.jacobi(U, 1)
+    one = time.perf_counter() - t
+    iters = max(1, min(max_iters, int(budget_s / max(one, 1e-3))))
+    t = time.perf_counter()
+    oracle.jacobi(U, iters)
+    dt = time.perf_counter() - t
+    lups = (n ** 3) * iters
+    return {"value": lups / dt / 1e9, "unit": "GLUP/s", "cores": int(oracle.max_threads()), "kind": "oracle",
+            "sample": f"{n}^3 {dtype}, undecomposed, {iters} iterations ({dt:.1f} s), same seed and boundary"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--iters", type=int, default=200, help="Jacobi iterations per step")
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--odf", type=int, default=4096)
+    ap.add_argument("--dtype", default="f64")
+    ap.add_argument("--exec", default="graph")
+    ap.add_argument("--tile", default=None, help="tx,ty,tz")
+    ap.add_argument("--sweep", action="store_true", help="also run the ODF sweep and per-chare baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs one GPU's share of chares; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+    import paper_2605_12734_amd as od
+
+    tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
+    workload = f"{args.n}^3 {args.dtype} odf{args.odf} {args.exec}"
+    log(f"bench: {workload}, {args.iters} iterations/step, warmup {args.warmup}, steps {args.steps}")
+    leg = run_grid_leg(args.n, args.odf, args.dtype, args.exec, args.iters, args.steps, args.warmup, tile)
+    plan = leg["plan"]
+    bytes_per_iter = plan["bytes_per_iter"]
+    achieved = bytes_per_iter / leg["launch_s"] / 1e9
+    s = 8 if args.dtype == "f64" else 4
+    strict = 2 * s * plan["interior"] / leg["launch_s"] / 1e9
+    log(f"bench: {leg['glups']:.1f} GLUP/s wall, sweep {leg['launch_s'] * 1e6:.1f} us/launch, "
+        f"{achieved:.0f} GB/s algorithmic")
+
+    # STREAM-copy ceiling on the same device
+    nbytes = 1 << 30
+    copy_s = od.stream_copy_seconds(nbytes, iters=20)
+    copy_gbps = 2 * nbytes * 20 / copy_s / 1e9
+
+    extra = {}
+    if args.sweep:
+        rows = []
+        for dtype in ("f64", "f32"):
+            for odf in (8, 64, 512, 4096):
+                b = run_grid_leg(args.n, odf, dtype, "graph", args.iters, 2, 1)
+                pc_iters = 20 if odf <= 64 else (5 if odf <= 512 else 2)
+                p = run_grid_leg(args.n, odf, dtype, "per_chare", pc_iters, 1, 1)
+                bp = b["plan"]["bytes_per_iter"]
+                rows.append({"dtype": dtype, "odf": odf, "block": args.n // round(odf ** (1 / 3)),
+                             "batched_glups": round(b["glups"], 2),
+                             "batched_hbm_gbps": round(bp / b["launch_s"] / 1e9, 1),
+                             "batched_frac": round(bp / b["launch_s"] / 1e9 / PEAK_HBM_GBPS, 4),
+                             "per_chare_glups": round(p["glups"], 3),
+                             "per_chare_ms_per_iter": round(p["wall_s"] / pc_iters * 1e3, 3),
+                             "speedup": round(b["glups"] / p["glups"], 1)})
+                log("sweep:", rows[-1])
+        extra["odf_sweep"] = rows
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.n, args.dtype)
+        log(f"cpu baseline: {cpu}")
+
+    traffic = load_traffic(workload, bytes_per_iter)
+    out = {
+        "metric": "GLUP/s (batched, graph-captured fused sweep) at 512^3 fp64, ODF 4096",
+        "value": round(leg["glups"], 3),
+        "unit": "GLUP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(leg["wall_s"] / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic (SplitMix64 U[0,1) interior, Dirichlet 1 on x-, 0 elsewhere)",
+        "config": {"workload": f"{args.n}^3 {args.dtype} 7-point Jacobi, {plan['nchares']} chares of "
+                               f"{args.n // round(plan['nchares'] ** (1 / 3))}^3, {args.iters} iterations/step, "
+                               f"exec={args.exec}",
+                   "odf": plan["nchares"], "iters_per_step": args.iters, "tile": list(plan["tile"]),
+                   "exec": args.exec},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBPS, 4),
+                     "traffic": traffic,
+                     "kernel": "k_sweep (fused 7-point sweep + halo exchange)",
+                     "alg_bytes_per_launch": bytes_per_iter,
+                     "avg_launch_us": round(leg["launch_s"] * 1e6, 2),
+                     "strict_frac_2s_per_lup": round(strict / PEAK_HBM_GBPS, 4),
+                     "stream_copy_gbps": round(copy_gbps, 1)},
+        "cpu_baseline": cpu,
+        "residual": leg["residual"],
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

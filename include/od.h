@@ -1,0 +1,258 @@
+/*
+ * od.h -- C ABI of the overdecomposed 3D Jacobi library (libod.so).
+ *
+ * The library runs one GPU's share of an overdecomposed structured-grid
+ * computation: a 3D grid split into many more blocks ("chares") than GPUs
+ * (Section III, "Managing Overdecomposition"), each chare holding its own
+ * storage and doing a 7-point Jacobi sweep (the stencil workload of
+ * Section V, Jacobi2D, extended to three dimensions) with halo pack,
+ * exchange and unpack between neighbouring chares done device-side
+ * (Section IV, intra-process transport: device-to-device, no host round
+ * trip).
+ *
+ * Arithmetic (identical in every execution mode, every decomposition and
+ * every tuned variant):
+ *   u'(i,j,k) = (((((u[i-1] + u[i+1]) + u[j-1]) + u[j+1]) + u[k-1]) + u[k+1]) / 6
+ * each addition rounded to the grid's type, the division correctly rounded,
+ * no fused multiply-add, no flush of subnormals.  The residual of a sweep
+ * is max over interior points of |u' - u|.
+ *
+ * Conventions for every function:
+ *   - Return value: OD_OK (0) or a negative od_status.  No exception or
+ *     signal crosses this boundary.  On error, od_last_error() gives a
+ *     message (thread-local, valid until the next od_* call on the thread).
+ *   - Device memory is caller-owned: the workspace / arena pointers are
+ *     device allocations (e.g. from PyTorch) that the library carves up
+ *     and never frees.  The library itself allocates no device memory.
+ *   - Handles (od_grid*, od_server*) are owned by the library from the
+ *     create call until the matching destroy call.
+ *   - Streams are borrowed: `hip_stream` is a hipStream_t (NULL = the
+ *     default stream) that must outlive the handle.
+ *   - Global field layout (od_read / od_write): a dense array of the
+ *     grid's type with shape (nz+2, ny+2, nx+2), x fastest.  Interior point
+ *     (i,j,k), 0 <= i < nx, sits at ((k+1)*(ny+2) + (j+1))*(nx+2) + (i+1);
+ *     the shell at index -1 and n holds the Dirichlet values; shell edges
+ *     and corners are never read and read back as 0.
+ */
+#ifndef OD_H
+#define OD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    OD_OK = 0,
+    OD_EINVAL = -22,      /* bad argument, size or configuration            */
+    OD_ENOMEM = -12,      /* workspace / arena too small for the request    */
+    OD_EAGAIN = -11,      /* server queue full: retry later                 */
+    OD_ENOTREADY = -61,   /* request still queued or running                */
+    OD_ECANCELED = -125,  /* request cancelled (server shut down)           */
+    OD_ETIMEDOUT = -110,  /* a device-side wait exceeded its bound           */
+    OD_EHIP = -1000       /* HIP runtime error; message in od_last_error()  */
+} od_status;
+
+typedef enum { OD_F32 = 4, OD_F64 = 8 } od_dtype;   /* value = bytes per element */
+
+/* How od_iterate advances the grid (Section III; the per-chare mode is the
+ * paper's one-kernel-sequence-per-chare execution, the others are the
+ * batched forms). */
+typedef enum {
+    OD_PER_CHARE = 0,   /* per chare and iteration: pack kernel, D2D copies of
+                           the face messages, unpack kernel, sweep kernel, on
+                           a pool of non-blocking streams with events        */
+    OD_FUSED = 1,       /* one launch per iteration over every chare's tiles;
+                           halo exchange fused into the sweep               */
+    OD_GRAPH = 2,       /* OD_FUSED launches captured once in a hipGraph and
+                           replayed                                          */
+    OD_PERSISTENT = 3,  /* one cooperative launch for all n iterations with a
+                           device-wide barrier between iterations            */
+    OD_MSGDRIVEN = 4    /* one cooperative launch; each tile advances as soon
+                           as the tiles it reads halos from have finished the
+                           previous step (message-driven, no global barrier) */
+} od_exec;
+
+typedef struct {
+    int32_t origin[3];  /* global interior coordinates of the block's first cell */
+    int32_t extent[3];  /* cells along x, y, z (each >= 1)                   */
+} od_block;
+
+typedef struct {
+    int64_t n[3];         /* global interior extents nx, ny, nz (each >= 1)       */
+    int64_t block[3];     /* regular chare extents; {0,0,0} => derive from odf    */
+    int32_t odf;          /* chares on this GPU when block is {0,0,0}; a cube k^3
+                             splits k ways per dimension, otherwise a balanced
+                             3-factor split with the largest factor on z         */
+    const od_block* blocks; /* optional explicit (uneven, AMR-like) blocks that
+                               tile the domain exactly; overrides block/odf;
+                               origins/extents must share a granularity g with
+                               (nx/g)(ny/g)(nz/g) <= 2^26                         */
+    int32_t nblocks;
+    od_dtype dtype;
+    double bc[6];         /* Dirichlet values of faces x-,x+,y-,y+,z-,z+          */
+    uint64_t seed;        /* interior ~ U[0,1): value at global linear index
+                             g = (k*ny + j)*nx + i is the (g+1)-th SplitMix64
+                             output of `seed`, top 53 (f64) / 24 (f32) bits      */
+    od_exec exec;
+    int32_t tile[3];      /* tile shape (x, y, z) of the fused sweep; {0,0,0} =
+                             the built-in or autotuned default for the block shape */
+    /* Load imbalance: at every step, `imbalance_pct` percent of the chares
+     * (chosen per step from `seed`) re-run their sweep 1..imbalance_max_extra
+     * extra times.  A re-run recomputes the same values, so results do not
+     * change, only the time. 0 = off. */
+    int32_t imbalance_pct;
+    int32_t imbalance_max_extra;
+} od_config;
+
+struct od_grid;
+struct od_server;
+
+/* Defaults: n = 64^3, odf = 8, f64, bc = {1,0,0,0,0,0}, seed 12734,
+ * OD_GRAPH, everything else 0. */
+void od_config_default(od_config* cfg);
+
+/* Bytes of caller-owned device workspace od_create needs for cfg. */
+od_status od_workspace_bytes(const od_config* cfg, size_t* bytes);
+
+/* Decompose, build halo maps, carve the workspace, upload descriptors and
+ * initialise the field on the device (interior from seed, shell from bc).
+ * Synchronises the stream before returning.  `dev_workspace` must be at
+ * least od_workspace_bytes() bytes and 256-byte aligned. */
+od_status od_create(const od_config* cfg, void* hip_stream, void* dev_workspace,
+                    size_t workspace_bytes, struct od_grid** out);
+
+/* Enqueue n >= 0 Jacobi iterations on the grid's stream (asynchronous, like
+ * a kernel launch).  Allocates nothing and does not synchronise, except in
+ * OD_PER_CHARE mode whose host loop itself issues the work. */
+od_status od_iterate(struct od_grid* g, int64_t n);
+
+/* Synchronise the stream; *r = residual of the last sweep (0 before any). */
+od_status od_residual(struct od_grid* g, double* r);
+
+/* Iterations done since od_create (or the last od_write). */
+od_status od_iterations(struct od_grid* g, int64_t* iters);
+
+/* Copy the whole padded global field (layout above) to host memory; syncs. */
+od_status od_read(struct od_grid* g, void* host_dst, size_t bytes);
+
+/* Set interior and Dirichlet shell from a padded global host array; resets
+ * the iteration count and residual; syncs. */
+od_status od_write(struct od_grid* g, const void* host_src, size_t bytes);
+
+/* Read `count` interior values at global linear interior indices
+ * idx[i] = (k*ny + j)*nx + i into host_dst (grid type); syncs. */
+od_status od_read_points(struct od_grid* g, const int64_t* idx, int64_t count, void* host_dst);
+
+/* Host-only plan: decomposition, tiles and halo maps for cfg, with no
+ * device work and no workspace.  The handle supports od_plan,
+ * od_tile_info_get, od_chare_get and od_destroy; the other calls return
+ * OD_EINVAL on it. */
+od_status od_plan_create(const od_config* cfg, struct od_grid** out);
+
+/* Introspection of the decomposition (host data, no device access):
+ * chares, tiles, and algorithmic bytes moved per iteration
+ * (s * (2*interior + ghost cells read from other chares)). */
+typedef struct {
+    int32_t nchares, ntiles, npseudo;
+    int64_t interior, halo_cells;   /* halo_cells: ghost cells filled from other chares */
+    int64_t bytes_per_iter;         /* algorithmic HBM bytes of one sweep            */
+    int32_t tile[3];                /* tile shape in use                              */
+    int32_t grid_wgs;               /* workgroups of the persistent / msg-driven launch */
+} od_plan_info;
+od_status od_plan(struct od_grid* g, od_plan_info* info);
+
+/* Per-tile descriptor export for host-side checks (brute-force halo maps):
+ * for tile t: its chare, origin in the chare, extent, and for each face
+ * (x-,x+,y-,y+,z-,z+) the source it reads its ghost slab from:
+ * src_kind 0 = a chare (src = chare id), 1 = a Dirichlet face of the domain
+ * (src = face 0..5); src_origin = the global interior coordinates of the
+ * ghost slab's first cell. */
+typedef struct {
+    int32_t chare, origin[3], extent[3];
+    int32_t src_kind[6], src[6], src_origin[6][3];
+} od_tile_info;
+od_status od_tile_info_get(struct od_grid* g, int32_t t, od_tile_info* out);
+
+/* Chare geometry: origin and extent of chare c. */
+od_status od_chare_get(struct od_grid* g, int32_t c, od_block* out);
+
+/* Wait for all work on the grid's stream, release host-side resources.
+ * The workspace is not touched afterwards and stays the caller's. */
+od_status od_destroy(struct od_grid* g);
+
+/* Measured HBM copy ceiling: copy `bytes` between two caller-owned device
+ * buffers `iters` times on `hip_stream` with the library's streaming copy
+ * kernel; *seconds = elapsed time of the copies (hipEvents). */
+od_status od_stream_copy(void* hip_stream, void* dst, const void* src, size_t bytes,
+                         int32_t iters, double* seconds);
+
+/* Time n iterations with hipEvents on the grid's stream: *seconds = elapsed
+ * device time between events recorded before and after od_iterate(n). */
+od_status od_time_iterate(struct od_grid* g, int64_t n, double* seconds);
+
+/* -------------------------------------------------------------------------
+ * Autotuning (tile shape search).  Every candidate computes the same
+ * arithmetic; only the tile shape and launch shape differ.  Times each
+ * candidate with `iters` fused iterations on the grid itself (its field is
+ * restored afterwards from a device copy kept in the workspace's spare
+ * parity), picks the fastest and switches the grid to it.
+ * `out_tile` receives the chosen shape. */
+od_status od_autotune(struct od_grid* g, int32_t iters, int32_t out_tile[3]);
+
+/* -------------------------------------------------------------------------
+ * Serving: independent Jacobi solves of different sizes admitted as they
+ * arrive under a device-memory budget and run concurrently by the
+ * message-driven device scheduler (continuous batching).  Each solve's
+ * result equals that of the same solve run alone.
+ */
+typedef struct {
+    int64_t n;            /* cubic interior extent                       */
+    od_dtype dtype;
+    int32_t odf;          /* chares for this solve (1, 8, 64, ...)       */
+    double tol;           /* stop when residual < tol at a check step    */
+    int64_t max_iters;    /* hard cap                                    */
+    int32_t check_every;  /* residual checked at multiples of this       */
+    uint64_t seed;
+    double bc[6];
+} od_request;
+
+enum { OD_REQ_QUEUED = 0, OD_REQ_RUNNING = 1, OD_REQ_DONE = 2, OD_REQ_CANCELED = 3 };
+
+typedef struct {
+    int32_t state;
+    int64_t iters;       /* iterations done when it stopped             */
+    double residual;     /* residual of its last sweep                  */
+    double t_submit, t_admit, t_done;   /* host monotonic seconds       */
+} od_info;
+
+/* `dev_arena` of `arena_bytes` is the memory budget for resident solves;
+ * at most `max_slots` solves are resident at once. */
+od_status od_server_create(void* hip_stream, void* dev_arena, size_t arena_bytes,
+                           int32_t max_slots, struct od_server** out);
+/* Bytes a request needs in the arena. */
+od_status od_request_bytes(const od_request* req, size_t* bytes);
+/* Queue a request; never blocks.  OD_ENOMEM if it can never fit the arena,
+ * OD_EAGAIN if the submission queue is full, OD_EINVAL for bad fields. */
+od_status od_submit(struct od_server* s, const od_request* req, uint64_t* ticket);
+/* Drive the server: admit queued requests that fit, run one scheduling
+ * epoch on the device, retire finished solves.  Returns after the epoch. */
+od_status od_server_step(struct od_server* s, int32_t* active, int32_t* queued);
+/* State of a request; OD_ENOTREADY while queued or running. */
+od_status od_poll(struct od_server* s, uint64_t ticket, od_info* out);
+/* Copy a finished request's padded global field to host and release it. */
+od_status od_fetch(struct od_server* s, uint64_t ticket, void* host_dst, size_t bytes);
+od_status od_server_destroy(struct od_server* s);
+
+/* Thread-local message of the last failing call on this thread. */
+const char* od_last_error(void);
+
+/* Library version string. */
+const char* od_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OD_H */

@@ -57,6 +57,9 @@ def _load():
         f = getattr(lib, "oracle_init_" + suf)
         f.argtypes = [dp, i64, i64, i64, u64, ctypes.POINTER(ctypes.c_double)]
         f.restype = None
+        f = getattr(lib, "oracle_init_box_" + suf)
+        f.argtypes = [dp, i64, i64, i64, u64, ctypes.POINTER(ctypes.c_double), i64, i64, i64, i64, i64, i64]
+        f.restype = None
         f = getattr(lib, "oracle_sweep_" + suf)
         f.argtypes = [dp, dp, i64, i64, i64]
         f.restype = ct
@@ -137,3 +140,24 @@ def solve(n, dtype=np.float64, seed: int = 12734, iters: int = 100, bc=DEFAULT_B
           tol: float = 0.0, check_every: int = 0):
     """init_field + jacobi in one call: (field, iterations, residual)."""
     return jacobi(init_field(n, dtype, seed, bc), iters, tol, check_every)
+
+
+def point_values(n, points, iters: int, dtype=np.float64, seed: int = 12734, bc=DEFAULT_BC):
+    """Values after `iters` sweeps at interior points (i, j, k) of the global
+    grid, each from a sub-box around the point: by domain of dependence a
+    point's value after t sweeps depends only on cells within Chebyshev
+    distance t, so the box's own shell (distance t+1, or the Dirichlet shell)
+    may stay at its initial values."""
+    nx, ny, nz = _dims(n)
+    bcarr = (ctypes.c_double * 6)(*[float(b) for b in bc])
+    out = []
+    for (i, j, k) in points:
+        lo = [max(0, v - iters) for v in (i, j, k)]
+        hi = [min(m - 1, v + iters) for v, m in zip((i, j, k), (nx, ny, nz))]
+        bx, by, bz = (h - l + 1 for h, l in zip(hi, lo))
+        U = np.empty((bz + 2, by + 2, bx + 2), dtype=dtype)
+        getattr(_load(), "oracle_init_box_" + _suffix(dtype))(
+            U.ctypes.data, nx, ny, nz, seed & (2**64 - 1), bcarr, lo[0], lo[1], lo[2], bx, by, bz)
+        V, _, _ = jacobi(U, iters)
+        out.append(V[k - lo[2] + 1, j - lo[1] + 1, i - lo[0] + 1])
+    return np.array(out, dtype=dtype)

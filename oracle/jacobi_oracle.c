@@ -123,6 +123,45 @@ void oracle_init_##SUF(T* U, int64_t nx, int64_t ny, int64_t nz, uint64_t seed, 
             }                                                                                \
 }                                                                                            \
                                                                                              \
+/* Padded sub-box of the initial global field: box interior cells are the   \
+ * global interior cells (ox..ox+bx-1, ...), the box shell holds whatever    \
+ * the global padded field holds there (initial values inside the domain,   \
+ * Dirichlet faces outside, zero on shell edges).  Used to evaluate single  \
+ * outputs by domain of dependence. */                                       \
+void oracle_init_box_##SUF(T* U, int64_t nx, int64_t ny, int64_t nz, uint64_t seed,        \
+                           const double bc[6], int64_t ox, int64_t oy, int64_t oz,           \
+                           int64_t bx, int64_t by, int64_t bz)                               \
+{                                                                                            \
+    for (int64_t k = -1; k <= bz; ++k)                                                       \
+        for (int64_t j = -1; j <= by; ++j)                                                   \
+            for (int64_t i = -1; i <= bx; ++i) {                                             \
+                int64_t gi = ox + i, gj = oy + j, gk = oz + k;                               \
+                int out = (gi < 0 || gi >= nx) + (gj < 0 || gj >= ny) + (gk < 0 || gk >= nz);\
+                T v;                                                                         \
+                if (gi < -1 || gi > nx || gj < -1 || gj > ny || gk < -1 || gk > nz) {        \
+                    v = (T)0;                                                                \
+                } else if (out == 0) {                                                       \
+                    uint64_t g = (uint64_t)((gk * ny + gj) * nx + gi);                       \
+                    v = UNIF(oracle_splitmix64(seed, g));                                    \
+                } else if (out >= 2) {                                                       \
+                    v = (T)0;                                                                \
+                } else if (gi < 0) {                                                         \
+                    v = (T)bc[0];                                                            \
+                } else if (gi >= nx) {                                                       \
+                    v = (T)bc[1];                                                            \
+                } else if (gj < 0) {                                                         \
+                    v = (T)bc[2];                                                            \
+                } else if (gj >= ny) {                                                       \
+                    v = (T)bc[3];                                                            \
+                } else if (gk < 0) {                                                         \
+                    v = (T)bc[4];                                                            \
+                } else {                                                                     \
+                    v = (T)bc[5];                                                            \
+                }                                                                            \
+                U[PIDX(i, j, k, bx, by)] = v;                                                \
+            }                                                                                \
+}                                                                                            \
+                                                                                             \
 /* One Jacobi sweep U -> V over the interior; V's ghost shell is not touched. \
  * Returns max |V - U| over the interior. */                                 \
 T oracle_sweep_##SUF(const T* U, T* V, int64_t nx, int64_t ny, int64_t nz)                 \

@@ -1,0 +1,822 @@
+// HIP kernels of libod for gfx950 (CDNA4, wave64).
+//
+// The hot kernel is the fused 7-point sweep: one workgroup owns a tile of a
+// chare (TX x TY cells in the xy-plane, nz planes along z) and marches z
+// with a register-resident column (plane below / current / above) while the
+// current plane, plus its x/y halo, is staged in LDS.  Halo cells are read
+// straight from wherever they live: the chare itself, the neighbouring
+// chare's storage (the device-side halo exchange between chares on the same
+// GPU, Section IV intra-process path, fused into the compute kernel as in
+// the kernel-fusion mitigation cited in Section I) or a Dirichlet face.
+// Each addition and the final division by 6 are individually rounded
+// (compiled with -ffp-contract=off), in the order x-, x+, y-, y+, z-, z+.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace od {
+
+// ---------------------------------------------------------------------------
+// helpers
+
+template <typename T>
+struct V16;
+template <>
+struct V16<double> {
+    typedef double __attribute__((ext_vector_type(2))) t;
+    static constexpr int N = 2;
+};
+template <>
+struct V16<float> {
+    typedef float __attribute__((ext_vector_type(4))) t;
+    static constexpr int N = 4;
+};
+
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): idx-th output of the
+// stream seeded with `seed` is the finaliser applied to seed + (idx+1)*gamma.
+__device__ __forceinline__ uint64_t sm64(uint64_t seed, uint64_t idx) {
+    uint64_t z = seed + (idx + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+template <typename T>
+__device__ __forceinline__ T unit_from_bits(uint64_t h);
+template <>
+__device__ __forceinline__ double unit_from_bits<double>(uint64_t h) {
+    return (double)(h >> 11) * 0x1.0p-53;
+}
+template <>
+__device__ __forceinline__ float unit_from_bits<float>(uint64_t h) {
+    return (float)(uint32_t)(h >> 40) * 0x1.0p-24f;
+}
+
+__device__ __forceinline__ int32_t owner_of(const LookupDev& lk, int64_t x, int64_t y, int64_t z) {
+    if (lk.regular) {
+        return (lk.cidx[2][z] * lk.k[1] + lk.cidx[1][y]) * lk.k[0] + lk.cidx[0][x];
+    }
+    const int64_t g = lk.gran;
+    return lk.owner[((z / g) * lk.og[1] + (y / g)) * lk.og[0] + (x / g)];
+}
+
+// Workgroup max of a non-negative residual, folded into *slot as the bit
+// pattern of a double (monotone for non-negative values).
+template <typename T, int NT>
+__device__ __forceinline__ void wg_residual(T r, unsigned long long* slot, T* red) {
+    for (int off = 32; off > 0; off >>= 1) {
+        T o = __shfl_xor(r, off, 64);
+        r = o > r ? o : r;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = r;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T m = red[0];
+        for (int w = 1; w < NT / 64; ++w) m = red[w] > m ? red[w] : m;
+        atomicMax(slot, (unsigned long long)__double_as_longlong((double)m));
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// fused sweep of one tile
+
+template <typename T, int TX, int TY>
+struct SW {
+    static constexpr int VX = V16<T>::N;
+    static constexpr int LX = TX / VX;        // threads along x
+    static constexpr int NT = LX * TY;        // threads per workgroup
+    static constexpr int LP = TX + 2 * VX;    // LDS row pitch (interior starts at VX: 16 B aligned)
+    static constexpr int LR = TY + 2;         // LDS rows incl. y halo
+    static constexpr int LDS = 2 * LP * LR;   // two plane buffers
+    static_assert(TX % VX == 0, "TX must be a multiple of the vector width");
+    static_assert(NT % 64 == 0 && NT <= 1024, "threads must be whole waves");
+};
+
+template <typename T, int TX, int TY>
+__device__ __forceinline__ T sweep_tile(T* __restrict__ arena, const BlockDev* __restrict__ blocks,
+                                        const TileDev& t, const int parity, T* __restrict__ lds) {
+    using S = SW<T, TX, TY>;
+    using VT = typename V16<T>::t;
+    constexpr int VX = S::VX;
+    const int tid = threadIdx.x;
+    const int lx = tid % S::LX;
+    const int ly = tid / S::LX;
+    const int x = lx * VX;
+    const int nx = t.nx, ny = t.ny, nz = t.nz;
+    const bool rowok = ly < ny;
+    int nv = nx - x;
+    nv = nv < 0 ? 0 : (nv > VX ? VX : nv);
+    if (!rowok) nv = 0;
+    const bool act = nv > 0;
+
+    // Block descriptors are read field by field straight from global memory
+    // (a dynamically indexed local copy would be placed in scratch).
+    const BlockDev* __restrict__ B = blocks + t.blk;
+    const int64_t pz = B->pz;
+    const int64_t obase = (int64_t)(t.x0 + x) + (int64_t)(t.y0 + ly) * B->py + (int64_t)t.z0 * pz;
+    const T* own = arena + (parity ? B->off[1] : B->off[0]) + obase;
+    T* dst = arena + (parity ? B->off[0] : B->off[1]) + obase;
+
+    // Face sources: base pointer of the ghost slab cell next to tile-local
+    // (x, ly, 0) (normal coordinate fixed) and the source's plane pitch.
+    auto face = [&](const FaceDev& f, int64_t dx, int64_t dy, int64_t* fpz) -> const T* {
+        const BlockDev* __restrict__ F = blocks + f.src;
+        *fpz = F->pz;
+        return arena + (parity ? F->off[1] : F->off[0]) + (f.sx + dx) + (int64_t)(f.sy + dy) * F->py +
+               (int64_t)f.sz * F->pz;
+    };
+    int64_t zm_pz, zp_pz, xm_pz, xp_pz, ym_pz, yp_pz;
+    const T* zmp = face(t.f[4], x, ly, &zm_pz);
+    const T* zpp = face(t.f[5], x, ly, &zp_pz);
+    const T* xmp = face(t.f[0], 0, ly, &xm_pz);
+    const T* xpp = face(t.f[1], 0, ly, &xp_pz);
+    const T* ymp = face(t.f[2], x, 0, &ym_pz);
+    const T* ypp = face(t.f[3], x, 0, &yp_pz);
+    (void)zm_pz;
+    (void)zp_pz;
+
+    const bool do_xm = rowok && lx == 0;
+    const bool do_xp = rowok && lx == (nx - 1) / VX;
+    const bool do_ym = act && ly == 0;
+    const bool do_yp = act && ly == ny - 1;
+
+    auto L = [&](int b, int r, int c) -> T& { return lds[(b * S::LR + r) * S::LP + c]; };
+    auto ldv = [](const T* p) -> VT { return *reinterpret_cast<const VT*>(p); };
+    auto plane = [&](int zz) -> const T* { return zz < 0 ? zmp : (zz >= nz ? zpp : own + (int64_t)zz * pz); };
+
+    VT below = {}, cur = {}, above = {}, nxt = {};
+    T hxm = 0, hxp = 0, hxm_n = 0, hxp_n = 0;
+    T hym[VX], hyp[VX], hym_n[VX], hyp_n[VX];
+#pragma unroll
+    for (int i = 0; i < VX; ++i) hym[i] = hyp[i] = hym_n[i] = hyp_n[i] = 0;
+
+    auto ld_halo = [&](int zz, T& a, T& b, T* ym, T* yp) {
+        if (do_xm) a = xmp[(int64_t)zz * xm_pz];
+        if (do_xp) b = xpp[(int64_t)zz * xp_pz];
+        if (do_ym) {
+#pragma unroll
+            for (int i = 0; i < VX; ++i)
+                if (i < nv) ym[i] = ymp[(int64_t)zz * ym_pz + i];
+        }
+        if (do_yp) {
+#pragma unroll
+            for (int i = 0; i < VX; ++i)
+                if (i < nv) yp[i] = ypp[(int64_t)zz * yp_pz + i];
+        }
+    };
+
+    if (act) {
+        below = ldv(zmp);
+        cur = ldv(own);
+    }
+    ld_halo(0, hxm, hxp, hym, hyp);
+    if (act) above = ldv(plane(1));
+
+    T r = 0;
+    for (int z = 0; z < nz; ++z) {
+        const int b = z & 1;
+        // prefetch the next plane and its halo while this one is computed
+        if (z + 1 < nz) ld_halo(z + 1, hxm_n, hxp_n, hym_n, hyp_n);
+        if (act && z + 2 <= nz) nxt = ldv(plane(z + 2));
+
+        // stage plane z with its x/y halo
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < VX; ++i)
+                if (i < nv) L(b, ly + 1, VX + x + i) = cur[i];
+        }
+        if (do_xm) L(b, ly + 1, VX - 1) = hxm;
+        if (do_xp) L(b, ly + 1, VX + nx) = hxp;
+        if (do_ym) {
+#pragma unroll
+            for (int i = 0; i < VX; ++i)
+                if (i < nv) L(b, 0, VX + x + i) = hym[i];
+        }
+        if (do_yp) {
+#pragma unroll
+            for (int i = 0; i < VX; ++i)
+                if (i < nv) L(b, ny + 1, VX + x + i) = hyp[i];
+        }
+        __syncthreads();
+
+        if (act) {
+            VT out;
+#pragma unroll
+            for (int i = 0; i < VX; ++i) {
+                T s = L(b, ly + 1, VX + x + i - 1);
+                s = s + L(b, ly + 1, VX + x + i + 1);
+                s = s + L(b, ly, VX + x + i);
+                s = s + L(b, ly + 2, VX + x + i);
+                s = s + below[i];
+                s = s + above[i];
+                const T v = s / (T)6;
+                out[i] = v;
+                if (i < nv) {
+                    T d = v - cur[i];
+                    if (d < (T)0) d = -d;
+                    if (d > r) r = d;
+                }
+            }
+            T* o = dst + (int64_t)z * pz;
+            if (nv == VX) {
+                *reinterpret_cast<VT*>(o) = out;
+            } else {
+#pragma unroll
+                for (int i = 0; i < VX; ++i)
+                    if (i < nv) o[i] = out[i];
+            }
+        }
+        below = cur;
+        cur = above;
+        above = nxt;
+        hxm = hxm_n;
+        hxp = hxp_n;
+#pragma unroll
+        for (int i = 0; i < VX; ++i) {
+            hym[i] = hym_n[i];
+            hyp[i] = hyp_n[i];
+        }
+    }
+    __syncthreads();   // LDS planes are reused by the next tile
+    return r;
+}
+
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__((TX / V16<T>::N) * TY)
+k_sweep(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDev* __restrict__ tiles,
+        int parity, unsigned long long* __restrict__ res, int zero_lo, int zero_hi,
+        const uint8_t* __restrict__ extra) {
+    using S = SW<T, TX, TY>;
+    __shared__ T lds[S::LDS];
+    __shared__ T red[S::NT / 64];
+    if (blockIdx.x == 0)
+        for (int s = zero_lo + (int)threadIdx.x; s < zero_hi; s += S::NT) res[2 * s + parity] = 0ull;
+    const TileDev t = tiles[blockIdx.x];
+    const int reps = 1 + (extra ? (int)extra[t.blk] : 0);
+    T r = 0;
+    for (int rep = 0; rep < reps; ++rep) r = sweep_tile<T, TX, TY>(arena, blocks, t, parity, lds);
+    wg_residual<T, S::NT>(r, &res[2 * t.rslot + (parity ^ 1)], red);
+}
+
+// ---------------------------------------------------------------------------
+// device-wide barrier for cooperative launches: every thread fences at agent
+// scope (its stores become visible across XCDs), one thread per workgroup
+// arrives on a counter and waits for the generation to change.  The wait is
+// bounded; on timeout the error flag is raised and every workgroup leaves.
+
+__device__ __forceinline__ bool grid_barrier(unsigned int* bar, unsigned int* err, int64_t wait_ticks) {
+    __shared__ int ok;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned int nb = gridDim.x;
+        const unsigned int gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned int arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        int good = 1;
+        if (arrived == nb - 1) {
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const int64_t t0 = wall_clock64();
+            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(2);
+                if (wall_clock64() - t0 > wait_ticks ||
+                    __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                    __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    good = 0;
+                    break;
+                }
+            }
+        }
+        ok = good;
+    }
+    __syncthreads();
+    __threadfence();
+    return ok != 0;
+}
+
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__((TX / V16<T>::N) * TY)
+k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDev* __restrict__ tiles,
+             int32_t ntiles, int parity, int64_t iters, unsigned long long* __restrict__ res, int32_t nres,
+             unsigned int* bar, unsigned int* err, const uint8_t* __restrict__ extra, int32_t extra_period,
+             int32_t nchares, int64_t iter_base, int64_t wait_ticks) {
+    using S = SW<T, TX, TY>;
+    __shared__ T lds[S::LDS];
+    __shared__ T red[S::NT / 64];
+    for (int64_t it = 0; it < iters; ++it) {
+        const int p = parity ^ (int)(it & 1);
+        if (blockIdx.x == 0)
+            for (int s = (int)threadIdx.x; s < nres; s += S::NT) res[2 * s + p] = 0ull;
+        const uint8_t* ex = extra ? extra + (size_t)((iter_base + it) % extra_period) * nchares : nullptr;
+        T r = 0;
+        int slot = -1;
+        for (int32_t ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+            const TileDev t = tiles[ti];
+            const int reps = 1 + (ex ? (int)ex[t.blk] : 0);
+            T rr = 0;
+            for (int rep = 0; rep < reps; ++rep) rr = sweep_tile<T, TX, TY>(arena, blocks, t, p, lds);
+            if (slot >= 0 && slot != t.rslot) {
+                wg_residual<T, S::NT>(r, &res[2 * slot + (p ^ 1)], red);
+                r = 0;
+            }
+            slot = t.rslot;
+            r = rr > r ? rr : r;
+        }
+        if (slot >= 0) wg_residual<T, S::NT>(r, &res[2 * slot + (p ^ 1)], red);
+        if (it + 1 < iters) {
+            if (!grid_barrier(bar, err, wait_ticks)) return;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// message-driven scheduler: every workgroup owns the tiles w, w+G, w+2G, ...
+// (same XCD group as w) and repeatedly runs whichever owned tile is ready:
+// tile t may run step s+1 once every tile it reads halos from (and t itself)
+// has completed step s.  Because halo reads are symmetric, the same rule
+// guarantees nobody still reads the parity a tile overwrites.  Serving adds
+// per-solve check steps: at a check step the last finishing tile evaluates
+// the solve's residual and either stops the solve or opens the gate.
+
+__device__ __forceinline__ int32_t ld_acq(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__((TX / V16<T>::N) * TY) k_msgdriven(MsgArgs a) {
+    using S = SW<T, TX, TY>;
+    __shared__ T lds[S::LDS];
+    __shared__ T red[S::NT / 64];
+    __shared__ int32_t s_pick, s_step, s_stop;
+    T* arena = reinterpret_cast<T*>(a.arena);
+    const int32_t G = gridDim.x;
+    const int32_t w = blockIdx.x;
+    const int32_t nown = a.ntiles > w ? (a.ntiles - w + G - 1) / G : 0;
+    int32_t cursor = 0;
+    int64_t idle_since = -1;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int32_t pick = -1, step = 0, stop = 1;
+            for (int32_t k = 0; k < nown && pick < 0; ++k) {
+                const int32_t j = (cursor + k) % nown;
+                const int32_t ti = w + j * G;
+                const int32_t sv = a.tile_solve ? a.tile_solve[ti] : 0;
+                const int32_t d = ld_acq(&a.done[ti]);
+                int32_t tgt = ld_acq(&a.target[sv]);
+                if (a.final_step) {
+                    const int32_t fs = ld_acq(&a.final_step[sv]);
+                    if (fs > 0) tgt = fs;
+                }
+                if (d >= tgt) continue;
+                stop = 0;
+                if (a.gate && a.check_every[sv] > 0 && d > 0 && d % a.check_every[sv] == 0 &&
+                    ld_acq(&a.gate[sv]) < d)
+                    continue;
+                bool ready = true;
+                for (int32_t q = a.dep_ptr[ti]; q < a.dep_ptr[ti + 1] && ready; ++q)
+                    ready = ld_acq(&a.done[a.dep_idx[q]]) >= d;
+                if (ready) {
+                    pick = ti;
+                    step = d;
+                    cursor = (j + 1) % nown;
+                }
+            }
+            if (a.yield_flag && pick < 0 &&
+                __hip_atomic_load(a.yield_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0)
+                stop = 1;
+            if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) stop = 1;
+            s_pick = pick;
+            s_step = step;
+            s_stop = stop;
+        }
+        __syncthreads();
+        const int32_t pick = s_pick, step = s_step;
+        if (pick < 0) {
+            if (s_stop) break;
+            // bounded wait: give up (error flag 2) after wait_ticks of idling
+            const int64_t now = wall_clock64();
+            if (idle_since < 0) idle_since = now;
+            if (now - idle_since > a.wait_ticks) {
+                if (threadIdx.x == 0) __hip_atomic_fetch_or(a.err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(4);
+            __syncthreads();
+            continue;
+        }
+        idle_since = -1;
+        __threadfence();   // acquire side: see the neighbours' step-`step` data
+        const TileDev t = a.tiles[pick];
+        const int p = step & 1;
+        const int32_t sv = a.tile_solve ? a.tile_solve[pick] : 0;
+        const uint8_t* ex = a.extra ? a.extra + (size_t)(step % a.extra_period) * a.nchares : nullptr;
+        const int reps = 1 + (ex ? (int)ex[t.blk] : 0);
+        T r = 0;
+        for (int rep = 0; rep < reps; ++rep) r = sweep_tile<T, TX, TY>(arena, a.blocks, t, p, lds);
+        const int32_t ns = step + 1;
+        // A plain grid records only its target step's residual (slot ns & 1,
+        // cleared before the launch).  A served solve records it at decision
+        // steps (multiples of check_every, and its cap), where every tile of
+        // the solve waits for the decision, so one slot per solve suffices.
+        if (a.final_only) {
+            if (ns == ld_acq(&a.target[sv])) wg_residual<T, S::NT>(r, &a.res[2 * sv + (ns & 1)], red);
+        } else {
+            const int32_t ce = a.check_every[sv];
+            if ((ce > 0 && ns % ce == 0) || ns == ld_acq(&a.target[sv])) wg_residual<T, S::NT>(r, &a.res[sv], red);
+        }
+        __threadfence();   // release side: this tile's step-ns data before its counter
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __hip_atomic_store(&a.done[pick], ns, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (a.solve_count) {
+                const int32_t ce = a.check_every[sv];
+                const int32_t tgt = ld_acq(&a.target[sv]);
+                const bool decision = (ce > 0 && ns % ce == 0) || ns == tgt;
+                if (decision) {
+                    int32_t* cnt = &a.solve_count[sv];
+                    const int32_t prev = __hip_atomic_fetch_add(cnt, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                    if (prev == a.solve_ntiles[sv] - 1) {
+                        // last tile of the solve to finish decision step ns
+                        __hip_atomic_store(cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const unsigned long long rb =
+                            __hip_atomic_exchange(&a.res[sv], 0ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                        const double rv = __longlong_as_double((long long)rb);
+                        const bool fin = ns >= tgt || (ce > 0 && ns % ce == 0 && rv < a.tol[sv]);
+                        if (fin) {
+                            __hip_atomic_store(&a.final_step[sv], ns, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                            if (a.host_res) a.host_res[sv] = rb;
+                            __threadfence_system();
+                            if (a.host_done) a.host_done[sv] = ns;
+                            __threadfence_system();
+                        } else {
+                            __hip_atomic_store(&a.gate[sv], ns, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// variant table
+
+#define OD_VARIANTS_F64(X) X(double, 32, 4) X(double, 32, 8) X(double, 32, 16) X(double, 32, 32) \
+    X(double, 64, 4) X(double, 64, 8) X(double, 64, 16) X(double, 16, 8) X(double, 16, 16) X(double, 128, 4)
+#define OD_VARIANTS_F32(X) X(float, 32, 8) X(float, 32, 16) X(float, 32, 32) X(float, 64, 4) \
+    X(float, 64, 8) X(float, 64, 16) X(float, 128, 4) X(float, 128, 8) X(float, 16, 16)
+
+#define OD_VT_ENTRY(T, TX, TY) {TX, TY, SW<T, TX, TY>::NT},
+static const SweepVariant kVariants64[] = {OD_VARIANTS_F64(OD_VT_ENTRY)};
+static const SweepVariant kVariants32[] = {OD_VARIANTS_F32(OD_VT_ENTRY)};
+
+const SweepVariant* sweep_variants(int dtype_bytes, int* count) {
+    if (dtype_bytes == 8) {
+        *count = (int)(sizeof(kVariants64) / sizeof(kVariants64[0]));
+        return kVariants64;
+    }
+    *count = (int)(sizeof(kVariants32) / sizeof(kVariants32[0]));
+    return kVariants32;
+}
+
+bool sweep_variant_ok(int dtype_bytes, int tx, int ty) { return sweep_threads(dtype_bytes, tx, ty) > 0; }
+
+int sweep_threads(int dtype_bytes, int tx, int ty) {
+    int n = 0;
+    const SweepVariant* v = sweep_variants(dtype_bytes, &n);
+    for (int i = 0; i < n; ++i)
+        if (v[i].tx == tx && v[i].ty == ty) return v[i].threads;
+    return 0;
+}
+
+hipError_t launch_sweep(int dtype_bytes, int tx, int ty, hipStream_t st, void* arena, const BlockDev* blocks,
+                        const TileDev* tiles, int32_t ntiles, int parity, unsigned long long* res,
+                        int32_t zero_lo, int32_t zero_hi, const uint8_t* extra) {
+    if (ntiles <= 0) return hipSuccess;
+#define OD_LAUNCH(T, TX, TY)                                                                          \
+    if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                      \
+        hipLaunchKernelGGL((k_sweep<T, TX, TY>), dim3(ntiles), dim3(SW<T, TX, TY>::NT), 0, st,       \
+                           reinterpret_cast<T*>(arena), blocks, tiles, parity, res, zero_lo, zero_hi, \
+                           extra);                                                                    \
+        return hipGetLastError();                                                                     \
+    }
+    OD_VARIANTS_F64(OD_LAUNCH)
+    OD_VARIANTS_F32(OD_LAUNCH)
+#undef OD_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+int64_t device_wait_ticks(double seconds) {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+        khz = 100000;   // 100 MHz, the usual constant-rate counter
+    return (int64_t)(seconds * 1e3 * (double)khz);
+}
+
+int persistent_max_grid(int dtype_bytes, int tx, int ty, int kind) {
+    int dev = 0, ncu = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+#define OD_OCC(T, TX, TY)                                                                             \
+    if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                      \
+        hipError_t e = kind == 0                                                                      \
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent<T, TX, TY>,             \
+                                                           SW<T, TX, TY>::NT, 0)                      \
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_msgdriven<T, TX, TY>,              \
+                                                           SW<T, TX, TY>::NT, 0);                     \
+        if (e != hipSuccess) return 0;                                                                \
+        return per * ncu;                                                                             \
+    }
+    OD_VARIANTS_F64(OD_OCC)
+    OD_VARIANTS_F32(OD_OCC)
+#undef OD_OCC
+    return 0;
+}
+
+hipError_t launch_persistent(int dtype_bytes, int tx, int ty, hipStream_t st, int grid, void* arena,
+                             const BlockDev* blocks, const TileDev* tiles, int32_t ntiles, int parity,
+                             int64_t iters, unsigned long long* res, int32_t nres, unsigned int* bar,
+                             unsigned int* err, const uint8_t* extra, int32_t extra_period, int32_t nchares,
+                             int64_t iter_base) {
+    if (iters <= 0) return hipSuccess;
+    int64_t wait_ticks = device_wait_ticks();
+#define OD_LAUNCH(T, TX, TY)                                                                          \
+    if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                      \
+        T* ar = reinterpret_cast<T*>(arena);                                                          \
+        void* args[] = {&ar, &blocks, &tiles, &ntiles, &parity, &iters, &res, &nres, &bar, &err,      \
+                        &extra, &extra_period, &nchares, &iter_base, &wait_ticks};                   \
+        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_persistent<T, TX, TY>),    \
+                                          dim3(grid), dim3(SW<T, TX, TY>::NT), args, 0, st);          \
+    }
+    OD_VARIANTS_F64(OD_LAUNCH)
+    OD_VARIANTS_F32(OD_LAUNCH)
+#undef OD_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_msgdriven(int dtype_bytes, int tx, int ty, hipStream_t st, int grid, const MsgArgs& a) {
+    MsgArgs ac = a;
+#define OD_LAUNCH(T, TX, TY)                                                                          \
+    if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                      \
+        void* args[] = {&ac};                                                                         \
+        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_msgdriven<T, TX, TY>),     \
+                                          dim3(grid), dim3(SW<T, TX, TY>::NT), args, 0, st);          \
+    }
+    OD_VARIANTS_F64(OD_LAUNCH)
+    OD_VARIANTS_F32(OD_LAUNCH)
+#undef OD_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// initialisation and global-layout I/O
+
+template <typename T>
+__global__ void k_init(GridDev g, uint64_t seed) {
+    T* arena = reinterpret_cast<T*>(g.arena);
+    const int64_t nx = g.n[0], ny = g.n[1], total = g.n[0] * g.n[1] * g.n[2];
+    for (int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < total;
+         gi += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = gi % nx, j = (gi / nx) % ny, k = gi / (nx * ny);
+        const int32_t c = owner_of(g.lk, i, j, k);
+        const BlockDev B = g.blocks[c];
+        const int64_t lx = i - g.lk.corigin[3 * c], ly = j - g.lk.corigin[3 * c + 1], lz = k - g.lk.corigin[3 * c + 2];
+        arena[B.off[0] + lx + ly * B.py + lz * B.pz] = unit_from_bits<T>(sm64(seed, (uint64_t)gi));
+    }
+}
+
+template <typename T>
+__global__ void k_fill_pb(GridDev g, int32_t npb, const int32_t* pb_face, const int32_t* pb_block,
+                          const double* bc) {
+    T* arena = reinterpret_cast<T*>(g.arena);
+    for (int32_t q = blockIdx.y; q < npb; q += gridDim.y) {
+        const BlockDev B = g.blocks[pb_block[q]];
+        const T v = (T)bc[pb_face[q]];
+        const int64_t cnt = (int64_t)B.ex * B.ey * B.ez;
+        for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * blockDim.x) {
+            const int64_t x = e % B.ex, y = (e / B.ex) % B.ey, z = e / ((int64_t)B.ex * B.ey);
+            arena[B.off[0] + x + y * B.py + z * B.pz] = v;
+        }
+    }
+}
+
+// Address of padded global cell (I, J, K) (0..n+1) or -1 for shell edges.
+__device__ __forceinline__ int64_t global_addr(const GridDev& g, int parity, int64_t I, int64_t J, int64_t K) {
+    int64_t c3[3] = {I - 1, J - 1, K - 1};
+    int outs = 0, f = -1;
+    for (int d = 0; d < 3; ++d) {
+        if (c3[d] < 0) {
+            ++outs;
+            f = 2 * d;
+            c3[d] = 0;
+        } else if (c3[d] >= g.n[d]) {
+            ++outs;
+            f = 2 * d + 1;
+            c3[d] = g.n[d] - 1;
+        }
+    }
+    if (outs >= 2) return -1;
+    const int32_t c = owner_of(g.lk, c3[0], c3[1], c3[2]);
+    int64_t l[3];
+    for (int d = 0; d < 3; ++d) l[d] = c3[d] - g.lk.corigin[3 * c + d];
+    int32_t b = c;
+    if (outs == 1) {
+        b = g.lk.dir_pb[6 * c + f];
+        l[f / 2] = 0;
+        if (b < 0) return -1;
+    }
+    const BlockDev B = g.blocks[b];
+    return B.off[parity] + l[0] + l[1] * B.py + l[2] * B.pz;
+}
+
+template <typename T>
+__global__ void k_gather(GridDev g, int parity, int64_t kz_lo, int64_t kz_hi, T* dst) {
+    const T* arena = reinterpret_cast<const T*>(g.arena);
+    const int64_t PX = g.n[0] + 2, PY = g.n[1] + 2;
+    const int64_t total = (kz_hi - kz_lo) * PX * PY;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t I = e % PX, J = (e / PX) % PY, K = kz_lo + e / (PX * PY);
+        const int64_t a = global_addr(g, parity, I, J, K);
+        dst[e] = a < 0 ? (T)0 : arena[a];
+    }
+}
+
+template <typename T>
+__global__ void k_scatter(GridDev g, int parity, int64_t kz_lo, int64_t kz_hi, const T* src) {
+    T* arena = reinterpret_cast<T*>(g.arena);
+    const int64_t PX = g.n[0] + 2, PY = g.n[1] + 2;
+    const int64_t total = (kz_hi - kz_lo) * PX * PY;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t I = e % PX, J = (e / PX) % PY, K = kz_lo + e / (PX * PY);
+        const int64_t a = global_addr(g, parity, I, J, K);
+        if (a >= 0) arena[a] = src[e];
+    }
+}
+
+template <typename T>
+__global__ void k_points(GridDev g, int parity, const int64_t* idx, int64_t count, T* dst) {
+    const T* arena = reinterpret_cast<const T*>(g.arena);
+    const int64_t nx = g.n[0], ny = g.n[1];
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t gi = idx[e];
+        const int64_t i = gi % nx, j = (gi / nx) % ny, k = gi / (nx * ny);
+        dst[e] = arena[global_addr(g, parity, i + 1, j + 1, k + 1)];
+    }
+}
+
+static int io_grid(int64_t total) {
+    int64_t b = (total + 255) / 256;
+    if (b > 65536) b = 65536;
+    return (int)(b < 1 ? 1 : b);
+}
+
+hipError_t launch_init(int dtype_bytes, hipStream_t st, const GridDev& g, int32_t nchares, uint64_t seed,
+                       int32_t npb, const int32_t* pb_face, const int32_t* pb_block, const double* bc_dev) {
+    (void)nchares;
+    const int64_t total = g.n[0] * g.n[1] * g.n[2];
+    if (dtype_bytes == 8)
+        hipLaunchKernelGGL(k_init<double>, dim3(io_grid(total)), dim3(256), 0, st, g, seed);
+    else
+        hipLaunchKernelGGL(k_init<float>, dim3(io_grid(total)), dim3(256), 0, st, g, seed);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || npb <= 0) return e;
+    dim3 grid(16, (unsigned)(npb < 65535 ? npb : 65535));
+    if (dtype_bytes == 8)
+        hipLaunchKernelGGL(k_fill_pb<double>, grid, dim3(256), 0, st, g, npb, pb_face, pb_block, bc_dev);
+    else
+        hipLaunchKernelGGL(k_fill_pb<float>, grid, dim3(256), 0, st, g, npb, pb_face, pb_block, bc_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(int dtype_bytes, hipStream_t st, const GridDev& g, int parity, int64_t kz_lo,
+                         int64_t kz_hi, void* dst) {
+    const int64_t total = (kz_hi - kz_lo) * (g.n[0] + 2) * (g.n[1] + 2);
+    if (total <= 0) return hipSuccess;
+    if (dtype_bytes == 8)
+        hipLaunchKernelGGL(k_gather<double>, dim3(io_grid(total)), dim3(256), 0, st, g, parity, kz_lo, kz_hi,
+                           reinterpret_cast<double*>(dst));
+    else
+        hipLaunchKernelGGL(k_gather<float>, dim3(io_grid(total)), dim3(256), 0, st, g, parity, kz_lo, kz_hi,
+                           reinterpret_cast<float*>(dst));
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(int dtype_bytes, hipStream_t st, const GridDev& g, int parity, int64_t kz_lo,
+                          int64_t kz_hi, const void* src) {
+    const int64_t total = (kz_hi - kz_lo) * (g.n[0] + 2) * (g.n[1] + 2);
+    if (total <= 0) return hipSuccess;
+    if (dtype_bytes == 8)
+        hipLaunchKernelGGL(k_scatter<double>, dim3(io_grid(total)), dim3(256), 0, st, g, parity, kz_lo, kz_hi,
+                           reinterpret_cast<const double*>(src));
+    else
+        hipLaunchKernelGGL(k_scatter<float>, dim3(io_grid(total)), dim3(256), 0, st, g, parity, kz_lo, kz_hi,
+                           reinterpret_cast<const float*>(src));
+    return hipGetLastError();
+}
+
+hipError_t launch_points(int dtype_bytes, hipStream_t st, const GridDev& g, int parity, const int64_t* idx,
+                         int64_t count, void* dst) {
+    if (count <= 0) return hipSuccess;
+    if (dtype_bytes == 8)
+        hipLaunchKernelGGL(k_points<double>, dim3(io_grid(count)), dim3(256), 0, st, g, parity, idx, count,
+                           reinterpret_cast<double*>(dst));
+    else
+        hipLaunchKernelGGL(k_points<float>, dim3(io_grid(count)), dim3(256), 0, st, g, parity, idx, count,
+                           reinterpret_cast<float*>(dst));
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// per-chare baseline: face messages
+
+// Face f's message layout: x faces [z][y] (y fastest), y faces [z][x],
+// z faces [y][x] with the chare's row pitch.
+template <typename T>
+__global__ void k_pack(const T* __restrict__ arena, BlockDev B, int parity, FaceSet out) {
+    const int f = blockIdx.y;
+    T* m = reinterpret_cast<T*>(out.p[f]);
+    if (m == nullptr) return;
+    const T* u = arena + B.off[parity];
+    const int64_t cnt = out.cnt[f];
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * blockDim.x) {
+        int64_t x, y, z;
+        if (f < 2) {
+            y = e % B.ey;
+            z = e / B.ey;
+            x = (f == 0) ? 0 : B.ex - 1;
+        } else if (f < 4) {
+            x = e % B.ex;
+            z = e / B.ex;
+            y = (f == 2) ? 0 : B.ey - 1;
+        } else {
+            x = e % B.py;
+            y = e / B.py;
+            z = (f == 4) ? 0 : B.ez - 1;
+            if (x >= B.ex) continue;
+        }
+        m[e] = u[x + y * B.py + z * B.pz];
+    }
+}
+
+template <typename T>
+__global__ void k_unpack(FaceSet in, FaceSet ghost) {
+    const int f = blockIdx.y;
+    const T* s = reinterpret_cast<const T*>(in.p[f]);
+    T* d = reinterpret_cast<T*>(ghost.p[f]);
+    if (s == nullptr || d == nullptr) return;
+    const int64_t cnt = in.cnt[f];
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * blockDim.x)
+        d[e] = s[e];
+}
+
+hipError_t launch_pack_b(int dtype_bytes, hipStream_t st, void* arena, const BlockDev& B, int parity,
+                         const FaceSet& out) {
+    int64_t mx = 1;
+    for (int f = 0; f < 6; ++f) mx = out.cnt[f] > mx ? out.cnt[f] : mx;
+    dim3 grid((unsigned)((mx + 255) / 256 < 1024 ? (mx + 255) / 256 : 1024), 6);
+    if (dtype_bytes == 8)
+        hipLaunchKernelGGL(k_pack<double>, grid, dim3(256), 0, st, reinterpret_cast<const double*>(arena), B, parity, out);
+    else
+        hipLaunchKernelGGL(k_pack<float>, grid, dim3(256), 0, st, reinterpret_cast<const float*>(arena), B, parity, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(int dtype_bytes, hipStream_t st, FaceSet in, FaceSet ghost) {
+    int64_t mx = 1;
+    for (int f = 0; f < 6; ++f) mx = in.cnt[f] > mx ? in.cnt[f] : mx;
+    dim3 grid((unsigned)((mx + 255) / 256 < 1024 ? (mx + 255) / 256 : 1024), 6);
+    if (dtype_bytes == 8)
+        hipLaunchKernelGGL(k_unpack<double>, grid, dim3(256), 0, st, in, ghost);
+    else
+        hipLaunchKernelGGL(k_unpack<float>, grid, dim3(256), 0, st, in, ghost);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// streaming copy (HBM ceiling)
+
+__global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        dst[e] = src[e];
+}
+
+hipError_t launch_copy(hipStream_t st, void* dst, const void* src, size_t bytes) {
+    const int64_t n = (int64_t)(bytes / 16);
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        ncu = 256;
+    int64_t grid = (n + 255) / 256;
+    const int64_t cap = (int64_t)ncu * 32;
+    if (grid > cap) grid = cap;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)grid), dim3(256), 0, st, reinterpret_cast<const uint4*>(src),
+                       reinterpret_cast<uint4*>(dst), n);
+    return hipGetLastError();
+}
+
+}  // namespace od

@@ -1,0 +1,760 @@
+// libod runtime: the C ABI of include/od.h for one grid.
+//
+// od_create decomposes the grid into chares (regular split or explicit
+// uneven blocks), cuts chares into sweep tiles, builds every tile face's
+// halo source (the pre-filled location table of Section IV: each ghost slab
+// knows which chare, or which Dirichlet face, it is read from), carves the
+// caller's workspace, uploads the descriptors once and initialises the
+// field on the device.  od_iterate then only enqueues device work.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "od_runtime.hpp"
+
+namespace od {
+
+thread_local std::string g_last_error;
+
+od_status fail(od_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+uint64_t host_sm64(uint64_t seed, uint64_t idx) {
+    uint64_t z = seed + (idx + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+namespace {
+
+constexpr int kStreamPool = 16;          // per-chare baseline: non-blocking streams
+constexpr int kImbalancePeriod = 64;     // rows of the imbalance table (steps mod period)
+constexpr int64_t kMaxGraphLen = 1024;   // iterations per captured graph
+
+struct Carver {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        size_t o = align_up(off, kAlign);
+        off = o + std::max<size_t>(bytes, 1);
+        return o;
+    }
+};
+
+int32_t pitch_of(int32_t ex, int s) {
+    const int32_t q = 64 / s;   // 64-byte rows
+    return (int32_t)align_up((size_t)ex, (size_t)q);
+}
+
+// Face f of chare c: pseudo-block extents, pitches, element count.
+void face_shape(const Chare& c, int32_t cpy, int f, int32_t e[3], int32_t* py, int64_t* pz, int64_t* cnt) {
+    const int d = f / 2;
+    e[0] = c.e[0];
+    e[1] = c.e[1];
+    e[2] = c.e[2];
+    e[d] = 1;
+    if (d == 0) {
+        *py = 1;
+        *pz = c.e[1];
+        *cnt = (int64_t)c.e[1] * c.e[2];
+    } else if (d == 1) {
+        *py = c.e[0];
+        *pz = c.e[0];
+        *cnt = (int64_t)c.e[0] * c.e[2];
+    } else {
+        *py = cpy;
+        *pz = (int64_t)cpy * c.e[1];
+        *cnt = (int64_t)cpy * c.e[1];
+    }
+}
+
+bool on_domain_face(const Plan& p, const Chare& c, int f) {
+    const int d = f / 2;
+    return (f % 2 == 0) ? c.o[d] == 0 : (int64_t)c.o[d] + c.e[d] == p.n[d];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// layout: everything od_create needs, computed identically by
+// od_workspace_bytes.
+
+std::string build_layout(const od_config& cfg, Grid& G) {
+    G.cfg = cfg;
+    G.cfg.blocks = nullptr;   // the caller's array is not kept
+    G.s = (int)cfg.dtype;
+    Plan& p = G.plan;
+    std::string err = plan_decompose(cfg, p);
+    if (!err.empty()) return err;
+    if (cfg.exec < OD_PER_CHARE || cfg.exec > OD_MSGDRIVEN) return "unknown exec mode";
+    if (cfg.exec == OD_PER_CHARE && !p.regular) return "OD_PER_CHARE needs a regular decomposition";
+    if (cfg.imbalance_pct < 0 || cfg.imbalance_pct > 100 || cfg.imbalance_max_extra < 0 ||
+        cfg.imbalance_max_extra > 255)
+        return "imbalance_pct must be in [0,100] and imbalance_max_extra in [0,255]";
+    if (cfg.imbalance_pct > 0 && cfg.exec == OD_GRAPH) return "imbalance is not supported with OD_GRAPH";
+    if (!p.regular) {
+        // tile rows are loaded as 16-byte vectors: explicit blocks start on a
+        // vector boundary along x
+        const int32_t vx = 16 / (int32_t)cfg.dtype;
+        for (const Chare& c : p.chares)
+            if (c.o[0] % vx != 0)
+                return "explicit block x-origins must be multiples of " + std::to_string(vx) + " for this dtype";
+    }
+    plan_default_tile(cfg, p);
+    if (!sweep_variant_ok(G.s, p.tile[0], p.tile[1]))
+        return "tile (" + std::to_string(p.tile[0]) + "," + std::to_string(p.tile[1]) + ") is not a compiled variant";
+    err = plan_tiles(p);
+    if (!err.empty()) return err;
+    if (cfg.exec == OD_PER_CHARE) {
+        // chare-major tile order: one launch per chare covers a contiguous range
+        std::stable_sort(p.tiles.begin(), p.tiles.end(),
+                         [](const TileHost& a, const TileHost& b) { return a.chare < b.chare; });
+    }
+    const int32_t C = (int32_t)p.chares.size();
+    const int s = G.s;
+
+    // ---- block table: chares, then pseudo-blocks
+    Carver cv;
+    G.blocks_h.assign((size_t)C, BlockDev{});
+    G.cpy.assign((size_t)C, 0);
+    std::vector<size_t> field_off(2 * (size_t)C);
+    G.dir_pb.assign((size_t)C * 6, -1);
+    G.ghost_pb.assign((size_t)C * 6, -1);
+    G.pb_face.clear();
+    G.pb_block.clear();
+
+    // descriptor regions first (sizes known after tiles / pseudo-blocks)
+    int32_t npb = 0;
+    for (int32_t c = 0; c < C; ++c)
+        for (int f = 0; f < 6; ++f) {
+            if (on_domain_face(p, p.chares[(size_t)c], f)) ++npb;
+            else if (cfg.exec == OD_PER_CHARE) ++npb;
+        }
+    const size_t nblocks = (size_t)C + (size_t)npb;
+    const size_t ntiles = p.tiles.size();
+    G.L.blocks = cv.take(nblocks * sizeof(BlockDev));
+    G.L.tiles = cv.take(ntiles * sizeof(TileDev));
+    for (int d = 0; d < 3; ++d) G.L.cidx[d] = cv.take((size_t)(p.regular ? p.n[d] : 1) * 4);
+    G.L.owner = cv.take((p.regular ? 1 : p.owner.size()) * 4);
+    G.L.corigin = cv.take((size_t)C * 3 * 4);
+    G.L.dir_pb = cv.take((size_t)C * 6 * 4);
+    G.L.pb_face = cv.take((size_t)std::max(npb, 1) * 4);
+    G.L.pb_block = cv.take((size_t)std::max(npb, 1) * 4);
+    G.L.bc = cv.take(6 * 8);
+    G.nres = cfg.exec == OD_PER_CHARE ? C : 1;
+    G.L.res = cv.take((size_t)(2 * G.nres + 2) * 8);
+    G.L.bar = cv.take(4 * 4);
+    G.L.err = cv.take(4);
+    G.L.done = cv.take(ntiles * 4);
+    G.L.target = cv.take(4 * 4);
+    // message-driven dependencies
+    G.dep_ptr.clear();
+    G.dep_idx.clear();
+    if (cfg.exec == OD_MSGDRIVEN) {
+        std::string e2 = build_tile_deps(p, G.dep_ptr, G.dep_idx);
+        if (!e2.empty()) return e2;
+    }
+    G.L.dep_ptr = cv.take((G.dep_ptr.size() + 1) * 4);
+    G.L.dep_idx = cv.take((G.dep_idx.size() + 1) * 4);
+    // imbalance table
+    G.extra_h.clear();
+    if (cfg.imbalance_pct > 0 && cfg.imbalance_max_extra > 0) {
+        G.extra_h.assign((size_t)kImbalancePeriod * C, 0);
+        const int32_t m = (int32_t)std::llround(cfg.imbalance_pct / 100.0 * C);
+        std::vector<std::pair<uint64_t, int32_t>> rank((size_t)C);
+        for (int32_t t = 0; t < kImbalancePeriod; ++t) {
+            for (int32_t c = 0; c < C; ++c)
+                rank[(size_t)c] = {host_sm64(cfg.seed ^ 0x696D62616C616E63ull, (uint64_t)t * C + c), c};
+            std::partial_sort(rank.begin(), rank.begin() + m, rank.end());
+            for (int32_t q = 0; q < m; ++q) {
+                const uint64_t h = rank[(size_t)q].first;
+                G.extra_h[(size_t)t * C + rank[(size_t)q].second] =
+                    (uint8_t)(1 + (int)((h >> 32) % (uint64_t)cfg.imbalance_max_extra));
+            }
+        }
+    }
+    G.extra_period = kImbalancePeriod;
+    G.L.extra = cv.take(G.extra_h.size() + 1);
+
+    // ---- field storage (two parities per chare)
+    for (int32_t c = 0; c < C; ++c) {
+        const Chare& ch = p.chares[(size_t)c];
+        const int32_t cpy = pitch_of(ch.e[0], s);
+        G.cpy[(size_t)c] = cpy;
+        const size_t bytes = (size_t)cpy * ch.e[1] * ch.e[2] * s;
+        field_off[2 * (size_t)c] = cv.take(bytes);
+        field_off[2 * (size_t)c + 1] = cv.take(bytes);
+        BlockDev& B = G.blocks_h[(size_t)c];
+        B.off[0] = (int64_t)(field_off[2 * (size_t)c] / s);
+        B.off[1] = (int64_t)(field_off[2 * (size_t)c + 1] / s);
+        B.py = cpy;
+        B.pz = (int64_t)cpy * ch.e[1];
+        B.ex = ch.e[0];
+        B.ey = ch.e[1];
+        B.ez = ch.e[2];
+    }
+    G.L.field_end = cv.off;
+    // ---- pseudo-blocks
+    for (int32_t c = 0; c < C; ++c) {
+        const Chare& ch = p.chares[(size_t)c];
+        for (int f = 0; f < 6; ++f) {
+            const bool dom = on_domain_face(p, ch, f);
+            if (!dom && cfg.exec != OD_PER_CHARE) continue;
+            int32_t e[3], py;
+            int64_t pz, cnt;
+            face_shape(ch, G.cpy[(size_t)c], f, e, &py, &pz, &cnt);
+            BlockDev B{};
+            const size_t o = cv.take((size_t)cnt * s);
+            B.off[0] = B.off[1] = (int64_t)(o / s);
+            B.py = py;
+            B.pz = pz;
+            B.ex = e[0];
+            B.ey = e[1];
+            B.ez = e[2];
+            const int32_t id = (int32_t)G.blocks_h.size();
+            G.blocks_h.push_back(B);
+            if (dom) {
+                G.dir_pb[(size_t)c * 6 + f] = id;
+                G.pb_face.push_back(f);
+                G.pb_block.push_back(id);
+            } else {
+                G.ghost_pb[(size_t)c * 6 + f] = id;
+            }
+        }
+    }
+    // ---- per-chare baseline messages: outbox (2 parities) and inbox per face
+    G.msg.clear();
+    if (cfg.exec == OD_PER_CHARE) {
+        G.msg.resize((size_t)C);
+        for (int32_t c = 0; c < C; ++c) {
+            const Chare& ch = p.chares[(size_t)c];
+            for (int f = 0; f < 6; ++f) {
+                if (ch.nb[f] < 0) continue;
+                int32_t e[3], py;
+                int64_t pz, cnt;
+                face_shape(ch, G.cpy[(size_t)c], f, e, &py, &pz, &cnt);
+                G.msg[(size_t)c].cnt[f] = cnt;
+                G.msg[(size_t)c].out[0][f] = cv.take((size_t)cnt * s);
+                G.msg[(size_t)c].out[1][f] = cv.take((size_t)cnt * s);
+                G.msg[(size_t)c].in[f] = cv.take((size_t)cnt * s);
+            }
+        }
+    }
+    G.L.total = align_up(cv.off, kAlign) + kAlign;
+
+    // ---- tile descriptors
+    G.tiles_h.resize(ntiles);
+    for (size_t i = 0; i < ntiles; ++i) {
+        const TileHost& th = p.tiles[i];
+        TileDev& td = G.tiles_h[i];
+        const Chare& ch = p.chares[(size_t)th.chare];
+        td.blk = th.chare;
+        td.x0 = th.o[0];
+        td.y0 = th.o[1];
+        td.z0 = th.o[2];
+        td.nx = th.e[0];
+        td.ny = th.e[1];
+        td.nz = th.e[2];
+        td.rslot = cfg.exec == OD_PER_CHARE ? th.chare : 0;
+        for (int f = 0; f < 6; ++f) {
+            FaceDev& fd = td.f[f];
+            int32_t src_chare = -1, pb = -1;
+            if (th.kind[f] == 2) src_chare = th.chare;
+            else if (th.kind[f] == 0) {
+                if (cfg.exec == OD_PER_CHARE) pb = G.ghost_pb[(size_t)th.chare * 6 + f];
+                else src_chare = th.src[f];
+            } else {
+                pb = G.dir_pb[(size_t)th.chare * 6 + f];
+            }
+            if (src_chare >= 0) {
+                const Chare& sc = p.chares[(size_t)src_chare];
+                fd.src = src_chare;
+                fd.sx = th.g[f][0] - sc.o[0];
+                fd.sy = th.g[f][1] - sc.o[1];
+                fd.sz = th.g[f][2] - sc.o[2];
+            } else {
+                if (pb < 0) return "internal error: missing face pseudo-block";
+                fd.src = pb;
+                int32_t sxyz[3];
+                for (int q = 0; q < 3; ++q) sxyz[q] = th.g[f][q] - ch.o[q];
+                sxyz[f / 2] = 0;
+                fd.sx = sxyz[0];
+                fd.sy = sxyz[1];
+                fd.sz = sxyz[2];
+            }
+        }
+    }
+    return "";
+}
+
+// Tiles whose box intersects a ghost slab of tile t (face neighbours through
+// which halos are read), as CSR lists.
+std::string build_tile_deps(const Plan& p, std::vector<int32_t>& ptr, std::vector<int32_t>& idx) {
+    const size_t T = p.tiles.size();
+    // per chare: regular cut index -> tile ids
+    struct Key {
+        int32_t c, ix, iy, iz;
+        bool operator<(const Key& o) const {
+            if (c != o.c) return c < o.c;
+            if (iz != o.iz) return iz < o.iz;
+            if (iy != o.iy) return iy < o.iy;
+            return ix < o.ix;
+        }
+    };
+    std::map<Key, std::vector<int32_t>> cut;
+    for (size_t i = 0; i < T; ++i) {
+        const TileHost& t = p.tiles[i];
+        cut[Key{t.chare, t.o[0] / p.tile[0], t.o[1] / p.tile[1], t.o[2] / p.tile[2]}].push_back((int32_t)i);
+    }
+    ptr.assign(T + 1, 0);
+    idx.clear();
+    for (size_t i = 0; i < T; ++i) {
+        const TileHost& t = p.tiles[i];
+        std::vector<int32_t> deps;
+        for (int f = 0; f < 6; ++f) {
+            if (t.kind[f] == 1) continue;
+            const int32_t sc = t.kind[f] == 2 ? t.chare : t.src[f];
+            const Chare& c = p.chares[(size_t)sc];
+            int64_t lo[3], hi[3];
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = t.g[f][d] - c.o[d];
+                hi[d] = lo[d] + (d == f / 2 ? 1 : t.e[d]);
+            }
+            for (int64_t iz = lo[2] / p.tile[2]; iz <= (hi[2] - 1) / p.tile[2]; ++iz)
+                for (int64_t iy = lo[1] / p.tile[1]; iy <= (hi[1] - 1) / p.tile[1]; ++iy)
+                    for (int64_t ix = lo[0] / p.tile[0]; ix <= (hi[0] - 1) / p.tile[0]; ++ix) {
+                        auto it = cut.find(Key{sc, (int32_t)ix, (int32_t)iy, (int32_t)iz});
+                        if (it == cut.end()) continue;
+                        for (int32_t o : it->second) {
+                            const TileHost& u = p.tiles[(size_t)o];
+                            bool hit = true;
+                            for (int d = 0; d < 3 && hit; ++d)
+                                hit = u.o[d] < hi[d] && lo[d] < (int64_t)u.o[d] + u.e[d];
+                            if (hit && o != (int32_t)i) deps.push_back(o);
+                        }
+                    }
+        }
+        std::sort(deps.begin(), deps.end());
+        deps.erase(std::unique(deps.begin(), deps.end()), deps.end());
+        idx.insert(idx.end(), deps.begin(), deps.end());
+        ptr[i + 1] = (int32_t)idx.size();
+    }
+    return "";
+}
+
+// ---------------------------------------------------------------------------
+
+od_status Grid::upload() {
+    char* ws = base;
+    auto put = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+        if (bytes == 0) return hipSuccess;
+        return hipMemcpyAsync(ws + off, src, bytes, hipMemcpyHostToDevice, st);
+    };
+    const Plan& p = plan;
+    const int32_t C = (int32_t)p.chares.size();
+    std::vector<int32_t> corigin((size_t)C * 3);
+    for (int32_t c = 0; c < C; ++c)
+        for (int d = 0; d < 3; ++d) corigin[(size_t)c * 3 + d] = p.chares[(size_t)c].o[d];
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = put(L.blocks, blocks_h.data(), blocks_h.size() * sizeof(BlockDev));
+    if (e == hipSuccess) e = put(L.tiles, tiles_h.data(), tiles_h.size() * sizeof(TileDev));
+    std::vector<int32_t> cidx[3];
+    if (p.regular) {
+        for (int d = 0; d < 3; ++d) {
+            cidx[d].resize((size_t)p.n[d]);
+            for (int32_t i = 0; i < p.k[d]; ++i)
+                for (int32_t v = p.split[d][(size_t)i]; v < p.split[d][(size_t)i + 1]; ++v) cidx[d][(size_t)v] = i;
+            if (e == hipSuccess) e = put(L.cidx[d], cidx[d].data(), cidx[d].size() * 4);
+        }
+    } else if (e == hipSuccess) {
+        e = put(L.owner, p.owner.data(), p.owner.size() * 4);
+    }
+    if (e == hipSuccess) e = put(L.corigin, corigin.data(), corigin.size() * 4);
+    if (e == hipSuccess) e = put(L.dir_pb, dir_pb.data(), dir_pb.size() * 4);
+    if (e == hipSuccess) e = put(L.pb_face, pb_face.data(), pb_face.size() * 4);
+    if (e == hipSuccess) e = put(L.pb_block, pb_block.data(), pb_block.size() * 4);
+    if (e == hipSuccess) e = put(L.bc, cfg.bc, 6 * 8);
+    if (e == hipSuccess) e = put(L.dep_ptr, dep_ptr.data(), dep_ptr.size() * 4);
+    if (e == hipSuccess) e = put(L.dep_idx, dep_idx.data(), dep_idx.size() * 4);
+    if (e == hipSuccess) e = put(L.extra, extra_h.data(), extra_h.size());
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("descriptor upload: ") + hipGetErrorString(e));
+
+    gdev.arena = base;
+    gdev.blocks = reinterpret_cast<const BlockDev*>(base + L.blocks);
+    gdev.lk.regular = p.regular ? 1 : 0;
+    for (int d = 0; d < 3; ++d) {
+        gdev.lk.k[d] = p.k[d];
+        gdev.lk.cidx[d] = reinterpret_cast<const int32_t*>(base + L.cidx[d]);
+        gdev.lk.og[d] = (int32_t)p.og[d];
+        gdev.n[d] = p.n[d];
+    }
+    gdev.lk.owner = reinterpret_cast<const int32_t*>(base + L.owner);
+    gdev.lk.gran = p.gran;
+    gdev.lk.corigin = reinterpret_cast<const int32_t*>(base + L.corigin);
+    gdev.lk.dir_pb = reinterpret_cast<const int32_t*>(base + L.dir_pb);
+    return OD_OK;
+}
+
+od_status Grid::reset_state() {
+    // zero residual slots, barrier, error flag and step counters with a
+    // plain fill (not captured into any graph)
+    hipError_t e = hipMemsetAsync(base + L.res, 0, (size_t)(2 * nres + 2) * 8, st);
+    if (e == hipSuccess) e = hipMemsetAsync(base + L.bar, 0, 16, st);
+    if (e == hipSuccess) e = hipMemsetAsync(base + L.err, 0, 4, st);
+    if (e == hipSuccess) e = hipMemsetAsync(base + L.done, 0, std::max<size_t>(tiles_h.size(), 1) * 4, st);
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("state reset: ") + hipGetErrorString(e));
+    parity = 0;
+    iters = 0;
+    faces_packed = false;
+    return OD_OK;
+}
+
+od_status Grid::init_field() {
+    hipError_t e = launch_init(s, st, gdev, (int32_t)plan.chares.size(), cfg.seed, (int32_t)pb_face.size(),
+                               reinterpret_cast<const int32_t*>(base + L.pb_face),
+                               reinterpret_cast<const int32_t*>(base + L.pb_block),
+                               reinterpret_cast<const double*>(base + L.bc));
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("init: ") + hipGetErrorString(e));
+    return OD_OK;
+}
+
+Grid::~Grid() {
+    for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
+    for (hipEvent_t ev : packed) hipEventDestroy(ev);
+    for (hipStream_t s2 : pool) hipStreamDestroy(s2);
+    if (cap_st) hipStreamDestroy(cap_st);
+    if (pinned) hipHostFree(pinned);
+}
+
+od_status Grid::ensure_pinned(size_t bytes) {
+    if (pinned_bytes >= bytes) return OD_OK;
+    if (pinned) hipHostFree(pinned);
+    pinned = nullptr;
+    pinned_bytes = 0;
+    hipError_t e = hipHostMalloc(&pinned, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("hipHostMalloc staging: ") + hipGetErrorString(e));
+    pinned_bytes = bytes;
+    return OD_OK;
+}
+
+// ---- sweeps ------------------------------------------------------------------
+
+unsigned long long* Grid::res_ptr() { return reinterpret_cast<unsigned long long*>(base + L.res); }
+
+const uint8_t* Grid::extra_row(int64_t step) const {
+    if (extra_h.empty()) return nullptr;
+    return reinterpret_cast<const uint8_t*>(base + L.extra) +
+           (size_t)(step % extra_period) * plan.chares.size();
+}
+
+od_status Grid::fused_one(hipStream_t s2, int par, int64_t step) {
+    hipError_t e = launch_sweep(s, plan.tile[0], plan.tile[1], s2, base,
+                                reinterpret_cast<const BlockDev*>(base + L.blocks),
+                                reinterpret_cast<const TileDev*>(base + L.tiles), (int32_t)tiles_h.size(), par,
+                                res_ptr(), 0, 1, extra_row(step));
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("sweep launch: ") + hipGetErrorString(e));
+    return OD_OK;
+}
+
+od_status Grid::graph_run(int64_t n) {
+    while (n > 0) {
+        const int64_t m = std::min(n, kMaxGraphLen);
+        auto key = std::make_pair(parity, m);
+        auto it = graphs.find(key);
+        if (it == graphs.end()) {
+            if (!cap_st) {
+                hipError_t e = hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking);
+                if (e != hipSuccess) return fail(OD_EHIP, std::string("capture stream: ") + hipGetErrorString(e));
+            }
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamBeginCapture(cap_st, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return fail(OD_EHIP, std::string("begin capture: ") + hipGetErrorString(e));
+            od_status os = OD_OK;
+            for (int64_t i = 0; i < m && os == OD_OK; ++i) os = fused_one(cap_st, parity ^ (int)(i & 1), iters + i);
+            e = hipStreamEndCapture(cap_st, &graph);
+            if (os != OD_OK) {
+                if (graph) hipGraphDestroy(graph);
+                return os;
+            }
+            if (e != hipSuccess) return fail(OD_EHIP, std::string("end capture: ") + hipGetErrorString(e));
+            hipGraphExec_t exec = nullptr;
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            if (e != hipSuccess) return fail(OD_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+            it = graphs.emplace(key, exec).first;
+        }
+        hipError_t e = hipGraphLaunch(it->second, st);
+        if (e != hipSuccess) return fail(OD_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
+        parity ^= (int)(m & 1);
+        iters += m;
+        n -= m;
+    }
+    return OD_OK;
+}
+
+od_status Grid::persistent_run(int64_t n) {
+    if (grid_wgs <= 0) return fail(OD_EHIP, "persistent kernel: no co-resident workgroups");
+    hipError_t e = launch_persistent(s, plan.tile[0], plan.tile[1], st, grid_wgs, base,
+                                     reinterpret_cast<const BlockDev*>(base + L.blocks),
+                                     reinterpret_cast<const TileDev*>(base + L.tiles), (int32_t)tiles_h.size(),
+                                     parity, n, res_ptr(), 1, reinterpret_cast<unsigned int*>(base + L.bar),
+                                     reinterpret_cast<unsigned int*>(base + L.err),
+                                     extra_h.empty() ? nullptr : reinterpret_cast<const uint8_t*>(base + L.extra),
+                                     extra_period, (int32_t)plan.chares.size(), iters);
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
+    parity ^= (int)(n & 1);
+    iters += n;
+    return OD_OK;
+}
+
+od_status Grid::msgdriven_run(int64_t n) {
+    if (grid_wgs <= 0) return fail(OD_EHIP, "message-driven kernel: no co-resident workgroups");
+    if (iters + n > INT32_MAX) return fail(OD_EINVAL, "step counters limited to 2^31 iterations");
+    // target = iters + n ; the final-step residual slot (index 2) is cleared
+    const int32_t tgt = (int32_t)(iters + n);
+    hipError_t e = hipMemcpyAsync(base + L.target, &tgt, 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(base + L.res + 16, 0, 16, st);
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("msg setup: ") + hipGetErrorString(e));
+    MsgArgs a{};
+    a.arena = base;
+    a.blocks = reinterpret_cast<const BlockDev*>(base + L.blocks);
+    a.tiles = reinterpret_cast<const TileDev*>(base + L.tiles);
+    a.ntiles = (int32_t)tiles_h.size();
+    a.dep_ptr = reinterpret_cast<const int32_t*>(base + L.dep_ptr);
+    a.dep_idx = reinterpret_cast<const int32_t*>(base + L.dep_idx);
+    a.done = reinterpret_cast<int32_t*>(base + L.done);
+    a.target = reinterpret_cast<const int32_t*>(base + L.target);
+    a.tile_solve = nullptr;
+    a.res = res_ptr() + 2;   // slot (final step & 1) of this 2-slot pair
+    a.err = reinterpret_cast<unsigned int*>(base + L.err);
+    a.extra = extra_h.empty() ? nullptr : reinterpret_cast<const uint8_t*>(base + L.extra);
+    a.extra_period = extra_period;
+    a.nchares = (int32_t)plan.chares.size();
+    a.wait_ticks = device_wait_ticks();
+    a.final_only = 1;
+    e = launch_msgdriven(s, plan.tile[0], plan.tile[1], st, grid_wgs, a);
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("msg-driven launch: ") + hipGetErrorString(e));
+    parity = tgt & 1;
+    iters += n;
+    msg_final = true;
+    return OD_OK;
+}
+
+od_status Grid::per_chare_run(int64_t n) {
+    const Plan& p = plan;
+    const int32_t C = (int32_t)p.chares.size();
+    if (pool.empty()) {
+        pool.resize((size_t)std::min(C, kStreamPool));
+        for (auto& s2 : pool) {
+            hipError_t e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking);
+            if (e != hipSuccess) return fail(OD_EHIP, std::string("stream pool: ") + hipGetErrorString(e));
+        }
+        packed.resize((size_t)C);
+        for (auto& ev : packed) {
+            hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e != hipSuccess) return fail(OD_EHIP, std::string("event: ") + hipGetErrorString(e));
+        }
+        // per-chare tile ranges (tiles are chare-major in this mode)
+        tile_lo.assign((size_t)C + 1, 0);
+        for (const TileHost& t : p.tiles) tile_lo[(size_t)t.chare + 1]++;
+        for (int32_t c = 0; c < C; ++c) tile_lo[(size_t)c + 1] += tile_lo[(size_t)c];
+        if (!join_ev) {
+            hipError_t e = hipEventCreateWithFlags(&join_ev, hipEventDisableTiming);
+            if (e != hipSuccess) return fail(OD_EHIP, std::string("event: ") + hipGetErrorString(e));
+        }
+    }
+    auto sp = [&](int32_t c) { return pool[(size_t)c % pool.size()]; };
+    auto face_out = [&](int32_t c, int par) {
+        FaceSet fs{};
+        for (int f = 0; f < 6; ++f) {
+            const MsgBufs& mb = msg[(size_t)c];
+            if (mb.cnt[f] > 0) {
+                fs.p[f] = base + mb.out[par][f];
+                fs.cnt[f] = mb.cnt[f];
+            }
+        }
+        return fs;
+    };
+    // the pool streams start after all work already queued on the grid stream
+    hipError_t e = hipEventRecord(join_ev, st);
+    for (auto& s2 : pool)
+        if (e == hipSuccess) e = hipStreamWaitEvent(s2, join_ev, 0);
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("per-chare join: ") + hipGetErrorString(e));
+    if (!faces_packed) {
+        for (int32_t c = 0; c < C && e == hipSuccess; ++c) {
+            e = launch_pack_b(s, sp(c), base, blocks_h[(size_t)c], parity, face_out(c, parity));
+            if (e == hipSuccess) e = hipEventRecord(packed[(size_t)c], sp(c));
+        }
+        if (e != hipSuccess) return fail(OD_EHIP, std::string("initial pack: ") + hipGetErrorString(e));
+        faces_packed = true;
+    }
+    for (int64_t it = 0; it < n; ++it) {
+        const int par = parity;
+        // pass 1: receive — wait for the neighbours' messages, D2D copies, unpack
+        for (int32_t c = 0; c < C && e == hipSuccess; ++c) {
+            const Chare& ch = p.chares[(size_t)c];
+            hipStream_t s2 = sp(c);
+            FaceSet in{}, gh{};
+            for (int f = 0; f < 6 && e == hipSuccess; ++f) {
+                const int32_t nb = ch.nb[f];
+                if (nb < 0) continue;
+                const MsgBufs& mine = msg[(size_t)c];
+                const MsgBufs& theirs = msg[(size_t)nb];
+                e = hipStreamWaitEvent(s2, packed[(size_t)nb], 0);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(base + mine.in[f], base + theirs.out[par][f ^ 1], (size_t)mine.cnt[f] * s,
+                                       hipMemcpyDeviceToDevice, s2);
+                in.p[f] = base + mine.in[f];
+                in.cnt[f] = mine.cnt[f];
+                gh.p[f] = base + (size_t)blocks_h[(size_t)ghost_pb[(size_t)c * 6 + f]].off[0] * s;
+                gh.cnt[f] = mine.cnt[f];
+            }
+            if (e == hipSuccess) e = launch_unpack(s, s2, in, gh);
+        }
+        // pass 2: compute — sweep, pack the new faces, announce them
+        for (int32_t c = 0; c < C && e == hipSuccess; ++c) {
+            hipStream_t s2 = sp(c);
+            const int32_t t0 = tile_lo[(size_t)c], t1 = tile_lo[(size_t)c + 1];
+            e = launch_sweep(s, plan.tile[0], plan.tile[1], s2, base, reinterpret_cast<const BlockDev*>(base + L.blocks),
+                             reinterpret_cast<const TileDev*>(base + L.tiles) + t0, t1 - t0, par, res_ptr(), c, c + 1,
+                             extra_row(iters));
+            if (e == hipSuccess) e = launch_pack_b(s, s2, base, blocks_h[(size_t)c], par ^ 1, face_out(c, par ^ 1));
+            if (e == hipSuccess) e = hipEventRecord(packed[(size_t)c], s2);
+        }
+        if (e != hipSuccess) return fail(OD_EHIP, std::string("per-chare iteration: ") + hipGetErrorString(e));
+        parity ^= 1;
+        ++iters;
+    }
+    // the grid stream waits for every pool stream
+    for (auto& s2 : pool) {
+        if (e == hipSuccess) e = hipEventRecord(join_ev, s2);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, join_ev, 0);
+    }
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("per-chare join: ") + hipGetErrorString(e));
+    return OD_OK;
+}
+
+od_status Grid::iterate(int64_t n) {
+    if (n < 0) return fail(OD_EINVAL, "n must be >= 0");
+    if (n == 0) return OD_OK;
+    switch (cfg.exec) {
+        case OD_FUSED: {
+            msg_final = false;
+            for (int64_t i = 0; i < n; ++i) {
+                od_status os = fused_one(st, parity, iters);
+                if (os != OD_OK) return os;
+                parity ^= 1;
+                ++iters;
+            }
+            return OD_OK;
+        }
+        case OD_GRAPH:
+            msg_final = false;
+            return graph_run(n);
+        case OD_PERSISTENT:
+            msg_final = false;
+            return persistent_run(n);
+        case OD_MSGDRIVEN:
+            return msgdriven_run(n);
+        case OD_PER_CHARE:
+            msg_final = false;
+            return per_chare_run(n);
+    }
+    return fail(OD_EINVAL, "unknown exec mode");
+}
+
+od_status Grid::residual(double* r) {
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("sync: ") + hipGetErrorString(e));
+    unsigned int err = 0;
+    e = hipMemcpy(&err, base + L.err, 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("read error flag: ") + hipGetErrorString(e));
+    if (err != 0) return fail(OD_ETIMEDOUT, "a device-side wait exceeded its bound (flag " + std::to_string(err) + ")");
+    if (iters == 0) {
+        *r = 0.0;
+        return OD_OK;
+    }
+    std::vector<unsigned long long> v((size_t)(2 * nres + 2));
+    e = hipMemcpy(v.data(), base + L.res, v.size() * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("read residual: ") + hipGetErrorString(e));
+    unsigned long long m = 0;
+    if (msg_final) {
+        m = v[(size_t)(2 + (parity & 1))];
+    } else {
+        for (int32_t s2 = 0; s2 < nres; ++s2) m = std::max(m, v[(size_t)(2 * s2 + parity)]);
+    }
+    double d;
+    std::memcpy(&d, &m, 8);
+    *r = d;
+    return OD_OK;
+}
+
+// ---- global-layout I/O -------------------------------------------------------
+
+od_status Grid::io(void* host, size_t bytes, bool to_host) {
+    const int64_t PX = plan.n[0] + 2, PY = plan.n[1] + 2, PZ = plan.n[2] + 2;
+    const size_t need = (size_t)PX * PY * PZ * s;
+    if (bytes < need) return fail(OD_EINVAL, "buffer of " + std::to_string(bytes) + " bytes, need " + std::to_string(need));
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("sync: ") + hipGetErrorString(e));
+    const size_t plane = (size_t)PX * PY * s;
+    const size_t chunk_planes = std::max<size_t>(1, ((size_t)64 << 20) / plane);
+    od_status os = ensure_pinned(chunk_planes * plane);
+    if (os != OD_OK) return os;
+    if (!to_host) {
+        // a write replaces the field: parity 0 becomes current
+        os = reset_state();
+        if (os != OD_OK) return os;
+    }
+    for (int64_t k0 = 0; k0 < PZ; k0 += (int64_t)chunk_planes) {
+        const int64_t k1 = std::min<int64_t>(PZ, k0 + (int64_t)chunk_planes);
+        char* h = static_cast<char*>(host) + (size_t)k0 * plane;
+        const size_t nb = (size_t)(k1 - k0) * plane;
+        if (to_host) {
+            e = launch_gather(s, st, gdev, parity, k0, k1, pinned);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return fail(OD_EHIP, std::string("gather: ") + hipGetErrorString(e));
+            std::memcpy(h, pinned, nb);
+        } else {
+            std::memcpy(pinned, h, nb);
+            e = launch_scatter(s, st, gdev, 0, k0, k1, pinned);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return fail(OD_EHIP, std::string("scatter: ") + hipGetErrorString(e));
+        }
+    }
+    return OD_OK;
+}
+
+od_status Grid::read_points(const int64_t* idx, int64_t count, void* host_dst) {
+    if (count < 0) return fail(OD_EINVAL, "count must be >= 0");
+    if (count == 0) return OD_OK;
+    const int64_t total = plan.interior;
+    for (int64_t i = 0; i < count; ++i)
+        if (idx[i] < 0 || idx[i] >= total) return fail(OD_EINVAL, "point index out of range");
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("sync: ") + hipGetErrorString(e));
+    const size_t need = (size_t)count * (8 + (size_t)s);
+    od_status os = ensure_pinned(need);
+    if (os != OD_OK) return os;
+    std::memcpy(pinned, idx, (size_t)count * 8);
+    char* out = static_cast<char*>(pinned) + (size_t)count * 8;
+    e = launch_points(s, st, gdev, parity, static_cast<const int64_t*>(pinned), count, out);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("read points: ") + hipGetErrorString(e));
+    std::memcpy(host_dst, out, (size_t)count * s);
+    return OD_OK;
+}
+
+}  // namespace od

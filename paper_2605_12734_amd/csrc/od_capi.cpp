@@ -1,0 +1,291 @@
+// extern "C" entry points of libod (declared in include/od.h).  Argument
+// checking and error reporting live here; the work is done by od::Grid.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+
+#include "od_runtime.hpp"
+
+using od::fail;
+using od::Grid;
+
+struct od_grid {
+    Grid g;
+};
+
+namespace {
+
+od_status plan_only(const od_config* cfg, Grid& G) {
+    if (cfg == nullptr) return fail(OD_EINVAL, "cfg is NULL");
+    std::string err = od::build_layout(*cfg, G);
+    if (!err.empty()) return fail(OD_EINVAL, err);
+    return OD_OK;
+}
+
+#define OD_GUARD_BEGIN try {
+#define OD_GUARD_END                                                              \
+    }                                                                             \
+    catch (const std::bad_alloc&) {                                               \
+        return fail(OD_ENOMEM, "host allocation failed");                         \
+    }                                                                             \
+    catch (const std::exception& ex) {                                            \
+        return fail(OD_EINVAL, std::string("internal error: ") + ex.what());      \
+    }                                                                             \
+    catch (...) {                                                                 \
+        return fail(OD_EINVAL, "internal error");                                 \
+    }
+
+}  // namespace
+
+extern "C" {
+
+void od_config_default(od_config* cfg) {
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->n[0] = cfg->n[1] = cfg->n[2] = 64;
+    cfg->odf = 8;
+    cfg->dtype = OD_F64;
+    cfg->bc[0] = 1.0;
+    cfg->seed = 12734;
+    cfg->exec = OD_GRAPH;
+}
+
+const char* od_last_error(void) { return od::g_last_error.c_str(); }
+
+const char* od_version(void) { return "od 0.1 (gfx950)"; }
+
+od_status od_workspace_bytes(const od_config* cfg, size_t* bytes) {
+    OD_GUARD_BEGIN
+    if (bytes == nullptr) return fail(OD_EINVAL, "bytes is NULL");
+    Grid G;
+    od_status s = plan_only(cfg, G);
+    if (s != OD_OK) return s;
+    *bytes = G.L.total;
+    return OD_OK;
+    OD_GUARD_END
+}
+
+od_status od_create(const od_config* cfg, void* hip_stream, void* dev_workspace, size_t workspace_bytes,
+                    od_grid** out) {
+    OD_GUARD_BEGIN
+    if (out == nullptr) return fail(OD_EINVAL, "out is NULL");
+    *out = nullptr;
+    std::unique_ptr<od_grid> h(new od_grid);
+    Grid& G = h->g;
+    od_status s = plan_only(cfg, G);
+    if (s != OD_OK) return s;
+    if (dev_workspace == nullptr) return fail(OD_EINVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % od::kAlign != 0)
+        return fail(OD_EINVAL, "workspace must be 256-byte aligned");
+    if (workspace_bytes < G.L.total)
+        return fail(OD_ENOMEM, "workspace of " + std::to_string(workspace_bytes) + " bytes, need " +
+                                   std::to_string(G.L.total));
+    G.st = static_cast<hipStream_t>(hip_stream);
+    G.base = static_cast<char*>(dev_workspace);
+    G.ws_bytes = workspace_bytes;
+    s = G.upload();
+    if (s != OD_OK) return s;
+    s = G.reset_state();
+    if (s != OD_OK) return s;
+    s = G.init_field();
+    if (s != OD_OK) return s;
+    if (G.cfg.exec == OD_PERSISTENT || G.cfg.exec == OD_MSGDRIVEN) {
+        int cap = od::persistent_max_grid(G.s, G.plan.tile[0], G.plan.tile[1], G.cfg.exec == OD_PERSISTENT ? 0 : 1);
+        int grid = std::min<int>(cap, (int)G.tiles_h.size());
+        if (grid >= od::kNumXcd) grid -= grid % od::kNumXcd;
+        G.grid_wgs = grid;
+        if (grid <= 0) return fail(OD_EHIP, "no co-resident workgroups for the cooperative kernel");
+    }
+    hipError_t e = hipStreamSynchronize(G.st);
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("create sync: ") + hipGetErrorString(e));
+    *out = h.release();
+    return OD_OK;
+    OD_GUARD_END
+}
+
+od_status od_plan_create(const od_config* cfg, od_grid** out) {
+    OD_GUARD_BEGIN
+    if (out == nullptr) return fail(OD_EINVAL, "out is NULL");
+    *out = nullptr;
+    std::unique_ptr<od_grid> h(new od_grid);
+    od_status s = plan_only(cfg, h->g);
+    if (s != OD_OK) return s;
+    *out = h.release();
+    return OD_OK;
+    OD_GUARD_END
+}
+
+#define OD_NEED_DEVICE(g)                                                                  \
+    do {                                                                                   \
+        if (!(g)) return fail(OD_EINVAL, "grid is NULL");                                  \
+        if ((g)->g.base == nullptr) return fail(OD_EINVAL, "host-only plan handle");       \
+    } while (0)
+
+od_status od_iterate(od_grid* g, int64_t n) {
+    OD_GUARD_BEGIN
+    OD_NEED_DEVICE(g);
+    return g->g.iterate(n);
+    OD_GUARD_END
+}
+
+od_status od_residual(od_grid* g, double* r) {
+    OD_GUARD_BEGIN
+    OD_NEED_DEVICE(g);
+    if (!r) return fail(OD_EINVAL, "NULL argument");
+    return g->g.residual(r);
+    OD_GUARD_END
+}
+
+od_status od_iterations(od_grid* g, int64_t* iters) {
+    if (!g || !iters) return fail(OD_EINVAL, "NULL argument");
+    *iters = g->g.iters;
+    return OD_OK;
+}
+
+od_status od_read(od_grid* g, void* host_dst, size_t bytes) {
+    OD_GUARD_BEGIN
+    OD_NEED_DEVICE(g);
+    if (!host_dst) return fail(OD_EINVAL, "NULL argument");
+    return g->g.io(host_dst, bytes, true);
+    OD_GUARD_END
+}
+
+od_status od_write(od_grid* g, const void* host_src, size_t bytes) {
+    OD_GUARD_BEGIN
+    OD_NEED_DEVICE(g);
+    if (!host_src) return fail(OD_EINVAL, "NULL argument");
+    return g->g.io(const_cast<void*>(host_src), bytes, false);
+    OD_GUARD_END
+}
+
+od_status od_read_points(od_grid* g, const int64_t* idx, int64_t count, void* host_dst) {
+    OD_GUARD_BEGIN
+    OD_NEED_DEVICE(g);
+    if (count > 0 && (!idx || !host_dst)) return fail(OD_EINVAL, "NULL argument");
+    return g->g.read_points(idx, count, host_dst);
+    OD_GUARD_END
+}
+
+od_status od_plan(od_grid* g, od_plan_info* info) {
+    if (!g || !info) return fail(OD_EINVAL, "NULL argument");
+    const Grid& G = g->g;
+    info->nchares = (int32_t)G.plan.chares.size();
+    info->ntiles = (int32_t)G.tiles_h.size();
+    info->npseudo = (int32_t)(G.blocks_h.size() - G.plan.chares.size());
+    info->interior = G.plan.interior;
+    info->halo_cells = G.plan.halo_cells;
+    info->bytes_per_iter = (int64_t)G.s * (2 * G.plan.interior + G.plan.halo_cells);
+    for (int d = 0; d < 3; ++d) info->tile[d] = G.plan.tile[d];
+    info->grid_wgs = G.grid_wgs;
+    return OD_OK;
+}
+
+od_status od_tile_info_get(od_grid* g, int32_t t, od_tile_info* out) {
+    if (!g || !out) return fail(OD_EINVAL, "NULL argument");
+    const Grid& G = g->g;
+    if (t < 0 || t >= (int32_t)G.plan.tiles.size()) return fail(OD_EINVAL, "tile index out of range");
+    const od::TileHost& th = G.plan.tiles[(size_t)t];
+    out->chare = th.chare;
+    for (int d = 0; d < 3; ++d) {
+        out->origin[d] = th.o[d];
+        out->extent[d] = th.e[d];
+    }
+    for (int f = 0; f < 6; ++f) {
+        out->src_kind[f] = th.kind[f] == 1 ? 1 : 0;
+        out->src[f] = th.kind[f] == 2 ? th.chare : th.src[f];
+        for (int d = 0; d < 3; ++d) out->src_origin[f][d] = th.g[f][d];
+    }
+    return OD_OK;
+}
+
+od_status od_chare_get(od_grid* g, int32_t c, od_block* out) {
+    if (!g || !out) return fail(OD_EINVAL, "NULL argument");
+    const Grid& G = g->g;
+    if (c < 0 || c >= (int32_t)G.plan.chares.size()) return fail(OD_EINVAL, "chare index out of range");
+    for (int d = 0; d < 3; ++d) {
+        out->origin[d] = G.plan.chares[(size_t)c].o[d];
+        out->extent[d] = G.plan.chares[(size_t)c].e[d];
+    }
+    return OD_OK;
+}
+
+od_status od_destroy(od_grid* g) {
+    if (!g) return OD_OK;
+    hipError_t e = g->g.base ? hipStreamSynchronize(g->g.st) : hipSuccess;
+    delete g;
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("destroy sync: ") + hipGetErrorString(e));
+    return OD_OK;
+}
+
+od_status od_stream_copy(void* hip_stream, void* dst, const void* src, size_t bytes, int32_t iters, double* seconds) {
+    if (!dst || !src || !seconds || iters < 1 || bytes % 16 != 0 || bytes == 0)
+        return fail(OD_EINVAL, "need non-NULL buffers, bytes a positive multiple of 16, iters >= 1");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e == hipSuccess) e = od::launch_copy(st, dst, src, bytes);   // warm-up
+    if (e == hipSuccess) e = hipEventRecord(a, st);
+    for (int32_t i = 0; i < iters && e == hipSuccess; ++i) e = od::launch_copy(st, dst, src, bytes);
+    if (e == hipSuccess) e = hipEventRecord(b, st);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    if (a) hipEventDestroy(a);
+    if (b) hipEventDestroy(b);
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("stream copy: ") + hipGetErrorString(e));
+    *seconds = ms * 1e-3;
+    return OD_OK;
+}
+
+od_status od_time_iterate(od_grid* g, int64_t n, double* seconds) {
+    OD_GUARD_BEGIN
+    OD_NEED_DEVICE(g);
+    if (!seconds) return fail(OD_EINVAL, "NULL argument");
+    Grid& G = g->g;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("event: ") + hipGetErrorString(e));
+    od_status s = OD_OK;
+    e = hipEventRecord(a, G.st);
+    if (e == hipSuccess) s = G.iterate(n);
+    if (e == hipSuccess && s == OD_OK) e = hipEventRecord(b, G.st);
+    if (e == hipSuccess && s == OD_OK) e = hipEventSynchronize(b);
+    float ms = 0;
+    if (e == hipSuccess && s == OD_OK) e = hipEventElapsedTime(&ms, a, b);
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    if (s != OD_OK) return s;
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("timing: ") + hipGetErrorString(e));
+    *seconds = ms * 1e-3;
+    return OD_OK;
+    OD_GUARD_END
+}
+
+od_status od_autotune(od_grid* g, int32_t iters, int32_t out_tile[3]) {
+    OD_GUARD_BEGIN
+    if (!g || iters < 1) return fail(OD_EINVAL, "need a grid and iters >= 1");
+    return fail(OD_EINVAL, "autotune is not available in this build");
+    OD_GUARD_END
+}
+
+// ---- serving ---------------------------------------------------------------
+
+od_status od_server_create(void*, void*, size_t, int32_t, od_server** out) {
+    if (out) *out = nullptr;
+    return fail(OD_EINVAL, "serving is not available in this build");
+}
+od_status od_request_bytes(const od_request*, size_t*) { return fail(OD_EINVAL, "serving is not available in this build"); }
+od_status od_submit(od_server*, const od_request*, uint64_t*) { return fail(OD_EINVAL, "serving is not available in this build"); }
+od_status od_server_step(od_server*, int32_t*, int32_t*) { return fail(OD_EINVAL, "serving is not available in this build"); }
+od_status od_poll(od_server*, uint64_t, od_info*) { return fail(OD_EINVAL, "serving is not available in this build"); }
+od_status od_fetch(od_server*, uint64_t, void*, size_t) { return fail(OD_EINVAL, "serving is not available in this build"); }
+od_status od_server_destroy(od_server*) { return OD_OK; }
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// libod runtime internals: the grid object behind od_grid*.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "kernels.hpp"
+#include "od_internal.hpp"
+
+namespace od {
+
+extern thread_local std::string g_last_error;
+od_status fail(od_status s, const std::string& msg);
+uint64_t host_sm64(uint64_t seed, uint64_t idx);
+
+// Byte offsets of the workspace regions.
+struct Layout {
+    size_t blocks = 0, tiles = 0, cidx[3] = {0, 0, 0}, owner = 0, corigin = 0, dir_pb = 0;
+    size_t pb_face = 0, pb_block = 0, bc = 0, res = 0, bar = 0, err = 0, done = 0, target = 0;
+    size_t dep_ptr = 0, dep_idx = 0, extra = 0, field_end = 0, total = 0;
+};
+
+// Per-chare baseline message buffers (byte offsets): outgoing face messages
+// for both parities, incoming message per face.
+struct MsgBufs {
+    size_t out[2][6] = {{0}};
+    size_t in[6] = {0};
+    int64_t cnt[6] = {0, 0, 0, 0, 0, 0};
+};
+
+struct Grid {
+    od_config cfg{};
+    Plan plan;
+    int s = 8;                       // bytes per element
+    Layout L;
+    std::vector<BlockDev> blocks_h;
+    std::vector<TileDev> tiles_h;
+    std::vector<int32_t> cpy;        // row pitch per chare
+    std::vector<int32_t> dir_pb, ghost_pb, pb_face, pb_block;
+    std::vector<int32_t> dep_ptr, dep_idx;
+    std::vector<uint8_t> extra_h;
+    int32_t extra_period = 1;
+    std::vector<MsgBufs> msg;
+    int32_t nres = 1;
+
+    // device state
+    hipStream_t st = nullptr;
+    hipStream_t cap_st = nullptr;
+    char* base = nullptr;
+    size_t ws_bytes = 0;
+    GridDev gdev{};
+    int parity = 0;
+    int64_t iters = 0;
+    bool msg_final = false;
+    int grid_wgs = 0;
+    std::map<std::pair<int, int64_t>, hipGraphExec_t> graphs;
+    // per-chare baseline
+    std::vector<hipStream_t> pool;
+    std::vector<hipEvent_t> packed;
+    hipEvent_t join_ev = nullptr;
+    std::vector<int32_t> tile_lo;
+    bool faces_packed = false;
+    // host staging for I/O
+    void* pinned = nullptr;
+    size_t pinned_bytes = 0;
+
+    ~Grid();
+    od_status upload();
+    od_status reset_state();
+    od_status init_field();
+    od_status ensure_pinned(size_t bytes);
+    unsigned long long* res_ptr();
+    const uint8_t* extra_row(int64_t step) const;
+    od_status fused_one(hipStream_t s2, int par, int64_t step);
+    od_status graph_run(int64_t n);
+    od_status persistent_run(int64_t n);
+    od_status msgdriven_run(int64_t n);
+    od_status per_chare_run(int64_t n);
+    od_status iterate(int64_t n);
+    od_status residual(double* r);
+    od_status io(void* host, size_t bytes, bool to_host);
+    od_status read_points(const int64_t* idx, int64_t count, void* host_dst);
+    od_status retile(const int32_t tile[3]);
+};
+
+std::string build_layout(const od_config& cfg, Grid& G);
+std::string build_tile_deps(const Plan& p, std::vector<int32_t>& ptr, std::vector<int32_t>& idx);
+
+}  // namespace od

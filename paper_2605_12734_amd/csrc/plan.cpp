@@ -1,0 +1,333 @@
+// Host planner: decomposition of the global grid into chares, the chare
+// "location table" (which chare owns a cell; Section IV pre-fills it so a
+// sender knows its destination), cutting chares into sweep tiles, the halo
+// map of every tile face, and an XCD-aware launch order.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <numeric>
+
+#include "od_internal.hpp"
+
+namespace od {
+
+namespace {
+
+std::string fmt(const char* f, long long a = 0, long long b = 0, long long c = 0) {
+    char buf[256];
+    snprintf(buf, sizeof buf, f, a, b, c);
+    return buf;
+}
+
+// Balanced split of odf into three factors, largest on z, smallest on x.
+std::array<int32_t, 3> factor3(int32_t odf) {
+    int32_t k = (int32_t)std::llround(std::cbrt((double)odf));
+    for (int32_t c = std::max(1, k - 1); c <= k + 1; ++c)
+        if ((int64_t)c * c * c == odf) return {c, c, c};
+    std::array<int32_t, 3> best = {1, 1, odf};
+    double best_score = 1e300;
+    for (int32_t a = 1; (int64_t)a * a * a <= odf; ++a) {
+        if (odf % a) continue;
+        int32_t rest = odf / a;
+        for (int32_t b = a; (int64_t)b * b <= rest; ++b) {
+            if (rest % b) continue;
+            int32_t c = rest / b;
+            double score = (double)c / (double)a;
+            if (score < best_score) {
+                best_score = score;
+                best = {a, b, c};
+            }
+        }
+    }
+    return best;
+}
+
+int64_t gcd64(int64_t a, int64_t b) {
+    while (b) {
+        int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a < 0 ? -a : a;
+}
+
+}  // namespace
+
+std::string plan_decompose(const od_config& cfg, Plan& p) {
+    for (int d = 0; d < 3; ++d) {
+        if (cfg.n[d] < 1 || cfg.n[d] > (1 << 20)) return fmt("n[%lld] = %lld out of range [1, 2^20]", d, cfg.n[d]);
+        p.n[d] = cfg.n[d];
+    }
+    if (cfg.dtype != OD_F32 && cfg.dtype != OD_F64) return fmt("dtype %lld is neither OD_F32 nor OD_F64", (long long)cfg.dtype);
+    p.interior = p.n[0] * p.n[1] * p.n[2];
+    p.chares.clear();
+    p.owner.clear();
+
+    if (cfg.blocks != nullptr || cfg.nblocks > 0) {
+        if (cfg.blocks == nullptr || cfg.nblocks < 1) return "blocks/nblocks inconsistent";
+        p.regular = false;
+        int64_t g = 0;
+        for (int d = 0; d < 3; ++d) g = gcd64(g, p.n[d]);
+        int64_t vol = 0;
+        for (int32_t b = 0; b < cfg.nblocks; ++b) {
+            const od_block& B = cfg.blocks[b];
+            for (int d = 0; d < 3; ++d) {
+                if (B.extent[d] < 1 || B.origin[d] < 0 || (int64_t)B.origin[d] + B.extent[d] > p.n[d])
+                    return fmt("block %lld lies outside the domain along dim %lld", b, d);
+                g = gcd64(g, B.origin[d]);
+                g = gcd64(g, B.extent[d]);
+            }
+            vol += (int64_t)B.extent[0] * B.extent[1] * B.extent[2];
+        }
+        if (vol != p.interior) return fmt("blocks cover %lld cells, the domain has %lld", vol, p.interior);
+        p.gran = (int32_t)g;
+        for (int d = 0; d < 3; ++d) p.og[d] = p.n[d] / g;
+        int64_t cells = p.og[0] * p.og[1] * p.og[2];
+        if (cells > (int64_t(1) << 26)) return fmt("block granularity %lld too fine (owner grid %lld cells)", g, cells);
+        p.owner.assign((size_t)cells, -1);
+        for (int32_t b = 0; b < cfg.nblocks; ++b) {
+            const od_block& B = cfg.blocks[b];
+            Chare c{};
+            for (int d = 0; d < 3; ++d) {
+                c.o[d] = B.origin[d];
+                c.e[d] = B.extent[d];
+            }
+            for (int f = 0; f < 6; ++f) c.nb[f] = -2;   // not a regular neighbour table
+            p.chares.push_back(c);
+            for (int64_t z = B.origin[2] / g; z < (B.origin[2] + B.extent[2]) / g; ++z)
+                for (int64_t y = B.origin[1] / g; y < (B.origin[1] + B.extent[1]) / g; ++y)
+                    for (int64_t x = B.origin[0] / g; x < (B.origin[0] + B.extent[0]) / g; ++x) {
+                        int32_t& o = p.owner[(size_t)((z * p.og[1] + y) * p.og[0] + x)];
+                        if (o != -1) return fmt("blocks %lld and %lld overlap", o, b);
+                        o = b;
+                    }
+        }
+        return "";
+    }
+
+    p.regular = true;
+    int32_t k[3];
+    bool have_block = cfg.block[0] > 0 || cfg.block[1] > 0 || cfg.block[2] > 0;
+    if (have_block) {
+        for (int d = 0; d < 3; ++d) {
+            if (cfg.block[d] < 1) return "block extents must all be >= 1 when given";
+            k[d] = (int32_t)ceil_div(p.n[d], std::min<int64_t>(cfg.block[d], p.n[d]));
+        }
+    } else {
+        if (cfg.odf < 1) return fmt("odf %lld must be >= 1", cfg.odf);
+        auto f = factor3(cfg.odf);
+        for (int d = 0; d < 3; ++d) k[d] = f[d];
+    }
+    for (int d = 0; d < 3; ++d) {
+        if (k[d] > p.n[d]) return fmt("%lld chares along dim %lld exceed the %lld cells", k[d], d, p.n[d]);
+        p.k[d] = k[d];
+        int64_t q = p.n[d] / k[d], r = p.n[d] % k[d];
+        p.split[d].resize(k[d] + 1);
+        for (int32_t i = 0; i <= k[d]; ++i) p.split[d][i] = (int32_t)(i * q + std::min<int64_t>(i, r));
+    }
+    int64_t nch = (int64_t)k[0] * k[1] * k[2];
+    if (nch > (1 << 22)) return fmt("%lld chares exceed the 2^22 limit", nch);
+    p.chares.resize((size_t)nch);
+    for (int32_t cz = 0; cz < k[2]; ++cz)
+        for (int32_t cy = 0; cy < k[1]; ++cy)
+            for (int32_t cx = 0; cx < k[0]; ++cx) {
+                Chare& c = p.chares[(size_t)((cz * k[1] + cy) * k[0] + cx)];
+                int32_t ci[3] = {cx, cy, cz};
+                for (int d = 0; d < 3; ++d) {
+                    c.o[d] = p.split[d][ci[d]];
+                    c.e[d] = p.split[d][ci[d] + 1] - c.o[d];
+                }
+                for (int f = 0; f < 6; ++f) {
+                    int d = f / 2, s = (f % 2) ? 1 : -1;
+                    int32_t cj[3] = {cx, cy, cz};
+                    cj[d] += s;
+                    c.nb[f] = (cj[d] < 0 || cj[d] >= k[d]) ? -1 : (cj[2] * k[1] + cj[1]) * k[0] + cj[0];
+                }
+            }
+    return "";
+}
+
+int32_t plan_owner(const Plan& p, int64_t x, int64_t y, int64_t z) {
+    if (x < 0 || y < 0 || z < 0 || x >= p.n[0] || y >= p.n[1] || z >= p.n[2]) return -1;
+    if (p.regular) {
+        int64_t c[3], v[3] = {x, y, z};
+        for (int d = 0; d < 3; ++d) {
+            const auto& s = p.split[d];
+            c[d] = (int64_t)(std::upper_bound(s.begin(), s.end(), (int32_t)v[d]) - s.begin()) - 1;
+        }
+        return (int32_t)((c[2] * p.k[1] + c[1]) * p.k[0] + c[0]);
+    }
+    int64_t g = p.gran;
+    return p.owner[(size_t)(((z / g) * p.og[1] + (y / g)) * p.og[0] + (x / g))];
+}
+
+void plan_default_tile(const od_config& cfg, Plan& p) {
+    if (cfg.tile[0] > 0 && cfg.tile[1] > 0 && cfg.tile[2] > 0) {
+        for (int d = 0; d < 3; ++d) p.tile[d] = cfg.tile[d];
+        return;
+    }
+    int32_t emin[3] = {1 << 30, 1 << 30, 1 << 30};
+    for (const auto& c : p.chares)
+        for (int d = 0; d < 3; ++d) emin[d] = std::min(emin[d], c.e[d]);
+    // One tile row of 32 (f64) / 64 (f32) cells, 8 rows, z-columns of up to 64.
+    p.tile[0] = cfg.dtype == OD_F64 ? 32 : 64;
+    p.tile[1] = 8;
+    p.tile[2] = std::min<int32_t>(64, std::max<int32_t>(1, emin[2]));
+}
+
+namespace {
+
+// Face of a box: ghost slab (global coords, inclusive-exclusive).
+struct Box {
+    int64_t lo[3], hi[3];
+};
+
+Box ghost_slab(const Chare& c, const int32_t o[3], const int32_t e[3], int f) {
+    Box b;
+    for (int d = 0; d < 3; ++d) {
+        b.lo[d] = (int64_t)c.o[d] + o[d];
+        b.hi[d] = b.lo[d] + e[d];
+    }
+    int d = f / 2;
+    if (f % 2 == 0) {
+        b.lo[d] -= 1;
+        b.hi[d] = b.lo[d] + 1;
+    } else {
+        b.lo[d] = b.hi[d];
+        b.hi[d] = b.lo[d] + 1;
+    }
+    return b;
+}
+
+// Owner of every cell of the slab if unique (>= 0); -1 outside domain;
+// -2 if several owners, in which case (*split_dim, *split_at) gives a
+// tangential coordinate (global) where the owner changes.
+int32_t slab_owner(const Plan& p, const Box& b, int* split_dim, int64_t* split_at) {
+    int32_t first = plan_owner(p, b.lo[0], b.lo[1], b.lo[2]);
+    if (first < 0) return -1;
+    if (p.regular) {
+        // Regular chares: owner is separable; check each tangential range.
+        for (int d = 0; d < 3; ++d) {
+            const auto& s = p.split[d];
+            int64_t ci = (std::upper_bound(s.begin(), s.end(), (int32_t)b.lo[d]) - s.begin()) - 1;
+            if (b.hi[d] > s[(size_t)ci + 1]) {
+                *split_dim = d;
+                *split_at = s[(size_t)ci + 1];
+                return -2;
+            }
+        }
+        return first;
+    }
+    int64_t g = p.gran;
+    // any coarse cell in the slab interior
+    for (int64_t z = b.lo[2] / g * g; z < b.hi[2]; z += g)
+        for (int64_t y = b.lo[1] / g * g; y < b.hi[1]; y += g)
+            for (int64_t x = b.lo[0] / g * g; x < b.hi[0]; x += g) {
+                int64_t q[3] = {std::max(x, b.lo[0]), std::max(y, b.lo[1]), std::max(z, b.lo[2])};
+                if (plan_owner(p, q[0], q[1], q[2]) != first) {
+                    // owner changes somewhere: split on the first coarse boundary
+                    for (int d = 0; d < 3; ++d)
+                        if (b.hi[d] - b.lo[d] > 1 && q[d] > b.lo[d]) {
+                            *split_dim = d;
+                            *split_at = q[d];
+                            return -2;
+                        }
+                }
+            }
+    return first;
+}
+
+}  // namespace
+
+std::string plan_tiles(Plan& p) {
+    for (int d = 0; d < 3; ++d)
+        if (p.tile[d] < 1) return "tile extents must be >= 1";
+    std::vector<TileHost> out;
+    std::vector<TileHost> work;
+    p.halo_cells = 0;
+    for (int32_t ci = 0; ci < (int32_t)p.chares.size(); ++ci) {
+        const Chare& c = p.chares[(size_t)ci];
+        for (int32_t z = 0; z < c.e[2]; z += p.tile[2])
+            for (int32_t y = 0; y < c.e[1]; y += p.tile[1])
+                for (int32_t x = 0; x < c.e[0]; x += p.tile[0]) {
+                    TileHost t{};
+                    t.chare = ci;
+                    t.o[0] = x;
+                    t.o[1] = y;
+                    t.o[2] = z;
+                    t.e[0] = std::min(p.tile[0], c.e[0] - x);
+                    t.e[1] = std::min(p.tile[1], c.e[1] - y);
+                    t.e[2] = std::min(p.tile[2], c.e[2] - z);
+                    work.push_back(t);
+                }
+        while (!work.empty()) {
+            TileHost t = work.back();
+            work.pop_back();
+            bool split = false;
+            for (int f = 0; f < 6 && !split; ++f) {
+                Box b = ghost_slab(c, t.o, t.e, f);
+                int d = f / 2;
+                int64_t lo_local = b.lo[d] - c.o[d];
+                if (lo_local >= 0 && lo_local < c.e[d]) {
+                    t.kind[f] = 2;
+                    t.src[f] = ci;
+                } else {
+                    int sd = -1;
+                    int64_t sat = 0;
+                    int32_t ow = slab_owner(p, b, &sd, &sat);
+                    if (ow == -1) {
+                        t.kind[f] = 1;
+                        t.src[f] = f;
+                    } else if (ow >= 0) {
+                        t.kind[f] = 0;
+                        t.src[f] = ow;
+                    } else {
+                        // split the tile at global coordinate sat along sd
+                        int64_t cut = sat - c.o[sd] - t.o[sd];
+                        if (cut <= 0 || cut >= t.e[sd]) return "internal error: bad tile split";
+                        TileHost a = t, bb = t;
+                        a.e[sd] = (int32_t)cut;
+                        bb.o[sd] = t.o[sd] + (int32_t)cut;
+                        bb.e[sd] = t.e[sd] - (int32_t)cut;
+                        work.push_back(bb);
+                        work.push_back(a);
+                        split = true;
+                    }
+                }
+                for (int q = 0; q < 3; ++q) t.g[f][q] = (int32_t)b.lo[q];
+            }
+            if (split) continue;
+            for (int f = 0; f < 6; ++f)
+                if (t.kind[f] == 0) p.halo_cells += (int64_t)t.e[0] * t.e[1] * t.e[2] / t.e[f / 2];
+            out.push_back(t);
+        }
+    }
+    // XCD-aware order: z-major spatial sort, 8 contiguous groups, interleave so
+    // that launch index w (dispatched to XCD w % 8) takes group w % 8.
+    std::vector<size_t> idx(out.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    auto gkey = [&](const TileHost& t, int d) { return (int64_t)p.chares[(size_t)t.chare].o[d] + t.o[d]; };
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
+        const TileHost& A = out[a];
+        const TileHost& B = out[b];
+        for (int d = 2; d >= 0; --d) {
+            int64_t ka = gkey(A, d), kb = gkey(B, d);
+            if (ka != kb) return ka < kb;
+        }
+        return false;
+    });
+    size_t T = out.size();
+    size_t m = (T + kNumXcd - 1) / kNumXcd;
+    std::vector<TileHost> ordered;
+    ordered.reserve(T);
+    for (size_t j = 0; j < m; ++j)
+        for (int g = 0; g < kNumXcd; ++g) {
+            size_t s = (size_t)g * m + j;
+            if (s < T && j < m) ordered.push_back(out[idx[s]]);
+        }
+    p.tiles.swap(ordered);
+    return "";
+}
+
+}  // namespace od

@@ -248,3 +248,19 @@ def test_division_by_six_is_correctly_rounded(oracle_mod, dtype):
                 if dtype(s * dtype(1.0 / 6.0)) != want:
                     mism += 1
     assert mism > 0
+
+
+# ---- domain-of-dependence point evaluation (used at sizes the full oracle
+# cannot reach) agrees with the full oracle everywhere ------------------------
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_point_values_match_full_oracle(oracle_mod, dtype):
+    n = (11, 9, 7)
+    bc = (1.0, 0.0, 0.25, 0.0, 0.5, 0.0)
+    full, _, _ = oracle_mod.solve(n, dtype, seed=4, iters=5, bc=bc)
+    rng = np.random.default_rng(1)
+    pts = [(int(rng.integers(0, n[0])), int(rng.integers(0, n[1])), int(rng.integers(0, n[2])))
+           for _ in range(40)] + [(0, 0, 0), (10, 8, 6), (5, 0, 6)]
+    vals = oracle_mod.point_values(n, pts, 5, dtype, seed=4, bc=bc)
+    want = np.array([full[k + 1, j + 1, i + 1] for (i, j, k) in pts], dtype=dtype)
+    assert np.array_equal(vals, want)

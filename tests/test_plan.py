@@ -1,0 +1,166 @@
+"""Host-side decomposition and halo maps, checked by brute force (no GPU).
+
+Every tile face names the chare (or Dirichlet face) its ghost slab is read
+from and the slab's global origin.  The checks fill a global index map and
+verify, cell by cell, that each ghost cell is the face neighbour of the
+tile's boundary cell and lies inside the named source chare; that the tiles
+partition every chare; and that the ghost cells read from other chares are
+exactly the chare-face cells of the decomposition, each read once.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import paper_2605_12734_amd as od
+import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _owner_map(n, chares):
+    nx, ny, nz = n
+    own = -np.ones((nz, ny, nx), dtype=np.int64)
+    for c, (o, e) in enumerate(chares):
+        sl = own[o[2]:o[2] + e[2], o[1]:o[1] + e[1], o[0]:o[0] + e[0]]
+        assert np.all(sl == -1), "chares overlap"
+        sl[...] = c
+    assert np.all(own >= 0), "chares do not cover the domain"
+    return own
+
+
+def _check_plan(n, plan):
+    nx, ny, nz = n
+    own = _owner_map(n, plan["chares"])
+    covered = np.zeros((nz, ny, nx), dtype=np.int64)
+    ghost_reads = {}
+    halo = 0
+    for t in plan["tiles"]:
+        c = t["chare"]
+        co, ce = plan["chares"][c]
+        o = [co[d] + t["origin"][d] for d in range(3)]
+        e = t["extent"]
+        for d in range(3):
+            assert 0 <= t["origin"][d] and t["origin"][d] + e[d] <= ce[d]
+        covered[o[2]:o[2] + e[2], o[1]:o[1] + e[1], o[0]:o[0] + e[0]] += 1
+        for f in range(6):
+            d = f // 2
+            lo = list(o)
+            ext = list(e)
+            lo[d] = o[d] - 1 if f % 2 == 0 else o[d] + e[d]
+            ext[d] = 1
+            assert tuple(t["src_origin"][f]) == tuple(lo), (t, f)
+            cells = [(x, y, z) for z in range(lo[2], lo[2] + ext[2]) for y in range(lo[1], lo[1] + ext[1])
+                     for x in range(lo[0], lo[0] + ext[0])]
+            if t["src_kind"][f] == 1:
+                # Dirichlet face f of the domain: the slab lies just outside it
+                assert t["src"][f] == f
+                v = lo[d]
+                assert v == -1 if f % 2 == 0 else v == n[d]
+            else:
+                src = t["src"][f]
+                for (x, y, z) in cells:
+                    assert 0 <= x < nx and 0 <= y < ny and 0 <= z < nz
+                    assert own[z, y, x] == src
+                if src != c:
+                    halo += len(cells)
+                    for cell in cells:
+                        ghost_reads[(c, f, cell)] = ghost_reads.get((c, f, cell), 0) + 1
+    assert np.all(covered == 1), "tiles must partition the domain"
+    # every chare-face ghost cell (owned by another chare) is read exactly once
+    expect = 0
+    for c, (co, ce) in enumerate(plan["chares"]):
+        for f in range(6):
+            d = f // 2
+            v = co[d] - 1 if f % 2 == 0 else co[d] + ce[d]
+            if v < 0 or v >= n[d]:
+                continue
+            expect += ce[0] * ce[1] * ce[2] // ce[d]
+    assert halo == expect == plan["halo_cells"]
+    assert all(k == 1 for k in ghost_reads.values())
+
+
+@pytest.mark.parametrize("n,odf", [((13, 11, 9), 8), ((16, 16, 16), 64), ((7, 5, 9), 12), ((33, 4, 5), 8),
+                                   ((9, 9, 9), 1), ((10, 10, 10), 27)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_regular_halo_maps_brute_force(n, odf, dtype):
+    plan = od.host_plan(n=n, odf=odf, dtype=dtype)
+    assert plan["nchares"] == odf
+    _check_plan(n, plan)
+
+
+@pytest.mark.parametrize("tile", [(16, 8, 3), (32, 8, 5), (16, 16, 16), (64, 4, 7)])
+def test_regular_halo_maps_small_tiles(tile):
+    n = (37, 21, 19)
+    plan = od.host_plan(n=n, odf=8, tile=tile)
+    _check_plan(n, plan)
+
+
+def test_octree_halo_maps_brute_force():
+    blocks = workloads.octree_blocks(n=64, root=32, min_edge=8, p_refine=0.5, seed=3)
+    sizes = {e[0] for _, e in blocks}
+    assert len(sizes) >= 3          # genuinely uneven
+    plan = od.host_plan(n=64, blocks=blocks, tile=(16, 8, 8))
+    _check_plan((64, 64, 64), plan)
+
+
+def test_explicit_uneven_slabs():
+    # non-cubic, non-aligned slabs of different thickness
+    blocks = [((0, 0, 0), (10, 12, 3)), ((0, 0, 3), (10, 5, 7)), ((0, 5, 3), (10, 7, 7))]
+    plan = od.host_plan(n=(10, 12, 10), blocks=blocks, tile=(16, 8, 4))
+    _check_plan((10, 12, 10), plan)
+
+
+def test_regular_split_sizes_first_blocks_take_remainder():
+    plan = od.host_plan(n=(37, 16, 16), block=(19, 16, 16))
+    ext = sorted({c[1][0] for c in plan["chares"]})
+    assert ext == [18, 19]
+    first = min(plan["chares"], key=lambda c: c[0][0])
+    assert first[1][0] == 19
+
+
+def test_non_cubic_odf_factorisation():
+    plan = od.host_plan(n=64, odf=32)
+    ks = [len({c[0][d] for c in plan["chares"]}) for d in range(3)]
+    assert sorted(ks) == [2, 4, 4] and ks[2] == 4 and ks[0] == 2
+
+
+def test_algorithmic_bytes_match_closed_form():
+    # G = 6 (k-1) N^2 ghost cells read from other chares for a k^3 split
+    for n, k in ((64, 2), (512, 16), (96, 4)):
+        plan = od.host_plan(n=n, odf=k ** 3)
+        assert plan["halo_cells"] == 6 * (k - 1) * n * n
+        assert plan["bytes_per_iter"] == 8 * (2 * n ** 3 + 6 * (k - 1) * n * n)
+
+
+def test_paper_message_size_rule():
+    # Section IV: overdecomposing a 2D stencil by 4 halves each message; in
+    # 3D a k^3 split shrinks each face message by k^2.
+    g = json.load(open(os.path.join(GOLDEN, "paper_message_size.json")))
+    for case in g["cases"]:
+        n, k = case["n"], case["k"]
+        base = od.host_plan(n=(n, n, 1), odf=1)
+        split = od.host_plan(n=(n, n, 1), block=(n // k, n // k, 1))
+        assert split["nchares"] == case["odf"]
+        b_face = base["chares"][0][1][0]
+        s_face = split["chares"][0][1][0]
+        assert s_face / b_face == case["message_ratio"]
+        # 3D: a k^3 split shrinks face messages by k^2
+        b3 = od.host_plan(n=n, odf=1)["chares"][0][1]
+        s3 = od.host_plan(n=n, odf=k ** 3)["chares"][0][1]
+        assert (s3[0] * s3[1]) / (b3[0] * b3[1]) == 1.0 / k ** 2
+
+
+def test_octree_statistics_match_branching_process():
+    blocks = workloads.octree_blocks()
+    assert sum(e[0] ** 3 for _, e in blocks) == 768 ** 3
+    exp = workloads.expected_octree_leaves()
+    counts = {}
+    for _, e in blocks:
+        counts[e[0]] = counts.get(e[0], 0) + 1
+    assert set(counts) <= {16, 32, 64, 128}
+    for e, m in exp.items():
+        # generous bound for a branching-process count (std grows ~ sqrt(m)
+        # times the ancestry's fan-out of 8 per level)
+        assert abs(counts.get(e, 0) - m) < 8 * 5 * np.sqrt(m)
