@@ -84,7 +84,7 @@ def run_grid_leg(n, odf, dtype, exec_, iters, steps, warmup, tile=None):
             "launch_s": dev_s / (iters * steps)}
 
 
-def cpu_baseline(n, dtype, budget_s=12.0, max_iters=12):
+def cpu_baseline(n, dtype, budget_s=12.0, max_iters=200):
     import numpy as np
     import oracle
 
