@@ -105,6 +105,9 @@ typedef struct {
      * change, only the time. 0 = off. */
     int32_t imbalance_pct;
     int32_t imbalance_max_extra;
+    /* Implementation hints, 0 = defaults; none of them changes a result.
+     * bit 0: write the sweep's output with non-temporal (streaming) stores. */
+    int32_t hints;
 } od_config;
 
 struct od_grid;
@@ -184,8 +187,9 @@ od_status od_chare_get(struct od_grid* g, int32_t c, od_block* out);
 od_status od_destroy(struct od_grid* g);
 
 /* Measured HBM copy ceiling: copy `bytes` between two caller-owned device
- * buffers `iters` times on `hip_stream` with the library's streaming copy
- * kernel; *seconds = elapsed time of the copies (hipEvents). */
+ * buffers `iters` times on `hip_stream` with each of the library's
+ * streaming-copy kernel variants; *seconds = elapsed time (hipEvents) of the
+ * fastest variant's `iters` copies. */
 od_status od_stream_copy(void* hip_stream, void* dst, const void* src, size_t bytes,
                          int32_t iters, double* seconds);
 
@@ -228,21 +232,30 @@ typedef struct {
     double t_submit, t_admit, t_done;   /* host monotonic seconds       */
 } od_info;
 
-/* `dev_arena` of `arena_bytes` is the memory budget for resident solves;
- * at most `max_slots` solves are resident at once. */
+/* `dev_arena` of `arena_bytes` (caller-owned, 256-byte aligned) is the
+ * memory budget: a fixed control region for `max_slots` slots, the rest
+ * holds the resident solves.  At most `max_slots` solves are resident at
+ * once.  Starts the worker thread that owns `hip_stream`; timestamps are
+ * CLOCK_MONOTONIC seconds. */
 od_status od_server_create(void* hip_stream, void* dev_arena, size_t arena_bytes,
                            int32_t max_slots, struct od_server** out);
-/* Bytes a request needs in the arena. */
+/* Bytes of the fixed control region od_server_create carves from the
+ * start of the arena for `max_slots` slots. */
+od_status od_server_control_bytes(int32_t max_slots, size_t* bytes);
+/* Bytes a request needs in the arena (besides the control region). */
 od_status od_request_bytes(const od_request* req, size_t* bytes);
 /* Queue a request; never blocks.  OD_ENOMEM if it can never fit the arena,
  * OD_EAGAIN if the submission queue is full, OD_EINVAL for bad fields. */
 od_status od_submit(struct od_server* s, const od_request* req, uint64_t* ticket);
-/* Drive the server: admit queued requests that fit, run one scheduling
- * epoch on the device, retire finished solves.  Returns after the epoch. */
+/* The server's worker thread drives the device (admission, scheduling
+ * epochs, retirement).  This reports how many requests are resident
+ * (`active`) and waiting (`queued`); OD_ECANCELED once the server has
+ * stopped after a device error. */
 od_status od_server_step(struct od_server* s, int32_t* active, int32_t* queued);
 /* State of a request; OD_ENOTREADY while queued or running. */
 od_status od_poll(struct od_server* s, uint64_t ticket, od_info* out);
-/* Copy a finished request's padded global field to host and release it. */
+/* Copy a finished request's padded global field (global layout above) to
+ * host_dst and forget the request.  OD_ENOTREADY while it runs. */
 od_status od_fetch(struct od_server* s, uint64_t ticket, void* host_dst, size_t bytes);
 od_status od_server_destroy(struct od_server* s);
 

@@ -36,7 +36,7 @@ def _dims(n) -> tuple:
 
 def make_config(n, odf: int = 8, block=None, blocks: Optional[Sequence] = None, dtype="f64",
                 bc=DEFAULT_BC, seed: int = 12734, exec: str = "graph", tile=None,
-                imbalance_pct: int = 0, imbalance_max_extra: int = 0):
+                imbalance_pct: int = 0, imbalance_max_extra: int = 0, hints: int = 0):
     """Fill an od_config; returns (cfg, keepalive) where keepalive holds arrays it points to."""
     cfg = B.od_config()
     lib().od_config_default(ctypes.byref(cfg))
@@ -66,6 +66,7 @@ def make_config(n, odf: int = 8, block=None, blocks: Optional[Sequence] = None, 
             cfg.tile[d] = int(tile[d])
     cfg.imbalance_pct = int(imbalance_pct)
     cfg.imbalance_max_extra = int(imbalance_max_extra)
+    cfg.hints = int(hints)
     return cfg, keep
 
 
@@ -143,7 +144,7 @@ class Grid:
 
     def __init__(self, n, odf: int = 8, block=None, blocks=None, dtype="f64", bc=DEFAULT_BC,
                  seed: int = 12734, exec: str = "graph", tile=None, imbalance_pct: int = 0,
-                 imbalance_max_extra: int = 0, device: str = "cuda:0", stream=None):
+                 imbalance_max_extra: int = 0, hints: int = 0, device: str = "cuda:0", stream=None):
         import torch
 
         self.n = _dims(n)
@@ -151,7 +152,7 @@ class Grid:
         self.exec = exec
         cfg, self._keep = make_config(n=n, odf=odf, block=block, blocks=blocks, dtype=dtype, bc=bc, seed=seed,
                                       exec=exec, tile=tile, imbalance_pct=imbalance_pct,
-                                      imbalance_max_extra=imbalance_max_extra)
+                                      imbalance_max_extra=imbalance_max_extra, hints=hints)
         nbytes = ctypes.c_size_t()
         check(lib().od_workspace_bytes(ctypes.byref(cfg), ctypes.byref(nbytes)), "od_workspace_bytes")
         self.device = torch.device(device)

@@ -39,7 +39,7 @@ class od_config(ctypes.Structure):
     _fields_ = [("n", c_i64 * 3), ("block", c_i64 * 3), ("odf", c_i32), ("blocks", ctypes.POINTER(od_block)),
                 ("nblocks", c_i32), ("dtype", ctypes.c_int), ("bc", c_dbl * 6), ("seed", c_u64),
                 ("exec", ctypes.c_int), ("tile", c_i32 * 3), ("imbalance_pct", c_i32),
-                ("imbalance_max_extra", c_i32)]
+                ("imbalance_max_extra", c_i32), ("hints", c_i32)]
 
 
 class od_plan_info(ctypes.Structure):
@@ -83,6 +83,7 @@ SIGNATURES = {
     "od_autotune": (ctypes.c_int, [c_vp, c_i32, ctypes.POINTER(c_i32)]),
     "od_server_create": (ctypes.c_int, [c_vp, c_vp, c_sz, c_i32, ctypes.POINTER(c_vp)]),
     "od_request_bytes": (ctypes.c_int, [ctypes.POINTER(od_request), ctypes.POINTER(c_sz)]),
+    "od_server_control_bytes": (ctypes.c_int, [c_i32, ctypes.POINTER(c_sz)]),
     "od_submit": (ctypes.c_int, [c_vp, ctypes.POINTER(od_request), ctypes.POINTER(c_u64)]),
     "od_server_step": (ctypes.c_int, [c_vp, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]),
     "od_poll": (ctypes.c_int, [c_vp, c_u64, ctypes.POINTER(od_info)]),

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libod.so")
-SOURCES = ["kernels.hip", "plan.cpp", "od_api.cpp", "od_capi.cpp"]
+SOURCES = ["kernels.hip", "plan.cpp", "od_api.cpp", "od_capi.cpp", "tune.cpp", "server.cpp"]
 
 # Bit-exactness: no contraction into FMA, correctly rounded fp32 division,
 # subnormals kept.  Packed-fp32 instructions are disabled for the device.
@@ -53,7 +53,7 @@ def build(verbose: bool = False) -> str:
             sys.stderr.write(f"--- {src} failed ---\n{out}\n")
         raise RuntimeError("libod build failed: " + ", ".join(s for s, _ in failed))
     tmp = LIB + ".tmp"
-    link = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    link = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.run(link, check=True)

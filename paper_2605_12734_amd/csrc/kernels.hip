@@ -95,7 +95,8 @@ struct SW {
 
 template <typename T, int TX, int TY>
 __device__ __forceinline__ T sweep_tile(T* __restrict__ arena, const BlockDev* __restrict__ blocks,
-                                        const TileDev& t, const int parity, T* __restrict__ lds) {
+                                        const TileDev& t, const int parity, T* __restrict__ lds,
+                                        const int hints) {
     using S = SW<T, TX, TY>;
     using VT = typename V16<T>::t;
     constexpr int VX = S::VX;
@@ -114,12 +115,15 @@ __device__ __forceinline__ T sweep_tile(T* __restrict__ arena, const BlockDev* _
     // (a dynamically indexed local copy would be placed in scratch).
     const BlockDev* __restrict__ B = blocks + t.blk;
     const int64_t pz = B->pz;
-    const int64_t obase = (int64_t)(t.x0 + x) + (int64_t)(t.y0 + ly) * B->py + (int64_t)t.z0 * pz;
-    const T* own = arena + (parity ? B->off[1] : B->off[0]) + obase;
-    T* dst = arena + (parity ? B->off[0] : B->off[1]) + obase;
+    const T* own0 = arena + (parity ? B->off[1] : B->off[0]) + t.x0 + (int64_t)t.y0 * B->py + (int64_t)t.z0 * pz;
+    const int64_t obase = (int64_t)x + (int64_t)ly * B->py;
+    T* dst = arena + (parity ? B->off[0] : B->off[1]) + t.x0 + (int64_t)t.y0 * B->py + (int64_t)t.z0 * pz + obase;
 
-    // Face sources: base pointer of the ghost slab cell next to tile-local
-    // (x, ly, 0) (normal coordinate fixed) and the source's plane pitch.
+    // Every thread issues the same loads in the same order every plane (no
+    // load sits behind a branch), so the compiler can count outstanding
+    // loads exactly and the prefetched planes really overlap the compute.
+    // Threads with nothing to load read a safe in-bounds address instead:
+    // the tile's first (16-byte aligned) cell, `own0`.
     auto face = [&](const FaceDev& f, int64_t dx, int64_t dy, int64_t* fpz) -> const T* {
         const BlockDev* __restrict__ F = blocks + f.src;
         *fpz = F->pz;
@@ -135,56 +139,70 @@ __device__ __forceinline__ T sweep_tile(T* __restrict__ arena, const BlockDev* _
     const T* ypp = face(t.f[3], x, 0, &yp_pz);
     (void)zm_pz;
     (void)zp_pz;
-
+    const T* own = act ? own0 + obase : own0;
+    if (!act) {
+        zmp = own0;
+        zpp = own0;
+    }
     const bool do_xm = rowok && lx == 0;
     const bool do_xp = rowok && lx == (nx - 1) / VX;
     const bool do_ym = act && ly == 0;
     const bool do_yp = act && ly == ny - 1;
+    const int64_t own_pz = act ? pz : 0;
+    if (!do_xm) { xmp = own0; xm_pz = 0; }
+    if (!do_xp) { xpp = own0; xp_pz = 0; }
+    if (!do_ym) { ymp = own0; ym_pz = 0; }
+    if (!do_yp) { ypp = own0; yp_pz = 0; }
+
+    // fused pack: the thread holding the chare's x = 0 (x = ex-1) cell of a
+    // row also writes it into the chare's x- (x+) face message
+    T* wm = nullptr;
+    T* wp = nullptr;
+    int64_t wm_pz = 0, wp_pz = 0;
+    int ip = 0;
+    if (rowok) {
+        const int32_t mm = B->xmsg[0], mp = B->xmsg[1];
+        if (mm >= 0 && t.x0 == 0 && lx == 0) {
+            const BlockDev* __restrict__ M = blocks + mm;
+            wm = arena + (parity ? M->off[0] : M->off[1]) + (int64_t)(t.y0 + ly) + (int64_t)t.z0 * M->pz;
+            wm_pz = M->pz;
+        }
+        ip = B->ex - 1 - (t.x0 + x);
+        if (mp >= 0 && ip >= 0 && ip < VX && ip < nv) {
+            const BlockDev* __restrict__ M = blocks + mp;
+            wp = arena + (parity ? M->off[0] : M->off[1]) + (int64_t)(t.y0 + ly) + (int64_t)t.z0 * M->pz;
+            wp_pz = M->pz;
+        }
+    }
 
     auto L = [&](int b, int r, int c) -> T& { return lds[(b * S::LR + r) * S::LP + c]; };
     auto ldv = [](const T* p) -> VT { return *reinterpret_cast<const VT*>(p); };
-    auto plane = [&](int zz) -> const T* { return zz < 0 ? zmp : (zz >= nz ? zpp : own + (int64_t)zz * pz); };
+    // plane zz in [-1, nz]: -1 and nz come from the z faces
+    auto plane = [&](int zz) -> const T* { return zz < 0 ? zmp : (zz >= nz ? zpp : own + zz * own_pz); };
 
-    VT below = {}, cur = {}, above = {}, nxt = {};
-    T hxm = 0, hxp = 0, hxm_n = 0, hxp_n = 0;
-    T hym[VX], hyp[VX], hym_n[VX], hyp_n[VX];
-#pragma unroll
-    for (int i = 0; i < VX; ++i) hym[i] = hyp[i] = hym_n[i] = hyp_n[i] = 0;
-
-    auto ld_halo = [&](int zz, T& a, T& b, T* ym, T* yp) {
-        if (do_xm) a = xmp[(int64_t)zz * xm_pz];
-        if (do_xp) b = xpp[(int64_t)zz * xp_pz];
-        if (do_ym) {
-#pragma unroll
-            for (int i = 0; i < VX; ++i)
-                if (i < nv) ym[i] = ymp[(int64_t)zz * ym_pz + i];
-        }
-        if (do_yp) {
-#pragma unroll
-            for (int i = 0; i < VX; ++i)
-                if (i < nv) yp[i] = ypp[(int64_t)zz * yp_pz + i];
-        }
-    };
-
-    if (act) {
-        below = ldv(zmp);
-        cur = ldv(own);
-    }
-    ld_halo(0, hxm, hxp, hym, hyp);
-    if (act) above = ldv(plane(1));
+    // register column: p0 = plane z-1, p1 = z, p2 = z+1, p3 = z+2, p4 = z+3
+    VT p0 = ldv(zmp);
+    VT p1 = ldv(own);
+    VT p2 = ldv(plane(1));
+    VT p3 = ldv(plane(2 <= nz ? 2 : nz));
+    VT hym = ldv(ymp), hyp = ldv(ypp);
+    T hxm = xmp[0], hxp = xpp[0];
 
     T r = 0;
     for (int z = 0; z < nz; ++z) {
         const int b = z & 1;
-        // prefetch the next plane and its halo while this one is computed
-        if (z + 1 < nz) ld_halo(z + 1, hxm_n, hxp_n, hym_n, hyp_n);
-        if (act && z + 2 <= nz) nxt = ldv(plane(z + 2));
+        // prefetch: plane z+3 (clamped to the z+ face) and the halo of z+1
+        const int zq = z + 3 <= nz ? z + 3 : nz;
+        const VT p4 = ldv(plane(zq));
+        const int zh = z + 1 < nz ? z + 1 : z;
+        const VT nym = ldv(ymp + zh * ym_pz), nyp = ldv(ypp + zh * yp_pz);
+        const T nxm = xmp[zh * xm_pz], nxp = xpp[zh * xp_pz];
 
         // stage plane z with its x/y halo
         if (act) {
 #pragma unroll
             for (int i = 0; i < VX; ++i)
-                if (i < nv) L(b, ly + 1, VX + x + i) = cur[i];
+                if (i < nv) L(b, ly + 1, VX + x + i) = p1[i];
         }
         if (do_xm) L(b, ly + 1, VX - 1) = hxm;
         if (do_xp) L(b, ly + 1, VX + nx) = hxp;
@@ -204,39 +222,47 @@ __device__ __forceinline__ T sweep_tile(T* __restrict__ arena, const BlockDev* _
             VT out;
 #pragma unroll
             for (int i = 0; i < VX; ++i) {
-                T s = L(b, ly + 1, VX + x + i - 1);
-                s = s + L(b, ly + 1, VX + x + i + 1);
+                // x neighbours inside the thread's vector come from registers,
+                // the ones across its edges from LDS (same values either way)
+                const T xm = i > 0 ? p1[i - 1] : L(b, ly + 1, VX + x - 1);
+                const T xp = (i < VX - 1 && i + 1 < nv) ? p1[i + 1] : L(b, ly + 1, VX + x + i + 1);
+                T s = xm;
+                s = s + xp;
                 s = s + L(b, ly, VX + x + i);
                 s = s + L(b, ly + 2, VX + x + i);
-                s = s + below[i];
-                s = s + above[i];
+                s = s + p0[i];
+                s = s + p2[i];
                 const T v = s / (T)6;
                 out[i] = v;
                 if (i < nv) {
-                    T d = v - cur[i];
+                    T d = v - p1[i];
                     if (d < (T)0) d = -d;
                     if (d > r) r = d;
                 }
             }
-            T* o = dst + (int64_t)z * pz;
-            if (nv == VX) {
-                *reinterpret_cast<VT*>(o) = out;
-            } else {
+            // a partial vector only occurs at the chare's row end, where the
+            // lanes past nx land in the row's padding: store the whole vector
+            if (hints & 1)
+                __builtin_nontemporal_store(out, reinterpret_cast<VT*>(dst + (int64_t)z * pz));
+            else
+                *reinterpret_cast<VT*>(dst + (int64_t)z * pz) = out;
+            if (wm) wm[(int64_t)z * wm_pz] = out[0];
+            if (wp) {
+                T vlast = out[0];
 #pragma unroll
-                for (int i = 0; i < VX; ++i)
-                    if (i < nv) o[i] = out[i];
+                for (int i = 1; i < VX; ++i)
+                    if (i == ip) vlast = out[i];
+                wp[(int64_t)z * wp_pz] = vlast;
             }
         }
-        below = cur;
-        cur = above;
-        above = nxt;
-        hxm = hxm_n;
-        hxp = hxp_n;
-#pragma unroll
-        for (int i = 0; i < VX; ++i) {
-            hym[i] = hym_n[i];
-            hyp[i] = hyp_n[i];
-        }
+        p0 = p1;
+        p1 = p2;
+        p2 = p3;
+        p3 = p4;
+        hym = nym;
+        hyp = nyp;
+        hxm = nxm;
+        hxp = nxp;
     }
     __syncthreads();   // LDS planes are reused by the next tile
     return r;
@@ -246,7 +272,7 @@ template <typename T, int TX, int TY>
 __global__ void __launch_bounds__((TX / V16<T>::N) * TY)
 k_sweep(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDev* __restrict__ tiles,
         int parity, unsigned long long* __restrict__ res, int zero_lo, int zero_hi,
-        const uint8_t* __restrict__ extra) {
+        const uint8_t* __restrict__ extra, int hints) {
     using S = SW<T, TX, TY>;
     __shared__ T lds[S::LDS];
     __shared__ T red[S::NT / 64];
@@ -255,7 +281,7 @@ k_sweep(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDe
     const TileDev t = tiles[blockIdx.x];
     const int reps = 1 + (extra ? (int)extra[t.blk] : 0);
     T r = 0;
-    for (int rep = 0; rep < reps; ++rep) r = sweep_tile<T, TX, TY>(arena, blocks, t, parity, lds);
+    for (int rep = 0; rep < reps; ++rep) r = sweep_tile<T, TX, TY>(arena, blocks, t, parity, lds, hints);
     wg_residual<T, S::NT>(r, &res[2 * t.rslot + (parity ^ 1)], red);
 }
 
@@ -301,7 +327,7 @@ __global__ void __launch_bounds__((TX / V16<T>::N) * TY)
 k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDev* __restrict__ tiles,
              int32_t ntiles, int parity, int64_t iters, unsigned long long* __restrict__ res, int32_t nres,
              unsigned int* bar, unsigned int* err, const uint8_t* __restrict__ extra, int32_t extra_period,
-             int32_t nchares, int64_t iter_base, int64_t wait_ticks) {
+             int32_t nchares, int64_t iter_base, int64_t wait_ticks, int hints) {
     using S = SW<T, TX, TY>;
     __shared__ T lds[S::LDS];
     __shared__ T red[S::NT / 64];
@@ -316,7 +342,7 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
             const TileDev t = tiles[ti];
             const int reps = 1 + (ex ? (int)ex[t.blk] : 0);
             T rr = 0;
-            for (int rep = 0; rep < reps; ++rep) rr = sweep_tile<T, TX, TY>(arena, blocks, t, p, lds);
+            for (int rep = 0; rep < reps; ++rep) rr = sweep_tile<T, TX, TY>(arena, blocks, t, p, lds, hints);
             if (slot >= 0 && slot != t.rslot) {
                 wg_residual<T, S::NT>(r, &res[2 * slot + (p ^ 1)], red);
                 r = 0;
@@ -333,24 +359,24 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
 
 // ---------------------------------------------------------------------------
 // message-driven scheduler: every workgroup owns the tiles w, w+G, w+2G, ...
-// (same XCD group as w) and repeatedly runs whichever owned tile is ready:
-// tile t may run step s+1 once every tile it reads halos from (and t itself)
-// has completed step s.  Because halo reads are symmetric, the same rule
-// guarantees nobody still reads the parity a tile overwrites.  Serving adds
-// per-solve check steps: at a check step the last finishing tile evaluates
-// the solve's residual and either stops the solve or opens the gate.
+// of the launch's tile list (same XCD group as w) and repeatedly runs
+// whichever owned tile is ready: tile t may run step s+1 once every tile it
+// reads halos from has completed step s (t itself has, by definition).
+// Because halo reads are symmetric, the same rule guarantees that nobody
+// still reads the parity a tile overwrites.  Serving adds per-solve decision
+// steps (multiples of check_every, and the cap): every tile of the solve
+// waits there until the last one to finish evaluates the solve's residual
+// and either stops the solve or opens the gate.
 
 __device__ __forceinline__ int32_t ld_acq(const int32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <typename T, int TX, int TY>
-__global__ void __launch_bounds__((TX / V16<T>::N) * TY) k_msgdriven(MsgArgs a) {
-    using S = SW<T, TX, TY>;
-    __shared__ T lds[S::LDS];
-    __shared__ T red[S::NT / 64];
+// One scheduler loop; `sweep(gid, step)` runs tile gid's step (reading
+// parity step & 1) with the whole workgroup and returns its residual.
+template <int NT, class SweepFn>
+__device__ __forceinline__ void msg_loop(const MsgArgs& a, SweepFn sweep, double* red) {
     __shared__ int32_t s_pick, s_step, s_stop;
-    T* arena = reinterpret_cast<T*>(a.arena);
     const int32_t G = gridDim.x;
     const int32_t w = blockIdx.x;
     const int32_t nown = a.ntiles > w ? (a.ntiles - w + G - 1) / G : 0;
@@ -361,7 +387,8 @@ __global__ void __launch_bounds__((TX / V16<T>::N) * TY) k_msgdriven(MsgArgs a) 
             int32_t pick = -1, step = 0, stop = 1;
             for (int32_t k = 0; k < nown && pick < 0; ++k) {
                 const int32_t j = (cursor + k) % nown;
-                const int32_t ti = w + j * G;
+                const int32_t li = w + j * G;
+                const int32_t ti = a.tile_list ? a.tile_list[li] : li;
                 const int32_t sv = a.tile_solve ? a.tile_solve[ti] : 0;
                 const int32_t d = ld_acq(&a.done[ti]);
                 int32_t tgt = ld_acq(&a.target[sv]);
@@ -383,10 +410,11 @@ __global__ void __launch_bounds__((TX / V16<T>::N) * TY) k_msgdriven(MsgArgs a) 
                     cursor = (j + 1) % nown;
                 }
             }
-            if (a.yield_flag && pick < 0 &&
-                __hip_atomic_load(a.yield_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0)
-                stop = 1;
-            if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) stop = 1;
+            // the host asks the launch to end: start no new task (every tile's
+            // state stays in HBM, a later launch resumes from it)
+            if (a.yield_flag && __hip_atomic_load(a.yield_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0)
+                stop = 1, pick = -1;
+            if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) stop = 1, pick = -1;
             s_pick = pick;
             s_step = step;
             s_stop = stop;
@@ -408,23 +436,18 @@ __global__ void __launch_bounds__((TX / V16<T>::N) * TY) k_msgdriven(MsgArgs a) 
         }
         idle_since = -1;
         __threadfence();   // acquire side: see the neighbours' step-`step` data
-        const TileDev t = a.tiles[pick];
-        const int p = step & 1;
         const int32_t sv = a.tile_solve ? a.tile_solve[pick] : 0;
-        const uint8_t* ex = a.extra ? a.extra + (size_t)(step % a.extra_period) * a.nchares : nullptr;
-        const int reps = 1 + (ex ? (int)ex[t.blk] : 0);
-        T r = 0;
-        for (int rep = 0; rep < reps; ++rep) r = sweep_tile<T, TX, TY>(arena, a.blocks, t, p, lds);
+        const double r = sweep(pick, step);
         const int32_t ns = step + 1;
         // A plain grid records only its target step's residual (slot ns & 1,
         // cleared before the launch).  A served solve records it at decision
-        // steps (multiples of check_every, and its cap), where every tile of
-        // the solve waits for the decision, so one slot per solve suffices.
+        // steps, where every tile of the solve waits for the decision, so one
+        // slot per solve suffices.
         if (a.final_only) {
-            if (ns == ld_acq(&a.target[sv])) wg_residual<T, S::NT>(r, &a.res[2 * sv + (ns & 1)], red);
+            if (ns == ld_acq(&a.target[sv])) wg_residual<double, NT>(r, &a.res[2 * sv + (ns & 1)], red);
         } else {
             const int32_t ce = a.check_every[sv];
-            if ((ce > 0 && ns % ce == 0) || ns == ld_acq(&a.target[sv])) wg_residual<T, S::NT>(r, &a.res[sv], red);
+            if ((ce > 0 && ns % ce == 0) || ns == ld_acq(&a.target[sv])) wg_residual<double, NT>(r, &a.res[sv], red);
         }
         __threadfence();   // release side: this tile's step-ns data before its counter
         __syncthreads();
@@ -446,8 +469,8 @@ __global__ void __launch_bounds__((TX / V16<T>::N) * TY) k_msgdriven(MsgArgs a) 
                         const bool fin = ns >= tgt || (ce > 0 && ns % ce == 0 && rv < a.tol[sv]);
                         if (fin) {
                             __hip_atomic_store(&a.final_step[sv], ns, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                            if (a.host_res) a.host_res[sv] = rb;
                             __threadfence_system();
+                            if (a.host_res) a.host_res[sv] = rb;
                             if (a.host_done) a.host_done[sv] = ns;
                             __threadfence_system();
                         } else {
@@ -459,6 +482,47 @@ __global__ void __launch_bounds__((TX / V16<T>::N) * TY) k_msgdriven(MsgArgs a) 
         }
         __syncthreads();
     }
+}
+
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__((TX / V16<T>::N) * TY) k_msgdriven(MsgArgs a) {
+    using S = SW<T, TX, TY>;
+    __shared__ T lds[S::LDS];
+    __shared__ double red[S::NT / 64];
+    T* arena = reinterpret_cast<T*>(a.arena);
+    auto sweep = [&](int32_t gid, int32_t step) -> double {
+        const TileDev t = a.tiles[gid];
+        const uint8_t* ex = a.extra ? a.extra + (size_t)(step % a.extra_period) * a.nchares : nullptr;
+        const int reps = 1 + (ex ? (int)ex[t.blk] : 0);
+        T r = 0;
+        for (int rep = 0; rep < reps; ++rep) r = sweep_tile<T, TX, TY>(arena, a.blocks, t, step & 1, lds, a.hints);
+        return (double)r;
+    };
+    msg_loop<S::NT>(a, sweep, red);
+}
+
+// Serving: tiles of independent fp64 and fp32 solves in one launch.  The two
+// tile variants have the same thread count; each task runs the variant of
+// its solve's dtype on a shared LDS buffer.  Block offsets are in elements
+// of the block's own dtype from the (256-byte aligned) arena base.
+template <int TX8, int TY8, int TX4, int TY4>
+__global__ void __launch_bounds__((TX8 / 2) * TY8) k_serve(MsgArgs a) {
+    using S8 = SW<double, TX8, TY8>;
+    using S4 = SW<float, TX4, TY4>;
+    static_assert(S8::NT == S4::NT, "fp64 and fp32 serving tiles need the same thread count");
+    constexpr int LDSB = S8::LDS * 8 > S4::LDS * 4 ? S8::LDS * 8 : S4::LDS * 4;
+    __shared__ __attribute__((aligned(16))) unsigned char lds_raw[LDSB];
+    __shared__ double red[S8::NT / 64];
+    auto sweep = [&](int32_t gid, int32_t step) -> double {
+        const TileDev t = a.tiles[gid];
+        const int32_t sv = a.tile_solve[gid];
+        if (a.solve_dtype[sv] == 8)
+            return (double)sweep_tile<double, TX8, TY8>(reinterpret_cast<double*>(a.arena), a.blocks, t, step & 1,
+                                                        reinterpret_cast<double*>(lds_raw), a.hints);
+        return (double)sweep_tile<float, TX4, TY4>(reinterpret_cast<float*>(a.arena), a.blocks, t, step & 1,
+                                                   reinterpret_cast<float*>(lds_raw), a.hints);
+    };
+    msg_loop<S8::NT>(a, sweep, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -494,13 +558,13 @@ int sweep_threads(int dtype_bytes, int tx, int ty) {
 
 hipError_t launch_sweep(int dtype_bytes, int tx, int ty, hipStream_t st, void* arena, const BlockDev* blocks,
                         const TileDev* tiles, int32_t ntiles, int parity, unsigned long long* res,
-                        int32_t zero_lo, int32_t zero_hi, const uint8_t* extra) {
+                        int32_t zero_lo, int32_t zero_hi, const uint8_t* extra, int hints) {
     if (ntiles <= 0) return hipSuccess;
 #define OD_LAUNCH(T, TX, TY)                                                                          \
     if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                      \
         hipLaunchKernelGGL((k_sweep<T, TX, TY>), dim3(ntiles), dim3(SW<T, TX, TY>::NT), 0, st,       \
                            reinterpret_cast<T*>(arena), blocks, tiles, parity, res, zero_lo, zero_hi, \
-                           extra);                                                                    \
+                           extra, hints);                                                             \
         return hipGetLastError();                                                                     \
     }
     OD_VARIANTS_F64(OD_LAUNCH)
@@ -541,14 +605,14 @@ hipError_t launch_persistent(int dtype_bytes, int tx, int ty, hipStream_t st, in
                              const BlockDev* blocks, const TileDev* tiles, int32_t ntiles, int parity,
                              int64_t iters, unsigned long long* res, int32_t nres, unsigned int* bar,
                              unsigned int* err, const uint8_t* extra, int32_t extra_period, int32_t nchares,
-                             int64_t iter_base) {
+                             int64_t iter_base, int hints) {
     if (iters <= 0) return hipSuccess;
     int64_t wait_ticks = device_wait_ticks();
 #define OD_LAUNCH(T, TX, TY)                                                                          \
     if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                      \
         T* ar = reinterpret_cast<T*>(arena);                                                          \
         void* args[] = {&ar, &blocks, &tiles, &ntiles, &parity, &iters, &res, &nres, &bar, &err,      \
-                        &extra, &extra_period, &nchares, &iter_base, &wait_ticks};                   \
+                        &extra, &extra_period, &nchares, &iter_base, &wait_ticks, &hints};                   \
         return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_persistent<T, TX, TY>),    \
                                           dim3(grid), dim3(SW<T, TX, TY>::NT), args, 0, st);          \
     }
@@ -556,6 +620,24 @@ hipError_t launch_persistent(int dtype_bytes, int tx, int ty, hipStream_t st, in
     OD_VARIANTS_F32(OD_LAUNCH)
 #undef OD_LAUNCH
     return hipErrorInvalidValue;
+}
+
+int serve_max_grid() {
+    int dev = 0, ncu = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_serve<kServeTx8, kServeTy8, kServeTx4, kServeTy4>,
+                                                     SW<double, kServeTx8, kServeTy8>::NT, 0) != hipSuccess)
+        return 0;
+    return per * ncu;
+}
+
+hipError_t launch_serve(hipStream_t st, int grid, const MsgArgs& a) {
+    MsgArgs ac = a;
+    void* args[] = {&ac};
+    return hipLaunchCooperativeKernel(
+        reinterpret_cast<const void*>(k_serve<kServeTx8, kServeTy8, kServeTx4, kServeTy4>), dim3(grid),
+        dim3(SW<double, kServeTx8, kServeTy8>::NT), args, 0, st);
 }
 
 hipError_t launch_msgdriven(int dtype_bytes, int tx, int ty, hipStream_t st, int grid, const MsgArgs& a) {
@@ -733,8 +815,8 @@ hipError_t launch_points(int dtype_bytes, hipStream_t st, const GridDev& g, int 
 // ---------------------------------------------------------------------------
 // per-chare baseline: face messages
 
-// Face f's message layout: x faces [z][y] (y fastest), y faces [z][x],
-// z faces [y][x] with the chare's row pitch.
+// Face f's message layout: x faces [z][y] (y fastest), y faces [z][x] and
+// z faces [y][x], both with the chare's row pitch.
 template <typename T>
 __global__ void k_pack(const T* __restrict__ arena, BlockDev B, int parity, FaceSet out) {
     const int f = blockIdx.y;
@@ -749,9 +831,10 @@ __global__ void k_pack(const T* __restrict__ arena, BlockDev B, int parity, Face
             z = e / B.ey;
             x = (f == 0) ? 0 : B.ex - 1;
         } else if (f < 4) {
-            x = e % B.ex;
-            z = e / B.ex;
+            x = e % B.py;
+            z = e / B.py;
             y = (f == 2) ? 0 : B.ey - 1;
+            if (x >= B.ex) continue;
         } else {
             x = e % B.py;
             y = e / B.py;
@@ -771,6 +854,45 @@ __global__ void k_unpack(FaceSet in, FaceSet ghost) {
     const int64_t cnt = in.cnt[f];
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * blockDim.x)
         d[e] = s[e];
+}
+
+// x-face messages of parity `par` from the chares' own storage (after the
+// field was initialised or written).
+template <typename T>
+__global__ void k_pack_xmsg(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const int32_t* list, int par) {
+    const int32_t c = list[blockIdx.y];
+    const BlockDev* B = blocks + c;
+    const int64_t cnt = (int64_t)B->ey * B->ez;
+    const T* u = arena + (par ? B->off[1] : B->off[0]);
+    for (int side = 0; side < 2; ++side) {
+        const int32_t m = B->xmsg[side];
+        if (m < 0) continue;
+        const BlockDev* M = blocks + m;
+        T* d = arena + (par ? M->off[1] : M->off[0]);
+        const int64_t x = side == 0 ? 0 : B->ex - 1;
+        for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * blockDim.x) {
+            const int64_t y = e % B->ey, z = e / B->ey;
+            d[y + z * M->pz] = u[x + y * B->py + z * B->pz];
+        }
+    }
+}
+
+hipError_t launch_pack_xmsg(int dtype_bytes, hipStream_t st, void* arena, const BlockDev* blocks, const int32_t* list,
+                            int32_t count, int par) {
+    if (count <= 0) return hipSuccess;
+    for (int32_t c0 = 0; c0 < count; c0 += 65535) {
+        const int32_t n = count - c0 < 65535 ? count - c0 : 65535;
+        dim3 grid(4, (unsigned)n);
+        if (dtype_bytes == 8)
+            hipLaunchKernelGGL(k_pack_xmsg<double>, grid, dim3(256), 0, st, reinterpret_cast<double*>(arena), blocks,
+                               list + c0, par);
+        else
+            hipLaunchKernelGGL(k_pack_xmsg<float>, grid, dim3(256), 0, st, reinterpret_cast<float*>(arena), blocks,
+                               list + c0, par);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_pack_b(int dtype_bytes, hipStream_t st, void* arena, const BlockDev& B, int parity,
@@ -799,24 +921,63 @@ hipError_t launch_unpack(int dtype_bytes, hipStream_t st, FaceSet in, FaceSet gh
 // ---------------------------------------------------------------------------
 // streaming copy (HBM ceiling)
 
-__global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n) {
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
-        dst[e] = src[e];
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <int U, bool NT>
+__global__ void __launch_bounds__(256) k_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst, int64_t n) {
+    // U independent 16-byte loads in flight per thread, then U stores
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; e + (U - 1) * stride < n; e += U * stride) {
+        u32x4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = NT ? __builtin_nontemporal_load(src + e + u * stride) : src[e + u * stride];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (NT)
+                __builtin_nontemporal_store(v[u], dst + e + u * stride);
+            else
+                dst[e + u * stride] = v[u];
+        }
+    }
+    for (; e < n; e += stride) dst[e] = src[e];
 }
 
-hipError_t launch_copy(hipStream_t st, void* dst, const void* src, size_t bytes) {
+struct CopyVariant {
+    int blocks_per_cu, unroll;
+    bool nt;
+};
+static const CopyVariant kCopyVariants[] = {{32, 1, false}, {16, 4, false}, {16, 4, true}, {64, 2, false},
+                                            {64, 2, true},  {8, 8, true}};
+
+int copy_variant_count() { return (int)(sizeof(kCopyVariants) / sizeof(kCopyVariants[0])); }
+
+hipError_t launch_copy(hipStream_t st, void* dst, const void* src, size_t bytes, int variant) {
     const int64_t n = (int64_t)(bytes / 16);
     int dev = 0, ncu = 256;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         ncu = 256;
+    const CopyVariant& cv = kCopyVariants[variant % copy_variant_count()];
     int64_t grid = (n + 255) / 256;
-    const int64_t cap = (int64_t)ncu * 32;
+    const int64_t cap = (int64_t)ncu * cv.blocks_per_cu;
     if (grid > cap) grid = cap;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_copy, dim3((unsigned)grid), dim3(256), 0, st, reinterpret_cast<const uint4*>(src),
-                       reinterpret_cast<uint4*>(dst), n);
-    return hipGetLastError();
+    const u32x4* s4 = reinterpret_cast<const u32x4*>(src);
+    u32x4* d4 = reinterpret_cast<u32x4*>(dst);
+#define OD_COPY(UU, NTT)                                                                        \
+    if (cv.unroll == UU && cv.nt == NTT) {                                                      \
+        hipLaunchKernelGGL((k_copy<UU, NTT>), dim3((unsigned)grid), dim3(256), 0, st, s4, d4, n); \
+        return hipGetLastError();                                                               \
+    }
+    OD_COPY(1, false)
+    OD_COPY(4, false)
+    OD_COPY(4, true)
+    OD_COPY(2, false)
+    OD_COPY(2, true)
+    OD_COPY(8, true)
+#undef OD_COPY
+    return hipErrorInvalidValue;
 }
 
 }  // namespace od

@@ -44,7 +44,7 @@ int sweep_threads(int dtype_bytes, int tx, int ty);
 hipError_t launch_sweep(int dtype_bytes, int tx, int ty, hipStream_t st, void* arena,
                         const BlockDev* blocks, const TileDev* tiles, int32_t ntiles, int parity,
                         unsigned long long* res, int32_t zero_lo, int32_t zero_hi,
-                        const uint8_t* extra);
+                        const uint8_t* extra, int hints);
 
 // Persistent cooperative sweep: all `iters` iterations in one launch with a
 // device-wide barrier between them.  `bar` = 2 zeroed uint32 (count,
@@ -55,7 +55,7 @@ hipError_t launch_persistent(int dtype_bytes, int tx, int ty, hipStream_t st, in
                              int32_t ntiles, int parity, int64_t iters,
                              unsigned long long* res, int32_t nres, unsigned int* bar,
                              unsigned int* err, const uint8_t* extra, int32_t extra_period,
-                             int32_t nchares, int64_t iter_base);
+                             int32_t nchares, int64_t iter_base, int hints);
 // Wall-clock ticks in `seconds` (bound of every device-side wait).
 int64_t device_wait_ticks(double seconds = 10.0);
 // Max co-resident workgroups of the persistent / message-driven kernels.
@@ -64,24 +64,27 @@ int persistent_max_grid(int dtype_bytes, int tx, int ty, int kind);
 // Message-driven cooperative sweep (see sched kernels): per-tile step
 // counters `done`, dependency lists (CSR: dep_ptr[ntiles+1], dep_idx).
 struct MsgArgs {
+    const int32_t* tile_list;   // launch's tiles (global ids); null => 0..ntiles-1
+    const int32_t* solve_dtype; // serving: bytes per element of each solve
     void* arena;
     const BlockDev* blocks;
     const TileDev* tiles;
-    int32_t ntiles;
+    int32_t ntiles;             // tiles in this launch
     const int32_t* dep_ptr;
     const int32_t* dep_idx;
-    int32_t* done;              // steps completed per tile (monotone)
+    int32_t* done;              // steps completed per tile (monotone), by global id
     const int32_t* target;      // per-solve target step (for a plain grid: 1 entry)
     const int32_t* tile_solve;  // solve of each tile (null => solve 0)
-    unsigned long long* res;    // per-solve residual, 2 slots (step parity)
+    unsigned long long* res;    // plain grid: 2 slots (step parity); serving: 1 slot per solve
     unsigned int* err;
     const uint8_t* extra;       // [period][nchares] or null
     int32_t extra_period;
     int32_t nchares;
     int64_t wait_ticks;         // bound on a workgroup's idle wait (wall-clock ticks)
     int32_t final_only;         // plain grid: record the residual only at the target step
+    int32_t hints;              // od_config.hints
     // serving only (null for a plain grid)
-    int32_t* solve_count;       // per solve, per step parity: tiles finished
+    int32_t* solve_count;       // per solve: tiles that finished the current decision step
     int32_t* gate;              // per solve: highest step whose check passed
     const int32_t* solve_ntiles;
     const int32_t* check_every;
@@ -92,6 +95,12 @@ struct MsgArgs {
     volatile int32_t* yield_flag;   // pinned host: nonzero => stop after current tasks
 };
 hipError_t launch_msgdriven(int dtype_bytes, int tx, int ty, hipStream_t st, int grid, const MsgArgs& a);
+
+// Serving kernel: fp64 tiles of (kServeTx8, kServeTy8) and fp32 tiles of
+// (kServeTx4, kServeTy4) columns, same thread count, one cooperative launch.
+constexpr int kServeTx8 = 32, kServeTy8 = 8, kServeTx4 = 32, kServeTy4 = 16;
+int serve_max_grid();
+hipError_t launch_serve(hipStream_t st, int grid, const MsgArgs& a);
 
 // Initialise parity 0 of every chare from seed, Dirichlet pseudo-blocks from bc.
 hipError_t launch_init(int dtype_bytes, hipStream_t st, const GridDev& g, int32_t nchares,
@@ -117,8 +126,13 @@ struct FaceSet {
 hipError_t launch_pack_b(int dtype_bytes, hipStream_t st, void* arena, const BlockDev& B, int parity,
                          const FaceSet& out);
 hipError_t launch_unpack(int dtype_bytes, hipStream_t st, FaceSet in, FaceSet ghost);
+// Fill the x-face messages (parity `par`) of the listed chares from their storage.
+hipError_t launch_pack_xmsg(int dtype_bytes, hipStream_t st, void* arena, const BlockDev* blocks, const int32_t* list,
+                            int32_t count, int par);
 
-// Streaming copy of `bytes` (multiple of 16) from src to dst.
-hipError_t launch_copy(hipStream_t st, void* dst, const void* src, size_t bytes);
+// Streaming copy of `bytes` (multiple of 16) from src to dst with copy
+// kernel variant `variant` (0 .. copy_variant_count()-1).
+int copy_variant_count();
+hipError_t launch_copy(hipStream_t st, void* dst, const void* src, size_t bytes, int variant);
 
 }  // namespace od

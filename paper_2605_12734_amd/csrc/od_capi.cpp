@@ -229,17 +229,21 @@ od_status od_stream_copy(void* hip_stream, void* dst, const void* src, size_t by
     hipEvent_t a = nullptr, b = nullptr;
     hipError_t e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
-    if (e == hipSuccess) e = od::launch_copy(st, dst, src, bytes);   // warm-up
-    if (e == hipSuccess) e = hipEventRecord(a, st);
-    for (int32_t i = 0; i < iters && e == hipSuccess; ++i) e = od::launch_copy(st, dst, src, bytes);
-    if (e == hipSuccess) e = hipEventRecord(b, st);
-    if (e == hipSuccess) e = hipEventSynchronize(b);
-    float ms = 0;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+    double best = 1e30;
+    for (int v = 0; v < od::copy_variant_count() && e == hipSuccess; ++v) {
+        e = od::launch_copy(st, dst, src, bytes, v);   // warm-up
+        if (e == hipSuccess) e = hipEventRecord(a, st);
+        for (int32_t i = 0; i < iters && e == hipSuccess; ++i) e = od::launch_copy(st, dst, src, bytes, v);
+        if (e == hipSuccess) e = hipEventRecord(b, st);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (e == hipSuccess) best = std::min(best, ms * 1e-3);
+    }
     if (a) hipEventDestroy(a);
     if (b) hipEventDestroy(b);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("stream copy: ") + hipGetErrorString(e));
-    *seconds = ms * 1e-3;
+    *seconds = best;
     return OD_OK;
 }
 
@@ -270,22 +274,10 @@ od_status od_time_iterate(od_grid* g, int64_t n, double* seconds) {
 
 od_status od_autotune(od_grid* g, int32_t iters, int32_t out_tile[3]) {
     OD_GUARD_BEGIN
-    if (!g || iters < 1) return fail(OD_EINVAL, "need a grid and iters >= 1");
-    return fail(OD_EINVAL, "autotune is not available in this build");
+    OD_NEED_DEVICE(g);
+    if (iters < 1) return fail(OD_EINVAL, "iters must be >= 1");
+    return od::autotune(g->g, iters, out_tile);
     OD_GUARD_END
 }
-
-// ---- serving ---------------------------------------------------------------
-
-od_status od_server_create(void*, void*, size_t, int32_t, od_server** out) {
-    if (out) *out = nullptr;
-    return fail(OD_EINVAL, "serving is not available in this build");
-}
-od_status od_request_bytes(const od_request*, size_t*) { return fail(OD_EINVAL, "serving is not available in this build"); }
-od_status od_submit(od_server*, const od_request*, uint64_t*) { return fail(OD_EINVAL, "serving is not available in this build"); }
-od_status od_server_step(od_server*, int32_t*, int32_t*) { return fail(OD_EINVAL, "serving is not available in this build"); }
-od_status od_poll(od_server*, uint64_t, od_info*) { return fail(OD_EINVAL, "serving is not available in this build"); }
-od_status od_fetch(od_server*, uint64_t, void*, size_t) { return fail(OD_EINVAL, "serving is not available in this build"); }
-od_status od_server_destroy(od_server*) { return OD_OK; }
 
 }  // extern "C"

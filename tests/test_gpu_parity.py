@@ -204,3 +204,37 @@ def test_imbalance_does_not_change_results(exec_):
     U, r, _ = _run(48, 11, odf=64, dtype="f64", exec=exec_, imbalance_pct=10, imbalance_max_extra=4)
     _assert_same(U, want)
     assert r == r_w
+
+
+@pytest.mark.parametrize("exec_,dtype", [("graph", "f64"), ("persistent", "f32"), ("fused", "f64")])
+def test_autotune_keeps_bits(exec_, dtype):
+    # tuning picks a tile shape by timing; it must not change a bit, and it
+    # must not disturb the field or the residual already computed
+    want5, _, r5 = _oracle(64, dtype, 5)
+    want, _, r_w = _oracle(64, dtype, 15)
+    g = od.Grid(64, odf=64, dtype=dtype, exec=exec_)
+    try:
+        g.iterate(5)
+        assert g.residual() == r5
+        tile = g.autotune(iters=1)
+        assert g.plan()["tile"] == tuple(tile)
+        assert g.residual() == r5
+        _assert_same(g.read(), want5)
+        g.iterate(10)
+        r = g.residual()
+        U = g.read()
+    finally:
+        g.close()
+    _assert_same(U, want)
+    assert r == r_w
+
+
+@pytest.mark.parametrize("hints", [1, 2, 3])
+@pytest.mark.parametrize("exec_", ["graph", "msgdriven"])
+def test_hints_keep_bits(hints, exec_):
+    # bit 0: non-temporal output stores; bit 1: x halos read straight from the
+    # neighbour's storage instead of the fused x-face messages
+    want, _, r_w = _oracle((70, 36, 40), "f64", 9, seed=3)
+    U, r, _ = _run((70, 36, 40), 9, odf=64, dtype="f64", exec=exec_, hints=hints, seed=3)
+    _assert_same(U, want)
+    assert r == r_w
