@@ -1,16 +1,25 @@
 """Benchmark: overdecomposed 3D 7-point Jacobi on one MI355X.
 
-Default workload (one "step" = one pass of the whole hot path):
-512^3 fp64 interior split into 4096 chares of 32^3 (16^3 chares), 200 Jacobi
-iterations with in-kernel halo exchange, graph-captured fused sweeps, residual
+Headline workload (one "step" = one pass of the whole hot path): a 512^3
+fp64 interior split into 4096 chares of 32^3, 200 Jacobi iterations with the
+halo exchange fused into the sweep, graph-captured, autotuned tile, residual
 of the last sweep read back.  value = GLUP/s (10^9 lattice-site updates/s).
 
-Prints ONE JSON line (metric, value, roofline of the sweep kernel measured
-live with HIP events on the grid's stream, the CPU oracle on a bounded sample
-of the same workload).  Extra legs (--sweep) add the ODF sweep, fp32, and the
-per-chare baseline.
+Prints ONE JSON line: the headline, the roofline of the sweep kernel (its
+average launch time measured live with HIP events on the grid's stream),
+the measured HBM copy ceiling, the ODF sweep (batched vs per-chare launches,
+fp64 and fp32), and the CPU oracle on a bounded sample of the same workload.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--sweep]
+Optional legs (each adds a key to the same line):
+  --amr        768^3 fp64 octree of uneven blocks: 500 iterations captured in
+               a hipGraph, and as one persistent launch
+  --imbalance  1024^3 fp64, ODF 8..32768, 10% of chares re-run 1-4 times per
+               step: message-driven scheduler vs bulk-synchronous forms
+  --serving    Poisson stream of independent solves at 10..2000 /s under a
+               200 GB budget: p50/p99 latency, solves/s, GLUP/s
+  --all        all of the above
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--amr] [--imbalance] [--serving]
 """
 from __future__ import annotations
 
@@ -38,50 +47,66 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str, per_launch_alg_bytes: float):
-    """HBM bytes per sweep launch from committed rocprofv3 counter runs, if
-    they were taken on the current kernel source; else None."""
+def load_traffic(key: str):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter runs,
+    if they were taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "sweep_traffic.json")
-    if not os.path.exists(path):
-        return None
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
         return None
-    e = d.get(workload)
+    e = d.get(key)
     if not e or e.get("kernel_hash") != kernel_source_hash():
         return None
     return e.get("bytes_per_launch")
 
 
-def run_grid_leg(n, odf, dtype, exec_, iters, steps, warmup, tile=None):
-    import torch
+def make_grid(n, odf=None, blocks=None, dtype="f64", exec_="graph", tile=None, hints=1, autotune=True, **kw):
     import paper_2605_12734_amd as od
 
-    g = od.Grid(n, odf=odf, dtype=dtype, exec=exec_, tile=tile)
+    if autotune and tile is None and exec_ in ("graph", "fused", "persistent"):
+        g = od.Grid(n, odf=odf or 1, blocks=blocks, dtype=dtype, exec=exec_, hints=hints, **kw)
+        g.autotune(2)
+        return g
+    if autotune and tile is None and exec_ in ("msgdriven", "per_chare"):
+        # these modes take the shape tuned on a fused grid of the same decomposition
+        t = od.Grid(n, odf=odf or 1, blocks=blocks, dtype=dtype, exec="fused", hints=hints)
+        tile = t.autotune(2)
+        t.close()
+    return od.Grid(n, odf=odf or 1, blocks=blocks, dtype=dtype, exec=exec_, tile=tile, hints=hints, **kw)
+
+
+def timed(g, iters, steps, warmup):
+    """Wall and device time of `steps` x od_iterate(iters) after `warmup`."""
+    import torch
+
+    for _ in range(warmup):
+        g.iterate(iters)
+    g.residual()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(g.stream)
+    for _ in range(steps):
+        g.iterate(iters)
+    ev1.record(g.stream)
+    r = g.residual()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return {"wall_s": t1 - t0, "dev_s": ev0.elapsed_time(ev1) * 1e-3, "residual": r}
+
+
+def grid_leg(n, odf, dtype, exec_, iters, steps, warmup, tile=None, **kw):
+    g = make_grid(n, odf=odf, dtype=dtype, exec_=exec_, tile=tile, **kw)
     try:
         plan = g.plan()
-        for _ in range(warmup):
-            g.iterate(iters)
-        g.residual()
-        torch.cuda.synchronize()
-        st = g.stream
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        ev0.record(st)
-        for _ in range(steps):
-            g.iterate(iters)
-        ev1.record(st)
-        r = g.residual()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        dev_s = ev0.elapsed_time(ev1) * 1e-3
+        t = timed(g, iters, steps, warmup)
     finally:
         g.close()
     lups = plan["interior"] * iters * steps
-    return {"wall_s": t1 - t0, "dev_s": dev_s, "glups": lups / (t1 - t0) / 1e9, "residual": r, "plan": plan,
-            "launch_s": dev_s / (iters * steps)}
+    t.update({"plan": plan, "glups": lups / t["wall_s"] / 1e9, "launch_s": t["dev_s"] / (iters * steps)})
+    return t
 
 
 def cpu_baseline(n, dtype, budget_s=12.0, max_iters=200):
@@ -92,16 +117,128 @@ def cpu_baseline(n, dtype, budget_s=12.0, max_iters=200):
     nt = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     oracle.set_threads(nt)
     U = oracle.init_field(n, np.float64 if dtype == "f64" else np.float32, 12734)
+    oracle.jacobi(U, 1)                       # first touch
     t = time.perf_counter()
-    oracle.jacobi(U, 1)
-    one = time.perf_counter() - t
-    iters = max(1, min(max_iters, int(budget_s / max(one, 1e-3))))
+    oracle.jacobi(U, 2)
+    per = (time.perf_counter() - t) / 2
+    iters = max(1, min(max_iters, int(budget_s / max(per, 1e-3))))
     t = time.perf_counter()
     oracle.jacobi(U, iters)
     dt = time.perf_counter() - t
-    lups = (n ** 3) * iters
-    return {"value": lups / dt / 1e9, "unit": "GLUP/s", "cores": int(oracle.max_threads()), "kind": "oracle",
-            "sample": f"{n}^3 {dtype}, undecomposed, {iters} iterations ({dt:.1f} s), same seed and boundary"}
+    return {"value": round(n ** 3 * iters / dt / 1e9, 3), "unit": "GLUP/s", "cores": int(oracle.max_threads()),
+            "kind": "oracle",
+            "sample": f"{n}^3 {dtype} undecomposed, {iters} of the step's 200 iterations ({dt:.1f} s), same seed/bc"}
+
+
+def odf_sweep(n, iters):
+    rows = []
+    for dtype in ("f64", "f32"):
+        for odf in (8, 64, 512, 4096):
+            b = grid_leg(n, odf, dtype, "graph", iters, 2, 1)
+            pc_iters = 10 if odf <= 64 else (4 if odf <= 512 else 2)
+            p = grid_leg(n, odf, dtype, "per_chare", pc_iters, 1, 1, tile=b["plan"]["tile"])
+            bp = b["plan"]["bytes_per_iter"]
+            k = round(odf ** (1 / 3))
+            rows.append({"dtype": dtype, "odf": odf, "block": n // k, "tile": list(b["plan"]["tile"]),
+                         "batched_glups": round(b["glups"], 2),
+                         "batched_hbm_gbps": round(bp / b["launch_s"] / 1e9, 1),
+                         "batched_frac": round(bp / b["launch_s"] / 1e9 / PEAK_HBM_GBPS, 4),
+                         "per_chare_glups": round(p["glups"], 3),
+                         "per_chare_ms_per_iter": round(p["wall_s"] / pc_iters * 1e3, 2),
+                         "speedup_batched_vs_per_chare": round(b["glups"] / p["glups"], 1)})
+            log("odf sweep:", rows[-1])
+    return rows
+
+
+def amr_leg(iters=500):
+    import workloads
+
+    blocks = workloads.octree_blocks(n=768, root=128, min_edge=16, p_refine=0.4, seed=12734)
+    out = {"blocks": len(blocks), "edges": sorted({e[0] for _, e in blocks})}
+    for exec_ in ("graph", "persistent"):
+        g = make_grid(768, blocks=blocks, dtype="f64", exec_=exec_)
+        try:
+            plan = g.plan()
+            t = timed(g, iters, 1, 1)
+        finally:
+            g.close()
+        bp = plan["bytes_per_iter"]
+        out[exec_] = {"glups": round(plan["interior"] * iters / t["wall_s"] / 1e9, 2),
+                      "hbm_gbps": round(bp * iters / t["dev_s"] / 1e9, 1),
+                      "frac": round(bp * iters / t["dev_s"] / 1e9 / PEAK_HBM_GBPS, 4),
+                      "tile": list(plan["tile"]), "tiles": plan["ntiles"], "iters": iters}
+        log("amr:", exec_, out[exec_])
+    return out
+
+
+def imbalance_leg(iters=1000, odfs=(8, 64, 512, 4096, 32768)):
+    rows = []
+    for odf in odfs:
+        row = {"odf": odf, "block": 1024 // round(odf ** (1 / 3))}
+        tile = None
+        for exec_ in ("fused", "persistent", "msgdriven"):
+            g = make_grid(1024, odf=odf, dtype="f64", exec_=exec_, tile=tile, imbalance_pct=10,
+                          imbalance_max_extra=4)
+            try:
+                tile = tile or g.plan()["tile"]
+                plan = g.plan()
+                t = timed(g, iters, 1, 0)
+            finally:
+                g.close()
+            row[exec_ + "_glups"] = round(plan["interior"] * iters / t["wall_s"] / 1e9, 2)
+            row[exec_ + "_s"] = round(t["wall_s"], 3)
+        row["msgdriven_vs_bsp_launches"] = round(row["msgdriven_glups"] / row["fused_glups"], 3)
+        row["msgdriven_vs_bsp_barrier"] = round(row["msgdriven_glups"] / row["persistent_glups"], 3)
+        log("imbalance:", row)
+        rows.append(row)
+    return rows
+
+
+def serving_leg(rates=(10, 30, 100, 300, 1000, 2000), count=64, arena_gb=200.0):
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2605_12734_amd.serving import Server
+
+    free = torch.cuda.mem_get_info()[0]
+    arena = int(min(arena_gb * 1e9, free * 0.85)) // 256 * 256
+    out = []
+    for rate in rates:
+        reqs = workloads.serving_requests(rate, count, seed=12734 + int(rate))
+        with Server(arena_bytes=arena, max_slots=min(count, 256)) as srv:
+            t0 = time.monotonic()
+            tickets = {}
+            pending = list(reqs)
+            done = {}
+            while pending or len(done) < len(reqs):
+                now = time.monotonic() - t0
+                while pending and pending[0]["t_arrival"] <= now:
+                    q = pending.pop(0)
+                    tickets[srv.submit(q["n"], q["dtype"], odf=q["odf"], tol=q["tol"], max_iters=q["max_iters"],
+                                       check_every=q["check_every"], seed=q["seed"])] = q
+                for t in list(tickets):
+                    if t in done:
+                        continue
+                    r = srv.poll(t)
+                    if r is not None:
+                        done[t] = r
+                        srv.fetch(t)
+                if pending and not any(t not in done for t in tickets):
+                    time.sleep(max(0.0, min(0.002, pending[0]["t_arrival"] - (time.monotonic() - t0))))
+                else:
+                    time.sleep(2e-4)
+        lat = np.array([done[t]["t_done"] - done[t]["t_submit"] for t in tickets])
+        first = min(r["t_submit"] for r in done.values())
+        last = max(r["t_done"] for r in done.values())
+        lups = sum(q["n"] ** 3 * done[t]["iters"] for t, q in tickets.items())
+        row = {"rate": rate, "requests": count, "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+               "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+               "solves_per_s": round(count / (last - first), 2), "glups": round(lups / (last - first) / 1e9, 2),
+               "mean_iters": round(float(np.mean([r["iters"] for r in done.values()])), 1)}
+        log("serving:", row)
+        out.append(row)
+    return out
 
 
 def main():
@@ -114,9 +251,16 @@ def main():
     ap.add_argument("--odf", type=int, default=4096)
     ap.add_argument("--dtype", default="f64")
     ap.add_argument("--exec", default="graph")
-    ap.add_argument("--tile", default=None, help="tx,ty,tz")
-    ap.add_argument("--sweep", action="store_true", help="also run the ODF sweep and per-chare baseline")
+    ap.add_argument("--tile", default=None, help="tx,ty,tz (default: autotuned)")
+    ap.add_argument("--hints", type=int, default=1)
+    ap.add_argument("--no-sweep", action="store_true", help="skip the ODF sweep")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--amr", action="store_true")
+    ap.add_argument("--imbalance", action="store_true")
+    ap.add_argument("--imb-iters", type=int, default=1000)
+    ap.add_argument("--serving", action="store_true")
+    ap.add_argument("--serving-count", type=int, default=64)
+    ap.add_argument("--all", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -124,53 +268,30 @@ def main():
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
-    import torch
     import paper_2605_12734_amd as od
 
     tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
-    workload = f"{args.n}^3 {args.dtype} odf{args.odf} {args.exec}"
-    log(f"bench: {workload}, {args.iters} iterations/step, warmup {args.warmup}, steps {args.steps}")
-    leg = run_grid_leg(args.n, args.odf, args.dtype, args.exec, args.iters, args.steps, args.warmup, tile)
+    log(f"bench: {args.n}^3 {args.dtype} odf {args.odf} {args.exec}, {args.iters} iterations/step, "
+        f"warmup {args.warmup}, steps {args.steps}")
+    leg = grid_leg(args.n, args.odf, args.dtype, args.exec, args.iters, args.steps, args.warmup, tile,
+                   hints=args.hints)
     plan = leg["plan"]
     bytes_per_iter = plan["bytes_per_iter"]
     achieved = bytes_per_iter / leg["launch_s"] / 1e9
     s = 8 if args.dtype == "f64" else 4
     strict = 2 * s * plan["interior"] / leg["launch_s"] / 1e9
-    log(f"bench: {leg['glups']:.1f} GLUP/s wall, sweep {leg['launch_s'] * 1e6:.1f} us/launch, "
-        f"{achieved:.0f} GB/s algorithmic")
+    log(f"bench: {leg['glups']:.1f} GLUP/s, sweep {leg['launch_s'] * 1e6:.1f} us/launch, "
+        f"{achieved:.0f} GB/s algorithmic, tile {plan['tile']}")
 
-    # STREAM-copy ceiling on the same device
     nbytes = 1 << 30
     copy_s = od.stream_copy_seconds(nbytes, iters=20)
     copy_gbps = 2 * nbytes * 20 / copy_s / 1e9
 
-    extra = {}
-    if args.sweep:
-        rows = []
-        for dtype in ("f64", "f32"):
-            for odf in (8, 64, 512, 4096):
-                b = run_grid_leg(args.n, odf, dtype, "graph", args.iters, 2, 1)
-                pc_iters = 20 if odf <= 64 else (5 if odf <= 512 else 2)
-                p = run_grid_leg(args.n, odf, dtype, "per_chare", pc_iters, 1, 1)
-                bp = b["plan"]["bytes_per_iter"]
-                rows.append({"dtype": dtype, "odf": odf, "block": args.n // round(odf ** (1 / 3)),
-                             "batched_glups": round(b["glups"], 2),
-                             "batched_hbm_gbps": round(bp / b["launch_s"] / 1e9, 1),
-                             "batched_frac": round(bp / b["launch_s"] / 1e9 / PEAK_HBM_GBPS, 4),
-                             "per_chare_glups": round(p["glups"], 3),
-                             "per_chare_ms_per_iter": round(p["wall_s"] / pc_iters * 1e3, 3),
-                             "speedup": round(b["glups"] / p["glups"], 1)})
-                log("sweep:", rows[-1])
-        extra["odf_sweep"] = rows
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.n, args.dtype)
-        log(f"cpu baseline: {cpu}")
-
-    traffic = load_traffic(workload, bytes_per_iter)
+    k = round(plan["nchares"] ** (1 / 3))
+    workload = f"{args.n}^3 {args.dtype} odf{plan['nchares']} tile{'x'.join(map(str, plan['tile']))} hints{args.hints}"
     out = {
-        "metric": "GLUP/s (batched, graph-captured fused sweep) at 512^3 fp64, ODF 4096",
+        "metric": "GLUP/s at 512^3 fp64, ODF 4096 (batched: graph-captured fused sweeps); ODF sweep batched vs "
+                  "per-chare; HBM GB/s vs roofline",
         "value": round(leg["glups"], 3),
         "unit": "GLUP/s",
         "n_gpus": 1,
@@ -181,24 +302,31 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": args.dtype,
-        "data": "synthetic (SplitMix64 U[0,1) interior, Dirichlet 1 on x-, 0 elsewhere)",
+        "data": "synthetic: SplitMix64 U[0,1) interior, Dirichlet 1 on x-, 0 elsewhere",
         "config": {"workload": f"{args.n}^3 {args.dtype} 7-point Jacobi, {plan['nchares']} chares of "
-                               f"{args.n // round(plan['nchares'] ** (1 / 3))}^3, {args.iters} iterations/step, "
-                               f"exec={args.exec}",
+                               f"{args.n // k}^3, {args.iters} iterations per step, exec={args.exec}",
                    "odf": plan["nchares"], "iters_per_step": args.iters, "tile": list(plan["tile"]),
-                   "exec": args.exec},
+                   "exec": args.exec, "hints": args.hints},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBPS, 4),
-                     "traffic": traffic,
-                     "kernel": "k_sweep (fused 7-point sweep + halo exchange)",
+                     "traffic": load_traffic(workload),
+                     "kernel": "k_sweep (fused 7-point sweep + halo pack/exchange/unpack)",
                      "alg_bytes_per_launch": bytes_per_iter,
                      "avg_launch_us": round(leg["launch_s"] * 1e6, 2),
                      "strict_frac_2s_per_lup": round(strict / PEAK_HBM_GBPS, 4),
-                     "stream_copy_gbps": round(copy_gbps, 1)},
-        "cpu_baseline": cpu,
+                     "copy_ceiling_gbps": round(copy_gbps, 1),
+                     "frac_of_copy_ceiling": round(achieved / copy_gbps, 4)},
         "residual": leg["residual"],
     }
-    out.update(extra)
+    if not args.no_sweep:
+        out["odf_sweep"] = odf_sweep(args.n, args.iters)
+    if args.amr or args.all:
+        out["amr_octree_768"] = amr_leg()
+    if args.imbalance or args.all:
+        out["imbalance_1024"] = imbalance_leg(args.imb_iters)
+    if args.serving or args.all:
+        out["serving"] = serving_leg(count=args.serving_count)
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.n, args.dtype)
     print(json.dumps(out), flush=True)
 
 

@@ -106,8 +106,14 @@ typedef struct {
     int32_t imbalance_pct;
     int32_t imbalance_max_extra;
     /* Implementation hints, 0 = defaults; none of them changes a result.
-     * bit 0: write the sweep's output with non-temporal (streaming) stores. */
+     * bit 0: write the sweep's output with non-temporal (streaming) stores;
+     * other bits are ignored. */
     int32_t hints;
+    /* 7 (or 0): 3D 7-point stencil.  5: the 2D 5-point stencil of the
+     * paper's Jacobi2D workload, u' = (((u[i-1] + u[i+1]) + u[k-1]) + u[k+1]) / 4,
+     * on a grid with n[1] == 1: the 2D plane is (x, z), its second direction
+     * stored as z; bc[2] and bc[3] (the y faces) are not read. */
+    int32_t stencil;
 } od_config;
 
 struct od_grid;

@@ -67,6 +67,18 @@ def _load():
         f.argtypes = [dp, dp, i64, i64, i64, i64, ctypes.c_double, i64,
                       ctypes.POINTER(ctypes.c_double)]
         f.restype = i64
+        f = getattr(lib, "oracle_init2d_" + suf)
+        f.argtypes = [dp, i64, i64, u64, ctypes.POINTER(ctypes.c_double)]
+        f.restype = None
+        f = getattr(lib, "oracle_init2d_box_" + suf)
+        f.argtypes = [dp, i64, i64, u64, ctypes.POINTER(ctypes.c_double), i64, i64, i64, i64]
+        f.restype = None
+        f = getattr(lib, "oracle_sweep2d_" + suf)
+        f.argtypes = [dp, dp, i64, i64]
+        f.restype = ct
+        f = getattr(lib, "oracle_jacobi2d_" + suf)
+        f.argtypes = [dp, dp, i64, i64, i64, ctypes.c_double, i64, ctypes.POINTER(ctypes.c_double)]
+        f.restype = i64
     _lib = lib
     return lib
 
@@ -160,4 +172,58 @@ def point_values(n, points, iters: int, dtype=np.float64, seed: int = 12734, bc=
             U.ctypes.data, nx, ny, nz, seed & (2**64 - 1), bcarr, lo[0], lo[1], lo[2], bx, by, bz)
         V, _, _ = jacobi(U, iters)
         out.append(V[k - lo[2] + 1, j - lo[1] + 1, i - lo[0] + 1])
+    return np.array(out, dtype=dtype)
+
+
+# ---- Jacobi2D (Section V): 5-point stencil on an (ny+2, nx+2) padded field --
+
+DEFAULT_BC2D = (1.0, 0.0, 0.0, 0.0)
+
+
+def init_field2d(n2, dtype=np.float64, seed: int = 12734, bc=DEFAULT_BC2D) -> np.ndarray:
+    nx, ny = (int(n2), int(n2)) if np.isscalar(n2) else (int(n2[0]), int(n2[1]))
+    U = np.empty((ny + 2, nx + 2), dtype=dtype)
+    bcarr = (ctypes.c_double * 4)(*[float(b) for b in bc])
+    getattr(_load(), "oracle_init2d_" + _suffix(dtype))(U.ctypes.data, nx, ny, seed & (2**64 - 1), bcarr)
+    return U
+
+
+def sweep2d(U: np.ndarray):
+    U = np.ascontiguousarray(U)
+    ny, nx = (s - 2 for s in U.shape)
+    V = U.copy()
+    r = getattr(_load(), "oracle_sweep2d_" + _suffix(U.dtype))(U.ctypes.data, V.ctypes.data, nx, ny)
+    return V, float(r)
+
+
+def jacobi2d(U: np.ndarray, max_iters: int, tol: float = 0.0, check_every: int = 0):
+    A = np.array(U, copy=True, order="C")
+    B = np.empty_like(A)
+    ny, nx = (s - 2 for s in A.shape)
+    r = ctypes.c_double(0.0)
+    it = getattr(_load(), "oracle_jacobi2d_" + _suffix(A.dtype))(
+        A.ctypes.data, B.ctypes.data, nx, ny, int(max_iters), float(tol), int(check_every), ctypes.byref(r))
+    return A, int(it), float(r.value)
+
+
+def solve2d(n2, dtype=np.float64, seed: int = 12734, iters: int = 100, bc=DEFAULT_BC2D, tol: float = 0.0,
+            check_every: int = 0):
+    return jacobi2d(init_field2d(n2, dtype, seed, bc), iters, tol, check_every)
+
+
+def point_values2d(n2, points, iters: int, dtype=np.float64, seed: int = 12734, bc=DEFAULT_BC2D):
+    """2D analogue of point_values: each (i, j) after `iters` sweeps from a
+    sub-box of half-width iters (domain of dependence)."""
+    nx, ny = int(n2[0]), int(n2[1])
+    bcarr = (ctypes.c_double * 4)(*[float(b) for b in bc])
+    out = []
+    for (i, j) in points:
+        lo = [max(0, i - iters), max(0, j - iters)]
+        hi = [min(nx - 1, i + iters), min(ny - 1, j + iters)]
+        bx, by = hi[0] - lo[0] + 1, hi[1] - lo[1] + 1
+        U = np.empty((by + 2, bx + 2), dtype=dtype)
+        getattr(_load(), "oracle_init2d_box_" + _suffix(dtype))(
+            U.ctypes.data, nx, ny, seed & (2**64 - 1), bcarr, lo[0], lo[1], bx, by)
+        V, _, _ = jacobi2d(U, iters)
+        out.append(V[j - lo[1] + 1, i - lo[0] + 1])
     return np.array(out, dtype=dtype)

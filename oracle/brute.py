@@ -92,3 +92,46 @@ def jacobi(U, max_iters, tol=0.0, check_every=0):
 
 def to_numpy(U, dtype):
     return np.array(U, dtype=dtype)
+
+
+# ---- Jacobi2D: 5-point, order x-, x+, y-, y+, divided by 4 ------------------
+
+def init_field2d(nx, ny, dtype, seed, bc):
+    T = np.float64 if np.dtype(dtype) == np.float64 else np.float32
+    U = [[T(0) for _ in range(nx + 2)] for _ in range(ny + 2)]
+    for j in range(-1, ny + 1):
+        for i in range(-1, nx + 1):
+            outs = (i < 0 or i >= nx) + (j < 0 or j >= ny)
+            if outs == 0:
+                v = T(unif(splitmix64(seed, j * nx + i), T))
+            elif outs == 2:
+                v = T(0)
+            elif i < 0:
+                v = T(bc[0])
+            elif i >= nx:
+                v = T(bc[1])
+            elif j < 0:
+                v = T(bc[2])
+            else:
+                v = T(bc[3])
+            U[j + 1][i + 1] = v
+    return U
+
+
+def sweep2d(U):
+    ny, nx = len(U) - 2, len(U[0]) - 2
+    T = type(U[1][1])
+    V = [list(row) for row in U]
+    r = T(0)
+    for j in range(1, ny + 1):
+        for i in range(1, nx + 1):
+            s = U[j][i - 1]
+            s = T(s + U[j][i + 1])
+            s = T(s + U[j - 1][i])
+            s = T(s + U[j + 1][i])
+            v = T(s / T(4))
+            d = abs(T(v - U[j][i]))
+            if d > r:
+                r = d
+            V[j][i] = v
+    return V, r

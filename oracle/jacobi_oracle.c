@@ -213,8 +213,95 @@ int64_t oracle_jacobi_##SUF(T* U, T* V, int64_t nx, int64_t ny, int64_t nz,     
     return it;                                                                               \
 }
 
+/*
+ * The paper's own workload, Jacobi2D (Section V): the same iteration on a
+ * 2D grid, 5-point stencil u'(i,j) = mean of the four edge neighbours,
+ * added in the order x-, x+, y-, y+ and divided by 4.  Padded array
+ * (ny+2)(nx+2), x fastest; bc = {x-, x+, y-, y+}; shell corners zero;
+ * interior value at g = j*nx + i from SplitMix64 as in 3D.
+ */
+#define PIDX2(i, j, nx) ((((int64_t)(j) + 1) * ((int64_t)(nx) + 2)) + ((int64_t)(i) + 1))
+
+#define ORACLE2D_DEFINE(T, SUF, UNIF)                                                        \
+void oracle_init2d_##SUF(T* U, int64_t nx, int64_t ny, uint64_t seed, const double bc[4])  \
+{                                                                                            \
+    for (int64_t j = -1; j <= ny; ++j)                                                       \
+        for (int64_t i = -1; i <= nx; ++i) {                                                 \
+            int out = (i < 0 || i >= nx) + (j < 0 || j >= ny);                               \
+            T v;                                                                             \
+            if (out == 0) v = UNIF(oracle_splitmix64(seed, (uint64_t)(j * nx + i)));         \
+            else if (out == 2) v = (T)0;                                                     \
+            else if (i < 0) v = (T)bc[0];                                                    \
+            else if (i >= nx) v = (T)bc[1];                                                  \
+            else if (j < 0) v = (T)bc[2];                                                    \
+            else v = (T)bc[3];                                                               \
+            U[PIDX2(i, j, nx)] = v;                                                          \
+        }                                                                                    \
+}                                                                                            \
+                                                                                             \
+/* Padded sub-box (bx, by at global origin ox, oy) of the initial 2D field,  \
+ * shell included, for evaluating single outputs by domain of dependence. */ \
+void oracle_init2d_box_##SUF(T* U, int64_t nx, int64_t ny, uint64_t seed, const double bc[4], \
+                             int64_t ox, int64_t oy, int64_t bx, int64_t by)               \
+{                                                                                            \
+    for (int64_t j = -1; j <= by; ++j)                                                       \
+        for (int64_t i = -1; i <= bx; ++i) {                                                 \
+            int64_t gi = ox + i, gj = oy + j;                                                \
+            int out = (gi < 0 || gi >= nx) + (gj < 0 || gj >= ny);                           \
+            T v;                                                                             \
+            if (out == 0) v = UNIF(oracle_splitmix64(seed, (uint64_t)(gj * nx + gi)));      \
+            else if (out == 2) v = (T)0;                                                     \
+            else if (gi < 0) v = (T)bc[0];                                                   \
+            else if (gi >= nx) v = (T)bc[1];                                                 \
+            else if (gj < 0) v = (T)bc[2];                                                   \
+            else v = (T)bc[3];                                                               \
+            U[PIDX2(i, j, bx)] = v;                                                          \
+        }                                                                                    \
+}                                                                                            \
+                                                                                             \
+T oracle_sweep2d_##SUF(const T* U, T* V, int64_t nx, int64_t ny)                           \
+{                                                                                            \
+    T r = (T)0;                                                                              \
+    _Pragma("omp parallel for schedule(static) reduction(max : r)")                         \
+    for (int64_t j = 0; j < ny; ++j)                                                         \
+        for (int64_t i = 0; i < nx; ++i) {                                                   \
+            T s = U[PIDX2(i - 1, j, nx)];                                                    \
+            s = s + U[PIDX2(i + 1, j, nx)];                                                  \
+            s = s + U[PIDX2(i, j - 1, nx)];                                                  \
+            s = s + U[PIDX2(i, j + 1, nx)];                                                  \
+            T v = s / (T)4;                                                                  \
+            T d = v - U[PIDX2(i, j, nx)];                                                    \
+            if (d < (T)0) d = -d;                                                            \
+            if (d > r) r = d;                                                                \
+            V[PIDX2(i, j, nx)] = v;                                                          \
+        }                                                                                    \
+    return r;                                                                                \
+}                                                                                            \
+                                                                                             \
+int64_t oracle_jacobi2d_##SUF(T* U, T* V, int64_t nx, int64_t ny, int64_t max_iters,        \
+                              double tol, int64_t check_every, double* residual)             \
+{                                                                                            \
+    size_t total = (size_t)(nx + 2) * (size_t)(ny + 2);                                      \
+    memcpy(V, U, total * sizeof(T));                                                         \
+    T* a = U;                                                                                \
+    T* b = V;                                                                                \
+    T r = (T)0;                                                                              \
+    int64_t it = 0;                                                                          \
+    while (it < max_iters) {                                                                 \
+        r = oracle_sweep2d_##SUF(a, b, nx, ny);                                              \
+        ++it;                                                                                \
+        T* t = a; a = b; b = t;                                                              \
+        if (check_every > 0 && it % check_every == 0 && (double)r < tol) break;              \
+    }                                                                                        \
+    if (a != U) memcpy(U, a, total * sizeof(T));                                             \
+    if (residual) *residual = (double)r;                                                     \
+    return it;                                                                               \
+}
+
 #define UNIF_F64(h) ((double)((h) >> 11) * 0x1.0p-53)
 #define UNIF_F32(h) ((float)((h) >> 40) * 0x1.0p-24f)
 
 ORACLE_DEFINE(double, f64, UNIF_F64)
 ORACLE_DEFINE(float, f32, UNIF_F32)
+ORACLE2D_DEFINE(double, f64, UNIF_F64)
+ORACLE2D_DEFINE(float, f32, UNIF_F32)

@@ -20,7 +20,7 @@ import numpy as np
 from . import _binding as B
 from ._binding import ODError, check, lib
 
-__all__ = ["Grid", "ODError", "DEFAULT_BC", "stream_copy_seconds", "plan_info", "tile_infos", "lib",
+__all__ = ["Grid", "Grid2D", "ODError", "DEFAULT_BC", "stream_copy_seconds", "plan_info", "tile_infos", "lib",
            "Server"]
 
 DEFAULT_BC = (1.0, 0.0, 0.0, 0.0, 0.0, 0.0)
@@ -36,7 +36,7 @@ def _dims(n) -> tuple:
 
 def make_config(n, odf: int = 8, block=None, blocks: Optional[Sequence] = None, dtype="f64",
                 bc=DEFAULT_BC, seed: int = 12734, exec: str = "graph", tile=None,
-                imbalance_pct: int = 0, imbalance_max_extra: int = 0, hints: int = 0):
+                imbalance_pct: int = 0, imbalance_max_extra: int = 0, hints: int = 0, stencil: int = 7):
     """Fill an od_config; returns (cfg, keepalive) where keepalive holds arrays it points to."""
     cfg = B.od_config()
     lib().od_config_default(ctypes.byref(cfg))
@@ -67,6 +67,7 @@ def make_config(n, odf: int = 8, block=None, blocks: Optional[Sequence] = None, 
     cfg.imbalance_pct = int(imbalance_pct)
     cfg.imbalance_max_extra = int(imbalance_max_extra)
     cfg.hints = int(hints)
+    cfg.stencil = int(stencil)
     return cfg, keep
 
 
@@ -144,7 +145,8 @@ class Grid:
 
     def __init__(self, n, odf: int = 8, block=None, blocks=None, dtype="f64", bc=DEFAULT_BC,
                  seed: int = 12734, exec: str = "graph", tile=None, imbalance_pct: int = 0,
-                 imbalance_max_extra: int = 0, hints: int = 0, device: str = "cuda:0", stream=None):
+                 imbalance_max_extra: int = 0, hints: int = 0, stencil: int = 7, device: str = "cuda:0",
+                 stream=None):
         import torch
 
         self.n = _dims(n)
@@ -152,7 +154,7 @@ class Grid:
         self.exec = exec
         cfg, self._keep = make_config(n=n, odf=odf, block=block, blocks=blocks, dtype=dtype, bc=bc, seed=seed,
                                       exec=exec, tile=tile, imbalance_pct=imbalance_pct,
-                                      imbalance_max_extra=imbalance_max_extra, hints=hints)
+                                      imbalance_max_extra=imbalance_max_extra, hints=hints, stencil=stencil)
         nbytes = ctypes.c_size_t()
         check(lib().od_workspace_bytes(ctypes.byref(cfg), ctypes.byref(nbytes)), "od_workspace_bytes")
         self.device = torch.device(device)
@@ -233,6 +235,35 @@ class Grid:
             self.close()
         except Exception:
             pass
+
+
+class Grid2D(Grid):
+    """The paper's Jacobi2D workload: a 5-point stencil on an nx x ny grid,
+    stored as an (nx, 1, ny) grid whose second direction is marched in
+    registers.  Fields read/written here are 2D padded (ny+2, nx+2) arrays,
+    bc = (x-, x+, y-, y+)."""
+
+    def __init__(self, n2, odf: int = 1, dtype="f64", bc=(1.0, 0.0, 0.0, 0.0), **kw):
+        nx, ny = (int(n2), int(n2)) if np.isscalar(n2) else (int(n2[0]), int(n2[1]))
+        self.n2 = (nx, ny)
+        bc3 = (bc[0], bc[1], 0.0, 0.0, bc[2], bc[3])
+        super().__init__((nx, 1, ny), odf=odf, dtype=dtype, bc=bc3, stencil=5, **kw)
+
+    def read(self) -> np.ndarray:
+        return np.ascontiguousarray(super().read()[:, 1, :])
+
+    def write(self, U: np.ndarray) -> None:
+        nx, ny = self.n2
+        U = np.asarray(U, dtype=self.dtype)
+        if U.shape != (ny + 2, nx + 2):
+            raise ValueError(f"field shape {U.shape} != {(ny + 2, nx + 2)}")
+        F = np.zeros((ny + 2, 3, nx + 2), dtype=self.dtype)
+        F[:, 1, :] = U
+        super().write(F)
+
+    def read_points(self, idx) -> np.ndarray:
+        # 2D linear index j*nx + i is the 3D index (k*1 + 0)*nx + i with k = j
+        return super().read_points(idx)
 
 
 def stream_copy_seconds(nbytes: int, iters: int = 10, device: str = "cuda:0") -> float:

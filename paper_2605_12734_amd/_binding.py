@@ -39,7 +39,7 @@ class od_config(ctypes.Structure):
     _fields_ = [("n", c_i64 * 3), ("block", c_i64 * 3), ("odf", c_i32), ("blocks", ctypes.POINTER(od_block)),
                 ("nblocks", c_i32), ("dtype", ctypes.c_int), ("bc", c_dbl * 6), ("seed", c_u64),
                 ("exec", ctypes.c_int), ("tile", c_i32 * 3), ("imbalance_pct", c_i32),
-                ("imbalance_max_extra", c_i32), ("hints", c_i32)]
+                ("imbalance_max_extra", c_i32), ("hints", c_i32), ("stencil", c_i32)]
 
 
 class od_plan_info(ctypes.Structure):

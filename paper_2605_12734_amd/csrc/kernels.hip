@@ -100,6 +100,7 @@ __device__ __forceinline__ T sweep_tile(T* __restrict__ arena, const BlockDev* _
     using S = SW<T, TX, TY>;
     using VT = typename V16<T>::t;
     constexpr int VX = S::VX;
+    constexpr int64_t ES = (int64_t)sizeof(T);
     const int tid = threadIdx.x;
     const int lx = tid % S::LX;
     const int ly = tid / S::LX;
@@ -110,93 +111,83 @@ __device__ __forceinline__ T sweep_tile(T* __restrict__ arena, const BlockDev* _
     nv = nv < 0 ? 0 : (nv > VX ? VX : nv);
     if (!rowok) nv = 0;
     const bool act = nv > 0;
+    // mode bit 8: the 2D 5-point stencil on the (x, z) plane (no y terms, / 4)
+    const bool five = (hints & 0x100) != 0;
+
+    // Addressing: every load is a uniform 64-bit base (per tile and face,
+    // held in scalar registers) plus a small 32-bit per-thread byte offset.
+    // Lanes outside the tile clamp to its last valid row / vector column, so
+    // every thread issues the same loads in the same order each plane and
+    // every load is in bounds; only in-tile lanes stage or store results.
+    // (A load behind a branch would make the compiler wait for all
+    // outstanding loads before using any, serialising the prefetch.)
+    const int xc = x < nx ? x : ((nx - 1) / VX) * VX;
+    const int lc = ly < ny ? ly : ny - 1;
+    const char* __restrict__ ab = reinterpret_cast<const char*>(arena);
 
     // Block descriptors are read field by field straight from global memory
     // (a dynamically indexed local copy would be placed in scratch).
     const BlockDev* __restrict__ B = blocks + t.blk;
-    const int64_t pz = B->pz;
-    const T* own0 = arena + (parity ? B->off[1] : B->off[0]) + t.x0 + (int64_t)t.y0 * B->py + (int64_t)t.z0 * pz;
-    const int64_t obase = (int64_t)x + (int64_t)ly * B->py;
-    T* dst = arena + (parity ? B->off[0] : B->off[1]) + t.x0 + (int64_t)t.y0 * B->py + (int64_t)t.z0 * pz + obase;
+    const int64_t own_py = B->py, own_pz = B->pz;
+    const int64_t tile_el = t.x0 + (int64_t)t.y0 * own_py + (int64_t)t.z0 * own_pz;
+    const char* own_b = ab + ((parity ? B->off[1] : B->off[0]) + tile_el) * ES;
+    char* dst_b = reinterpret_cast<char*>(arena) + ((parity ? B->off[0] : B->off[1]) + tile_el) * ES;
+    const uint32_t o_own = (uint32_t)((xc + (int64_t)lc * own_py) * ES);
 
-    // Every thread issues the same loads in the same order every plane (no
-    // load sits behind a branch), so the compiler can count outstanding
-    // loads exactly and the prefetched planes really overlap the compute.
-    // Threads with nothing to load read a safe in-bounds address instead:
-    // the tile's first (16-byte aligned) cell, `own0`.
-    auto face = [&](const FaceDev& f, int64_t dx, int64_t dy, int64_t* fpz) -> const T* {
+    // face f: uniform base at its ghost slab's first cell, uniform plane pitch
+    auto face = [&](const FaceDev& f, int64_t* fpy, int64_t* fpz) -> const char* {
         const BlockDev* __restrict__ F = blocks + f.src;
+        *fpy = F->py;
         *fpz = F->pz;
-        return arena + (parity ? F->off[1] : F->off[0]) + (f.sx + dx) + (int64_t)(f.sy + dy) * F->py +
-               (int64_t)f.sz * F->pz;
+        return ab + ((parity ? F->off[1] : F->off[0]) + f.sx + (int64_t)f.sy * F->py + (int64_t)f.sz * F->pz) * ES;
     };
-    int64_t zm_pz, zp_pz, xm_pz, xp_pz, ym_pz, yp_pz;
-    const T* zmp = face(t.f[4], x, ly, &zm_pz);
-    const T* zpp = face(t.f[5], x, ly, &zp_pz);
-    const T* xmp = face(t.f[0], 0, ly, &xm_pz);
-    const T* xpp = face(t.f[1], 0, ly, &xp_pz);
-    const T* ymp = face(t.f[2], x, 0, &ym_pz);
-    const T* ypp = face(t.f[3], x, 0, &yp_pz);
+    int64_t zm_py, zm_pz, zp_py, zp_pz, xm_py, xm_pz, xp_py, xp_pz, ym_py, ym_pz, yp_py, yp_pz;
+    const char* zm_b = face(t.f[4], &zm_py, &zm_pz);
+    const char* zp_b = face(t.f[5], &zp_py, &zp_pz);
+    const char* xm_b = face(t.f[0], &xm_py, &xm_pz);
+    const char* xp_b = face(t.f[1], &xp_py, &xp_pz);
+    const char* ym_b = face(t.f[2], &ym_py, &ym_pz);
+    const char* yp_b = face(t.f[3], &yp_py, &yp_pz);
     (void)zm_pz;
     (void)zp_pz;
-    const T* own = act ? own0 + obase : own0;
-    if (!act) {
-        zmp = own0;
-        zpp = own0;
-    }
+    (void)ym_py;
+    (void)yp_py;
+    const uint32_t o_zm = (uint32_t)((xc + (int64_t)lc * zm_py) * ES);
+    const uint32_t o_zp = (uint32_t)((xc + (int64_t)lc * zp_py) * ES);
+    const uint32_t o_xm = (uint32_t)((int64_t)lc * xm_py * ES);
+    const uint32_t o_xp = (uint32_t)((int64_t)lc * xp_py * ES);
+    const uint32_t o_y = (uint32_t)((int64_t)xc * ES);
+
     const bool do_xm = rowok && lx == 0;
     const bool do_xp = rowok && lx == (nx - 1) / VX;
     const bool do_ym = act && ly == 0;
     const bool do_yp = act && ly == ny - 1;
-    const int64_t own_pz = act ? pz : 0;
-    if (!do_xm) { xmp = own0; xm_pz = 0; }
-    if (!do_xp) { xpp = own0; xp_pz = 0; }
-    if (!do_ym) { ymp = own0; ym_pz = 0; }
-    if (!do_yp) { ypp = own0; yp_pz = 0; }
-
-    // fused pack: the thread holding the chare's x = 0 (x = ex-1) cell of a
-    // row also writes it into the chare's x- (x+) face message
-    T* wm = nullptr;
-    T* wp = nullptr;
-    int64_t wm_pz = 0, wp_pz = 0;
-    int ip = 0;
-    if (rowok) {
-        const int32_t mm = B->xmsg[0], mp = B->xmsg[1];
-        if (mm >= 0 && t.x0 == 0 && lx == 0) {
-            const BlockDev* __restrict__ M = blocks + mm;
-            wm = arena + (parity ? M->off[0] : M->off[1]) + (int64_t)(t.y0 + ly) + (int64_t)t.z0 * M->pz;
-            wm_pz = M->pz;
-        }
-        ip = B->ex - 1 - (t.x0 + x);
-        if (mp >= 0 && ip >= 0 && ip < VX && ip < nv) {
-            const BlockDev* __restrict__ M = blocks + mp;
-            wp = arena + (parity ? M->off[0] : M->off[1]) + (int64_t)(t.y0 + ly) + (int64_t)t.z0 * M->pz;
-            wp_pz = M->pz;
-        }
-    }
 
     auto L = [&](int b, int r, int c) -> T& { return lds[(b * S::LR + r) * S::LP + c]; };
-    auto ldv = [](const T* p) -> VT { return *reinterpret_cast<const VT*>(p); };
+    auto ldv = [](const char* p) -> VT { return *reinterpret_cast<const VT*>(p); };
+    auto lds1 = [](const char* p) -> T { return *reinterpret_cast<const T*>(p); };
     // plane zz in [-1, nz]: -1 and nz come from the z faces
-    auto plane = [&](int zz) -> const T* { return zz < 0 ? zmp : (zz >= nz ? zpp : own + zz * own_pz); };
+    auto plane = [&](int zz) -> VT {
+        return zz < 0 ? ldv(zm_b + o_zm) : (zz >= nz ? ldv(zp_b + o_zp) : ldv(own_b + zz * own_pz * ES + o_own));
+    };
 
     // register column: p0 = plane z-1, p1 = z, p2 = z+1, p3 = z+2, p4 = z+3
-    VT p0 = ldv(zmp);
-    VT p1 = ldv(own);
-    VT p2 = ldv(plane(1));
-    VT p3 = ldv(plane(2 <= nz ? 2 : nz));
-    VT hym = ldv(ymp), hyp = ldv(ypp);
-    T hxm = xmp[0], hxp = xpp[0];
+    VT p0 = plane(-1);
+    VT p1 = plane(0);
+    VT p2 = plane(1);
+    VT p3 = plane(2 <= nz ? 2 : nz);
+    VT hym = ldv(ym_b + o_y), hyp = ldv(yp_b + o_y);
+    T hxm = lds1(xm_b + o_xm), hxp = lds1(xp_b + o_xp);
 
     T r = 0;
     for (int z = 0; z < nz; ++z) {
         const int b = z & 1;
         // prefetch: plane z+3 (clamped to the z+ face) and the halo of z+1
         const int zq = z + 3 <= nz ? z + 3 : nz;
-        const VT p4 = ldv(plane(zq));
-        const int zh = z + 1 < nz ? z + 1 : z;
-        const VT nym = ldv(ymp + zh * ym_pz), nyp = ldv(ypp + zh * yp_pz);
-        const T nxm = xmp[zh * xm_pz], nxp = xpp[zh * xp_pz];
+        const VT p4 = plane(zq);
+        const int64_t zh = z + 1 < nz ? z + 1 : z;
+        const VT nym = ldv(ym_b + zh * ym_pz * ES + o_y), nyp = ldv(yp_b + zh * yp_pz * ES + o_y);
+        const T nxm = lds1(xm_b + zh * xm_pz * ES + o_xm), nxp = lds1(xp_b + zh * xp_pz * ES + o_xp);
 
         // stage plane z with its x/y halo
         if (act) {
@@ -228,11 +219,13 @@ __device__ __forceinline__ T sweep_tile(T* __restrict__ arena, const BlockDev* _
                 const T xp = (i < VX - 1 && i + 1 < nv) ? p1[i + 1] : L(b, ly + 1, VX + x + i + 1);
                 T s = xm;
                 s = s + xp;
-                s = s + L(b, ly, VX + x + i);
-                s = s + L(b, ly + 2, VX + x + i);
+                if (!five) {
+                    s = s + L(b, ly, VX + x + i);
+                    s = s + L(b, ly + 2, VX + x + i);
+                }
                 s = s + p0[i];
                 s = s + p2[i];
-                const T v = s / (T)6;
+                const T v = five ? s / (T)4 : s / (T)6;
                 out[i] = v;
                 if (i < nv) {
                     T d = v - p1[i];
@@ -242,18 +235,11 @@ __device__ __forceinline__ T sweep_tile(T* __restrict__ arena, const BlockDev* _
             }
             // a partial vector only occurs at the chare's row end, where the
             // lanes past nx land in the row's padding: store the whole vector
+            VT* o = reinterpret_cast<VT*>(dst_b + (int64_t)z * own_pz * ES + o_own);
             if (hints & 1)
-                __builtin_nontemporal_store(out, reinterpret_cast<VT*>(dst + (int64_t)z * pz));
+                __builtin_nontemporal_store(out, o);
             else
-                *reinterpret_cast<VT*>(dst + (int64_t)z * pz) = out;
-            if (wm) wm[(int64_t)z * wm_pz] = out[0];
-            if (wp) {
-                T vlast = out[0];
-#pragma unroll
-                for (int i = 1; i < VX; ++i)
-                    if (i == ip) vlast = out[i];
-                wp[(int64_t)z * wp_pz] = vlast;
-            }
+                *o = out;
         }
         p0 = p1;
         p1 = p2;
@@ -529,9 +515,11 @@ __global__ void __launch_bounds__((TX8 / 2) * TY8) k_serve(MsgArgs a) {
 // variant table
 
 #define OD_VARIANTS_F64(X) X(double, 32, 4) X(double, 32, 8) X(double, 32, 16) X(double, 32, 32) \
-    X(double, 64, 4) X(double, 64, 8) X(double, 64, 16) X(double, 16, 8) X(double, 16, 16) X(double, 128, 4)
+    X(double, 64, 4) X(double, 64, 8) X(double, 64, 16) X(double, 16, 8) X(double, 16, 16) X(double, 128, 4) \
+    X(double, 128, 1) X(double, 256, 1)
 #define OD_VARIANTS_F32(X) X(float, 32, 8) X(float, 32, 16) X(float, 32, 32) X(float, 64, 4) \
-    X(float, 64, 8) X(float, 64, 16) X(float, 128, 4) X(float, 128, 8) X(float, 16, 16)
+    X(float, 64, 8) X(float, 64, 16) X(float, 128, 4) X(float, 128, 8) X(float, 16, 16) X(float, 256, 1) \
+    X(float, 512, 1)
 
 #define OD_VT_ENTRY(T, TX, TY) {TX, TY, SW<T, TX, TY>::NT},
 static const SweepVariant kVariants64[] = {OD_VARIANTS_F64(OD_VT_ENTRY)};
@@ -854,45 +842,6 @@ __global__ void k_unpack(FaceSet in, FaceSet ghost) {
     const int64_t cnt = in.cnt[f];
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * blockDim.x)
         d[e] = s[e];
-}
-
-// x-face messages of parity `par` from the chares' own storage (after the
-// field was initialised or written).
-template <typename T>
-__global__ void k_pack_xmsg(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const int32_t* list, int par) {
-    const int32_t c = list[blockIdx.y];
-    const BlockDev* B = blocks + c;
-    const int64_t cnt = (int64_t)B->ey * B->ez;
-    const T* u = arena + (par ? B->off[1] : B->off[0]);
-    for (int side = 0; side < 2; ++side) {
-        const int32_t m = B->xmsg[side];
-        if (m < 0) continue;
-        const BlockDev* M = blocks + m;
-        T* d = arena + (par ? M->off[1] : M->off[0]);
-        const int64_t x = side == 0 ? 0 : B->ex - 1;
-        for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * blockDim.x) {
-            const int64_t y = e % B->ey, z = e / B->ey;
-            d[y + z * M->pz] = u[x + y * B->py + z * B->pz];
-        }
-    }
-}
-
-hipError_t launch_pack_xmsg(int dtype_bytes, hipStream_t st, void* arena, const BlockDev* blocks, const int32_t* list,
-                            int32_t count, int par) {
-    if (count <= 0) return hipSuccess;
-    for (int32_t c0 = 0; c0 < count; c0 += 65535) {
-        const int32_t n = count - c0 < 65535 ? count - c0 : 65535;
-        dim3 grid(4, (unsigned)n);
-        if (dtype_bytes == 8)
-            hipLaunchKernelGGL(k_pack_xmsg<double>, grid, dim3(256), 0, st, reinterpret_cast<double*>(arena), blocks,
-                               list + c0, par);
-        else
-            hipLaunchKernelGGL(k_pack_xmsg<float>, grid, dim3(256), 0, st, reinterpret_cast<float*>(arena), blocks,
-                               list + c0, par);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
 }
 
 hipError_t launch_pack_b(int dtype_bytes, hipStream_t st, void* arena, const BlockDev& B, int parity,

@@ -126,9 +126,6 @@ struct FaceSet {
 hipError_t launch_pack_b(int dtype_bytes, hipStream_t st, void* arena, const BlockDev& B, int parity,
                          const FaceSet& out);
 hipError_t launch_unpack(int dtype_bytes, hipStream_t st, FaceSet in, FaceSet ghost);
-// Fill the x-face messages (parity `par`) of the listed chares from their storage.
-hipError_t launch_pack_xmsg(int dtype_bytes, hipStream_t st, void* arena, const BlockDev* blocks, const int32_t* list,
-                            int32_t count, int par);
 
 // Streaming copy of `bytes` (multiple of 16) from src to dst with copy
 // kernel variant `variant` (0 .. copy_variant_count()-1).

@@ -110,24 +110,14 @@ std::string fill_tile_descs(Grid& G) {
         for (int f = 0; f < 6; ++f) {
             FaceDev& fd = td.f[f];
             int32_t src_chare = -1, pb = -1;
-            int32_t msg = -1;
             if (th.kind[f] == 2) src_chare = th.chare;
             else if (th.kind[f] == 0) {
                 if (cfg.exec == OD_PER_CHARE) pb = G.ghost_pb[(size_t)th.chare * 6 + f];
-                else if (G.use_xmsg && f < 2) msg = G.blocks_h[(size_t)th.src[f]].xmsg[f ^ 1];
                 else src_chare = th.src[f];
-                if (G.use_xmsg && f < 2 && msg < 0) return "internal error: missing x-face message";
             } else {
                 pb = G.dir_pb[(size_t)th.chare * 6 + f];
             }
-            if (msg >= 0) {
-                // the neighbour's x-face column, indexed by its local (y, z)
-                const Chare& sc = p.chares[(size_t)th.src[f]];
-                fd.src = msg;
-                fd.sx = 0;
-                fd.sy = th.g[f][1] - sc.o[1];
-                fd.sz = th.g[f][2] - sc.o[2];
-            } else if (src_chare >= 0) {
+            if (src_chare >= 0) {
                 const Chare& sc = p.chares[(size_t)src_chare];
                 fd.src = src_chare;
                 fd.sx = th.g[f][0] - sc.o[0];
@@ -197,14 +187,11 @@ std::string build_layout(const od_config& cfg, Grid& G) {
     G.pb_block.clear();
 
     // descriptor regions first (sizes known after tiles / pseudo-blocks)
-    // x-face messages: batched modes, unless hints bit 1 asks for direct reads
-    G.use_xmsg = cfg.exec != OD_PER_CHARE && (cfg.hints & 2) == 0;
     int32_t npb = 0;
     for (int32_t c = 0; c < C; ++c)
         for (int f = 0; f < 6; ++f) {
             if (on_domain_face(p, p.chares[(size_t)c], f)) ++npb;
             else if (cfg.exec == OD_PER_CHARE) ++npb;
-            else if (G.use_xmsg && f < 2) ++npb;
         }
     const size_t nblocks = (size_t)C + (size_t)npb;
     const size_t ntiles = p.tiles.size();
@@ -213,8 +200,9 @@ std::string build_layout(const od_config& cfg, Grid& G) {
     // plus splits down to the block granularity for explicit blocks)
     G.tile_cap = ntiles;
     if (cfg.exec == OD_FUSED || cfg.exec == OD_GRAPH || cfg.exec == OD_PERSISTENT) {
-        int32_t m[3];
-        tune_min_tile(G.s, m);
+        int32_t m[3], eymax = 1;
+        for (const Chare& c : p.chares) eymax = std::max(eymax, c.e[1]);
+        tune_min_tile(G.s, eymax, m);
         size_t cap = 0;
         for (const Chare& c : p.chares) {
             size_t k = 1;
@@ -248,7 +236,6 @@ std::string build_layout(const od_config& cfg, Grid& G) {
         std::string e2 = build_tile_deps(p, G.dep_ptr, G.dep_idx);
         if (!e2.empty()) return e2;
     }
-    G.L.xmsg_list = cv.take((size_t)C * 4);
     G.L.dep_ptr = cv.take((G.dep_ptr.size() + 1) * 4);
     G.L.dep_idx = cv.take((G.dep_idx.size() + 1) * 4);
     // imbalance table
@@ -287,25 +274,20 @@ std::string build_layout(const od_config& cfg, Grid& G) {
         B.ex = ch.e[0];
         B.ey = ch.e[1];
         B.ez = ch.e[2];
-        B.xmsg[0] = B.xmsg[1] = -1;
     }
     G.L.field_end = cv.off;
     // ---- pseudo-blocks
-    G.xmsg_chares.clear();
     for (int32_t c = 0; c < C; ++c) {
         const Chare& ch = p.chares[(size_t)c];
         for (int f = 0; f < 6; ++f) {
             const bool dom = on_domain_face(p, ch, f);
-            const bool xmsg = !dom && G.use_xmsg && f < 2;
-            if (!dom && cfg.exec != OD_PER_CHARE && !xmsg) continue;
+            if (!dom && cfg.exec != OD_PER_CHARE) continue;
             int32_t e[3], py;
             int64_t pz, cnt;
             face_shape(ch, G.cpy[(size_t)c], f, e, &py, &pz, &cnt);
             BlockDev B{};
             const size_t o = cv.take((size_t)cnt * s);
             B.off[0] = B.off[1] = (int64_t)(o / s);
-            if (xmsg) B.off[1] = (int64_t)(cv.take((size_t)cnt * s) / s);   // second parity
-            B.xmsg[0] = B.xmsg[1] = -1;
             B.py = py;
             B.pz = pz;
             B.ex = e[0];
@@ -313,11 +295,6 @@ std::string build_layout(const od_config& cfg, Grid& G) {
             B.ez = e[2];
             const int32_t id = (int32_t)G.blocks_h.size();
             G.blocks_h.push_back(B);
-            if (xmsg) {
-                G.blocks_h[(size_t)c].xmsg[f] = id;
-                if (G.xmsg_chares.empty() || G.xmsg_chares.back() != c) G.xmsg_chares.push_back(c);
-                continue;
-            }
             if (dom) {
                 G.dir_pb[(size_t)c * 6 + f] = id;
                 G.pb_face.push_back(f);
@@ -437,7 +414,6 @@ od_status Grid::upload() {
     if (e == hipSuccess) e = put(L.pb_face, pb_face.data(), pb_face.size() * 4);
     if (e == hipSuccess) e = put(L.pb_block, pb_block.data(), pb_block.size() * 4);
     if (e == hipSuccess) e = put(L.bc, cfg.bc, 6 * 8);
-    if (e == hipSuccess) e = put(L.xmsg_list, xmsg_chares.data(), xmsg_chares.size() * 4);
     if (e == hipSuccess) e = put(L.dep_ptr, dep_ptr.data(), dep_ptr.size() * 4);
     if (e == hipSuccess) e = put(L.dep_idx, dep_idx.data(), dep_idx.size() * 4);
     if (e == hipSuccess) e = put(L.extra, extra_h.data(), extra_h.size());
@@ -480,15 +456,6 @@ od_status Grid::init_field() {
                                reinterpret_cast<const int32_t*>(base + L.pb_block),
                                reinterpret_cast<const double*>(base + L.bc));
     if (e != hipSuccess) return fail(OD_EHIP, std::string("init: ") + hipGetErrorString(e));
-    return pack_xmsg(0);
-}
-
-od_status Grid::pack_xmsg(int par) {
-    if (xmsg_chares.empty()) return OD_OK;
-    hipError_t e = launch_pack_xmsg(s, st, base, reinterpret_cast<const BlockDev*>(base + L.blocks),
-                                    reinterpret_cast<const int32_t*>(base + L.xmsg_list),
-                                    (int32_t)xmsg_chares.size(), par);
-    if (e != hipSuccess) return fail(OD_EHIP, std::string("x-face pack: ") + hipGetErrorString(e));
     return OD_OK;
 }
 
@@ -526,7 +493,7 @@ od_status Grid::fused_one(hipStream_t s2, int par, int64_t step) {
     hipError_t e = launch_sweep(s, plan.tile[0], plan.tile[1], s2, base,
                                 reinterpret_cast<const BlockDev*>(base + L.blocks),
                                 reinterpret_cast<const TileDev*>(base + L.tiles), (int32_t)tiles_h.size(), par,
-                                res_ptr(), 0, 1, extra_row(step), cfg.hints);
+                                res_ptr(), 0, 1, extra_row(step), mode());
     if (e != hipSuccess) return fail(OD_EHIP, std::string("sweep launch: ") + hipGetErrorString(e));
     return OD_OK;
 }
@@ -575,7 +542,7 @@ od_status Grid::persistent_run(int64_t n) {
                                      parity, n, res_ptr(), 1, reinterpret_cast<unsigned int*>(base + L.bar),
                                      reinterpret_cast<unsigned int*>(base + L.err),
                                      extra_h.empty() ? nullptr : reinterpret_cast<const uint8_t*>(base + L.extra),
-                                     extra_period, (int32_t)plan.chares.size(), iters, cfg.hints);
+                                     extra_period, (int32_t)plan.chares.size(), iters, mode());
     if (e != hipSuccess) return fail(OD_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
     parity ^= (int)(n & 1);
     iters += n;
@@ -607,7 +574,7 @@ od_status Grid::msgdriven_run(int64_t n) {
     a.nchares = (int32_t)plan.chares.size();
     a.wait_ticks = device_wait_ticks();
     a.final_only = 1;
-    a.hints = cfg.hints;
+    a.hints = mode();
     e = launch_msgdriven(s, plan.tile[0], plan.tile[1], st, grid_wgs, a);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("msg-driven launch: ") + hipGetErrorString(e));
     parity = tgt & 1;
@@ -693,7 +660,7 @@ od_status Grid::per_chare_run(int64_t n) {
             const int32_t t0 = tile_lo[(size_t)c], t1 = tile_lo[(size_t)c + 1];
             e = launch_sweep(s, plan.tile[0], plan.tile[1], s2, base, reinterpret_cast<const BlockDev*>(base + L.blocks),
                              reinterpret_cast<const TileDev*>(base + L.tiles) + t0, t1 - t0, par, res_ptr(), c, c + 1,
-                             extra_row(iters), cfg.hints);
+                             extra_row(iters), mode());
             if (e == hipSuccess) e = launch_pack_b(s, s2, base, blocks_h[(size_t)c], par ^ 1, face_out(c, par ^ 1));
             if (e == hipSuccess) e = hipEventRecord(packed[(size_t)c], s2);
         }
@@ -797,12 +764,6 @@ od_status Grid::io(void* host, size_t bytes, bool to_host) {
             if (e == hipSuccess) e = hipStreamSynchronize(st);
             if (e != hipSuccess) return fail(OD_EHIP, std::string("scatter: ") + hipGetErrorString(e));
         }
-    }
-    if (!to_host) {
-        od_status os2 = pack_xmsg(0);
-        if (os2 != OD_OK) return os2;
-        e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return fail(OD_EHIP, std::string("sync: ") + hipGetErrorString(e));
     }
     return OD_OK;
 }

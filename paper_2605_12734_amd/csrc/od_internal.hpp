@@ -21,22 +21,14 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // face's ghost values (Dirichlet values of the domain, or the per-chare
 // ghost layer of the per-chare baseline), single-buffered (off[0]==off[1]).
 // Element (x, y, z) of the block lives at arena[off[p] + x + y*py + z*pz].
-//
-// A chare whose x- / x+ face borders another chare also owns an x-face
-// message per face (xmsg[0] / xmsg[1], block ids, -1 if none): its x = 0 /
-// x = ex-1 column, double-buffered like the field and written by the same
-// sweep that computes it (the pack step, fused).  Neighbours read their x
-// halo from these contiguous columns (the unpack step, fused) instead of
-// one scattered value per row of the chare's own storage.
 struct BlockDev {
     int64_t off[2];
     int64_t pz;
     int32_t py;
     int32_t ex, ey, ez;
-    int32_t xmsg[2];
-    int32_t pad_[4];
+    int32_t pad_;
 };
-static_assert(sizeof(BlockDev) == 64, "BlockDev layout");
+static_assert(sizeof(BlockDev) == 48, "BlockDev layout");
 
 // Where a tile reads the ghost slab of one face: block `src`, whose local
 // coordinates (sx, sy, sz) correspond to the slab cell next to the tile's

@@ -21,7 +21,7 @@ uint64_t host_sm64(uint64_t seed, uint64_t idx);
 struct Layout {
     size_t blocks = 0, tiles = 0, cidx[3] = {0, 0, 0}, owner = 0, corigin = 0, dir_pb = 0;
     size_t pb_face = 0, pb_block = 0, bc = 0, res = 0, bar = 0, err = 0, done = 0, target = 0;
-    size_t dep_ptr = 0, dep_idx = 0, extra = 0, field_end = 0, total = 0, xmsg_list = 0;
+    size_t dep_ptr = 0, dep_idx = 0, extra = 0, field_end = 0, total = 0;
 };
 
 // Per-chare baseline message buffers (byte offsets): outgoing face messages
@@ -47,8 +47,6 @@ struct Grid {
     std::vector<MsgBufs> msg;
     int32_t nres = 1;
     size_t tile_cap = 0;             // tile descriptors the workspace has room for
-    bool use_xmsg = false;           // x halos read from fused x-face messages
-    std::vector<int32_t> xmsg_chares;  // chares owning at least one x-face message
 
     // device state
     hipStream_t st = nullptr;
@@ -73,10 +71,11 @@ struct Grid {
     bool pinned_borrowed = false;    // staging owned by someone else (serving)
 
     ~Grid();
+    // kernel mode bits: od_config.hints, plus bit 8 for the 5-point stencil
+    int mode() const { return cfg.hints | (cfg.stencil == 5 ? 0x100 : 0); }
     od_status upload();
     od_status reset_state();
     od_status init_field();
-    od_status pack_xmsg(int par);
     od_status ensure_pinned(size_t bytes);
     unsigned long long* res_ptr();
     const uint8_t* extra_row(int64_t step) const;
@@ -95,7 +94,7 @@ struct Grid {
 std::string build_layout(const od_config& cfg, Grid& G);
 std::string fill_tile_descs(Grid& G);
 // Smallest tile extents any autotune candidate uses for a dtype.
-void tune_min_tile(int dtype_bytes, int32_t m[3]);
+void tune_min_tile(int dtype_bytes, int32_t ey_max, int32_t m[3]);
 od_status autotune(Grid& G, int32_t iters, int32_t out_tile[3]);
 std::string build_tile_deps(const Plan& p, std::vector<int32_t>& ptr, std::vector<int32_t>& idx);
 

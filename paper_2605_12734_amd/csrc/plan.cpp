@@ -60,6 +60,8 @@ std::string plan_decompose(const od_config& cfg, Plan& p) {
         p.n[d] = cfg.n[d];
     }
     if (cfg.dtype != OD_F32 && cfg.dtype != OD_F64) return fmt("dtype %lld is neither OD_F32 nor OD_F64", (long long)cfg.dtype);
+    if (cfg.stencil != 0 && cfg.stencil != 7 && cfg.stencil != 5) return fmt("stencil %lld must be 7 or 5", cfg.stencil);
+    if (cfg.stencil == 5 && cfg.n[1] != 1) return "the 5-point (2D) stencil needs n[1] == 1";
     p.interior = p.n[0] * p.n[1] * p.n[2];
     p.chares.clear();
     p.owner.clear();
@@ -116,8 +118,24 @@ std::string plan_decompose(const od_config& cfg, Plan& p) {
         }
     } else {
         if (cfg.odf < 1) return fmt("odf %lld must be >= 1", cfg.odf);
-        auto f = factor3(cfg.odf);
-        for (int d = 0; d < 3; ++d) k[d] = f[d];
+        // split over the dimensions that have more than one cell
+        int act[3], na = 0;
+        for (int d = 0; d < 3; ++d)
+            if (p.n[d] > 1) act[na++] = d;
+        for (int d = 0; d < 3; ++d) k[d] = 1;
+        if (na == 3) {
+            auto f = factor3(cfg.odf);
+            for (int d = 0; d < 3; ++d) k[d] = f[d];
+        } else if (na == 2) {
+            int32_t a = (int32_t)std::llround(std::sqrt((double)cfg.odf));
+            while (a > 1 && cfg.odf % a) --a;
+            k[act[0]] = a;
+            k[act[1]] = cfg.odf / a;
+        } else if (na == 1) {
+            k[act[0]] = cfg.odf;
+        } else if (cfg.odf != 1) {
+            return "a 1x1x1 grid has one chare";
+        }
     }
     for (int d = 0; d < 3; ++d) {
         if (k[d] > p.n[d]) return fmt("%lld chares along dim %lld exceed the %lld cells", k[d], d, p.n[d]);
@@ -170,10 +188,20 @@ void plan_default_tile(const od_config& cfg, Plan& p) {
     int32_t emin[3] = {1 << 30, 1 << 30, 1 << 30};
     for (const auto& c : p.chares)
         for (int d = 0; d < 3; ++d) emin[d] = std::min(emin[d], c.e[d]);
-    // One tile row of 32 (f64) / 64 (f32) cells, 8 rows, z-columns of up to 64.
-    p.tile[0] = cfg.dtype == OD_F64 ? 32 : 64;
-    p.tile[1] = 8;
-    p.tile[2] = std::min<int32_t>(64, std::max<int32_t>(1, emin[2]));
+    int32_t emax1 = 1;
+    for (const auto& c : p.chares) emax1 = std::max(emax1, c.e[1]);
+    if (emax1 == 1) {
+        // one cell thick in y (2D): long single-row tiles marching z
+        p.tile[0] = cfg.dtype == OD_F64 ? 256 : 512;
+        p.tile[1] = 1;
+        p.tile[2] = std::min<int32_t>(64, std::max<int32_t>(1, emin[2]));
+        return;
+    }
+    // rows of 32 cells (one 16-lane row of 16-byte vectors for f64), 16 rows
+    // (f64) / 32 rows (f32), z-columns of up to 32 cells
+    p.tile[0] = 32;
+    p.tile[1] = cfg.dtype == OD_F64 ? 16 : 32;
+    p.tile[2] = std::min<int32_t>(32, std::max<int32_t>(1, emin[2]));
 }
 
 namespace {

@@ -173,8 +173,6 @@ od_status Server::setup_slot(Request& R, int32_t slot) {
     for (BlockDev& b : blocks) {
         b.off[0] += (int64_t)(R.off / (size_t)sb);
         b.off[1] += (int64_t)(R.off / (size_t)sb);
-        for (int q = 0; q < 2; ++q)
-            if (b.xmsg[q] >= 0) b.xmsg[q] += slot * kMaxBlocks;
     }
     std::vector<TileDev> tiles(G.tiles_h);
     for (TileDev& t : tiles) {

@@ -63,11 +63,16 @@ void store_file_cache(const std::string& key, const std::array<int32_t, 3>& t) {
 
 }  // namespace
 
-void tune_min_tile(int dtype_bytes, int32_t m[3]) {
+// Candidates for chares of at most ey_max rows: single-row variants only for
+// grids one cell thick in y (the 2D stencil), multi-row ones otherwise.
+static bool candidate_ok(const SweepVariant& v, int32_t ey_max) { return (v.ty == 1) == (ey_max == 1); }
+
+void tune_min_tile(int dtype_bytes, int32_t ey_max, int32_t m[3]) {
     int n = 0;
     const SweepVariant* v = sweep_variants(dtype_bytes, &n);
     m[0] = m[1] = 1 << 30;
     for (int i = 0; i < n; ++i) {
+        if (!candidate_ok(v[i], ey_max)) continue;
         m[0] = std::min(m[0], v[i].tx);
         m[1] = std::min(m[1], v[i].ty);
     }
@@ -136,6 +141,7 @@ od_status autotune(Grid& G, int32_t iters, int32_t out_tile[3]) {
     const SweepVariant* v = sweep_variants(G.s, &nv);
     const int32_t vx = 16 / G.s;
     for (int i = 0; i < nv; ++i) {
+        if (!candidate_ok(v[i], emax[1])) continue;
         if (v[i].tx > 2 * ((emax[0] + vx - 1) / vx * vx) && v[i].tx > 16) continue;   // mostly idle lanes
         if (v[i].ty > 2 * emax[1] && v[i].ty > 4) continue;
         std::vector<int32_t> tzs;
@@ -158,7 +164,7 @@ od_status autotune(Grid& G, int32_t iters, int32_t out_tile[3]) {
             return launch_sweep(G.s, G.plan.tile[0], G.plan.tile[1], G.st, G.base,
                                 reinterpret_cast<const BlockDev*>(G.base + G.L.blocks),
                                 reinterpret_cast<const TileDev*>(G.base + G.L.tiles), (int32_t)G.tiles_h.size(),
-                                G.parity, G.res_ptr(), 0, 1, nullptr, G.cfg.hints);
+                                G.parity, G.res_ptr(), 0, 1, nullptr, G.mode());
         };
         he = launch();   // warm-up
         if (he == hipSuccess) he = hipEventRecord(a, G.st);

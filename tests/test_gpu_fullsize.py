@@ -1,0 +1,158 @@
+"""Parity at the benchmark's full sizes, in the launch configurations the
+benchmark times.
+
+Outputs the oracle cannot compute for the whole grid are checked one by one
+(each sampled point's value after t sweeps depends only on cells within
+Chebyshev distance t, so the oracle evaluates it on a small sub-box), and
+properties that hold at any size are checked on the whole field: identical
+bits across execution modes and decompositions at the full iteration
+count, and a discrete-harmonic linear field that must stay fixed.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2605_12734_amd as od
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _sample_points(n, count, seed):
+    rng = np.random.default_rng(seed)
+    pts = [tuple(int(rng.integers(0, m)) for m in n) for _ in range(count)]
+    nx, ny, nz = n
+    # corners, faces and chare-boundary neighbourhoods
+    pts += [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (0, ny // 2, nz // 2), (nx - 1, 0, nz - 1),
+            (31, 31, 31), (32, 32, 32), (31, 32, 33), (nx // 2, ny // 2, 0)]
+    return pts
+
+
+def _lin(pts, n):
+    nx, ny, _ = n
+    return np.array([(k * ny + j) * nx + i for (i, j, k) in pts], dtype=np.int64)
+
+
+def _tuned(n, odf, dtype, exec_="graph", hints=1, **kw):
+    g = od.Grid(n, odf=odf, dtype=dtype, exec="fused", hints=hints, **kw)
+    tile = g.autotune(2)
+    g.close()
+    return od.Grid(n, odf=odf, dtype=dtype, exec=exec_, tile=tile, hints=hints, **kw)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_512_odf4096_sampled_against_oracle(dtype):
+    n = (512, 512, 512)
+    iters = 10
+    g = _tuned(n, 4096, dtype)
+    try:
+        g.iterate(iters)
+        pts = _sample_points(n, 48, 1)
+        got = g.read_points(_lin(pts, n))
+    finally:
+        g.close()
+    want = oracle.point_values(n, pts, iters, np.float64 if dtype == "f64" else np.float32)
+    assert np.array_equal(got, want)
+
+
+def test_512_odf4096_full_iterations_identical_across_modes():
+    # 200 iterations: graph (bench launch configuration) = persistent =
+    # message-driven = fused with another tile = ODF 8
+    n = 512
+    g = _tuned(n, 4096, "f64", "graph")
+    try:
+        g.iterate(200)
+        ref = g.read()
+        r_ref = g.residual()
+    finally:
+        g.close()
+    assert np.isfinite(ref).all()
+    for kw in (dict(odf=4096, exec="persistent"), dict(odf=4096, exec="msgdriven"),
+               dict(odf=4096, exec="fused", tile=(32, 8, 16)), dict(odf=8, exec="graph", tile=(64, 8, 32))):
+        g = od.Grid(n, dtype="f64", hints=1, **kw)
+        try:
+            g.iterate(200)
+            U = g.read()
+            r = g.residual()
+        finally:
+            g.close()
+        assert r == r_ref, kw
+        assert np.array_equal(U, ref), kw
+
+
+def test_512_linear_field_fixed_full_size():
+    n = (512, 512, 512)
+    k, j, i = np.meshgrid(np.arange(-1, 513), np.arange(-1, 513), np.arange(-1, 513), indexing="ij",
+                          sparse=True)
+    L = (7.0 + i + 2.0 * j - 3.0 * k).astype(np.float64)
+    g = _tuned(n, 4096, "f64")
+    try:
+        g.write(np.broadcast_to(L, (514, 514, 514)))
+        g.iterate(200)
+        assert g.residual() == 0.0
+        U = g.read()
+    finally:
+        g.close()
+    inner = (slice(1, -1), slice(1, -1), slice(1, -1))
+    assert np.array_equal(U[inner], np.broadcast_to(L, (514, 514, 514))[inner])
+
+
+@pytest.mark.parametrize("exec_", ["msgdriven", "persistent"])
+def test_1024_odf32768_imbalance_sampled(exec_):
+    n = (1024, 1024, 1024)
+    iters = 12
+    g = od.Grid(n, odf=32768, dtype="f64", exec=exec_, tile=(32, 16, 32), hints=1, imbalance_pct=10,
+                imbalance_max_extra=4)
+    try:
+        g.iterate(iters)
+        pts = _sample_points(n, 32, 2)
+        got = g.read_points(_lin(pts, n))
+    finally:
+        g.close()
+    want = oracle.point_values(n, pts, iters, np.float64)
+    assert np.array_equal(got, want)
+
+
+def test_768_octree_sampled_graph_and_persistent():
+    blocks = workloads.octree_blocks(n=768, root=128, min_edge=16, p_refine=0.4, seed=12734)
+    n = (768, 768, 768)
+    iters = 12
+    pts = _sample_points(n, 32, 3)
+    want = oracle.point_values(n, pts, iters, np.float64)
+    for exec_ in ("graph", "persistent"):
+        g = od.Grid(768, blocks=blocks, dtype="f64", exec="fused", hints=1)
+        tile = g.autotune(2)
+        g.close()
+        g = od.Grid(768, blocks=blocks, dtype="f64", exec=exec_, tile=tile, hints=1)
+        try:
+            g.iterate(iters)
+            got = g.read_points(_lin(pts, n))
+        finally:
+            g.close()
+        assert np.array_equal(got, want), exec_
+
+
+def test_served_384_request_matches_oracle():
+    from paper_2605_12734_amd.serving import Server
+    q = dict(n=384, dtype="f64", odf=64, tol=1e-6, max_iters=30, check_every=10, seed=77)
+    want, it, r = oracle.solve(384, np.float64, seed=77, iters=30, tol=1e-6, check_every=10)
+    with Server(arena_bytes=3 << 30, max_slots=4) as srv:
+        t = srv.submit(**q)
+        res = srv.wait(t, timeout=300)
+        field = srv.fetch(t)
+    assert res["iters"] == it and res["residual"] == r
+    assert np.array_equal(field, want)
+
+
+@pytest.mark.parametrize("n", [(1, 1, 1), (1, 5, 1), (2, 1, 3), (3, 3, 1)])
+@pytest.mark.parametrize("exec_", ["fused", "persistent", "msgdriven", "per_chare", "graph"])
+def test_degenerate_tiny_grids(n, exec_):
+    want, _, r_w = oracle.solve(n, np.float64, seed=5, iters=7)
+    g = od.Grid(n, odf=1, dtype="f64", exec=exec_, seed=5)
+    try:
+        g.iterate(7)
+        r = g.residual()
+        U = g.read()
+    finally:
+        g.close()
+    assert np.array_equal(U, want) and r == r_w

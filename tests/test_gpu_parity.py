@@ -229,11 +229,10 @@ def test_autotune_keeps_bits(exec_, dtype):
     assert r == r_w
 
 
-@pytest.mark.parametrize("hints", [1, 2, 3])
-@pytest.mark.parametrize("exec_", ["graph", "msgdriven"])
+@pytest.mark.parametrize("hints", [1])
+@pytest.mark.parametrize("exec_", ["graph", "msgdriven", "persistent"])
 def test_hints_keep_bits(hints, exec_):
-    # bit 0: non-temporal output stores; bit 1: x halos read straight from the
-    # neighbour's storage instead of the fused x-face messages
+    # bit 0: non-temporal output stores
     want, _, r_w = _oracle((70, 36, 40), "f64", 9, seed=3)
     U, r, _ = _run((70, 36, 40), 9, odf=64, dtype="f64", exec=exec_, hints=hints, seed=3)
     _assert_same(U, want)

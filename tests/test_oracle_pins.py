@@ -264,3 +264,74 @@ def test_point_values_match_full_oracle(oracle_mod, dtype):
     vals = oracle_mod.point_values(n, pts, 5, dtype, seed=4, bc=bc)
     want = np.array([full[k + 1, j + 1, i + 1] for (i, j, k) in pts], dtype=dtype)
     assert np.array_equal(vals, want)
+
+
+# ---- Jacobi2D (the paper's own workload, Section V) -------------------------
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_2d_brute_force_bit_identical(oracle_mod, dtype):
+    bc = (1.0, 0.0, 0.5, 0.25)
+    for nx, ny in ((7, 5), (1, 6), (9, 9)):
+        Ub = brute.init_field2d(nx, ny, dtype, 9, bc)
+        Uc = oracle_mod.init_field2d((nx, ny), dtype, 9, bc)
+        assert np.array_equal(np.array(Ub, dtype=dtype), Uc)
+        r_b = None
+        for _ in range(5):
+            Ub, r_b = brute.sweep2d(Ub)
+        Oc, it, r_c = oracle_mod.jacobi2d(Uc, 5)
+        assert np.array_equal(np.array(Ub, dtype=dtype), Oc) and float(r_b) == r_c
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_2d_constant_and_linear_fixed(oracle_mod, dtype):
+    U = oracle_mod.init_field2d((8, 6), dtype, 1, (0.5,) * 4)
+    U[...] = dtype(0.5)
+    O, _, r = oracle_mod.jacobi2d(U, 9)
+    assert r == 0.0 and np.all(O[1:-1, 1:-1] == dtype(0.5))
+    j, i = np.meshgrid(np.arange(-1, 7), np.arange(-1, 9), indexing="ij")
+    L = (2.0 + 3.0 * i - 1.0 * j).astype(dtype)
+    O, _, r = oracle_mod.jacobi2d(L, 4)
+    assert r == 0.0 and np.array_equal(O, L)
+
+
+def test_2d_spectral_eigenfunction_and_decay(oracle_mod):
+    nx, ny = 12, 9
+    j, i = np.meshgrid(np.arange(-1, ny + 1), np.arange(-1, nx + 1), indexing="ij")
+    U = np.sin(np.pi * 2 * (i + 1) / (nx + 1)) * np.sin(np.pi * 3 * (j + 1) / (ny + 1))
+    U[:, 0] = U[:, -1] = 0
+    U[0, :] = U[-1, :] = 0
+    lam = (np.cos(2 * np.pi / (nx + 1)) + np.cos(3 * np.pi / (ny + 1))) / 2
+    V, _ = oracle_mod.sweep2d(U)
+    assert np.abs(V[1:-1, 1:-1] - lam * U[1:-1, 1:-1]).max() < 1e-15
+    # residual decays two steps at a time like cos^2(pi/(N+1)) on a square
+    n = 10
+    U = oracle_mod.init_field2d(n, np.float64, 4)
+    rs = []
+    for _ in range(404):
+        U, r = oracle_mod.sweep2d(U)
+        rs.append(r)
+    assert abs(rs[402] / rs[400] - np.cos(np.pi / (n + 1)) ** 2) < 1e-6
+
+
+def test_2d_superposition_centre_quarter(oracle_mod):
+    n = 9
+    total, centre = None, []
+    for f in range(4):
+        bc = [0.0] * 4
+        bc[f] = 1.0
+        U = oracle_mod.init_field2d(n, np.float64, 2, bc)
+        U[1:-1, 1:-1] = 0.0
+        O, _, r = oracle_mod.jacobi2d(U, 5000, tol=1e-15, check_every=1)
+        I = O[1:-1, 1:-1]
+        centre.append(I[n // 2, n // 2])
+        total = I if total is None else total + I
+    assert np.abs(total - 1.0).max() < 1e-12
+    assert all(abs(c - 0.25) < 1e-13 for c in centre)
+
+
+def test_2d_point_values_match_full_oracle(oracle_mod):
+    n2 = (13, 11)
+    full, _, _ = oracle_mod.solve2d(n2, np.float64, seed=6, iters=6)
+    pts = [(0, 0), (12, 10), (6, 5), (1, 9), (12, 0)]
+    got = oracle_mod.point_values2d(n2, pts, 6, np.float64, seed=6)
+    assert np.array_equal(got, np.array([full[j + 1, i + 1] for i, j in pts]))
