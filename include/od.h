@@ -107,7 +107,8 @@ typedef struct {
     int32_t imbalance_max_extra;
     /* Implementation hints, 0 = defaults; none of them changes a result.
      * bit 0: write the sweep's output with non-temporal (streaming) stores;
-     * other bits are ignored. */
+     * bit 1: launch tiles in plain spatial order instead of grouping
+     * spatial neighbours on one XCD; other bits are ignored. */
     int32_t hints;
     /* 7 (or 0): 3D 7-point stencil.  5: the 2D 5-point stencil of the
      * paper's Jacobi2D workload, u' = (((u[i-1] + u[i+1]) + u[k-1]) + u[k+1]) / 4,

@@ -14,6 +14,12 @@
 
 #include "kernels.hpp"
 
+// Planes of the register column loaded ahead of the one being computed
+// (beyond the plane above it).
+#ifndef OD_PREFETCH
+#define OD_PREFETCH 2
+#endif
+
 namespace od {
 
 // ---------------------------------------------------------------------------
@@ -171,20 +177,24 @@ __device__ __forceinline__ T sweep_tile(T* __restrict__ arena, const BlockDev* _
         return zz < 0 ? ldv(zm_b + o_zm) : (zz >= nz ? ldv(zp_b + o_zp) : ldv(own_b + zz * own_pz * ES + o_own));
     };
 
-    // register column: p0 = plane z-1, p1 = z, p2 = z+1, p3 = z+2, p4 = z+3
-    VT p0 = plane(-1);
-    VT p1 = plane(0);
-    VT p2 = plane(1);
-    VT p3 = plane(2 <= nz ? 2 : nz);
+    // register column pl[k] = plane z-1+k: below, current, above, and PF
+    // planes prefetched ahead (clamped to the z+ face)
+    constexpr int PF = OD_PREFETCH;
+    VT pl[PF + 3];
+#pragma unroll
+    for (int k = 0; k < PF + 2; ++k) pl[k] = plane(k - 1 <= nz ? k - 1 : nz);
     VT hym = ldv(ym_b + o_y), hyp = ldv(yp_b + o_y);
     T hxm = lds1(xm_b + o_xm), hxp = lds1(xp_b + o_xp);
 
     T r = 0;
     for (int z = 0; z < nz; ++z) {
         const int b = z & 1;
-        // prefetch: plane z+3 (clamped to the z+ face) and the halo of z+1
-        const int zq = z + 3 <= nz ? z + 3 : nz;
-        const VT p4 = plane(zq);
+        // prefetch: plane z+PF+1 and the halo of z+1
+        const int zq = z + PF + 1 <= nz ? z + PF + 1 : nz;
+        pl[PF + 2] = plane(zq);
+        const VT& p0 = pl[0];
+        const VT& p1 = pl[1];
+        const VT& p2 = pl[2];
         const int64_t zh = z + 1 < nz ? z + 1 : z;
         const VT nym = ldv(ym_b + zh * ym_pz * ES + o_y), nyp = ldv(yp_b + zh * yp_pz * ES + o_y);
         const T nxm = lds1(xm_b + zh * xm_pz * ES + o_xm), nxp = lds1(xp_b + zh * xp_pz * ES + o_xp);
@@ -241,10 +251,8 @@ __device__ __forceinline__ T sweep_tile(T* __restrict__ arena, const BlockDev* _
             else
                 *o = out;
         }
-        p0 = p1;
-        p1 = p2;
-        p2 = p3;
-        p3 = p4;
+#pragma unroll
+        for (int k = 0; k < PF + 2; ++k) pl[k] = pl[k + 1];
         hym = nym;
         hyp = nyp;
         hxm = nxm;

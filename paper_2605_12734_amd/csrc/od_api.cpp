@@ -164,6 +164,7 @@ std::string build_layout(const od_config& cfg, Grid& G) {
                 return "explicit block x-origins must be multiples of " + std::to_string(vx) + " for this dtype";
     }
     plan_default_tile(cfg, p);
+    p.xcd_order = (cfg.hints & 2) == 0;
     if (!sweep_variant_ok(G.s, p.tile[0], p.tile[1]))
         return "tile (" + std::to_string(p.tile[0]) + "," + std::to_string(p.tile[1]) + ") is not a compiled variant";
     err = plan_tiles(p);

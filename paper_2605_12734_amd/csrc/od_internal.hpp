@@ -79,6 +79,7 @@ struct Plan {
     std::vector<int32_t> owner;          // (og z, og y, og x) -> chare
     std::vector<TileHost> tiles;         // in launch order (XCD-interleaved)
     int32_t tile[3] = {0, 0, 0};
+    bool xcd_order = true;               // group tiles per XCD (else plain spatial order)
     int64_t interior = 0;
     int64_t halo_cells = 0;              // ghost cells read from other chares per sweep
 };

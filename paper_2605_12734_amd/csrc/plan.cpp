@@ -349,11 +349,15 @@ std::string plan_tiles(Plan& p) {
     size_t m = (T + kNumXcd - 1) / kNumXcd;
     std::vector<TileHost> ordered;
     ordered.reserve(T);
-    for (size_t j = 0; j < m; ++j)
-        for (int g = 0; g < kNumXcd; ++g) {
-            size_t s = (size_t)g * m + j;
-            if (s < T && j < m) ordered.push_back(out[idx[s]]);
-        }
+    if (!p.xcd_order) {
+        for (size_t s = 0; s < T; ++s) ordered.push_back(out[idx[s]]);
+    } else {
+        for (size_t j = 0; j < m; ++j)
+            for (int g = 0; g < kNumXcd; ++g) {
+                size_t s = (size_t)g * m + j;
+                if (s < T) ordered.push_back(out[idx[s]]);
+            }
+    }
     p.tiles.swap(ordered);
     return "";
 }
