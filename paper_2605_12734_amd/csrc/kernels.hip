@@ -272,7 +272,7 @@ k_sweep(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDe
     __shared__ T red[S::NT / 64];
     if (blockIdx.x == 0)
         for (int s = zero_lo + (int)threadIdx.x; s < zero_hi; s += S::NT) res[2 * s + parity] = 0ull;
-    const TileDev t = tiles[blockIdx.x];
+    const TileDev& t = tiles[blockIdx.x];
     const int reps = 1 + (extra ? (int)extra[t.blk] : 0);
     T r = 0;
     for (int rep = 0; rep < reps; ++rep) r = sweep_tile<T, TX, TY>(arena, blocks, t, parity, lds, hints);
@@ -333,7 +333,7 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
         T r = 0;
         int slot = -1;
         for (int32_t ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
-            const TileDev t = tiles[ti];
+            const TileDev& t = tiles[ti];
             const int reps = 1 + (ex ? (int)ex[t.blk] : 0);
             T rr = 0;
             for (int rep = 0; rep < reps; ++rep) rr = sweep_tile<T, TX, TY>(arena, blocks, t, p, lds, hints);
@@ -485,7 +485,7 @@ __global__ void __launch_bounds__((TX / V16<T>::N) * TY) k_msgdriven(MsgArgs a) 
     __shared__ double red[S::NT / 64];
     T* arena = reinterpret_cast<T*>(a.arena);
     auto sweep = [&](int32_t gid, int32_t step) -> double {
-        const TileDev t = a.tiles[gid];
+        const TileDev& t = a.tiles[gid];
         const uint8_t* ex = a.extra ? a.extra + (size_t)(step % a.extra_period) * a.nchares : nullptr;
         const int reps = 1 + (ex ? (int)ex[t.blk] : 0);
         T r = 0;
@@ -508,7 +508,7 @@ __global__ void __launch_bounds__((TX8 / 2) * TY8) k_serve(MsgArgs a) {
     __shared__ __attribute__((aligned(16))) unsigned char lds_raw[LDSB];
     __shared__ double red[S8::NT / 64];
     auto sweep = [&](int32_t gid, int32_t step) -> double {
-        const TileDev t = a.tiles[gid];
+        const TileDev& t = a.tiles[gid];
         const int32_t sv = a.tile_solve[gid];
         if (a.solve_dtype[sv] == 8)
             return (double)sweep_tile<double, TX8, TY8>(reinterpret_cast<double*>(a.arena), a.blocks, t, step & 1,
