@@ -15,6 +15,11 @@ Optional legs (each adds a key to the same line):
                a hipGraph, and as one persistent launch
   --imbalance  1024^3 fp64, ODF 8..32768, 10% of chares re-run 1-4 times per
                step: message-driven scheduler vs bulk-synchronous forms
+  --jacobi2d   the paper's Jacobi2D: 32768^2 fp64 5-point, 100 iterations,
+               ODF 1..1024, batched vs per-chare launches
+  --launch     launch-cost microbenchmarks: fixed work split into 1..1024
+               kernels released at once from a stream gate; launch rate
+               from 1-4 host threads x 1-4 chares per thread
   --serving    Poisson stream of independent solves at 10..2000 /s under a
                200 GB budget: p50/p99 latency, solves/s, GLUP/s
   --all        all of the above
@@ -194,8 +199,71 @@ def imbalance_leg(iters=1000, odfs=(8, 64, 512, 4096, 32768)):
     return rows
 
 
+def jacobi2d_leg(n=32768, iters=100, odfs=(1, 4, 16, 64, 256, 1024)):
+    """The paper's Jacobi2D workload on one GPU's share: n^2 fp64, 5-point,
+    `iters` iterations, batched (graph) vs per-chare launches per ODF."""
+    import paper_2605_12734_amd as od
+
+    rows = []
+    for odf in odfs:
+        t = od.Grid2D(n, odf=odf, dtype="f64", exec="fused", hints=1)
+        try:
+            tile = t.autotune(2)
+        finally:
+            t.close()
+        row = {"n": n, "odf": odf, "tile": list(tile)}
+        for exec_, it, steps in (("graph", iters, 2), ("per_chare", 10 if odf <= 64 else 4, 1)):
+            g = od.Grid2D(n, odf=odf, dtype="f64", exec=exec_, tile=tile, hints=1)
+            try:
+                plan = g.plan()
+                tm = timed(g, it, steps, 1)
+            finally:
+                g.close()
+            glups = plan["interior"] * it * steps / tm["wall_s"] / 1e9
+            row[exec_ + "_glups"] = round(glups, 2)
+            if exec_ == "graph":
+                gbps = plan["bytes_per_iter"] * it * steps / tm["dev_s"] / 1e9
+                row["graph_hbm_gbps"] = round(gbps, 1)
+                row["graph_frac"] = round(gbps / PEAK_HBM_GBPS, 4)
+                row["graph_ms_per_100_iters"] = round(tm["wall_s"] / (it * steps) * 100 * 1e3, 2)
+        row["speedup_batched_vs_per_chare"] = round(row["graph_glups"] / row["per_chare_glups"], 1)
+        log("jacobi2d:", row)
+        rows.append(row)
+    return rows
+
+
+def launch_leg(totals=(1 << 18, 1 << 20), kernels=(1, 2, 4, 8, 16, 32, 64, 256, 1024), work=20000,
+               rate_threads=(1, 2, 4), rate_chares=(1, 2, 4)):
+    """Launch-cost microbenchmarks: the same work split over more kernels,
+    all released at once from a stream gate (device makespan vs ODF); and
+    kernels launched per second from host threads x chares per thread."""
+    import paper_2605_12734_amd as od
+
+    overlap = []
+    for total in totals:
+        base = None
+        for nk in kernels:
+            best = None
+            for _ in range(3):
+                r = od.launch_overlap(total, nk, work=work)
+                best = r if best is None or r["makespan_us"] < best["makespan_us"] else best
+            base = base or best["makespan_us"]
+            row = {"threads": total, "kernels": nk, "streams": best["nstreams"],
+                   "makespan_us": round(best["makespan_us"], 1), "host_us": round(best["host_us"], 1),
+                   "enqueue_us": round(best["enqueue_us"], 1),
+                   "makespan_vs_1_kernel": round(best["makespan_us"] / base, 3)}
+            log("launch overlap:", row)
+            overlap.append(row)
+    rate = []
+    for t in rate_threads:
+        for c in rate_chares:
+            n, kps = od.launch_rate(t, c, seconds=0.5)
+            rate.append({"host_threads": t, "chares_per_thread": c, "kernels_per_s": round(kps)})
+            log("launch rate:", rate[-1])
+    return {"work_per_thread": work, "overlap": overlap, "rate": rate}
+
+
 def serving_leg(rates=(10, 30, 100, 300, 1000, 2000), count=64, arena_gb=200.0):
-    import numpy as np
     import torch
 
     import workloads
@@ -204,41 +272,50 @@ def serving_leg(rates=(10, 30, 100, 300, 1000, 2000), count=64, arena_gb=200.0):
     free = torch.cuda.mem_get_info()[0]
     arena = int(min(arena_gb * 1e9, free * 0.85)) // 256 * 256
     out = []
-    for rate in rates:
-        reqs = workloads.serving_requests(rate, count, seed=12734 + int(rate))
-        with Server(arena_bytes=arena, max_slots=min(count, 256)) as srv:
-            t0 = time.monotonic()
-            tickets = {}
-            pending = list(reqs)
-            done = {}
-            while pending or len(done) < len(reqs):
-                now = time.monotonic() - t0
-                while pending and pending[0]["t_arrival"] <= now:
-                    q = pending.pop(0)
-                    tickets[srv.submit(q["n"], q["dtype"], odf=q["odf"], tol=q["tol"], max_iters=q["max_iters"],
-                                       check_every=q["check_every"], seed=q["seed"])] = q
-                for t in list(tickets):
-                    if t in done:
-                        continue
-                    r = srv.poll(t)
-                    if r is not None:
-                        done[t] = r
-                        srv.fetch(t)
-                if pending and not any(t not in done for t in tickets):
-                    time.sleep(max(0.0, min(0.002, pending[0]["t_arrival"] - (time.monotonic() - t0))))
-                else:
-                    time.sleep(2e-4)
-        lat = np.array([done[t]["t_done"] - done[t]["t_submit"] for t in tickets])
-        first = min(r["t_submit"] for r in done.values())
-        last = max(r["t_done"] for r in done.values())
-        lups = sum(q["n"] ** 3 * done[t]["iters"] for t, q in tickets.items())
-        row = {"rate": rate, "requests": count, "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
-               "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
-               "solves_per_s": round(count / (last - first), 2), "glups": round(lups / (last - first) / 1e9, 2),
-               "mean_iters": round(float(np.mean([r["iters"] for r in done.values()])), 1)}
-        log("serving:", row)
-        out.append(row)
+    # one server (one arena) for every arrival rate: the arena is most of HBM
+    with Server(arena_bytes=arena, max_slots=min(count, 256)) as srv:
+        for rate in rates:
+            out.append(_serve_rate(srv, rate, count))
     return out
+
+
+def _serve_rate(srv, rate, count):
+    import numpy as np
+
+    import workloads
+
+    reqs = workloads.serving_requests(rate, count, seed=12734 + int(rate))
+    t0 = time.monotonic()
+    tickets = {}
+    pending = list(reqs)
+    done = {}
+    while pending or len(done) < len(reqs):
+        now = time.monotonic() - t0
+        while pending and pending[0]["t_arrival"] <= now:
+            q = pending.pop(0)
+            tickets[srv.submit(q["n"], q["dtype"], odf=q["odf"], tol=q["tol"], max_iters=q["max_iters"],
+                               check_every=q["check_every"], seed=q["seed"])] = q
+        for t in list(tickets):
+            if t in done:
+                continue
+            r = srv.poll(t)
+            if r is not None:
+                done[t] = r
+                srv.fetch(t)
+        if pending and not any(t not in done for t in tickets):
+            time.sleep(max(0.0, min(0.002, pending[0]["t_arrival"] - (time.monotonic() - t0))))
+        else:
+            time.sleep(2e-4)
+    lat = np.array([done[t]["t_done"] - done[t]["t_submit"] for t in tickets])
+    first = min(r["t_submit"] for r in done.values())
+    last = max(r["t_done"] for r in done.values())
+    lups = sum(q["n"] ** 3 * done[t]["iters"] for t, q in tickets.items())
+    row = {"rate": rate, "requests": count, "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+           "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+           "solves_per_s": round(count / (last - first), 2), "glups": round(lups / (last - first) / 1e9, 2),
+           "mean_iters": round(float(np.mean([r["iters"] for r in done.values()])), 1)}
+    log("serving:", row)
+    return row
 
 
 def main():
@@ -258,6 +335,8 @@ def main():
     ap.add_argument("--amr", action="store_true")
     ap.add_argument("--imbalance", action="store_true")
     ap.add_argument("--imb-iters", type=int, default=1000)
+    ap.add_argument("--jacobi2d", action="store_true")
+    ap.add_argument("--launch", action="store_true")
     ap.add_argument("--serving", action="store_true")
     ap.add_argument("--serving-count", type=int, default=64)
     ap.add_argument("--all", action="store_true")
@@ -324,6 +403,10 @@ def main():
         out["amr_octree_768"] = amr_leg()
     if args.imbalance or args.all:
         out["imbalance_1024"] = imbalance_leg(args.imb_iters)
+    if args.jacobi2d or args.all:
+        out["jacobi2d_32768"] = jacobi2d_leg()
+    if args.launch or args.all:
+        out["launch"] = launch_leg()
     if args.serving or args.all:
         out["serving"] = serving_leg(count=args.serving_count)
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.n, args.dtype)

@@ -205,6 +205,53 @@ od_status od_stream_copy(void* hip_stream, void* dst, const void* src, size_t by
 od_status od_time_iterate(struct od_grid* g, int64_t n, double* seconds);
 
 /* -------------------------------------------------------------------------
+ * Launch-cost microbenchmarks (Section III-A, Managing Overdecomposition:
+ * the kernel-overlap experiment with streams gated on one flag, and the
+ * kernel-launch-rate experiment over host threads x chares per thread).
+ * Both run on the current HIP device and create and destroy their own
+ * non-blocking streams (default priority).
+ */
+typedef struct {
+    int64_t total_threads;
+    int32_t nkernels;
+    int32_t nstreams;     /* streams actually used: min(nstreams, nkernels) */
+    int32_t work;
+    int32_t pad;
+    double makespan_us;   /* device: earliest workgroup start -> latest workgroup end */
+    double host_us;       /* host: release enqueued -> every stream's event complete  */
+    double enqueue_us;    /* host: time to enqueue the gates, kernels and events      */
+} od_overlap_result;
+
+/* Workspace for od_launch_overlap: 256 bytes of timestamps followed by
+ * total_threads uint32 outputs.  0 if total_threads <= 0. */
+size_t od_launch_overlap_bytes(int64_t total_threads);
+
+/* Split total_threads threads (each `work` dependent 32-bit multiply-adds
+ * x <- x*1664525 + 1013904223 from x = thread_index ^ 0x9E3779B9, stored to
+ * outputs[thread_index]) into nkernels near-equal kernels of 256-thread
+ * workgroups, round-robin over nstreams streams.  Each stream first waits on
+ * a device signal word (hipStreamWaitValue32, allocated once per device and
+ * kept until the process ends); after every kernel is enqueued, the word is
+ * written from a separate stream and all kernels start together.  Blocks
+ * until every kernel has completed (bounded: OD_ETIMEDOUT after 60 s).
+ * dev_ws: caller-owned device memory, 256-byte aligned, at least
+ * od_launch_overlap_bytes(total_threads).  Limits: total_threads in
+ * [1, 2^31], nkernels in [1, min(65536, total_threads)], nstreams in
+ * [1, 256], work in [0, 2^24]; otherwise OD_EINVAL.  OD_EINVAL as well if
+ * the device cannot run stream wait-value operations. */
+od_status od_launch_overlap(void* dev_ws, size_t ws_bytes, int64_t total_threads, int32_t nkernels,
+                            int32_t nstreams, int32_t work, od_overlap_result* out);
+
+/* host_threads threads each own chares_per_thread streams and, for
+ * `seconds` of wall time, launch an empty kernel (one 64-thread workgroup
+ * per compute unit) on each of their streams whose previous kernel has
+ * completed (event query).  *launches = kernels launched, *kernels_per_s =
+ * launches / wall time including the final drain.  host_threads and
+ * chares_per_thread in [1, 16], seconds in (0, 60]. */
+od_status od_launch_rate(int32_t host_threads, int32_t chares_per_thread, double seconds, int64_t* launches,
+                         double* kernels_per_s);
+
+/* -------------------------------------------------------------------------
  * Autotuning (tile shape search).  Every candidate computes the same
  * arithmetic; only the tile shape and launch shape differ.  Times each
  * candidate with `iters` fused iterations on the grid itself (its field is

@@ -21,7 +21,7 @@ from . import _binding as B
 from ._binding import ODError, check, lib
 
 __all__ = ["Grid", "Grid2D", "ODError", "DEFAULT_BC", "stream_copy_seconds", "plan_info", "tile_infos", "lib",
-           "Server"]
+           "Server", "launch_overlap", "launch_rate"]
 
 DEFAULT_BC = (1.0, 0.0, 0.0, 0.0, 0.0, 0.0)
 _DTYPES = {"f64": (B.OD_F64, np.float64), "f32": (B.OD_F32, np.float32),
@@ -278,6 +278,44 @@ def stream_copy_seconds(nbytes: int, iters: int = 10, device: str = "cuda:0") ->
                                ctypes.c_void_p(src.data_ptr()), nbytes, int(iters), ctypes.byref(s)),
           "od_stream_copy")
     return float(s.value)
+
+
+def launch_overlap(total_threads: int, nkernels: int, nstreams: int | None = None, work: int = 2000,
+                   device: str = "cuda:0", return_outputs: bool = False):
+    """Kernel-overlap microbenchmark: total_threads threads of `work`
+    multiply-adds split into nkernels kernels on min(nstreams, nkernels)
+    streams, all released at once.  Returns the od_overlap_result fields as
+    a dict (plus the uint32 outputs if asked)."""
+    import torch
+
+    from ._binding import od_overlap_result
+
+    nstreams = min(int(nkernels), 64) if nstreams is None else int(nstreams)
+    nbytes = int(lib().od_launch_overlap_bytes(int(total_threads)))
+    if nbytes == 0:
+        raise ValueError("total_threads must be positive")
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    res = od_overlap_result()
+    with torch.cuda.device(torch.device(device)):
+        torch.cuda.synchronize()
+        check(lib().od_launch_overlap(ctypes.c_void_p(ws.data_ptr()), nbytes, int(total_threads), int(nkernels),
+                                      nstreams, int(work), ctypes.byref(res)), "od_launch_overlap")
+    out = {f: getattr(res, f) for f, _ in res._fields_ if f != "pad"}
+    if return_outputs:
+        out["outputs"] = ws[256:].view(torch.int32).cpu().numpy().view(np.uint32)
+    return out
+
+
+def launch_rate(host_threads: int, chares_per_thread: int, seconds: float = 0.5, device: str = "cuda:0"):
+    """Kernel-launch-rate microbenchmark: (launches, kernels per second)."""
+    import torch
+
+    n = ctypes.c_int64()
+    r = ctypes.c_double()
+    with torch.cuda.device(torch.device(device)):
+        check(lib().od_launch_rate(int(host_threads), int(chares_per_thread), float(seconds), ctypes.byref(n),
+                                   ctypes.byref(r)), "od_launch_rate")
+    return int(n.value), float(r.value)
 
 
 def Server(*args, **kwargs):  # replaced by the serving module once built

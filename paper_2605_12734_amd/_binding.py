@@ -62,6 +62,11 @@ class od_info(ctypes.Structure):
                 ("t_admit", c_dbl), ("t_done", c_dbl)]
 
 
+class od_overlap_result(ctypes.Structure):
+    _fields_ = [("total_threads", c_i64), ("nkernels", c_i32), ("nstreams", c_i32), ("work", c_i32),
+                ("pad", c_i32), ("makespan_us", c_dbl), ("host_us", c_dbl), ("enqueue_us", c_dbl)]
+
+
 # name -> (restype, argtypes); the full exported surface of include/od.h
 SIGNATURES = {
     "od_config_default": (None, [ctypes.POINTER(od_config)]),
@@ -80,6 +85,9 @@ SIGNATURES = {
     "od_destroy": (ctypes.c_int, [c_vp]),
     "od_stream_copy": (ctypes.c_int, [c_vp, c_vp, c_vp, c_sz, c_i32, ctypes.POINTER(c_dbl)]),
     "od_time_iterate": (ctypes.c_int, [c_vp, c_i64, ctypes.POINTER(c_dbl)]),
+    "od_launch_overlap_bytes": (c_sz, [c_i64]),
+    "od_launch_overlap": (ctypes.c_int, [c_vp, c_sz, c_i64, c_i32, c_i32, c_i32, ctypes.POINTER(od_overlap_result)]),
+    "od_launch_rate": (ctypes.c_int, [c_i32, c_i32, c_dbl, ctypes.POINTER(c_i64), ctypes.POINTER(c_dbl)]),
     "od_autotune": (ctypes.c_int, [c_vp, c_i32, ctypes.POINTER(c_i32)]),
     "od_server_create": (ctypes.c_int, [c_vp, c_vp, c_sz, c_i32, ctypes.POINTER(c_vp)]),
     "od_request_bytes": (ctypes.c_int, [ctypes.POINTER(od_request), ctypes.POINTER(c_sz)]),

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libod.so")
-SOURCES = ["kernels.hip", "plan.cpp", "od_api.cpp", "od_capi.cpp", "tune.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "plan.cpp", "od_api.cpp", "od_capi.cpp", "tune.cpp", "server.cpp", "launch_bench.hip"]
 
 # Bit-exactness: no contraction into FMA, correctly rounded fp32 division,
 # subnormals kept.  Packed-fp32 instructions are disabled for the device.

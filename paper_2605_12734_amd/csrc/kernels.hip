@@ -280,18 +280,33 @@ k_sweep(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDe
 }
 
 // ---------------------------------------------------------------------------
-// device-wide barrier for cooperative launches: every thread fences at agent
-// scope (its stores become visible across XCDs), one thread per workgroup
-// arrives on a counter and waits for the generation to change.  The wait is
-// bounded; on timeout the error flag is raised and every workgroup leaves.
+// Synchronisation between workgroups.  On gfx950 an agent-scope release
+// writes back the XCD's L2 and an agent-scope acquire invalidates caches, so
+// both are issued once per workgroup, never per wave and never inside a
+// polling loop: polls are relaxed agent-scope loads (coherent across XCDs,
+// no invalidation), and one acquire fence follows the poll that succeeds.
+// Before one thread publishes for the workgroup, every wave waits for its
+// own stores to complete (s_waitcnt 0) and the workgroup meets at a barrier.
 
+__device__ __forceinline__ int32_t ld_rlx(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void wg_stores_done() {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+}
+
+// device-wide barrier for cooperative launches: one thread per workgroup
+// arrives on a counter (acq_rel: publishes the workgroup's stores) and polls
+// the generation.  The wait is bounded; on timeout the error flag is raised
+// and every workgroup leaves.
 __device__ __forceinline__ bool grid_barrier(unsigned int* bar, unsigned int* err, int64_t wait_ticks) {
     __shared__ int ok;
-    __threadfence();
-    __syncthreads();
+    wg_stores_done();
     if (threadIdx.x == 0) {
         const unsigned int nb = gridDim.x;
-        const unsigned int gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned int gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned int arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         int good = 1;
         if (arrived == nb - 1) {
@@ -299,8 +314,8 @@ __device__ __forceinline__ bool grid_barrier(unsigned int* bar, unsigned int* er
             __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             const int64_t t0 = wall_clock64();
-            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                __builtin_amdgcn_s_sleep(2);
+            while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(8);
                 if (wall_clock64() - t0 > wait_ticks ||
                     __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
                     __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -308,11 +323,11 @@ __device__ __forceinline__ bool grid_barrier(unsigned int* bar, unsigned int* er
                     break;
                 }
             }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         ok = good;
     }
     __syncthreads();
-    __threadfence();
     return ok != 0;
 }
 
@@ -362,12 +377,10 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
 // waits there until the last one to finish evaluates the solve's residual
 // and either stops the solve or opens the gate.
 
-__device__ __forceinline__ int32_t ld_acq(const int32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // One scheduler loop; `sweep(gid, step)` runs tile gid's step (reading
 // parity step & 1) with the whole workgroup and returns its residual.
+// Wave 0 looks for a ready tile, 64 owned tiles at a time (one per lane,
+// starting after the last tile run), and takes the first ready one.
 template <int NT, class SweepFn>
 __device__ __forceinline__ void msg_loop(const MsgArgs& a, SweepFn sweep, double* red) {
     __shared__ int32_t s_pick, s_step, s_stop;
@@ -377,41 +390,60 @@ __device__ __forceinline__ void msg_loop(const MsgArgs& a, SweepFn sweep, double
     int32_t cursor = 0;
     int64_t idle_since = -1;
     for (;;) {
-        if (threadIdx.x == 0) {
-            int32_t pick = -1, step = 0, stop = 1;
-            for (int32_t k = 0; k < nown && pick < 0; ++k) {
-                const int32_t j = (cursor + k) % nown;
-                const int32_t li = w + j * G;
-                const int32_t ti = a.tile_list ? a.tile_list[li] : li;
-                const int32_t sv = a.tile_solve ? a.tile_solve[ti] : 0;
-                const int32_t d = ld_acq(&a.done[ti]);
-                int32_t tgt = ld_acq(&a.target[sv]);
-                if (a.final_step) {
-                    const int32_t fs = ld_acq(&a.final_step[sv]);
-                    if (fs > 0) tgt = fs;
+        if (threadIdx.x < 64) {
+            const int lane = threadIdx.x;
+            int32_t pick = -1, step = 0;
+            bool live_any = false;
+            for (int32_t base = 0; base < nown && pick < 0; base += 64) {
+                const int32_t k = base + lane;
+                bool live = false, ready = false;
+                int32_t ti = 0, d = 0, j = 0;
+                if (k < nown) {
+                    j = cursor + k < nown ? cursor + k : cursor + k - nown;
+                    const int32_t li = w + j * G;
+                    ti = a.tile_list ? a.tile_list[li] : li;
+                    const int32_t sv = a.tile_solve ? a.tile_solve[ti] : 0;
+                    d = ld_rlx(&a.done[ti]);
+                    int32_t tgt = ld_rlx(&a.target[sv]);
+                    if (a.final_step) {
+                        const int32_t fs = ld_rlx(&a.final_step[sv]);
+                        if (fs > 0) tgt = fs;
+                    }
+                    live = d < tgt;
+                    ready = live;
+                    if (ready && a.gate) {
+                        const int32_t ce = a.check_every[sv];
+                        if (ce > 0 && d > 0 && d % ce == 0) ready = ld_rlx(&a.gate[sv]) >= d;
+                    }
+                    if (ready) {
+                        const int32_t q1 = a.dep_ptr[ti + 1];
+                        for (int32_t q = a.dep_ptr[ti]; q < q1; ++q) ready &= ld_rlx(&a.done[a.dep_idx[q]]) >= d;
+                    }
                 }
-                if (d >= tgt) continue;
-                stop = 0;
-                if (a.gate && a.check_every[sv] > 0 && d > 0 && d % a.check_every[sv] == 0 &&
-                    ld_acq(&a.gate[sv]) < d)
-                    continue;
-                bool ready = true;
-                for (int32_t q = a.dep_ptr[ti]; q < a.dep_ptr[ti + 1] && ready; ++q)
-                    ready = ld_acq(&a.done[a.dep_idx[q]]) >= d;
-                if (ready) {
-                    pick = ti;
-                    step = d;
-                    cursor = (j + 1) % nown;
+                live_any = live_any || __ballot(live) != 0ull;
+                const unsigned long long m = __ballot(ready);
+                if (m != 0ull) {
+                    const int src = __ffsll((unsigned long long)m) - 1;
+                    pick = __shfl(ti, src, 64);
+                    step = __shfl(d, src, 64);
+                    const int32_t pj = __shfl(j, src, 64);
+                    cursor = pj + 1 < nown ? pj + 1 : 0;
                 }
             }
-            // the host asks the launch to end: start no new task (every tile's
-            // state stays in HBM, a later launch resumes from it)
-            if (a.yield_flag && __hip_atomic_load(a.yield_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0)
-                stop = 1, pick = -1;
-            if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) stop = 1, pick = -1;
-            s_pick = pick;
-            s_step = step;
-            s_stop = stop;
+            if (lane == 0) {
+                int32_t stop = live_any ? 0 : 1;
+                // the host asks the launch to end: start no new task (every
+                // tile's state stays in HBM, a later launch resumes from it)
+                if (a.yield_flag && __hip_atomic_load(a.yield_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0)
+                    stop = 1, pick = -1;
+                if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) stop = 1, pick = -1;
+                // acquire side: the step-`step` data of the tiles whose
+                // counters were just read
+                if (pick >= 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                s_pick = pick;
+                s_step = step;
+                s_stop = stop;
+            }
         }
         __syncthreads();
         const int32_t pick = s_pick, step = s_step;
@@ -429,47 +461,42 @@ __device__ __forceinline__ void msg_loop(const MsgArgs& a, SweepFn sweep, double
             continue;
         }
         idle_since = -1;
-        __threadfence();   // acquire side: see the neighbours' step-`step` data
         const int32_t sv = a.tile_solve ? a.tile_solve[pick] : 0;
         const double r = sweep(pick, step);
         const int32_t ns = step + 1;
+        const int32_t tgt = ld_rlx(&a.target[sv]);
+        const int32_t ce = a.check_every ? a.check_every[sv] : 0;
         // A plain grid records only its target step's residual (slot ns & 1,
         // cleared before the launch).  A served solve records it at decision
         // steps, where every tile of the solve waits for the decision, so one
         // slot per solve suffices.
         if (a.final_only) {
-            if (ns == ld_acq(&a.target[sv])) wg_residual<double, NT>(r, &a.res[2 * sv + (ns & 1)], red);
+            if (ns == tgt) wg_residual<double, NT>(r, &a.res[2 * sv + (ns & 1)], red);
         } else {
-            const int32_t ce = a.check_every[sv];
-            if ((ce > 0 && ns % ce == 0) || ns == ld_acq(&a.target[sv])) wg_residual<double, NT>(r, &a.res[sv], red);
+            if ((ce > 0 && ns % ce == 0) || ns == tgt) wg_residual<double, NT>(r, &a.res[sv], red);
         }
-        __threadfence();   // release side: this tile's step-ns data before its counter
-        __syncthreads();
+        wg_stores_done();
         if (threadIdx.x == 0) {
+            // release side: this tile's step-ns data before its counter
             __hip_atomic_store(&a.done[pick], ns, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            if (a.solve_count) {
-                const int32_t ce = a.check_every[sv];
-                const int32_t tgt = ld_acq(&a.target[sv]);
-                const bool decision = (ce > 0 && ns % ce == 0) || ns == tgt;
-                if (decision) {
-                    int32_t* cnt = &a.solve_count[sv];
-                    const int32_t prev = __hip_atomic_fetch_add(cnt, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-                    if (prev == a.solve_ntiles[sv] - 1) {
-                        // last tile of the solve to finish decision step ns
-                        __hip_atomic_store(cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        const unsigned long long rb =
-                            __hip_atomic_exchange(&a.res[sv], 0ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-                        const double rv = __longlong_as_double((long long)rb);
-                        const bool fin = ns >= tgt || (ce > 0 && ns % ce == 0 && rv < a.tol[sv]);
-                        if (fin) {
-                            __hip_atomic_store(&a.final_step[sv], ns, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                            __threadfence_system();
-                            if (a.host_res) a.host_res[sv] = rb;
-                            if (a.host_done) a.host_done[sv] = ns;
-                            __threadfence_system();
-                        } else {
-                            __hip_atomic_store(&a.gate[sv], ns, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                        }
+            if (a.solve_count && ((ce > 0 && ns % ce == 0) || ns == tgt)) {
+                int32_t* cnt = &a.solve_count[sv];
+                const int32_t prev = __hip_atomic_fetch_add(cnt, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                if (prev == a.solve_ntiles[sv] - 1) {
+                    // last tile of the solve to finish decision step ns
+                    __hip_atomic_store(cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const unsigned long long rb =
+                        __hip_atomic_exchange(&a.res[sv], 0ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                    const double rv = __longlong_as_double((long long)rb);
+                    const bool fin = ns >= tgt || (ce > 0 && ns % ce == 0 && rv < a.tol[sv]);
+                    if (fin) {
+                        __hip_atomic_store(&a.final_step[sv], ns, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                        __threadfence_system();
+                        if (a.host_res) a.host_res[sv] = rb;
+                        if (a.host_done) a.host_done[sv] = ns;
+                        __threadfence_system();
+                    } else {
+                        __hip_atomic_store(&a.gate[sv], ns, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                     }
                 }
             }

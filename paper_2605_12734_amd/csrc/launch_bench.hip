@@ -1,0 +1,286 @@
+// Launch-cost microbenchmarks for overdecomposed execution (Section III-A,
+// "Managing Overdecomposition"): how much of a fine-grained kernel's cost is
+// device-side launch processing, and how fast one process can keep firing
+// kernels from several host threads and streams.
+//
+//  - overlap: a fixed amount of work (total_threads threads, `work` dependent
+//    integer multiply-adds each) split into nkernels kernels on a pool of
+//    non-blocking streams.  Every stream first waits on one signal word
+//    (hipStreamWaitValue32); once everything is enqueued, a separate stream
+//    writes the word (hipStreamWriteValue32), releasing all kernels at once.
+//    The device makespan (earliest workgroup start to latest workgroup end,
+//    constant-rate wall clock) therefore excludes host submission cost.
+//  - rate: host threads each own `chares` streams; a thread fires an empty
+//    full-device kernel on a stream whenever that stream's previous kernel
+//    has completed (event query), for a fixed wall time.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "od_runtime.hpp"
+
+namespace {
+
+constexpr int kWorkBlock = 256;
+constexpr size_t kStampBytes = 256;   // stamp area ahead of the outputs
+
+__global__ void __launch_bounds__(kWorkBlock)
+k_work(uint32_t* __restrict__ out, unsigned long long* __restrict__ stamps, int64_t first, int64_t count,
+       int32_t work) {
+    if (threadIdx.x == 0) atomicMin(&stamps[0], (unsigned long long)wall_clock64());
+    const int64_t i = (int64_t)blockIdx.x * kWorkBlock + threadIdx.x;
+    if (i < count) {
+        uint32_t x = (uint32_t)(first + i) ^ 0x9E3779B9u;
+        for (int32_t k = 0; k < work; ++k) x = x * 1664525u + 1013904223u;
+        out[first + i] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(&stamps[1], (unsigned long long)wall_clock64());
+}
+
+__global__ void k_stamp_init(unsigned long long* stamps) {
+    if (threadIdx.x == 0) {
+        stamps[0] = ~0ull;
+        stamps[1] = 0ull;
+    }
+}
+
+__global__ void k_empty() {}
+
+double now_us() {
+    return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// One signal word per device, kept until the process ends.
+uint32_t* signal_word(int dev, std::string& err) {
+    static std::vector<uint32_t*> words(64, nullptr);
+    if (dev < 0 || dev >= (int)words.size()) {
+        err = "device index out of range";
+        return nullptr;
+    }
+    if (!words[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipExtMallocWithFlags(&p, 8, hipMallocSignalMemory);
+        if (e != hipSuccess) {
+            err = std::string("hipExtMallocWithFlags(signal): ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        words[dev] = static_cast<uint32_t*>(p);
+    }
+    return words[dev];
+}
+
+struct Streams {
+    std::vector<hipStream_t> s;
+    std::vector<hipEvent_t> e;
+    ~Streams() {
+        for (auto ev : e) hipEventDestroy(ev);
+        for (auto st : s) hipStreamDestroy(st);
+    }
+    hipError_t create(int n) {
+        for (int i = 0; i < n; ++i) {
+            hipStream_t st = nullptr;
+            hipError_t r = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+            if (r != hipSuccess) return r;
+            s.push_back(st);
+            hipEvent_t ev = nullptr;
+            r = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (r != hipSuccess) return r;
+            e.push_back(ev);
+        }
+        return hipSuccess;
+    }
+};
+
+// Waits for every event with a wall-clock bound.
+bool wait_events(const std::vector<hipEvent_t>& evs, double seconds) {
+    const double t_end = now_us() + seconds * 1e6;
+    for (auto ev : evs) {
+        for (;;) {
+            const hipError_t q = hipEventQuery(ev);
+            if (q == hipSuccess) break;
+            if (q != hipErrorNotReady) return false;
+            if (now_us() > t_end) return false;
+            std::this_thread::yield();
+        }
+    }
+    return true;
+}
+
+}  // namespace
+
+#define OD_HIP_OR_FAIL(call)                                                        \
+    do {                                                                            \
+        hipError_t e_ = (call);                                                     \
+        if (e_ != hipSuccess) return od::fail(OD_EHIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+extern "C" {
+
+size_t od_launch_overlap_bytes(int64_t total_threads) {
+    if (total_threads <= 0) return 0;
+    return kStampBytes + (size_t)total_threads * sizeof(uint32_t);
+}
+
+od_status od_launch_overlap(void* dev_ws, size_t ws_bytes, int64_t total_threads, int32_t nkernels,
+                            int32_t nstreams, int32_t work, od_overlap_result* out) {
+    try {
+        if (!out) return od::fail(OD_EINVAL, "out is NULL");
+        std::memset(out, 0, sizeof(*out));
+        if (!dev_ws) return od::fail(OD_EINVAL, "dev_ws is NULL");
+        if (total_threads <= 0 || total_threads > (int64_t(1) << 31))
+            return od::fail(OD_EINVAL, "total_threads must be in [1, 2^31]");
+        if (nkernels <= 0 || nkernels > 65536 || nkernels > total_threads)
+            return od::fail(OD_EINVAL, "nkernels must be in [1, min(65536, total_threads)]");
+        if (nstreams <= 0 || nstreams > 256) return od::fail(OD_EINVAL, "nstreams must be in [1, 256]");
+        if (work < 0 || work > (1 << 24)) return od::fail(OD_EINVAL, "work must be in [0, 2^24]");
+        if (ws_bytes < od_launch_overlap_bytes(total_threads))
+            return od::fail(OD_EINVAL, "workspace smaller than od_launch_overlap_bytes(total_threads)");
+        if ((reinterpret_cast<uintptr_t>(dev_ws) & 255) != 0) return od::fail(OD_EINVAL, "dev_ws not 256-byte aligned");
+        int dev = 0, can_wait = 0, khz = 0;
+        OD_HIP_OR_FAIL(hipGetDevice(&dev));
+        OD_HIP_OR_FAIL(hipDeviceGetAttribute(&can_wait, hipDeviceAttributeCanUseStreamWaitValue, dev));
+        if (!can_wait) return od::fail(OD_EINVAL, "device does not support stream wait-value operations");
+        OD_HIP_OR_FAIL(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        if (khz <= 0) return od::fail(OD_EHIP, "device reports no wall-clock rate");
+        std::string err;
+        uint32_t* sig = signal_word(dev, err);
+        if (!sig) return od::fail(OD_EHIP, err);
+
+        const int ns = std::min(nstreams, nkernels);
+        Streams S, R;
+        OD_HIP_OR_FAIL(S.create(ns));
+        OD_HIP_OR_FAIL(R.create(1));
+        auto* stamps = static_cast<unsigned long long*>(dev_ws);
+        auto* outv = reinterpret_cast<uint32_t*>(static_cast<char*>(dev_ws) + kStampBytes);
+        // arm: signal = 0 and stamps reset, completed before any wait is enqueued
+        OD_HIP_OR_FAIL(hipStreamWriteValue32(R.s[0], sig, 0u, 0));
+        hipLaunchKernelGGL(k_stamp_init, dim3(1), dim3(64), 0, R.s[0], stamps);
+        OD_HIP_OR_FAIL(hipGetLastError());
+        OD_HIP_OR_FAIL(hipStreamSynchronize(R.s[0]));
+
+        // enqueue: a gate per stream, then the kernels round-robin over the streams
+        const double t0 = now_us();
+        hipError_t enq = hipSuccess;
+        for (int s = 0; s < ns && enq == hipSuccess; ++s)
+            enq = hipStreamWaitValue32(S.s[s], sig, 1u, hipStreamWaitValueGte, 0xFFFFFFFFu);
+        const int64_t per = total_threads / nkernels, rem = total_threads % nkernels;
+        int64_t first = 0;
+        for (int32_t k = 0; k < nkernels && enq == hipSuccess; ++k) {
+            const int64_t cnt = per + (k < rem ? 1 : 0);
+            const unsigned int blocks = (unsigned int)((cnt + kWorkBlock - 1) / kWorkBlock);
+            hipLaunchKernelGGL(k_work, dim3(blocks), dim3(kWorkBlock), 0, S.s[k % ns], outv, stamps, first, cnt,
+                               work);
+            enq = hipGetLastError();
+            first += cnt;
+        }
+        for (int s = 0; s < ns && enq == hipSuccess; ++s) enq = hipEventRecord(S.e[s], S.s[s]);
+        const double t1 = now_us();
+        // release (always, also after a failed enqueue, so no stream stays gated)
+        const hipError_t rel = hipStreamWriteValue32(R.s[0], sig, 1u, 0);
+        const double t2 = now_us();
+        if (rel != hipSuccess) return od::fail(OD_EHIP, std::string("hipStreamWriteValue32: ") + hipGetErrorString(rel));
+        const bool done = wait_events(S.e, 60.0);
+        const double t3 = now_us();
+        if (enq != hipSuccess) {
+            hipDeviceSynchronize();
+            return od::fail(OD_EHIP, std::string("enqueue: ") + hipGetErrorString(enq));
+        }
+        if (!done) return od::fail(OD_ETIMEDOUT, "released kernels did not complete within 60 s");
+        unsigned long long st[2] = {0, 0};
+        OD_HIP_OR_FAIL(hipMemcpy(st, stamps, sizeof(st), hipMemcpyDeviceToHost));
+        out->total_threads = total_threads;
+        out->nkernels = nkernels;
+        out->nstreams = ns;
+        out->work = work;
+        out->enqueue_us = t1 - t0;
+        out->host_us = t3 - t2;
+        out->makespan_us = st[1] >= st[0] ? (double)(st[1] - st[0]) * 1e3 / (double)khz : 0.0;
+        return OD_OK;
+    } catch (const std::exception& ex) {
+        return od::fail(OD_EINVAL, std::string("internal error: ") + ex.what());
+    } catch (...) {
+        return od::fail(OD_EINVAL, "internal error");
+    }
+}
+
+od_status od_launch_rate(int32_t host_threads, int32_t chares_per_thread, double seconds, int64_t* launches,
+                         double* kernels_per_s) {
+    try {
+        if (!launches || !kernels_per_s) return od::fail(OD_EINVAL, "output pointer is NULL");
+        *launches = 0;
+        *kernels_per_s = 0.0;
+        if (host_threads <= 0 || host_threads > 16) return od::fail(OD_EINVAL, "host_threads must be in [1, 16]");
+        if (chares_per_thread <= 0 || chares_per_thread > 16)
+            return od::fail(OD_EINVAL, "chares_per_thread must be in [1, 16]");
+        if (!(seconds > 0.0) || seconds > 60.0) return od::fail(OD_EINVAL, "seconds must be in (0, 60]");
+        int dev = 0, ncu = 0;
+        OD_HIP_OR_FAIL(hipGetDevice(&dev));
+        OD_HIP_OR_FAIL(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        const int nst = host_threads * chares_per_thread;
+        Streams S;
+        OD_HIP_OR_FAIL(S.create(nst));
+        std::vector<int64_t> counts(host_threads, 0);
+        std::vector<hipError_t> errs(host_threads, hipSuccess);
+        std::atomic<bool> go{false};
+        std::vector<std::thread> th;
+        const double t_len = seconds * 1e6;
+        double t_start = 0.0;
+        for (int t = 0; t < host_threads; ++t) {
+            th.emplace_back([&, t] {
+                if (hipSetDevice(dev) != hipSuccess) {
+                    errs[t] = hipErrorInvalidDevice;
+                    return;
+                }
+                while (!go.load(std::memory_order_acquire)) std::this_thread::yield();
+                const double t_end = now_us() + t_len;
+                int64_t n = 0;
+                while (now_us() < t_end) {
+                    for (int c = 0; c < chares_per_thread; ++c) {
+                        const int i = t * chares_per_thread + c;
+                        const hipError_t q = hipEventQuery(S.e[i]);
+                        if (q == hipErrorNotReady) continue;
+                        if (q != hipSuccess) {
+                            errs[t] = q;
+                            return;
+                        }
+                        hipLaunchKernelGGL(k_empty, dim3(ncu), dim3(64), 0, S.s[i]);
+                        hipError_t r = hipGetLastError();
+                        if (r == hipSuccess) r = hipEventRecord(S.e[i], S.s[i]);
+                        if (r != hipSuccess) {
+                            errs[t] = r;
+                            return;
+                        }
+                        ++n;
+                    }
+                }
+                counts[t] = n;
+            });
+        }
+        t_start = now_us();
+        go.store(true, std::memory_order_release);
+        for (auto& x : th) x.join();
+        const bool done = wait_events(S.e, 60.0);
+        const double t_stop = now_us();
+        for (int t = 0; t < host_threads; ++t)
+            if (errs[t] != hipSuccess) return od::fail(OD_EHIP, std::string("launch thread: ") + hipGetErrorString(errs[t]));
+        if (!done) return od::fail(OD_ETIMEDOUT, "kernels did not complete within 60 s");
+        int64_t total = 0;
+        for (auto c : counts) total += c;
+        *launches = total;
+        *kernels_per_s = (double)total / ((t_stop - t_start) * 1e-6);
+        return OD_OK;
+    } catch (const std::exception& ex) {
+        return od::fail(OD_EINVAL, std::string("internal error: ") + ex.what());
+    } catch (...) {
+        return od::fail(OD_EINVAL, "internal error");
+    }
+}
+
+}  // extern "C"

@@ -82,3 +82,17 @@ def test_device_calls_refuse_host_only_handle():
         assert B.lib().od_residual(p.h, ctypes.byref(r)) == B.OD_EINVAL
     finally:
         p.close()
+
+
+def test_launch_overlap_host_checks():
+    # argument checks run before any device call
+    from paper_2605_12734_amd import _binding as B
+    L = B.lib()
+    assert L.od_launch_overlap_bytes(0) == 0
+    assert L.od_launch_overlap_bytes(10) == 256 + 40
+    res = B.od_overlap_result()
+    assert L.od_launch_overlap(None, 0, 10, 1, 1, 1, ctypes.byref(res)) == -22
+    assert L.od_launch_overlap(ctypes.c_void_p(256), 1 << 20, 10, 11, 1, 1, ctypes.byref(res)) == -22
+    n, r = ctypes.c_int64(), ctypes.c_double()
+    assert L.od_launch_rate(0, 1, 0.1, ctypes.byref(n), ctypes.byref(r)) == -22
+    assert L.od_launch_rate(1, 1, 0.0, ctypes.byref(n), ctypes.byref(r)) == -22
