@@ -24,6 +24,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "jacobi_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "ml_oracle.c")]
 _LIB_PATH = os.path.join(_HERE, "libjacobi_oracle.so")
 _lib = None
 
@@ -35,7 +36,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
-               "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"]
+               "-fopenmp", "-shared", "-fPIC", "-o", tmp, *_SRCS, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -45,7 +46,7 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < max(os.path.getmtime(f) for f in _SRCS):
         build()
     lib = ctypes.CDLL(_LIB_PATH)
     u64, i64, dp = ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p
@@ -227,3 +228,74 @@ def point_values2d(n2, points, iters: int, dtype=np.float64, seed: int = 12734, 
         V, _, _ = jacobi2d(U, iters)
         out.append(V[j - lo[1] + 1, i - lo[0] + 1])
     return np.array(out, dtype=dtype)
+
+
+# ---- multi-resolution blocks (ml_oracle.c) ----------------------------------
+
+def _ml_lib():
+    lib = _load()
+    if not getattr(lib, "_ml_ready", False):
+        i64, u64, dp = ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p
+        lib.oracle_ml_layout.argtypes = [i64, dp, dp, dp]
+        lib.oracle_ml_layout.restype = i64
+        for suf in ("f64", "f32"):
+            f = getattr(lib, "oracle_ml_init_" + suf)
+            f.argtypes = [dp, i64, dp, dp, dp, dp, i64, i64, i64, u64]
+            f.restype = None
+            f = getattr(lib, "oracle_ml_jacobi_" + suf)
+            f.argtypes = [dp, dp, i64, dp, dp, dp, dp, i64, i64, i64, ctypes.POINTER(ctypes.c_double), i64,
+                          ctypes.POINTER(ctypes.c_double)]
+            f.restype = i64
+        lib._ml_ready = True
+    return lib
+
+
+class MLGrid:
+    """Multi-resolution blocks: `blocks` = [(origin, extent)] in grid units,
+    `cell` = cell edge (units, power of two) per block.  Holds every block's
+    padded array in one flat buffer (see ml_oracle.c)."""
+
+    def __init__(self, n, blocks, cell, dtype=np.float64, seed: int = 12734, bc=DEFAULT_BC):
+        self.n = _dims(n)
+        self.dtype = np.dtype(dtype)
+        self.org = np.ascontiguousarray([list(o) for o, _ in blocks], dtype=np.int64)
+        self.ext = np.ascontiguousarray([list(e) for _, e in blocks], dtype=np.int64)
+        self.h = np.ascontiguousarray(list(cell), dtype=np.int64)
+        if len(self.h) != len(blocks):
+            raise ValueError("one cell size per block")
+        if np.any(self.ext % self.h[:, None]) or np.any(self.org % self.h[:, None]):
+            raise ValueError("block origins and extents must be multiples of their cell size")
+        self.m = self.ext // self.h[:, None]
+        self.offs = np.zeros(len(blocks), dtype=np.int64)
+        lib = _ml_lib()
+        total = lib.oracle_ml_layout(len(blocks), self.ext.ctypes.data, self.h.ctypes.data, self.offs.ctypes.data)
+        self.U = np.zeros(int(total), dtype=self.dtype)
+        self.bc = (ctypes.c_double * 6)(*[float(v) for v in bc])
+        getattr(lib, "oracle_ml_init_" + _suffix(self.dtype))(
+            self.U.ctypes.data, len(blocks), self.org.ctypes.data, self.ext.ctypes.data, self.h.ctypes.data,
+            self.offs.ctypes.data, *self.n, int(seed) & (2**64 - 1))
+        self.iters = 0
+        self.residual = 0.0
+
+    def block(self, b: int) -> np.ndarray:
+        """View of block b's padded array, shape (mz+2, my+2, mx+2)."""
+        mx, my, mz = (int(v) for v in self.m[b])
+        o = int(self.offs[b])
+        return self.U[o:o + (mx + 2) * (my + 2) * (mz + 2)].reshape(mz + 2, my + 2, mx + 2)
+
+    def interior(self, b: int) -> np.ndarray:
+        return self.block(b)[1:-1, 1:-1, 1:-1].copy()
+
+    def jacobi(self, iters: int) -> float:
+        V = np.zeros_like(self.U)
+        r = ctypes.c_double()
+        lib = _ml_lib()
+        done = getattr(lib, "oracle_ml_jacobi_" + _suffix(self.dtype))(
+            self.U.ctypes.data, V.ctypes.data, len(self.h), self.org.ctypes.data, self.ext.ctypes.data,
+            self.h.ctypes.data, self.offs.ctypes.data, *self.n, self.bc, int(iters), ctypes.byref(r))
+        if done < 0:
+            raise ValueError("block layout not covered: blocks must tile the domain, and across a "
+                             "resolution change the finer block must align to the coarser cells")
+        self.iters += int(done)
+        self.residual = float(r.value) if done > 0 else self.residual
+        return self.residual

@@ -135,3 +135,84 @@ def sweep2d(U):
                 r = d
             V[j][i] = v
     return V, r
+
+
+# ---- multi-resolution blocks: injection from coarser, face mean of finer ----
+
+def ml_init(n, blocks, cell, dtype, seed):
+    """Per block: padded nested list [k][j][i] (ghosts 0), cell (i,j,k) from
+    SplitMix64 at the unit index of its lower corner."""
+    nx, ny, _ = n
+    T = np.float64 if np.dtype(dtype) == np.float64 else np.float32
+    out = []
+    for (o, e), h in zip(blocks, cell):
+        mx, my, mz = e[0] // h, e[1] // h, e[2] // h
+        A = [[[T(0) for _ in range(mx + 2)] for _ in range(my + 2)] for _ in range(mz + 2)]
+        for k in range(mz):
+            for j in range(my):
+                for i in range(mx):
+                    q = (o[0] + i * h, o[1] + j * h, o[2] + k * h)
+                    A[k + 1][j + 1][i + 1] = T(unif(splitmix64(seed, (q[2] * ny + q[1]) * nx + q[0]), T))
+        out.append(A)
+    return out
+
+
+def _ml_owner(blocks, p):
+    for b, (o, e) in enumerate(blocks):
+        if all(o[d] <= p[d] < o[d] + e[d] for d in range(3)):
+            return b
+    raise ValueError("point not covered")
+
+
+def ml_step(n, blocks, cell, A, bc):
+    """One iteration: fill every ghost layer, then the 7-point update."""
+    T = type(A[0][1][1][1])
+    for b, ((o, e), h) in enumerate(zip(blocks, cell)):
+        m = [e[d] // h for d in range(3)]
+        for f in range(6):
+            d, hi = f // 2, f % 2
+            t1, t2 = [q for q in range(3) if q != d]
+            for c2 in range(m[t2]):
+                for c1 in range(m[t1]):
+                    p = [0, 0, 0]
+                    p[t1] = o[t1] + c1 * h
+                    p[t2] = o[t2] + c2 * h
+                    p[d] = o[d] + e[d] if hi else o[d] - 1
+                    if p[d] < 0 or p[d] >= n[d]:
+                        v = T(bc[f])
+                    else:
+                        N = _ml_owner(blocks, p)
+                        (oN, _), hN = blocks[N], cell[N]
+                        base = [(p[q] - oN[q]) // hN for q in range(3)]
+                        B = A[N]
+                        if hN >= h:
+                            v = B[base[2] + 1][base[1] + 1][base[0] + 1]
+                        else:
+                            r = h // hN
+                            s = None
+                            for q2 in range(r):
+                                for q1 in range(r):
+                                    w = list(base)
+                                    w[t1] += q1
+                                    w[t2] += q2
+                                    x = B[w[2] + 1][w[1] + 1][w[0] + 1]
+                                    s = x if s is None else T(s + x)
+                            v = T(s / T(r * r))
+                    g = [0, 0, 0]
+                    g[t1], g[t2] = c1 + 1, c2 + 1
+                    g[d] = m[d] + 1 if hi else 0
+                    A[b][g[2]][g[1]][g[0]] = v
+    res = T(0)
+    out = []
+    for b, ((o, e), h) in enumerate(zip(blocks, cell)):
+        U, ret = sweep(A[b])
+        res = max(res, ret)
+        out.append(U)
+    return out, float(res)
+
+
+def ml_jacobi(n, blocks, cell, A, iters, bc):
+    r = 0.0
+    for _ in range(iters):
+        A, r = ml_step(n, blocks, cell, A, bc)
+    return A, r
