@@ -115,6 +115,24 @@ typedef struct {
      * on a grid with n[1] == 1: the 2D plane is (x, z), its second direction
      * stored as z; bc[2] and bc[3] (the y faces) are not read. */
     int32_t stencil;
+    /* Multi-resolution blocks (explicit blocks only; NULL = every block has
+     * unit cells, the uniform grid).  block_cell[b] is the cell edge of
+     * block b in grid units, a power of two in [1, 1024]; the block's
+     * origin and extent must be multiples of it and it holds extent/cell
+     * cells per dimension.  Interior cell (i,j,k) of block b starts at unit
+     * q = origin + (i,j,k)*cell and is initialised from SplitMix64 at unit
+     * index (q_z*ny + q_y)*nx + q_x.  Every iteration first fills the ghost
+     * cells of faces where the resolution changes: from a coarser
+     * neighbour, the value of the neighbour cell containing the ghost
+     * cell (injection); from a finer one (ratio r), the mean of the r x r
+     * neighbour cells of the layer touching the face, summed with the
+     * second tangential axis outer and the first inner (tangential axes in
+     * x, y, z order) and divided by r*r.  Across such a face the finer
+     * block's tangential origin and extent must be multiples of the coarser
+     * cell, else OD_EINVAL.  Supported with OD_FUSED and OD_GRAPH; the
+     * global od_read / od_write / od_read_points calls are refused, use
+     * od_read_block / od_write_block. */
+    const int32_t* block_cell;
 } od_config;
 
 struct od_grid;
@@ -156,6 +174,14 @@ od_status od_write(struct od_grid* g, const void* host_src, size_t bytes);
  * idx[i] = (k*ny + j)*nx + i into host_dst (grid type); syncs. */
 od_status od_read_points(struct od_grid* g, const int64_t* idx, int64_t count, void* host_dst);
 
+/* Block-level I/O for any grid (regular, uneven or multi-resolution):
+ * chare `b`'s interior cells, x fastest, shape (cells[2], cells[1],
+ * cells[0]) as reported by od_block_cells; od_write_block sets them in the
+ * current iterate (the iteration count and residual are kept).  Both sync. */
+od_status od_block_cells(struct od_grid* g, int32_t b, int32_t cells[3]);
+od_status od_read_block(struct od_grid* g, int32_t b, void* host_dst, size_t bytes);
+od_status od_write_block(struct od_grid* g, int32_t b, const void* host_src, size_t bytes);
+
 /* Host-only plan: decomposition, tiles and halo maps for cfg, with no
  * device work and no workspace.  The handle supports od_plan,
  * od_tile_info_get, od_chare_get and od_destroy; the other calls return
@@ -178,15 +204,18 @@ od_status od_plan(struct od_grid* g, od_plan_info* info);
  * for tile t: its chare, origin in the chare, extent, and for each face
  * (x-,x+,y-,y+,z-,z+) the source it reads its ghost slab from:
  * src_kind 0 = a chare (src = chare id), 1 = a Dirichlet face of the domain
- * (src = face 0..5); src_origin = the global interior coordinates of the
- * ghost slab's first cell. */
+ * (src = face 0..5), 2 = the ghost buffer of a resolution-change face of
+ * the tile's own chare (src = face 0..5); src_origin = the coordinates of
+ * the ghost slab's first cell in cells of the chare's size (global interior
+ * coordinates for unit cells). */
 typedef struct {
     int32_t chare, origin[3], extent[3];
     int32_t src_kind[6], src[6], src_origin[6][3];
 } od_tile_info;
 od_status od_tile_info_get(struct od_grid* g, int32_t t, od_tile_info* out);
 
-/* Chare geometry: origin and extent of chare c. */
+/* Chare geometry: origin and extent of chare c in grid units (for
+ * multi-resolution blocks: the block as given; cells = extent / cell). */
 od_status od_chare_get(struct od_grid* g, int32_t c, od_block* out);
 
 /* Wait for all work on the grid's stream, release host-side resources.
@@ -229,16 +258,16 @@ size_t od_launch_overlap_bytes(int64_t total_threads);
 /* Split total_threads threads (each `work` dependent 32-bit multiply-adds
  * x <- x*1664525 + 1013904223 from x = thread_index ^ 0x9E3779B9, stored to
  * outputs[thread_index]) into nkernels near-equal kernels of 256-thread
- * workgroups, round-robin over nstreams streams.  Each stream first waits on
- * a device signal word (hipStreamWaitValue32, allocated once per device and
- * kept until the process ends); after every kernel is enqueued, the word is
- * written from a separate stream and all kernels start together.  Blocks
- * until every kernel has completed (bounded: OD_ETIMEDOUT after 60 s).
+ * workgroups, round-robin over nstreams streams.  Each stream first runs a
+ * one-wave gate kernel polling a flag in pinned host memory (allocated once
+ * per device and kept until the process ends); after every kernel is
+ * enqueued the host raises the flag and all streams start together.  A gate
+ * gives up after 10 s (OD_ETIMEDOUT).  Blocks until every kernel has
+ * completed (bounded: OD_ETIMEDOUT after 60 s).
  * dev_ws: caller-owned device memory, 256-byte aligned, at least
  * od_launch_overlap_bytes(total_threads).  Limits: total_threads in
  * [1, 2^31], nkernels in [1, min(65536, total_threads)], nstreams in
- * [1, 256], work in [0, 2^24]; otherwise OD_EINVAL.  OD_EINVAL as well if
- * the device cannot run stream wait-value operations. */
+ * [1, 256], work in [0, 2^24]; otherwise OD_EINVAL. */
 od_status od_launch_overlap(void* dev_ws, size_t ws_bytes, int64_t total_threads, int32_t nkernels,
                             int32_t nstreams, int32_t work, od_overlap_result* out);
 

@@ -36,8 +36,10 @@ def _dims(n) -> tuple:
 
 def make_config(n, odf: int = 8, block=None, blocks: Optional[Sequence] = None, dtype="f64",
                 bc=DEFAULT_BC, seed: int = 12734, exec: str = "graph", tile=None,
-                imbalance_pct: int = 0, imbalance_max_extra: int = 0, hints: int = 0, stencil: int = 7):
-    """Fill an od_config; returns (cfg, keepalive) where keepalive holds arrays it points to."""
+                imbalance_pct: int = 0, imbalance_max_extra: int = 0, hints: int = 0, stencil: int = 7,
+                cell: Optional[Sequence] = None):
+    """Fill an od_config; returns (cfg, keepalive) where keepalive holds arrays it points to.
+    `cell`: per explicit block, its cell edge in grid units (multi-resolution)."""
     cfg = B.od_config()
     lib().od_config_default(ctypes.byref(cfg))
     nx, ny, nz = _dims(n)
@@ -55,7 +57,15 @@ def make_config(n, odf: int = 8, block=None, blocks: Optional[Sequence] = None, 
                 arr[i].extent[d] = int(e[d])
         cfg.blocks = ctypes.cast(arr, ctypes.POINTER(B.od_block))
         cfg.nblocks = len(blocks)
-        keep = arr
+        keep = [arr]
+        if cell is not None:
+            if len(cell) != len(blocks):
+                raise ValueError("one cell size per block")
+            carr = (ctypes.c_int32 * len(cell))(*[int(v) for v in cell])
+            cfg.block_cell = ctypes.cast(carr, ctypes.POINTER(ctypes.c_int32))
+            keep.append(carr)
+    elif cell is not None:
+        raise ValueError("cell sizes need explicit blocks")
     cfg.dtype = _DTYPES[dtype][0]
     for i in range(6):
         cfg.bc[i] = float(bc[i])
@@ -146,7 +156,7 @@ class Grid:
     def __init__(self, n, odf: int = 8, block=None, blocks=None, dtype="f64", bc=DEFAULT_BC,
                  seed: int = 12734, exec: str = "graph", tile=None, imbalance_pct: int = 0,
                  imbalance_max_extra: int = 0, hints: int = 0, stencil: int = 7, device: str = "cuda:0",
-                 stream=None):
+                 stream=None, cell=None):
         import torch
 
         self.n = _dims(n)
@@ -154,7 +164,8 @@ class Grid:
         self.exec = exec
         cfg, self._keep = make_config(n=n, odf=odf, block=block, blocks=blocks, dtype=dtype, bc=bc, seed=seed,
                                       exec=exec, tile=tile, imbalance_pct=imbalance_pct,
-                                      imbalance_max_extra=imbalance_max_extra, hints=hints, stencil=stencil)
+                                      imbalance_max_extra=imbalance_max_extra, hints=hints, stencil=stencil,
+                                      cell=cell)
         nbytes = ctypes.c_size_t()
         check(lib().od_workspace_bytes(ctypes.byref(cfg), ctypes.byref(nbytes)), "od_workspace_bytes")
         self.device = torch.device(device)
@@ -192,6 +203,25 @@ class Grid:
         out = np.empty((nz + 2, ny + 2, nx + 2), dtype=self.dtype)
         check(lib().od_read(self.h, out.ctypes.data, out.nbytes), "od_read")
         return out
+
+    def block_cells(self, b: int) -> tuple:
+        c = (ctypes.c_int32 * 3)()
+        check(lib().od_block_cells(self.h, int(b), c), "od_block_cells")
+        return tuple(c)
+
+    def read_block(self, b: int) -> np.ndarray:
+        """Chare b's interior cells, shape (cz, cy, cx)."""
+        cx, cy, cz = self.block_cells(b)
+        out = np.empty((cz, cy, cx), dtype=self.dtype)
+        check(lib().od_read_block(self.h, int(b), out.ctypes.data, out.nbytes), "od_read_block")
+        return out
+
+    def write_block(self, b: int, A: np.ndarray) -> None:
+        cx, cy, cz = self.block_cells(b)
+        A = np.ascontiguousarray(A, dtype=self.dtype)
+        if A.shape != (cz, cy, cx):
+            raise ValueError(f"block shape {A.shape} != {(cz, cy, cx)}")
+        check(lib().od_write_block(self.h, int(b), A.ctypes.data, A.nbytes), "od_write_block")
 
     def write(self, U: np.ndarray) -> None:
         nx, ny, nz = self.n

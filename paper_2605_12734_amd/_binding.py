@@ -39,7 +39,8 @@ class od_config(ctypes.Structure):
     _fields_ = [("n", c_i64 * 3), ("block", c_i64 * 3), ("odf", c_i32), ("blocks", ctypes.POINTER(od_block)),
                 ("nblocks", c_i32), ("dtype", ctypes.c_int), ("bc", c_dbl * 6), ("seed", c_u64),
                 ("exec", ctypes.c_int), ("tile", c_i32 * 3), ("imbalance_pct", c_i32),
-                ("imbalance_max_extra", c_i32), ("hints", c_i32), ("stencil", c_i32)]
+                ("imbalance_max_extra", c_i32), ("hints", c_i32), ("stencil", c_i32),
+                ("block_cell", ctypes.POINTER(c_i32))]
 
 
 class od_plan_info(ctypes.Structure):
@@ -85,6 +86,9 @@ SIGNATURES = {
     "od_destroy": (ctypes.c_int, [c_vp]),
     "od_stream_copy": (ctypes.c_int, [c_vp, c_vp, c_vp, c_sz, c_i32, ctypes.POINTER(c_dbl)]),
     "od_time_iterate": (ctypes.c_int, [c_vp, c_i64, ctypes.POINTER(c_dbl)]),
+    "od_block_cells": (ctypes.c_int, [c_vp, c_i32, ctypes.POINTER(c_i32)]),
+    "od_read_block": (ctypes.c_int, [c_vp, c_i32, c_vp, c_sz]),
+    "od_write_block": (ctypes.c_int, [c_vp, c_i32, c_vp, c_sz]),
     "od_launch_overlap_bytes": (c_sz, [c_i64]),
     "od_launch_overlap": (ctypes.c_int, [c_vp, c_sz, c_i64, c_i32, c_i32, c_i32, ctypes.POINTER(od_overlap_result)]),
     "od_launch_rate": (ctypes.c_int, [c_i32, c_i32, c_dbl, ctypes.POINTER(c_i64), ctypes.POINTER(c_dbl)]),

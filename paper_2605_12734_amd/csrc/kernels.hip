@@ -301,7 +301,9 @@ __device__ __forceinline__ void wg_stores_done() {
 // arrives on a counter (acq_rel: publishes the workgroup's stores) and polls
 // the generation.  The wait is bounded; on timeout the error flag is raised
 // and every workgroup leaves.
-__device__ __forceinline__ bool grid_barrier(unsigned int* bar, unsigned int* err, int64_t wait_ticks) {
+// `reset` (may be null): 8 words the last arrival zeroes before releasing.
+__device__ __forceinline__ bool grid_barrier(unsigned int* bar, unsigned int* err, int64_t wait_ticks,
+                                             unsigned int* reset = nullptr) {
     __shared__ int ok;
     wg_stores_done();
     if (threadIdx.x == 0) {
@@ -311,6 +313,8 @@ __device__ __forceinline__ bool grid_barrier(unsigned int* bar, unsigned int* er
         int good = 1;
         if (arrived == nb - 1) {
             __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (reset)
+                for (int x = 0; x < 8; ++x) __hip_atomic_store(&reset[x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             const int64_t t0 = wall_clock64();
@@ -340,6 +344,11 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
     using S = SW<T, TX, TY>;
     __shared__ T lds[S::LDS];
     __shared__ T red[S::NT / 64];
+    __shared__ int32_t s_idx;
+    // XCD groups: launch index w runs on XCD w % 8 and takes tiles of list
+    // positions = w (mod 8), the spatial chunk the planner gave that XCD
+    const int ng = (gridDim.x >= 8 && gridDim.x % 8 == 0) ? 8 : 1;
+    const int xg = (int)(blockIdx.x % ng);
     for (int64_t it = 0; it < iters; ++it) {
         const int p = parity ^ (int)(it & 1);
         if (blockIdx.x == 0)
@@ -347,7 +356,17 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
         const uint8_t* ex = extra ? extra + (size_t)((iter_base + it) % extra_period) * nchares : nullptr;
         T r = 0;
         int slot = -1;
-        for (int32_t ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+        // tiles of this workgroup's XCD group, taken one at a time from the
+        // group's counter (the next index is requested while a tile sweeps)
+        unsigned int* ctr = &bar[8 + 8 * (int)(it & 1) + xg];
+        if (threadIdx.x == 0) s_idx = (int32_t)__hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        int32_t idx = s_idx;
+        for (;;) {
+            const int32_t ti = xg + ng * idx;
+            if (ti >= ntiles) break;
+            int32_t nxt = 0;
+            if (threadIdx.x == 0) nxt = (int32_t)__hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const TileDev& t = tiles[ti];
             const int reps = 1 + (ex ? (int)ex[t.blk] : 0);
             T rr = 0;
@@ -358,10 +377,24 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
             }
             slot = t.rslot;
             r = rr > r ? rr : r;
+            __syncthreads();
+            if (threadIdx.x == 0) s_idx = nxt;
+            __syncthreads();
+            idx = s_idx;
         }
         if (slot >= 0) wg_residual<T, S::NT>(r, &res[2 * slot + (p ^ 1)], red);
         if (it + 1 < iters) {
-            if (!grid_barrier(bar, err, wait_ticks)) return;
+            // the last arrival clears the counters of the step after next
+            if (!grid_barrier(bar, err, wait_ticks, &bar[8 + 8 * (int)((it + 1) & 1)])) return;
+        }
+    }
+    // the last workgroup to leave clears the counters for the next launch
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned int prev = __hip_atomic_fetch_add(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == gridDim.x - 1) {
+            for (int x = 8; x < 24; ++x) __hip_atomic_store(&bar[x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&bar[2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -381,14 +414,47 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
 // parity step & 1) with the whole workgroup and returns its residual.
 // Wave 0 looks for a ready tile, 64 owned tiles at a time (one per lane,
 // starting after the last tile run), and takes the first ready one.
+// hwreg(HW_REG_XCC_ID, 0, 4): the XCD this wave runs on
+constexpr int kXccIdReg = ((4 - 1) << 11) | (0 << 6) | 20;
+
+// Launch start of the XCD-aware publication: record this workgroup's XCD,
+// meet every other workgroup, then mark each owned launch position whose
+// tile has a dependent owned on another XCD (or outside the launch).
+// Returns false if the start barrier timed out.
+template <int NT>
+__device__ __forceinline__ bool mark_cross_xcd(const MsgArgs& a, int32_t nown) {
+    const int32_t G = gridDim.x, w = blockIdx.x;
+    if (threadIdx.x == 0)
+        __hip_atomic_store(&a.wg_xcd[w], (int32_t)(__builtin_amdgcn_s_getreg(kXccIdReg) & 0xF), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    if (!grid_barrier(a.bar, a.err, a.wait_ticks)) return false;
+    const int32_t mine = ld_rlx(&a.wg_xcd[w]);
+    for (int32_t j = threadIdx.x; j < nown; j += NT) {
+        const int32_t pos = w + j * G;
+        const int32_t ti = a.tile_list ? a.tile_list[pos] : pos;
+        uint8_t cross = 0;
+        const int32_t q1 = a.dep_ptr[ti + 1];
+        for (int32_t q = a.dep_ptr[ti]; q < q1; ++q) {
+            const int32_t dt = a.dep_idx[q];
+            const int32_t dp = a.tile_pos ? a.tile_pos[dt] : dt;
+            if (dp < 0 || dp >= a.ntiles || ld_rlx(&a.wg_xcd[dp % G]) != mine) cross = 1;
+        }
+        a.xpub[pos] = cross;
+    }
+    __syncthreads();
+    return true;
+}
+
 template <int NT, class SweepFn>
 __device__ __forceinline__ void msg_loop(const MsgArgs& a, SweepFn sweep, double* red) {
     __shared__ int32_t s_pick, s_step, s_stop;
     const int32_t G = gridDim.x;
     const int32_t w = blockIdx.x;
     const int32_t nown = a.ntiles > w ? (a.ntiles - w + G - 1) / G : 0;
+    if (a.wg_xcd && !mark_cross_xcd<NT>(a, nown)) return;
     int32_t cursor = 0;
     int64_t idle_since = -1;
+    int64_t last_poll = 0;
     for (;;) {
         if (threadIdx.x < 64) {
             const int lane = threadIdx.x;
@@ -434,8 +500,18 @@ __device__ __forceinline__ void msg_loop(const MsgArgs& a, SweepFn sweep, double
                 int32_t stop = live_any ? 0 : 1;
                 // the host asks the launch to end: start no new task (every
                 // tile's state stays in HBM, a later launch resumes from it)
-                if (a.yield_flag && __hip_atomic_load(a.yield_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0)
-                    stop = 1, pick = -1;
+                if (a.yield_dev) {
+                    if (w == 0) {
+                        const int64_t now = wall_clock64();
+                        if (now - last_poll >= a.yield_poll_ticks) {
+                            last_poll = now;
+                            if (__hip_atomic_load(a.yield_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0)
+                                __hip_atomic_store(a.yield_dev, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                    }
+                    if (__hip_atomic_load(a.yield_dev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+                        stop = 1, pick = -1;
+                }
                 if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) stop = 1, pick = -1;
                 // acquire side: the step-`step` data of the tiles whose
                 // counters were just read
@@ -477,11 +553,18 @@ __device__ __forceinline__ void msg_loop(const MsgArgs& a, SweepFn sweep, double
         }
         wg_stores_done();
         if (threadIdx.x == 0) {
-            // release side: this tile's step-ns data before its counter
-            __hip_atomic_store(&a.done[pick], ns, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            // release side: this tile's step-ns data before its counter.
+            // Every wave has drained its stores into the XCD's L2; only a
+            // tile read from another XCD needs the L2 written back.
+            if (!a.xpub || a.xpub[a.tile_pos ? a.tile_pos[pick] : pick])
+                __hip_atomic_store(&a.done[pick], ns, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            else
+                __hip_atomic_store(&a.done[pick], ns, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (a.solve_count && ((ce > 0 && ns % ce == 0) || ns == tgt)) {
                 int32_t* cnt = &a.solve_count[sv];
-                const int32_t prev = __hip_atomic_fetch_add(cnt, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                // the residual max above has completed (drained with the
+                // stores); the decision maker's exchange reads it
+                const int32_t prev = __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (prev == a.solve_ntiles[sv] - 1) {
                     // last tile of the solve to finish decision step ns
                     __hip_atomic_store(cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -694,6 +777,66 @@ __global__ void k_init(GridDev g, uint64_t seed) {
     }
 }
 
+// Multi-resolution initialisation: one chare per blockIdx.y step, its cells
+// grid-strided over blockIdx.x.
+template <typename T>
+__global__ void k_init_cells(GridDev g, const int32_t* __restrict__ ccell, int32_t nchares, uint64_t seed) {
+    T* arena = reinterpret_cast<T*>(g.arena);
+    const int64_t nx = g.n[0], ny = g.n[1];
+    for (int32_t c = blockIdx.y; c < nchares; c += gridDim.y) {
+        const BlockDev B = g.blocks[c];
+        const int64_t h = ccell[c];
+        const int64_t ux = g.lk.corigin[3 * c], uy = g.lk.corigin[3 * c + 1], uz = g.lk.corigin[3 * c + 2];
+        const int64_t cnt = (int64_t)B.ex * B.ey * B.ez;
+        for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * blockDim.x) {
+            const int64_t x = e % B.ex, y = (e / B.ex) % B.ey, z = e / ((int64_t)B.ex * B.ey);
+            const int64_t gi = ((uz + z * h) * ny + (uy + y * h)) * nx + (ux + x * h);
+            arena[B.off[0] + x + y * B.py + z * B.pz] = unit_from_bits<T>(sm64(seed, (uint64_t)gi));
+        }
+    }
+}
+
+// Resolution-change ghost fill: one thread per ghost cell of the launch.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_amr_fill(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const FillSeg* __restrict__ segs,
+           int32_t nseg, int64_t total, int parity) {
+    for (int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < total;
+         gi += (int64_t)gridDim.x * blockDim.x) {
+        int32_t lo = 0, hi = nseg - 1;          // last segment with first <= gi
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (segs[mid].first <= gi) lo = mid;
+            else hi = mid - 1;
+        }
+        const FillSeg& S = segs[lo];
+        const int64_t loc = gi - S.first;
+        const int32_t c1 = (int32_t)(loc % S.n1), c2 = (int32_t)(loc / S.n1);
+        const int d = S.d, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+        const BlockDev& N = blocks[S.src];
+        const int64_t nb = parity ? N.off[1] : N.off[0];
+        const int64_t step[3] = {1, N.py, N.pz};
+        const int32_t i1 = (S.r1 + c1 * S.hc) >> S.lhn, i2 = (S.r2 + c2 * S.hc) >> S.lhn;
+        const int64_t at = nb + (int64_t)S.lay * step[d] + (int64_t)i1 * step[t1] + (int64_t)i2 * step[t2];
+        T v;
+        const int32_t r = S.hc >> S.lhn;
+        if (r <= 1) {
+            v = arena[at];
+        } else {
+            T sum = 0;
+            for (int32_t q2 = 0; q2 < r; ++q2)
+                for (int32_t q1 = 0; q1 < r; ++q1) {
+                    const T x = arena[at + (int64_t)q1 * step[t1] + (int64_t)q2 * step[t2]];
+                    sum = (q1 == 0 && q2 == 0) ? x : sum + x;
+                }
+            v = sum / (T)(r * r);
+        }
+        const BlockDev& D = blocks[S.dst];
+        const int64_t dstep[3] = {1, D.py, D.pz};
+        arena[D.off[0] + (int64_t)(S.a1 + c1) * dstep[t1] + (int64_t)(S.a2 + c2) * dstep[t2]] = v;
+    }
+}
+
 template <typename T>
 __global__ void k_fill_pb(GridDev g, int32_t npb, const int32_t* pb_face, const int32_t* pb_block,
                           const double* bc) {
@@ -780,13 +923,16 @@ static int io_grid(int64_t total) {
 }
 
 hipError_t launch_init(int dtype_bytes, hipStream_t st, const GridDev& g, int32_t nchares, uint64_t seed,
-                       int32_t npb, const int32_t* pb_face, const int32_t* pb_block, const double* bc_dev) {
+                       int32_t npb, const int32_t* pb_face, const int32_t* pb_block, const double* bc_dev,
+                       bool interior) {
     (void)nchares;
     const int64_t total = g.n[0] * g.n[1] * g.n[2];
-    if (dtype_bytes == 8)
-        hipLaunchKernelGGL(k_init<double>, dim3(io_grid(total)), dim3(256), 0, st, g, seed);
-    else
-        hipLaunchKernelGGL(k_init<float>, dim3(io_grid(total)), dim3(256), 0, st, g, seed);
+    if (interior) {
+        if (dtype_bytes == 8)
+            hipLaunchKernelGGL(k_init<double>, dim3(io_grid(total)), dim3(256), 0, st, g, seed);
+        else
+            hipLaunchKernelGGL(k_init<float>, dim3(io_grid(total)), dim3(256), 0, st, g, seed);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || npb <= 0) return e;
     dim3 grid(16, (unsigned)(npb < 65535 ? npb : 65535));
@@ -794,6 +940,31 @@ hipError_t launch_init(int dtype_bytes, hipStream_t st, const GridDev& g, int32_
         hipLaunchKernelGGL(k_fill_pb<double>, grid, dim3(256), 0, st, g, npb, pb_face, pb_block, bc_dev);
     else
         hipLaunchKernelGGL(k_fill_pb<float>, grid, dim3(256), 0, st, g, npb, pb_face, pb_block, bc_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_cells(int dtype_bytes, hipStream_t st, const GridDev& g, const int32_t* ccell,
+                             int32_t nchares, uint64_t seed) {
+    if (nchares <= 0) return hipSuccess;
+    dim3 grid(8, (unsigned)(nchares < 65535 ? nchares : 65535));
+    if (dtype_bytes == 8)
+        hipLaunchKernelGGL(k_init_cells<double>, grid, dim3(256), 0, st, g, ccell, nchares, seed);
+    else
+        hipLaunchKernelGGL(k_init_cells<float>, grid, dim3(256), 0, st, g, ccell, nchares, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_amr_fill(int dtype_bytes, hipStream_t st, void* arena, const BlockDev* blocks,
+                           const FillSeg* segs, int32_t nseg, int64_t total, int parity) {
+    if (nseg <= 0 || total <= 0) return hipSuccess;
+    const int64_t want = (total + 255) / 256;
+    const unsigned int grid = (unsigned int)(want < 4096 ? want : 4096);
+    if (dtype_bytes == 8)
+        hipLaunchKernelGGL(k_amr_fill<double>, dim3(grid), dim3(256), 0, st, reinterpret_cast<double*>(arena),
+                           blocks, segs, nseg, total, parity);
+    else
+        hipLaunchKernelGGL(k_amr_fill<float>, dim3(grid), dim3(256), 0, st, reinterpret_cast<float*>(arena),
+                           blocks, segs, nseg, total, parity);
     return hipGetLastError();
 }
 

@@ -47,8 +47,11 @@ hipError_t launch_sweep(int dtype_bytes, int tx, int ty, hipStream_t st, void* a
                         const uint8_t* extra, int hints);
 
 // Persistent cooperative sweep: all `iters` iterations in one launch with a
-// device-wide barrier between them.  `bar` = 2 zeroed uint32 (count,
-// generation); `err` = error flag.  `extra` (may be null): table of
+// device-wide barrier between them.  Workgroups take tiles dynamically from
+// per-XCD-group counters (load balance under imbalance and uneven blocks).
+// `bar` = 32 zeroed uint32: [0] arrivals, [1] generation, [2] exits,
+// [8..24) tile counters (8 XCD groups x 2 step parities); the kernel leaves
+// them zeroed.  `err` = error flag.  `extra` (may be null): table of
 // [period][nchares] extra re-runs, row (iter_base + it) % period.
 hipError_t launch_persistent(int dtype_bytes, int tx, int ty, hipStream_t st, int grid,
                              void* arena, const BlockDev* blocks, const TileDev* tiles,
@@ -93,19 +96,71 @@ struct MsgArgs {
     volatile int32_t* host_done;     // pinned host: per solve final step when done
     volatile unsigned long long* host_res;
     volatile int32_t* yield_flag;   // pinned host: nonzero => stop after current tasks
+    int32_t* yield_dev;             // device copy of the yield flag (zeroed before the launch):
+                                    // workgroup 0 polls the host flag at most every
+                                    // yield_poll_ticks and raises this word, which every
+                                    // workgroup reads (no host-memory poll per task)
+    int64_t yield_poll_ticks;
+    // XCD-aware publication (wg_xcd null => every finished task publishes
+    // with a full agent-scope release, which writes back the XCD's L2).
+    // At launch start every workgroup records its XCD, a device-wide
+    // barrier follows, and each workgroup marks its tiles whose dependents
+    // are all owned on its own XCD: those publish with a plain ordered
+    // store, since the XCD's L2 is coherent for all of its CUs.
+    int32_t* wg_xcd;            // per workgroup of the launch (kMaxLaunchWgs entries)
+    uint8_t* xpub;              // per launch position: 1 = some dependent lives on another XCD
+    const int32_t* tile_pos;    // tile id -> launch position (null => identity)
+    unsigned int* bar;          // 2 words for the start barrier (count, generation)
 };
 hipError_t launch_msgdriven(int dtype_bytes, int tx, int ty, hipStream_t st, int grid, const MsgArgs& a);
+constexpr int kMaxLaunchWgs = 8192;   // bound of a cooperative launch's workgroups (wg_xcd entries)
 
 // Serving kernel: fp64 tiles of (kServeTx8, kServeTy8) and fp32 tiles of
 // (kServeTx4, kServeTy4) columns, same thread count, one cooperative launch.
-constexpr int kServeTx8 = 32, kServeTy8 = 8, kServeTx4 = 32, kServeTy4 = 16;
+#ifndef OD_SERVE_TY8
+#define OD_SERVE_TY8 8     // rows of an fp64 serving tile (fp32 tiles have twice as many)
+#endif
+constexpr int kServeTx8 = 32, kServeTy8 = OD_SERVE_TY8, kServeTx4 = 32, kServeTy4 = 2 * OD_SERVE_TY8;
 int serve_max_grid();
 hipError_t launch_serve(hipStream_t st, int grid, const MsgArgs& a);
 
+// Multi-resolution ghost fill: one rectangle of a chare face's ghost buffer
+// read from one neighbour chare of another cell size.  Ghost cell (c1, c2)
+// of the rectangle (tangential axes t1 < t2 of the face's normal axis d)
+// lies at neighbour-relative unit offsets (r1 + c1*hc, r2 + c2*hc); the
+// neighbour cell edge is 2^lhn units.  A coarser or equal neighbour gives
+// its cell containing that point, a finer one the mean of the
+// (hc >> lhn)^2 cells of its layer `lay` covering the ghost cell's face.
+struct FillSeg {
+    int32_t dst;            // ghost pseudo-block (block table index)
+    int32_t src;            // neighbour chare
+    int32_t d;              // normal axis
+    int32_t lay;            // neighbour cell index along d
+    int32_t a1, a2;         // rectangle origin in the face's ghost cells
+    int32_t n1, n2;         // rectangle extent
+    int32_t r1, r2;         // neighbour-relative unit offset of ghost cell (a1, a2)
+    int32_t hc, lhn;        // ghost cell edge (units), log2 neighbour cell edge
+    int64_t first;          // launch index of the rectangle's first ghost cell
+};
+static_assert(sizeof(FillSeg) == 56, "FillSeg layout");
+
+// Fill every resolution-change ghost buffer from parity `parity` of the
+// chares: segs[0..nseg) sorted by `first`, total ghost cells `total`.
+hipError_t launch_amr_fill(int dtype_bytes, hipStream_t st, void* arena, const BlockDev* blocks,
+                           const FillSeg* segs, int32_t nseg, int64_t total, int parity);
+
+// Multi-resolution initialisation of parity 0: chare c's cell (i,j,k)
+// starts at unit corigin_c + (i,j,k)*ccell[c] and takes the SplitMix64
+// value of that unit's global index.
+hipError_t launch_init_cells(int dtype_bytes, hipStream_t st, const GridDev& g, const int32_t* ccell,
+                             int32_t nchares, uint64_t seed);
+
 // Initialise parity 0 of every chare from seed, Dirichlet pseudo-blocks from bc.
+// `interior` = false: only the Dirichlet pseudo-blocks (the chares are
+// initialised by launch_init_cells).
 hipError_t launch_init(int dtype_bytes, hipStream_t st, const GridDev& g, int32_t nchares,
                        uint64_t seed, int32_t npb, const int32_t* pb_face, const int32_t* pb_block,
-                       const double* bc_dev);
+                       const double* bc_dev, bool interior = true);
 
 // Gather planes [kz_lo, kz_hi) of the padded global array into dst (device- or
 // host-mapped), plane kz_lo at dst[0].  scatter: the inverse.

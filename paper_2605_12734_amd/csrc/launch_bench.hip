@@ -5,11 +5,15 @@
 //
 //  - overlap: a fixed amount of work (total_threads threads, `work` dependent
 //    integer multiply-adds each) split into nkernels kernels on a pool of
-//    non-blocking streams.  Every stream first waits on one signal word
-//    (hipStreamWaitValue32); once everything is enqueued, a separate stream
-//    writes the word (hipStreamWriteValue32), releasing all kernels at once.
-//    The device makespan (earliest workgroup start to latest workgroup end,
+//    non-blocking streams.  Every stream first runs a one-wave gate kernel
+//    that polls a flag in pinned host memory; once everything is enqueued,
+//    the host sets the flag and all streams proceed at once.  The device
+//    makespan (earliest work-workgroup start to latest work-workgroup end,
 //    constant-rate wall clock) therefore excludes host submission cost.
+//    The gate is released by the host, not by a stream operation: HIP
+//    multiplexes streams onto a few hardware queues, so a release enqueued
+//    on another stream can sit in the same queue behind a gate and never
+//    run.  Every gate gives up after a bounded wait and reports it.
 //  - rate: host threads each own `chares` streams; a thread fires an empty
 //    full-device kernel on a stream whenever that stream's previous kernel
 //    has completed (event query), for a fixed wall time.
@@ -48,6 +52,21 @@ __global__ void k_stamp_init(unsigned long long* stamps) {
     if (threadIdx.x == 0) {
         stamps[0] = ~0ull;
         stamps[1] = 0ull;
+        stamps[2] = 0ull;
+    }
+}
+
+// Waits until the host sets *flag (system-scope polls), at most wait_ticks
+// of the constant-rate clock; a timeout is recorded in stamps[2].
+__global__ void k_gate(const uint32_t* flag, unsigned long long* stamps, int64_t wait_ticks) {
+    if (threadIdx.x != 0) return;
+    const int64_t t0 = wall_clock64();
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) == 0u) {
+        __builtin_amdgcn_s_sleep(8);
+        if (wall_clock64() - t0 > wait_ticks) {
+            atomicOr(&stamps[2], 1ull);
+            break;
+        }
     }
 }
 
@@ -57,23 +76,23 @@ double now_us() {
     return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// One signal word per device, kept until the process ends.
-uint32_t* signal_word(int dev, std::string& err) {
-    static std::vector<uint32_t*> words(64, nullptr);
-    if (dev < 0 || dev >= (int)words.size()) {
+// One pinned, device-visible host flag per device, kept until the process ends.
+uint32_t* host_flag(int dev, std::string& err) {
+    static std::vector<uint32_t*> flags(64, nullptr);
+    if (dev < 0 || dev >= (int)flags.size()) {
         err = "device index out of range";
         return nullptr;
     }
-    if (!words[dev]) {
+    if (!flags[dev]) {
         void* p = nullptr;
-        hipError_t e = hipExtMallocWithFlags(&p, 8, hipMallocSignalMemory);
+        hipError_t e = hipHostMalloc(&p, 64, hipHostMallocMapped | hipHostMallocCoherent);
         if (e != hipSuccess) {
-            err = std::string("hipExtMallocWithFlags(signal): ") + hipGetErrorString(e);
+            err = std::string("hipHostMalloc(flag): ") + hipGetErrorString(e);
             return nullptr;
         }
-        words[dev] = static_cast<uint32_t*>(p);
+        flags[dev] = static_cast<uint32_t*>(p);
     }
-    return words[dev];
+    return flags[dev];
 }
 
 struct Streams {
@@ -143,33 +162,35 @@ od_status od_launch_overlap(void* dev_ws, size_t ws_bytes, int64_t total_threads
         if (ws_bytes < od_launch_overlap_bytes(total_threads))
             return od::fail(OD_EINVAL, "workspace smaller than od_launch_overlap_bytes(total_threads)");
         if ((reinterpret_cast<uintptr_t>(dev_ws) & 255) != 0) return od::fail(OD_EINVAL, "dev_ws not 256-byte aligned");
-        int dev = 0, can_wait = 0, khz = 0;
+        int dev = 0, khz = 0;
         OD_HIP_OR_FAIL(hipGetDevice(&dev));
-        OD_HIP_OR_FAIL(hipDeviceGetAttribute(&can_wait, hipDeviceAttributeCanUseStreamWaitValue, dev));
-        if (!can_wait) return od::fail(OD_EINVAL, "device does not support stream wait-value operations");
         OD_HIP_OR_FAIL(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
         if (khz <= 0) return od::fail(OD_EHIP, "device reports no wall-clock rate");
         std::string err;
-        uint32_t* sig = signal_word(dev, err);
-        if (!sig) return od::fail(OD_EHIP, err);
+        uint32_t* flag = host_flag(dev, err);
+        if (!flag) return od::fail(OD_EHIP, err);
+        uint32_t* dflag = nullptr;
+        OD_HIP_OR_FAIL(hipHostGetDevicePointer(reinterpret_cast<void**>(&dflag), flag, 0));
+        const int64_t gate_ticks = (int64_t)(10.0 * 1e3 * (double)khz);   // 10 s
 
         const int ns = std::min(nstreams, nkernels);
-        Streams S, R;
+        Streams S;
         OD_HIP_OR_FAIL(S.create(ns));
-        OD_HIP_OR_FAIL(R.create(1));
         auto* stamps = static_cast<unsigned long long*>(dev_ws);
         auto* outv = reinterpret_cast<uint32_t*>(static_cast<char*>(dev_ws) + kStampBytes);
-        // arm: signal = 0 and stamps reset, completed before any wait is enqueued
-        OD_HIP_OR_FAIL(hipStreamWriteValue32(R.s[0], sig, 0u, 0));
-        hipLaunchKernelGGL(k_stamp_init, dim3(1), dim3(64), 0, R.s[0], stamps);
+        // arm: flag down, stamps reset (completed before any gate is enqueued)
+        __atomic_store_n(flag, 0u, __ATOMIC_SEQ_CST);
+        hipLaunchKernelGGL(k_stamp_init, dim3(1), dim3(64), 0, S.s[0], stamps);
         OD_HIP_OR_FAIL(hipGetLastError());
-        OD_HIP_OR_FAIL(hipStreamSynchronize(R.s[0]));
+        OD_HIP_OR_FAIL(hipStreamSynchronize(S.s[0]));
 
         // enqueue: a gate per stream, then the kernels round-robin over the streams
         const double t0 = now_us();
         hipError_t enq = hipSuccess;
-        for (int s = 0; s < ns && enq == hipSuccess; ++s)
-            enq = hipStreamWaitValue32(S.s[s], sig, 1u, hipStreamWaitValueGte, 0xFFFFFFFFu);
+        for (int s = 0; s < ns && enq == hipSuccess; ++s) {
+            hipLaunchKernelGGL(k_gate, dim3(1), dim3(64), 0, S.s[s], dflag, stamps, gate_ticks);
+            enq = hipGetLastError();
+        }
         const int64_t per = total_threads / nkernels, rem = total_threads % nkernels;
         int64_t first = 0;
         for (int32_t k = 0; k < nkernels && enq == hipSuccess; ++k) {
@@ -182,10 +203,9 @@ od_status od_launch_overlap(void* dev_ws, size_t ws_bytes, int64_t total_threads
         }
         for (int s = 0; s < ns && enq == hipSuccess; ++s) enq = hipEventRecord(S.e[s], S.s[s]);
         const double t1 = now_us();
-        // release (always, also after a failed enqueue, so no stream stays gated)
-        const hipError_t rel = hipStreamWriteValue32(R.s[0], sig, 1u, 0);
+        // release from the host (always, also after a failed enqueue)
+        __atomic_store_n(flag, 1u, __ATOMIC_SEQ_CST);
         const double t2 = now_us();
-        if (rel != hipSuccess) return od::fail(OD_EHIP, std::string("hipStreamWriteValue32: ") + hipGetErrorString(rel));
         const bool done = wait_events(S.e, 60.0);
         const double t3 = now_us();
         if (enq != hipSuccess) {
@@ -193,8 +213,9 @@ od_status od_launch_overlap(void* dev_ws, size_t ws_bytes, int64_t total_threads
             return od::fail(OD_EHIP, std::string("enqueue: ") + hipGetErrorString(enq));
         }
         if (!done) return od::fail(OD_ETIMEDOUT, "released kernels did not complete within 60 s");
-        unsigned long long st[2] = {0, 0};
+        unsigned long long st[3] = {0, 0, 0};
         OD_HIP_OR_FAIL(hipMemcpy(st, stamps, sizeof(st), hipMemcpyDeviceToHost));
+        if (st[2] != 0) return od::fail(OD_ETIMEDOUT, "a stream gate was not released within its bound");
         out->total_threads = total_threads;
         out->nkernels = nkernels;
         out->nstreams = ns;

@@ -83,7 +83,74 @@ void face_shape(const Chare& c, int32_t cpy, int f, int32_t e[3], int32_t* py, i
 
 bool on_domain_face(const Plan& p, const Chare& c, int f) {
     const int d = f / 2;
-    return (f % 2 == 0) ? c.o[d] == 0 : (int64_t)c.o[d] + c.e[d] == p.n[d];
+    return (f % 2 == 0) ? c.u[d] == 0 : (int64_t)c.u[d] + (int64_t)c.e[d] * c.h == p.n[d];
+}
+
+int32_t log2i(int32_t v) {
+    int32_t l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+// Ghost-fill rectangles of every resolution-change face: one per (face,
+// neighbour chare), found by walking the face's unit slab at the owner
+// grid's granularity.  Returns the number of neighbour cells the fill reads.
+int64_t build_fill_segments(Grid& G) {
+    const Plan& p = G.plan;
+    G.segs_h.clear();
+    G.fill_total = 0;
+    int64_t reads = 0;
+    const int64_t g = p.gran;
+    for (int32_t ci = 0; ci < (int32_t)p.chares.size(); ++ci) {
+        const Chare& c = p.chares[(size_t)ci];
+        for (int f = 0; f < 6; ++f) {
+            const int32_t pb = G.amr_pb[(size_t)ci * 6 + f];
+            if (pb < 0) continue;
+            const int d = f / 2, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+            const int64_t nrm = (f % 2) ? (int64_t)c.u[d] + (int64_t)c.e[d] * c.h : (int64_t)c.u[d] - 1;
+            int64_t lo[3], hi[3];
+            for (int q = 0; q < 3; ++q) {
+                lo[q] = c.u[q];
+                hi[q] = (int64_t)c.u[q] + (int64_t)c.e[q] * c.h;
+            }
+            lo[d] = nrm;
+            hi[d] = nrm + 1;
+            std::vector<int32_t> seen;
+            for (int64_t z = lo[2] / g * g; z < hi[2]; z += g)
+                for (int64_t y = lo[1] / g * g; y < hi[1]; y += g)
+                    for (int64_t x = lo[0] / g * g; x < hi[0]; x += g) {
+                        const int32_t nb = plan_owner(p, std::max(x, lo[0]), std::max(y, lo[1]), std::max(z, lo[2]));
+                        if (std::find(seen.begin(), seen.end(), nb) != seen.end()) continue;
+                        seen.push_back(nb);
+                        const Chare& N = p.chares[(size_t)nb];
+                        int64_t a[3], b[3];
+                        for (int q = 0; q < 3; ++q) {
+                            a[q] = std::max<int64_t>(lo[q], N.u[q]);
+                            b[q] = std::min<int64_t>(hi[q], (int64_t)N.u[q] + (int64_t)N.e[q] * N.h);
+                        }
+                        FillSeg S{};
+                        S.dst = pb;
+                        S.src = nb;
+                        S.d = d;
+                        S.lay = (int32_t)((nrm - N.u[d]) / N.h);
+                        S.a1 = (int32_t)((a[t1] - c.u[t1]) / c.h);
+                        S.a2 = (int32_t)((a[t2] - c.u[t2]) / c.h);
+                        S.n1 = (int32_t)((b[t1] - a[t1]) / c.h);
+                        S.n2 = (int32_t)((b[t2] - a[t2]) / c.h);
+                        S.r1 = (int32_t)(a[t1] - N.u[t1]);
+                        S.r2 = (int32_t)(a[t2] - N.u[t2]);
+                        S.hc = c.h;
+                        S.lhn = log2i(N.h);
+                        S.first = G.fill_total;
+                        const int64_t cells = (int64_t)S.n1 * S.n2;
+                        G.fill_total += cells;
+                        const int64_t r = N.h < c.h ? c.h / N.h : 1;
+                        reads += cells * r * r;
+                        G.segs_h.push_back(S);
+                    }
+        }
+    }
+    return reads;
 }
 
 }  // namespace
@@ -114,6 +181,8 @@ std::string fill_tile_descs(Grid& G) {
             else if (th.kind[f] == 0) {
                 if (cfg.exec == OD_PER_CHARE) pb = G.ghost_pb[(size_t)th.chare * 6 + f];
                 else src_chare = th.src[f];
+            } else if (th.kind[f] == 3) {
+                pb = G.amr_pb[(size_t)th.chare * 6 + f];
             } else {
                 pb = G.dir_pb[(size_t)th.chare * 6 + f];
             }
@@ -155,6 +224,9 @@ std::string build_layout(const od_config& cfg, Grid& G) {
         cfg.imbalance_max_extra > 255)
         return "imbalance_pct must be in [0,100] and imbalance_max_extra in [0,255]";
     if (cfg.imbalance_pct > 0 && cfg.exec == OD_GRAPH) return "imbalance is not supported with OD_GRAPH";
+    if (p.multires && cfg.exec != OD_FUSED && cfg.exec != OD_GRAPH)
+        return "multi-resolution blocks are supported with OD_FUSED and OD_GRAPH";
+    if (p.multires && cfg.stencil == 5) return "multi-resolution blocks need the 3D 7-point stencil";
     if (!p.regular) {
         // tile rows are loaded as 16-byte vectors: explicit blocks start on a
         // vector boundary along x
@@ -193,6 +265,7 @@ std::string build_layout(const od_config& cfg, Grid& G) {
         for (int f = 0; f < 6; ++f) {
             if (on_domain_face(p, p.chares[(size_t)c], f)) ++npb;
             else if (cfg.exec == OD_PER_CHARE) ++npb;
+            else if (p.multires && p.mr[(size_t)c * 6 + f]) ++npb;
         }
     const size_t nblocks = (size_t)C + (size_t)npb;
     const size_t ntiles = p.tiles.size();
@@ -209,7 +282,7 @@ std::string build_layout(const od_config& cfg, Grid& G) {
             size_t k = 1;
             for (int d = 0; d < 3; ++d) {
                 int32_t md = m[d];
-                if (!p.regular) md = std::min(md, p.gran);
+                if (!p.regular) md = std::min(md, std::max<int32_t>(1, p.gcell));
                 k *= (size_t)ceil_div(c.e[d], md);
             }
             cap += k;
@@ -220,13 +293,14 @@ std::string build_layout(const od_config& cfg, Grid& G) {
     for (int d = 0; d < 3; ++d) G.L.cidx[d] = cv.take((size_t)(p.regular ? p.n[d] : 1) * 4);
     G.L.owner = cv.take((p.regular ? 1 : p.owner.size()) * 4);
     G.L.corigin = cv.take((size_t)C * 3 * 4);
+    G.L.ccell = cv.take((size_t)C * 4);
     G.L.dir_pb = cv.take((size_t)C * 6 * 4);
     G.L.pb_face = cv.take((size_t)std::max(npb, 1) * 4);
     G.L.pb_block = cv.take((size_t)std::max(npb, 1) * 4);
     G.L.bc = cv.take(6 * 8);
     G.nres = cfg.exec == OD_PER_CHARE ? C : 1;
     G.L.res = cv.take((size_t)(2 * G.nres + 2) * 8);
-    G.L.bar = cv.take(4 * 4);
+    G.L.bar = cv.take(32 * 4);
     G.L.err = cv.take(4);
     G.L.done = cv.take(ntiles * 4);
     G.L.target = cv.take(4 * 4);
@@ -237,6 +311,8 @@ std::string build_layout(const od_config& cfg, Grid& G) {
         std::string e2 = build_tile_deps(p, G.dep_ptr, G.dep_idx);
         if (!e2.empty()) return e2;
     }
+    G.L.wgxcd = cv.take(cfg.exec == OD_MSGDRIVEN ? (size_t)kMaxLaunchWgs * 4 : 4);
+    G.L.xpub = cv.take(cfg.exec == OD_MSGDRIVEN ? ntiles : 1);
     G.L.dep_ptr = cv.take((G.dep_ptr.size() + 1) * 4);
     G.L.dep_idx = cv.take((G.dep_idx.size() + 1) * 4);
     // imbalance table
@@ -278,11 +354,13 @@ std::string build_layout(const od_config& cfg, Grid& G) {
     }
     G.L.field_end = cv.off;
     // ---- pseudo-blocks
+    G.amr_pb.assign((size_t)C * 6, -1);
     for (int32_t c = 0; c < C; ++c) {
         const Chare& ch = p.chares[(size_t)c];
         for (int f = 0; f < 6; ++f) {
             const bool dom = on_domain_face(p, ch, f);
-            if (!dom && cfg.exec != OD_PER_CHARE) continue;
+            const bool res = !dom && p.multires && p.mr[(size_t)c * 6 + f];
+            if (!dom && !res && cfg.exec != OD_PER_CHARE) continue;
             int32_t e[3], py;
             int64_t pz, cnt;
             face_shape(ch, G.cpy[(size_t)c], f, e, &py, &pz, &cnt);
@@ -300,6 +378,8 @@ std::string build_layout(const od_config& cfg, Grid& G) {
                 G.dir_pb[(size_t)c * 6 + f] = id;
                 G.pb_face.push_back(f);
                 G.pb_block.push_back(id);
+            } else if (res) {
+                G.amr_pb[(size_t)c * 6 + f] = id;
             } else {
                 G.ghost_pb[(size_t)c * 6 + f] = id;
             }
@@ -323,6 +403,20 @@ std::string build_layout(const od_config& cfg, Grid& G) {
             }
         }
     }
+    // ---- multi-resolution ghost fill rectangles
+    G.segs_h.clear();
+    G.fill_total = 0;
+    if (p.multires) {
+        const int64_t reads = build_fill_segments(G);
+        // algorithmic ghost traffic: same-size faces read their neighbour
+        // cells, resolution-change faces the neighbour cells their fill reads
+        int64_t direct = 0;
+        for (const TileHost& t : p.tiles)
+            for (int f = 0; f < 6; ++f)
+                if (t.kind[f] == 0) direct += (int64_t)t.e[0] * t.e[1] * t.e[2] / t.e[f / 2];
+        p.halo_cells = direct + reads;
+    }
+    G.L.segs = cv.take(std::max<size_t>(G.segs_h.size(), 1) * sizeof(FillSeg));
     G.L.total = align_up(cv.off, kAlign) + kAlign;
 
     return fill_tile_descs(G);
@@ -394,8 +488,11 @@ od_status Grid::upload() {
     const Plan& p = plan;
     const int32_t C = (int32_t)p.chares.size();
     std::vector<int32_t> corigin((size_t)C * 3);
-    for (int32_t c = 0; c < C; ++c)
-        for (int d = 0; d < 3; ++d) corigin[(size_t)c * 3 + d] = p.chares[(size_t)c].o[d];
+    std::vector<int32_t> ccell((size_t)C);
+    for (int32_t c = 0; c < C; ++c) {
+        for (int d = 0; d < 3; ++d) corigin[(size_t)c * 3 + d] = p.chares[(size_t)c].u[d];
+        ccell[(size_t)c] = p.chares[(size_t)c].h;
+    }
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = put(L.blocks, blocks_h.data(), blocks_h.size() * sizeof(BlockDev));
     if (e == hipSuccess) e = put(L.tiles, tiles_h.data(), tiles_h.size() * sizeof(TileDev));
@@ -411,6 +508,8 @@ od_status Grid::upload() {
         e = put(L.owner, p.owner.data(), p.owner.size() * 4);
     }
     if (e == hipSuccess) e = put(L.corigin, corigin.data(), corigin.size() * 4);
+    if (e == hipSuccess) e = put(L.ccell, ccell.data(), ccell.size() * 4);
+    if (e == hipSuccess) e = put(L.segs, segs_h.data(), segs_h.size() * sizeof(FillSeg));
     if (e == hipSuccess) e = put(L.dir_pb, dir_pb.data(), dir_pb.size() * 4);
     if (e == hipSuccess) e = put(L.pb_face, pb_face.data(), pb_face.size() * 4);
     if (e == hipSuccess) e = put(L.pb_block, pb_block.data(), pb_block.size() * 4);
@@ -441,7 +540,7 @@ od_status Grid::reset_state() {
     // zero residual slots, barrier, error flag and step counters with a
     // plain fill (not captured into any graph)
     hipError_t e = hipMemsetAsync(base + L.res, 0, (size_t)(2 * nres + 2) * 8, st);
-    if (e == hipSuccess) e = hipMemsetAsync(base + L.bar, 0, 16, st);
+    if (e == hipSuccess) e = hipMemsetAsync(base + L.bar, 0, 32 * 4, st);
     if (e == hipSuccess) e = hipMemsetAsync(base + L.err, 0, 4, st);
     if (e == hipSuccess) e = hipMemsetAsync(base + L.done, 0, std::max<size_t>(tiles_h.size(), 1) * 4, st);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("state reset: ") + hipGetErrorString(e));
@@ -455,7 +554,10 @@ od_status Grid::init_field() {
     hipError_t e = launch_init(s, st, gdev, (int32_t)plan.chares.size(), cfg.seed, (int32_t)pb_face.size(),
                                reinterpret_cast<const int32_t*>(base + L.pb_face),
                                reinterpret_cast<const int32_t*>(base + L.pb_block),
-                               reinterpret_cast<const double*>(base + L.bc));
+                               reinterpret_cast<const double*>(base + L.bc), !plan.multires);
+    if (e == hipSuccess && plan.multires)
+        e = launch_init_cells(s, st, gdev, reinterpret_cast<const int32_t*>(base + L.ccell),
+                              (int32_t)plan.chares.size(), cfg.seed);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("init: ") + hipGetErrorString(e));
     return OD_OK;
 }
@@ -491,6 +593,12 @@ const uint8_t* Grid::extra_row(int64_t step) const {
 }
 
 od_status Grid::fused_one(hipStream_t s2, int par, int64_t step) {
+    if (!segs_h.empty()) {
+        hipError_t e0 = launch_amr_fill(s, s2, base, reinterpret_cast<const BlockDev*>(base + L.blocks),
+                                        reinterpret_cast<const FillSeg*>(base + L.segs), (int32_t)segs_h.size(),
+                                        fill_total, par);
+        if (e0 != hipSuccess) return fail(OD_EHIP, std::string("ghost fill launch: ") + hipGetErrorString(e0));
+    }
     hipError_t e = launch_sweep(s, plan.tile[0], plan.tile[1], s2, base,
                                 reinterpret_cast<const BlockDev*>(base + L.blocks),
                                 reinterpret_cast<const TileDev*>(base + L.tiles), (int32_t)tiles_h.size(), par,
@@ -552,6 +660,7 @@ od_status Grid::persistent_run(int64_t n) {
 
 od_status Grid::msgdriven_run(int64_t n) {
     if (grid_wgs <= 0) return fail(OD_EHIP, "message-driven kernel: no co-resident workgroups");
+    if (grid_wgs > kMaxLaunchWgs) return fail(OD_EINVAL, "message-driven launch wider than its XCD table");
     if (iters + n > INT32_MAX) return fail(OD_EINVAL, "step counters limited to 2^31 iterations");
     // target = iters + n ; the final-step residual slot (index 2) is cleared
     const int32_t tgt = (int32_t)(iters + n);
@@ -576,6 +685,10 @@ od_status Grid::msgdriven_run(int64_t n) {
     a.wait_ticks = device_wait_ticks();
     a.final_only = 1;
     a.hints = mode();
+    a.wg_xcd = reinterpret_cast<int32_t*>(base + L.wgxcd);
+    a.xpub = reinterpret_cast<uint8_t*>(base + L.xpub);
+    a.tile_pos = nullptr;
+    a.bar = reinterpret_cast<unsigned int*>(base + L.bar);
     e = launch_msgdriven(s, plan.tile[0], plan.tile[1], st, grid_wgs, a);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("msg-driven launch: ") + hipGetErrorString(e));
     parity = tgt & 1;
@@ -765,6 +878,41 @@ od_status Grid::io(void* host, size_t bytes, bool to_host) {
             if (e == hipSuccess) e = hipStreamSynchronize(st);
             if (e != hipSuccess) return fail(OD_EHIP, std::string("scatter: ") + hipGetErrorString(e));
         }
+    }
+    return OD_OK;
+}
+
+od_status Grid::block_io(int32_t b, void* host, size_t bytes, bool to_host) {
+    if (b < 0 || b >= (int32_t)plan.chares.size()) return fail(OD_EINVAL, "block index out of range");
+    const BlockDev& B = blocks_h[(size_t)b];
+    const size_t row = (size_t)B.ex * s, need = row * B.ey * B.ez;
+    if (bytes < need) return fail(OD_EINVAL, "buffer of " + std::to_string(bytes) + " bytes, need " + std::to_string(need));
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("sync: ") + hipGetErrorString(e));
+    const size_t pitch = (size_t)B.py * s, store = (size_t)B.pz * B.ez * s;
+    od_status os = ensure_pinned(store);
+    if (os != OD_OK) return os;
+    char* dev = base + (size_t)(parity ? B.off[1] : B.off[0]) * s;
+    char* h = static_cast<char*>(host);
+    char* pin = static_cast<char*>(pinned);
+    if (to_host) {
+        e = hipMemcpyAsync(pin, dev, store, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return fail(OD_EHIP, std::string("read block: ") + hipGetErrorString(e));
+        for (int32_t z = 0; z < B.ez; ++z)
+            for (int32_t y = 0; y < B.ey; ++y)
+                std::memcpy(h + ((size_t)z * B.ey + y) * row, pin + (size_t)z * B.pz * s + (size_t)y * pitch, row);
+    } else {
+        e = hipMemcpyAsync(pin, dev, store, hipMemcpyDeviceToHost, st);   // keep the row padding
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return fail(OD_EHIP, std::string("write block: ") + hipGetErrorString(e));
+        for (int32_t z = 0; z < B.ez; ++z)
+            for (int32_t y = 0; y < B.ey; ++y)
+                std::memcpy(pin + (size_t)z * B.pz * s + (size_t)y * pitch, h + ((size_t)z * B.ey + y) * row, row);
+        e = hipMemcpyAsync(dev, pin, store, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return fail(OD_EHIP, std::string("write block: ") + hipGetErrorString(e));
+        faces_packed = false;
     }
     return OD_OK;
 }

@@ -147,9 +147,16 @@ od_status od_iterations(od_grid* g, int64_t* iters) {
     return OD_OK;
 }
 
+#define OD_NEED_UNIFORM(g)                                                                           \
+    do {                                                                                             \
+        if ((g)->g.plan.multires)                                                                    \
+            return fail(OD_EINVAL, "multi-resolution grid: use od_read_block / od_write_block");     \
+    } while (0)
+
 od_status od_read(od_grid* g, void* host_dst, size_t bytes) {
     OD_GUARD_BEGIN
     OD_NEED_DEVICE(g);
+    OD_NEED_UNIFORM(g);
     if (!host_dst) return fail(OD_EINVAL, "NULL argument");
     return g->g.io(host_dst, bytes, true);
     OD_GUARD_END
@@ -158,6 +165,7 @@ od_status od_read(od_grid* g, void* host_dst, size_t bytes) {
 od_status od_write(od_grid* g, const void* host_src, size_t bytes) {
     OD_GUARD_BEGIN
     OD_NEED_DEVICE(g);
+    OD_NEED_UNIFORM(g);
     if (!host_src) return fail(OD_EINVAL, "NULL argument");
     return g->g.io(const_cast<void*>(host_src), bytes, false);
     OD_GUARD_END
@@ -166,8 +174,33 @@ od_status od_write(od_grid* g, const void* host_src, size_t bytes) {
 od_status od_read_points(od_grid* g, const int64_t* idx, int64_t count, void* host_dst) {
     OD_GUARD_BEGIN
     OD_NEED_DEVICE(g);
+    OD_NEED_UNIFORM(g);
     if (count > 0 && (!idx || !host_dst)) return fail(OD_EINVAL, "NULL argument");
     return g->g.read_points(idx, count, host_dst);
+    OD_GUARD_END
+}
+
+od_status od_block_cells(od_grid* g, int32_t b, int32_t cells[3]) {
+    if (!g || !cells) return fail(OD_EINVAL, "NULL argument");
+    const Grid& G = g->g;
+    if (b < 0 || b >= (int32_t)G.plan.chares.size()) return fail(OD_EINVAL, "block index out of range");
+    for (int d = 0; d < 3; ++d) cells[d] = G.plan.chares[(size_t)b].e[d];
+    return OD_OK;
+}
+
+od_status od_read_block(od_grid* g, int32_t b, void* host_dst, size_t bytes) {
+    OD_GUARD_BEGIN
+    OD_NEED_DEVICE(g);
+    if (!host_dst) return fail(OD_EINVAL, "NULL argument");
+    return g->g.block_io(b, host_dst, bytes, true);
+    OD_GUARD_END
+}
+
+od_status od_write_block(od_grid* g, int32_t b, const void* host_src, size_t bytes) {
+    OD_GUARD_BEGIN
+    OD_NEED_DEVICE(g);
+    if (!host_src) return fail(OD_EINVAL, "NULL argument");
+    return g->g.block_io(b, const_cast<void*>(host_src), bytes, false);
     OD_GUARD_END
 }
 
@@ -196,7 +229,7 @@ od_status od_tile_info_get(od_grid* g, int32_t t, od_tile_info* out) {
         out->extent[d] = th.e[d];
     }
     for (int f = 0; f < 6; ++f) {
-        out->src_kind[f] = th.kind[f] == 1 ? 1 : 0;
+        out->src_kind[f] = th.kind[f] == 1 ? 1 : (th.kind[f] == 3 ? 2 : 0);
         out->src[f] = th.kind[f] == 2 ? th.chare : th.src[f];
         for (int d = 0; d < 3; ++d) out->src_origin[f][d] = th.g[f][d];
     }
@@ -207,9 +240,10 @@ od_status od_chare_get(od_grid* g, int32_t c, od_block* out) {
     if (!g || !out) return fail(OD_EINVAL, "NULL argument");
     const Grid& G = g->g;
     if (c < 0 || c >= (int32_t)G.plan.chares.size()) return fail(OD_EINVAL, "chare index out of range");
+    const od::Chare& ch = G.plan.chares[(size_t)c];
     for (int d = 0; d < 3; ++d) {
-        out->origin[d] = G.plan.chares[(size_t)c].o[d];
-        out->extent[d] = G.plan.chares[(size_t)c].e[d];
+        out->origin[d] = ch.u[d];
+        out->extent[d] = ch.e[d] * ch.h;
     }
     return OD_OK;
 }

@@ -53,9 +53,11 @@ static_assert(sizeof(TileDev) == 128, "TileDev layout");
 // Host-side plan of one grid.
 
 struct Chare {
-    int32_t o[3];           // global origin
-    int32_t e[3];           // extent
+    int32_t o[3];           // origin in cells of the chare's own size (= grid units when h == 1)
+    int32_t e[3];           // extent in cells
     int32_t nb[6];          // regular decompositions: neighbour chare per face, -1 = domain boundary
+    int32_t h = 1;          // cell edge in grid units (multi-resolution blocks)
+    int32_t u[3];           // origin in grid units (= o * h)
 };
 
 struct TileHost {
@@ -63,7 +65,9 @@ struct TileHost {
     int32_t o[3];           // origin within chare
     int32_t e[3];           // extent
     // per face: kind 0 = chare (src = chare id), 1 = Dirichlet face of the
-    // domain (src = face id), 2 = own chare; global coords of the slab start
+    // domain (src = face id), 2 = own chare, 3 = resolution-change ghost
+    // buffer of the chare's face (src = face id); g = slab start in cells of
+    // the chare's size
     int32_t kind[6], src[6], g[6][3];
 };
 
@@ -82,6 +86,10 @@ struct Plan {
     bool xcd_order = true;               // group tiles per XCD (else plain spatial order)
     int64_t interior = 0;
     int64_t halo_cells = 0;              // ghost cells read from other chares per sweep
+    // multi-resolution blocks
+    bool multires = false;               // some chare has h != 1
+    std::vector<uint8_t> mr;             // per (chare, face): the face borders another cell size
+    int32_t gcell = 0;                   // gcd of chare origins / extents in own cells (tile splits)
 };
 
 // Build the decomposition (chares + owner lookup).  Returns "" or an error.

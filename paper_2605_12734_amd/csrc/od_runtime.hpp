@@ -22,6 +22,7 @@ struct Layout {
     size_t blocks = 0, tiles = 0, cidx[3] = {0, 0, 0}, owner = 0, corigin = 0, dir_pb = 0;
     size_t pb_face = 0, pb_block = 0, bc = 0, res = 0, bar = 0, err = 0, done = 0, target = 0;
     size_t dep_ptr = 0, dep_idx = 0, extra = 0, field_end = 0, total = 0;
+    size_t ccell = 0, segs = 0, wgxcd = 0, xpub = 0;
 };
 
 // Per-chare baseline message buffers (byte offsets): outgoing face messages
@@ -41,6 +42,9 @@ struct Grid {
     std::vector<TileDev> tiles_h;
     std::vector<int32_t> cpy;        // row pitch per chare
     std::vector<int32_t> dir_pb, ghost_pb, pb_face, pb_block;
+    std::vector<int32_t> amr_pb;     // multi-resolution ghost buffer of (chare, face), -1 if none
+    std::vector<FillSeg> segs_h;     // multi-resolution ghost fill rectangles
+    int64_t fill_total = 0;          // ghost cells filled per iteration
     std::vector<int32_t> dep_ptr, dep_idx;
     std::vector<uint8_t> extra_h;
     int32_t extra_period = 1;
@@ -88,6 +92,7 @@ struct Grid {
     od_status residual(double* r);
     od_status io(void* host, size_t bytes, bool to_host);
     od_status read_points(const int64_t* idx, int64_t count, void* host_dst);
+    od_status block_io(int32_t b, void* host, size_t bytes, bool to_host);
     od_status retile(const int32_t tile[3]);
 };
 

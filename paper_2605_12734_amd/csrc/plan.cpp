@@ -54,6 +54,50 @@ int64_t gcd64(int64_t a, int64_t b) {
 
 }  // namespace
 
+// Every chare face of a multi-resolution plan that borders a block of
+// another cell size is marked in p.mr; across such a face a finer
+// neighbour must align to the chare's cells (each averaged patch lies in one
+// block).  Uses the owner grid, so it runs after it is built.
+std::string plan_resolution_faces(Plan& p) {
+    const int32_t C = (int32_t)p.chares.size();
+    p.mr.assign((size_t)C * 6, 0);
+    const int64_t g = p.gran;
+    for (int32_t ci = 0; ci < C; ++ci) {
+        const Chare& c = p.chares[(size_t)ci];
+        for (int f = 0; f < 6; ++f) {
+            const int d = f / 2;
+            const int64_t nrm = (f % 2) ? (int64_t)c.u[d] + (int64_t)c.e[d] * c.h : (int64_t)c.u[d] - 1;
+            if (nrm < 0 || nrm >= p.n[d]) continue;
+            int64_t lo[3], hi[3];
+            for (int q = 0; q < 3; ++q) {
+                lo[q] = c.u[q];
+                hi[q] = (int64_t)c.u[q] + (int64_t)c.e[q] * c.h;
+            }
+            lo[d] = nrm;
+            hi[d] = nrm + 1;
+            bool differs = false;
+            for (int64_t z = lo[2] / g * g; z < hi[2]; z += g)
+                for (int64_t y = lo[1] / g * g; y < hi[1]; y += g)
+                    for (int64_t x = lo[0] / g * g; x < hi[0]; x += g) {
+                        const int32_t nb = plan_owner(p, std::max(x, lo[0]), std::max(y, lo[1]), std::max(z, lo[2]));
+                        const Chare& N = p.chares[(size_t)nb];
+                        if (N.h == c.h) continue;
+                        differs = true;
+                        if (N.h > c.h) continue;
+                        for (int q = 0; q < 3; ++q) {
+                            if (q == d) continue;
+                            const int64_t a = N.u[q], b = (int64_t)N.u[q] + (int64_t)N.e[q] * N.h;
+                            if ((a > lo[q] && a % c.h != 0) || (b < hi[q] && b % c.h != 0))
+                                return fmt("block %lld: a finer neighbour across face %lld does not align to its cells",
+                                           ci, f);
+                        }
+                    }
+            if (differs) p.mr[(size_t)ci * 6 + f] = 1;
+        }
+    }
+    return "";
+}
+
 std::string plan_decompose(const od_config& cfg, Plan& p) {
     for (int d = 0; d < 3; ++d) {
         if (cfg.n[d] < 1 || cfg.n[d] > (1 << 20)) return fmt("n[%lld] = %lld out of range [1, 2^20]", d, cfg.n[d]);
@@ -66,6 +110,9 @@ std::string plan_decompose(const od_config& cfg, Plan& p) {
     p.chares.clear();
     p.owner.clear();
 
+    p.multires = false;
+    p.mr.clear();
+    if (cfg.block_cell != nullptr && cfg.blocks == nullptr) return "block_cell needs explicit blocks";
     if (cfg.blocks != nullptr || cfg.nblocks > 0) {
         if (cfg.blocks == nullptr || cfg.nblocks < 1) return "blocks/nblocks inconsistent";
         p.regular = false;
@@ -81,6 +128,13 @@ std::string plan_decompose(const od_config& cfg, Plan& p) {
                 g = gcd64(g, B.extent[d]);
             }
             vol += (int64_t)B.extent[0] * B.extent[1] * B.extent[2];
+            const int32_t h = cfg.block_cell ? cfg.block_cell[b] : 1;
+            if (h < 1 || h > 1024 || (h & (h - 1)) != 0)
+                return fmt("block %lld: cell edge %lld is not a power of two in [1, 1024]", b, h);
+            for (int d = 0; d < 3; ++d)
+                if (B.origin[d] % h != 0 || B.extent[d] % h != 0)
+                    return fmt("block %lld: origin and extent must be multiples of its cell edge %lld", b, h);
+            if (h != 1) p.multires = true;
         }
         if (vol != p.interior) return fmt("blocks cover %lld cells, the domain has %lld", vol, p.interior);
         p.gran = (int32_t)g;
@@ -88,13 +142,17 @@ std::string plan_decompose(const od_config& cfg, Plan& p) {
         int64_t cells = p.og[0] * p.og[1] * p.og[2];
         if (cells > (int64_t(1) << 26)) return fmt("block granularity %lld too fine (owner grid %lld cells)", g, cells);
         p.owner.assign((size_t)cells, -1);
+        p.interior = 0;
         for (int32_t b = 0; b < cfg.nblocks; ++b) {
             const od_block& B = cfg.blocks[b];
             Chare c{};
+            c.h = cfg.block_cell ? cfg.block_cell[b] : 1;
             for (int d = 0; d < 3; ++d) {
-                c.o[d] = B.origin[d];
-                c.e[d] = B.extent[d];
+                c.u[d] = B.origin[d];
+                c.o[d] = B.origin[d] / c.h;
+                c.e[d] = B.extent[d] / c.h;
             }
+            p.interior += (int64_t)c.e[0] * c.e[1] * c.e[2];
             for (int f = 0; f < 6; ++f) c.nb[f] = -2;   // not a regular neighbour table
             p.chares.push_back(c);
             for (int64_t z = B.origin[2] / g; z < (B.origin[2] + B.extent[2]) / g; ++z)
@@ -104,6 +162,13 @@ std::string plan_decompose(const od_config& cfg, Plan& p) {
                         if (o != -1) return fmt("blocks %lld and %lld overlap", o, b);
                         o = b;
                     }
+        }
+        p.gcell = 0;
+        for (const Chare& c : p.chares)
+            for (int d = 0; d < 3; ++d) p.gcell = (int32_t)gcd64(gcd64(p.gcell, c.o[d]), c.e[d]);
+        if (p.multires) {
+            std::string err = plan_resolution_faces(p);
+            if (!err.empty()) return err;
         }
         return "";
     }
@@ -152,9 +217,11 @@ std::string plan_decompose(const od_config& cfg, Plan& p) {
             for (int32_t cx = 0; cx < k[0]; ++cx) {
                 Chare& c = p.chares[(size_t)((cz * k[1] + cy) * k[0] + cx)];
                 int32_t ci[3] = {cx, cy, cz};
+                c.h = 1;
                 for (int d = 0; d < 3; ++d) {
                     c.o[d] = p.split[d][ci[d]];
                     c.e[d] = p.split[d][ci[d] + 1] - c.o[d];
+                    c.u[d] = c.o[d];
                 }
                 for (int f = 0; f < 6; ++f) {
                     int d = f / 2, s = (f % 2) ? 1 : -1;
@@ -211,11 +278,13 @@ struct Box {
     int64_t lo[3], hi[3];
 };
 
+// Ghost slab of a tile face in grid units: the tile's tangential extent,
+// one unit layer across the face.
 Box ghost_slab(const Chare& c, const int32_t o[3], const int32_t e[3], int f) {
     Box b;
     for (int d = 0; d < 3; ++d) {
-        b.lo[d] = (int64_t)c.o[d] + o[d];
-        b.hi[d] = b.lo[d] + e[d];
+        b.lo[d] = (int64_t)c.u[d] + (int64_t)o[d] * c.h;
+        b.hi[d] = b.lo[d] + (int64_t)e[d] * c.h;
     }
     int d = f / 2;
     if (f % 2 == 0) {
@@ -296,10 +365,13 @@ std::string plan_tiles(Plan& p) {
             for (int f = 0; f < 6 && !split; ++f) {
                 Box b = ghost_slab(c, t.o, t.e, f);
                 int d = f / 2;
-                int64_t lo_local = b.lo[d] - c.o[d];
+                int64_t lo_local = (f % 2) ? (int64_t)t.o[d] + t.e[d] : (int64_t)t.o[d] - 1;
                 if (lo_local >= 0 && lo_local < c.e[d]) {
                     t.kind[f] = 2;
                     t.src[f] = ci;
+                } else if (p.multires && p.mr[(size_t)ci * 6 + f]) {
+                    t.kind[f] = 3;
+                    t.src[f] = f;
                 } else {
                     int sd = -1;
                     int64_t sat = 0;
@@ -311,8 +383,8 @@ std::string plan_tiles(Plan& p) {
                         t.kind[f] = 0;
                         t.src[f] = ow;
                     } else {
-                        // split the tile at global coordinate sat along sd
-                        int64_t cut = sat - c.o[sd] - t.o[sd];
+                        // split the tile at grid coordinate sat along sd
+                        int64_t cut = (sat - c.u[sd]) / c.h - t.o[sd];
                         if (cut <= 0 || cut >= t.e[sd]) return "internal error: bad tile split";
                         TileHost a = t, bb = t;
                         a.e[sd] = (int32_t)cut;
@@ -323,11 +395,11 @@ std::string plan_tiles(Plan& p) {
                         split = true;
                     }
                 }
-                for (int q = 0; q < 3; ++q) t.g[f][q] = (int32_t)b.lo[q];
+                for (int q = 0; q < 3; ++q) t.g[f][q] = (int32_t)(b.lo[q] >= 0 ? b.lo[q] / c.h : -1);
             }
             if (split) continue;
             for (int f = 0; f < 6; ++f)
-                if (t.kind[f] == 0) p.halo_cells += (int64_t)t.e[0] * t.e[1] * t.e[2] / t.e[f / 2];
+                if (t.kind[f] == 0 || t.kind[f] == 3) p.halo_cells += (int64_t)t.e[0] * t.e[1] * t.e[2] / t.e[f / 2];
             out.push_back(t);
         }
     }
@@ -335,7 +407,10 @@ std::string plan_tiles(Plan& p) {
     // that launch index w (dispatched to XCD w % 8) takes group w % 8.
     std::vector<size_t> idx(out.size());
     std::iota(idx.begin(), idx.end(), 0);
-    auto gkey = [&](const TileHost& t, int d) { return (int64_t)p.chares[(size_t)t.chare].o[d] + t.o[d]; };
+    auto gkey = [&](const TileHost& t, int d) {
+        const Chare& c = p.chares[(size_t)t.chare];
+        return (int64_t)c.u[d] + (int64_t)t.o[d] * c.h;
+    };
     std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
         const TileHost& A = out[a];
         const TileHost& B = out[b];

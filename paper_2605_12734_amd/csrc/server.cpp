@@ -90,7 +90,8 @@ struct Server {
     // control region (byte offsets from arena)
     size_t c_blocks = 0, c_tiles = 0, c_done = 0, c_dep_ptr = 0, c_dep_idx = 0, c_tile_solve = 0;
     size_t c_target = 0, c_final = 0, c_gate = 0, c_count = 0, c_res = 0, c_ce = 0, c_tol = 0, c_ntiles = 0;
-    size_t c_dtype = 0, c_list = 0, c_err = 0, data_begin = 0;
+    size_t c_dtype = 0, c_list = 0, c_err = 0, c_yield = 0, c_wgxcd = 0, c_xpub = 0, c_tpos = 0, c_bar = 0;
+    size_t data_begin = 0;
     // host-coherent completion records and the yield flag
     int32_t* h_done = nullptr;
     unsigned long long* h_res = nullptr;
@@ -245,6 +246,7 @@ void Server::retire(Request& R) {
 
 void Server::run() {
     const int64_t wait_ticks = device_wait_ticks(20.0);
+    const int64_t yield_poll_ticks = device_wait_ticks(20e-6);   // host flag polled every 20 us
     hipEvent_t ev = nullptr;
     if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
         std::lock_guard<std::mutex> lk(mu);
@@ -252,6 +254,7 @@ void Server::run() {
         return;
     }
     std::vector<int32_t> list;
+    std::vector<int32_t> tpos((size_t)max_slots * kTileStride, -1);
     for (;;) {
         std::vector<Request*> admitted;
         {
@@ -309,7 +312,12 @@ void Server::run() {
         // tile list: solves back to back; each solve's tiles keep their own
         // XCD-interleaved order, so a solve's XCD groups stay together
         hipError_t e = hipMemcpyAsync(arena + c_list, list.data(), list.size() * 4, hipMemcpyHostToDevice, st);
+        // launch position of every tile in this epoch (XCD-aware publication)
+        std::fill(tpos.begin(), tpos.end(), -1);
+        for (size_t q = 0; q < list.size(); ++q) tpos[(size_t)list[q]] = (int32_t)q;
+        if (e == hipSuccess) e = hipMemcpyAsync(arena + c_tpos, tpos.data(), tpos.size() * 4, hipMemcpyHostToDevice, st);
         __atomic_store_n(h_yield, 0, __ATOMIC_RELEASE);
+        if (e == hipSuccess) e = hipMemsetAsync(arena + c_yield, 0, 4, st);
         MsgArgs a{};
         a.tile_list = reinterpret_cast<const int32_t*>(arena + c_list);
         a.solve_dtype = reinterpret_cast<const int32_t*>(arena + c_dtype);
@@ -335,7 +343,13 @@ void Server::run() {
         a.host_done = h_done;
         a.host_res = h_res;
         a.yield_flag = h_yield;
-        int grid = std::min<int>(grid_cap, (int)list.size());
+        a.yield_dev = reinterpret_cast<int32_t*>(arena + c_yield);
+        a.yield_poll_ticks = yield_poll_ticks;
+        a.wg_xcd = reinterpret_cast<int32_t*>(arena + c_wgxcd);
+        a.xpub = reinterpret_cast<uint8_t*>(arena + c_xpub);
+        a.tile_pos = reinterpret_cast<const int32_t*>(arena + c_tpos);
+        a.bar = reinterpret_cast<unsigned int*>(arena + c_bar);
+        int grid = std::min<int>(std::min<int>(grid_cap, kMaxLaunchWgs), (int)list.size());
         if (grid >= kNumXcd) grid -= grid % kNumXcd;
         const double t_epoch = now_s();
         if (e == hipSuccess) e = launch_serve(st, grid, a);
@@ -429,6 +443,11 @@ size_t control_layout(Server& S, int32_t max_slots) {
     S.c_dtype = take(ms * 4);
     S.c_list = take(ms * kTileStride * 4);
     S.c_err = take(16);
+    S.c_yield = take(16);
+    S.c_wgxcd = take((size_t)kMaxLaunchWgs * 4);
+    S.c_xpub = take(ms * kTileStride);
+    S.c_tpos = take(ms * kTileStride * 4);
+    S.c_bar = take(16);
     S.data_begin = align_up(o, kAlign);
     return S.data_begin;
 }
@@ -520,6 +539,7 @@ od_status od_server_create(void* hip_stream, void* dev_arena, size_t arena_bytes
         S.staging_bytes = (size_t)64 << 20;
         if (e == hipSuccess) e = hipHostMalloc(&S.staging, S.staging_bytes, hipHostMallocDefault);
         if (e == hipSuccess) e = hipMemsetAsync(S.arena + S.c_err, 0, 16, S.st);
+        if (e == hipSuccess) e = hipMemsetAsync(S.arena + S.c_bar, 0, 16, S.st);
         if (e == hipSuccess) e = hipStreamSynchronize(S.st);
         if (e != hipSuccess) {
             if (S.h_done) hipHostFree(S.h_done);
