@@ -248,35 +248,37 @@ def jacobi2d_leg(n=32768, iters=100, odfs=(1, 4, 16, 64, 256, 1024)):
     return rows
 
 
-def launch_leg(totals=(1 << 18, 1 << 20), kernels=(1, 2, 4, 8, 16, 32, 64, 256, 1024), work=20000,
+def launch_leg(totals=(1 << 18, 1 << 20), kernels=(1, 2, 4, 8, 16, 32, 64, 256, 1024), works=(0, 20000),
                rate_threads=(1, 2, 4), rate_chares=(1, 2, 4)):
     """Launch-cost microbenchmarks: the same work split over more kernels,
-    all released at once from a stream gate (device makespan vs ODF); and
-    kernels launched per second from host threads x chares per thread."""
+    all released at once from a stream gate (device makespan vs ODF; work 0
+    isolates the per-kernel device cost); and kernels launched per second
+    from host threads x chares per thread."""
     import paper_2605_12734_amd as od
 
     overlap = []
-    for total in totals:
-        base = None
-        for nk in kernels:
-            best = None
-            for _ in range(3):
-                r = od.launch_overlap(total, nk, work=work)
-                best = r if best is None or r["makespan_us"] < best["makespan_us"] else best
-            base = base or best["makespan_us"]
-            row = {"threads": total, "kernels": nk, "streams": best["nstreams"],
-                   "makespan_us": round(best["makespan_us"], 1), "host_us": round(best["host_us"], 1),
-                   "enqueue_us": round(best["enqueue_us"], 1),
-                   "makespan_vs_1_kernel": round(best["makespan_us"] / base, 3)}
-            log("launch overlap:", row)
-            overlap.append(row)
+    for work in works:
+        for total in totals:
+            base = None
+            for nk in kernels:
+                best = None
+                for _ in range(3):
+                    r = od.launch_overlap(total, nk, work=work)
+                    best = r if best is None or r["makespan_us"] < best["makespan_us"] else best
+                base = base or best["makespan_us"]
+                row = {"work": work, "threads": total, "kernels": nk, "streams": best["nstreams"],
+                       "makespan_us": round(best["makespan_us"], 1), "host_us": round(best["host_us"], 1),
+                       "enqueue_us": round(best["enqueue_us"], 1),
+                       "makespan_vs_1_kernel": round(best["makespan_us"] / base, 3)}
+                log("launch overlap:", row)
+                overlap.append(row)
     rate = []
     for t in rate_threads:
         for c in rate_chares:
             n, kps = od.launch_rate(t, c, seconds=0.5)
             rate.append({"host_threads": t, "chares_per_thread": c, "kernels_per_s": round(kps)})
             log("launch rate:", rate[-1])
-    return {"work_per_thread": work, "overlap": overlap, "rate": rate}
+    return {"overlap": overlap, "rate": rate}
 
 
 def serving_leg(rates=(10, 30, 100, 300, 1000, 2000), count=64, arena_gb=200.0):

@@ -340,7 +340,7 @@ __global__ void __launch_bounds__((TX / V16<T>::N) * TY)
 k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDev* __restrict__ tiles,
              int32_t ntiles, int parity, int64_t iters, unsigned long long* __restrict__ res, int32_t nres,
              unsigned int* bar, unsigned int* err, const uint8_t* __restrict__ extra, int32_t extra_period,
-             int32_t nchares, int64_t iter_base, int64_t wait_ticks, int hints) {
+             int32_t nchares, int64_t iter_base, int64_t wait_ticks, int hints, int dyn) {
     using S = SW<T, TX, TY>;
     __shared__ T lds[S::LDS];
     __shared__ T red[S::NT / 64];
@@ -356,17 +356,22 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
         const uint8_t* ex = extra ? extra + (size_t)((iter_base + it) % extra_period) * nchares : nullptr;
         T r = 0;
         int slot = -1;
-        // tiles of this workgroup's XCD group, taken one at a time from the
-        // group's counter (the next index is requested while a tile sweeps)
+        // dyn: tiles of this workgroup's XCD group, taken one at a time from
+        // the group's counter (the next index is requested while a tile
+        // sweeps); otherwise the fixed stride w, w + G, w + 2G, ...
         unsigned int* ctr = &bar[8 + 8 * (int)(it & 1) + xg];
-        if (threadIdx.x == 0) s_idx = (int32_t)__hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        int32_t idx = s_idx;
+        if (dyn) {
+            if (threadIdx.x == 0)
+                s_idx = (int32_t)__hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+        }
+        int32_t idx = dyn ? s_idx : (int32_t)blockIdx.x;
         for (;;) {
-            const int32_t ti = xg + ng * idx;
+            const int32_t ti = dyn ? xg + ng * idx : idx;
             if (ti >= ntiles) break;
-            int32_t nxt = 0;
-            if (threadIdx.x == 0) nxt = (int32_t)__hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            int32_t nxt = idx + (int32_t)gridDim.x;
+            if (dyn && threadIdx.x == 0)
+                nxt = (int32_t)__hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const TileDev& t = tiles[ti];
             const int reps = 1 + (ex ? (int)ex[t.blk] : 0);
             T rr = 0;
@@ -377,10 +382,13 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
             }
             slot = t.rslot;
             r = rr > r ? rr : r;
-            __syncthreads();
-            if (threadIdx.x == 0) s_idx = nxt;
-            __syncthreads();
-            idx = s_idx;
+            if (dyn) {
+                __syncthreads();
+                if (threadIdx.x == 0) s_idx = nxt;
+                __syncthreads();
+                nxt = s_idx;
+            }
+            idx = nxt;
         }
         if (slot >= 0) wg_residual<T, S::NT>(r, &res[2 * slot + (p ^ 1)], red);
         if (it + 1 < iters) {
@@ -432,6 +440,7 @@ __device__ __forceinline__ bool mark_cross_xcd(const MsgArgs& a, int32_t nown) {
     for (int32_t j = threadIdx.x; j < nown; j += NT) {
         const int32_t pos = w + j * G;
         const int32_t ti = a.tile_list ? a.tile_list[pos] : pos;
+        if (ti < 0) continue;   // padding entry of a serving launch
         uint8_t cross = 0;
         const int32_t q1 = a.dep_ptr[ti + 1];
         for (int32_t q = a.dep_ptr[ti]; q < q1; ++q) {
@@ -468,6 +477,8 @@ __device__ __forceinline__ void msg_loop(const MsgArgs& a, SweepFn sweep, double
                     j = cursor + k < nown ? cursor + k : cursor + k - nown;
                     const int32_t li = w + j * G;
                     ti = a.tile_list ? a.tile_list[li] : li;
+                }
+                if (k < nown && ti >= 0) {   // negative: padding entry of a serving launch
                     const int32_t sv = a.tile_solve ? a.tile_solve[ti] : 0;
                     d = ld_rlx(&a.done[ti]);
                     int32_t tgt = ld_rlx(&a.target[sv]);
@@ -634,10 +645,10 @@ __global__ void __launch_bounds__((TX8 / 2) * TY8) k_serve(MsgArgs a) {
 
 #define OD_VARIANTS_F64(X) X(double, 32, 4) X(double, 32, 8) X(double, 32, 16) X(double, 32, 32) \
     X(double, 64, 4) X(double, 64, 8) X(double, 64, 16) X(double, 16, 8) X(double, 16, 16) X(double, 128, 4) \
-    X(double, 128, 1) X(double, 256, 1)
+    X(double, 128, 1) X(double, 256, 1) X(double, 512, 1)
 #define OD_VARIANTS_F32(X) X(float, 32, 8) X(float, 32, 16) X(float, 32, 32) X(float, 64, 4) \
     X(float, 64, 8) X(float, 64, 16) X(float, 128, 4) X(float, 128, 8) X(float, 16, 16) X(float, 256, 1) \
-    X(float, 512, 1)
+    X(float, 512, 1) X(float, 1024, 1)
 
 #define OD_VT_ENTRY(T, TX, TY) {TX, TY, SW<T, TX, TY>::NT},
 static const SweepVariant kVariants64[] = {OD_VARIANTS_F64(OD_VT_ENTRY)};
@@ -711,14 +722,14 @@ hipError_t launch_persistent(int dtype_bytes, int tx, int ty, hipStream_t st, in
                              const BlockDev* blocks, const TileDev* tiles, int32_t ntiles, int parity,
                              int64_t iters, unsigned long long* res, int32_t nres, unsigned int* bar,
                              unsigned int* err, const uint8_t* extra, int32_t extra_period, int32_t nchares,
-                             int64_t iter_base, int hints) {
+                             int64_t iter_base, int hints, int dyn) {
     if (iters <= 0) return hipSuccess;
     int64_t wait_ticks = device_wait_ticks();
 #define OD_LAUNCH(T, TX, TY)                                                                          \
     if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                      \
         T* ar = reinterpret_cast<T*>(arena);                                                          \
         void* args[] = {&ar, &blocks, &tiles, &ntiles, &parity, &iters, &res, &nres, &bar, &err,      \
-                        &extra, &extra_period, &nchares, &iter_base, &wait_ticks, &hints};                   \
+                        &extra, &extra_period, &nchares, &iter_base, &wait_ticks, &hints, &dyn};             \
         return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_persistent<T, TX, TY>),    \
                                           dim3(grid), dim3(SW<T, TX, TY>::NT), args, 0, st);          \
     }

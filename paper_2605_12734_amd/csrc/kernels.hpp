@@ -47,8 +47,9 @@ hipError_t launch_sweep(int dtype_bytes, int tx, int ty, hipStream_t st, void* a
                         const uint8_t* extra, int hints);
 
 // Persistent cooperative sweep: all `iters` iterations in one launch with a
-// device-wide barrier between them.  Workgroups take tiles dynamically from
-// per-XCD-group counters (load balance under imbalance and uneven blocks).
+// device-wide barrier between them.  dyn != 0: workgroups take tiles from
+// per-XCD-group counters (load balance under imbalance and uneven blocks);
+// dyn == 0: workgroup w takes tiles w, w + grid, ... (uniform work).
 // `bar` = 32 zeroed uint32: [0] arrivals, [1] generation, [2] exits,
 // [8..24) tile counters (8 XCD groups x 2 step parities); the kernel leaves
 // them zeroed.  `err` = error flag.  `extra` (may be null): table of
@@ -58,7 +59,7 @@ hipError_t launch_persistent(int dtype_bytes, int tx, int ty, hipStream_t st, in
                              int32_t ntiles, int parity, int64_t iters,
                              unsigned long long* res, int32_t nres, unsigned int* bar,
                              unsigned int* err, const uint8_t* extra, int32_t extra_period,
-                             int32_t nchares, int64_t iter_base, int hints);
+                             int32_t nchares, int64_t iter_base, int hints, int dyn);
 // Wall-clock ticks in `seconds` (bound of every device-side wait).
 int64_t device_wait_ticks(double seconds = 10.0);
 // Max co-resident workgroups of the persistent / message-driven kernels.
@@ -118,7 +119,7 @@ constexpr int kMaxLaunchWgs = 8192;   // bound of a cooperative launch's workgro
 // Serving kernel: fp64 tiles of (kServeTx8, kServeTy8) and fp32 tiles of
 // (kServeTx4, kServeTy4) columns, same thread count, one cooperative launch.
 #ifndef OD_SERVE_TY8
-#define OD_SERVE_TY8 8     // rows of an fp64 serving tile (fp32 tiles have twice as many)
+#define OD_SERVE_TY8 16    // rows of an fp64 serving tile (fp32 tiles have twice as many)
 #endif
 constexpr int kServeTx8 = 32, kServeTy8 = OD_SERVE_TY8, kServeTx4 = 32, kServeTy4 = 2 * OD_SERVE_TY8;
 int serve_max_grid();

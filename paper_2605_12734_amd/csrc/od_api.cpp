@@ -237,6 +237,9 @@ std::string build_layout(const od_config& cfg, Grid& G) {
     }
     plan_default_tile(cfg, p);
     p.xcd_order = (cfg.hints & 2) == 0;
+    // message-driven tiles publish to other XCDs only across group
+    // boundaries: compact boxes keep that boundary small
+    p.xcd_boxes = cfg.exec == OD_MSGDRIVEN;
     if (!sweep_variant_ok(G.s, p.tile[0], p.tile[1]))
         return "tile (" + std::to_string(p.tile[0]) + "," + std::to_string(p.tile[1]) + ") is not a compiled variant";
     err = plan_tiles(p);
@@ -651,7 +654,8 @@ od_status Grid::persistent_run(int64_t n) {
                                      parity, n, res_ptr(), 1, reinterpret_cast<unsigned int*>(base + L.bar),
                                      reinterpret_cast<unsigned int*>(base + L.err),
                                      extra_h.empty() ? nullptr : reinterpret_cast<const uint8_t*>(base + L.extra),
-                                     extra_period, (int32_t)plan.chares.size(), iters, mode());
+                                     extra_period, (int32_t)plan.chares.size(), iters, mode(),
+                                     (!extra_h.empty() || !plan.regular) ? 1 : 0);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
     parity ^= (int)(n & 1);
     iters += n;

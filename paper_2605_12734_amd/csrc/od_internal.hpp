@@ -84,6 +84,7 @@ struct Plan {
     std::vector<TileHost> tiles;         // in launch order (XCD-interleaved)
     int32_t tile[3] = {0, 0, 0};
     bool xcd_order = true;               // group tiles per XCD (else plain spatial order)
+    bool xcd_boxes = false;              // XCD groups are 8 compact boxes (else 8 z-slabs)
     int64_t interior = 0;
     int64_t halo_cells = 0;              // ghost cells read from other chares per sweep
     // multi-resolution blocks

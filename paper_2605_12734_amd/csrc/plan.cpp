@@ -421,6 +421,57 @@ std::string plan_tiles(Plan& p) {
         return false;
     });
     size_t T = out.size();
+    if (p.xcd_order && p.xcd_boxes && T >= (size_t)kNumXcd) {
+        // three rounds of bisection by tile count, each along the longest
+        // extent of the part: 8 compact boxes (fewer tiles on a group
+        // boundary than 8 thin slabs); z-major order inside each box
+        std::vector<std::pair<size_t, size_t>> parts{{0, T}};
+        for (int round = 0; round < 3; ++round) {
+            std::vector<std::pair<size_t, size_t>> next;
+            for (auto [lo, hi] : parts) {
+                int64_t mn[3], mx[3];
+                for (int d = 0; d < 3; ++d) {
+                    mn[d] = INT64_MAX;
+                    mx[d] = INT64_MIN;
+                }
+                for (size_t q = lo; q < hi; ++q)
+                    for (int d = 0; d < 3; ++d) {
+                        mn[d] = std::min(mn[d], gkey(out[idx[q]], d));
+                        mx[d] = std::max(mx[d], gkey(out[idx[q]], d));
+                    }
+                int dim = 2;
+                for (int d = 1; d >= 0; --d)
+                    if (mx[d] - mn[d] > mx[dim] - mn[dim]) dim = d;
+                std::stable_sort(idx.begin() + (std::ptrdiff_t)lo, idx.begin() + (std::ptrdiff_t)hi,
+                                 [&](size_t a, size_t b) { return gkey(out[a], dim) < gkey(out[b], dim); });
+                const size_t mid = lo + (hi - lo) / 2;
+                next.push_back({lo, mid});
+                next.push_back({mid, hi});
+            }
+            parts.swap(next);
+        }
+        for (auto [lo, hi] : parts)
+            std::stable_sort(idx.begin() + (std::ptrdiff_t)lo, idx.begin() + (std::ptrdiff_t)hi, [&](size_t a, size_t b) {
+                for (int d = 2; d >= 0; --d) {
+                    int64_t ka = gkey(out[a], d), kb = gkey(out[b], d);
+                    if (ka != kb) return ka < kb;
+                }
+                return false;
+            });
+        // the j-th tile of box g goes to launch position 8j + g (boxes
+        // differ by at most one tile)
+        std::vector<TileHost> seq;
+        seq.reserve(T);
+        size_t maxc = 0;
+        for (auto [lo, hi] : parts) maxc = std::max(maxc, hi - lo);
+        for (size_t j = 0; j < maxc; ++j)
+            for (int g = 0; g < kNumXcd; ++g) {
+                const auto [lo, hi] = parts[(size_t)g];
+                if (lo + j < hi) seq.push_back(out[idx[lo + j]]);
+            }
+        p.tiles.swap(seq);
+        return "";
+    }
     size_t m = (T + kNumXcd - 1) / kNumXcd;
     std::vector<TileHost> ordered;
     ordered.reserve(T);

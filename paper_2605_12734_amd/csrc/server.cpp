@@ -306,15 +306,19 @@ void Server::run() {
                 active.push_back(&R);
                 const int32_t nt = (int32_t)R.grid->tiles_h.size();
                 for (int32_t i = 0; i < nt; ++i) list.push_back(s2 * kTileStride + i);
+                // keep every solve's XCD groups aligned to launch positions mod 8
+                while (list.size() % kNumXcd) list.push_back(-1);
             }
         }
         if (active.empty()) continue;
-        // tile list: solves back to back; each solve's tiles keep their own
-        // XCD-interleaved order, so a solve's XCD groups stay together
+        // tile list: solves back to back, each padded (-1) to a multiple of
+        // 8 entries; each solve's tiles keep their own XCD-interleaved order,
+        // so a solve's XCD groups stay together
         hipError_t e = hipMemcpyAsync(arena + c_list, list.data(), list.size() * 4, hipMemcpyHostToDevice, st);
         // launch position of every tile in this epoch (XCD-aware publication)
         std::fill(tpos.begin(), tpos.end(), -1);
-        for (size_t q = 0; q < list.size(); ++q) tpos[(size_t)list[q]] = (int32_t)q;
+        for (size_t q = 0; q < list.size(); ++q)
+            if (list[q] >= 0) tpos[(size_t)list[q]] = (int32_t)q;
         if (e == hipSuccess) e = hipMemcpyAsync(arena + c_tpos, tpos.data(), tpos.size() * 4, hipMemcpyHostToDevice, st);
         __atomic_store_n(h_yield, 0, __ATOMIC_RELEASE);
         if (e == hipSuccess) e = hipMemsetAsync(arena + c_yield, 0, 4, st);
@@ -441,11 +445,11 @@ size_t control_layout(Server& S, int32_t max_slots) {
     S.c_tol = take(ms * 8);
     S.c_ntiles = take(ms * 4);
     S.c_dtype = take(ms * 4);
-    S.c_list = take(ms * kTileStride * 4);
+    S.c_list = take(ms * (kTileStride + kNumXcd) * 4);
     S.c_err = take(16);
     S.c_yield = take(16);
     S.c_wgxcd = take((size_t)kMaxLaunchWgs * 4);
-    S.c_xpub = take(ms * kTileStride);
+    S.c_xpub = take(ms * (kTileStride + kNumXcd));
     S.c_tpos = take(ms * kTileStride * 4);
     S.c_bar = take(16);
     S.data_begin = align_up(o, kAlign);
