@@ -114,7 +114,10 @@ def grid_leg(n, odf, dtype, exec_, iters, steps, warmup, tile=None, **kw):
     return t
 
 
-def cpu_baseline(n, dtype, budget_s=12.0, max_iters=200):
+def cpu_baseline(n, dtype, budget_s=25.0, max_iters=200, chunk=10):
+    """The oracle on this host's cores: the whole step (max_iters
+    iterations) of the same workload, or as many iterations as fit in about
+    budget_s seconds at the rate of a `chunk`-iteration estimate."""
     import numpy as np
     import oracle
 
@@ -122,17 +125,17 @@ def cpu_baseline(n, dtype, budget_s=12.0, max_iters=200):
     nt = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     oracle.set_threads(nt)
     U = oracle.init_field(n, np.float64 if dtype == "f64" else np.float32, 12734)
-    oracle.jacobi(U, 1)                       # first touch
+    oracle.jacobi(U, 1)                       # first touch, thread start-up
     t = time.perf_counter()
-    oracle.jacobi(U, 2)
-    per = (time.perf_counter() - t) / 2
-    iters = max(1, min(max_iters, int(budget_s / max(per, 1e-3))))
-    t = time.perf_counter()
-    oracle.jacobi(U, iters)
-    dt = time.perf_counter() - t
-    return {"value": round(n ** 3 * iters / dt / 1e9, 3), "unit": "GLUP/s", "cores": int(oracle.max_threads()),
+    oracle.jacobi(U, chunk)                   # rate estimate
+    per = (time.perf_counter() - t) / chunk
+    done = max(1, min(max_iters, int(budget_s / max(per, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.jacobi(U, done)
+    dt = time.perf_counter() - t0
+    return {"value": round(n ** 3 * done / dt / 1e9, 3), "unit": "GLUP/s", "cores": int(oracle.max_threads()),
             "kind": "oracle",
-            "sample": f"{n}^3 {dtype} undecomposed, {iters} of the step's 200 iterations ({dt:.1f} s), same seed/bc"}
+            "sample": f"{n}^3 {dtype} undecomposed, {done} of the step's {max_iters} iterations ({dt:.1f} s), same seed/bc"}
 
 
 def odf_sweep(n, iters):

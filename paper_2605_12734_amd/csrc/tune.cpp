@@ -33,6 +33,8 @@ std::map<std::string, std::array<int32_t, 3>> g_cache;
 bool g_cache_loaded = false;
 
 const int32_t kTz[] = {8, 16, 32, 64, 128};
+// single-row (2D) tiles march their second direction: longer columns
+const int32_t kTz2d[] = {8, 32, 128, 512, 2048};
 
 std::string signature(const Grid& G) {
     std::map<std::array<int32_t, 3>, int64_t> hist;
@@ -145,8 +147,13 @@ od_status autotune(Grid& G, int32_t iters, int32_t out_tile[3]) {
         if (v[i].tx > 2 * ((emax[0] + vx - 1) / vx * vx) && v[i].tx > 16) continue;   // mostly idle lanes
         if (v[i].ty > 2 * emax[1] && v[i].ty > 4) continue;
         std::vector<int32_t> tzs;
-        for (int32_t tz : kTz)
-            if (tz < emax[2]) tzs.push_back(tz);
+        if (emax[1] == 1) {
+            for (int32_t tz : kTz2d)
+                if (tz < emax[2]) tzs.push_back(tz);
+        } else {
+            for (int32_t tz : kTz)
+                if (tz < emax[2]) tzs.push_back(tz);
+        }
         tzs.push_back(emax[2]);
         for (int32_t tz : tzs) cands.push_back({v[i].tx, v[i].ty, tz});
     }
