@@ -133,9 +133,22 @@ def cpu_baseline(n, dtype, budget_s=25.0, max_iters=200, chunk=10):
     t0 = time.perf_counter()
     oracle.jacobi(U, done)
     dt = time.perf_counter() - t0
-    return {"value": round(n ** 3 * done / dt / 1e9, 3), "unit": "GLUP/s", "cores": int(oracle.max_threads()),
-            "kind": "oracle",
-            "sample": f"{n}^3 {dtype} undecomposed, {done} of the step's {max_iters} iterations ({dt:.1f} s), same seed/bc"}
+    cores = int(oracle.max_threads())
+    # one thread, a few iterations
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    oracle.jacobi(U, 3)
+    dt1 = time.perf_counter() - t1
+    oracle.set_threads(nt)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": round(n ** 3 * done / dt / 1e9, 3), "unit": "GLUP/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n}^3 {dtype} undecomposed, {done} of the step's {max_iters} iterations ({dt:.1f} s), same seed/bc",
+            "single_thread_value": round(n ** 3 * 3 / dt1 / 1e9, 4), "cpu_model": model}
 
 
 def odf_sweep(n, iters):
@@ -306,6 +319,7 @@ def _serve_rate(srv, rate, count):
     import workloads
 
     reqs = workloads.serving_requests(rate, count, seed=12734 + int(rate))
+    st0 = srv.stats()
     t0 = time.monotonic()
     tickets = {}
     pending = list(reqs)
@@ -335,6 +349,10 @@ def _serve_rate(srv, rate, count):
            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
            "solves_per_s": round(count / (last - first), 2), "glups": round(lups / (last - first) / 1e9, 2),
            "mean_iters": round(float(np.mean([r["iters"] for r in done.values()])), 1)}
+    st1 = srv.stats()
+    wall = time.monotonic() - t0
+    row["worker"] = {k: round(st1[k] - st0[k], 3) for k in ("epochs", "epoch_s", "admit_s", "retire_s", "idle_s")}
+    row["worker"]["wall_s"] = round(wall, 3)
     log("serving:", row)
     return row
 

@@ -335,6 +335,17 @@ od_status od_submit(struct od_server* s, const od_request* req, uint64_t* ticket
  * (`active`) and waiting (`queued`); OD_ECANCELED once the server has
  * stopped after a device error. */
 od_status od_server_step(struct od_server* s, int32_t* active, int32_t* queued);
+
+/* Where the server's worker thread spent its time so far (host clock):
+ * inside scheduling epochs (launch to completion), admitting requests
+ * (planning, descriptor upload, field initialisation), retiring finished
+ * solves (copying the field to host memory, freeing arena space), and
+ * waiting for work. */
+typedef struct {
+    int64_t epochs;
+    double epoch_s, admit_s, retire_s, idle_s;
+} od_server_stats;
+od_status od_server_stats_get(struct od_server* s, od_server_stats* out);
 /* State of a request; OD_ENOTREADY while queued or running. */
 od_status od_poll(struct od_server* s, uint64_t ticket, od_info* out);
 /* Copy a finished request's padded global field (global layout above) to

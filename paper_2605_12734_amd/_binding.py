@@ -63,6 +63,10 @@ class od_info(ctypes.Structure):
                 ("t_admit", c_dbl), ("t_done", c_dbl)]
 
 
+class od_server_stats(ctypes.Structure):
+    _fields_ = [("epochs", c_i64), ("epoch_s", c_dbl), ("admit_s", c_dbl), ("retire_s", c_dbl), ("idle_s", c_dbl)]
+
+
 class od_overlap_result(ctypes.Structure):
     _fields_ = [("total_threads", c_i64), ("nkernels", c_i32), ("nstreams", c_i32), ("work", c_i32),
                 ("pad", c_i32), ("makespan_us", c_dbl), ("host_us", c_dbl), ("enqueue_us", c_dbl)]
@@ -89,6 +93,7 @@ SIGNATURES = {
     "od_block_cells": (ctypes.c_int, [c_vp, c_i32, ctypes.POINTER(c_i32)]),
     "od_read_block": (ctypes.c_int, [c_vp, c_i32, c_vp, c_sz]),
     "od_write_block": (ctypes.c_int, [c_vp, c_i32, c_vp, c_sz]),
+    "od_server_stats_get": (ctypes.c_int, [c_vp, ctypes.POINTER(od_server_stats)]),
     "od_launch_overlap_bytes": (c_sz, [c_i64]),
     "od_launch_overlap": (ctypes.c_int, [c_vp, c_sz, c_i64, c_i32, c_i32, c_i32, ctypes.POINTER(od_overlap_result)]),
     "od_launch_rate": (ctypes.c_int, [c_i32, c_i32, c_dbl, ctypes.POINTER(c_i64), ctypes.POINTER(c_dbl)]),

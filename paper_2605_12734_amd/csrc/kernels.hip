@@ -87,6 +87,10 @@ __device__ __forceinline__ void wg_residual(T r, unsigned long long* slot, T* re
 // ---------------------------------------------------------------------------
 // fused sweep of one tile
 
+#ifndef OD_MERGED_HALO
+#define OD_MERGED_HALO 1
+#endif
+
 template <typename T, int TX, int TY>
 struct SW {
     static constexpr int VX = V16<T>::N;
@@ -168,6 +172,21 @@ __device__ __forceinline__ T sweep_tile(T* __restrict__ arena, const BlockDev* _
     const bool do_xp = rowok && lx == (nx - 1) / VX;
     const bool do_ym = act && ly == 0;
     const bool do_yp = act && ly == ny - 1;
+#if OD_MERGED_HALO
+    // merged halo loads: the x+ value sits in a lane other than column 0
+    // (column 1 for a one-vector tile), the y+ row in a row other than 0
+    // (row 1 for a one-row tile of a multi-row variant)
+    int nvx = nx - x;
+    nvx = nvx < 0 ? 0 : (nvx > VX ? VX : nvx);
+    const int xp_lane = (nx - 1) / VX > 0 ? (nx - 1) / VX : 1;
+    const int yp_row = TY == 1 ? 0 : (ny - 1 > 0 ? ny - 1 : 1);
+    const bool mdo_xp = rowok && lx == xp_lane;
+    const bool mdo_ym = nvx > 0 && ly == 0;
+    const bool mdo_yp = nvx > 0 && ly == yp_row;
+    (void)do_xp;
+    (void)do_ym;
+    (void)do_yp;
+#endif
 
     auto L = [&](int b, int r, int c) -> T& { return lds[(b * S::LR + r) * S::LP + c]; };
     auto ldv = [](const char* p) -> VT { return *reinterpret_cast<const VT*>(p); };
@@ -183,8 +202,23 @@ __device__ __forceinline__ T sweep_tile(T* __restrict__ arena, const BlockDev* _
     VT pl[PF + 3];
 #pragma unroll
     for (int k = 0; k < PF + 2; ++k) pl[k] = plane(k - 1 <= nz ? k - 1 : nz);
+#if OD_MERGED_HALO
+    // one load per plane for each halo direction: column-0 lanes read the
+    // x- slab, the others the x+ slab (used by lane column xp_lane); with
+    // two or more rows, row-0 lanes read the y- slab and the others the y+
+    // slab (used by row yp_row)
+    const bool xlo = lx == 0, ylo = ly == 0 || TY == 1;
+    const char* x_b = xlo ? xm_b + o_xm : xp_b + o_xp;
+    const int64_t x_pz = (xlo ? xm_pz : xp_pz) * ES;
+    const char* y_b = ylo ? ym_b : yp_b;
+    const int64_t y_pz = (ylo ? ym_pz : yp_pz) * ES;
+    T hx = lds1(x_b);
+    VT hy = ldv(y_b + o_y);
+    VT hyp1 = TY == 1 ? ldv(yp_b + o_y) : hy;   // single-row tiles keep a separate y+ load
+#else
     VT hym = ldv(ym_b + o_y), hyp = ldv(yp_b + o_y);
     T hxm = lds1(xm_b + o_xm), hxp = lds1(xp_b + o_xp);
+#endif
 
     T r = 0;
     for (int z = 0; z < nz; ++z) {
@@ -196,8 +230,14 @@ __device__ __forceinline__ T sweep_tile(T* __restrict__ arena, const BlockDev* _
         const VT& p1 = pl[1];
         const VT& p2 = pl[2];
         const int64_t zh = z + 1 < nz ? z + 1 : z;
+#if OD_MERGED_HALO
+        const T nx1 = lds1(x_b + zh * x_pz);
+        const VT ny1 = ldv(y_b + zh * y_pz + o_y);
+        const VT nyp1 = TY == 1 ? ldv(yp_b + zh * yp_pz * ES + o_y) : ny1;
+#else
         const VT nym = ldv(ym_b + zh * ym_pz * ES + o_y), nyp = ldv(yp_b + zh * yp_pz * ES + o_y);
         const T nxm = lds1(xm_b + zh * xm_pz * ES + o_xm), nxp = lds1(xp_b + zh * xp_pz * ES + o_xp);
+#endif
 
         // stage plane z with its x/y halo
         if (act) {
@@ -205,6 +245,20 @@ __device__ __forceinline__ T sweep_tile(T* __restrict__ arena, const BlockDev* _
             for (int i = 0; i < VX; ++i)
                 if (i < nv) L(b, ly + 1, VX + x + i) = p1[i];
         }
+#if OD_MERGED_HALO
+        if (do_xm) L(b, ly + 1, VX - 1) = hx;
+        if (mdo_xp) L(b, ly + 1, VX + nx) = hx;
+        if (mdo_ym) {
+#pragma unroll
+            for (int i = 0; i < VX; ++i)
+                if (i < nvx) L(b, 0, VX + x + i) = hy[i];
+        }
+        if (mdo_yp) {
+#pragma unroll
+            for (int i = 0; i < VX; ++i)
+                if (i < nvx) L(b, ny + 1, VX + x + i) = (TY == 1 ? hyp1 : hy)[i];
+        }
+#else
         if (do_xm) L(b, ly + 1, VX - 1) = hxm;
         if (do_xp) L(b, ly + 1, VX + nx) = hxp;
         if (do_ym) {
@@ -217,6 +271,7 @@ __device__ __forceinline__ T sweep_tile(T* __restrict__ arena, const BlockDev* _
             for (int i = 0; i < VX; ++i)
                 if (i < nv) L(b, ny + 1, VX + x + i) = hyp[i];
         }
+#endif
         __syncthreads();
 
         if (act) {
@@ -253,10 +308,16 @@ __device__ __forceinline__ T sweep_tile(T* __restrict__ arena, const BlockDev* _
         }
 #pragma unroll
         for (int k = 0; k < PF + 2; ++k) pl[k] = pl[k + 1];
+#if OD_MERGED_HALO
+        hy = ny1;
+        hyp1 = nyp1;
+        hx = nx1;
+#else
         hym = nym;
         hyp = nyp;
         hxm = nxm;
         hxp = nxp;
+#endif
     }
     __syncthreads();   // LDS planes are reused by the next tile
     return r;

@@ -176,6 +176,14 @@ std::string fill_tile_descs(Grid& G) {
         td.rslot = cfg.exec == OD_PER_CHARE ? th.chare : 0;
         for (int f = 0; f < 6; ++f) {
             FaceDev& fd = td.f[f];
+            if (cfg.stencil == 5 && f / 2 == 1) {
+                // 2D stencil: the y ghost "slab" is the tile's own row (never used)
+                fd.src = th.chare;
+                fd.sx = th.o[0];
+                fd.sy = th.o[1];
+                fd.sz = th.o[2];
+                continue;
+            }
             int32_t src_chare = -1, pb = -1;
             if (th.kind[f] == 2) src_chare = th.chare;
             else if (th.kind[f] == 0) {
@@ -263,9 +271,13 @@ std::string build_layout(const od_config& cfg, Grid& G) {
     G.pb_block.clear();
 
     // descriptor regions first (sizes known after tiles / pseudo-blocks)
+    // the 2D stencil never reads y neighbours: no y-face buffers (each would
+    // be as large as the chare), y ghost slabs point at the tile itself
+    const bool flat = cfg.stencil == 5;
     int32_t npb = 0;
     for (int32_t c = 0; c < C; ++c)
         for (int f = 0; f < 6; ++f) {
+            if (flat && f / 2 == 1) continue;
             if (on_domain_face(p, p.chares[(size_t)c], f)) ++npb;
             else if (cfg.exec == OD_PER_CHARE) ++npb;
             else if (p.multires && p.mr[(size_t)c * 6 + f]) ++npb;
@@ -361,6 +373,7 @@ std::string build_layout(const od_config& cfg, Grid& G) {
     for (int32_t c = 0; c < C; ++c) {
         const Chare& ch = p.chares[(size_t)c];
         for (int f = 0; f < 6; ++f) {
+            if (flat && f / 2 == 1) continue;
             const bool dom = on_domain_face(p, ch, f);
             const bool res = !dom && p.multires && p.mr[(size_t)c * 6 + f];
             if (!dom && !res && cfg.exec != OD_PER_CHARE) continue;

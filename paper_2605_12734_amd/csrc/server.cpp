@@ -111,6 +111,7 @@ struct Server {
     uint64_t next_ticket = 1;
     int32_t grid_cap = 0;
     std::string fatal;
+    od_server_stats stats{};          // guarded by mu
 
     size_t alloc(size_t bytes) {
         bytes = align_up(bytes, kAlign);
@@ -257,6 +258,7 @@ void Server::run() {
     std::vector<int32_t> tpos((size_t)max_slots * kTileStride, -1);
     for (;;) {
         std::vector<Request*> admitted;
+        const double t_wait = now_s();
         {
             std::unique_lock<std::mutex> lk(mu);
             cv.wait(lk, [&] {
@@ -266,6 +268,7 @@ void Server::run() {
                 return false;
             });
             if (stop) break;
+            stats.idle_s += now_s() - t_wait;
             // FIFO admission while a slot and arena space are free
             while (!queue.empty()) {
                 Request& R = *reqs[queue.front()];
@@ -280,6 +283,7 @@ void Server::run() {
                 admitted.push_back(&R);
             }
         }
+        const double t_admit0 = now_s();
         for (Request* R : admitted) {
             od_status s = setup_slot(*R, R->slot);
             std::lock_guard<std::mutex> lk(mu);
@@ -298,6 +302,7 @@ void Server::run() {
         list.clear();
         {
             std::lock_guard<std::mutex> lk(mu);
+            stats.admit_s += now_s() - t_admit0;
             for (int32_t s2 = 0; s2 < max_slots; ++s2) {
                 const uint64_t t = slot_ticket[(size_t)s2];
                 if (!t) continue;
@@ -388,6 +393,11 @@ void Server::run() {
             }
             std::this_thread::sleep_for(std::chrono::microseconds(20));
         }
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            stats.epochs += 1;
+            stats.epoch_s += now_s() - t_epoch;
+        }
         unsigned int derr = 0;
         if (e == hipSuccess) e = hipMemcpy(&derr, arena + c_err, 4, hipMemcpyDeviceToHost);
         if (e != hipSuccess || derr != 0) {
@@ -402,11 +412,16 @@ void Server::run() {
             }
             break;
         }
+        const double t_ret0 = now_s();
         for (size_t i = 0; i < active.size(); ++i)
             if (__atomic_load_n(&h_done[active[i]->slot], __ATOMIC_ACQUIRE) > 0) {
                 if (!seen[i]) active[i]->t_done = now_s();
                 retire(*active[i]);
             }
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            stats.retire_s += now_s() - t_ret0;
+        }
     }
     hipEventDestroy(ev);
     std::lock_guard<std::mutex> lk(mu);
@@ -612,6 +627,14 @@ od_status od_server_step(od_server* sv, int32_t* active, int32_t* queued) {
     if (active) *active = a;
     if (queued) *queued = (int32_t)S.queue.size();
     if (!S.fatal.empty()) return fail(OD_ECANCELED, S.fatal);
+    return OD_OK;
+}
+
+od_status od_server_stats_get(od_server* sv, od_server_stats* out) {
+    if (!sv || !out) return fail(OD_EINVAL, "NULL argument");
+    od::Server& S = sv->s;
+    std::lock_guard<std::mutex> lk(S.mu);
+    *out = S.stats;
     return OD_OK;
 }
 

@@ -100,6 +100,13 @@ class Server:
         check(lib().od_server_step(self.h, ctypes.byref(a), ctypes.byref(q)), "od_server_step")
         return int(a.value), int(q.value)
 
+    def stats(self) -> dict:
+        """Worker-thread time accounting: epochs, seconds in epochs, admission,
+        retirement and idle."""
+        st = B.od_server_stats()
+        check(lib().od_server_stats_get(self.h, ctypes.byref(st)), "od_server_stats_get")
+        return {f: getattr(st, f) for f, _ in st._fields_}
+
     def close(self) -> None:
         if getattr(self, "h", None):
             check(lib().od_server_destroy(self.h), "od_server_destroy")
