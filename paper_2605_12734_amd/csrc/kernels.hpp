@@ -141,12 +141,13 @@ struct FillSeg {
     int32_t n1, n2;         // rectangle extent
     int32_t r1, r2;         // neighbour-relative unit offset of ghost cell (a1, a2)
     int32_t hc, lhn;        // ghost cell edge (units), log2 neighbour cell edge
-    int64_t first;          // launch index of the rectangle's first ghost cell
+    int64_t first;          // index of the rectangle's first ghost cell over all rectangles
 };
 static_assert(sizeof(FillSeg) == 56, "FillSeg layout");
 
 // Fill every resolution-change ghost buffer from parity `parity` of the
-// chares: segs[0..nseg) sorted by `first`, total ghost cells `total`.
+// chares: one workgroup per rectangle segs[0..nseg); `total` (ghost cells
+// over all rectangles) only skips an empty launch.
 hipError_t launch_amr_fill(int dtype_bytes, hipStream_t st, void* arena, const BlockDev* blocks,
                            const FillSeg* segs, int32_t nseg, int64_t total, int parity);
 
