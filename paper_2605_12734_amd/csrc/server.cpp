@@ -14,8 +14,10 @@
 // admit new arrivals or retire finished solves the worker raises a yield
 // flag; every workgroup then stops taking new tasks and the epoch ends.  All
 // scheduler state (per-tile step counters, gates, residual slots) lives in
-// HBM, so the next epoch resumes exactly where this one stopped.  A retired
-// solve's field is copied to host memory and its arena space freed.
+// HBM, so the next epoch resumes exactly where this one stopped.  A
+// finished solve leaves the next epoch's tile list; while that epoch runs,
+// its field is copied to host memory with the copy engine and its arena
+// space freed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -79,11 +81,13 @@ struct Request {
     double residual = 0;
     std::unique_ptr<Grid> grid;
     size_t off = 0;
+    bool finished = false;           // final step reached; waiting to be copied out
     std::vector<char> result;
 };
 
 struct Server {
     hipStream_t st = nullptr;
+    hipStream_t cst = nullptr;        // result copies (copy engine), overlapping the next epoch
     char* arena = nullptr;
     size_t arena_bytes = 0;
     int32_t max_slots = 0;
@@ -217,28 +221,66 @@ od_status Server::setup_slot(Request& R, int32_t slot) {
 }
 
 void Server::retire(Request& R) {
-    // the solve's field is final: copy it to host, free its arena space
+    // The solve's field is final and no kernel touches it any more: copy
+    // each chare's storage (final parity) to host memory with the copy
+    // engine while the next epoch runs, lay it out as the padded global
+    // field (Dirichlet shell from the request), free the arena space.
     Grid& G = *R.grid;
     const int32_t fs = __atomic_load_n(&h_done[R.slot], __ATOMIC_ACQUIRE);
     unsigned long long rb = __atomic_load_n(&h_res[R.slot], __ATOMIC_ACQUIRE);
     double r;
     std::memcpy(&r, &rb, 8);
-    G.parity = fs & 1;
-    G.iters = fs;
-    const size_t nb = (size_t)(R.req.n + 2) * (R.req.n + 2) * (R.req.n + 2) * (size_t)G.s;
-    std::vector<char> host(nb);
-    G.pinned = staging;
-    G.pinned_bytes = staging_bytes;
-    G.pinned_borrowed = true;
-    od_status s = G.io(host.data(), nb, true);
+    const int par = fs & 1;
+    const int64_t n = R.req.n, P = n + 2;
+    const size_t s = (size_t)G.s;
+    std::vector<char> host((size_t)P * P * P * s, 0);
+    auto put = [&](int64_t i, int64_t j, int64_t k, double v) {
+        char* d = host.data() + (size_t)((k * P + j) * P + i) * s;
+        if (s == 8) std::memcpy(d, &v, 8);
+        else {
+            const float f = (float)v;
+            std::memcpy(d, &f, 4);
+        }
+    };
+    for (int64_t a = 1; a <= n; ++a)
+        for (int64_t b = 1; b <= n; ++b) {
+            put(0, a, b, R.req.bc[0]);
+            put(P - 1, a, b, R.req.bc[1]);
+            put(a, 0, b, R.req.bc[2]);
+            put(a, P - 1, b, R.req.bc[3]);
+            put(a, b, 0, R.req.bc[4]);
+            put(a, b, P - 1, R.req.bc[5]);
+        }
+    hipError_t e = hipSuccess;
+    char* stage = static_cast<char*>(staging);
+    for (size_t c = 0; c < G.plan.chares.size() && e == hipSuccess; ++c) {
+        const Chare& ch = G.plan.chares[c];
+        const BlockDev& B = G.blocks_h[c];
+        const char* src = G.base + (size_t)(par ? B.off[1] : B.off[0]) * s;
+        const size_t plane = (size_t)B.pz * s, row = (size_t)B.ex * s;
+        const int32_t per = (int32_t)std::max<size_t>(1, staging_bytes / plane);
+        for (int32_t z0 = 0; z0 < B.ez && e == hipSuccess; z0 += per) {
+            const int32_t nz = std::min<int32_t>(per, B.ez - z0);
+            e = hipMemcpyAsync(stage, src + (size_t)z0 * plane, (size_t)nz * plane, hipMemcpyDeviceToHost, cst);
+            if (e == hipSuccess) e = hipStreamSynchronize(cst);
+            if (e != hipSuccess) break;
+            for (int32_t z = 0; z < nz; ++z)
+                for (int32_t y = 0; y < B.ey; ++y) {
+                    const int64_t k = ch.o[2] + z0 + z + 1, j = ch.o[1] + y + 1, i = ch.o[0] + 1;
+                    std::memcpy(host.data() + (size_t)((k * P + j) * P + i) * s,
+                                stage + (size_t)z * plane + (size_t)y * B.py * s, row);
+                }
+        }
+    }
     std::lock_guard<std::mutex> lk(mu);
     R.iters = fs;
     R.residual = r;
-    if (s == OD_OK) {
+    if (e == hipSuccess) {
         R.result.swap(host);
         R.state = OD_REQ_DONE;
     } else {
         R.state = OD_REQ_CANCELED;
+        if (fatal.empty()) fatal = std::string("result copy: ") + hipGetErrorString(e);
     }
     slot_ticket[(size_t)R.slot] = 0;
     release(R.off, R.bytes);
@@ -256,6 +298,7 @@ void Server::run() {
     }
     std::vector<int32_t> list;
     std::vector<int32_t> tpos((size_t)max_slots * kTileStride, -1);
+    std::vector<Request*> retiring;
     for (;;) {
         std::vector<Request*> admitted;
         const double t_wait = now_s();
@@ -307,7 +350,7 @@ void Server::run() {
                 const uint64_t t = slot_ticket[(size_t)s2];
                 if (!t) continue;
                 Request& R = *reqs[t];
-                if (R.state != OD_REQ_RUNNING) continue;
+                if (R.state != OD_REQ_RUNNING || R.finished) continue;
                 active.push_back(&R);
                 const int32_t nt = (int32_t)R.grid->tiles_h.size();
                 for (int32_t i = 0; i < nt; ++i) list.push_back(s2 * kTileStride + i);
@@ -315,11 +358,15 @@ void Server::run() {
                 while (list.size() % kNumXcd) list.push_back(-1);
             }
         }
-        if (active.empty()) continue;
+        hipError_t e = hipSuccess;
+        bool launched = false;
+        double t_epoch = now_s();
+        std::vector<char> seen(active.size(), 0);
+        if (!active.empty()) {
         // tile list: solves back to back, each padded (-1) to a multiple of
         // 8 entries; each solve's tiles keep their own XCD-interleaved order,
         // so a solve's XCD groups stay together
-        hipError_t e = hipMemcpyAsync(arena + c_list, list.data(), list.size() * 4, hipMemcpyHostToDevice, st);
+        e = hipMemcpyAsync(arena + c_list, list.data(), list.size() * 4, hipMemcpyHostToDevice, st);
         // launch position of every tile in this epoch (XCD-aware publication)
         std::fill(tpos.begin(), tpos.end(), -1);
         for (size_t q = 0; q < list.size(); ++q)
@@ -360,10 +407,21 @@ void Server::run() {
         a.bar = reinterpret_cast<unsigned int*>(arena + c_bar);
         int grid = std::min<int>(std::min<int>(grid_cap, kMaxLaunchWgs), (int)list.size());
         if (grid >= kNumXcd) grid -= grid % kNumXcd;
-        const double t_epoch = now_s();
+        t_epoch = now_s();
         if (e == hipSuccess) e = launch_serve(st, grid, a);
         if (e == hipSuccess) e = hipEventRecord(ev, st);
-        std::vector<char> seen(active.size(), 0);
+        launched = e == hipSuccess;
+        }
+        // the previous epoch's finished solves are copied out while this
+        // epoch runs (their chares are not in its tile list)
+        if (!retiring.empty()) {
+            const double t_ret0 = now_s();
+            for (Request* R : retiring) retire(*R);
+            retiring.clear();
+            std::lock_guard<std::mutex> lk(mu);
+            stats.retire_s += now_s() - t_ret0;
+        }
+        if (!launched && e == hipSuccess) continue;
         while (e == hipSuccess) {
             const hipError_t q = hipEventQuery(ev);
             const double t = now_s();
@@ -412,17 +470,15 @@ void Server::run() {
             }
             break;
         }
-        const double t_ret0 = now_s();
         for (size_t i = 0; i < active.size(); ++i)
             if (__atomic_load_n(&h_done[active[i]->slot], __ATOMIC_ACQUIRE) > 0) {
+                std::lock_guard<std::mutex> lk(mu);
                 if (!seen[i]) active[i]->t_done = now_s();
-                retire(*active[i]);
+                active[i]->finished = true;
+                retiring.push_back(active[i]);
             }
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            stats.retire_s += now_s() - t_ret0;
-        }
     }
+    for (Request* R : retiring) retire(*R);
     hipEventDestroy(ev);
     std::lock_guard<std::mutex> lk(mu);
     for (auto& kv : reqs) {
@@ -557,6 +613,7 @@ od_status od_server_create(void* hip_stream, void* dev_arena, size_t arena_bytes
         // staging for result copies: the largest plane chunk od_read uses
         S.staging_bytes = (size_t)64 << 20;
         if (e == hipSuccess) e = hipHostMalloc(&S.staging, S.staging_bytes, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&S.cst, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipMemsetAsync(S.arena + S.c_err, 0, 16, S.st);
         if (e == hipSuccess) e = hipMemsetAsync(S.arena + S.c_bar, 0, 16, S.st);
         if (e == hipSuccess) e = hipStreamSynchronize(S.st);
@@ -565,6 +622,7 @@ od_status od_server_create(void* hip_stream, void* dev_arena, size_t arena_bytes
             if (S.h_res) hipHostFree(S.h_res);
             if (S.h_yield) hipHostFree(S.h_yield);
             if (S.staging) hipHostFree(S.staging);
+            if (S.cst) hipStreamDestroy(S.cst);
             return fail(OD_EHIP, std::string("server setup: ") + hipGetErrorString(e));
         }
         std::memset(S.h_done, 0, ms * 4);
@@ -576,6 +634,7 @@ od_status od_server_create(void* hip_stream, void* dev_arena, size_t arena_bytes
             hipHostFree(S.h_res);
             hipHostFree(S.h_yield);
             hipHostFree(S.staging);
+            hipStreamDestroy(S.cst);
             return fail(OD_EHIP, "no co-resident workgroups for the serving kernel");
         }
         S.worker = std::thread([&S] { S.run(); });
@@ -683,6 +742,11 @@ od_status od_server_destroy(od_server* sv) {
     }
     if (S.worker.joinable()) S.worker.join();
     hipError_t e = hipStreamSynchronize(S.st);
+    if (S.cst) {
+        const hipError_t e2 = hipStreamSynchronize(S.cst);
+        if (e == hipSuccess) e = e2;
+        hipStreamDestroy(S.cst);
+    }
     if (S.h_done) hipHostFree(S.h_done);
     if (S.h_res) hipHostFree(S.h_res);
     if (S.h_yield) hipHostFree(S.h_yield);
