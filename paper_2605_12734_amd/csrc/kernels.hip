@@ -397,6 +397,57 @@ __device__ __forceinline__ bool grid_barrier(unsigned int* bar, unsigned int* er
     return ok != 0;
 }
 
+// hwreg(HW_REG_XCC_ID, 0, 4): the XCD this wave runs on
+constexpr int kXccIdReg = ((4 - 1) << 11) | (0 << 6) | 20;
+
+// Device-wide barrier with one L2 write-back per XCD.  The workgroups of an
+// XCD share its L2: each drains its stores into it and arrives on the XCD's
+// counter (relaxed); the last of them publishes for all of them with one
+// release (write-back of that L2) on the device counter; the last XCD bumps
+// the generation.  Bounded wait as in grid_barrier.  bar[32 + x]: arrivals
+// of XCD x (zeroed by its last arrival), `xcd_wgs` workgroups on this XCD,
+// `nxcd` XCDs with workgroups.
+__device__ __forceinline__ bool xcd_barrier(unsigned int* bar, unsigned int* err, int64_t wait_ticks,
+                                            unsigned int* reset, int xcd, unsigned int xcd_wgs,
+                                            unsigned int nxcd) {
+    __shared__ int ok;
+    wg_stores_done();
+    if (threadIdx.x == 0) {
+        const unsigned int gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int good = 1;
+        bool released = false;
+        const unsigned int a = __hip_atomic_fetch_add(&bar[32 + xcd], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (a == xcd_wgs - 1) {
+            __hip_atomic_store(&bar[32 + xcd], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned int g = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (g == nxcd - 1) {
+                __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (reset)
+                    for (int x = 0; x < 8; ++x)
+                        __hip_atomic_store(&reset[x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                released = true;
+            }
+        }
+        if (!released) {
+            const int64_t t0 = wall_clock64();
+            while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(8);
+                if (wall_clock64() - t0 > wait_ticks ||
+                    __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                    __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    good = 0;
+                    break;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        ok = good;
+    }
+    __syncthreads();
+    return ok != 0;
+}
+
 template <typename T, int TX, int TY>
 __global__ void __launch_bounds__((TX / V16<T>::N) * TY)
 k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDev* __restrict__ tiles,
@@ -411,6 +462,25 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
     // positions = w (mod 8), the spatial chunk the planner gave that XCD
     const int ng = (gridDim.x >= 8 && gridDim.x % 8 == 0) ? 8 : 1;
     const int xg = (int)(blockIdx.x % ng);
+    // register on this workgroup's XCD (bar[40 + x] counts them), then one
+    // full barrier so every count is final
+    __shared__ int s_xcd;
+    __shared__ unsigned int s_xwgs, s_nxcd;
+    if (iters > 1) {
+        if (threadIdx.x == 0) {
+            s_xcd = (int)(__builtin_amdgcn_s_getreg(kXccIdReg) & 7);
+            __hip_atomic_fetch_add(&bar[40 + s_xcd], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (!grid_barrier(bar, err, wait_ticks)) return;
+        if (threadIdx.x == 0) {
+            s_xwgs = __hip_atomic_load(&bar[40 + s_xcd], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            unsigned int nx = 0;
+            for (int x = 0; x < 8; ++x)
+                nx += __hip_atomic_load(&bar[40 + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1u : 0u;
+            s_nxcd = nx;
+        }
+        __syncthreads();
+    }
     for (int64_t it = 0; it < iters; ++it) {
         const int p = parity ^ (int)(it & 1);
         if (blockIdx.x == 0)
@@ -455,7 +525,8 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
         if (slot >= 0) wg_residual<T, S::NT>(r, &res[2 * slot + (p ^ 1)], red);
         if (it + 1 < iters) {
             // the last arrival clears the counters of the step after next
-            if (!grid_barrier(bar, err, wait_ticks, &bar[8 + 8 * (int)((it + 1) & 1)])) return;
+            if (!xcd_barrier(bar, err, wait_ticks, &bar[8 + 8 * (int)((it + 1) & 1)], s_xcd, s_xwgs, s_nxcd))
+                return;
         }
     }
     // the last workgroup to leave clears the counters for the next launch
@@ -464,6 +535,7 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
         const unsigned int prev = __hip_atomic_fetch_add(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (prev == gridDim.x - 1) {
             for (int x = 8; x < 24; ++x) __hip_atomic_store(&bar[x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int x = 32; x < 48; ++x) __hip_atomic_store(&bar[x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&bar[2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
@@ -484,9 +556,6 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
 // parity step & 1) with the whole workgroup and returns its residual.
 // Wave 0 looks for a ready tile, 64 owned tiles at a time (one per lane,
 // starting after the last tile run), and takes the first ready one.
-// hwreg(HW_REG_XCC_ID, 0, 4): the XCD this wave runs on
-constexpr int kXccIdReg = ((4 - 1) << 11) | (0 << 6) | 20;
-
 // Launch start of the XCD-aware publication: record this workgroup's XCD,
 // meet every other workgroup, then mark each owned launch position whose
 // tile has a dependent owned on another XCD (or outside the launch).
@@ -661,8 +730,19 @@ __device__ __forceinline__ void msg_loop(const MsgArgs& a, SweepFn sweep, double
     }
 }
 
+// Minimum waves per SIMD the scheduler kernels are compiled for (0 = the
+// compiler's choice).
+#ifndef OD_SCHED_WAVES
+#define OD_SCHED_WAVES 0
+#endif
+#if OD_SCHED_WAVES > 0
+#define OD_SCHED_OCC __attribute__((amdgpu_waves_per_eu(OD_SCHED_WAVES, 8)))
+#else
+#define OD_SCHED_OCC
+#endif
+
 template <typename T, int TX, int TY>
-__global__ void __launch_bounds__((TX / V16<T>::N) * TY) k_msgdriven(MsgArgs a) {
+__global__ void __launch_bounds__((TX / V16<T>::N) * TY) OD_SCHED_OCC k_msgdriven(MsgArgs a) {
     using S = SW<T, TX, TY>;
     __shared__ T lds[S::LDS];
     __shared__ double red[S::NT / 64];
@@ -683,7 +763,7 @@ __global__ void __launch_bounds__((TX / V16<T>::N) * TY) k_msgdriven(MsgArgs a) 
 // its solve's dtype on a shared LDS buffer.  Block offsets are in elements
 // of the block's own dtype from the (256-byte aligned) arena base.
 template <int TX8, int TY8, int TX4, int TY4>
-__global__ void __launch_bounds__((TX8 / 2) * TY8) k_serve(MsgArgs a) {
+__global__ void __launch_bounds__((TX8 / 2) * TY8) OD_SCHED_OCC k_serve(MsgArgs a) {
     using S8 = SW<double, TX8, TY8>;
     using S4 = SW<float, TX4, TY4>;
     static_assert(S8::NT == S4::NT, "fp64 and fp32 serving tiles need the same thread count");

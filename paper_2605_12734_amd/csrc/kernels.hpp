@@ -50,9 +50,11 @@ hipError_t launch_sweep(int dtype_bytes, int tx, int ty, hipStream_t st, void* a
 // device-wide barrier between them.  dyn != 0: workgroups take tiles from
 // per-XCD-group counters (load balance under imbalance and uneven blocks);
 // dyn == 0: workgroup w takes tiles w, w + grid, ... (uniform work).
-// `bar` = 32 zeroed uint32: [0] arrivals, [1] generation, [2] exits,
-// [8..24) tile counters (8 XCD groups x 2 step parities); the kernel leaves
-// them zeroed.  `err` = error flag.  `extra` (may be null): table of
+// `bar` = 64 zeroed uint32: [0] arrivals, [1] generation, [2] exits,
+// [8..24) tile counters (8 XCD groups x 2 step parities), [32..40) per-XCD
+// barrier arrivals, [40..48) workgroups per XCD; the kernel leaves them
+// zeroed.  Between iterations, one L2 write-back per XCD publishes its
+// workgroups' results (the XCD's workgroups share that L2).  `err` = error flag.  `extra` (may be null): table of
 // [period][nchares] extra re-runs, row (iter_base + it) % period.
 hipError_t launch_persistent(int dtype_bytes, int tx, int ty, hipStream_t st, int grid,
                              void* arena, const BlockDev* blocks, const TileDev* tiles,

@@ -315,7 +315,7 @@ std::string build_layout(const od_config& cfg, Grid& G) {
     G.L.bc = cv.take(6 * 8);
     G.nres = cfg.exec == OD_PER_CHARE ? C : 1;
     G.L.res = cv.take((size_t)(2 * G.nres + 2) * 8);
-    G.L.bar = cv.take(32 * 4);
+    G.L.bar = cv.take(64 * 4);
     G.L.err = cv.take(4);
     G.L.done = cv.take(ntiles * 4);
     G.L.target = cv.take(4 * 4);
@@ -556,7 +556,7 @@ od_status Grid::reset_state() {
     // zero residual slots, barrier, error flag and step counters with a
     // plain fill (not captured into any graph)
     hipError_t e = hipMemsetAsync(base + L.res, 0, (size_t)(2 * nres + 2) * 8, st);
-    if (e == hipSuccess) e = hipMemsetAsync(base + L.bar, 0, 32 * 4, st);
+    if (e == hipSuccess) e = hipMemsetAsync(base + L.bar, 0, 64 * 4, st);
     if (e == hipSuccess) e = hipMemsetAsync(base + L.err, 0, 4, st);
     if (e == hipSuccess) e = hipMemsetAsync(base + L.done, 0, std::max<size_t>(tiles_h.size(), 1) * 4, st);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("state reset: ") + hipGetErrorString(e));
