@@ -46,9 +46,18 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
+    """Hash of the fused sweep's source: the prefetch-depth and halo-load
+    settings and everything from the tile geometry to the end of k_sweep
+    (edits elsewhere in kernels.hip leave measured traffic valid)."""
+    with open(os.path.join(ROOT, "paper_2605_12734_amd", "csrc", "kernels.hip")) as f:
+        src = f.read()
+    a = src.index("#ifndef OD_PREFETCH")
+    b = src.index("namespace od {", a)
+    c = src.index("#ifndef OD_MERGED_HALO")
+    d = src.index("(parity ^ 1)], red);\n}", c)
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_2605_12734_amd", "csrc", "kernels.hip"), "rb") as f:
-        h.update(f.read())
+    h.update(src[a:b].encode())
+    h.update(src[c:d].encode())
     return h.hexdigest()[:16]
 
 
