@@ -12,6 +12,8 @@
 // (compiled with -ffp-contract=off), in the order x-, x+, y-, y+, z-, z+.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 
 // Planes of the register column loaded ahead of the one being computed
@@ -730,6 +732,179 @@ __device__ __forceinline__ void msg_loop(const MsgArgs& a, SweepFn sweep, double
     }
 }
 
+// Dependency-counting scheduler of a plain grid.  Tile c may run step k
+// once it and every tile it reads halos from have finished step k-1.  The
+// finishes count in pend[2c + (k&1)] (counts only grow); the finish that
+// completes a multiple of (deg(c) + 1) queues c.  Step k+2 counts reach the
+// same word only after c has run step k+1, i.e. after that round is whole.
+//
+// Queues are per XCD: group g of tiles (t mod 8 == g) lives in the queue of
+// XCD g, or, if no workgroup of the launch runs on XCD g, of a present XCD
+// (the groups of absent XCDs are dealt round-robin over the present ones).
+// The workgroups of an XCD pop from its queue only, so a tile always runs
+// on one XCD and needs an L2 write-back only if some tile that reads it is
+// queued on another.  Every tile is queued once per step; a workgroup
+// whose pop ticket passes its queue's total leaves.  Every wait is bounded
+// (error flag 2).
+//
+// Queue x: ring of cap_x (power of two >= its tile count, so a push never
+// waits for good) 64-bit slots (sequence << 32 | tile) at qslots + off_x;
+// ticket counters qhead[x], qtail[x]; qhead[16] = mask of present XCDs.
+struct QueueMap {
+    int32_t phys[8];   // queue (XCD) of tile group g
+    int32_t off[8];    // first slot of queue x
+    int32_t cap[8];    // slots of queue x (0 if XCD x is absent)
+    int32_t n[8];      // tiles of queue x
+    int32_t pre[8];    // queue position of the first tile of group g
+};
+
+__device__ __forceinline__ void queue_map(uint32_t mask, int32_t ntiles, QueueMap& m) {
+    int32_t pres[8], np = 0;
+    for (int x = 0; x < 8; ++x)
+        if ((mask >> x) & 1u) pres[np++] = x;
+    for (int x = 0; x < 8; ++x) m.n[x] = 0;
+    for (int g = 0; g < 8; ++g) {
+        m.phys[g] = ((mask >> g) & 1u) ? g : pres[g % np];
+        m.pre[g] = m.n[m.phys[g]];
+        m.n[m.phys[g]] += ntiles > g ? (ntiles - g + 7) / 8 : 0;
+    }
+    int32_t o = 0;
+    for (int x = 0; x < 8; ++x) {
+        int32_t c = 0;
+        if ((mask >> x) & 1u) {
+            c = 1;
+            while (c < m.n[x]) c *= 2;
+        }
+        m.off[x] = o;
+        m.cap[x] = c;
+        o += c;
+    }
+}
+
+__device__ __forceinline__ bool queue_push(const MsgArgs& a, const QueueMap& m, int32_t u) {
+    const int x = m.phys[u & 7];
+    unsigned long long* q = a.qslots + m.off[x];
+    const uint32_t t = __hip_atomic_fetch_add(&a.qtail[x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned long long* sl = &q[t & (uint32_t)(m.cap[x] - 1)];
+    const int64_t t0 = wall_clock64();
+    while ((uint32_t)(__hip_atomic_load(sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32) != t) {
+        if (wall_clock64() - t0 > a.wait_ticks) {
+            __hip_atomic_fetch_or(a.err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __hip_atomic_store(sl, ((unsigned long long)(t + 1u) << 32) | (uint32_t)u, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+}
+
+template <int NT, class SweepFn>
+__device__ __forceinline__ void queue_loop(const MsgArgs& a, SweepFn sweep, double* red) {
+    __shared__ QueueMap s_m;
+    __shared__ int32_t s_tile, s_stop;
+    const int32_t G = gridDim.x, w = blockIdx.x;
+    unsigned int* qmask = a.qhead + 16;
+    // launch start: find the XCDs this launch runs on, lay out the queues
+    // and queue every tile for its next step
+    if (threadIdx.x == 0)
+        __hip_atomic_fetch_or(qmask, 1u << (__builtin_amdgcn_s_getreg(kXccIdReg) & 7), __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT);
+    if (!grid_barrier(a.bar, a.err, a.wait_ticks)) return;
+    if (threadIdx.x == 0) queue_map(__hip_atomic_load(qmask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), a.ntiles, s_m);
+    __syncthreads();
+    const int64_t stride = (int64_t)G * NT, gtid = (int64_t)w * NT + threadIdx.x;
+    for (int64_t i = gtid; i < a.ntiles; i += stride) {
+        const int32_t u = (int32_t)i, x = s_m.phys[u & 7], pos = s_m.pre[u & 7] + (u >> 3);
+        a.qslots[s_m.off[x] + pos] = ((unsigned long long)(pos + 1) << 32) | (uint32_t)u;
+        a.pend[2 * u] = 0;
+        a.pend[2 * u + 1] = 0;
+    }
+    for (int x = 0; x < 8; ++x)
+        for (int64_t i = s_m.n[x] + gtid; i < s_m.cap[x]; i += stride)
+            a.qslots[s_m.off[x] + i] = (unsigned long long)i << 32;
+    if (w == 0 && threadIdx.x < 8) {
+        a.qhead[threadIdx.x] = 0u;
+        a.qtail[threadIdx.x] = (uint32_t)s_m.n[threadIdx.x];
+    }
+    if (!grid_barrier(a.bar, a.err, a.wait_ticks)) return;
+
+    const int x = (int)(__builtin_amdgcn_s_getreg(kXccIdReg) & 7);
+    const uint32_t total = (uint32_t)s_m.n[x] * (uint32_t)a.qsteps;
+    const uint32_t qm = (uint32_t)(s_m.cap[x] - 1);
+    unsigned long long* q = a.qslots + s_m.off[x];
+    const int32_t tgt = ld_rlx(&a.target[0]);
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int32_t tile = -1, stop = 0;
+            const uint32_t t = __hip_atomic_fetch_add(&a.qhead[x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (t >= total) {
+                stop = 1;
+            } else {
+                unsigned long long* sl = &q[t & qm];
+                const int64_t t0 = wall_clock64();
+                for (;;) {
+                    const unsigned long long v = __hip_atomic_load(sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if ((uint32_t)(v >> 32) == t + 1u) {
+                        tile = (int32_t)(uint32_t)v;
+                        break;
+                    }
+                    if (wall_clock64() - t0 > a.wait_ticks ||
+                        __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                        __hip_atomic_fetch_or(a.err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        stop = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+                if (tile >= 0) {
+                    // free the slot for ticket t + cap
+                    __hip_atomic_store(sl, (unsigned long long)(t + qm + 1u) << 32, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    // acquire side: the neighbours' step data
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                }
+            }
+            s_tile = tile;
+            s_stop = stop;
+        }
+        __syncthreads();
+        if (s_stop) break;
+        const int32_t c = s_tile;
+        const int32_t step = ld_rlx(&a.done[c]);
+        const double r = sweep(c, step);
+        const int32_t ns = step + 1;
+        if (ns == tgt) wg_residual<double, NT>(r, &a.res[ns & 1], red);
+        wg_stores_done();
+        if (threadIdx.x < 64) {
+            const int lane = threadIdx.x;
+            const int32_t q0 = a.dep_ptr[c], cnt = a.dep_ptr[c + 1] - q0 + 1;
+            const int32_t xc = s_m.phys[c & 7];
+            // only a tile read from another XCD needs the L2 written back
+            bool cross = false;
+            for (int32_t i = lane; i < cnt - 1; i += 64) cross |= s_m.phys[a.dep_idx[q0 + i] & 7] != xc;
+            cross = __ballot(cross) != 0ull;
+            if (lane == 0) {
+                if (cross) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __hip_atomic_store(&a.done[c], ns, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // the step counter lands before any count it enables
+                __builtin_amdgcn_s_waitcnt(0);
+            }
+            if (ns < tgt) {
+                // this finish counts for c and for every tile that reads c
+                for (int32_t i = lane; i < cnt; i += 64) {
+                    const int32_t u = i == 0 ? c : a.dep_idx[q0 + i - 1];
+                    const int32_t need = a.dep_ptr[u + 1] - a.dep_ptr[u] + 1;
+                    const int32_t prev =
+                        __hip_atomic_fetch_add(&a.pend[2 * u + (ns & 1)], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if ((prev + 1) % need == 0) queue_push(a, s_m, u);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Minimum waves per SIMD the scheduler kernels are compiled for (0 = the
 // compiler's choice).
 #ifndef OD_SCHED_WAVES
@@ -755,7 +930,11 @@ __global__ void __launch_bounds__((TX / V16<T>::N) * TY) OD_SCHED_OCC k_msgdrive
         for (int rep = 0; rep < reps; ++rep) r = sweep_tile<T, TX, TY>(arena, a.blocks, t, step & 1, lds, a.hints);
         return (double)r;
     };
-    msg_loop<S::NT>(a, sweep, red);
+    if (a.pend) {
+        queue_loop<S::NT>(a, sweep, red);
+    } else {
+        msg_loop<S::NT>(a, sweep, red);
+    }
 }
 
 // Serving: tiles of independent fp64 and fp32 solves in one launch.  The two
@@ -911,6 +1090,15 @@ hipError_t launch_msgdriven(int dtype_bytes, int tx, int ty, hipStream_t st, int
     OD_VARIANTS_F32(OD_LAUNCH)
 #undef OD_LAUNCH
     return hipErrorInvalidValue;
+}
+
+__global__ void k_queue_init(MsgArgs a) {
+    if (threadIdx.x == 0) a.qhead[16] = 0u;   // present-XCD mask, filled at launch start
+}
+
+hipError_t launch_queue_init(hipStream_t st, const MsgArgs& a) {
+    hipLaunchKernelGGL(k_queue_init, dim3(1), dim3(64), 0, st, a);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -114,8 +114,20 @@ struct MsgArgs {
     uint8_t* xpub;              // per launch position: 1 = some dependent lives on another XCD
     const int32_t* tile_pos;    // tile id -> launch position (null => identity)
     unsigned int* bar;          // 2 words for the start barrier (count, generation)
+    // dependency-counting scheduler (plain grids; null => the scanning
+    // loop): pend = 2 counters per tile, qslots = 2 * ntiles + 8 queue
+    // slots, qhead = 17 words (heads, then qtail = tails, then the mask of
+    // present XCDs), qsteps = steps this launch runs
+    int32_t* pend;
+    unsigned long long* qslots;
+    unsigned int* qhead;
+    unsigned int* qtail;
+    int32_t qsteps;
 };
 hipError_t launch_msgdriven(int dtype_bytes, int tx, int ty, hipStream_t st, int grid, const MsgArgs& a);
+// Clear the present-XCD mask of a dependency-counting message-driven
+// launch (the launch itself lays out and fills its queues).
+hipError_t launch_queue_init(hipStream_t st, const MsgArgs& a);
 constexpr int kMaxLaunchWgs = 8192;   // bound of a cooperative launch's workgroups (wg_xcd entries)
 
 // Serving kernel: fp64 tiles of (kServeTx8, kServeTy8) and fp32 tiles of

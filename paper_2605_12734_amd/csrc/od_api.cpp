@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -51,6 +52,13 @@ struct Carver {
         return o;
     }
 };
+
+// Message-driven scheduler of plain grids: dependency counters + XCD
+// queues (default), or the owner scan (OD_MSG_SCHED=scan).
+bool msg_queue_sched() {
+    const char* v = std::getenv("OD_MSG_SCHED");
+    return !(v && std::string(v) == "scan");
+}
 
 int32_t pitch_of(int32_t ex, int s) {
     const int32_t q = 64 / s;   // 64-byte rows
@@ -328,6 +336,14 @@ std::string build_layout(const od_config& cfg, Grid& G) {
     }
     G.L.wgxcd = cv.take(cfg.exec == OD_MSGDRIVEN ? (size_t)kMaxLaunchWgs * 4 : 4);
     G.L.xpub = cv.take(cfg.exec == OD_MSGDRIVEN ? ntiles : 1);
+    G.L.qsched = false;
+    if (cfg.exec == OD_MSGDRIVEN && msg_queue_sched()) {
+        // per present XCD a ring of the next power of two >= its tile count
+        G.L.qsched = true;
+        G.L.pend = cv.take(ntiles * 2 * 4);
+        G.L.qslots = cv.take((2 * ntiles + 8) * 8);
+        G.L.qctl = cv.take(17 * 4);
+    }
     G.L.dep_ptr = cv.take((G.dep_ptr.size() + 1) * 4);
     G.L.dep_idx = cv.take((G.dep_idx.size() + 1) * 4);
     // imbalance table
@@ -489,6 +505,29 @@ std::string build_tile_deps(const Plan& p, std::vector<int32_t>& ptr, std::vecto
         deps.erase(std::unique(deps.begin(), deps.end()), deps.end());
         idx.insert(idx.end(), deps.begin(), deps.end());
         ptr[i + 1] = (int32_t)idx.size();
+    }
+    // The schedulers need the relation symmetric (a tile waits for the
+    // tiles that read it before overwriting a parity, and counts its finish
+    // for them): add any missing reverse edge.
+    std::vector<std::vector<int32_t>> adj(T);
+    bool sym = true;
+    for (size_t i = 0; i < T; ++i)
+        for (int32_t q = ptr[i]; q < ptr[i + 1]; ++q) {
+            const int32_t j = idx[(size_t)q];
+            adj[i].push_back(j);
+            if (!std::binary_search(idx.begin() + ptr[(size_t)j], idx.begin() + ptr[(size_t)j + 1], (int32_t)i)) {
+                adj[(size_t)j].push_back((int32_t)i);
+                sym = false;
+            }
+        }
+    if (!sym) {
+        idx.clear();
+        for (size_t i = 0; i < T; ++i) {
+            std::sort(adj[i].begin(), adj[i].end());
+            adj[i].erase(std::unique(adj[i].begin(), adj[i].end()), adj[i].end());
+            idx.insert(idx.end(), adj[i].begin(), adj[i].end());
+            ptr[i + 1] = (int32_t)idx.size();
+        }
     }
     return "";
 }
@@ -706,6 +745,15 @@ od_status Grid::msgdriven_run(int64_t n) {
     a.xpub = reinterpret_cast<uint8_t*>(base + L.xpub);
     a.tile_pos = nullptr;
     a.bar = reinterpret_cast<unsigned int*>(base + L.bar);
+    if (L.qsched) {
+        a.pend = reinterpret_cast<int32_t*>(base + L.pend);
+        a.qslots = reinterpret_cast<unsigned long long*>(base + L.qslots);
+        a.qhead = reinterpret_cast<unsigned int*>(base + L.qctl);
+        a.qtail = a.qhead + kNumXcd;
+        a.qsteps = (int32_t)n;
+        e = launch_queue_init(st, a);
+        if (e != hipSuccess) return fail(OD_EHIP, std::string("queue init: ") + hipGetErrorString(e));
+    }
     e = launch_msgdriven(s, plan.tile[0], plan.tile[1], st, grid_wgs, a);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("msg-driven launch: ") + hipGetErrorString(e));
     parity = tgt & 1;
