@@ -742,14 +742,21 @@ __device__ __forceinline__ void msg_loop(const MsgArgs& a, SweepFn sweep, double
 // XCD g, or, if no workgroup of the launch runs on XCD g, of a present XCD
 // (the groups of absent XCDs are dealt round-robin over the present ones).
 // The workgroups of an XCD pop from its queue only, so a tile always runs
-// on one XCD and needs an L2 write-back only if some tile that reads it is
-// queued on another.  Every tile is queued once per step; a workgroup
-// whose pop ticket passes its queue's total leaves.  Every wait is bounded
-// (error flag 2).
+// on one XCD.  Every tile is queued once per step; a workgroup whose pop
+// ticket passes its queue's total leaves.  Every wait is bounded (error
+// flag 2).
 //
-// Queue x: ring of cap_x (power of two >= its tile count, so a push never
-// waits for good) 64-bit slots (sequence << 32 | tile) at qslots + off_x;
-// ticket counters qhead[x], qtail[x]; qhead[16] = mask of present XCDs.
+// Publication.  A tile read only by tiles of its own XCD is published by
+// the XCD's L2 (every wave drains its stores first).  A tile read from
+// another XCD ("cross" tile) needs the L2 written back before its counts
+// go out.  An XCD with enough workgroups sets one of them aside as its
+// publisher: workers hand finished cross tiles to it through a list, and
+// it writes the L2 back once per batch of up to 64 tiles, then counts
+// them.  On an XCD with few workgroups each worker writes back itself.
+//
+// Queue / list x: ring of cap_x (power of two >= its tile count, so a push
+// never waits for good) 64-bit slots (sequence << 32 | tile) at
+// qslots + off_x (ready queue) and pslots + off_x (cross list).
 struct QueueMap {
     int32_t phys[8];   // queue (XCD) of tile group g
     int32_t off[8];    // first slot of queue x
@@ -757,6 +764,9 @@ struct QueueMap {
     int32_t n[8];      // tiles of queue x
     int32_t pre[8];    // queue position of the first tile of group g
 };
+
+constexpr int kQcHead = 0, kQcTail = 8, kQcMask = 16, kQcWgs = 24, kQcPTail = 32, kQcCross = 40;
+constexpr uint32_t kPublisherMinWgs = 4;   // workgroups an XCD needs to set one aside as publisher
 
 __device__ __forceinline__ void queue_map(uint32_t mask, int32_t ntiles, QueueMap& m) {
     int32_t pres[8], np = 0;
@@ -781,11 +791,11 @@ __device__ __forceinline__ void queue_map(uint32_t mask, int32_t ntiles, QueueMa
     }
 }
 
-__device__ __forceinline__ bool queue_push(const MsgArgs& a, const QueueMap& m, int32_t u) {
-    const int x = m.phys[u & 7];
-    unsigned long long* q = a.qslots + m.off[x];
-    const uint32_t t = __hip_atomic_fetch_add(&a.qtail[x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned long long* sl = &q[t & (uint32_t)(m.cap[x] - 1)];
+// Append u to ring (base, cap) at a fresh ticket of *tail.
+__device__ __forceinline__ bool ring_push(const MsgArgs& a, unsigned long long* q, uint32_t cap, unsigned int* tail,
+                                          int32_t u) {
+    const uint32_t t = __hip_atomic_fetch_add(tail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned long long* sl = &q[t & (cap - 1u)];
     const int64_t t0 = wall_clock64();
     while ((uint32_t)(__hip_atomic_load(sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32) != t) {
         if (wall_clock64() - t0 > a.wait_ticks) {
@@ -799,106 +809,166 @@ __device__ __forceinline__ bool queue_push(const MsgArgs& a, const QueueMap& m, 
     return true;
 }
 
+// Take ticket t's entry of ring (base, cap): wait until it is filled, free
+// the slot for ticket t + cap.  Returns -1 on timeout or a raised error.
+__device__ __forceinline__ int32_t ring_take(const MsgArgs& a, unsigned long long* q, uint32_t cap, uint32_t t) {
+    unsigned long long* sl = &q[t & (cap - 1u)];
+    const int64_t t0 = wall_clock64();
+    for (;;) {
+        const unsigned long long v = __hip_atomic_load(sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)(v >> 32) == t + 1u) {
+            __hip_atomic_store(sl, (unsigned long long)(t + cap) << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return (int32_t)(uint32_t)v;
+        }
+        if (wall_clock64() - t0 > a.wait_ticks ||
+            __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+            __hip_atomic_fetch_or(a.err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return -1;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
+// Count finish ns of tile c for its i-th counter (i = 0: c itself, else its
+// (i-1)-th reader); queue the tile whose counter this completes.
+__device__ __forceinline__ void count_finish(const MsgArgs& a, const QueueMap& m, int32_t c, int32_t ns, int32_t i) {
+    const int32_t u = i == 0 ? c : a.dep_idx[a.dep_ptr[c] + i - 1];
+    const int32_t need = a.dep_ptr[u + 1] - a.dep_ptr[u] + 1;
+    const int32_t prev = __hip_atomic_fetch_add(&a.pend[2 * u + (ns & 1)], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((prev + 1) % need == 0) {
+        const int x = m.phys[u & 7];
+        ring_push(a, a.qslots + m.off[x], (uint32_t)m.cap[x], &a.qhead[kQcTail + x], u);
+    }
+}
+
+// Publisher of XCD x (wave 0 only): take the cross tiles workers list, in
+// batches of up to 64, write the L2 back once per batch, then count them.
+__device__ __forceinline__ void publisher_loop(const MsgArgs& a, const QueueMap& m, int x, uint32_t want) {
+    const int lane = threadIdx.x;
+    unsigned long long* pl = a.pslots + m.off[x];
+    const uint32_t cap = (uint32_t)m.cap[x];
+    uint32_t h = 0;
+    int64_t idle = wall_clock64();
+    while (h < want) {
+        uint32_t e = __hip_atomic_load(&a.qhead[kQcPTail + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (e > want) e = want;
+        if (e == h) {
+            if (wall_clock64() - idle > a.wait_ticks ||
+                __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                if (lane == 0) __hip_atomic_fetch_or(a.err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        if (e - h > 64u) e = h + 64u;
+        int32_t c = -1;
+        if ((uint32_t)lane < e - h) c = ring_take(a, pl, cap, h + (uint32_t)lane);
+        if (__ballot(c < 0 && (uint32_t)lane < e - h) != 0ull) return;   // timed out (flag raised)
+        // every listed worker drained its stores into this XCD's L2 before
+        // listing: one write-back publishes the whole batch
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (c >= 0) {
+            const int32_t ns = ld_rlx(&a.done[c]);
+            const int32_t cnt = a.dep_ptr[c + 1] - a.dep_ptr[c] + 1;
+            for (int32_t i = 0; i < cnt; ++i) count_finish(a, m, c, ns, i);
+        }
+        h = e;
+        idle = wall_clock64();
+    }
+}
+
 template <int NT, class SweepFn>
 __device__ __forceinline__ void queue_loop(const MsgArgs& a, SweepFn sweep, double* red) {
     __shared__ QueueMap s_m;
-    __shared__ int32_t s_tile, s_stop;
+    __shared__ int32_t s_tile, s_stop, s_role;
     const int32_t G = gridDim.x, w = blockIdx.x;
-    unsigned int* qmask = a.qhead + 16;
-    // launch start: find the XCDs this launch runs on, lay out the queues
-    // and queue every tile for its next step
-    if (threadIdx.x == 0)
-        __hip_atomic_fetch_or(qmask, 1u << (__builtin_amdgcn_s_getreg(kXccIdReg) & 7), __ATOMIC_RELAXED,
-                              __HIP_MEMORY_SCOPE_AGENT);
+    unsigned int* qc = a.qhead;
+    const int x = (int)(__builtin_amdgcn_s_getreg(kXccIdReg) & 7);
+    // launch start: find the XCDs this launch runs on (and how many
+    // workgroups each has), lay out the queues, mark the cross tiles and
+    // queue every tile for its next step
+    if (threadIdx.x == 0) {
+        const uint32_t rank = __hip_atomic_fetch_add(&qc[kQcWgs + x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_or(&qc[kQcMask], 1u << x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_role = rank == 0 ? 1 : 0;
+    }
     if (!grid_barrier(a.bar, a.err, a.wait_ticks)) return;
-    if (threadIdx.x == 0) queue_map(__hip_atomic_load(qmask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), a.ntiles, s_m);
+    if (threadIdx.x == 0) queue_map(__hip_atomic_load(&qc[kQcMask], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), a.ntiles, s_m);
     __syncthreads();
     const int64_t stride = (int64_t)G * NT, gtid = (int64_t)w * NT + threadIdx.x;
     for (int64_t i = gtid; i < a.ntiles; i += stride) {
-        const int32_t u = (int32_t)i, x = s_m.phys[u & 7], pos = s_m.pre[u & 7] + (u >> 3);
-        a.qslots[s_m.off[x] + pos] = ((unsigned long long)(pos + 1) << 32) | (uint32_t)u;
+        const int32_t u = (int32_t)i, xu = s_m.phys[u & 7], pos = s_m.pre[u & 7] + (u >> 3);
+        a.qslots[s_m.off[xu] + pos] = ((unsigned long long)(pos + 1) << 32) | (uint32_t)u;
         a.pend[2 * u] = 0;
         a.pend[2 * u + 1] = 0;
+        uint8_t cross = 0;
+        for (int32_t q = a.dep_ptr[u]; q < a.dep_ptr[u + 1]; ++q) cross |= s_m.phys[a.dep_idx[q] & 7] != xu;
+        a.xpub[u] = cross;
+        if (cross) __hip_atomic_fetch_add(&qc[kQcCross + xu], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    for (int x = 0; x < 8; ++x)
-        for (int64_t i = s_m.n[x] + gtid; i < s_m.cap[x]; i += stride)
-            a.qslots[s_m.off[x] + i] = (unsigned long long)i << 32;
-    if (w == 0 && threadIdx.x < 8) {
-        a.qhead[threadIdx.x] = 0u;
-        a.qtail[threadIdx.x] = (uint32_t)s_m.n[threadIdx.x];
+    for (int y = 0; y < 8; ++y) {
+        for (int64_t i = s_m.n[y] + gtid; i < s_m.cap[y]; i += stride)
+            a.qslots[s_m.off[y] + i] = (unsigned long long)i << 32;
+        for (int64_t i = gtid; i < s_m.cap[y]; i += stride) a.pslots[s_m.off[y] + i] = (unsigned long long)i << 32;
     }
+    if (w == 0 && threadIdx.x < 8) qc[kQcTail + threadIdx.x] = (uint32_t)s_m.n[threadIdx.x];
     if (!grid_barrier(a.bar, a.err, a.wait_ticks)) return;
 
-    const int x = (int)(__builtin_amdgcn_s_getreg(kXccIdReg) & 7);
+    const bool haspub =
+        __hip_atomic_load(&qc[kQcWgs + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= kPublisherMinWgs;
+    if (haspub && s_role) {
+        if (threadIdx.x >= 64 || a.qsteps < 2) return;
+        const uint32_t ncross = __hip_atomic_load(&qc[kQcCross + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        publisher_loop(a, s_m, x, ncross * (uint32_t)(a.qsteps - 1));
+        return;
+    }
     const uint32_t total = (uint32_t)s_m.n[x] * (uint32_t)a.qsteps;
-    const uint32_t qm = (uint32_t)(s_m.cap[x] - 1);
     unsigned long long* q = a.qslots + s_m.off[x];
+    const uint32_t cap = (uint32_t)s_m.cap[x];
     const int32_t tgt = ld_rlx(&a.target[0]);
     for (;;) {
         if (threadIdx.x == 0) {
             int32_t tile = -1, stop = 0;
-            const uint32_t t = __hip_atomic_fetch_add(&a.qhead[x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t t = __hip_atomic_fetch_add(&qc[kQcHead + x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (t >= total) {
                 stop = 1;
             } else {
-                unsigned long long* sl = &q[t & qm];
-                const int64_t t0 = wall_clock64();
-                for (;;) {
-                    const unsigned long long v = __hip_atomic_load(sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if ((uint32_t)(v >> 32) == t + 1u) {
-                        tile = (int32_t)(uint32_t)v;
-                        break;
-                    }
-                    if (wall_clock64() - t0 > a.wait_ticks ||
-                        __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                        __hip_atomic_fetch_or(a.err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        stop = 1;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(2);
-                }
-                if (tile >= 0) {
-                    // free the slot for ticket t + cap
-                    __hip_atomic_store(sl, (unsigned long long)(t + qm + 1u) << 32, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                    // acquire side: the neighbours' step data
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                }
+                tile = ring_take(a, q, cap, t);
+                if (tile < 0) stop = 1;
+                // acquire side: the neighbours' step data
+                else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             s_tile = tile;
             s_stop = stop;
         }
         __syncthreads();
         if (s_stop) break;
-        const int32_t c = s_tile;
-        const int32_t step = ld_rlx(&a.done[c]);
+        // uniform across the workgroup: keep the tile descriptor in scalar
+        // registers
+        const int32_t c = __builtin_amdgcn_readfirstlane(s_tile);
+        const int32_t step = __builtin_amdgcn_readfirstlane(ld_rlx(&a.done[c]));
         const double r = sweep(c, step);
         const int32_t ns = step + 1;
         if (ns == tgt) wg_residual<double, NT>(r, &a.res[ns & 1], red);
         wg_stores_done();
         if (threadIdx.x < 64) {
             const int lane = threadIdx.x;
-            const int32_t q0 = a.dep_ptr[c], cnt = a.dep_ptr[c + 1] - q0 + 1;
-            const int32_t xc = s_m.phys[c & 7];
-            // only a tile read from another XCD needs the L2 written back
-            bool cross = false;
-            for (int32_t i = lane; i < cnt - 1; i += 64) cross |= s_m.phys[a.dep_idx[q0 + i] & 7] != xc;
-            cross = __ballot(cross) != 0ull;
+            const bool cross = a.xpub[c] != 0;
+            const bool listed = cross && haspub && ns < tgt;
             if (lane == 0) {
-                if (cross) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                // the next run of c reads its step here; it lands before any
+                // count that lets that run start
                 __hip_atomic_store(&a.done[c], ns, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                // the step counter lands before any count it enables
+                // no publisher on this XCD: write the L2 back before counting
+                // (the launch's end publishes its last step)
+                if (cross && !haspub && ns < tgt) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                 __builtin_amdgcn_s_waitcnt(0);
+                if (listed) ring_push(a, a.pslots + s_m.off[x], cap, &qc[kQcPTail + x], c);
             }
-            if (ns < tgt) {
-                // this finish counts for c and for every tile that reads c
-                for (int32_t i = lane; i < cnt; i += 64) {
-                    const int32_t u = i == 0 ? c : a.dep_idx[q0 + i - 1];
-                    const int32_t need = a.dep_ptr[u + 1] - a.dep_ptr[u] + 1;
-                    const int32_t prev =
-                        __hip_atomic_fetch_add(&a.pend[2 * u + (ns & 1)], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if ((prev + 1) % need == 0) queue_push(a, s_m, u);
-                }
+            if (ns < tgt && !listed) {
+                const int32_t cnt = a.dep_ptr[c + 1] - a.dep_ptr[c] + 1;
+                for (int32_t i = lane; i < cnt; i += 64) count_finish(a, s_m, c, ns, i);
             }
         }
         __syncthreads();
@@ -1093,7 +1163,9 @@ hipError_t launch_msgdriven(int dtype_bytes, int tx, int ty, hipStream_t st, int
 }
 
 __global__ void k_queue_init(MsgArgs a) {
-    if (threadIdx.x == 0) a.qhead[16] = 0u;   // present-XCD mask, filled at launch start
+    // heads, tails, present-XCD mask, workgroups per XCD, list tails and
+    // cross-tile counts start at zero; the launch fills in the rest
+    a.qhead[threadIdx.x] = 0u;
 }
 
 hipError_t launch_queue_init(hipStream_t st, const MsgArgs& a) {

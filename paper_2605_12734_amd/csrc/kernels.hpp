@@ -115,18 +115,19 @@ struct MsgArgs {
     const int32_t* tile_pos;    // tile id -> launch position (null => identity)
     unsigned int* bar;          // 2 words for the start barrier (count, generation)
     // dependency-counting scheduler (plain grids; null => the scanning
-    // loop): pend = 2 counters per tile, qslots = 2 * ntiles + 8 queue
-    // slots, qhead = 17 words (heads, then qtail = tails, then the mask of
-    // present XCDs), qsteps = steps this launch runs
+    // loop): pend = 2 counters per tile; qslots, pslots = 2 * ntiles + 8
+    // ready-queue and cross-list slots; qhead = 48 control words (heads,
+    // tails, present-XCD mask, workgroups per XCD, list tails, cross tiles
+    // per XCD; 8 each except the mask); qsteps = steps this launch runs
     int32_t* pend;
     unsigned long long* qslots;
+    unsigned long long* pslots;
     unsigned int* qhead;
-    unsigned int* qtail;
     int32_t qsteps;
 };
 hipError_t launch_msgdriven(int dtype_bytes, int tx, int ty, hipStream_t st, int grid, const MsgArgs& a);
-// Clear the present-XCD mask of a dependency-counting message-driven
-// launch (the launch itself lays out and fills its queues).
+// Clear the control words of a dependency-counting message-driven launch
+// (the launch itself lays out and fills its queues).
 hipError_t launch_queue_init(hipStream_t st, const MsgArgs& a);
 constexpr int kMaxLaunchWgs = 8192;   // bound of a cooperative launch's workgroups (wg_xcd entries)
 

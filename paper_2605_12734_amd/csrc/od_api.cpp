@@ -341,8 +341,8 @@ std::string build_layout(const od_config& cfg, Grid& G) {
         // per present XCD a ring of the next power of two >= its tile count
         G.L.qsched = true;
         G.L.pend = cv.take(ntiles * 2 * 4);
-        G.L.qslots = cv.take((2 * ntiles + 8) * 8);
-        G.L.qctl = cv.take(17 * 4);
+        G.L.qslots = cv.take(2 * (2 * ntiles + 8) * 8);   // ready queues, then cross lists
+        G.L.qctl = cv.take(64 * 4);
     }
     G.L.dep_ptr = cv.take((G.dep_ptr.size() + 1) * 4);
     G.L.dep_idx = cv.take((G.dep_idx.size() + 1) * 4);
@@ -748,8 +748,8 @@ od_status Grid::msgdriven_run(int64_t n) {
     if (L.qsched) {
         a.pend = reinterpret_cast<int32_t*>(base + L.pend);
         a.qslots = reinterpret_cast<unsigned long long*>(base + L.qslots);
+        a.pslots = a.qslots + (2 * tiles_h.size() + 8);
         a.qhead = reinterpret_cast<unsigned int*>(base + L.qctl);
-        a.qtail = a.qhead + kNumXcd;
         a.qsteps = (int32_t)n;
         e = launch_queue_init(st, a);
         if (e != hipSuccess) return fail(OD_EHIP, std::string("queue init: ") + hipGetErrorString(e));
