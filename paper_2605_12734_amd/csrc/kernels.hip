@@ -1000,11 +1000,7 @@ __global__ void __launch_bounds__((TX / V16<T>::N) * TY) OD_SCHED_OCC k_msgdrive
         for (int rep = 0; rep < reps; ++rep) r = sweep_tile<T, TX, TY>(arena, a.blocks, t, step & 1, lds, a.hints);
         return (double)r;
     };
-    if (a.pend) {
-        queue_loop<S::NT>(a, sweep, red);
-    } else {
-        msg_loop<S::NT>(a, sweep, red);
-    }
+    queue_loop<S::NT>(a, sweep, red);
 }
 
 // Serving: tiles of independent fp64 and fp32 solves in one launch.  The two

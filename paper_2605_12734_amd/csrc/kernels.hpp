@@ -104,18 +104,19 @@ struct MsgArgs {
                                     // yield_poll_ticks and raises this word, which every
                                     // workgroup reads (no host-memory poll per task)
     int64_t yield_poll_ticks;
-    // XCD-aware publication (wg_xcd null => every finished task publishes
-    // with a full agent-scope release, which writes back the XCD's L2).
-    // At launch start every workgroup records its XCD, a device-wide
-    // barrier follows, and each workgroup marks its tiles whose dependents
-    // are all owned on its own XCD: those publish with a plain ordered
-    // store, since the XCD's L2 is coherent for all of its CUs.
+    // XCD-aware publication (serving; wg_xcd null => every finished task
+    // publishes with a full agent-scope release, which writes back the
+    // XCD's L2).  At launch start every workgroup records its XCD, a
+    // device-wide barrier follows, and each workgroup marks its tiles whose
+    // dependents are all owned on its own XCD: those publish with a plain
+    // ordered store, since the XCD's L2 is coherent for all of its CUs.
+    // Plain grids (k_msgdriven) mark xpub per tile at launch start.
     int32_t* wg_xcd;            // per workgroup of the launch (kMaxLaunchWgs entries)
     uint8_t* xpub;              // per launch position: 1 = some dependent lives on another XCD
     const int32_t* tile_pos;    // tile id -> launch position (null => identity)
     unsigned int* bar;          // 2 words for the start barrier (count, generation)
-    // dependency-counting scheduler (plain grids; null => the scanning
-    // loop): pend = 2 counters per tile; qslots, pslots = 2 * ntiles + 8
+    // dependency-counting scheduler of plain grids (k_msgdriven):
+    // pend = 2 counters per tile; qslots, pslots = 2 * ntiles + 8
     // ready-queue and cross-list slots; qhead = 48 control words (heads,
     // tails, present-XCD mask, workgroups per XCD, list tails, cross tiles
     // per XCD; 8 each except the mask); qsteps = steps this launch runs
@@ -129,7 +130,7 @@ hipError_t launch_msgdriven(int dtype_bytes, int tx, int ty, hipStream_t st, int
 // Clear the control words of a dependency-counting message-driven launch
 // (the launch itself lays out and fills its queues).
 hipError_t launch_queue_init(hipStream_t st, const MsgArgs& a);
-constexpr int kMaxLaunchWgs = 8192;   // bound of a cooperative launch's workgroups (wg_xcd entries)
+constexpr int kMaxLaunchWgs = 8192;   // bound of a serving launch's workgroups (wg_xcd entries)
 
 // Serving kernel: fp64 tiles of (kServeTx8, kServeTy8) and fp32 tiles of
 // (kServeTx4, kServeTy4) columns, same thread count, one cooperative launch.

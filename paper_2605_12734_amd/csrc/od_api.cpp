@@ -53,13 +53,6 @@ struct Carver {
     }
 };
 
-// Message-driven scheduler of plain grids: dependency counters + XCD
-// queues (default), or the owner scan (OD_MSG_SCHED=scan).
-bool msg_queue_sched() {
-    const char* v = std::getenv("OD_MSG_SCHED");
-    return !(v && std::string(v) == "scan");
-}
-
 int32_t pitch_of(int32_t ex, int s) {
     const int32_t q = 64 / s;   // 64-byte rows
     return (int32_t)align_up((size_t)ex, (size_t)q);
@@ -334,12 +327,10 @@ std::string build_layout(const od_config& cfg, Grid& G) {
         std::string e2 = build_tile_deps(p, G.dep_ptr, G.dep_idx);
         if (!e2.empty()) return e2;
     }
-    G.L.wgxcd = cv.take(cfg.exec == OD_MSGDRIVEN ? (size_t)kMaxLaunchWgs * 4 : 4);
     G.L.xpub = cv.take(cfg.exec == OD_MSGDRIVEN ? ntiles : 1);
-    G.L.qsched = false;
-    if (cfg.exec == OD_MSGDRIVEN && msg_queue_sched()) {
-        // per present XCD a ring of the next power of two >= its tile count
-        G.L.qsched = true;
+    if (cfg.exec == OD_MSGDRIVEN) {
+        // dependency counters; per present XCD a ready ring and a cross
+        // list of the next power of two >= its tile count
         G.L.pend = cv.take(ntiles * 2 * 4);
         G.L.qslots = cv.take(2 * (2 * ntiles + 8) * 8);   // ready queues, then cross lists
         G.L.qctl = cv.take(64 * 4);
@@ -716,7 +707,6 @@ od_status Grid::persistent_run(int64_t n) {
 
 od_status Grid::msgdriven_run(int64_t n) {
     if (grid_wgs <= 0) return fail(OD_EHIP, "message-driven kernel: no co-resident workgroups");
-    if (grid_wgs > kMaxLaunchWgs) return fail(OD_EINVAL, "message-driven launch wider than its XCD table");
     if (iters + n > INT32_MAX) return fail(OD_EINVAL, "step counters limited to 2^31 iterations");
     // target = iters + n ; the final-step residual slot (index 2) is cleared
     const int32_t tgt = (int32_t)(iters + n);
@@ -741,19 +731,16 @@ od_status Grid::msgdriven_run(int64_t n) {
     a.wait_ticks = device_wait_ticks();
     a.final_only = 1;
     a.hints = mode();
-    a.wg_xcd = reinterpret_cast<int32_t*>(base + L.wgxcd);
     a.xpub = reinterpret_cast<uint8_t*>(base + L.xpub);
     a.tile_pos = nullptr;
     a.bar = reinterpret_cast<unsigned int*>(base + L.bar);
-    if (L.qsched) {
-        a.pend = reinterpret_cast<int32_t*>(base + L.pend);
-        a.qslots = reinterpret_cast<unsigned long long*>(base + L.qslots);
-        a.pslots = a.qslots + (2 * tiles_h.size() + 8);
-        a.qhead = reinterpret_cast<unsigned int*>(base + L.qctl);
-        a.qsteps = (int32_t)n;
-        e = launch_queue_init(st, a);
-        if (e != hipSuccess) return fail(OD_EHIP, std::string("queue init: ") + hipGetErrorString(e));
-    }
+    a.pend = reinterpret_cast<int32_t*>(base + L.pend);
+    a.qslots = reinterpret_cast<unsigned long long*>(base + L.qslots);
+    a.pslots = a.qslots + (2 * tiles_h.size() + 8);
+    a.qhead = reinterpret_cast<unsigned int*>(base + L.qctl);
+    a.qsteps = (int32_t)n;
+    e = launch_queue_init(st, a);
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("queue init: ") + hipGetErrorString(e));
     e = launch_msgdriven(s, plan.tile[0], plan.tile[1], st, grid_wgs, a);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("msg-driven launch: ") + hipGetErrorString(e));
     parity = tgt & 1;

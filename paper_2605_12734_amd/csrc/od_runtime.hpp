@@ -22,9 +22,8 @@ struct Layout {
     size_t blocks = 0, tiles = 0, cidx[3] = {0, 0, 0}, owner = 0, corigin = 0, dir_pb = 0;
     size_t pb_face = 0, pb_block = 0, bc = 0, res = 0, bar = 0, err = 0, done = 0, target = 0;
     size_t dep_ptr = 0, dep_idx = 0, extra = 0, field_end = 0, total = 0;
-    size_t ccell = 0, segs = 0, wgxcd = 0, xpub = 0;
+    size_t ccell = 0, segs = 0, xpub = 0;
     size_t pend = 0, qslots = 0, qctl = 0;   // message-driven dependency counters and XCD queues
-    bool qsched = false;                     // dependency-counting scheduler (else the owner scan)
 };
 
 // Per-chare baseline message buffers (byte offsets): outgoing face messages
