@@ -544,193 +544,7 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
 }
 
 // ---------------------------------------------------------------------------
-// message-driven scheduler: every workgroup owns the tiles w, w+G, w+2G, ...
-// of the launch's tile list (same XCD group as w) and repeatedly runs
-// whichever owned tile is ready: tile t may run step s+1 once every tile it
-// reads halos from has completed step s (t itself has, by definition).
-// Because halo reads are symmetric, the same rule guarantees that nobody
-// still reads the parity a tile overwrites.  Serving adds per-solve decision
-// steps (multiples of check_every, and the cap): every tile of the solve
-// waits there until the last one to finish evaluates the solve's residual
-// and either stops the solve or opens the gate.
-
-// One scheduler loop; `sweep(gid, step)` runs tile gid's step (reading
-// parity step & 1) with the whole workgroup and returns its residual.
-// Wave 0 looks for a ready tile, 64 owned tiles at a time (one per lane,
-// starting after the last tile run), and takes the first ready one.
-// Launch start of the XCD-aware publication: record this workgroup's XCD,
-// meet every other workgroup, then mark each owned launch position whose
-// tile has a dependent owned on another XCD (or outside the launch).
-// Returns false if the start barrier timed out.
-template <int NT>
-__device__ __forceinline__ bool mark_cross_xcd(const MsgArgs& a, int32_t nown) {
-    const int32_t G = gridDim.x, w = blockIdx.x;
-    if (threadIdx.x == 0)
-        __hip_atomic_store(&a.wg_xcd[w], (int32_t)(__builtin_amdgcn_s_getreg(kXccIdReg) & 0xF), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    if (!grid_barrier(a.bar, a.err, a.wait_ticks)) return false;
-    const int32_t mine = ld_rlx(&a.wg_xcd[w]);
-    for (int32_t j = threadIdx.x; j < nown; j += NT) {
-        const int32_t pos = w + j * G;
-        const int32_t ti = a.tile_list ? a.tile_list[pos] : pos;
-        if (ti < 0) continue;   // padding entry of a serving launch
-        uint8_t cross = 0;
-        const int32_t q1 = a.dep_ptr[ti + 1];
-        for (int32_t q = a.dep_ptr[ti]; q < q1; ++q) {
-            const int32_t dt = a.dep_idx[q];
-            const int32_t dp = a.tile_pos ? a.tile_pos[dt] : dt;
-            if (dp < 0 || dp >= a.ntiles || ld_rlx(&a.wg_xcd[dp % G]) != mine) cross = 1;
-        }
-        a.xpub[pos] = cross;
-    }
-    __syncthreads();
-    return true;
-}
-
-template <int NT, class SweepFn>
-__device__ __forceinline__ void msg_loop(const MsgArgs& a, SweepFn sweep, double* red) {
-    __shared__ int32_t s_pick, s_step, s_stop;
-    const int32_t G = gridDim.x;
-    const int32_t w = blockIdx.x;
-    const int32_t nown = a.ntiles > w ? (a.ntiles - w + G - 1) / G : 0;
-    if (a.wg_xcd && !mark_cross_xcd<NT>(a, nown)) return;
-    int32_t cursor = 0;
-    int64_t idle_since = -1;
-    int64_t last_poll = 0;
-    for (;;) {
-        if (threadIdx.x < 64) {
-            const int lane = threadIdx.x;
-            int32_t pick = -1, step = 0;
-            bool live_any = false;
-            for (int32_t base = 0; base < nown && pick < 0; base += 64) {
-                const int32_t k = base + lane;
-                bool live = false, ready = false;
-                int32_t ti = 0, d = 0, j = 0;
-                if (k < nown) {
-                    j = cursor + k < nown ? cursor + k : cursor + k - nown;
-                    const int32_t li = w + j * G;
-                    ti = a.tile_list ? a.tile_list[li] : li;
-                }
-                if (k < nown && ti >= 0) {   // negative: padding entry of a serving launch
-                    const int32_t sv = a.tile_solve ? a.tile_solve[ti] : 0;
-                    d = ld_rlx(&a.done[ti]);
-                    int32_t tgt = ld_rlx(&a.target[sv]);
-                    if (a.final_step) {
-                        const int32_t fs = ld_rlx(&a.final_step[sv]);
-                        if (fs > 0) tgt = fs;
-                    }
-                    live = d < tgt;
-                    ready = live;
-                    if (ready && a.gate) {
-                        const int32_t ce = a.check_every[sv];
-                        if (ce > 0 && d > 0 && d % ce == 0) ready = ld_rlx(&a.gate[sv]) >= d;
-                    }
-                    if (ready) {
-                        const int32_t q1 = a.dep_ptr[ti + 1];
-                        for (int32_t q = a.dep_ptr[ti]; q < q1; ++q) ready &= ld_rlx(&a.done[a.dep_idx[q]]) >= d;
-                    }
-                }
-                live_any = live_any || __ballot(live) != 0ull;
-                const unsigned long long m = __ballot(ready);
-                if (m != 0ull) {
-                    const int src = __ffsll((unsigned long long)m) - 1;
-                    pick = __shfl(ti, src, 64);
-                    step = __shfl(d, src, 64);
-                    const int32_t pj = __shfl(j, src, 64);
-                    cursor = pj + 1 < nown ? pj + 1 : 0;
-                }
-            }
-            if (lane == 0) {
-                int32_t stop = live_any ? 0 : 1;
-                // the host asks the launch to end: start no new task (every
-                // tile's state stays in HBM, a later launch resumes from it)
-                if (a.yield_dev) {
-                    if (w == 0) {
-                        const int64_t now = wall_clock64();
-                        if (now - last_poll >= a.yield_poll_ticks) {
-                            last_poll = now;
-                            if (__hip_atomic_load(a.yield_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0)
-                                __hip_atomic_store(a.yield_dev, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        }
-                    }
-                    if (__hip_atomic_load(a.yield_dev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
-                        stop = 1, pick = -1;
-                }
-                if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) stop = 1, pick = -1;
-                // acquire side: the step-`step` data of the tiles whose
-                // counters were just read
-                if (pick >= 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                s_pick = pick;
-                s_step = step;
-                s_stop = stop;
-            }
-        }
-        __syncthreads();
-        const int32_t pick = s_pick, step = s_step;
-        if (pick < 0) {
-            if (s_stop) break;
-            // bounded wait: give up (error flag 2) after wait_ticks of idling
-            const int64_t now = wall_clock64();
-            if (idle_since < 0) idle_since = now;
-            if (now - idle_since > a.wait_ticks) {
-                if (threadIdx.x == 0) __hip_atomic_fetch_or(a.err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(4);
-            __syncthreads();
-            continue;
-        }
-        idle_since = -1;
-        const int32_t sv = a.tile_solve ? a.tile_solve[pick] : 0;
-        const double r = sweep(pick, step);
-        const int32_t ns = step + 1;
-        const int32_t tgt = ld_rlx(&a.target[sv]);
-        const int32_t ce = a.check_every ? a.check_every[sv] : 0;
-        // A plain grid records only its target step's residual (slot ns & 1,
-        // cleared before the launch).  A served solve records it at decision
-        // steps, where every tile of the solve waits for the decision, so one
-        // slot per solve suffices.
-        if (a.final_only) {
-            if (ns == tgt) wg_residual<double, NT>(r, &a.res[2 * sv + (ns & 1)], red);
-        } else {
-            if ((ce > 0 && ns % ce == 0) || ns == tgt) wg_residual<double, NT>(r, &a.res[sv], red);
-        }
-        wg_stores_done();
-        if (threadIdx.x == 0) {
-            // release side: this tile's step-ns data before its counter.
-            // Every wave has drained its stores into the XCD's L2; only a
-            // tile read from another XCD needs the L2 written back.
-            if (!a.xpub || a.xpub[a.tile_pos ? a.tile_pos[pick] : pick])
-                __hip_atomic_store(&a.done[pick], ns, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            else
-                __hip_atomic_store(&a.done[pick], ns, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (a.solve_count && ((ce > 0 && ns % ce == 0) || ns == tgt)) {
-                int32_t* cnt = &a.solve_count[sv];
-                // the residual max above has completed (drained with the
-                // stores); the decision maker's exchange reads it
-                const int32_t prev = __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (prev == a.solve_ntiles[sv] - 1) {
-                    // last tile of the solve to finish decision step ns
-                    __hip_atomic_store(cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    const unsigned long long rb =
-                        __hip_atomic_exchange(&a.res[sv], 0ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-                    const double rv = __longlong_as_double((long long)rb);
-                    const bool fin = ns >= tgt || (ce > 0 && ns % ce == 0 && rv < a.tol[sv]);
-                    if (fin) {
-                        __hip_atomic_store(&a.final_step[sv], ns, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                        __threadfence_system();
-                        if (a.host_res) a.host_res[sv] = rb;
-                        if (a.host_done) a.host_done[sv] = ns;
-                        __threadfence_system();
-                    } else {
-                        __hip_atomic_store(&a.gate[sv], ns, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                }
-            }
-        }
-        __syncthreads();
-    }
-}
+// message-driven schedulers
 
 // Dependency-counting scheduler of a plain grid.  Tile c may run step k
 // once it and every tile it reads halos from have finished step k-1.  The
@@ -765,8 +579,14 @@ struct QueueMap {
     int32_t pre[8];    // queue position of the first tile of group g
 };
 
-constexpr int kQcHead = 0, kQcTail = 8, kQcMask = 16, kQcWgs = 24, kQcPTail = 32, kQcCross = 40;
-constexpr uint32_t kPublisherMinWgs = 4;   // workgroups an XCD needs to set one aside as publisher
+constexpr int kQcHead = 0, kQcTail = 8, kQcMask = 16, kQcWgs = 24, kQcPTail = 32, kQcCross = 40, kQcLive = 48;
+// An XCD sets a workgroup aside as publisher when it has at least 8 and
+// at least two tasks per workgroup and step: then throughput matters more
+// than the extra hop on the critical path (a small launch is bound by the
+// latency of its dependency chain, and writes back itself).
+__device__ __forceinline__ bool use_publisher(uint32_t wgs, uint32_t ntasks) {
+    return wgs >= 8u && ntasks >= 2u * wgs;
+}
 
 __device__ __forceinline__ void queue_map(uint32_t mask, int32_t ntiles, QueueMap& m) {
     int32_t pres[8], np = 0;
@@ -791,13 +611,20 @@ __device__ __forceinline__ void queue_map(uint32_t mask, int32_t ntiles, QueueMa
     }
 }
 
-// Append u to ring (base, cap) at a fresh ticket of *tail.
+struct NoQuit {
+    __device__ bool operator()() const { return false; }
+};
+
+// Append u to ring (base, cap) at a fresh ticket of *tail.  Gives up
+// (false) when quit() turns true, or raises error flag 2 on timeout.
+template <class Quit = NoQuit>
 __device__ __forceinline__ bool ring_push(const MsgArgs& a, unsigned long long* q, uint32_t cap, unsigned int* tail,
-                                          int32_t u) {
+                                          int32_t u, Quit quit = Quit()) {
     const uint32_t t = __hip_atomic_fetch_add(tail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     unsigned long long* sl = &q[t & (cap - 1u)];
     const int64_t t0 = wall_clock64();
     while ((uint32_t)(__hip_atomic_load(sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32) != t) {
+        if (quit()) return false;
         if (wall_clock64() - t0 > a.wait_ticks) {
             __hip_atomic_fetch_or(a.err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
@@ -810,8 +637,11 @@ __device__ __forceinline__ bool ring_push(const MsgArgs& a, unsigned long long* 
 }
 
 // Take ticket t's entry of ring (base, cap): wait until it is filled, free
-// the slot for ticket t + cap.  Returns -1 on timeout or a raised error.
-__device__ __forceinline__ int32_t ring_take(const MsgArgs& a, unsigned long long* q, uint32_t cap, uint32_t t) {
+// the slot for ticket t + cap.  Returns -1 when quit() turns true, or on
+// timeout or a raised error (then error flag 2 is raised).
+template <class Quit = NoQuit>
+__device__ __forceinline__ int32_t ring_take(const MsgArgs& a, unsigned long long* q, uint32_t cap, uint32_t t,
+                                             Quit quit = Quit()) {
     unsigned long long* sl = &q[t & (cap - 1u)];
     const int64_t t0 = wall_clock64();
     for (;;) {
@@ -820,6 +650,7 @@ __device__ __forceinline__ int32_t ring_take(const MsgArgs& a, unsigned long lon
             __hip_atomic_store(sl, (unsigned long long)(t + cap) << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return (int32_t)(uint32_t)v;
         }
+        if (quit()) return -1;
         if (wall_clock64() - t0 > a.wait_ticks ||
             __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
             __hip_atomic_fetch_or(a.err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -915,8 +746,8 @@ __device__ __forceinline__ void queue_loop(const MsgArgs& a, SweepFn sweep, doub
     if (w == 0 && threadIdx.x < 8) qc[kQcTail + threadIdx.x] = (uint32_t)s_m.n[threadIdx.x];
     if (!grid_barrier(a.bar, a.err, a.wait_ticks)) return;
 
-    const bool haspub =
-        __hip_atomic_load(&qc[kQcWgs + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= kPublisherMinWgs;
+    const bool haspub = use_publisher(__hip_atomic_load(&qc[kQcWgs + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                                      (uint32_t)s_m.n[x]);
     if (haspub && s_role) {
         if (threadIdx.x >= 64 || a.qsteps < 2) return;
         const uint32_t ncross = __hip_atomic_load(&qc[kQcCross + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -975,6 +806,231 @@ __device__ __forceinline__ void queue_loop(const MsgArgs& a, SweepFn sweep, doub
     }
 }
 
+// Serving with the same queues.  Launch positions u index the launch's
+// tile list (solves back to back, each padded to a multiple of 8, so a
+// solve keeps its XCD groups); counters and steps are per tile id.
+// Differences from a plain grid:
+//  * decision steps (multiples of the solve's check_every, and its cap):
+//    those finishes are not counted; the last tile of the solve to finish
+//    one evaluates the residual, and either stops the solve or opens its
+//    gate and queues every tile of the solve;
+//  * a launch ends early when the host asks (yield) or every solve has
+//    stopped, so queued tasks and uncounted finishes may be dropped.  At
+//    launch start the counters are therefore rebuilt from the step
+//    counters (the finishes each tile's current and next round already
+//    have) and every ready tile is queued.
+// Workgroup 0 forwards the host's yield flag to the device word, at most
+// once per yield_poll_ticks (every workgroup reads the device word).
+__device__ __forceinline__ void serve_poll_yield(const MsgArgs& a, int64_t& last_poll) {
+    if (blockIdx.x != 0) return;
+    const int64_t now = wall_clock64();
+    if (now - last_poll < a.yield_poll_ticks) return;
+    last_poll = now;
+    if (__hip_atomic_load(a.yield_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0)
+        __hip_atomic_store(a.yield_dev, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The launch is ending: the host asked to yield, or every solve stopped.
+struct ServeQuit {
+    const MsgArgs* a;
+    int64_t* last_poll;
+    __device__ bool operator()() const {
+        serve_poll_yield(*a, *last_poll);
+        return __hip_atomic_load(a->yield_dev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+               __hip_atomic_load(&a->qhead[kQcLive], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
+    }
+};
+
+__device__ __forceinline__ bool serve_decision(const MsgArgs& a, int32_t sv, int32_t ns) {
+    const int32_t ce = a.check_every[sv];
+    return (ce > 0 && ns % ce == 0) || ns >= a.target[sv];
+}
+
+// Count ordinary finish ns of tile t for counter i (0 = t, else its
+// (i-1)-th reader) and queue the reader whose round this completes.
+__device__ __forceinline__ void serve_count(const MsgArgs& a, const QueueMap& m, int32_t t, int32_t ns, int32_t i) {
+    const int32_t v = i == 0 ? t : a.dep_idx[a.dep_ptr[t] + i - 1];
+    const int32_t need = a.dep_ptr[v + 1] - a.dep_ptr[v] + 1;
+    const int32_t prev = __hip_atomic_fetch_add(&a.pend[2 * v + (ns & 1)], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((prev + 1) % need == 0) {
+        const int32_t u = a.tile_pos[v];
+        const int x = m.phys[u & 7];
+        int64_t lp = 0;
+        ring_push(a, a.qslots + m.off[x], (uint32_t)m.cap[x], &a.qhead[kQcTail + x], u, ServeQuit{&a, &lp});
+    }
+}
+
+template <int NT, class SweepFn>
+__device__ __forceinline__ void serve_loop(const MsgArgs& a, SweepFn sweep, double* red) {
+    __shared__ QueueMap s_m;
+    __shared__ int32_t s_u, s_stop, s_role;
+    const int32_t G = gridDim.x, w = blockIdx.x;
+    unsigned int* qc = a.qhead;
+    const int x = (int)(__builtin_amdgcn_s_getreg(kXccIdReg) & 7);
+    int64_t last_poll = 0;
+    const ServeQuit quit{&a, &last_poll};
+    if (threadIdx.x == 0) {
+        const uint32_t rank = __hip_atomic_fetch_add(&qc[kQcWgs + x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_or(&qc[kQcMask], 1u << x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_role = rank == 0 ? 1 : 0;
+    }
+    if (!grid_barrier(a.bar, a.err, a.wait_ticks)) return;
+    if (threadIdx.x == 0) queue_map(__hip_atomic_load(&qc[kQcMask], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), a.ntiles, s_m);
+    __syncthreads();
+    // launch start, part 1: free every slot; per position the cross flag,
+    // the rebuilt counters and whether the tile is ready (bit 1)
+    const int64_t stride = (int64_t)G * NT, gtid = (int64_t)w * NT + threadIdx.x;
+    for (int y = 0; y < 8; ++y)
+        for (int64_t i = gtid; i < s_m.cap[y]; i += stride) {
+            a.qslots[s_m.off[y] + i] = (unsigned long long)i << 32;
+            a.pslots[s_m.off[y] + i] = (unsigned long long)i << 32;
+        }
+    for (int64_t i = gtid; i < a.ntiles; i += stride) {
+        const int32_t u = (int32_t)i, t = a.tile_list[u];
+        if (t < 0) continue;
+        const int32_t sv = a.tile_solve[t], d = ld_rlx(&a.done[t]);
+        const int32_t fs = ld_rlx(&a.final_step[sv]);
+        const int32_t fin = fs > 0 ? fs : a.target[sv];
+        const int32_t ce = a.check_every[sv];
+        const int32_t xu = s_m.phys[u & 7];
+        int32_t c0 = 1, c1 = 0;
+        uint8_t cross = 0;
+        for (int32_t q = a.dep_ptr[t]; q < a.dep_ptr[t + 1]; ++q) {
+            const int32_t v = a.dep_idx[q];
+            const int32_t dv = ld_rlx(&a.done[v]);
+            c0 += dv >= d;
+            c1 += dv >= d + 1;
+            cross |= s_m.phys[a.tile_pos[v] & 7] != xu;
+        }
+        const int32_t need = a.dep_ptr[t + 1] - a.dep_ptr[t] + 1;
+        const bool gated = ce > 0 && d > 0 && d % ce == 0;
+        const bool ready = d < fin && (gated ? ld_rlx(&a.gate[sv]) >= d : c0 == need);
+        a.pend[2 * t + (d & 1)] = gated || ready ? 0 : c0;
+        a.pend[2 * t + ((d + 1) & 1)] = ce > 0 && (d + 1) % ce == 0 ? 0 : c1;
+        a.xpub[u] = cross | (ready ? 2 : 0);
+    }
+    if (w == 0 && threadIdx.x == 0) qc[kQcLive] = (uint32_t)a.nlive;
+    if (!grid_barrier(a.bar, a.err, a.wait_ticks)) return;
+    // part 2: queue the ready tiles
+    for (int64_t i = gtid; i < a.ntiles; i += stride) {
+        const int32_t u = (int32_t)i;
+        if (a.tile_list[u] < 0 || !(a.xpub[u] & 2)) continue;
+        const int xu = s_m.phys[u & 7];
+        ring_push(a, a.qslots + s_m.off[xu], (uint32_t)s_m.cap[xu], &qc[kQcTail + xu], u, quit);
+    }
+
+    const bool haspub = use_publisher(__hip_atomic_load(&qc[kQcWgs + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                                      (uint32_t)s_m.n[x]);
+    const uint32_t cap = (uint32_t)s_m.cap[x];
+    if (haspub && s_role) {
+        // publisher of XCD x: batches of listed cross tiles, one L2
+        // write-back each, then their counts; ends with the launch
+        if (threadIdx.x >= 64) return;
+        const int lane = threadIdx.x;
+        unsigned long long* pl = a.pslots + s_m.off[x];
+        uint32_t h = 0;
+        for (;;) {
+            if (quit()) return;
+            uint32_t e = __hip_atomic_load(&qc[kQcPTail + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (e == h) {
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            if (e - h > 64u) e = h + 64u;
+            int32_t u = -1;
+            if ((uint32_t)lane < e - h) u = ring_take(a, pl, cap, h + (uint32_t)lane, quit);
+            if (__ballot(u < 0 && (uint32_t)lane < e - h) != 0ull) return;   // launch ending, or timed out
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if (u >= 0) {
+                const int32_t t = a.tile_list[u];
+                const int32_t ns = ld_rlx(&a.done[t]);
+                const int32_t cnt = a.dep_ptr[t + 1] - a.dep_ptr[t] + 1;
+                for (int32_t i = 0; i < cnt; ++i) serve_count(a, s_m, t, ns, i);
+            }
+            h = e;
+        }
+    }
+    unsigned long long* q = a.qslots + s_m.off[x];
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int32_t u = -1, stop = 0;
+            if (quit() || __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                stop = 1;
+            } else {
+                const uint32_t t = __hip_atomic_fetch_add(&qc[kQcHead + x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                u = ring_take(a, q, cap, t, quit);
+                if (u < 0) stop = 1;
+                else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            s_u = u;
+            s_stop = stop;
+        }
+        __syncthreads();
+        if (s_stop) break;
+        const int32_t u = __builtin_amdgcn_readfirstlane(s_u);
+        const int32_t t = a.tile_list[u];
+        const int32_t sv = a.tile_solve[t];
+        const int32_t step = __builtin_amdgcn_readfirstlane(ld_rlx(&a.done[t]));
+        const double r = sweep(t, step);
+        const int32_t ns = step + 1;
+        const bool dec = serve_decision(a, sv, ns);
+        // decision steps record the solve's residual (every tile of the
+        // solve waits there, so one slot per solve suffices)
+        if (dec) wg_residual<double, NT>(r, &a.res[sv], red);
+        wg_stores_done();
+        if (threadIdx.x < 64) {
+            const int lane = threadIdx.x;
+            const bool cross = (a.xpub[u] & 1) != 0;
+            const bool listed = cross && haspub && !dec;
+            int32_t decided = 0;   // lane 0: 1 = the solve goes on (queue all its tiles)
+            if (lane == 0) {
+                __hip_atomic_store(&a.done[t], ns, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // a decision lets tiles of any XCD go on: publish first
+                if (cross && !listed) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __builtin_amdgcn_s_waitcnt(0);
+                if (listed) ring_push(a, a.pslots + s_m.off[x], cap, &qc[kQcPTail + x], u, quit);
+                if (dec) {
+                    int32_t* cnt = &a.solve_count[sv];
+                    const int32_t prev = __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (prev == a.solve_ntiles[sv] - 1) {
+                        // last tile of the solve to finish decision step ns
+                        __hip_atomic_store(cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const unsigned long long rb =
+                            __hip_atomic_exchange(&a.res[sv], 0ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                        const double rv = __longlong_as_double((long long)rb);
+                        const int32_t ce = a.check_every[sv];
+                        const bool fin = ns >= a.target[sv] || (ce > 0 && ns % ce == 0 && rv < a.tol[sv]);
+                        if (fin) {
+                            __hip_atomic_store(&a.final_step[sv], ns, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                            __threadfence_system();
+                            if (a.host_res) a.host_res[sv] = rb;
+                            if (a.host_done) a.host_done[sv] = ns;
+                            __threadfence_system();
+                            __hip_atomic_fetch_sub(&qc[kQcLive], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        } else {
+                            __hip_atomic_store(&a.gate[sv], ns, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                            decided = 1;
+                        }
+                    }
+                }
+            }
+            if (__shfl(decided, 0, 64)) {
+                // the solve goes on: every tile of it has finished step ns
+                const int32_t b0 = a.solve_base[sv], nt = a.solve_ntiles[sv];
+                for (int32_t i = lane; i < nt; i += 64) {
+                    const int32_t v = b0 + i;
+                    const int xv = s_m.phys[v & 7];
+                    ring_push(a, a.qslots + s_m.off[xv], (uint32_t)s_m.cap[xv], &qc[kQcTail + xv], v, quit);
+                }
+            } else if (!dec && !listed) {
+                const int32_t cnt = a.dep_ptr[t + 1] - a.dep_ptr[t] + 1;
+                for (int32_t i = lane; i < cnt; i += 64) serve_count(a, s_m, t, ns, i);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Minimum waves per SIMD the scheduler kernels are compiled for (0 = the
 // compiler's choice).
 #ifndef OD_SCHED_WAVES
@@ -1024,7 +1080,7 @@ __global__ void __launch_bounds__((TX8 / 2) * TY8) OD_SCHED_OCC k_serve(MsgArgs 
         return (double)sweep_tile<float, TX4, TY4>(reinterpret_cast<float*>(a.arena), a.blocks, t, step & 1,
                                                    reinterpret_cast<float*>(lds_raw), a.hints);
     };
-    msg_loop<S8::NT>(a, sweep, red);
+    serve_loop<S8::NT>(a, sweep, red);
 }
 
 // ---------------------------------------------------------------------------

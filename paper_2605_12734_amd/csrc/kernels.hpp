@@ -67,29 +67,29 @@ int64_t device_wait_ticks(double seconds = 10.0);
 // Max co-resident workgroups of the persistent / message-driven kernels.
 int persistent_max_grid(int dtype_bytes, int tx, int ty, int kind);
 
-// Message-driven cooperative sweep (see sched kernels): per-tile step
-// counters `done`, dependency lists (CSR: dep_ptr[ntiles+1], dep_idx).
+// Message-driven cooperative sweep: per-tile step counters `done`,
+// dependency lists (CSR: dep_ptr[ntiles+1], dep_idx; symmetric), counters
+// of finishes per tile and step parity, and per-XCD ready queues.
 struct MsgArgs {
-    const int32_t* tile_list;   // launch's tiles (global ids); null => 0..ntiles-1
+    const int32_t* tile_list;   // serving: launch position -> tile id (-1 = padding)
     const int32_t* solve_dtype; // serving: bytes per element of each solve
     void* arena;
     const BlockDev* blocks;
     const TileDev* tiles;
-    int32_t ntiles;             // tiles in this launch
+    int32_t ntiles;             // launch positions (plain grid: tiles)
     const int32_t* dep_ptr;
     const int32_t* dep_idx;
-    int32_t* done;              // steps completed per tile (monotone), by global id
+    int32_t* done;              // steps completed per tile (monotone), by tile id
     const int32_t* target;      // per-solve target step (for a plain grid: 1 entry)
-    const int32_t* tile_solve;  // solve of each tile (null => solve 0)
+    const int32_t* tile_solve;  // serving: solve of each tile
     unsigned long long* res;    // plain grid: 2 slots (step parity); serving: 1 slot per solve
     unsigned int* err;
     const uint8_t* extra;       // [period][nchares] or null
     int32_t extra_period;
     int32_t nchares;
-    int64_t wait_ticks;         // bound on a workgroup's idle wait (wall-clock ticks)
-    int32_t final_only;         // plain grid: record the residual only at the target step
+    int64_t wait_ticks;         // bound on every device-side wait (wall-clock ticks)
     int32_t hints;              // od_config.hints
-    // serving only (null for a plain grid)
+    // serving only
     int32_t* solve_count;       // per solve: tiles that finished the current decision step
     int32_t* gate;              // per solve: highest step whose check passed
     const int32_t* solve_ntiles;
@@ -104,22 +104,19 @@ struct MsgArgs {
                                     // yield_poll_ticks and raises this word, which every
                                     // workgroup reads (no host-memory poll per task)
     int64_t yield_poll_ticks;
-    // XCD-aware publication (serving; wg_xcd null => every finished task
-    // publishes with a full agent-scope release, which writes back the
-    // XCD's L2).  At launch start every workgroup records its XCD, a
-    // device-wide barrier follows, and each workgroup marks its tiles whose
-    // dependents are all owned on its own XCD: those publish with a plain
-    // ordered store, since the XCD's L2 is coherent for all of its CUs.
-    // Plain grids (k_msgdriven) mark xpub per tile at launch start.
-    int32_t* wg_xcd;            // per workgroup of the launch (kMaxLaunchWgs entries)
-    uint8_t* xpub;              // per launch position: 1 = some dependent lives on another XCD
-    const int32_t* tile_pos;    // tile id -> launch position (null => identity)
-    unsigned int* bar;          // 2 words for the start barrier (count, generation)
-    // dependency-counting scheduler of plain grids (k_msgdriven):
+    const int32_t* tile_pos;    // serving: tile id -> launch position
+    const int32_t* solve_base;  // serving: launch position of each solve's first tile
+    int32_t nlive;              // serving: running solves in the launch
+    // per launch position: bit 0 = some tile that reads it is queued on
+    // another XCD (its finish needs an L2 write-back); serving, bit 1 =
+    // ready at launch start
+    uint8_t* xpub;
+    unsigned int* bar;          // 2 words for the launch-start barriers (count, generation)
     // pend = 2 counters per tile; qslots, pslots = 2 * ntiles + 8
-    // ready-queue and cross-list slots; qhead = 48 control words (heads,
+    // ready-queue and cross-list slots; qhead = 64 control words (heads,
     // tails, present-XCD mask, workgroups per XCD, list tails, cross tiles
-    // per XCD; 8 each except the mask); qsteps = steps this launch runs
+    // per XCD, running solves; 8 each except the mask and the count);
+    // qsteps = steps a plain-grid launch runs
     int32_t* pend;
     unsigned long long* qslots;
     unsigned long long* pslots;
@@ -130,7 +127,6 @@ hipError_t launch_msgdriven(int dtype_bytes, int tx, int ty, hipStream_t st, int
 // Clear the control words of a dependency-counting message-driven launch
 // (the launch itself lays out and fills its queues).
 hipError_t launch_queue_init(hipStream_t st, const MsgArgs& a);
-constexpr int kMaxLaunchWgs = 8192;   // bound of a serving launch's workgroups (wg_xcd entries)
 
 // Serving kernel: fp64 tiles of (kServeTx8, kServeTy8) and fp32 tiles of
 // (kServeTx4, kServeTy4) columns, same thread count, one cooperative launch.

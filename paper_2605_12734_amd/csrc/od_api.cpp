@@ -729,7 +729,6 @@ od_status Grid::msgdriven_run(int64_t n) {
     a.extra_period = extra_period;
     a.nchares = (int32_t)plan.chares.size();
     a.wait_ticks = device_wait_ticks();
-    a.final_only = 1;
     a.hints = mode();
     a.xpub = reinterpret_cast<uint8_t*>(base + L.xpub);
     a.tile_pos = nullptr;

@@ -94,7 +94,8 @@ struct Server {
     // control region (byte offsets from arena)
     size_t c_blocks = 0, c_tiles = 0, c_done = 0, c_dep_ptr = 0, c_dep_idx = 0, c_tile_solve = 0;
     size_t c_target = 0, c_final = 0, c_gate = 0, c_count = 0, c_res = 0, c_ce = 0, c_tol = 0, c_ntiles = 0;
-    size_t c_dtype = 0, c_list = 0, c_err = 0, c_yield = 0, c_wgxcd = 0, c_xpub = 0, c_tpos = 0, c_bar = 0;
+    size_t c_dtype = 0, c_list = 0, c_err = 0, c_yield = 0, c_xpub = 0, c_tpos = 0, c_bar = 0;
+    size_t c_sbase = 0, c_pend = 0, c_qslots = 0, c_qctl = 0;
     size_t data_begin = 0;
     // host-coherent completion records and the yield flag
     int32_t* h_done = nullptr;
@@ -298,6 +299,7 @@ void Server::run() {
     }
     std::vector<int32_t> list;
     std::vector<int32_t> tpos((size_t)max_slots * kTileStride, -1);
+    std::vector<int32_t> sbase((size_t)max_slots, -1);
     std::vector<Request*> retiring;
     for (;;) {
         std::vector<Request*> admitted;
@@ -367,11 +369,16 @@ void Server::run() {
         // 8 entries; each solve's tiles keep their own XCD-interleaved order,
         // so a solve's XCD groups stay together
         e = hipMemcpyAsync(arena + c_list, list.data(), list.size() * 4, hipMemcpyHostToDevice, st);
-        // launch position of every tile in this epoch (XCD-aware publication)
+        // launch position of every tile and of every solve's first tile
         std::fill(tpos.begin(), tpos.end(), -1);
+        std::fill(sbase.begin(), sbase.end(), -1);
         for (size_t q = 0; q < list.size(); ++q)
-            if (list[q] >= 0) tpos[(size_t)list[q]] = (int32_t)q;
+            if (list[q] >= 0) {
+                tpos[(size_t)list[q]] = (int32_t)q;
+                if (list[q] % kTileStride == 0) sbase[(size_t)(list[q] / kTileStride)] = (int32_t)q;
+            }
         if (e == hipSuccess) e = hipMemcpyAsync(arena + c_tpos, tpos.data(), tpos.size() * 4, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(arena + c_sbase, sbase.data(), sbase.size() * 4, hipMemcpyHostToDevice, st);
         __atomic_store_n(h_yield, 0, __ATOMIC_RELEASE);
         if (e == hipSuccess) e = hipMemsetAsync(arena + c_yield, 0, 4, st);
         MsgArgs a{};
@@ -389,7 +396,6 @@ void Server::run() {
         a.res = reinterpret_cast<unsigned long long*>(arena + c_res);
         a.err = reinterpret_cast<unsigned int*>(arena + c_err);
         a.wait_ticks = wait_ticks;
-        a.final_only = 0;
         a.solve_count = reinterpret_cast<int32_t*>(arena + c_count);
         a.gate = reinterpret_cast<int32_t*>(arena + c_gate);
         a.solve_ntiles = reinterpret_cast<const int32_t*>(arena + c_ntiles);
@@ -401,12 +407,18 @@ void Server::run() {
         a.yield_flag = h_yield;
         a.yield_dev = reinterpret_cast<int32_t*>(arena + c_yield);
         a.yield_poll_ticks = yield_poll_ticks;
-        a.wg_xcd = reinterpret_cast<int32_t*>(arena + c_wgxcd);
         a.xpub = reinterpret_cast<uint8_t*>(arena + c_xpub);
         a.tile_pos = reinterpret_cast<const int32_t*>(arena + c_tpos);
+        a.solve_base = reinterpret_cast<const int32_t*>(arena + c_sbase);
+        a.nlive = (int32_t)active.size();
         a.bar = reinterpret_cast<unsigned int*>(arena + c_bar);
-        int grid = std::min<int>(std::min<int>(grid_cap, kMaxLaunchWgs), (int)list.size());
+        a.pend = reinterpret_cast<int32_t*>(arena + c_pend);
+        a.qslots = reinterpret_cast<unsigned long long*>(arena + c_qslots);
+        a.pslots = a.qslots + (2 * list.size() + 8);
+        a.qhead = reinterpret_cast<unsigned int*>(arena + c_qctl);
+        int grid = std::min<int>(grid_cap, (int)list.size());
         if (grid >= kNumXcd) grid -= grid % kNumXcd;
+        if (e == hipSuccess) e = launch_queue_init(st, a);
         t_epoch = now_s();
         if (e == hipSuccess) e = launch_serve(st, grid, a);
         if (e == hipSuccess) e = hipEventRecord(ev, st);
@@ -519,8 +531,12 @@ size_t control_layout(Server& S, int32_t max_slots) {
     S.c_list = take(ms * (kTileStride + kNumXcd) * 4);
     S.c_err = take(16);
     S.c_yield = take(16);
-    S.c_wgxcd = take((size_t)kMaxLaunchWgs * 4);
     S.c_xpub = take(ms * (kTileStride + kNumXcd));
+    S.c_sbase = take(ms * 4);
+    S.c_pend = take(ms * kTileStride * 2 * 4);
+    // ready queues, then cross lists: 2 * positions + 8 slots each
+    S.c_qslots = take(2 * (2 * ms * (kTileStride + kNumXcd) + 8) * 8);
+    S.c_qctl = take(64 * 4);
     S.c_tpos = take(ms * kTileStride * 4);
     S.c_bar = take(16);
     S.data_begin = align_up(o, kAlign);
