@@ -144,6 +144,37 @@ def test_served_384_request_matches_oracle():
     assert np.array_equal(field, want)
 
 
+def test_served_384_request_survives_yields():
+    # small requests arriving while a 384^3 solve runs end its scheduling
+    # epochs early (queued tasks dropped, counters rebuilt at the next
+    # launch); every result must still be the oracle's, bit for bit
+    import time
+    from paper_2605_12734_amd.serving import Server
+    big = dict(n=384, dtype="f64", odf=64, tol=1e-6, max_iters=60, check_every=10, seed=78)
+    small = [dict(n=20 + 3 * i, dtype=("f32", "f64")[i % 2], odf=(1, 8)[i % 2], tol=1e-4, max_iters=120,
+                  check_every=(5, 0, 1)[i % 3], seed=90 + i) for i in range(6)]
+    with Server(arena_bytes=3 << 30, max_slots=8) as srv:
+        tb = srv.submit(**big)
+        ts = []
+        for q in small:
+            time.sleep(0.004)
+            ts.append(srv.submit(**q))
+        res = srv.wait(tb, timeout=300)
+        field = srv.fetch(tb)
+        smalls = [(srv.wait(t, timeout=300), srv.fetch(t)) for t in ts]
+        epochs = srv.stats()["epochs"]
+    want, it, r = oracle.solve(384, np.float64, seed=78, iters=60, tol=1e-6, check_every=10)
+    assert res["iters"] == it and res["residual"] == r
+    assert np.array_equal(field, want)
+    for q, (rs, f) in zip(small, smalls):
+        dt = np.float32 if q["dtype"] == "f32" else np.float64
+        w, i2, r2 = oracle.solve(q["n"], dt, seed=q["seed"], iters=q["max_iters"], tol=q["tol"],
+                                 check_every=q["check_every"])
+        assert rs["iters"] == i2 and rs["residual"] == r2, q
+        assert np.array_equal(f, w), q
+    assert epochs >= 2
+
+
 @pytest.mark.parametrize("n", [(1, 1, 1), (1, 5, 1), (2, 1, 3), (3, 3, 1)])
 @pytest.mark.parametrize("exec_", ["fused", "persistent", "msgdriven", "per_chare", "graph"])
 def test_degenerate_tiny_grids(n, exec_):
