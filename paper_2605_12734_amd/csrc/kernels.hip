@@ -1261,39 +1261,64 @@ __global__ void k_init_cells(GridDev g, const int32_t* __restrict__ ccell, int32
     }
 }
 
-// Resolution-change ghost fill: one workgroup per rectangle, its threads
-// stride over the rectangle's ghost cells.
+// Resolution-change ghost fill: one single-wave workgroup per rectangle.
+// A ghost cell takes R = r*r source values (r = 1: the coarser or equal
+// neighbour's cell; r > 1: the finer neighbour's r x r cells).  The wave
+// loads a batch of up to 256 source values with every lane (4 loads in
+// flight per lane; values of one cell are consecutive, so lanes read along
+// the face's first tangential axis), stages them in LDS, then each lane
+// takes every 64th ghost cell of the batch, sums its R values in the fixed
+// order (q2 outer, q1 inner) and stores the mean.  (Summing in each lane straight from memory serialised
+// the loads: r = 8 cells took 64 dependent loads each.  Batches of 1024
+// values were slower: fewer waves fit.  What remains is mostly the x-normal
+// faces, whose source values are one per row of the neighbour.)
+constexpr int kFillLanes = 64, kFillBatch = 256;
+
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kFillLanes)
 k_amr_fill(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const FillSeg* __restrict__ segs,
            int32_t nseg, int parity) {
+    __shared__ T vals[kFillBatch];
+    const int lane = (int)threadIdx.x;
     for (int32_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
         const FillSeg& S = segs[sg];
         const int d = S.d, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
         const BlockDev& N = blocks[S.src];
-        const int64_t nb = parity ? N.off[1] : N.off[0];
-        const int64_t step[3] = {1, N.py, N.pz};
+        const int64_t nb = (parity ? N.off[1] : N.off[0]) + (int64_t)S.lay * (d == 0 ? 1 : d == 1 ? N.py : N.pz);
+        const int64_t s1 = t1 == 0 ? 1 : N.py, s2 = t2 == 1 ? N.py : N.pz;
         const BlockDev& D = blocks[S.dst];
-        const int64_t dstep[3] = {1, D.py, D.pz};
-        const int32_t r = S.hc >> S.lhn;
+        const int64_t ds1 = t1 == 0 ? 1 : D.py, ds2 = t2 == 1 ? D.py : D.pz;
+        const int32_t rr = S.hc >> S.lhn, r = rr > 1 ? rr : 1, R = r * r;
         const int32_t cells = S.n1 * S.n2;
-        for (int32_t loc = threadIdx.x; loc < cells; loc += blockDim.x) {
-            const int32_t c1 = loc % S.n1, c2 = loc / S.n1;
-            const int32_t i1 = (S.r1 + c1 * S.hc) >> S.lhn, i2 = (S.r2 + c2 * S.hc) >> S.lhn;
-            const int64_t at = nb + (int64_t)S.lay * step[d] + (int64_t)i1 * step[t1] + (int64_t)i2 * step[t2];
-            T v;
-            if (r <= 1) {
-                v = arena[at];
-            } else {
-                T sum = 0;
-                for (int32_t q2 = 0; q2 < r; ++q2)
-                    for (int32_t q1 = 0; q1 < r; ++q1) {
-                        const T x = arena[at + (int64_t)q1 * step[t1] + (int64_t)q2 * step[t2]];
-                        sum = (q1 == 0 && q2 == 0) ? x : sum + x;
-                    }
-                v = sum / (T)(r * r);
+        const int32_t cpb = kFillBatch / R;   // cells per batch (r <= 16)
+        for (int32_t cb = 0; cb < cells; cb += cpb) {
+            const int32_t nc = cells - cb < cpb ? cells - cb : cpb, nval = nc * R;
+            T v[kFillBatch / kFillLanes];
+#pragma unroll
+            for (int j = 0; j < kFillBatch / kFillLanes; ++j) {
+                // whole waves of loads past the batch are skipped (uniform);
+                // in the last one every lane loads a valid (clamped) value
+                if (j * kFillLanes < nval) {
+                    int32_t f = lane + j * kFillLanes;
+                    f = f < nval ? f : nval - 1;
+                    const int32_t cell = cb + f / R, q = f % R;
+                    const int32_t c1 = cell % S.n1, c2 = cell / S.n1;
+                    const int32_t i1 = ((S.r1 + c1 * S.hc) >> S.lhn) + q % r, i2 = ((S.r2 + c2 * S.hc) >> S.lhn) + q / r;
+                    v[j] = arena[nb + (int64_t)i1 * s1 + (int64_t)i2 * s2];
+                }
             }
-            arena[D.off[0] + (int64_t)(S.a1 + c1) * dstep[t1] + (int64_t)(S.a2 + c2) * dstep[t2]] = v;
+#pragma unroll
+            for (int j = 0; j < kFillBatch / kFillLanes; ++j)
+                if (lane + j * kFillLanes < nval) vals[lane + j * kFillLanes] = v[j];
+            __syncthreads();
+            for (int32_t k = lane; k < nc; k += kFillLanes) {
+                T sum = vals[k * R];
+                for (int32_t q = 1; q < R; ++q) sum = sum + vals[k * R + q];
+                const T m = R > 1 ? sum / (T)R : sum;
+                const int32_t cell = cb + k, c1 = cell % S.n1, c2 = cell / S.n1;
+                arena[D.off[0] + (int64_t)(S.a1 + c1) * ds1 + (int64_t)(S.a2 + c2) * ds2] = m;
+            }
+            __syncthreads();
         }
     }
 }
@@ -1420,10 +1445,10 @@ hipError_t launch_amr_fill(int dtype_bytes, hipStream_t st, void* arena, const B
     if (nseg <= 0 || total <= 0) return hipSuccess;
     const unsigned int grid = (unsigned int)(nseg < (1 << 20) ? nseg : (1 << 20));
     if (dtype_bytes == 8)
-        hipLaunchKernelGGL(k_amr_fill<double>, dim3(grid), dim3(256), 0, st, reinterpret_cast<double*>(arena),
+        hipLaunchKernelGGL(k_amr_fill<double>, dim3(grid), dim3(kFillLanes), 0, st, reinterpret_cast<double*>(arena),
                            blocks, segs, nseg, parity);
     else
-        hipLaunchKernelGGL(k_amr_fill<float>, dim3(grid), dim3(256), 0, st, reinterpret_cast<float*>(arena),
+        hipLaunchKernelGGL(k_amr_fill<float>, dim3(grid), dim3(kFillLanes), 0, st, reinterpret_cast<float*>(arena),
                            blocks, segs, nseg, parity);
     return hipGetLastError();
 }

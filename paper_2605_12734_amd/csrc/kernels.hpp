@@ -158,7 +158,7 @@ struct FillSeg {
 static_assert(sizeof(FillSeg) == 56, "FillSeg layout");
 
 // Fill every resolution-change ghost buffer from parity `parity` of the
-// chares: one workgroup per rectangle segs[0..nseg); `total` (ghost cells
+// chares: one single-wave workgroup per rectangle segs[0..nseg); `total` (ghost cells
 // over all rectangles) only skips an empty launch.
 hipError_t launch_amr_fill(int dtype_bytes, hipStream_t st, void* arena, const BlockDev* blocks,
                            const FillSeg* segs, int32_t nseg, int64_t total, int parity);

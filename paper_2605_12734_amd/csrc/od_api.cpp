@@ -95,7 +95,9 @@ int32_t log2i(int32_t v) {
 
 // Ghost-fill rectangles of every resolution-change face: one per (face,
 // neighbour chare), found by walking the face's unit slab at the owner
-// grid's granularity.  Returns the number of neighbour cells the fill reads.
+// grid's granularity.  Returns the number of neighbour cells the fill reads,
+// or -1 if a face has a neighbour more than 16 times finer (the largest
+// ratio the fill is built and tested for: 256 source values per ghost cell).
 int64_t build_fill_segments(Grid& G) {
     const Plan& p = G.plan;
     G.segs_h.clear();
@@ -146,6 +148,7 @@ int64_t build_fill_segments(Grid& G) {
                         const int64_t cells = (int64_t)S.n1 * S.n2;
                         G.fill_total += cells;
                         const int64_t r = N.h < c.h ? c.h / N.h : 1;
+                        if (r > 16) return -1;
                         reads += cells * r * r;
                         G.segs_h.push_back(S);
                     }
@@ -431,6 +434,7 @@ std::string build_layout(const od_config& cfg, Grid& G) {
     G.fill_total = 0;
     if (p.multires) {
         const int64_t reads = build_fill_segments(G);
+        if (reads < 0) return "a block face borders cells more than 16 times finer (cell ratio across a face is limited to 16)";
         // algorithmic ghost traffic: same-size faces read their neighbour
         // cells, resolution-change faces the neighbour cells their fill reads
         int64_t direct = 0;

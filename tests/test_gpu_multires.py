@@ -52,7 +52,20 @@ def _compare(n, blocks, cell, dtype, exec_, iters, tile=None, bc=oracle.DEFAULT_
     assert r == r_want
 
 
-@pytest.mark.parametrize("layout", [_two_level, _three_level, _octree])
+def _ratio_16():
+    # a 2^3-cell block beside 32^3 unit cells and a 4^3-cell block: ratio-16
+    # and ratio-4 faces (one ghost cell averages 256 finer cells)
+    blocks = [((0, 0, 0), (32, 32, 32)), ((32, 0, 0), (32, 32, 32)), ((0, 32, 0), (64, 32, 32))]
+    return (64, 64, 32), blocks, [16, 1, 4]
+
+
+def _ratio_8_octree():
+    # octree leaves of edge 8..64 units, 8 cells per leaf edge: ratios up to 8
+    blocks = workloads.octree_blocks(n=128, root=64, min_edge=8, p_refine=0.45, seed=5)
+    return (128, 128, 128), blocks, [e[0] // 8 for _, e in blocks]
+
+
+@pytest.mark.parametrize("layout", [_two_level, _three_level, _octree, _ratio_16, _ratio_8_octree])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("exec_", ["fused", "graph"])
 def test_multires_matches_oracle(layout, dtype, exec_):

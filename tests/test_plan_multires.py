@@ -88,7 +88,16 @@ def test_unit_cells_plan_unchanged():
     ([((0, 0, 0), (16, 16, 16)), ((16, 0, 0), (16, 16, 16))], [2, 1], "msgdriven"),
     ([((0, 0, 0), (16, 16, 16)), ((16, 0, 0), (16, 16, 16))], [2, 1], "persistent"),
     ([((0, 0, 0), (12, 16, 16)), ((12, 0, 0), (20, 16, 16))], [8, 1], "fused"),          # origin not a multiple
+    ([((0, 0, 0), (32, 32, 32)), ((32, 0, 0), (32, 32, 32))], [32, 1], "fused"),          # cell ratio 32 > 16
 ])
 def test_uncovered_layouts_refused(blocks, cell, exec_):
+    n = tuple(max(o[d] + e[d] for o, e in blocks) for d in range(3))
     with pytest.raises(od.ODError):
-        od.host_plan(n=(32, 16, 16), blocks=blocks, cell=cell, dtype="f64", exec=exec_)
+        od.host_plan(n=n, blocks=blocks, cell=cell, dtype="f64", exec=exec_)
+
+
+def test_cell_ratio_16_accepted():
+    # the largest ratio the ghost fill stages (16 x 16 finer cells per ghost cell)
+    blocks = [((0, 0, 0), (32, 32, 32)), ((32, 0, 0), (32, 32, 32))]
+    p = od.host_plan(n=(64, 32, 32), blocks=blocks, cell=[16, 1], dtype="f64", exec="fused")
+    assert p["interior"] == 8 + 32 ** 3
