@@ -712,6 +712,19 @@ od_status Grid::persistent_run(int64_t n) {
 od_status Grid::msgdriven_run(int64_t n) {
     if (grid_wgs <= 0) return fail(OD_EHIP, "message-driven kernel: no co-resident workgroups");
     if (iters + n > INT32_MAX) return fail(OD_EINVAL, "step counters limited to 2^31 iterations");
+    // One launch runs at most 2^30 tasks and 2^26 steps, so 32-bit queue
+    // tickets and finish counters never wrap within a launch.
+    const int64_t per = std::max<int64_t>(1, std::min<int64_t>((int64_t)1 << 26,
+                                                               ((int64_t)1 << 30) / std::max<size_t>(tiles_h.size(), 1)));
+    while (n > per) {
+        od_status st2 = msgdriven_launch(per);
+        if (st2 != OD_OK) return st2;
+        n -= per;
+    }
+    return msgdriven_launch(n);
+}
+
+od_status Grid::msgdriven_launch(int64_t n) {
     // target = iters + n ; the final-step residual slot (index 2) is cleared
     const int32_t tgt = (int32_t)(iters + n);
     hipError_t e = hipMemcpyAsync(base + L.target, &tgt, 4, hipMemcpyHostToDevice, st);

@@ -88,6 +88,7 @@ struct Grid {
     od_status graph_run(int64_t n);
     od_status persistent_run(int64_t n);
     od_status msgdriven_run(int64_t n);
+    od_status msgdriven_launch(int64_t n);
     od_status per_chare_run(int64_t n);
     od_status iterate(int64_t n);
     od_status residual(double* r);

@@ -453,7 +453,9 @@ void Server::run() {
                     want_admit = free_slot() >= 0 && fits_somewhere(H.bytes);
                 }
                 const double age = t - t_epoch;
-                if ((want_admit && age > 1e-3) || (finished_any && age > 2e-3) || stop)
+                // a launch also ends every few seconds, which bounds its
+                // queue tickets and finish counters (rebuilt at the next start)
+                if ((want_admit && age > 1e-3) || (finished_any && age > 2e-3) || age > 4.0 || stop)
                     __atomic_store_n(h_yield, 1, __ATOMIC_RELEASE);
             }
             if (q == hipSuccess) break;
