@@ -70,7 +70,8 @@ typedef enum {
                            replayed                                          */
     OD_PERSISTENT = 3,  /* one cooperative launch for all n iterations with a
                            device-wide barrier between iterations            */
-    OD_MSGDRIVEN = 4    /* one cooperative launch; each tile advances as soon
+    OD_MSGDRIVEN = 4    /* one cooperative launch per od_iterate call (split
+                           every 2^30 tile-steps); each tile advances as soon
                            as the tiles it reads halos from have finished the
                            previous step (message-driven, no global barrier) */
 } od_exec;
