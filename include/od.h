@@ -134,6 +134,12 @@ typedef struct {
      * global od_read / od_write / od_read_points calls are refused, use
      * od_read_block / od_write_block. */
     const int32_t* block_cell;
+    /* Bound, in seconds, on every device-side wait of the persistent and
+     * message-driven launches (barriers, ready queues); 0 = 10 s.  A wait
+     * that reaches it raises the grid's error flag and every workgroup
+     * leaves (reads then return OD_ETIMEDOUT).  Tests use a tiny bound to
+     * exercise that path. */
+    double wait_s;
 } od_config;
 
 struct od_grid;
@@ -158,7 +164,11 @@ od_status od_create(const od_config* cfg, void* hip_stream, void* dev_workspace,
  * OD_PER_CHARE mode whose host loop itself issues the work. */
 od_status od_iterate(struct od_grid* g, int64_t n);
 
-/* Synchronise the stream; *r = residual of the last sweep (0 before any). */
+/* Synchronise the stream; *r = residual of the last sweep (0 before any).
+ * od_residual and the reads below (od_read, od_read_points, od_read_block)
+ * return OD_ETIMEDOUT instead of a result if a device-side wait of an
+ * earlier persistent or message-driven launch gave up; the grid's state is
+ * then undefined until od_write. */
 od_status od_residual(struct od_grid* g, double* r);
 
 /* Iterations done since od_create (or the last od_write). */

@@ -37,9 +37,10 @@ def _dims(n) -> tuple:
 def make_config(n, odf: int = 8, block=None, blocks: Optional[Sequence] = None, dtype="f64",
                 bc=DEFAULT_BC, seed: int = 12734, exec: str = "graph", tile=None,
                 imbalance_pct: int = 0, imbalance_max_extra: int = 0, hints: int = 0, stencil: int = 7,
-                cell: Optional[Sequence] = None):
+                cell: Optional[Sequence] = None, wait_s: float = 0.0):
     """Fill an od_config; returns (cfg, keepalive) where keepalive holds arrays it points to.
-    `cell`: per explicit block, its cell edge in grid units (multi-resolution)."""
+    `cell`: per explicit block, its cell edge in grid units (multi-resolution).
+    `wait_s`: bound on device-side waits of cooperative launches (0 = 10 s)."""
     cfg = B.od_config()
     lib().od_config_default(ctypes.byref(cfg))
     nx, ny, nz = _dims(n)
@@ -78,6 +79,7 @@ def make_config(n, odf: int = 8, block=None, blocks: Optional[Sequence] = None, 
     cfg.imbalance_max_extra = int(imbalance_max_extra)
     cfg.hints = int(hints)
     cfg.stencil = int(stencil)
+    cfg.wait_s = float(wait_s)
     return cfg, keep
 
 
@@ -156,7 +158,7 @@ class Grid:
     def __init__(self, n, odf: int = 8, block=None, blocks=None, dtype="f64", bc=DEFAULT_BC,
                  seed: int = 12734, exec: str = "graph", tile=None, imbalance_pct: int = 0,
                  imbalance_max_extra: int = 0, hints: int = 0, stencil: int = 7, device: str = "cuda:0",
-                 stream=None, cell=None):
+                 stream=None, cell=None, wait_s: float = 0.0):
         import torch
 
         self.n = _dims(n)
@@ -165,7 +167,7 @@ class Grid:
         cfg, self._keep = make_config(n=n, odf=odf, block=block, blocks=blocks, dtype=dtype, bc=bc, seed=seed,
                                       exec=exec, tile=tile, imbalance_pct=imbalance_pct,
                                       imbalance_max_extra=imbalance_max_extra, hints=hints, stencil=stencil,
-                                      cell=cell)
+                                      cell=cell, wait_s=wait_s)
         nbytes = ctypes.c_size_t()
         check(lib().od_workspace_bytes(ctypes.byref(cfg), ctypes.byref(nbytes)), "od_workspace_bytes")
         self.device = torch.device(device)

@@ -40,7 +40,7 @@ class od_config(ctypes.Structure):
                 ("nblocks", c_i32), ("dtype", ctypes.c_int), ("bc", c_dbl * 6), ("seed", c_u64),
                 ("exec", ctypes.c_int), ("tile", c_i32 * 3), ("imbalance_pct", c_i32),
                 ("imbalance_max_extra", c_i32), ("hints", c_i32), ("stencil", c_i32),
-                ("block_cell", ctypes.POINTER(c_i32))]
+                ("block_cell", ctypes.POINTER(c_i32)), ("wait_s", ctypes.c_double)]
 
 
 class od_plan_info(ctypes.Structure):

@@ -1165,9 +1165,8 @@ hipError_t launch_persistent(int dtype_bytes, int tx, int ty, hipStream_t st, in
                              const BlockDev* blocks, const TileDev* tiles, int32_t ntiles, int parity,
                              int64_t iters, unsigned long long* res, int32_t nres, unsigned int* bar,
                              unsigned int* err, const uint8_t* extra, int32_t extra_period, int32_t nchares,
-                             int64_t iter_base, int hints, int dyn) {
+                             int64_t iter_base, int hints, int dyn, int64_t wait_ticks) {
     if (iters <= 0) return hipSuccess;
-    int64_t wait_ticks = device_wait_ticks();
 #define OD_LAUNCH(T, TX, TY)                                                                          \
     if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                      \
         T* ar = reinterpret_cast<T*>(arena);                                                          \

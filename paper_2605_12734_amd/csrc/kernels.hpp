@@ -61,7 +61,7 @@ hipError_t launch_persistent(int dtype_bytes, int tx, int ty, hipStream_t st, in
                              int32_t ntiles, int parity, int64_t iters,
                              unsigned long long* res, int32_t nres, unsigned int* bar,
                              unsigned int* err, const uint8_t* extra, int32_t extra_period,
-                             int32_t nchares, int64_t iter_base, int hints, int dyn);
+                             int32_t nchares, int64_t iter_base, int hints, int dyn, int64_t wait_ticks);
 // Wall-clock ticks in `seconds` (bound of every device-side wait).
 int64_t device_wait_ticks(double seconds = 10.0);
 // Max co-resident workgroups of the persistent / message-driven kernels.

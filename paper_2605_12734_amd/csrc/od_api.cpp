@@ -235,6 +235,7 @@ std::string build_layout(const od_config& cfg, Grid& G) {
     if (cfg.imbalance_pct < 0 || cfg.imbalance_pct > 100 || cfg.imbalance_max_extra < 0 ||
         cfg.imbalance_max_extra > 255)
         return "imbalance_pct must be in [0,100] and imbalance_max_extra in [0,255]";
+    if (!(cfg.wait_s >= 0.0) || cfg.wait_s > 3600.0) return "wait_s must be in [0, 3600] seconds";
     if (cfg.imbalance_pct > 0 && cfg.exec == OD_GRAPH) return "imbalance is not supported with OD_GRAPH";
     if (p.multires && cfg.exec != OD_FUSED && cfg.exec != OD_GRAPH)
         return "multi-resolution blocks are supported with OD_FUSED and OD_GRAPH";
@@ -702,7 +703,8 @@ od_status Grid::persistent_run(int64_t n) {
                                      reinterpret_cast<unsigned int*>(base + L.err),
                                      extra_h.empty() ? nullptr : reinterpret_cast<const uint8_t*>(base + L.extra),
                                      extra_period, (int32_t)plan.chares.size(), iters, mode(),
-                                     (!extra_h.empty() || !plan.regular) ? 1 : 0);
+                                     (!extra_h.empty() || !plan.regular) ? 1 : 0,
+                                     device_wait_ticks(cfg.wait_s > 0 ? cfg.wait_s : 10.0));
     if (e != hipSuccess) return fail(OD_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
     parity ^= (int)(n & 1);
     iters += n;
@@ -745,7 +747,7 @@ od_status Grid::msgdriven_launch(int64_t n) {
     a.extra = extra_h.empty() ? nullptr : reinterpret_cast<const uint8_t*>(base + L.extra);
     a.extra_period = extra_period;
     a.nchares = (int32_t)plan.chares.size();
-    a.wait_ticks = device_wait_ticks();
+    a.wait_ticks = device_wait_ticks(cfg.wait_s > 0 ? cfg.wait_s : 10.0);
     a.hints = mode();
     a.xpub = reinterpret_cast<uint8_t*>(base + L.xpub);
     a.tile_pos = nullptr;
@@ -888,13 +890,20 @@ od_status Grid::iterate(int64_t n) {
     return fail(OD_EINVAL, "unknown exec mode");
 }
 
-od_status Grid::residual(double* r) {
+od_status Grid::device_error() {
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("sync: ") + hipGetErrorString(e));
     unsigned int err = 0;
     e = hipMemcpy(&err, base + L.err, 4, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("read error flag: ") + hipGetErrorString(e));
     if (err != 0) return fail(OD_ETIMEDOUT, "a device-side wait exceeded its bound (flag " + std::to_string(err) + ")");
+    return OD_OK;
+}
+
+od_status Grid::residual(double* r) {
+    od_status es = device_error();
+    if (es != OD_OK) return es;
+    hipError_t e = hipSuccess;
     if (iters == 0) {
         *r = 0.0;
         return OD_OK;
@@ -920,8 +929,15 @@ od_status Grid::io(void* host, size_t bytes, bool to_host) {
     const int64_t PX = plan.n[0] + 2, PY = plan.n[1] + 2, PZ = plan.n[2] + 2;
     const size_t need = (size_t)PX * PY * PZ * s;
     if (bytes < need) return fail(OD_EINVAL, "buffer of " + std::to_string(bytes) + " bytes, need " + std::to_string(need));
-    hipError_t e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return fail(OD_EHIP, std::string("sync: ") + hipGetErrorString(e));
+    hipError_t e = hipSuccess;
+    if (to_host) {
+        // a result of a run whose device-side wait gave up is not returned
+        od_status es = device_error();
+        if (es != OD_OK) return es;
+    } else {
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return fail(OD_EHIP, std::string("sync: ") + hipGetErrorString(e));
+    }
     const size_t plane = (size_t)PX * PY * s;
     const size_t chunk_planes = std::max<size_t>(1, ((size_t)64 << 20) / plane);
     od_status os = ensure_pinned(chunk_planes * plane);
@@ -955,8 +971,14 @@ od_status Grid::block_io(int32_t b, void* host, size_t bytes, bool to_host) {
     const BlockDev& B = blocks_h[(size_t)b];
     const size_t row = (size_t)B.ex * s, need = row * B.ey * B.ez;
     if (bytes < need) return fail(OD_EINVAL, "buffer of " + std::to_string(bytes) + " bytes, need " + std::to_string(need));
-    hipError_t e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return fail(OD_EHIP, std::string("sync: ") + hipGetErrorString(e));
+    hipError_t e = hipSuccess;
+    if (to_host) {
+        od_status es = device_error();
+        if (es != OD_OK) return es;
+    } else {
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return fail(OD_EHIP, std::string("sync: ") + hipGetErrorString(e));
+    }
     const size_t pitch = (size_t)B.py * s, store = (size_t)B.pz * B.ez * s;
     od_status os = ensure_pinned(store);
     if (os != OD_OK) return os;
@@ -991,8 +1013,9 @@ od_status Grid::read_points(const int64_t* idx, int64_t count, void* host_dst) {
     const int64_t total = plan.interior;
     for (int64_t i = 0; i < count; ++i)
         if (idx[i] < 0 || idx[i] >= total) return fail(OD_EINVAL, "point index out of range");
-    hipError_t e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return fail(OD_EHIP, std::string("sync: ") + hipGetErrorString(e));
+    od_status es = device_error();
+    if (es != OD_OK) return es;
+    hipError_t e = hipSuccess;
     const size_t need = (size_t)count * (8 + (size_t)s);
     od_status os = ensure_pinned(need);
     if (os != OD_OK) return os;

@@ -92,6 +92,8 @@ struct Grid {
     od_status per_chare_run(int64_t n);
     od_status iterate(int64_t n);
     od_status residual(double* r);
+    // sync the grid's stream; OD_ETIMEDOUT if a device-side wait gave up
+    od_status device_error();
     od_status io(void* host, size_t bytes, bool to_host);
     od_status read_points(const int64_t* idx, int64_t count, void* host_dst);
     od_status block_io(int32_t b, void* host, size_t bytes, bool to_host);

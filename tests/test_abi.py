@@ -43,6 +43,7 @@ def test_config_default_and_version():
     B.lib().od_config_default(ctypes.byref(cfg))
     assert tuple(cfg.n) == (64, 64, 64) and cfg.odf == 8 and cfg.dtype == B.OD_F64
     assert tuple(cfg.bc) == (1.0, 0, 0, 0, 0, 0) and cfg.seed == 12734
+    assert cfg.wait_s == 0.0 and not cfg.block_cell
     assert b"gfx950" in B.lib().od_version()
 
 
@@ -55,6 +56,8 @@ def test_config_default_and_version():
     (dict(n=8, blocks=[((0, 0, 0), (8, 8, 4))]), -22),             # does not cover
     (dict(n=8, blocks=[((0, 0, 0), (8, 8, 8)), ((0, 0, 0), (8, 8, 8))]), -22),   # overlap / over-cover
     (dict(n=8, imbalance_pct=150), -22),
+    (dict(n=8, wait_s=-1.0), -22),
+    (dict(n=8, wait_s=float("nan")), -22),
 ])
 def test_invalid_configs_rejected(kw, code):
     import paper_2605_12734_amd as od

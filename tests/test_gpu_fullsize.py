@@ -175,6 +175,35 @@ def test_served_384_request_survives_yields():
     assert epochs >= 2
 
 
+@pytest.mark.parametrize("exec_", ["persistent", "msgdriven"])
+def test_device_wait_bound_reports_timeout(exec_):
+    # a 1 ns bound on every device-side wait: the launch's barriers and
+    # queues give up (every workgroup leaves normally) and the host sees
+    # OD_ETIMEDOUT instead of a result; od_write makes the grid usable
+    g = od.Grid(256, odf=512, dtype="f64", exec=exec_, tile=(32, 16, 32), hints=1, wait_s=1e-9)
+    try:
+        g.iterate(50)
+        with pytest.raises(od.ODError) as ei:
+            g.residual()
+        assert ei.value.status == -110
+        with pytest.raises(od.ODError) as ei:
+            g.read_points([0, 1, 2])
+        assert ei.value.status == -110
+    finally:
+        g.close()
+    # nothing is left behind on the device: a grid with the default bound
+    # right after it is exact
+    n = (64, 64, 64)
+    want, _, r_w = oracle.solve(n, np.float64, seed=3, iters=9)
+    g = od.Grid(n, odf=8, dtype="f64", exec=exec_, seed=3)
+    try:
+        g.iterate(9)
+        assert g.residual() == r_w
+        assert np.array_equal(g.read(), want)
+    finally:
+        g.close()
+
+
 @pytest.mark.parametrize("n", [(1, 1, 1), (1, 5, 1), (2, 1, 3), (3, 3, 1)])
 @pytest.mark.parametrize("exec_", ["fused", "persistent", "msgdriven", "per_chare", "graph"])
 def test_degenerate_tiny_grids(n, exec_):
