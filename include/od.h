@@ -71,7 +71,8 @@ typedef enum {
     OD_PERSISTENT = 3,  /* one cooperative launch for all n iterations with a
                            device-wide barrier between iterations            */
     OD_MSGDRIVEN = 4    /* one cooperative launch per od_iterate call (split
-                           every 2^30 tile-steps); each tile advances as soon
+                           every 2^23 tile-steps and 65535 steps; at most
+                           2^23 - 1 tiles); each tile advances as soon
                            as the tiles it reads halos from have finished the
                            previous step (message-driven, no global barrier) */
 } od_exec;

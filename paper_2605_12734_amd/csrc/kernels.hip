@@ -569,7 +569,7 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
 // them.  On an XCD with few workgroups each worker writes back itself.
 //
 // Queue / list x: ring of cap_x (power of two >= its tile count, so a push
-// never waits for good) 64-bit slots (sequence << 32 | tile) at
+// never waits for good) 64-bit slots at
 // qslots + off_x (ready queue) and pslots + off_x (cross list).
 struct QueueMap {
     int32_t phys[8];   // queue (XCD) of tile group g
@@ -615,15 +615,25 @@ struct NoQuit {
     __device__ bool operator()() const { return false; }
 };
 
-// Append u to ring (base, cap) at a fresh ticket of *tail.  Gives up
-// (false) when quit() turns true, or raises error flag 2 on timeout.
+// A slot holds a 24-bit sequence (bits 63..40) and a 40-bit payload: ticket
+// t's entry is filled when the sequence is (t+1) mod 2^24 and free for
+// ticket t when it is t mod 2^24.  A launch takes fewer than 2^24 tickets
+// per queue (the host splits longer runs), so no two tickets alias.
+constexpr unsigned long long kSlotPayload = (1ull << 40) - 1;
+__device__ __forceinline__ unsigned long long slot_word(uint32_t seq, unsigned long long payload) {
+    return ((unsigned long long)(seq & 0xFFFFFFu) << 40) | payload;
+}
+__device__ __forceinline__ uint32_t slot_seq(unsigned long long v) { return (uint32_t)(v >> 40); }
+
+// Append a payload to ring (base, cap) at a fresh ticket of *tail.  Gives
+// up (false) when quit() turns true, or raises error flag 2 on timeout.
 template <class Quit = NoQuit>
 __device__ __forceinline__ bool ring_push(const MsgArgs& a, unsigned long long* q, uint32_t cap, unsigned int* tail,
-                                          int32_t u, Quit quit = Quit()) {
+                                          unsigned long long payload, Quit quit = Quit()) {
     const uint32_t t = __hip_atomic_fetch_add(tail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     unsigned long long* sl = &q[t & (cap - 1u)];
     const int64_t t0 = wall_clock64();
-    while ((uint32_t)(__hip_atomic_load(sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32) != t) {
+    while (slot_seq(__hip_atomic_load(sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != (t & 0xFFFFFFu)) {
         if (quit()) return false;
         if (wall_clock64() - t0 > a.wait_ticks) {
             __hip_atomic_fetch_or(a.err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -631,24 +641,23 @@ __device__ __forceinline__ bool ring_push(const MsgArgs& a, unsigned long long* 
         }
         __builtin_amdgcn_s_sleep(1);
     }
-    __hip_atomic_store(sl, ((unsigned long long)(t + 1u) << 32) | (uint32_t)u, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(sl, slot_word(t + 1u, payload), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return true;
 }
 
-// Take ticket t's entry of ring (base, cap): wait until it is filled, free
-// the slot for ticket t + cap.  Returns -1 when quit() turns true, or on
-// timeout or a raised error (then error flag 2 is raised).
+// Take ticket t's payload from ring (base, cap): wait until it is filled,
+// free the slot for ticket t + cap.  Returns -1 when quit() turns true, or
+// on timeout or a raised error (then error flag 2 is raised).
 template <class Quit = NoQuit>
-__device__ __forceinline__ int32_t ring_take(const MsgArgs& a, unsigned long long* q, uint32_t cap, uint32_t t,
+__device__ __forceinline__ int64_t ring_take(const MsgArgs& a, unsigned long long* q, uint32_t cap, uint32_t t,
                                              Quit quit = Quit()) {
     unsigned long long* sl = &q[t & (cap - 1u)];
     const int64_t t0 = wall_clock64();
     for (;;) {
         const unsigned long long v = __hip_atomic_load(sl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((uint32_t)(v >> 32) == t + 1u) {
-            __hip_atomic_store(sl, (unsigned long long)(t + cap) << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return (int32_t)(uint32_t)v;
+        if (slot_seq(v) == ((t + 1u) & 0xFFFFFFu)) {
+            __hip_atomic_store(sl, slot_word(t + cap, 0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return (int64_t)(v & kSlotPayload);
         }
         if (quit()) return -1;
         if (wall_clock64() - t0 > a.wait_ticks ||
@@ -660,21 +669,29 @@ __device__ __forceinline__ int32_t ring_take(const MsgArgs& a, unsigned long lon
     }
 }
 
+// Plain-grid payload: the tile and the step it runs next, relative to the
+// launch's first step d0 (a launch runs fewer than 2^16 steps).
+__device__ __forceinline__ unsigned long long task_payload(int32_t tile, int32_t rel) {
+    return ((unsigned long long)(uint32_t)tile << 16) | (uint32_t)rel;
+}
+
 // Count finish ns of tile c for its i-th counter (i = 0: c itself, else its
-// (i-1)-th reader); queue the tile whose counter this completes.
-__device__ __forceinline__ void count_finish(const MsgArgs& a, const QueueMap& m, int32_t c, int32_t ns, int32_t i) {
+// (i-1)-th reader); queue the tile whose counter this completes, for the
+// step that reads ns.
+__device__ __forceinline__ void count_finish(const MsgArgs& a, const QueueMap& m, int32_t c, int32_t ns, int32_t d0,
+                                             int32_t i) {
     const int32_t u = i == 0 ? c : a.dep_idx[a.dep_ptr[c] + i - 1];
     const int32_t need = a.dep_ptr[u + 1] - a.dep_ptr[u] + 1;
     const int32_t prev = __hip_atomic_fetch_add(&a.pend[2 * u + (ns & 1)], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if ((prev + 1) % need == 0) {
         const int x = m.phys[u & 7];
-        ring_push(a, a.qslots + m.off[x], (uint32_t)m.cap[x], &a.qhead[kQcTail + x], u);
+        ring_push(a, a.qslots + m.off[x], (uint32_t)m.cap[x], &a.qhead[kQcTail + x], task_payload(u, ns - d0));
     }
 }
 
 // Publisher of XCD x (wave 0 only): take the cross tiles workers list, in
 // batches of up to 64, write the L2 back once per batch, then count them.
-__device__ __forceinline__ void publisher_loop(const MsgArgs& a, const QueueMap& m, int x, uint32_t want) {
+__device__ __forceinline__ void publisher_loop(const MsgArgs& a, const QueueMap& m, int x, uint32_t want, int32_t d0) {
     const int lane = threadIdx.x;
     unsigned long long* pl = a.pslots + m.off[x];
     const uint32_t cap = (uint32_t)m.cap[x];
@@ -693,16 +710,16 @@ __device__ __forceinline__ void publisher_loop(const MsgArgs& a, const QueueMap&
             continue;
         }
         if (e - h > 64u) e = h + 64u;
-        int32_t c = -1;
-        if ((uint32_t)lane < e - h) c = ring_take(a, pl, cap, h + (uint32_t)lane);
-        if (__ballot(c < 0 && (uint32_t)lane < e - h) != 0ull) return;   // timed out (flag raised)
+        int64_t pay = -1;
+        if ((uint32_t)lane < e - h) pay = ring_take(a, pl, cap, h + (uint32_t)lane);
+        if (__ballot(pay < 0 && (uint32_t)lane < e - h) != 0ull) return;   // timed out (flag raised)
         // every listed worker drained its stores into this XCD's L2 before
         // listing: one write-back publishes the whole batch
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if (c >= 0) {
-            const int32_t ns = ld_rlx(&a.done[c]);
+        if (pay >= 0) {
+            const int32_t c = (int32_t)(pay >> 16), ns = d0 + (int32_t)(pay & 0xFFFF);
             const int32_t cnt = a.dep_ptr[c + 1] - a.dep_ptr[c] + 1;
-            for (int32_t i = 0; i < cnt; ++i) count_finish(a, m, c, ns, i);
+            for (int32_t i = 0; i < cnt; ++i) count_finish(a, m, c, ns, d0, i);
         }
         h = e;
         idle = wall_clock64();
@@ -712,10 +729,12 @@ __device__ __forceinline__ void publisher_loop(const MsgArgs& a, const QueueMap&
 template <int NT, class SweepFn>
 __device__ __forceinline__ void queue_loop(const MsgArgs& a, SweepFn sweep, double* red) {
     __shared__ QueueMap s_m;
-    __shared__ int32_t s_tile, s_stop, s_role;
+    __shared__ int32_t s_tile, s_rel, s_stop, s_role;
     const int32_t G = gridDim.x, w = blockIdx.x;
     unsigned int* qc = a.qhead;
     const int x = (int)(__builtin_amdgcn_s_getreg(kXccIdReg) & 7);
+    // every tile starts the launch at step d0 and ends it at tgt
+    const int32_t tgt = ld_rlx(&a.target[0]), d0 = tgt - a.qsteps;
     // launch start: find the XCDs this launch runs on (and how many
     // workgroups each has), lay out the queues, mark the cross tiles and
     // queue every tile for its next step
@@ -730,7 +749,7 @@ __device__ __forceinline__ void queue_loop(const MsgArgs& a, SweepFn sweep, doub
     const int64_t stride = (int64_t)G * NT, gtid = (int64_t)w * NT + threadIdx.x;
     for (int64_t i = gtid; i < a.ntiles; i += stride) {
         const int32_t u = (int32_t)i, xu = s_m.phys[u & 7], pos = s_m.pre[u & 7] + (u >> 3);
-        a.qslots[s_m.off[xu] + pos] = ((unsigned long long)(pos + 1) << 32) | (uint32_t)u;
+        a.qslots[s_m.off[xu] + pos] = slot_word((uint32_t)pos + 1u, task_payload(u, 0));
         a.pend[2 * u] = 0;
         a.pend[2 * u + 1] = 0;
         uint8_t cross = 0;
@@ -740,8 +759,8 @@ __device__ __forceinline__ void queue_loop(const MsgArgs& a, SweepFn sweep, doub
     }
     for (int y = 0; y < 8; ++y) {
         for (int64_t i = s_m.n[y] + gtid; i < s_m.cap[y]; i += stride)
-            a.qslots[s_m.off[y] + i] = (unsigned long long)i << 32;
-        for (int64_t i = gtid; i < s_m.cap[y]; i += stride) a.pslots[s_m.off[y] + i] = (unsigned long long)i << 32;
+            a.qslots[s_m.off[y] + i] = slot_word((uint32_t)i, 0);
+        for (int64_t i = gtid; i < s_m.cap[y]; i += stride) a.pslots[s_m.off[y] + i] = slot_word((uint32_t)i, 0);
     }
     if (w == 0 && threadIdx.x < 8) qc[kQcTail + threadIdx.x] = (uint32_t)s_m.n[threadIdx.x];
     if (!grid_barrier(a.bar, a.err, a.wait_ticks)) return;
@@ -751,34 +770,35 @@ __device__ __forceinline__ void queue_loop(const MsgArgs& a, SweepFn sweep, doub
     if (haspub && s_role) {
         if (threadIdx.x >= 64 || a.qsteps < 2) return;
         const uint32_t ncross = __hip_atomic_load(&qc[kQcCross + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        publisher_loop(a, s_m, x, ncross * (uint32_t)(a.qsteps - 1));
+        publisher_loop(a, s_m, x, ncross * (uint32_t)(a.qsteps - 1), d0);
         return;
     }
     const uint32_t total = (uint32_t)s_m.n[x] * (uint32_t)a.qsteps;
     unsigned long long* q = a.qslots + s_m.off[x];
     const uint32_t cap = (uint32_t)s_m.cap[x];
-    const int32_t tgt = ld_rlx(&a.target[0]);
     for (;;) {
         if (threadIdx.x == 0) {
-            int32_t tile = -1, stop = 0;
+            int64_t pay = -1;
+            int32_t stop = 0;
             const uint32_t t = __hip_atomic_fetch_add(&qc[kQcHead + x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (t >= total) {
                 stop = 1;
             } else {
-                tile = ring_take(a, q, cap, t);
-                if (tile < 0) stop = 1;
+                pay = ring_take(a, q, cap, t);
+                if (pay < 0) stop = 1;
                 // acquire side: the neighbours' step data
                 else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
-            s_tile = tile;
+            s_tile = pay < 0 ? -1 : (int32_t)(pay >> 16);
+            s_rel = pay < 0 ? 0 : (int32_t)(pay & 0xFFFF);
             s_stop = stop;
         }
         __syncthreads();
         if (s_stop) break;
         // uniform across the workgroup: keep the tile descriptor in scalar
-        // registers
+        // registers; the step travels with the task
         const int32_t c = __builtin_amdgcn_readfirstlane(s_tile);
-        const int32_t step = __builtin_amdgcn_readfirstlane(ld_rlx(&a.done[c]));
+        const int32_t step = d0 + __builtin_amdgcn_readfirstlane(s_rel);
         const double r = sweep(c, step);
         const int32_t ns = step + 1;
         if (ns == tgt) wg_residual<double, NT>(r, &a.res[ns & 1], red);
@@ -788,18 +808,14 @@ __device__ __forceinline__ void queue_loop(const MsgArgs& a, SweepFn sweep, doub
             const bool cross = a.xpub[c] != 0;
             const bool listed = cross && haspub && ns < tgt;
             if (lane == 0) {
-                // the next run of c reads its step here; it lands before any
-                // count that lets that run start
-                __hip_atomic_store(&a.done[c], ns, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 // no publisher on this XCD: write the L2 back before counting
                 // (the launch's end publishes its last step)
                 if (cross && !haspub && ns < tgt) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                __builtin_amdgcn_s_waitcnt(0);
-                if (listed) ring_push(a, a.pslots + s_m.off[x], cap, &qc[kQcPTail + x], c);
+                if (listed) ring_push(a, a.pslots + s_m.off[x], cap, &qc[kQcPTail + x], task_payload(c, ns - d0));
             }
             if (ns < tgt && !listed) {
                 const int32_t cnt = a.dep_ptr[c + 1] - a.dep_ptr[c] + 1;
-                for (int32_t i = lane; i < cnt; i += 64) count_finish(a, s_m, c, ns, i);
+                for (int32_t i = lane; i < cnt; i += 64) count_finish(a, s_m, c, ns, d0, i);
             }
         }
         __syncthreads();
@@ -882,8 +898,8 @@ __device__ __forceinline__ void serve_loop(const MsgArgs& a, SweepFn sweep, doub
     const int64_t stride = (int64_t)G * NT, gtid = (int64_t)w * NT + threadIdx.x;
     for (int y = 0; y < 8; ++y)
         for (int64_t i = gtid; i < s_m.cap[y]; i += stride) {
-            a.qslots[s_m.off[y] + i] = (unsigned long long)i << 32;
-            a.pslots[s_m.off[y] + i] = (unsigned long long)i << 32;
+            a.qslots[s_m.off[y] + i] = slot_word((uint32_t)i, 0);
+            a.pslots[s_m.off[y] + i] = slot_word((uint32_t)i, 0);
         }
     for (int64_t i = gtid; i < a.ntiles; i += stride) {
         const int32_t u = (int32_t)i, t = a.tile_list[u];
@@ -938,7 +954,7 @@ __device__ __forceinline__ void serve_loop(const MsgArgs& a, SweepFn sweep, doub
             }
             if (e - h > 64u) e = h + 64u;
             int32_t u = -1;
-            if ((uint32_t)lane < e - h) u = ring_take(a, pl, cap, h + (uint32_t)lane, quit);
+            if ((uint32_t)lane < e - h) u = (int32_t)ring_take(a, pl, cap, h + (uint32_t)lane, quit);
             if (__ballot(u < 0 && (uint32_t)lane < e - h) != 0ull) return;   // launch ending, or timed out
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             if (u >= 0) {
@@ -958,7 +974,7 @@ __device__ __forceinline__ void serve_loop(const MsgArgs& a, SweepFn sweep, doub
                 stop = 1;
             } else {
                 const uint32_t t = __hip_atomic_fetch_add(&qc[kQcHead + x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                u = ring_take(a, q, cap, t, quit);
+                u = (int32_t)ring_take(a, q, cap, t, quit);
                 if (u < 0) stop = 1;
                 else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }

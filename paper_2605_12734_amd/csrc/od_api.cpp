@@ -333,6 +333,8 @@ std::string build_layout(const od_config& cfg, Grid& G) {
     }
     G.L.xpub = cv.take(cfg.exec == OD_MSGDRIVEN ? ntiles : 1);
     if (cfg.exec == OD_MSGDRIVEN) {
+        // a queue entry holds a tile index in 24 bits
+        if (ntiles >= ((size_t)1 << 23)) return "message-driven grids are limited to 2^23 - 1 tiles";
         // dependency counters; per present XCD a ready ring and a cross
         // list of the next power of two >= its tile count
         G.L.pend = cv.take(ntiles * 2 * 4);
@@ -714,10 +716,11 @@ od_status Grid::persistent_run(int64_t n) {
 od_status Grid::msgdriven_run(int64_t n) {
     if (grid_wgs <= 0) return fail(OD_EHIP, "message-driven kernel: no co-resident workgroups");
     if (iters + n > INT32_MAX) return fail(OD_EINVAL, "step counters limited to 2^31 iterations");
-    // One launch runs at most 2^30 tasks and 2^26 steps, so 32-bit queue
-    // tickets and finish counters never wrap within a launch.
-    const int64_t per = std::max<int64_t>(1, std::min<int64_t>((int64_t)1 << 26,
-                                                               ((int64_t)1 << 30) / std::max<size_t>(tiles_h.size(), 1)));
+    // One launch runs fewer than 2^16 steps (a task carries its step
+    // relative to the launch's first) and at most 2^23 tasks, so a queue's
+    // 24-bit slot sequences never alias and finish counters never wrap.
+    const int64_t per = std::max<int64_t>(1, std::min<int64_t>(((int64_t)1 << 16) - 1,
+                                                               ((int64_t)1 << 23) / std::max<size_t>(tiles_h.size(), 1)));
     while (n > per) {
         od_status st2 = msgdriven_launch(per);
         if (st2 != OD_OK) return st2;
