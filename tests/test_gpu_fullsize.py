@@ -113,13 +113,13 @@ def test_1024_odf32768_imbalance_sampled(exec_):
     assert np.array_equal(got, want)
 
 
-def test_768_octree_sampled_graph_and_persistent():
+def test_768_octree_sampled_graph_persistent_msgdriven():
     blocks = workloads.octree_blocks(n=768, root=128, min_edge=16, p_refine=0.4, seed=12734)
     n = (768, 768, 768)
     iters = 12
     pts = _sample_points(n, 32, 3)
     want = oracle.point_values(n, pts, iters, np.float64)
-    for exec_ in ("graph", "persistent"):
+    for exec_ in ("graph", "persistent", "msgdriven"):
         g = od.Grid(768, blocks=blocks, dtype="f64", exec="fused", hints=1)
         tile = g.autotune(2)
         g.close()
