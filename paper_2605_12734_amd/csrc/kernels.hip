@@ -571,6 +571,19 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
 // Queue / list x: ring of cap_x (power of two >= its tile count, so a push
 // never waits for good) 64-bit slots at
 // qslots + off_x (ready queue) and pslots + off_x (cross list).
+// Cursor mode (launches with at least kCursorTasksPerWg tiles per
+// workgroup): instead of ready queues, each XCD's workgroups claim ready
+// tiles in the XCD's spatial order from a shared cursor; a tile's ready
+// word holds the step it runs next (relative, plus one), set by the finish
+// that completes its count.  Tiles that share halo lines then run at the
+// same time, as in a fused launch, and find those lines in the XCD's L2.
+// With fewer tiles per workgroup most probes would miss, and the queues
+// are used.
+constexpr int32_t kCursorTasksPerWg = 4;
+__device__ __forceinline__ bool use_cursor(int32_t ntiles, int32_t grid) {
+    return ntiles >= kCursorTasksPerWg * grid;
+}
+
 struct QueueMap {
     int32_t phys[8];   // queue (XCD) of tile group g
     int32_t off[8];    // first slot of queue x
@@ -679,19 +692,24 @@ __device__ __forceinline__ unsigned long long task_payload(int32_t tile, int32_t
 // (i-1)-th reader); queue the tile whose counter this completes, for the
 // step that reads ns.
 __device__ __forceinline__ void count_finish(const MsgArgs& a, const QueueMap& m, int32_t c, int32_t ns, int32_t d0,
-                                             int32_t i) {
+                                             int32_t i, bool cursor) {
     const int32_t u = i == 0 ? c : a.dep_idx[a.dep_ptr[c] + i - 1];
     const int32_t need = a.dep_ptr[u + 1] - a.dep_ptr[u] + 1;
     const int32_t prev = __hip_atomic_fetch_add(&a.pend[2 * u + (ns & 1)], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if ((prev + 1) % need == 0) {
-        const int x = m.phys[u & 7];
-        ring_push(a, a.qslots + m.off[x], (uint32_t)m.cap[x], &a.qhead[kQcTail + x], task_payload(u, ns - d0));
+        if (cursor) {
+            __hip_atomic_store(&a.ready[u], ns - d0 + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const int x = m.phys[u & 7];
+            ring_push(a, a.qslots + m.off[x], (uint32_t)m.cap[x], &a.qhead[kQcTail + x], task_payload(u, ns - d0));
+        }
     }
 }
 
 // Publisher of XCD x (wave 0 only): take the cross tiles workers list, in
 // batches of up to 64, write the L2 back once per batch, then count them.
-__device__ __forceinline__ void publisher_loop(const MsgArgs& a, const QueueMap& m, int x, uint32_t want, int32_t d0) {
+__device__ __forceinline__ void publisher_loop(const MsgArgs& a, const QueueMap& m, int x, uint32_t want, int32_t d0,
+                                               bool cursor) {
     const int lane = threadIdx.x;
     unsigned long long* pl = a.pslots + m.off[x];
     const uint32_t cap = (uint32_t)m.cap[x];
@@ -719,7 +737,7 @@ __device__ __forceinline__ void publisher_loop(const MsgArgs& a, const QueueMap&
         if (pay >= 0) {
             const int32_t c = (int32_t)(pay >> 16), ns = d0 + (int32_t)(pay & 0xFFFF);
             const int32_t cnt = a.dep_ptr[c + 1] - a.dep_ptr[c] + 1;
-            for (int32_t i = 0; i < cnt; ++i) count_finish(a, m, c, ns, d0, i);
+            for (int32_t i = 0; i < cnt; ++i) count_finish(a, m, c, ns, d0, i, cursor);
         }
         h = e;
         idle = wall_clock64();
@@ -735,6 +753,7 @@ __device__ __forceinline__ void queue_loop(const MsgArgs& a, SweepFn sweep, doub
     const int x = (int)(__builtin_amdgcn_s_getreg(kXccIdReg) & 7);
     // every tile starts the launch at step d0 and ends it at tgt
     const int32_t tgt = ld_rlx(&a.target[0]), d0 = tgt - a.qsteps;
+    const bool cursor = use_cursor(a.ntiles, G);
     // launch start: find the XCDs this launch runs on (and how many
     // workgroups each has), lay out the queues, mark the cross tiles and
     // queue every tile for its next step
@@ -749,7 +768,10 @@ __device__ __forceinline__ void queue_loop(const MsgArgs& a, SweepFn sweep, doub
     const int64_t stride = (int64_t)G * NT, gtid = (int64_t)w * NT + threadIdx.x;
     for (int64_t i = gtid; i < a.ntiles; i += stride) {
         const int32_t u = (int32_t)i, xu = s_m.phys[u & 7], pos = s_m.pre[u & 7] + (u >> 3);
-        a.qslots[s_m.off[xu] + pos] = slot_word((uint32_t)pos + 1u, task_payload(u, 0));
+        if (cursor)
+            a.ready[u] = 1;   // every tile runs step d0 first
+        else
+            a.qslots[s_m.off[xu] + pos] = slot_word((uint32_t)pos + 1u, task_payload(u, 0));
         a.pend[2 * u] = 0;
         a.pend[2 * u + 1] = 0;
         uint8_t cross = 0;
@@ -758,11 +780,13 @@ __device__ __forceinline__ void queue_loop(const MsgArgs& a, SweepFn sweep, doub
         if (cross) __hip_atomic_fetch_add(&qc[kQcCross + xu], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     for (int y = 0; y < 8; ++y) {
-        for (int64_t i = s_m.n[y] + gtid; i < s_m.cap[y]; i += stride)
-            a.qslots[s_m.off[y] + i] = slot_word((uint32_t)i, 0);
+        // (cursor mode keeps its ready words in this region)
+        if (!cursor)
+            for (int64_t i = s_m.n[y] + gtid; i < s_m.cap[y]; i += stride)
+                a.qslots[s_m.off[y] + i] = slot_word((uint32_t)i, 0);
         for (int64_t i = gtid; i < s_m.cap[y]; i += stride) a.pslots[s_m.off[y] + i] = slot_word((uint32_t)i, 0);
     }
-    if (w == 0 && threadIdx.x < 8) qc[kQcTail + threadIdx.x] = (uint32_t)s_m.n[threadIdx.x];
+    if (!cursor && w == 0 && threadIdx.x < 8) qc[kQcTail + threadIdx.x] = (uint32_t)s_m.n[threadIdx.x];
     if (!grid_barrier(a.bar, a.err, a.wait_ticks)) return;
 
     const bool haspub = use_publisher(__hip_atomic_load(&qc[kQcWgs + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
@@ -770,7 +794,7 @@ __device__ __forceinline__ void queue_loop(const MsgArgs& a, SweepFn sweep, doub
     if (haspub && s_role) {
         if (threadIdx.x >= 64 || a.qsteps < 2) return;
         const uint32_t ncross = __hip_atomic_load(&qc[kQcCross + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        publisher_loop(a, s_m, x, ncross * (uint32_t)(a.qsteps - 1), d0);
+        publisher_loop(a, s_m, x, ncross * (uint32_t)(a.qsteps - 1), d0, cursor);
         return;
     }
     const uint32_t total = (uint32_t)s_m.n[x] * (uint32_t)a.qsteps;
@@ -780,6 +804,46 @@ __device__ __forceinline__ void queue_loop(const MsgArgs& a, SweepFn sweep, doub
         if (threadIdx.x == 0) {
             int64_t pay = -1;
             int32_t stop = 0;
+            if (cursor) {
+            // claim the next ready tile at or after the cursor; the
+            // claimed count (qc[kQcTail + x]) reaching total ends the loop
+            const int64_t t0 = wall_clock64();
+            int32_t misses = 0;
+            if (total == 0) stop = 1;
+            while (!stop) {
+                const uint32_t p = __hip_atomic_fetch_add(&qc[kQcHead + x], 1u, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT) % (uint32_t)s_m.n[x];
+                int32_t u = -1;
+                for (int g = 0; g < 8; ++g) {
+                    const int32_t ng = a.ntiles > g ? (a.ntiles - g + 7) / 8 : 0;
+                    if (s_m.phys[g] == x && (int32_t)p >= s_m.pre[g] && (int32_t)p < s_m.pre[g] + ng)
+                        u = g + 8 * ((int32_t)p - s_m.pre[g]);
+                }
+                if (u >= 0 && ld_rlx(&a.ready[u]) != 0) {
+                    const int32_t v = __hip_atomic_exchange(&a.ready[u], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (v != 0) {
+                        __hip_atomic_fetch_add(&qc[kQcTail + x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        pay = (int64_t)task_payload(u, v - 1);
+                        // acquire side: the neighbours' step data
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                        break;
+                    }
+                }
+                if (__hip_atomic_load(&qc[kQcTail + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= total) {
+                    stop = 1;
+                    break;
+                }
+                // a run of misses (end of the launch, or a wait on a slow
+                // neighbour): back off instead of hammering the cursor
+                if (++misses > 8) __builtin_amdgcn_s_sleep(2);
+                if (wall_clock64() - t0 > a.wait_ticks ||
+                    __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                    __hip_atomic_fetch_or(a.err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    stop = 1;
+                    break;
+                }
+            }
+            } else {
             const uint32_t t = __hip_atomic_fetch_add(&qc[kQcHead + x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (t >= total) {
                 stop = 1;
@@ -788,6 +852,7 @@ __device__ __forceinline__ void queue_loop(const MsgArgs& a, SweepFn sweep, doub
                 if (pay < 0) stop = 1;
                 // acquire side: the neighbours' step data
                 else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
             }
             s_tile = pay < 0 ? -1 : (int32_t)(pay >> 16);
             s_rel = pay < 0 ? 0 : (int32_t)(pay & 0xFFFF);
@@ -815,7 +880,7 @@ __device__ __forceinline__ void queue_loop(const MsgArgs& a, SweepFn sweep, doub
             }
             if (ns < tgt && !listed) {
                 const int32_t cnt = a.dep_ptr[c + 1] - a.dep_ptr[c] + 1;
-                for (int32_t i = lane; i < cnt; i += 64) count_finish(a, s_m, c, ns, d0, i);
+                for (int32_t i = lane; i < cnt; i += 64) count_finish(a, s_m, c, ns, d0, i, cursor);
             }
         }
         __syncthreads();

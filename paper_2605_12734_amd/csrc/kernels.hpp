@@ -118,6 +118,7 @@ struct MsgArgs {
     // per XCD, running solves; 8 each except the mask and the count);
     // qsteps = steps a plain-grid launch runs
     int32_t* pend;
+    int32_t* ready;             // cursor scheduler: per tile, next step - d0 + 1 (0 = not ready)
     unsigned long long* qslots;
     unsigned long long* pslots;
     unsigned int* qhead;

@@ -758,6 +758,7 @@ od_status Grid::msgdriven_launch(int64_t n) {
     a.pend = reinterpret_cast<int32_t*>(base + L.pend);
     a.qslots = reinterpret_cast<unsigned long long*>(base + L.qslots);
     a.pslots = a.qslots + (2 * tiles_h.size() + 8);
+    a.ready = reinterpret_cast<int32_t*>(a.qslots);   // the cursor scheduler uses the ready-queue region
     a.qhead = reinterpret_cast<unsigned int*>(base + L.qctl);
     a.qsteps = (int32_t)n;
     e = launch_queue_init(st, a);
