@@ -929,15 +929,32 @@ __device__ __forceinline__ bool serve_decision(const MsgArgs& a, int32_t sv, int
 
 // Count ordinary finish ns of tile t for counter i (0 = t, else its
 // (i-1)-th reader) and queue the reader whose round this completes.
-__device__ __forceinline__ void serve_count(const MsgArgs& a, const QueueMap& m, int32_t t, int32_t ns, int32_t i) {
+__device__ __forceinline__ void serve_count(const MsgArgs& a, const QueueMap& m, int32_t t, int32_t ns, int32_t i,
+                                            bool cursor) {
     const int32_t v = i == 0 ? t : a.dep_idx[a.dep_ptr[t] + i - 1];
     const int32_t need = a.dep_ptr[v + 1] - a.dep_ptr[v] + 1;
     const int32_t prev = __hip_atomic_fetch_add(&a.pend[2 * v + (ns & 1)], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if ((prev + 1) % need == 0) {
         const int32_t u = a.tile_pos[v];
+        if (cursor) {
+            __hip_atomic_store(&a.ready[u], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const int x = m.phys[u & 7];
+            int64_t lp = 0;
+            ring_push(a, a.qslots + m.off[x], (uint32_t)m.cap[x], &a.qhead[kQcTail + x], u, ServeQuit{&a, &lp});
+        }
+    }
+}
+
+// Serving in cursor mode: a tile is ready when its position's ready word
+// is 1 (its step lives in done[]).
+__device__ __forceinline__ void serve_ready(const MsgArgs& a, const QueueMap& m, int32_t u, bool cursor,
+                                            const ServeQuit& quit) {
+    if (cursor) {
+        __hip_atomic_store(&a.ready[u], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
         const int x = m.phys[u & 7];
-        int64_t lp = 0;
-        ring_push(a, a.qslots + m.off[x], (uint32_t)m.cap[x], &a.qhead[kQcTail + x], u, ServeQuit{&a, &lp});
+        ring_push(a, a.qslots + m.off[x], (uint32_t)m.cap[x], &a.qhead[kQcTail + x], u, quit);
     }
 }
 
@@ -950,6 +967,7 @@ __device__ __forceinline__ void serve_loop(const MsgArgs& a, SweepFn sweep, doub
     const int x = (int)(__builtin_amdgcn_s_getreg(kXccIdReg) & 7);
     int64_t last_poll = 0;
     const ServeQuit quit{&a, &last_poll};
+    const bool cursor = use_cursor(a.ntiles, G);
     if (threadIdx.x == 0) {
         const uint32_t rank = __hip_atomic_fetch_add(&qc[kQcWgs + x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_or(&qc[kQcMask], 1u << x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -959,15 +977,17 @@ __device__ __forceinline__ void serve_loop(const MsgArgs& a, SweepFn sweep, doub
     if (threadIdx.x == 0) queue_map(__hip_atomic_load(&qc[kQcMask], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), a.ntiles, s_m);
     __syncthreads();
     // launch start, part 1: free every slot; per position the cross flag,
-    // the rebuilt counters and whether the tile is ready (bit 1)
+    // the rebuilt counters and whether the tile is ready (bit 1; cursor
+    // mode: its ready word, which lives in the ready-queue region)
     const int64_t stride = (int64_t)G * NT, gtid = (int64_t)w * NT + threadIdx.x;
     for (int y = 0; y < 8; ++y)
         for (int64_t i = gtid; i < s_m.cap[y]; i += stride) {
-            a.qslots[s_m.off[y] + i] = slot_word((uint32_t)i, 0);
+            if (!cursor) a.qslots[s_m.off[y] + i] = slot_word((uint32_t)i, 0);
             a.pslots[s_m.off[y] + i] = slot_word((uint32_t)i, 0);
         }
     for (int64_t i = gtid; i < a.ntiles; i += stride) {
         const int32_t u = (int32_t)i, t = a.tile_list[u];
+        if (cursor) a.ready[u] = 0;
         if (t < 0) continue;
         const int32_t sv = a.tile_solve[t], d = ld_rlx(&a.done[t]);
         const int32_t fs = ld_rlx(&a.final_step[sv]);
@@ -989,11 +1009,12 @@ __device__ __forceinline__ void serve_loop(const MsgArgs& a, SweepFn sweep, doub
         a.pend[2 * t + (d & 1)] = gated || ready ? 0 : c0;
         a.pend[2 * t + ((d + 1) & 1)] = ce > 0 && (d + 1) % ce == 0 ? 0 : c1;
         a.xpub[u] = cross | (ready ? 2 : 0);
+        if (cursor && ready) a.ready[u] = 1;
     }
     if (w == 0 && threadIdx.x == 0) qc[kQcLive] = (uint32_t)a.nlive;
     if (!grid_barrier(a.bar, a.err, a.wait_ticks)) return;
     // part 2: queue the ready tiles
-    for (int64_t i = gtid; i < a.ntiles; i += stride) {
+    for (int64_t i = gtid; i < a.ntiles && !cursor; i += stride) {
         const int32_t u = (int32_t)i;
         if (a.tile_list[u] < 0 || !(a.xpub[u] & 2)) continue;
         const int xu = s_m.phys[u & 7];
@@ -1026,7 +1047,7 @@ __device__ __forceinline__ void serve_loop(const MsgArgs& a, SweepFn sweep, doub
                 const int32_t t = a.tile_list[u];
                 const int32_t ns = ld_rlx(&a.done[t]);
                 const int32_t cnt = a.dep_ptr[t + 1] - a.dep_ptr[t] + 1;
-                for (int32_t i = 0; i < cnt; ++i) serve_count(a, s_m, t, ns, i);
+                for (int32_t i = 0; i < cnt; ++i) serve_count(a, s_m, t, ns, i, cursor);
             }
             h = e;
         }
@@ -1037,6 +1058,34 @@ __device__ __forceinline__ void serve_loop(const MsgArgs& a, SweepFn sweep, doub
             int32_t u = -1, stop = 0;
             if (quit() || __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
                 stop = 1;
+            } else if (cursor) {
+                // claim the next ready position at or after the XCD's cursor
+                const int64_t t0 = wall_clock64();
+                int32_t misses = 0;
+                if (s_m.n[x] == 0) stop = 1;
+                while (u < 0 && !stop) {
+                    const uint32_t p = __hip_atomic_fetch_add(&qc[kQcHead + x], 1u, __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_AGENT) % (uint32_t)s_m.n[x];
+                    int32_t v = -1;
+                    for (int g = 0; g < 8; ++g) {
+                        const int32_t ng = a.ntiles > g ? (a.ntiles - g + 7) / 8 : 0;
+                        if (s_m.phys[g] == x && (int32_t)p >= s_m.pre[g] && (int32_t)p < s_m.pre[g] + ng)
+                            v = g + 8 * ((int32_t)p - s_m.pre[g]);
+                    }
+                    if (v >= 0 && ld_rlx(&a.ready[v]) != 0 &&
+                        __hip_atomic_exchange(&a.ready[v], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                        u = v;
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    } else if (quit()) {
+                        stop = 1;
+                    } else if (wall_clock64() - t0 > a.wait_ticks ||
+                               __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                        __hip_atomic_fetch_or(a.err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        stop = 1;
+                    } else if (++misses > 8) {
+                        __builtin_amdgcn_s_sleep(2);
+                    }
+                }
             } else {
                 const uint32_t t = __hip_atomic_fetch_add(&qc[kQcHead + x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 u = (int32_t)ring_take(a, q, cap, t, quit);
@@ -1098,14 +1147,10 @@ __device__ __forceinline__ void serve_loop(const MsgArgs& a, SweepFn sweep, doub
             if (__shfl(decided, 0, 64)) {
                 // the solve goes on: every tile of it has finished step ns
                 const int32_t b0 = a.solve_base[sv], nt = a.solve_ntiles[sv];
-                for (int32_t i = lane; i < nt; i += 64) {
-                    const int32_t v = b0 + i;
-                    const int xv = s_m.phys[v & 7];
-                    ring_push(a, a.qslots + s_m.off[xv], (uint32_t)s_m.cap[xv], &qc[kQcTail + xv], v, quit);
-                }
+                for (int32_t i = lane; i < nt; i += 64) serve_ready(a, s_m, b0 + i, cursor, quit);
             } else if (!dec && !listed) {
                 const int32_t cnt = a.dep_ptr[t + 1] - a.dep_ptr[t] + 1;
-                for (int32_t i = lane; i < cnt; i += 64) serve_count(a, s_m, t, ns, i);
+                for (int32_t i = lane; i < cnt; i += 64) serve_count(a, s_m, t, ns, i, cursor);
             }
         }
         __syncthreads();

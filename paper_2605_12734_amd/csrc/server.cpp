@@ -415,6 +415,7 @@ void Server::run() {
         a.pend = reinterpret_cast<int32_t*>(arena + c_pend);
         a.qslots = reinterpret_cast<unsigned long long*>(arena + c_qslots);
         a.pslots = a.qslots + (2 * list.size() + 8);
+        a.ready = reinterpret_cast<int32_t*>(a.qslots);   // cursor mode: ready words in the ready-queue region
         a.qhead = reinterpret_cast<unsigned int*>(arena + c_qctl);
         int grid = std::min<int>(grid_cap, (int)list.size());
         if (grid >= kNumXcd) grid -= grid % kNumXcd;

@@ -175,6 +175,30 @@ def test_served_384_request_survives_yields():
     assert epochs >= 2
 
 
+def test_served_two_384_requests_cursor_mode_with_yields():
+    # two 384^3 fp64 solves put 6912 tiles in a launch (at least 4 per
+    # workgroup: the serving scheduler claims ready tiles from per-XCD
+    # cursors); small requests arriving meanwhile end epochs early
+    import time
+    from paper_2605_12734_amd.serving import Server
+    big = [dict(n=384, dtype="f64", odf=64, tol=1e-6, max_iters=40, check_every=10, seed=83 + i) for i in range(2)]
+    small = [dict(n=24 + 5 * i, dtype=("f64", "f32")[i % 2], odf=(8, 1)[i % 2], tol=1e-4, max_iters=90,
+                  check_every=(0, 3)[i % 2], seed=95 + i) for i in range(4)]
+    with Server(arena_bytes=6 << 30, max_slots=8) as srv:
+        tb = [srv.submit(**q) for q in big]
+        ts = []
+        for q in small:
+            time.sleep(0.004)
+            ts.append(srv.submit(**q))
+        got = [(srv.wait(t, timeout=300), srv.fetch(t)) for t in tb + ts]
+    for q, (res, field) in zip(big + small, got):
+        dt = np.float32 if q["dtype"] == "f32" else np.float64
+        w, it, r = oracle.solve(q["n"], dt, seed=q["seed"], iters=q["max_iters"], tol=q["tol"],
+                                check_every=q["check_every"])
+        assert res["iters"] == it and res["residual"] == r, q
+        assert np.array_equal(field, w), q
+
+
 @pytest.mark.parametrize("exec_", ["persistent", "msgdriven"])
 def test_device_wait_bound_reports_timeout(exec_):
     # a 1 ns bound on every device-side wait: the launch's barriers and
