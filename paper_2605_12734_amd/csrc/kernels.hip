@@ -805,8 +805,9 @@ __device__ __forceinline__ void queue_loop(const MsgArgs& a, SweepFn sweep, doub
             int64_t pay = -1;
             int32_t stop = 0;
             if (cursor) {
-            // claim the next ready tile at or after the cursor; the
-            // claimed count (qc[kQcTail + x]) reaching total ends the loop
+            // claim the next ready tile at or after the cursor; the loop
+            // ends once every tile of the XCD has been claimed for its last
+            // step (counted in qc[kQcTail + x])
             const int64_t t0 = wall_clock64();
             int32_t misses = 0;
             if (total == 0) stop = 1;
@@ -819,17 +820,18 @@ __device__ __forceinline__ void queue_loop(const MsgArgs& a, SweepFn sweep, doub
                     if (s_m.phys[g] == x && (int32_t)p >= s_m.pre[g] && (int32_t)p < s_m.pre[g] + ng)
                         u = g + 8 * ((int32_t)p - s_m.pre[g]);
                 }
-                if (u >= 0 && ld_rlx(&a.ready[u]) != 0) {
-                    const int32_t v = __hip_atomic_exchange(&a.ready[u], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    if (v != 0) {
+                const int32_t v =
+                    u >= 0 ? __hip_atomic_exchange(&a.ready[u], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+                if (v != 0) {
+                    if (v == a.qsteps)
                         __hip_atomic_fetch_add(&qc[kQcTail + x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        pay = (int64_t)task_payload(u, v - 1);
-                        // acquire side: the neighbours' step data
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                        break;
-                    }
+                    pay = (int64_t)task_payload(u, v - 1);
+                    // acquire side: the neighbours' step data
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    break;
                 }
-                if (__hip_atomic_load(&qc[kQcTail + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= total) {
+                if (__hip_atomic_load(&qc[kQcTail + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+                    (uint32_t)s_m.n[x]) {
                     stop = 1;
                     break;
                 }
