@@ -61,6 +61,18 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+# Kernel whose device time the roofline divides by, per execution form (the
+# persistent and message-driven forms run every iteration in one launch:
+# their time per iteration is used).
+KERNEL_OF_EXEC = {
+    "graph": "k_sweep (fused 7-point sweep + halo pack/exchange/unpack)",
+    "fused": "k_sweep (fused 7-point sweep + halo pack/exchange/unpack)",
+    "per_chare": "k_sweep per chare + k_pack_b + k_unpack (time per iteration)",
+    "persistent": "k_persistent (time per iteration)",
+    "msgdriven": "k_msgdriven (time per iteration)",
+}
+
+
 def load_traffic(key: str):
     """HBM bytes per sweep launch from the committed rocprofv3 counter runs,
     if they were taken on the current kernel source; else None."""
@@ -436,8 +448,8 @@ def main():
                    "exec": args.exec, "hints": args.hints},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBPS, 4),
-                     "traffic": load_traffic(workload),
-                     "kernel": "k_sweep (fused 7-point sweep + halo pack/exchange/unpack)",
+                     "traffic": load_traffic(workload) if args.exec in ("graph", "fused") else None,
+                     "kernel": KERNEL_OF_EXEC.get(args.exec, args.exec),
                      "alg_bytes_per_launch": bytes_per_iter,
                      "avg_launch_us": round(leg["launch_s"] * 1e6, 2),
                      "strict_frac_2s_per_lup": round(strict / PEAK_HBM_GBPS, 4),

@@ -744,6 +744,58 @@ __device__ __forceinline__ void publisher_loop(const MsgArgs& a, const QueueMap&
     }
 }
 
+// Tile (plain grid) or launch position (serving) at cursor position p of
+// XCD x: the positions of the groups dealt to x, in order.
+__device__ __forceinline__ int32_t cursor_item(const QueueMap& m, int32_t n, int x, int32_t p) {
+    int32_t u = -1;
+    for (int g = 0; g < 8; ++g) {
+        const int32_t ng = n > g ? (n - g + 7) / 8 : 0;
+        if (m.phys[g] == x && p >= m.pre[g] && p < m.pre[g] + ng) u = g + 8 * (p - m.pre[g]);
+    }
+    return u;
+}
+
+// Cursor mode: take positions from XCD x's cursor until one holds a ready
+// word, exchange it for 0 (exactly one claimer wins) and return the task
+// payload (plain grid: the tile and its relative step; serving: the
+// position).  Plain grids stop (-1) once every tile of the XCD has been
+// claimed for its last step (counted in qhead[kQcTail + x]); serving stops
+// when quit() turns true.  A run of misses backs off; the wait is bounded
+// (error flag 2).
+template <class Quit>
+__device__ __forceinline__ int64_t cursor_claim(const MsgArgs& a, const QueueMap& m, int x, Quit quit) {
+    unsigned int* qc = a.qhead;
+    const bool plain = a.tile_list == nullptr;
+    const int64_t t0 = wall_clock64();
+    int32_t misses = 0;
+    if (m.n[x] == 0) return -1;
+    for (;;) {
+        const int32_t p = (int32_t)(__hip_atomic_fetch_add(&qc[kQcHead + x], 1u, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT) %
+                                    (uint32_t)m.n[x]);
+        const int32_t u = cursor_item(m, a.ntiles, x, p);
+        // serving reads the word first (most positions of a launch hold no
+        // ready solve step); plain grids exchange at once
+        const int32_t v = u >= 0 && (plain || ld_rlx(&a.ready[u]) != 0)
+                              ? __hip_atomic_exchange(&a.ready[u], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                              : 0;
+        if (v != 0) {
+            if (!plain) return u;
+            if (v == a.qsteps) __hip_atomic_fetch_add(&qc[kQcTail + x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return (int64_t)task_payload(u, v - 1);
+        }
+        if (plain ? __hip_atomic_load(&qc[kQcTail + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= (uint32_t)m.n[x]
+                  : quit())
+            return -1;
+        if (++misses > 8) __builtin_amdgcn_s_sleep(2);
+        if (wall_clock64() - t0 > a.wait_ticks ||
+            __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+            __hip_atomic_fetch_or(a.err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return -1;
+        }
+    }
+}
+
 template <int NT, class SweepFn>
 __device__ __forceinline__ void queue_loop(const MsgArgs& a, SweepFn sweep, double* red) {
     __shared__ QueueMap s_m;
@@ -805,57 +857,16 @@ __device__ __forceinline__ void queue_loop(const MsgArgs& a, SweepFn sweep, doub
             int64_t pay = -1;
             int32_t stop = 0;
             if (cursor) {
-            // claim the next ready tile at or after the cursor; the loop
-            // ends once every tile of the XCD has been claimed for its last
-            // step (counted in qc[kQcTail + x])
-            const int64_t t0 = wall_clock64();
-            int32_t misses = 0;
-            if (total == 0) stop = 1;
-            while (!stop) {
-                const uint32_t p = __hip_atomic_fetch_add(&qc[kQcHead + x], 1u, __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_AGENT) % (uint32_t)s_m.n[x];
-                int32_t u = -1;
-                for (int g = 0; g < 8; ++g) {
-                    const int32_t ng = a.ntiles > g ? (a.ntiles - g + 7) / 8 : 0;
-                    if (s_m.phys[g] == x && (int32_t)p >= s_m.pre[g] && (int32_t)p < s_m.pre[g] + ng)
-                        u = g + 8 * ((int32_t)p - s_m.pre[g]);
-                }
-                const int32_t v =
-                    u >= 0 ? __hip_atomic_exchange(&a.ready[u], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
-                if (v != 0) {
-                    if (v == a.qsteps)
-                        __hip_atomic_fetch_add(&qc[kQcTail + x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    pay = (int64_t)task_payload(u, v - 1);
-                    // acquire side: the neighbours' step data
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                    break;
-                }
-                if (__hip_atomic_load(&qc[kQcTail + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
-                    (uint32_t)s_m.n[x]) {
-                    stop = 1;
-                    break;
-                }
-                // a run of misses (end of the launch, or a wait on a slow
-                // neighbour): back off instead of hammering the cursor
-                if (++misses > 8) __builtin_amdgcn_s_sleep(2);
-                if (wall_clock64() - t0 > a.wait_ticks ||
-                    __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                    __hip_atomic_fetch_or(a.err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    stop = 1;
-                    break;
-                }
-            }
+                if (total == 0) stop = 1;
+                else pay = cursor_claim(a, s_m, x, [] { return false; });
             } else {
-            const uint32_t t = __hip_atomic_fetch_add(&qc[kQcHead + x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (t >= total) {
-                stop = 1;
-            } else {
-                pay = ring_take(a, q, cap, t);
-                if (pay < 0) stop = 1;
-                // acquire side: the neighbours' step data
-                else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                const uint32_t t =
+                    __hip_atomic_fetch_add(&qc[kQcHead + x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (t < total) pay = ring_take(a, q, cap, t);
             }
-            }
+            if (pay < 0) stop = 1;
+            // acquire side: the neighbours' step data
+            else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             s_tile = pay < 0 ? -1 : (int32_t)(pay >> 16);
             s_rel = pay < 0 ? 0 : (int32_t)(pay & 0xFFFF);
             s_stop = stop;
@@ -1061,33 +1072,9 @@ __device__ __forceinline__ void serve_loop(const MsgArgs& a, SweepFn sweep, doub
             if (quit() || __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
                 stop = 1;
             } else if (cursor) {
-                // claim the next ready position at or after the XCD's cursor
-                const int64_t t0 = wall_clock64();
-                int32_t misses = 0;
-                if (s_m.n[x] == 0) stop = 1;
-                while (u < 0 && !stop) {
-                    const uint32_t p = __hip_atomic_fetch_add(&qc[kQcHead + x], 1u, __ATOMIC_RELAXED,
-                                                              __HIP_MEMORY_SCOPE_AGENT) % (uint32_t)s_m.n[x];
-                    int32_t v = -1;
-                    for (int g = 0; g < 8; ++g) {
-                        const int32_t ng = a.ntiles > g ? (a.ntiles - g + 7) / 8 : 0;
-                        if (s_m.phys[g] == x && (int32_t)p >= s_m.pre[g] && (int32_t)p < s_m.pre[g] + ng)
-                            v = g + 8 * ((int32_t)p - s_m.pre[g]);
-                    }
-                    if (v >= 0 && ld_rlx(&a.ready[v]) != 0 &&
-                        __hip_atomic_exchange(&a.ready[v], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                        u = v;
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                    } else if (quit()) {
-                        stop = 1;
-                    } else if (wall_clock64() - t0 > a.wait_ticks ||
-                               __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                        __hip_atomic_fetch_or(a.err, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        stop = 1;
-                    } else if (++misses > 8) {
-                        __builtin_amdgcn_s_sleep(2);
-                    }
-                }
+                u = (int32_t)cursor_claim(a, s_m, x, quit);
+                if (u < 0) stop = 1;
+                else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             } else {
                 const uint32_t t = __hip_atomic_fetch_add(&qc[kQcHead + x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 u = (int32_t)ring_take(a, q, cap, t, quit);
