@@ -398,12 +398,12 @@ def main():
     ap.add_argument("--jacobi2d", action="store_true")
     ap.add_argument("--launch", action="store_true")
     ap.add_argument("--serving", action="store_true")
-    ap.add_argument("--serving-count", type=int, default=64)
+    ap.add_argument("--serving-count", type=int, default=256)
     ap.add_argument("--all", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs one GPU's share of chares; --gpus must be 1",
+        print(json.dumps({"error": "one GPU's share of chares only: a single-GPU benchmark; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
