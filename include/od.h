@@ -343,16 +343,18 @@ od_status od_request_bytes(const od_request* req, size_t* bytes);
  * OD_EAGAIN if the submission queue is full, OD_EINVAL for bad fields. */
 od_status od_submit(struct od_server* s, const od_request* req, uint64_t* ticket);
 /* The server's worker thread drives the device (admission, scheduling
- * epochs, retirement).  This reports how many requests are resident
+ * epochs); a second thread retires finished solves (copies each field to
+ * host memory, frees its slot and arena space).  This reports how many
+ * requests are resident
  * (`active`) and waiting (`queued`); OD_ECANCELED once the server has
  * stopped after a device error. */
 od_status od_server_step(struct od_server* s, int32_t* active, int32_t* queued);
 
-/* Where the server's worker thread spent its time so far (host clock):
- * inside scheduling epochs (launch to completion), admitting requests
- * (planning, descriptor upload, field initialisation), retiring finished
- * solves (copying the field to host memory, freeing arena space), and
- * waiting for work. */
+/* Where the server's threads spent their time so far (host clock): the
+ * worker inside scheduling epochs (launch to completion), admitting
+ * requests (planning, descriptor upload, field initialisation) and waiting
+ * for work; the retire thread copying finished fields to host memory
+ * (retire_s, which overlaps the epochs). */
 typedef struct {
     int64_t epochs;
     double epoch_s, admit_s, retire_s, idle_s;

@@ -1350,6 +1350,24 @@ hipError_t launch_queue_init(hipStream_t st, const MsgArgs& a) {
     return hipGetLastError();
 }
 
+__global__ void k_serve_positions(const int32_t* __restrict__ list, int32_t n, int32_t stride,
+                                  int32_t* __restrict__ tpos, int32_t* __restrict__ sbase) {
+    const int32_t q = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (q >= n) return;
+    const int32_t v = list[q];
+    if (v < 0) return;
+    tpos[v] = q;
+    if (v % stride == 0) sbase[v / stride] = q;
+}
+
+hipError_t launch_serve_positions(hipStream_t st, const int32_t* list, int32_t n, int32_t stride, int32_t* tpos,
+                                  int32_t* sbase) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_serve_positions, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, list, n, stride,
+                       tpos, sbase);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // initialisation and global-layout I/O
 

@@ -128,6 +128,12 @@ hipError_t launch_msgdriven(int dtype_bytes, int tx, int ty, hipStream_t st, int
 // Clear the control words of a dependency-counting message-driven launch
 // (the launch itself lays out and fills its queues).
 hipError_t launch_queue_init(hipStream_t st, const MsgArgs& a);
+// Serving: for every launch position q of list[0..n) holding a tile id v
+// (-1 = padding), tpos[v] = q, and sbase[v / stride] = q when v is a
+// solve's first tile (v % stride == 0).  Entries of tiles not in the list
+// are left as they are.
+hipError_t launch_serve_positions(hipStream_t st, const int32_t* list, int32_t n, int32_t stride, int32_t* tpos,
+                                  int32_t* sbase);
 
 // Serving kernel: fp64 tiles of (kServeTx8, kServeTy8) and fp32 tiles of
 // (kServeTx4, kServeTy4) columns, same thread count, one cooperative launch.

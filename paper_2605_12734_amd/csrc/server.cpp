@@ -15,9 +15,9 @@
 // flag; every workgroup then stops taking new tasks and the epoch ends.  All
 // scheduler state (per-tile step counters, gates, residual slots) lives in
 // HBM, so the next epoch resumes exactly where this one stopped.  A
-// finished solve leaves the next epoch's tile list; while that epoch runs,
-// its field is copied to host memory with the copy engine and its arena
-// space freed.
+// finished solve leaves the next epoch's tile list; a second host thread
+// copies its field to host memory with the copy engine while the worker
+// goes on launching and polling, then frees its slot and arena space.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -110,6 +110,11 @@ struct Server {
     std::condition_variable cv;
     std::thread worker;
     bool stop = false;
+    // finished solves waiting to be copied out, and the thread that does it
+    std::deque<Request*> retire_q;
+    std::condition_variable rcv;
+    std::thread retirer;
+    bool retire_stop = false;
     std::deque<uint64_t> queue;
     std::map<uint64_t, std::unique_ptr<Request>> reqs;
     std::vector<uint64_t> slot_ticket;
@@ -158,9 +163,24 @@ struct Server {
         return -1;
     }
 
+    // the worker has something to do: a running solve, or a queued request
+    // that a free slot and free arena space can take (caller holds mu)
+    bool worker_has_work() const {
+        for (uint64_t t : slot_ticket) {
+            if (!t) continue;
+            const auto it = reqs.find(t);
+            if (it != reqs.end() && it->second->state == OD_REQ_RUNNING && !it->second->finished) return true;
+        }
+        if (queue.empty()) return false;
+        const auto it = reqs.find(queue.front());
+        return it == reqs.end() || (free_slot() >= 0 && fits_somewhere(it->second->bytes));
+    }
+
     od_status setup_slot(Request& R, int32_t slot);
     void run();
     void retire(Request& R);
+    void retire_run();
+    void cancel_unfinished();
 };
 
 // ---- admission: plan the solve, initialise it, fill its slot's tables ------
@@ -298,20 +318,12 @@ void Server::run() {
         return;
     }
     std::vector<int32_t> list;
-    std::vector<int32_t> tpos((size_t)max_slots * kTileStride, -1);
-    std::vector<int32_t> sbase((size_t)max_slots, -1);
-    std::vector<Request*> retiring;
     for (;;) {
         std::vector<Request*> admitted;
         const double t_wait = now_s();
         {
             std::unique_lock<std::mutex> lk(mu);
-            cv.wait(lk, [&] {
-                if (stop || !queue.empty()) return true;
-                for (uint64_t t : slot_ticket)
-                    if (t) return true;
-                return false;
-            });
+            cv.wait(lk, [&] { return stop || worker_has_work(); });
             if (stop) break;
             stats.idle_s += now_s() - t_wait;
             // FIFO admission while a slot and arena space are free
@@ -369,16 +381,13 @@ void Server::run() {
         // 8 entries; each solve's tiles keep their own XCD-interleaved order,
         // so a solve's XCD groups stay together
         e = hipMemcpyAsync(arena + c_list, list.data(), list.size() * 4, hipMemcpyHostToDevice, st);
-        // launch position of every tile and of every solve's first tile
-        std::fill(tpos.begin(), tpos.end(), -1);
-        std::fill(sbase.begin(), sbase.end(), -1);
-        for (size_t q = 0; q < list.size(); ++q)
-            if (list[q] >= 0) {
-                tpos[(size_t)list[q]] = (int32_t)q;
-                if (list[q] % kTileStride == 0) sbase[(size_t)(list[q] / kTileStride)] = (int32_t)q;
-            }
-        if (e == hipSuccess) e = hipMemcpyAsync(arena + c_tpos, tpos.data(), tpos.size() * 4, hipMemcpyHostToDevice, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(arena + c_sbase, sbase.data(), sbase.size() * 4, hipMemcpyHostToDevice, st);
+        // launch position of every listed tile and of every listed solve's
+        // first tile, filled on the device (the kernel reads them only for
+        // the tiles of the list)
+        if (e == hipSuccess)
+            e = launch_serve_positions(st, reinterpret_cast<const int32_t*>(arena + c_list), (int32_t)list.size(),
+                                       kTileStride, reinterpret_cast<int32_t*>(arena + c_tpos),
+                                       reinterpret_cast<int32_t*>(arena + c_sbase));
         __atomic_store_n(h_yield, 0, __ATOMIC_RELEASE);
         if (e == hipSuccess) e = hipMemsetAsync(arena + c_yield, 0, 4, st);
         MsgArgs a{};
@@ -424,15 +433,6 @@ void Server::run() {
         if (e == hipSuccess) e = launch_serve(st, grid, a);
         if (e == hipSuccess) e = hipEventRecord(ev, st);
         launched = e == hipSuccess;
-        }
-        // the previous epoch's finished solves are copied out while this
-        // epoch runs (their chares are not in its tile list)
-        if (!retiring.empty()) {
-            const double t_ret0 = now_s();
-            for (Request* R : retiring) retire(*R);
-            retiring.clear();
-            std::lock_guard<std::mutex> lk(mu);
-            stats.retire_s += now_s() - t_ret0;
         }
         if (!launched && e == hipSuccess) continue;
         while (e == hipSuccess) {
@@ -485,19 +485,48 @@ void Server::run() {
             }
             break;
         }
+        // finished solves go to the retire thread (their chares are in no
+        // later tile list)
         for (size_t i = 0; i < active.size(); ++i)
             if (__atomic_load_n(&h_done[active[i]->slot], __ATOMIC_ACQUIRE) > 0) {
                 std::lock_guard<std::mutex> lk(mu);
                 if (!seen[i]) active[i]->t_done = now_s();
                 active[i]->finished = true;
-                retiring.push_back(active[i]);
+                retire_q.push_back(active[i]);
+                rcv.notify_one();
             }
     }
-    for (Request* R : retiring) retire(*R);
     hipEventDestroy(ev);
+    cancel_unfinished();
+}
+
+// Retire thread: copy out finished solves in completion order; each freed
+// slot and arena range may let the worker admit the next request.
+void Server::retire_run() {
+    for (;;) {
+        Request* R = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            rcv.wait(lk, [&] { return retire_stop || !retire_q.empty(); });
+            if (retire_q.empty()) return;   // asked to stop, nothing left
+            R = retire_q.front();
+            retire_q.pop_front();
+        }
+        const double t0 = now_s();
+        retire(*R);
+        std::lock_guard<std::mutex> lk(mu);
+        stats.retire_s += now_s() - t0;
+        cv.notify_all();
+    }
+}
+
+// Cancel every request that is queued or still running (finished solves
+// belong to the retire thread, which completes or cancels them itself).
+void Server::cancel_unfinished() {
     std::lock_guard<std::mutex> lk(mu);
     for (auto& kv : reqs) {
         Request& R = *kv.second;
+        if (R.finished) continue;
         if (R.state == OD_REQ_QUEUED || R.state == OD_REQ_RUNNING) R.state = OD_REQ_CANCELED;
         if (R.grid) {
             R.grid.reset();
@@ -656,6 +685,7 @@ od_status od_server_create(void* hip_stream, void* dev_arena, size_t arena_bytes
             hipStreamDestroy(S.cst);
             return fail(OD_EHIP, "no co-resident workgroups for the serving kernel");
         }
+        S.retirer = std::thread([&S] { S.retire_run(); });
         S.worker = std::thread([&S] { S.run(); });
         *out = h.release();
         return OD_OK;
@@ -737,16 +767,21 @@ od_status od_poll(od_server* sv, uint64_t ticket, od_info* out) {
 od_status od_fetch(od_server* sv, uint64_t ticket, void* host_dst, size_t bytes) {
     if (!sv || !host_dst) return fail(OD_EINVAL, "NULL argument");
     od::Server& S = sv->s;
-    std::lock_guard<std::mutex> lk(S.mu);
-    auto it = S.reqs.find(ticket);
-    if (it == S.reqs.end()) return fail(OD_EINVAL, "unknown ticket " + std::to_string(ticket));
-    od::Request& R = *it->second;
-    if (R.state == OD_REQ_CANCELED) return fail(OD_ECANCELED, "request cancelled");
-    if (R.state != OD_REQ_DONE) return fail(OD_ENOTREADY, "request not finished");
-    if (bytes < R.result.size())
-        return fail(OD_EINVAL, "buffer of " + std::to_string(bytes) + " bytes, need " + std::to_string(R.result.size()));
-    std::memcpy(host_dst, R.result.data(), R.result.size());
-    S.reqs.erase(it);
+    std::unique_ptr<od::Request> R;
+    {
+        std::lock_guard<std::mutex> lk(S.mu);
+        auto it = S.reqs.find(ticket);
+        if (it == S.reqs.end()) return fail(OD_EINVAL, "unknown ticket " + std::to_string(ticket));
+        const od::Request& Q = *it->second;
+        if (Q.state == OD_REQ_CANCELED) return fail(OD_ECANCELED, "request cancelled");
+        if (Q.state != OD_REQ_DONE) return fail(OD_ENOTREADY, "request not finished");
+        if (bytes < Q.result.size())
+            return fail(OD_EINVAL, "buffer of " + std::to_string(bytes) + " bytes, need " + std::to_string(Q.result.size()));
+        R = std::move(it->second);
+        S.reqs.erase(it);
+    }
+    // the (possibly large) copy runs without the server lock held
+    std::memcpy(host_dst, R->result.data(), R->result.size());
     return OD_OK;
 }
 
@@ -760,6 +795,13 @@ od_status od_server_destroy(od_server* sv) {
         S.cv.notify_all();
     }
     if (S.worker.joinable()) S.worker.join();
+    // the retire thread finishes the solves already handed to it, then stops
+    {
+        std::lock_guard<std::mutex> lk(S.mu);
+        S.retire_stop = true;
+        S.rcv.notify_all();
+    }
+    if (S.retirer.joinable()) S.retirer.join();
     hipError_t e = hipStreamSynchronize(S.st);
     if (S.cst) {
         const hipError_t e2 = hipStreamSynchronize(S.cst);
