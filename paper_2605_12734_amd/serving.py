@@ -101,8 +101,8 @@ class Server:
         return int(a.value), int(q.value)
 
     def stats(self) -> dict:
-        """Worker-thread time accounting: epochs, seconds in epochs, admission,
-        retirement and idle."""
+        """Time accounting: epochs, seconds in epochs, admission and idle
+        (worker thread), retirement (retire thread, overlapping epochs)."""
         st = B.od_server_stats()
         check(lib().od_server_stats_get(self.h, ctypes.byref(st)), "od_server_stats_get")
         return {f: getattr(st, f) for f, _ in st._fields_}

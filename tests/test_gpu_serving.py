@@ -112,3 +112,25 @@ def test_request_errors():
         assert res["iters"] == 20
         with pytest.raises(ODError):
             srv.poll(t + 1000)
+
+
+def test_close_with_work_in_flight():
+    # closing the server stops running epochs promptly, cancels what is
+    # unfinished and still completes the copy-out of finished solves
+    srv = Server(arena_bytes=512 << 20, max_slots=8)
+    try:
+        q = dict(n=10, dtype="f64", odf=1, tol=0.0, max_iters=20, check_every=0, seed=1)
+        small = srv.submit(**q)
+        for i in range(3):
+            srv.submit(n=64, dtype="f64", odf=8, tol=0.0, max_iters=10**6, check_every=0, seed=2 + i)
+        res = srv.wait(small)
+        _check(res, srv.fetch(small), q)
+        # the retire thread books its time just after the result is published
+        t0 = time.monotonic()
+        while srv.stats()["retire_s"] == 0.0 and time.monotonic() - t0 < 5.0:
+            time.sleep(1e-3)
+        assert srv.stats()["retire_s"] > 0.0
+    finally:
+        t0 = time.monotonic()
+        srv.close()
+        assert time.monotonic() - t0 < 30.0
