@@ -135,10 +135,11 @@ def grid_leg(n, odf, dtype, exec_, iters, steps, warmup, tile=None, **kw):
     return t
 
 
-def cpu_baseline(n, dtype, budget_s=25.0, max_iters=200, chunk=10):
-    """The oracle on this host's cores: the whole step (max_iters
-    iterations) of the same workload, or as many iterations as fit in about
-    budget_s seconds at the rate of a `chunk`-iteration estimate."""
+def cpu_baseline(n, dtype, target_s=12.0, max_iters=200, chunk=10):
+    """The oracle on this host's cores, on a bounded sample of the timed
+    job (max_iters iterations: the steps x iterations the GPU ran): as many
+    iterations as take about target_s seconds at the rate of a
+    `chunk`-iteration estimate, at least one."""
     import numpy as np
     import oracle
 
@@ -150,7 +151,7 @@ def cpu_baseline(n, dtype, budget_s=25.0, max_iters=200, chunk=10):
     t = time.perf_counter()
     oracle.jacobi(U, chunk)                   # rate estimate
     per = (time.perf_counter() - t) / chunk
-    done = max(1, min(max_iters, int(budget_s / max(per, 1e-6))))
+    done = max(1, min(max_iters, int(target_s / max(per, 1e-6))))
     t0 = time.perf_counter()
     oracle.jacobi(U, done)
     dt = time.perf_counter() - t0
@@ -168,7 +169,8 @@ def cpu_baseline(n, dtype, budget_s=25.0, max_iters=200, chunk=10):
     except OSError:
         pass
     return {"value": round(n ** 3 * done / dt / 1e9, 3), "unit": "GLUP/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n}^3 {dtype} undecomposed, {done} of the step's {max_iters} iterations ({dt:.1f} s), same seed/bc",
+            "sample": f"{n}^3 {dtype} undecomposed, {done} of the timed job's {max_iters} iterations "
+                      f"({dt:.1f} s), same seed/bc",
             "single_thread_value": round(n ** 3 * 3 / dt1 / 1e9, 4), "cpu_model": model}
 
 
@@ -469,7 +471,8 @@ def main():
         out["launch"] = launch_leg()
     if args.serving or args.all:
         out["serving"] = serving_leg(count=args.serving_count)
-    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.n, args.dtype)
+    out["cpu_baseline"] = (None if args.no_cpu_baseline
+                           else cpu_baseline(args.n, args.dtype, max_iters=args.iters * args.steps))
     print(json.dumps(out), flush=True)
 
 
