@@ -137,9 +137,10 @@ def grid_leg(n, odf, dtype, exec_, iters, steps, warmup, tile=None, **kw):
 
 def cpu_baseline(n, dtype, target_s=12.0, max_iters=200, chunk=10):
     """The oracle on this host's cores, on a bounded sample of the timed
-    job (max_iters iterations: the steps x iterations the GPU ran): as many
-    iterations as take about target_s seconds at the rate of a
-    `chunk`-iteration estimate, at least one."""
+    job (max_iters iterations: the steps x iterations the GPU ran): one call
+    of as many iterations as take about target_s seconds, at the marginal
+    rate of two short calls (chunk and 2 * chunk iterations; each call also
+    copies the field once)."""
     import numpy as np
     import oracle
 
@@ -149,9 +150,14 @@ def cpu_baseline(n, dtype, target_s=12.0, max_iters=200, chunk=10):
     U = oracle.init_field(n, np.float64 if dtype == "f64" else np.float32, 12734)
     oracle.jacobi(U, 1)                       # first touch, thread start-up
     t = time.perf_counter()
-    oracle.jacobi(U, chunk)                   # rate estimate
-    per = (time.perf_counter() - t) / chunk
-    done = max(1, min(max_iters, int(target_s / max(per, 1e-6))))
+    oracle.jacobi(U, chunk)
+    ta = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.jacobi(U, 2 * chunk)
+    tb = time.perf_counter() - t
+    per = max((tb - ta) / chunk, 1e-6)
+    over = max(ta - chunk * per, 0.0)
+    done = max(1, min(max_iters, int((target_s - over) / per)))
     t0 = time.perf_counter()
     oracle.jacobi(U, done)
     dt = time.perf_counter() - t0
