@@ -55,6 +55,23 @@ def test_512_odf4096_sampled_against_oracle(dtype):
     assert np.array_equal(got, want)
 
 
+def test_512_odf4096_one_full_step_sampled_against_oracle():
+    # the benchmark's step as timed: 200 iterations, graph form, autotuned
+    # tile; a few points the oracle evaluates on their domain of dependence
+    # (up to 401^3 cells each)
+    n = (512, 512, 512)
+    iters = 200
+    pts = [(0, 0, 0), (511, 511, 511), (31, 32, 480), (256, 255, 256), (5, 300, 40)]
+    g = _tuned(n, 4096, "f64")
+    try:
+        g.iterate(iters)
+        got = g.read_points(_lin(pts, n))
+    finally:
+        g.close()
+    want = oracle.point_values(n, pts, iters, np.float64)
+    assert np.array_equal(got, want)
+
+
 def test_512_odf4096_full_iterations_identical_across_modes():
     # 200 iterations: graph (bench launch configuration) = persistent =
     # message-driven = fused with another tile = ODF 8
