@@ -135,7 +135,7 @@ def grid_leg(n, odf, dtype, exec_, iters, steps, warmup, tile=None, **kw):
     return t
 
 
-def cpu_baseline(n, dtype, target_s=12.0, max_iters=200, chunk=10):
+def cpu_baseline(n, dtype, target_s=15.0, max_iters=200, chunk=10):
     """The oracle on this host's cores, on a bounded sample of the timed
     job (max_iters iterations: the steps x iterations the GPU ran): one call
     of as many iterations as take about target_s seconds, at the marginal
