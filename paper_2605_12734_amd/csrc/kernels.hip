@@ -450,12 +450,16 @@ __device__ __forceinline__ bool xcd_barrier(unsigned int* bar, unsigned int* err
     return ok != 0;
 }
 
-template <typename T, int TX, int TY>
+// DYN (a separate instantiation): tiles from per-XCD-group counters.  The
+// static form's tile index is uniform by construction, so its tile
+// descriptors stay in scalar registers (fewer VGPRs, more waves per SIMD);
+// the counter form keeps its own register allocation and occupancy.
+template <typename T, int TX, int TY, bool DYN>
 __global__ void __launch_bounds__((TX / V16<T>::N) * TY)
 k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDev* __restrict__ tiles,
              int32_t ntiles, int parity, int64_t iters, unsigned long long* __restrict__ res, int32_t nres,
              unsigned int* bar, unsigned int* err, const uint8_t* __restrict__ extra, int32_t extra_period,
-             int32_t nchares, int64_t iter_base, int64_t wait_ticks, int hints, int dyn) {
+             int32_t nchares, int64_t iter_base, int64_t wait_ticks, int hints) {
     using S = SW<T, TX, TY>;
     __shared__ T lds[S::LDS];
     __shared__ T red[S::NT / 64];
@@ -490,21 +494,21 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
         const uint8_t* ex = extra ? extra + (size_t)((iter_base + it) % extra_period) * nchares : nullptr;
         T r = 0;
         int slot = -1;
-        // dyn: tiles of this workgroup's XCD group, taken one at a time from
+        // DYN: tiles of this workgroup's XCD group, taken one at a time from
         // the group's counter (the next index is requested while a tile
         // sweeps); otherwise the fixed stride w, w + G, w + 2G, ...
         unsigned int* ctr = &bar[8 + 8 * (int)(it & 1) + xg];
-        if (dyn) {
+        if (DYN) {
             if (threadIdx.x == 0)
                 s_idx = (int32_t)__hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __syncthreads();
         }
-        int32_t idx = dyn ? s_idx : (int32_t)blockIdx.x;
+        int32_t idx = DYN ? s_idx : (int32_t)blockIdx.x;
         for (;;) {
-            const int32_t ti = dyn ? xg + ng * idx : idx;
+            const int32_t ti = DYN ? xg + ng * idx : idx;
             if (ti >= ntiles) break;
             int32_t nxt = idx + (int32_t)gridDim.x;
-            if (dyn && threadIdx.x == 0)
+            if (DYN && threadIdx.x == 0)
                 nxt = (int32_t)__hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const TileDev& t = tiles[ti];
             const int reps = 1 + (ex ? (int)ex[t.blk] : 0);
@@ -516,7 +520,7 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
             }
             slot = t.rslot;
             r = rr > r ? rr : r;
-            if (dyn) {
+            if (DYN) {
                 __syncthreads();
                 if (threadIdx.x == 0) s_idx = nxt;
                 __syncthreads();
@@ -1267,6 +1271,21 @@ int64_t device_wait_ticks(double seconds) {
     return (int64_t)(seconds * 1e3 * (double)khz);
 }
 
+// Co-resident workgroups per CU of a cooperative kernel with `threads` per
+// workgroup, from the occupancy query `per`, capped at `max_waves` (at most
+// 6) waves per SIMD.
+// The query counts waves by VGPRs and LDS, but on gfx950 a kernel with
+// about 100 or more SGPRs (the cooperative kernels here use 106) fits
+// only 6 waves per SIMD where the query reports 7 or 8 (measured: 256-thread
+// workgroups at 72 VGPRs hold 7 per CU at 86 SGPRs, 6 at 102 or 108).  A
+// cooperative grid larger than what is resident never completes its first
+// device-wide barrier.
+static int coop_per_cu(int per, int threads, int max_waves = 6) {
+    const int waves = (threads + 63) / 64;
+    const int cap = (max_waves * 4) / waves;   // 4 SIMDs per CU
+    return per < cap ? per : cap;
+}
+
 int persistent_max_grid(int dtype_bytes, int tx, int ty, int kind) {
     int dev = 0, ncu = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -1274,12 +1293,16 @@ int persistent_max_grid(int dtype_bytes, int tx, int ty, int kind) {
 #define OD_OCC(T, TX, TY)                                                                             \
     if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                      \
         hipError_t e = kind == 0                                                                      \
-            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent<T, TX, TY>,             \
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent<T, TX, TY, false>,      \
+                                                           SW<T, TX, TY>::NT, 0)                      \
+            : kind == 2                                                                               \
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent<T, TX, TY, true>,       \
                                                            SW<T, TX, TY>::NT, 0)                      \
             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_msgdriven<T, TX, TY>,              \
                                                            SW<T, TX, TY>::NT, 0);                     \
         if (e != hipSuccess) return 0;                                                                \
-        return per * ncu;                                                                             \
+        /* the counter form (imbalance, uneven blocks) measured faster at 5 */                         \
+        return coop_per_cu(per, SW<T, TX, TY>::NT, kind == 2 ? 5 : 6) * ncu;                          \
     }
     OD_VARIANTS_F64(OD_OCC)
     OD_VARIANTS_F32(OD_OCC)
@@ -1297,9 +1320,10 @@ hipError_t launch_persistent(int dtype_bytes, int tx, int ty, hipStream_t st, in
     if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                      \
         T* ar = reinterpret_cast<T*>(arena);                                                          \
         void* args[] = {&ar, &blocks, &tiles, &ntiles, &parity, &iters, &res, &nres, &bar, &err,      \
-                        &extra, &extra_period, &nchares, &iter_base, &wait_ticks, &hints, &dyn};             \
-        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_persistent<T, TX, TY>),    \
-                                          dim3(grid), dim3(SW<T, TX, TY>::NT), args, 0, st);          \
+                        &extra, &extra_period, &nchares, &iter_base, &wait_ticks, &hints};            \
+        const void* fn = dyn ? reinterpret_cast<const void*>(k_persistent<T, TX, TY, true>)           \
+                             : reinterpret_cast<const void*>(k_persistent<T, TX, TY, false>);         \
+        return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(SW<T, TX, TY>::NT), args, 0, st);      \
     }
     OD_VARIANTS_F64(OD_LAUNCH)
     OD_VARIANTS_F32(OD_LAUNCH)
@@ -1314,7 +1338,7 @@ int serve_max_grid() {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_serve<kServeTx8, kServeTy8, kServeTx4, kServeTy4>,
                                                      SW<double, kServeTx8, kServeTy8>::NT, 0) != hipSuccess)
         return 0;
-    return per * ncu;
+    return coop_per_cu(per, SW<double, kServeTx8, kServeTy8>::NT) * ncu;
 }
 
 hipError_t launch_serve(hipStream_t st, int grid, const MsgArgs& a) {

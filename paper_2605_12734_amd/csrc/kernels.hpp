@@ -64,7 +64,9 @@ hipError_t launch_persistent(int dtype_bytes, int tx, int ty, hipStream_t st, in
                              int32_t nchares, int64_t iter_base, int hints, int dyn, int64_t wait_ticks);
 // Wall-clock ticks in `seconds` (bound of every device-side wait).
 int64_t device_wait_ticks(double seconds = 10.0);
-// Max co-resident workgroups of the persistent / message-driven kernels.
+// Max co-resident workgroups of a cooperative kernel: kind 0 = persistent
+// with the static tile stride, 2 = persistent with tile counters (dyn),
+// 1 = message-driven.
 int persistent_max_grid(int dtype_bytes, int tx, int ty, int kind);
 
 // Message-driven cooperative sweep: per-tile step counters `done`,

@@ -705,7 +705,7 @@ od_status Grid::persistent_run(int64_t n) {
                                      reinterpret_cast<unsigned int*>(base + L.err),
                                      extra_h.empty() ? nullptr : reinterpret_cast<const uint8_t*>(base + L.extra),
                                      extra_period, (int32_t)plan.chares.size(), iters, mode(),
-                                     (!extra_h.empty() || !plan.regular) ? 1 : 0,
+                                     persistent_dyn() ? 1 : 0,
                                      device_wait_ticks(cfg.wait_s > 0 ? cfg.wait_s : 10.0));
     if (e != hipSuccess) return fail(OD_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
     parity ^= (int)(n & 1);

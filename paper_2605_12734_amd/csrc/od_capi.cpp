@@ -95,7 +95,7 @@ od_status od_create(const od_config* cfg, void* hip_stream, void* dev_workspace,
     s = G.init_field();
     if (s != OD_OK) return s;
     if (G.cfg.exec == OD_PERSISTENT || G.cfg.exec == OD_MSGDRIVEN) {
-        int cap = od::persistent_max_grid(G.s, G.plan.tile[0], G.plan.tile[1], G.cfg.exec == OD_PERSISTENT ? 0 : 1);
+        int cap = od::persistent_max_grid(G.s, G.plan.tile[0], G.plan.tile[1], G.coop_kind());
         int grid = std::min<int>(cap, (int)G.tiles_h.size());
         if (grid >= od::kNumXcd) grid -= grid % od::kNumXcd;
         G.grid_wgs = grid;

@@ -49,6 +49,11 @@ struct Grid {
     std::vector<int32_t> dep_ptr, dep_idx;
     std::vector<uint8_t> extra_h;
     int32_t extra_period = 1;
+    // the persistent form takes tiles from counters (imbalance or uneven
+    // blocks) rather than by a fixed stride
+    bool persistent_dyn() const { return !extra_h.empty() || !plan.regular; }
+    // cooperative-kernel kind for persistent_max_grid
+    int coop_kind() const { return cfg.exec == OD_MSGDRIVEN ? 1 : (persistent_dyn() ? 2 : 0); }
     std::vector<MsgBufs> msg;
     int32_t nres = 1;
     size_t tile_cap = 0;             // tile descriptors the workspace has room for

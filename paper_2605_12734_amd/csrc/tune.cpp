@@ -103,7 +103,7 @@ od_status Grid::retile(const int32_t tile[3]) {
     for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
     graphs.clear();
     if (cfg.exec == OD_PERSISTENT) {
-        int cap = persistent_max_grid(s, plan.tile[0], plan.tile[1], 0);
+        int cap = persistent_max_grid(s, plan.tile[0], plan.tile[1], coop_kind());
         int grid = std::min<int>(cap, (int)tiles_h.size());
         if (grid >= kNumXcd) grid -= grid % kNumXcd;
         grid_wgs = grid;
