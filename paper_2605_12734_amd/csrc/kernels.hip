@@ -1274,10 +1274,10 @@ int64_t device_wait_ticks(double seconds) {
 // Co-resident workgroups per CU of a cooperative kernel with `threads` per
 // workgroup, from the occupancy query `per`, capped at `max_waves` (at most
 // 6) waves per SIMD.
-// The query counts waves by VGPRs and LDS, but on gfx950 a kernel with
-// about 100 or more SGPRs (the cooperative kernels here use 106) fits
-// only 6 waves per SIMD where the query reports 7 or 8 (measured: 256-thread
-// workgroups at 72 VGPRs hold 7 per CU at 86 SGPRs, 6 at 102 or 108).  A
+// The query counts SGPRs more generously than gfx950 places waves:
+// measured with 256-thread workgroups at 64-72 VGPRs, kernels using 78
+// SGPRs hold 8 waves per SIMD, 86 hold 7, and 99-108 hold only 6 where the
+// query reports 7 or 8 (the cooperative kernels here use 106).  A
 // cooperative grid larger than what is resident never completes its first
 // device-wide barrier.
 static int coop_per_cu(int per, int threads, int max_waves = 6) {
