@@ -72,6 +72,25 @@ def test_512_odf4096_one_full_step_sampled_against_oracle():
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("tile", [(32, 32, 16), (32, 16, 32)])
+def test_512_fp32_persistent_full_grid_sampled(tile):
+    # a cooperative grid as large as the device holds (the static-stride
+    # persistent kernel at its capped occupancy): every workgroup must be
+    # resident for the device-wide barrier to complete
+    n = (512, 512, 512)
+    iters = 10
+    g = od.Grid(n, odf=4096, dtype="f32", exec="persistent", tile=tile, hints=1)
+    try:
+        assert g.plan()["grid_wgs"] >= 1024
+        g.iterate(iters)
+        pts = _sample_points(n, 24, 3)
+        got = g.read_points(_lin(pts, n))
+    finally:
+        g.close()
+    want = oracle.point_values(n, pts, iters, np.float32)
+    assert np.array_equal(got, want)
+
+
 def test_512_odf4096_full_iterations_identical_across_modes():
     # 200 iterations: graph (bench launch configuration) = persistent =
     # message-driven = fused with another tile = ODF 8
