@@ -87,6 +87,11 @@ def load_traffic(key: str):
     return e.get("bytes_per_launch")
 
 
+def msg_tile(tile):
+    """Message-driven tile from a tuned fused tile: z extent at most 32."""
+    return (tile[0], tile[1], min(tile[2], 32))
+
+
 def make_grid(n, odf=None, blocks=None, dtype="f64", exec_="graph", tile=None, hints=1, autotune=True, **kw):
     import paper_2605_12734_amd as od
 
@@ -95,9 +100,11 @@ def make_grid(n, odf=None, blocks=None, dtype="f64", exec_="graph", tile=None, h
         g.autotune(2)
         return g
     if autotune and tile is None and exec_ in ("msgdriven", "per_chare"):
-        # these modes take the shape tuned on a fused grid of the same decomposition
+        # these modes take the shape tuned on a fused grid of the same
+        # decomposition; message-driven tasks are tiles, so their z extent
+        # is capped at 32 (deep tiles leave too few tasks to overlap)
         t = od.Grid(n, odf=odf or 1, blocks=blocks, dtype=dtype, exec="fused", hints=hints)
-        tile = t.autotune(2)
+        tile = msg_tile(t.autotune(2)) if exec_ == "msgdriven" else t.autotune(2)
         t.close()
     return od.Grid(n, odf=odf or 1, blocks=blocks, dtype=dtype, exec=exec_, tile=tile, hints=hints, **kw)
 
@@ -243,7 +250,8 @@ def imbalance_leg(iters=1000, odfs=(8, 64, 512, 4096, 32768)):
         row = {"odf": odf, "block": 1024 // round(odf ** (1 / 3))}
         tile = None
         for exec_ in ("fused", "persistent", "msgdriven"):
-            g = make_grid(1024, odf=odf, dtype="f64", exec_=exec_, tile=tile, imbalance_pct=10,
+            g = make_grid(1024, odf=odf, dtype="f64", exec_=exec_,
+                          tile=msg_tile(tile) if tile and exec_ == "msgdriven" else tile, imbalance_pct=10,
                           imbalance_max_extra=4)
             try:
                 tile = tile or g.plan()["tile"]
@@ -253,6 +261,8 @@ def imbalance_leg(iters=1000, odfs=(8, 64, 512, 4096, 32768)):
                 g.close()
             row[exec_ + "_glups"] = round(plan["interior"] * iters / t["wall_s"] / 1e9, 2)
             row[exec_ + "_s"] = round(t["wall_s"], 3)
+        row["tile_bsp"] = list(tile)
+        row["tile_msgdriven"] = list(msg_tile(tile))
         row["msgdriven_vs_bsp_launches"] = round(row["msgdriven_glups"] / row["fused_glups"], 3)
         row["msgdriven_vs_bsp_barrier"] = round(row["msgdriven_glups"] / row["persistent_glups"], 3)
         log("imbalance:", row)

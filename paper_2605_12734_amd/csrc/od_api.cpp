@@ -253,6 +253,14 @@ std::string build_layout(const od_config& cfg, Grid& G) {
     // message-driven tiles publish to other XCDs only across group
     // boundaries: compact boxes keep that boundary small
     p.xcd_boxes = cfg.exec == OD_MSGDRIVEN;
+    // with per-chare load imbalance and few chares, compact boxes would give
+    // each XCD whole chares and the heavy chare's XCD its extra sweeps
+    // alone; below 512 chares (measured gains at ODF 8 and 64) every chare
+    // is cut into 8 boxes instead, one per XCD group
+#ifndef OD_SPLIT_CHARES_BELOW
+#define OD_SPLIT_CHARES_BELOW 512
+#endif
+    p.xcd_split_chares = p.xcd_boxes && cfg.imbalance_pct > 0 && p.chares.size() < (size_t)OD_SPLIT_CHARES_BELOW;
     if (!sweep_variant_ok(G.s, p.tile[0], p.tile[1]))
         return "tile (" + std::to_string(p.tile[0]) + "," + std::to_string(p.tile[1]) + ") is not a compiled variant";
     err = plan_tiles(p);

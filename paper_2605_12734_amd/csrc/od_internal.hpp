@@ -85,6 +85,7 @@ struct Plan {
     int32_t tile[3] = {0, 0, 0};
     bool xcd_order = true;               // group tiles per XCD (else plain spatial order)
     bool xcd_boxes = false;              // XCD groups are 8 compact boxes (else 8 z-slabs)
+    bool xcd_split_chares = false;       // with xcd_boxes: 8 boxes per chare, box g of each in group g
     int64_t interior = 0;
     int64_t halo_cells = 0;              // ghost cells read from other chares per sweep
     // multi-resolution blocks

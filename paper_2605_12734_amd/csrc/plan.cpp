@@ -425,50 +425,71 @@ std::string plan_tiles(Plan& p) {
         // three rounds of bisection by tile count, each along the longest
         // extent of the part: 8 compact boxes (fewer tiles on a group
         // boundary than 8 thin slabs); z-major order inside each box
-        std::vector<std::pair<size_t, size_t>> parts{{0, T}};
-        for (int round = 0; round < 3; ++round) {
-            std::vector<std::pair<size_t, size_t>> next;
-            for (auto [lo, hi] : parts) {
-                int64_t mn[3], mx[3];
-                for (int d = 0; d < 3; ++d) {
-                    mn[d] = INT64_MAX;
-                    mx[d] = INT64_MIN;
-                }
-                for (size_t q = lo; q < hi; ++q)
+        auto bisect8 = [&](size_t lo0, size_t hi0) {
+            std::vector<std::pair<size_t, size_t>> parts{{lo0, hi0}};
+            for (int round = 0; round < 3; ++round) {
+                std::vector<std::pair<size_t, size_t>> next;
+                for (auto [lo, hi] : parts) {
+                    int64_t mn[3], mx[3];
                     for (int d = 0; d < 3; ++d) {
-                        mn[d] = std::min(mn[d], gkey(out[idx[q]], d));
-                        mx[d] = std::max(mx[d], gkey(out[idx[q]], d));
+                        mn[d] = INT64_MAX;
+                        mx[d] = INT64_MIN;
                     }
-                int dim = 2;
-                for (int d = 1; d >= 0; --d)
-                    if (mx[d] - mn[d] > mx[dim] - mn[dim]) dim = d;
-                std::stable_sort(idx.begin() + (std::ptrdiff_t)lo, idx.begin() + (std::ptrdiff_t)hi,
-                                 [&](size_t a, size_t b) { return gkey(out[a], dim) < gkey(out[b], dim); });
-                const size_t mid = lo + (hi - lo) / 2;
-                next.push_back({lo, mid});
-                next.push_back({mid, hi});
-            }
-            parts.swap(next);
-        }
-        for (auto [lo, hi] : parts)
-            std::stable_sort(idx.begin() + (std::ptrdiff_t)lo, idx.begin() + (std::ptrdiff_t)hi, [&](size_t a, size_t b) {
-                for (int d = 2; d >= 0; --d) {
-                    int64_t ka = gkey(out[a], d), kb = gkey(out[b], d);
-                    if (ka != kb) return ka < kb;
+                    for (size_t q = lo; q < hi; ++q)
+                        for (int d = 0; d < 3; ++d) {
+                            mn[d] = std::min(mn[d], gkey(out[idx[q]], d));
+                            mx[d] = std::max(mx[d], gkey(out[idx[q]], d));
+                        }
+                    int dim = 2;
+                    for (int d = 1; d >= 0; --d)
+                        if (mx[d] - mn[d] > mx[dim] - mn[dim]) dim = d;
+                    std::stable_sort(idx.begin() + (std::ptrdiff_t)lo, idx.begin() + (std::ptrdiff_t)hi,
+                                     [&](size_t x, size_t y) { return gkey(out[x], dim) < gkey(out[y], dim); });
+                    const size_t mid = lo + (hi - lo) / 2;
+                    next.push_back({lo, mid});
+                    next.push_back({mid, hi});
                 }
-                return false;
-            });
-        // the j-th tile of box g goes to launch position 8j + g (boxes
-        // differ by at most one tile)
+                parts.swap(next);
+            }
+            for (auto [lo, hi] : parts)
+                std::stable_sort(idx.begin() + (std::ptrdiff_t)lo, idx.begin() + (std::ptrdiff_t)hi,
+                                 [&](size_t x, size_t y) {
+                                     for (int d = 2; d >= 0; --d) {
+                                         int64_t kx = gkey(out[x], d), ky = gkey(out[y], d);
+                                         if (kx != ky) return kx < ky;
+                                     }
+                                     return false;
+                                 });
+            return parts;
+        };
+        // group g: box g of the whole grid, or (xcd_split_chares) box g of
+        // every chare, so each chare's work is spread over all groups
+        std::vector<std::vector<size_t>> groups((size_t)kNumXcd);
+        if (p.xcd_split_chares) {
+            std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return out[x].chare < out[y].chare; });
+            size_t lo = 0;
+            while (lo < T) {
+                size_t hi = lo;
+                while (hi < T && out[idx[hi]].chare == out[idx[lo]].chare) ++hi;
+                const auto parts = bisect8(lo, hi);
+                for (int g = 0; g < kNumXcd; ++g)
+                    for (size_t q = parts[(size_t)g].first; q < parts[(size_t)g].second; ++q) groups[(size_t)g].push_back(idx[q]);
+                lo = hi;
+            }
+        } else {
+            const auto parts = bisect8(0, T);
+            for (int g = 0; g < kNumXcd; ++g)
+                for (size_t q = parts[(size_t)g].first; q < parts[(size_t)g].second; ++q) groups[(size_t)g].push_back(idx[q]);
+        }
+        // the j-th tile of group g goes to launch position 8j + g (groups
+        // differ by at most one tile per chare)
         std::vector<TileHost> seq;
         seq.reserve(T);
         size_t maxc = 0;
-        for (auto [lo, hi] : parts) maxc = std::max(maxc, hi - lo);
+        for (const auto& gr : groups) maxc = std::max(maxc, gr.size());
         for (size_t j = 0; j < maxc; ++j)
-            for (int g = 0; g < kNumXcd; ++g) {
-                const auto [lo, hi] = parts[(size_t)g];
-                if (lo + j < hi) seq.push_back(out[idx[lo + j]]);
-            }
+            for (int g = 0; g < kNumXcd; ++g)
+                if (j < groups[(size_t)g].size()) seq.push_back(out[groups[(size_t)g][j]]);
         p.tiles.swap(seq);
         return "";
     }

@@ -164,3 +164,25 @@ def test_octree_statistics_match_branching_process():
         # generous bound for a branching-process count (std grows ~ sqrt(m)
         # times the ancestry's fan-out of 8 per level)
         assert abs(counts.get(e, 0) - m) < 8 * 5 * np.sqrt(m)
+
+
+@pytest.mark.parametrize("odf,split", [(8, True), (64, True), (512, False)])
+def test_msgdriven_groups_under_imbalance(odf, split):
+    # message-driven launch position q runs in XCD group q % 8.  Without
+    # imbalance the groups are 8 compact boxes of the grid; with imbalance and
+    # fewer than 512 chares every chare is cut into 8 boxes, one per group, so
+    # a heavy chare's extra sweeps are shared by every XCD.  The tile set and
+    # its halo maps do not change.
+    n = (128, 128, 128)
+    base = dict(n=n, odf=odf, dtype="f64", exec="msgdriven", tile=(16, 8, 16))
+    a = od.host_plan(**base)
+    b = od.host_plan(**base, imbalance_pct=10, imbalance_max_extra=4)
+    key = lambda t: (t["chare"], t["origin"], t["extent"])
+    assert sorted(map(key, a["tiles"])) == sorted(map(key, b["tiles"]))
+    _check_plan(n, b)
+    for plan, spread in ((a, False), (b, split)):
+        per_group = [{t["chare"] for q, t in enumerate(plan["tiles"]) if q % 8 == g} for g in range(8)]
+        if spread:
+            assert all(len(s) == odf for s in per_group)
+        else:
+            assert all(len(s) <= max(1, odf // 8) + 1 for s in per_group)
