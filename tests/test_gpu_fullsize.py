@@ -149,6 +149,25 @@ def test_1024_odf32768_imbalance_sampled(exec_):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("odf", [8, 64])
+def test_1024_few_chares_imbalance_msgdriven_sampled(odf):
+    # the benchmark's message-driven configuration under imbalance with few
+    # chares: every chare spread over all XCD groups, tiles of depth 32
+    n = (1024, 1024, 1024)
+    iters = 12
+    g = od.Grid(n, odf=odf, dtype="f64", exec="msgdriven", tile=(64, 16, 32), hints=1, imbalance_pct=10,
+                imbalance_max_extra=4)
+    try:
+        g.iterate(iters)
+        pts = _sample_points(n, 32, 4)
+        pts += [(511, 511, 511), (512, 512, 512), (255, 767, 256)]
+        got = g.read_points(_lin(pts, n))
+    finally:
+        g.close()
+    want = oracle.point_values(n, pts, iters, np.float64)
+    assert np.array_equal(got, want)
+
+
 def test_768_octree_sampled_graph_persistent_msgdriven():
     blocks = workloads.octree_blocks(n=768, root=128, min_edge=16, p_refine=0.4, seed=12734)
     n = (768, 768, 768)
