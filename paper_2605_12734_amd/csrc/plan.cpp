@@ -481,8 +481,11 @@ std::string plan_tiles(Plan& p) {
             for (int g = 0; g < kNumXcd; ++g)
                 for (size_t q = parts[(size_t)g].first; q < parts[(size_t)g].second; ++q) groups[(size_t)g].push_back(idx[q]);
         }
-        // the j-th tile of group g goes to launch position 8j + g (groups
-        // differ by at most one tile per chare)
+        // while every group has a j-th tile it goes to launch position
+        // 8j + g; when group sizes differ (by at most one tile per box), the
+        // tiles of the last rounds fill the remaining positions in group
+        // order and so may run in another group (placement only: a launch
+        // takes each tile's group from its position)
         std::vector<TileHost> seq;
         seq.reserve(T);
         size_t maxc = 0;
