@@ -7,24 +7,26 @@ of the last sweep read back.  value = GLUP/s (10^9 lattice-site updates/s).
 
 Prints ONE JSON line: the headline, the roofline of the sweep kernel (its
 average launch time measured live with HIP events on the grid's stream),
-the measured HBM copy ceiling, the ODF sweep (batched vs per-chare launches,
-fp64 and fp32), and the CPU oracle on a bounded sample of the same workload.
+the measured HBM ceilings (copy, read-only, write-only), and, by default,
+every other part of the metric:
+  odf_sweep        512^3 fp64 and fp32, ODF 8..4096: batched (graph-captured
+                   fused launches), batched persistent (one cooperative launch)
+                   and per-chare launches, each with its roofline fraction
+  amr_octree_768   768^3 fp64 octree of uneven blocks, 500 iterations:
+                   graph-captured and persistent, plus the multi-resolution
+                   reading (ghost fill by injection / averaging)
+  imbalance_1024   1024^3 fp64, ODF 8..32768, 10% of chares re-run 1-4 times
+                   per step: message-driven scheduler vs both bulk-synchronous
+                   forms
+  serving          Poisson stream of independent solves at 10..2000 /s under a
+                   200 GB budget: p50/p99 of t_done - t_arrival, solves/s,
+                   aggregate GLUP/s
+and the CPU oracle on a bounded sample of the headline workload.
 
-Optional legs (each adds a key to the same line):
-  --amr        768^3 fp64 octree of uneven blocks: 500 iterations captured in
-               a hipGraph, and as one persistent launch
-  --imbalance  1024^3 fp64, ODF 8..32768, 10% of chares re-run 1-4 times per
-               step: message-driven scheduler vs bulk-synchronous forms
-  --jacobi2d   the paper's Jacobi2D: 32768^2 fp64 5-point, 100 iterations,
-               ODF 1..1024, batched vs per-chare launches
-  --launch     launch-cost microbenchmarks: fixed work split into 1..1024
-               kernels released at once from a stream gate; launch rate
-               from 1-4 host threads x 1-4 chares per thread
-  --serving    Poisson stream of independent solves at 10..2000 /s under a
-               200 GB budget: p50/p99 latency, solves/s, GLUP/s
-  --all        all of the above
+Optional legs: --jacobi2d (the paper's 2D workload, 32768^2 fp64), --launch
+(launch-overlap microbenchmark).  --quick skips the default extra legs.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--amr] [--imbalance] [--serving]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
 """
 from __future__ import annotations
 
@@ -147,7 +149,9 @@ def cpu_baseline(n, dtype, target_s=15.0, max_iters=200, chunk=10):
     job (max_iters iterations: the steps x iterations the GPU ran): one call
     of as many iterations as take about target_s seconds, at the marginal
     rate of two short calls (chunk and 2 * chunk iterations; each call also
-    copies the field once)."""
+    copies the field once).  The one-thread rate is marginal too: two calls
+    of 1 and 3 iterations, their difference over 2 iterations (the copy and
+    first touch cancel out)."""
     import numpy as np
     import oracle
 
@@ -169,11 +173,14 @@ def cpu_baseline(n, dtype, target_s=15.0, max_iters=200, chunk=10):
     oracle.jacobi(U, done)
     dt = time.perf_counter() - t0
     cores = int(oracle.max_threads())
-    # one thread, a few iterations
     oracle.set_threads(1)
     t1 = time.perf_counter()
+    oracle.jacobi(U, 1)
+    d1 = time.perf_counter() - t1
+    t1 = time.perf_counter()
     oracle.jacobi(U, 3)
-    dt1 = time.perf_counter() - t1
+    d3 = time.perf_counter() - t1
+    per1 = max((d3 - d1) / 2, 1e-6)
     oracle.set_threads(nt)
     model = ""
     try:
@@ -184,26 +191,43 @@ def cpu_baseline(n, dtype, target_s=15.0, max_iters=200, chunk=10):
     return {"value": round(n ** 3 * done / dt / 1e9, 3), "unit": "GLUP/s", "cores": cores, "kind": "oracle",
             "sample": f"{n}^3 {dtype} undecomposed, {done} of the timed job's {max_iters} iterations "
                       f"({dt:.1f} s), same seed/bc",
-            "single_thread_value": round(n ** 3 * 3 / dt1 / 1e9, 4), "cpu_model": model}
+            "single_thread_value": round(n ** 3 / per1 / 1e9, 4),
+            "single_thread_sample": f"marginal rate of 1- and 3-iteration calls ({d1:.1f} s, {d3:.1f} s)",
+            "cpu_model": model}
 
 
-def odf_sweep(n, iters):
+def odf_sweep(n, iters, persistent=True):
+    """Per dtype and ODF: graph-captured fused launches (tile autotuned),
+    the persistent cooperative form (same tile), per-chare launches.  Each
+    batched form's roofline fraction divides the algorithmic bytes per
+    iteration by its own kernel time per iteration (HIP events)."""
     rows = []
     for dtype in ("f64", "f32"):
         for odf in (8, 64, 512, 4096):
             b = grid_leg(n, odf, dtype, "graph", iters, 2, 1)
-            pc_iters = 10 if odf <= 64 else (4 if odf <= 512 else 2)
-            p = grid_leg(n, odf, dtype, "per_chare", pc_iters, 1, 1, tile=b["plan"]["tile"])
+            tile = b["plan"]["tile"]
             bp = b["plan"]["bytes_per_iter"]
             k = round(odf ** (1 / 3))
-            rows.append({"dtype": dtype, "odf": odf, "block": n // k, "tile": list(b["plan"]["tile"]),
-                         "batched_glups": round(b["glups"], 2),
-                         "batched_hbm_gbps": round(bp / b["launch_s"] / 1e9, 1),
-                         "batched_frac": round(bp / b["launch_s"] / 1e9 / PEAK_HBM_GBPS, 4),
-                         "per_chare_glups": round(p["glups"], 3),
-                         "per_chare_ms_per_iter": round(p["wall_s"] / pc_iters * 1e3, 2),
-                         "speedup_batched_vs_per_chare": round(b["glups"] / p["glups"], 1)})
-            log("odf sweep:", rows[-1])
+            row = {"dtype": dtype, "odf": odf, "block": n // k, "tile": list(tile),
+                   "batched_glups": round(b["glups"], 2),
+                   "batched_hbm_gbps": round(bp / b["launch_s"] / 1e9, 1),
+                   "batched_frac": round(bp / b["launch_s"] / 1e9 / PEAK_HBM_GBPS, 4)}
+            if persistent:
+                q = grid_leg(n, odf, dtype, "persistent", iters, 2, 1, tile=tile)
+                row.update({"persistent_glups": round(q["glups"], 2),
+                            "persistent_hbm_gbps": round(bp / q["launch_s"] / 1e9, 1),
+                            "persistent_frac": round(bp / q["launch_s"] / 1e9 / PEAK_HBM_GBPS, 4),
+                            "persistent_us_per_iter": round(q["launch_s"] * 1e6, 2),
+                            "persistent_grid_wgs": q["plan"]["grid_wgs"]})
+            pc_iters = 10 if odf <= 64 else (4 if odf <= 512 else 2)
+            p = grid_leg(n, odf, dtype, "per_chare", pc_iters, 1, 1, tile=tile)
+            row.update({"per_chare_glups": round(p["glups"], 3),
+                        "per_chare_ms_per_iter": round(p["wall_s"] / pc_iters * 1e3, 2),
+                        "speedup_batched_vs_per_chare": round(b["glups"] / p["glups"], 1)})
+            if persistent:
+                row["speedup_persistent_vs_per_chare"] = round(row["persistent_glups"] / p["glups"], 1)
+            log("odf sweep:", row)
+            rows.append(row)
     return rows
 
 
@@ -303,12 +327,10 @@ def jacobi2d_leg(n=32768, iters=100, odfs=(1, 4, 16, 64, 256, 1024)):
     return rows
 
 
-def launch_leg(totals=(1 << 18, 1 << 20), kernels=(1, 2, 4, 8, 16, 32, 64, 256, 1024), works=(0, 20000),
-               rate_threads=(1, 2, 4), rate_chares=(1, 2, 4)):
-    """Launch-cost microbenchmarks: the same work split over more kernels,
+def launch_leg(totals=(1 << 18, 1 << 20), kernels=(1, 2, 4, 8, 16, 32, 64, 256, 1024), works=(0, 20000)):
+    """Launch-overlap microbenchmark: the same work split over more kernels,
     all released at once from a stream gate (device makespan vs ODF; work 0
-    isolates the per-kernel device cost); and kernels launched per second
-    from host threads x chares per thread."""
+    isolates the per-kernel device cost)."""
     import paper_2605_12734_amd as od
 
     overlap = []
@@ -327,19 +349,12 @@ def launch_leg(totals=(1 << 18, 1 << 20), kernels=(1, 2, 4, 8, 16, 32, 64, 256, 
                        "makespan_vs_1_kernel": round(best["makespan_us"] / base, 3)}
                 log("launch overlap:", row)
                 overlap.append(row)
-    rate = []
-    for t in rate_threads:
-        for c in rate_chares:
-            n, kps = od.launch_rate(t, c, seconds=0.5)
-            rate.append({"host_threads": t, "chares_per_thread": c, "kernels_per_s": round(kps)})
-            log("launch rate:", rate[-1])
-    return {"overlap": overlap, "rate": rate}
+    return {"overlap": overlap}
 
 
-def serving_leg(rates=(10, 30, 100, 300, 1000, 2000), count=64, arena_gb=200.0):
+def serving_leg(rates=(10, 30, 100, 300, 1000, 2000), count=128, arena_gb=200.0):
     import torch
 
-    import workloads
     from paper_2605_12734_amd.serving import Server
 
     free = torch.cuda.mem_get_info()[0]
@@ -353,41 +368,79 @@ def serving_leg(rates=(10, 30, 100, 300, 1000, 2000), count=64, arena_gb=200.0):
 
 
 def _serve_rate(srv, rate, count):
+    """Submit a seeded Poisson stream at its arrival times; every request
+    carries its scheduled arrival time (t_arrival, the server's monotonic
+    clock), so latency = t_done - t_arrival counts any delay before
+    od_submit.  Finished fields are fetched by a second thread, so the
+    submitting loop only plans and submits."""
+    import queue
+    import threading
+
     import numpy as np
 
     import workloads
 
     reqs = workloads.serving_requests(rate, count, seed=12734 + int(rate))
     st0 = srv.stats()
+    fetch_q: "queue.Queue" = queue.Queue()
+    fetch_err = []
+
+    def fetcher():
+        while True:
+            t = fetch_q.get()
+            if t is None:
+                return
+            try:
+                srv.fetch(t)
+            except Exception as ex:   # reported after the run
+                fetch_err.append(repr(ex))
+
+    th = threading.Thread(target=fetcher, daemon=True)
+    th.start()
     t0 = time.monotonic()
     tickets = {}
+    lag = []
     pending = list(reqs)
     done = {}
-    while pending or len(done) < len(reqs):
-        now = time.monotonic() - t0
-        while pending and pending[0]["t_arrival"] <= now:
-            q = pending.pop(0)
-            tickets[srv.submit(q["n"], q["dtype"], odf=q["odf"], tol=q["tol"], max_iters=q["max_iters"],
-                               check_every=q["check_every"], seed=q["seed"])] = q
-        for t in list(tickets):
-            if t in done:
-                continue
-            r = srv.poll(t)
-            if r is not None:
-                done[t] = r
-                srv.fetch(t)
-        if pending and not any(t not in done for t in tickets):
-            time.sleep(max(0.0, min(0.002, pending[0]["t_arrival"] - (time.monotonic() - t0))))
-        else:
-            time.sleep(2e-4)
-    lat = np.array([done[t]["t_done"] - done[t]["t_submit"] for t in tickets])
-    first = min(r["t_submit"] for r in done.values())
+    try:
+        while pending or len(done) < len(reqs):
+            now = time.monotonic()
+            while pending and t0 + pending[0]["t_arrival"] <= now:
+                q = pending.pop(0)
+                ta = t0 + q["t_arrival"]
+                tk = srv.submit(q["n"], q["dtype"], odf=q["odf"], tol=q["tol"], max_iters=q["max_iters"],
+                                check_every=q["check_every"], seed=q["seed"], t_arrival=ta)
+                tickets[tk] = q
+                now = time.monotonic()
+                lag.append(now - ta)
+            for t in list(tickets):
+                if t in done:
+                    continue
+                r = srv.poll(t)
+                if r is not None:
+                    done[t] = r
+                    fetch_q.put(t)
+            if pending and not any(t not in done for t in tickets):
+                time.sleep(max(0.0, min(0.002, t0 + pending[0]["t_arrival"] - time.monotonic())))
+            else:
+                time.sleep(2e-4)
+    finally:
+        fetch_q.put(None)
+        th.join()
+    if fetch_err:
+        raise RuntimeError("serving fetch failed: " + fetch_err[0])
+    lat = np.array([done[t]["t_done"] - done[t]["t_arrival"] for t in tickets])
+    first = min(r["t_arrival"] for r in done.values())
     last = max(r["t_done"] for r in done.values())
     lups = sum(q["n"] ** 3 * done[t]["iters"] for t, q in tickets.items())
+    lag = np.array(lag)
     row = {"rate": rate, "requests": count, "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
            "solves_per_s": round(count / (last - first), 2), "glups": round(lups / (last - first) / 1e9, 2),
-           "mean_iters": round(float(np.mean([r["iters"] for r in done.values()])), 1)}
+           "mean_iters": round(float(np.mean([r["iters"] for r in done.values()])), 1),
+           "submit_lag_ms": {"p50": round(float(np.percentile(lag, 50)) * 1e3, 3),
+                             "p99": round(float(np.percentile(lag, 99)) * 1e3, 3),
+                             "max": round(float(lag.max()) * 1e3, 3)}}
     st1 = srv.stats()
     wall = time.monotonic() - t0
     row["worker"] = {k: round(st1[k] - st0[k], 3) for k in ("epochs", "epoch_s", "admit_s", "retire_s", "idle_s")}
@@ -408,16 +461,17 @@ def main():
     ap.add_argument("--exec", default="graph")
     ap.add_argument("--tile", default=None, help="tx,ty,tz (default: autotuned)")
     ap.add_argument("--hints", type=int, default=1)
+    ap.add_argument("--quick", action="store_true", help="headline, ceilings and CPU baseline only")
     ap.add_argument("--no-sweep", action="store_true", help="skip the ODF sweep")
+    ap.add_argument("--no-ceilings", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--amr", action="store_true")
-    ap.add_argument("--imbalance", action="store_true")
+    ap.add_argument("--no-amr", action="store_true")
+    ap.add_argument("--no-imbalance", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--imb-iters", type=int, default=1000)
     ap.add_argument("--jacobi2d", action="store_true")
     ap.add_argument("--launch", action="store_true")
-    ap.add_argument("--serving", action="store_true")
-    ap.add_argument("--serving-count", type=int, default=256)
-    ap.add_argument("--all", action="store_true")
+    ap.add_argument("--serving-count", type=int, default=128)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -427,6 +481,7 @@ def main():
 
     import paper_2605_12734_amd as od
 
+    t_start = time.monotonic()
     tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else None
     log(f"bench: {args.n}^3 {args.dtype} odf {args.odf} {args.exec}, {args.iters} iterations/step, "
         f"warmup {args.warmup}, steps {args.steps}")
@@ -440,15 +495,27 @@ def main():
     log(f"bench: {leg['glups']:.1f} GLUP/s, sweep {leg['launch_s'] * 1e6:.1f} us/launch, "
         f"{achieved:.0f} GB/s algorithmic, tile {plan['tile']}")
 
-    nbytes = 1 << 30
-    copy_s = od.stream_copy_seconds(nbytes, iters=20)
-    copy_gbps = 2 * nbytes * 20 / copy_s / 1e9
+    ceil = None if args.no_ceilings else od.hbm_ceilings(4 << 30, iters=8)
+    if ceil:
+        log("bench: ceilings", ceil)
 
     k = round(plan["nchares"] ** (1 / 3))
     workload = f"{args.n}^3 {args.dtype} odf{plan['nchares']} tile{'x'.join(map(str, plan['tile']))} hints{args.hints}"
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBPS, 4),
+            "traffic": load_traffic(workload) if args.exec in ("graph", "fused") else None,
+            "kernel": KERNEL_OF_EXEC.get(args.exec, args.exec),
+            "alg_bytes_per_launch": bytes_per_iter,
+            "avg_launch_us": round(leg["launch_s"] * 1e6, 2),
+            "strict_frac_2s_per_lup": round(strict / PEAK_HBM_GBPS, 4)}
+    if ceil:
+        roof.update({"copy_ceiling_gbps": ceil["copy_gbps"], "read_ceiling_gbps": ceil["read_gbps"],
+                     "write_ceiling_gbps": ceil["write_gbps"],
+                     "frac_of_copy_ceiling": round(achieved / ceil["copy_gbps"], 4)})
     out = {
-        "metric": "GLUP/s at 512^3 fp64, ODF 4096 (batched: graph-captured fused sweeps); ODF sweep batched vs "
-                  "per-chare; HBM GB/s vs roofline",
+        "metric": "GLUP/s at 512^3 fp64, ODF 4096 (batched: graph-captured fused sweeps); ODF sweep batched "
+                  "(graph, persistent) vs per-chare; HBM GB/s vs roofline; octree, imbalance and serving "
+                  "p50/p99 legs",
         "value": round(leg["glups"], 3),
         "unit": "GLUP/s",
         "n_gpus": 1,
@@ -464,31 +531,36 @@ def main():
                                f"{args.n // k}^3, {args.iters} iterations per step, exec={args.exec}",
                    "odf": plan["nchares"], "iters_per_step": args.iters, "tile": list(plan["tile"]),
                    "exec": args.exec, "hints": args.hints},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBPS, 4),
-                     "traffic": load_traffic(workload) if args.exec in ("graph", "fused") else None,
-                     "kernel": KERNEL_OF_EXEC.get(args.exec, args.exec),
-                     "alg_bytes_per_launch": bytes_per_iter,
-                     "avg_launch_us": round(leg["launch_s"] * 1e6, 2),
-                     "strict_frac_2s_per_lup": round(strict / PEAK_HBM_GBPS, 4),
-                     "copy_ceiling_gbps": round(copy_gbps, 1),
-                     "frac_of_copy_ceiling": round(achieved / copy_gbps, 4)},
+        "roofline": roof,
         "residual": leg["residual"],
     }
+    if ceil:
+        out["hbm_ceilings"] = ceil
+    legs = []
     if not args.no_sweep:
-        out["odf_sweep"] = odf_sweep(args.n, args.iters)
-    if args.amr or args.all:
-        out["amr_octree_768"] = amr_leg()
-    if args.imbalance or args.all:
-        out["imbalance_1024"] = imbalance_leg(args.imb_iters)
-    if args.jacobi2d or args.all:
-        out["jacobi2d_32768"] = jacobi2d_leg()
-    if args.launch or args.all:
-        out["launch"] = launch_leg()
-    if args.serving or args.all:
-        out["serving"] = serving_leg(count=args.serving_count)
+        legs.append(("odf_sweep", lambda: odf_sweep(args.n, args.iters)))
+    if not args.quick and not args.no_amr:
+        legs.append(("amr_octree_768", amr_leg))
+    if not args.quick and not args.no_imbalance:
+        legs.append(("imbalance_1024", lambda: imbalance_leg(args.imb_iters)))
+    if not args.quick and not args.no_serving:
+        legs.append(("serving", lambda: serving_leg(count=args.serving_count)))
+    if args.jacobi2d:
+        legs.append(("jacobi2d_32768", jacobi2d_leg))
+    if args.launch:
+        legs.append(("launch", launch_leg))
+    leg_s = {}
+    for name, fn in legs:
+        t0 = time.monotonic()
+        out[name] = fn()
+        leg_s[name] = round(time.monotonic() - t0, 1)
+        log(f"bench: leg {name} done in {leg_s[name]} s")
+    t0 = time.monotonic()
     out["cpu_baseline"] = (None if args.no_cpu_baseline
                            else cpu_baseline(args.n, args.dtype, max_iters=args.iters * args.steps))
+    leg_s["cpu_baseline"] = round(time.monotonic() - t0, 1)
+    leg_s["total"] = round(time.monotonic() - t_start, 1)
+    out["leg_seconds"] = leg_s
     print(json.dumps(out), flush=True)
 
 

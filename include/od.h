@@ -52,6 +52,9 @@ typedef enum {
     OD_ENOTREADY = -61,   /* request still queued or running                */
     OD_ECANCELED = -125,  /* request cancelled (server shut down)           */
     OD_ETIMEDOUT = -110,  /* a device-side wait exceeded its bound           */
+    OD_ESCHED = -71,      /* a message-driven schedule check failed (a tile's
+                             step counter did not advance by one, or a tile
+                             ran while a neighbour was not within one step) */
     OD_EHIP = -1000       /* HIP runtime error; message in od_last_error()  */
 } od_status;
 
@@ -101,16 +104,28 @@ typedef struct {
     od_exec exec;
     int32_t tile[3];      /* tile shape (x, y, z) of the fused sweep; {0,0,0} =
                              the built-in or autotuned default for the block shape */
-    /* Load imbalance: at every step, `imbalance_pct` percent of the chares
-     * (chosen per step from `seed`) re-run their sweep 1..imbalance_max_extra
-     * extra times.  A re-run recomputes the same values, so results do not
-     * change, only the time. 0 = off. */
+    /* Load imbalance (the dynamic imbalance that motivates overdecomposition,
+     * Section I; the configuration with 10 % of chares doing 1 to 4 extra
+     * sweeps).  At every step t, round(imbalance_pct / 100 * chares) chares
+     * re-run their sweep 1..imbalance_max_extra extra times: the chares
+     * taken first in a pseudo-random order of chare ids drawn from
+     * (seed, t), each re-run count drawn from SplitMix64 at (seed, t,
+     * chare); od_extra_sweeps reports the draw.  A re-run recomputes the
+     * same values, so results do not change, only the time.  0 = off. */
     int32_t imbalance_pct;
     int32_t imbalance_max_extra;
     /* Implementation hints, 0 = defaults; none of them changes a result.
      * bit 0: write the sweep's output with non-temporal (streaming) stores;
      * bit 1: launch tiles in plain spatial order instead of grouping
-     * spatial neighbours on one XCD; other bits are ignored. */
+     * spatial neighbours on one XCD;
+     * bit 2 (OD_MSGDRIVEN): schedule check: seeded delays before each task
+     * publishes its finish and before each claim, and seeded start
+     * positions of the per-XCD cursors, perturb the order in which tiles
+     * run, and every task checks that each tile it reads halos from is
+     * within one step of it (a failure raises the error flag: reads then
+     * return OD_ESCHED).  Every message-driven task also checks, in any
+     * mode, that its tile's step counter advances by exactly one.
+     * Other bits are ignored. */
     int32_t hints;
     /* 7 (or 0): 3D 7-point stencil.  5: the 2D 5-point stencil of the
      * paper's Jacobi2D workload, u' = (((u[i-1] + u[i+1]) + u[k-1]) + u[k+1]) / 4,
@@ -155,17 +170,32 @@ od_status od_workspace_bytes(const od_config* cfg, size_t* bytes);
 
 /* Decompose, build halo maps, carve the workspace, upload descriptors and
  * initialise the field on the device (interior from seed, shell from bc).
+ * The decomposition is the paper's overdecomposition: the grid's work and
+ * data are split into many more chares than GPUs, each with its own
+ * storage (Section II, Charm++ and Overdecomposition; Section III,
+ * Managing Overdecomposition); every chare face's halo source is resolved
+ * here, once, as with the pre-filled location table that lets a sender
+ * pick the transport (Section IV, Portable Communication Layer).
  * Synchronises the stream before returning.  `dev_workspace` must be at
  * least od_workspace_bytes() bytes and 256-byte aligned. */
 od_status od_create(const od_config* cfg, void* hip_stream, void* dev_workspace,
                     size_t workspace_bytes, struct od_grid** out);
 
 /* Enqueue n >= 0 Jacobi iterations on the grid's stream (asynchronous, like
- * a kernel launch).  Allocates nothing and does not synchronise, except in
- * OD_PER_CHARE mode whose host loop itself issues the work. */
+ * a kernel launch).  One iteration is the stencil application's step:
+ * every chare exchanges halos with its neighbours and sweeps its block
+ * (Section V, Jacobi2D, here with the 3D 7-point stencil), in the form
+ * cfg.exec names (Section III for the per-chare form and the fused and
+ * graph-captured mitigations cited in Section I).  Allocates nothing and
+ * does not synchronise, except in OD_PER_CHARE mode whose host loop itself
+ * issues the work. */
 od_status od_iterate(struct od_grid* g, int64_t n);
 
-/* Synchronise the stream; *r = residual of the last sweep (0 before any).
+/* Synchronise the stream; *r = residual of the last sweep (0 before any):
+ * max over interior points of |u_new - u_old|.  The paper runs its
+ * stencil for a fixed count without convergence checks (Section V,
+ * Jacobi2D); the residual is this library's addition (a max norm, so its
+ * value does not depend on the decomposition or the order of reduction).
  * od_residual and the reads below (od_read, od_read_points, od_read_block)
  * return OD_ETIMEDOUT instead of a result if a device-side wait of an
  * earlier persistent or message-driven launch gave up; the grid's state is
@@ -209,6 +239,10 @@ typedef struct {
     int64_t bytes_per_iter;         /* algorithmic HBM bytes of one sweep            */
     int32_t tile[3];                /* tile shape in use                              */
     int32_t grid_wgs;               /* workgroups of the persistent / msg-driven launch */
+    int64_t field_bytes;            /* leading part of the workspace holding the field
+                                       storage                                        */
+    int64_t control_bytes;          /* rest of the workspace: descriptors and device
+                                       state, for this handle's plan                 */
 } od_plan_info;
 od_status od_plan(struct od_grid* g, od_plan_info* info);
 
@@ -226,6 +260,12 @@ typedef struct {
 } od_tile_info;
 od_status od_tile_info_get(struct od_grid* g, int32_t t, od_tile_info* out);
 
+/* The load-imbalance draw of step `step` (0-based count of iterations since
+ * od_create): out[c] = extra re-runs of chare c's sweep, for the n ==
+ * nchares chares (all 0 without imbalance).  Host-only: it evaluates the
+ * same definition the kernels evaluate on the device. */
+od_status od_extra_sweeps(struct od_grid* g, int64_t step, int32_t* out, int32_t n);
+
 /* Chare geometry: origin and extent of chare c in grid units (for
  * multi-resolution blocks: the block as given; cells = extent / cell). */
 od_status od_chare_get(struct od_grid* g, int32_t c, od_block* out);
@@ -241,16 +281,26 @@ od_status od_destroy(struct od_grid* g);
 od_status od_stream_copy(void* hip_stream, void* dst, const void* src, size_t bytes,
                          int32_t iters, double* seconds);
 
+/* Measured HBM ceilings by access kind: kind 0 = copy (as od_stream_copy,
+ * 2 * bytes moved per pass), 1 = read-only (src is read, nothing is
+ * stored; dst must be device memory of at least 16 bytes, its first word
+ * may be modified), 2 = write-only (dst is overwritten with a pattern; src
+ * is not read but must be non-NULL).  Each of the streaming kernel
+ * variants runs `iters` passes over `bytes` (a positive multiple of 16);
+ * *seconds = the fastest variant's elapsed time (hipEvents), *variant its
+ * index (may be NULL).  Buffers are caller-owned device memory. */
+od_status od_stream_bench(void* hip_stream, void* dst, const void* src, size_t bytes, int32_t iters,
+                          int32_t kind, double* seconds, int32_t* variant);
+
 /* Time n iterations with hipEvents on the grid's stream: *seconds = elapsed
  * device time between events recorded before and after od_iterate(n). */
 od_status od_time_iterate(struct od_grid* g, int64_t n, double* seconds);
 
 /* -------------------------------------------------------------------------
- * Launch-cost microbenchmarks (Section III-A, Managing Overdecomposition:
- * the kernel-overlap experiment with streams gated on one flag, and the
- * kernel-launch-rate experiment over host threads x chares per thread).
- * Both run on the current HIP device and create and destroy their own
- * non-blocking streams (default priority).
+ * Launch-cost microbenchmark (Section III-A, Managing Overdecomposition:
+ * the kernel-overlap experiment with streams gated on one flag).  It runs
+ * on the current HIP device and creates and destroys its own non-blocking
+ * streams (default priority).
  */
 typedef struct {
     int64_t total_threads;
@@ -283,14 +333,6 @@ size_t od_launch_overlap_bytes(int64_t total_threads);
 od_status od_launch_overlap(void* dev_ws, size_t ws_bytes, int64_t total_threads, int32_t nkernels,
                             int32_t nstreams, int32_t work, od_overlap_result* out);
 
-/* host_threads threads each own chares_per_thread streams and, for
- * `seconds` of wall time, launch an empty kernel (one 64-thread workgroup
- * per compute unit) on each of their streams whose previous kernel has
- * completed (event query).  *launches = kernels launched, *kernels_per_s =
- * launches / wall time including the final drain.  host_threads and
- * chares_per_thread in [1, 16], seconds in (0, 60]. */
-od_status od_launch_rate(int32_t host_threads, int32_t chares_per_thread, double seconds, int64_t* launches,
-                         double* kernels_per_s);
 
 /* -------------------------------------------------------------------------
  * Autotuning (tile shape search).  Every candidate computes the same
@@ -306,6 +348,11 @@ od_status od_autotune(struct od_grid* g, int32_t iters, int32_t out_tile[3]);
  * arrive under a device-memory budget and run concurrently by the
  * message-driven device scheduler (continuous batching).  Each solve's
  * result equals that of the same solve run alone.
+ *
+ * Not from the paper: the paper schedules chares of one application from
+ * a message queue (Section II, asynchronous method invocation), and this
+ * layer carries that execution model over to many independent solves
+ * sharing one GPU.  Every call below is this library's own interface.
  */
 typedef struct {
     int64_t n;            /* cubic interior extent                       */
@@ -316,6 +363,12 @@ typedef struct {
     int32_t check_every;  /* residual checked at multiples of this       */
     uint64_t seed;
     double bc[6];
+    double t_arrival;     /* when the request arrived, CLOCK_MONOTONIC
+                             seconds (the clock of od_info's stamps); 0 =
+                             the od_submit time.  Must not lie in the
+                             future (OD_EINVAL).  Latency = t_done -
+                             t_arrival, so time a caller spent before
+                             submitting counts.                          */
 } od_request;
 
 enum { OD_REQ_QUEUED = 0, OD_REQ_RUNNING = 1, OD_REQ_DONE = 2, OD_REQ_CANCELED = 3 };
@@ -325,6 +378,7 @@ typedef struct {
     int64_t iters;       /* iterations done when it stopped             */
     double residual;     /* residual of its last sweep                  */
     double t_submit, t_admit, t_done;   /* host monotonic seconds       */
+    double t_arrival;    /* the request's t_arrival (t_submit if it was 0) */
 } od_info;
 
 /* `dev_arena` of `arena_bytes` (caller-owned, 256-byte aligned) is the
@@ -334,6 +388,13 @@ typedef struct {
  * CLOCK_MONOTONIC seconds. */
 od_status od_server_create(void* hip_stream, void* dev_arena, size_t arena_bytes,
                            int32_t max_slots, struct od_server** out);
+/* Kernel hints of the server's later scheduling epochs: 0 or 4 (bit 2, the
+ * schedule check of od_config.hints: seeded delays and cursor start
+ * positions from `seed` perturb the device schedule, and every task checks
+ * its neighbours' step counters; a failure cancels the running requests
+ * with OD_ECANCELED and a message naming the check).  OD_EINVAL for other
+ * bits.  Results never depend on it. */
+od_status od_server_set_hints(struct od_server* s, int32_t hints, uint64_t seed);
 /* Bytes of the fixed control region od_server_create carves from the
  * start of the arena for `max_slots` slots. */
 od_status od_server_control_bytes(int32_t max_slots, size_t* bytes);

@@ -21,7 +21,7 @@ from . import _binding as B
 from ._binding import ODError, check, lib
 
 __all__ = ["Grid", "Grid2D", "ODError", "DEFAULT_BC", "stream_copy_seconds", "plan_info", "tile_infos", "lib",
-           "Server", "launch_overlap", "launch_rate"]
+           "Server", "launch_overlap"]
 
 DEFAULT_BC = (1.0, 0.0, 0.0, 0.0, 0.0, 0.0)
 _DTYPES = {"f64": (B.OD_F64, np.float64), "f32": (B.OD_F32, np.float32),
@@ -116,7 +116,8 @@ def plan_info(handle) -> dict:
     check(lib().od_plan(handle, ctypes.byref(info)), "od_plan")
     return {"nchares": info.nchares, "ntiles": info.ntiles, "npseudo": info.npseudo,
             "interior": info.interior, "halo_cells": info.halo_cells,
-            "bytes_per_iter": info.bytes_per_iter, "tile": tuple(info.tile), "grid_wgs": info.grid_wgs}
+            "bytes_per_iter": info.bytes_per_iter, "tile": tuple(info.tile), "grid_wgs": info.grid_wgs,
+            "field_bytes": info.field_bytes, "control_bytes": info.control_bytes}
 
 
 def tile_infos(handle, count: int) -> list:
@@ -137,6 +138,25 @@ def chare_boxes(handle, count: int) -> list:
         check(lib().od_chare_get(handle, c, ctypes.byref(b)), "od_chare_get")
         out.append((tuple(b.origin), tuple(b.extent)))
     return out
+
+
+def extra_sweeps(handle, nchares: int, step: int) -> np.ndarray:
+    """Load-imbalance draw of one step: extra sweep re-runs per chare."""
+    out = np.zeros(nchares, dtype=np.int32)
+    check(lib().od_extra_sweeps(handle, int(step), out.ctypes.data_as(ctypes.c_void_p), int(nchares)),
+          "od_extra_sweeps")
+    return out
+
+
+def imbalance_draw(steps: Iterable[int], **kw) -> np.ndarray:
+    """Extra sweep re-runs per (step, chare) of a configuration, from a
+    host-only plan (rows in the order of `steps`)."""
+    p = _PlanHandle(**kw)
+    try:
+        C = plan_info(p.h)["nchares"]
+        return np.stack([extra_sweeps(p.h, C, t) for t in steps])
+    finally:
+        p.close()
 
 
 def host_plan(**kw) -> dict:
@@ -312,6 +332,31 @@ def stream_copy_seconds(nbytes: int, iters: int = 10, device: str = "cuda:0") ->
     return float(s.value)
 
 
+def hbm_ceilings(nbytes: int = 4 << 30, iters: int = 8, device: str = "cuda:0") -> dict:
+    """Measured HBM bandwidth (GB/s) of libod's streaming kernels on buffers
+    of nbytes: copy (2 * nbytes per pass), read-only and write-only (nbytes
+    per pass); the fastest variant of each, and its index."""
+    import torch
+
+    a = torch.zeros(nbytes, dtype=torch.uint8, device=device)
+    b = torch.zeros(nbytes, dtype=torch.uint8, device=device)
+    st = torch.cuda.current_stream(torch.device(device))
+    out = {}
+    try:
+        for kind, name, mult in ((0, "copy", 2), (1, "read", 1), (2, "write", 1)):
+            s = ctypes.c_double()
+            v = ctypes.c_int32()
+            check(lib().od_stream_bench(ctypes.c_void_p(st.cuda_stream), ctypes.c_void_p(b.data_ptr()),
+                                        ctypes.c_void_p(a.data_ptr()), int(nbytes), int(iters), kind,
+                                        ctypes.byref(s), ctypes.byref(v)), "od_stream_bench")
+            out[name + "_gbps"] = round(mult * nbytes * iters / s.value / 1e9, 1)
+            out[name + "_variant"] = int(v.value)
+    finally:
+        del a, b
+    out["bytes"] = int(nbytes)
+    return out
+
+
 def launch_overlap(total_threads: int, nkernels: int, nstreams: int | None = None, work: int = 2000,
                    device: str = "cuda:0", return_outputs: bool = False):
     """Kernel-overlap microbenchmark: total_threads threads of `work`
@@ -336,18 +381,6 @@ def launch_overlap(total_threads: int, nkernels: int, nstreams: int | None = Non
     if return_outputs:
         out["outputs"] = ws[256:].view(torch.int32).cpu().numpy().view(np.uint32)
     return out
-
-
-def launch_rate(host_threads: int, chares_per_thread: int, seconds: float = 0.5, device: str = "cuda:0"):
-    """Kernel-launch-rate microbenchmark: (launches, kernels per second)."""
-    import torch
-
-    n = ctypes.c_int64()
-    r = ctypes.c_double()
-    with torch.cuda.device(torch.device(device)):
-        check(lib().od_launch_rate(int(host_threads), int(chares_per_thread), float(seconds), ctypes.byref(n),
-                                   ctypes.byref(r)), "od_launch_rate")
-    return int(n.value), float(r.value)
 
 
 def Server(*args, **kwargs):  # replaced by the serving module once built

@@ -20,9 +20,11 @@ OD_EAGAIN = -11
 OD_ENOTREADY = -61
 OD_ECANCELED = -125
 OD_ETIMEDOUT = -110
+OD_ESCHED = -71
 OD_EHIP = -1000
 STATUS_NAMES = {0: "OD_OK", -22: "OD_EINVAL", -12: "OD_ENOMEM", -11: "OD_EAGAIN", -61: "OD_ENOTREADY",
-                -125: "OD_ECANCELED", -110: "OD_ETIMEDOUT", -1000: "OD_EHIP"}
+                -125: "OD_ECANCELED", -110: "OD_ETIMEDOUT", -71: "OD_ESCHED", -1000: "OD_EHIP"}
+HINT_NONTEMPORAL, HINT_SPATIAL_ORDER, HINT_SCHEDULE_CHECK = 1, 2, 4
 
 OD_F32, OD_F64 = 4, 8
 EXEC = {"per_chare": 0, "fused": 1, "graph": 2, "persistent": 3, "msgdriven": 4}
@@ -45,7 +47,8 @@ class od_config(ctypes.Structure):
 
 class od_plan_info(ctypes.Structure):
     _fields_ = [("nchares", c_i32), ("ntiles", c_i32), ("npseudo", c_i32), ("interior", c_i64),
-                ("halo_cells", c_i64), ("bytes_per_iter", c_i64), ("tile", c_i32 * 3), ("grid_wgs", c_i32)]
+                ("halo_cells", c_i64), ("bytes_per_iter", c_i64), ("tile", c_i32 * 3), ("grid_wgs", c_i32),
+                ("field_bytes", c_i64), ("control_bytes", c_i64)]
 
 
 class od_tile_info(ctypes.Structure):
@@ -55,12 +58,12 @@ class od_tile_info(ctypes.Structure):
 
 class od_request(ctypes.Structure):
     _fields_ = [("n", c_i64), ("dtype", ctypes.c_int), ("odf", c_i32), ("tol", c_dbl), ("max_iters", c_i64),
-                ("check_every", c_i32), ("seed", c_u64), ("bc", c_dbl * 6)]
+                ("check_every", c_i32), ("seed", c_u64), ("bc", c_dbl * 6), ("t_arrival", c_dbl)]
 
 
 class od_info(ctypes.Structure):
     _fields_ = [("state", c_i32), ("iters", c_i64), ("residual", c_dbl), ("t_submit", c_dbl),
-                ("t_admit", c_dbl), ("t_done", c_dbl)]
+                ("t_admit", c_dbl), ("t_done", c_dbl), ("t_arrival", c_dbl)]
 
 
 class od_server_stats(ctypes.Structure):
@@ -87,8 +90,10 @@ SIGNATURES = {
     "od_plan": (ctypes.c_int, [c_vp, ctypes.POINTER(od_plan_info)]),
     "od_tile_info_get": (ctypes.c_int, [c_vp, c_i32, ctypes.POINTER(od_tile_info)]),
     "od_chare_get": (ctypes.c_int, [c_vp, c_i32, ctypes.POINTER(od_block)]),
+    "od_extra_sweeps": (ctypes.c_int, [c_vp, c_i64, c_vp, c_i32]),
     "od_destroy": (ctypes.c_int, [c_vp]),
     "od_stream_copy": (ctypes.c_int, [c_vp, c_vp, c_vp, c_sz, c_i32, ctypes.POINTER(c_dbl)]),
+    "od_stream_bench": (ctypes.c_int, [c_vp, c_vp, c_vp, c_sz, c_i32, c_i32, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i32)]),
     "od_time_iterate": (ctypes.c_int, [c_vp, c_i64, ctypes.POINTER(c_dbl)]),
     "od_block_cells": (ctypes.c_int, [c_vp, c_i32, ctypes.POINTER(c_i32)]),
     "od_read_block": (ctypes.c_int, [c_vp, c_i32, c_vp, c_sz]),
@@ -96,12 +101,12 @@ SIGNATURES = {
     "od_server_stats_get": (ctypes.c_int, [c_vp, ctypes.POINTER(od_server_stats)]),
     "od_launch_overlap_bytes": (c_sz, [c_i64]),
     "od_launch_overlap": (ctypes.c_int, [c_vp, c_sz, c_i64, c_i32, c_i32, c_i32, ctypes.POINTER(od_overlap_result)]),
-    "od_launch_rate": (ctypes.c_int, [c_i32, c_i32, c_dbl, ctypes.POINTER(c_i64), ctypes.POINTER(c_dbl)]),
     "od_autotune": (ctypes.c_int, [c_vp, c_i32, ctypes.POINTER(c_i32)]),
     "od_server_create": (ctypes.c_int, [c_vp, c_vp, c_sz, c_i32, ctypes.POINTER(c_vp)]),
     "od_request_bytes": (ctypes.c_int, [ctypes.POINTER(od_request), ctypes.POINTER(c_sz)]),
     "od_server_control_bytes": (ctypes.c_int, [c_i32, ctypes.POINTER(c_sz)]),
     "od_submit": (ctypes.c_int, [c_vp, ctypes.POINTER(od_request), ctypes.POINTER(c_u64)]),
+    "od_server_set_hints": (ctypes.c_int, [c_vp, c_i32, c_u64]),
     "od_server_step": (ctypes.c_int, [c_vp, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32)]),
     "od_poll": (ctypes.c_int, [c_vp, c_u64, ctypes.POINTER(od_info)]),
     "od_fetch": (ctypes.c_int, [c_vp, c_u64, c_vp, c_sz]),

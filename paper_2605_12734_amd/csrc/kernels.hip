@@ -330,14 +330,14 @@ template <typename T, int TX, int TY>
 __global__ void __launch_bounds__((TX / V16<T>::N) * TY)
 k_sweep(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDev* __restrict__ tiles,
         int parity, unsigned long long* __restrict__ res, int zero_lo, int zero_hi,
-        const uint8_t* __restrict__ extra, int hints) {
+        const ImbDev imb, int64_t step, int hints) {
     using S = SW<T, TX, TY>;
     __shared__ T lds[S::LDS];
     __shared__ T red[S::NT / 64];
     if (blockIdx.x == 0)
         for (int s = zero_lo + (int)threadIdx.x; s < zero_hi; s += S::NT) res[2 * s + parity] = 0ull;
     const TileDev& t = tiles[blockIdx.x];
-    const int reps = 1 + (extra ? (int)extra[t.blk] : 0);
+    const int reps = 1 + imb_extra(imb, step, t.blk);
     T r = 0;
     for (int rep = 0; rep < reps; ++rep) r = sweep_tile<T, TX, TY>(arena, blocks, t, parity, lds, hints);
     wg_residual<T, S::NT>(r, &res[2 * t.rslot + (parity ^ 1)], red);
@@ -458,8 +458,8 @@ template <typename T, int TX, int TY, bool DYN>
 __global__ void __launch_bounds__((TX / V16<T>::N) * TY)
 k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDev* __restrict__ tiles,
              int32_t ntiles, int parity, int64_t iters, unsigned long long* __restrict__ res, int32_t nres,
-             unsigned int* bar, unsigned int* err, const uint8_t* __restrict__ extra, int32_t extra_period,
-             int32_t nchares, int64_t iter_base, int64_t wait_ticks, int hints) {
+             unsigned int* bar, unsigned int* err, const ImbDev imb, int64_t iter_base, int64_t wait_ticks,
+             int hints) {
     using S = SW<T, TX, TY>;
     __shared__ T lds[S::LDS];
     __shared__ T red[S::NT / 64];
@@ -491,7 +491,6 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
         const int p = parity ^ (int)(it & 1);
         if (blockIdx.x == 0)
             for (int s = (int)threadIdx.x; s < nres; s += S::NT) res[2 * s + p] = 0ull;
-        const uint8_t* ex = extra ? extra + (size_t)((iter_base + it) % extra_period) * nchares : nullptr;
         T r = 0;
         int slot = -1;
         // DYN: tiles of this workgroup's XCD group, taken one at a time from
@@ -511,7 +510,7 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
             if (DYN && threadIdx.x == 0)
                 nxt = (int32_t)__hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const TileDev& t = tiles[ti];
-            const int reps = 1 + (ex ? (int)ex[t.blk] : 0);
+            const int reps = 1 + imb_extra(imb, iter_base + it, t.blk);
             T rr = 0;
             for (int rep = 0; rep < reps; ++rep) rr = sweep_tile<T, TX, TY>(arena, blocks, t, p, lds, hints);
             if (slot >= 0 && slot != t.rslot) {
@@ -686,6 +685,28 @@ __device__ __forceinline__ int64_t ring_take(const MsgArgs& a, unsigned long lon
     }
 }
 
+// Schedule check: wait a seeded 0..a.pert_ticks wall-clock ticks (bounded).
+__device__ __forceinline__ void pert_delay(const MsgArgs& a, uint64_t salt, uint64_t idx) {
+    if (a.pert_ticks <= 0) return;
+    const int64_t d = (int64_t)(sm64(a.seed ^ salt, idx) % (uint64_t)(a.pert_ticks + 1));
+    const int64_t t0 = wall_clock64();
+    while (wall_clock64() - t0 < d) __builtin_amdgcn_s_sleep(1);
+}
+
+// Schedule check (wave 0): every tile that tile c reads halos from (dep
+// list) has finished step `step` - 1 and not yet step `step` + 1, i.e. its
+// step counter is step or step + 1.  Raises kErrSchedule otherwise.
+__device__ __forceinline__ void check_window(const MsgArgs& a, int32_t c, int32_t step) {
+    const int lane = threadIdx.x;
+    bool bad = false;
+    for (int32_t i = a.dep_ptr[c] + lane; i < a.dep_ptr[c + 1]; i += 64) {
+        const int32_t dv = ld_rlx(&a.done[a.dep_idx[i]]);
+        bad |= dv < step || dv > step + 1;
+    }
+    if (__ballot(bad) != 0ull && lane == 0)
+        __hip_atomic_fetch_or(a.err, kErrSchedule, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Plain-grid payload: the tile and the step it runs next, relative to the
 // launch's first step d0 (a launch runs fewer than 2^16 steps).
 __device__ __forceinline__ unsigned long long task_payload(int32_t tile, int32_t rel) {
@@ -843,6 +864,11 @@ __device__ __forceinline__ void queue_loop(const MsgArgs& a, SweepFn sweep, doub
         for (int64_t i = gtid; i < s_m.cap[y]; i += stride) a.pslots[s_m.off[y] + i] = slot_word((uint32_t)i, 0);
     }
     if (!cursor && w == 0 && threadIdx.x < 8) qc[kQcTail + threadIdx.x] = (uint32_t)s_m.n[threadIdx.x];
+    // schedule check: each XCD's cursor starts at a seeded position
+    const bool check = (a.hints & kHintCheck) != 0;
+    if (cursor && check && w == 0 && threadIdx.x < 8 && s_m.n[threadIdx.x] > 0)
+        qc[kQcHead + threadIdx.x] = (uint32_t)(sm64(a.seed ^ 0x637572736F72ull, (uint64_t)d0 * 8 + threadIdx.x) %
+                                               (uint64_t)s_m.n[threadIdx.x]);
     if (!grid_barrier(a.bar, a.err, a.wait_ticks)) return;
 
     const bool haspub = use_publisher(__hip_atomic_load(&qc[kQcWgs + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
@@ -856,10 +882,12 @@ __device__ __forceinline__ void queue_loop(const MsgArgs& a, SweepFn sweep, doub
     const uint32_t total = (uint32_t)s_m.n[x] * (uint32_t)a.qsteps;
     unsigned long long* q = a.qslots + s_m.off[x];
     const uint32_t cap = (uint32_t)s_m.cap[x];
+    uint32_t ntask = 0;
     for (;;) {
         if (threadIdx.x == 0) {
             int64_t pay = -1;
             int32_t stop = 0;
+            if (check) pert_delay(a, 0x636C61696Dull, ((uint64_t)w << 32) + ntask++);
             if (cursor) {
                 if (total == 0) stop = 1;
                 else pay = cursor_claim(a, s_m, x, [] { return false; });
@@ -881,14 +909,24 @@ __device__ __forceinline__ void queue_loop(const MsgArgs& a, SweepFn sweep, doub
         // registers; the step travels with the task
         const int32_t c = __builtin_amdgcn_readfirstlane(s_tile);
         const int32_t step = d0 + __builtin_amdgcn_readfirstlane(s_rel);
+        // the tile's step counter: `step` steps done so far (its last
+        // finish stored it before counting, on this XCD); checked after the
+        // sweep, so the load overlaps it
+        const int32_t seen = __builtin_amdgcn_readfirstlane(ld_rlx(&a.done[c]));
+        if (check && threadIdx.x < 64) check_window(a, c, step);
         const double r = sweep(c, step);
         const int32_t ns = step + 1;
         if (ns == tgt) wg_residual<double, NT>(r, &a.res[ns & 1], red);
+        if (threadIdx.x == 0) {
+            if (seen != step) __hip_atomic_fetch_or(a.err, kErrSchedule, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.done[c], ns, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         wg_stores_done();
         if (threadIdx.x < 64) {
             const int lane = threadIdx.x;
             const bool cross = a.xpub[c] != 0;
             const bool listed = cross && haspub && ns < tgt;
+            if (check && lane == 0) pert_delay(a, 0x7075626C697368ull, ((uint64_t)c << 20) + (uint64_t)step);
             if (lane == 0) {
                 // no publisher on this XCD: write the L2 back before counting
                 // (the launch's end publishes its last step)
@@ -1029,6 +1067,10 @@ __device__ __forceinline__ void serve_loop(const MsgArgs& a, SweepFn sweep, doub
         if (cursor && ready) a.ready[u] = 1;
     }
     if (w == 0 && threadIdx.x == 0) qc[kQcLive] = (uint32_t)a.nlive;
+    const bool check = (a.hints & kHintCheck) != 0;
+    if (cursor && check && w == 0 && threadIdx.x < 8 && s_m.n[threadIdx.x] > 0)
+        qc[kQcHead + threadIdx.x] =
+            (uint32_t)(sm64(a.seed ^ 0x637572736F72ull, threadIdx.x) % (uint64_t)s_m.n[threadIdx.x]);
     if (!grid_barrier(a.bar, a.err, a.wait_ticks)) return;
     // part 2: queue the ready tiles
     for (int64_t i = gtid; i < a.ntiles && !cursor; i += stride) {
@@ -1070,9 +1112,11 @@ __device__ __forceinline__ void serve_loop(const MsgArgs& a, SweepFn sweep, doub
         }
     }
     unsigned long long* q = a.qslots + s_m.off[x];
+    uint32_t ntask = 0;
     for (;;) {
         if (threadIdx.x == 0) {
             int32_t u = -1, stop = 0;
+            if (check) pert_delay(a, 0x636C61696Dull, ((uint64_t)w << 32) + ntask++);
             if (quit() || __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
                 stop = 1;
             } else if (cursor) {
@@ -1094,6 +1138,7 @@ __device__ __forceinline__ void serve_loop(const MsgArgs& a, SweepFn sweep, doub
         const int32_t t = a.tile_list[u];
         const int32_t sv = a.tile_solve[t];
         const int32_t step = __builtin_amdgcn_readfirstlane(ld_rlx(&a.done[t]));
+        if (check && threadIdx.x < 64) check_window(a, t, step);
         const double r = sweep(t, step);
         const int32_t ns = step + 1;
         const bool dec = serve_decision(a, sv, ns);
@@ -1106,8 +1151,12 @@ __device__ __forceinline__ void serve_loop(const MsgArgs& a, SweepFn sweep, doub
             const bool cross = (a.xpub[u] & 1) != 0;
             const bool listed = cross && haspub && !dec;
             int32_t decided = 0;   // lane 0: 1 = the solve goes on (queue all its tiles)
+            if (check && lane == 0) pert_delay(a, 0x7075626C697368ull, ((uint64_t)t << 20) + (uint64_t)step);
             if (lane == 0) {
-                __hip_atomic_store(&a.done[t], ns, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                // the step counter advances by exactly one (a tile claimed
+                // twice, or run twice, would show here)
+                const int32_t was = __hip_atomic_exchange(&a.done[t], ns, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (was != step) __hip_atomic_fetch_or(a.err, kErrSchedule, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 // a decision lets tiles of any XCD go on: publish first
                 if (cross && !listed) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                 __builtin_amdgcn_s_waitcnt(0);
@@ -1180,8 +1229,7 @@ __global__ void __launch_bounds__((TX / V16<T>::N) * TY) OD_MSG_OCC k_msgdriven(
     T* arena = reinterpret_cast<T*>(a.arena);
     auto sweep = [&](int32_t gid, int32_t step) -> double {
         const TileDev& t = a.tiles[gid];
-        const uint8_t* ex = a.extra ? a.extra + (size_t)(step % a.extra_period) * a.nchares : nullptr;
-        const int reps = 1 + (ex ? (int)ex[t.blk] : 0);
+        const int reps = 1 + imb_extra(a.imb, step, t.blk);
         T r = 0;
         for (int rep = 0; rep < reps; ++rep) r = sweep_tile<T, TX, TY>(arena, a.blocks, t, step & 1, lds, a.hints);
         return (double)r;
@@ -1248,13 +1296,13 @@ int sweep_threads(int dtype_bytes, int tx, int ty) {
 
 hipError_t launch_sweep(int dtype_bytes, int tx, int ty, hipStream_t st, void* arena, const BlockDev* blocks,
                         const TileDev* tiles, int32_t ntiles, int parity, unsigned long long* res,
-                        int32_t zero_lo, int32_t zero_hi, const uint8_t* extra, int hints) {
+                        int32_t zero_lo, int32_t zero_hi, const ImbDev& imb, int64_t step, int hints) {
     if (ntiles <= 0) return hipSuccess;
 #define OD_LAUNCH(T, TX, TY)                                                                          \
     if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                      \
         hipLaunchKernelGGL((k_sweep<T, TX, TY>), dim3(ntiles), dim3(SW<T, TX, TY>::NT), 0, st,       \
                            reinterpret_cast<T*>(arena), blocks, tiles, parity, res, zero_lo, zero_hi, \
-                           extra, hints);                                                             \
+                           imb, step, hints);                                                         \
         return hipGetLastError();                                                                     \
     }
     OD_VARIANTS_F64(OD_LAUNCH)
@@ -1313,14 +1361,15 @@ int persistent_max_grid(int dtype_bytes, int tx, int ty, int kind) {
 hipError_t launch_persistent(int dtype_bytes, int tx, int ty, hipStream_t st, int grid, void* arena,
                              const BlockDev* blocks, const TileDev* tiles, int32_t ntiles, int parity,
                              int64_t iters, unsigned long long* res, int32_t nres, unsigned int* bar,
-                             unsigned int* err, const uint8_t* extra, int32_t extra_period, int32_t nchares,
-                             int64_t iter_base, int hints, int dyn, int64_t wait_ticks) {
+                             unsigned int* err, const ImbDev& imb, int64_t iter_base, int hints, int dyn,
+                             int64_t wait_ticks) {
     if (iters <= 0) return hipSuccess;
 #define OD_LAUNCH(T, TX, TY)                                                                          \
     if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                      \
         T* ar = reinterpret_cast<T*>(arena);                                                          \
+        ImbDev im = imb;                                                                              \
         void* args[] = {&ar, &blocks, &tiles, &ntiles, &parity, &iters, &res, &nres, &bar, &err,      \
-                        &extra, &extra_period, &nchares, &iter_base, &wait_ticks, &hints};            \
+                        &im, &iter_base, &wait_ticks, &hints};                                        \
         const void* fn = dyn ? reinterpret_cast<const void*>(k_persistent<T, TX, TY, true>)           \
                              : reinterpret_cast<const void*>(k_persistent<T, TX, TY, false>);         \
         return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(SW<T, TX, TY>::NT), args, 0, st);      \
@@ -1363,14 +1412,17 @@ hipError_t launch_msgdriven(int dtype_bytes, int tx, int ty, hipStream_t st, int
     return hipErrorInvalidValue;
 }
 
-__global__ void k_queue_init(MsgArgs a) {
+__global__ void k_queue_init(MsgArgs a, int32_t target, int32_t* target_word, unsigned long long* res_clear) {
     // heads, tails, present-XCD mask, workgroups per XCD, list tails and
     // cross-tile counts start at zero; the launch fills in the rest
     a.qhead[threadIdx.x] = 0u;
+    if (target_word && threadIdx.x == 0) *target_word = target;
+    if (res_clear && threadIdx.x < 2) res_clear[threadIdx.x] = 0ull;
 }
 
-hipError_t launch_queue_init(hipStream_t st, const MsgArgs& a) {
-    hipLaunchKernelGGL(k_queue_init, dim3(1), dim3(64), 0, st, a);
+hipError_t launch_queue_init(hipStream_t st, const MsgArgs& a, int32_t target, int32_t* target_word,
+                             unsigned long long* res_clear) {
+    hipLaunchKernelGGL(k_queue_init, dim3(1), dim3(64), 0, st, a, target, target_word, res_clear);
     return hipGetLastError();
 }
 
@@ -1730,24 +1782,56 @@ hipError_t launch_unpack(int dtype_bytes, hipStream_t st, FaceSet in, FaceSet gh
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-template <int U, bool NT>
-__global__ void __launch_bounds__(256) k_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst, int64_t n) {
-    // U independent 16-byte loads in flight per thread, then U stores
+// HBM ceilings: streaming copy (KIND 0: dst <- src), read-only (KIND 1:
+// every 16-byte vector of src is loaded and folded into a per-thread xor
+// that is stored only if it equals `key`, which never holds for the data
+// used, so the loads stay and nothing is written) and write-only (KIND 2:
+// dst <- a per-element pattern).  U independent 16-byte accesses in flight
+// per thread, grid-stride over the buffer.
+template <int U, bool NT, int KIND>
+__global__ void __launch_bounds__(256) k_stream(const u32x4* __restrict__ src, u32x4* __restrict__ dst, int64_t n,
+                                                uint32_t key, uint32_t* __restrict__ sink) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    u32x4 acc = {0u, 0u, 0u, 0u};
     for (; e + (U - 1) * stride < n; e += U * stride) {
         u32x4 v[U];
+        if (KIND != 2) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = NT ? __builtin_nontemporal_load(src + e + u * stride) : src[e + u * stride];
+            for (int u = 0; u < U; ++u)
+                v[u] = NT ? __builtin_nontemporal_load(src + e + u * stride) : src[e + u * stride];
+        } else {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (NT)
-                __builtin_nontemporal_store(v[u], dst + e + u * stride);
-            else
-                dst[e + u * stride] = v[u];
+            for (int u = 0; u < U; ++u) {
+                const uint32_t x = (uint32_t)(e + u * stride);
+                v[u] = u32x4{x, x ^ key, x + key, ~x};
+            }
+        }
+        if (KIND == 1) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc ^= v[u];
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (NT)
+                    __builtin_nontemporal_store(v[u], dst + e + u * stride);
+                else
+                    dst[e + u * stride] = v[u];
+            }
         }
     }
-    for (; e < n; e += stride) dst[e] = src[e];
+    for (; e < n; e += stride) {
+        if (KIND == 0) dst[e] = src[e];
+        else if (KIND == 1) acc ^= src[e];
+        else {
+            const uint32_t x = (uint32_t)e;
+            dst[e] = u32x4{x, x ^ key, x + key, ~x};
+        }
+    }
+    if (KIND == 1) {
+        const uint32_t f = acc[0] ^ acc[1] ^ acc[2] ^ acc[3];
+        if (f == key) atomicOr(sink, 1u);
+    }
 }
 
 struct CopyVariant {
@@ -1755,11 +1839,13 @@ struct CopyVariant {
     bool nt;
 };
 static const CopyVariant kCopyVariants[] = {{32, 1, false}, {16, 4, false}, {16, 4, true}, {64, 2, false},
-                                            {64, 2, true},  {8, 8, true}};
+                                            {64, 2, true},  {8, 8, true},   {8, 8, false}, {32, 4, false},
+                                            {32, 4, true},  {4, 8, true}};
 
 int copy_variant_count() { return (int)(sizeof(kCopyVariants) / sizeof(kCopyVariants[0])); }
 
-hipError_t launch_copy(hipStream_t st, void* dst, const void* src, size_t bytes, int variant) {
+hipError_t launch_stream(hipStream_t st, void* dst, const void* src, size_t bytes, int variant, int kind,
+                         uint32_t* sink) {
     const int64_t n = (int64_t)(bytes / 16);
     int dev = 0, ncu = 256;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -1772,19 +1858,28 @@ hipError_t launch_copy(hipStream_t st, void* dst, const void* src, size_t bytes,
     if (grid < 1) grid = 1;
     const u32x4* s4 = reinterpret_cast<const u32x4*>(src);
     u32x4* d4 = reinterpret_cast<u32x4*>(dst);
-#define OD_COPY(UU, NTT)                                                                        \
-    if (cv.unroll == UU && cv.nt == NTT) {                                                      \
-        hipLaunchKernelGGL((k_copy<UU, NTT>), dim3((unsigned)grid), dim3(256), 0, st, s4, d4, n); \
-        return hipGetLastError();                                                               \
+    const uint32_t key = 0x9E3779B9u;   // the sink is a valid word: a chance match only sets a bit in it
+#define OD_STREAM(UU, NTT, K)                                                                             \
+    if (cv.unroll == UU && cv.nt == NTT && kind == K) {                                                   \
+        hipLaunchKernelGGL((k_stream<UU, NTT, K>), dim3((unsigned)grid), dim3(256), 0, st, s4, d4, n, key, \
+                           sink);                                                                         \
+        return hipGetLastError();                                                                         \
     }
-    OD_COPY(1, false)
-    OD_COPY(4, false)
-    OD_COPY(4, true)
-    OD_COPY(2, false)
-    OD_COPY(2, true)
-    OD_COPY(8, true)
-#undef OD_COPY
+#define OD_STREAM_K(UU, NTT) OD_STREAM(UU, NTT, 0) OD_STREAM(UU, NTT, 1) OD_STREAM(UU, NTT, 2)
+    OD_STREAM_K(1, false)
+    OD_STREAM_K(4, false)
+    OD_STREAM_K(4, true)
+    OD_STREAM_K(2, false)
+    OD_STREAM_K(2, true)
+    OD_STREAM_K(8, true)
+    OD_STREAM_K(8, false)
+#undef OD_STREAM_K
+#undef OD_STREAM
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_copy(hipStream_t st, void* dst, const void* src, size_t bytes, int variant) {
+    return launch_stream(st, dst, src, bytes, variant, 0, nullptr);
 }
 
 }  // namespace od

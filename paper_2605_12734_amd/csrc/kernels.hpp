@@ -26,6 +26,67 @@ struct GridDev {
     int64_t n[3];
 };
 
+// Seeded load imbalance (one definition for the host and the device).  At
+// step t the chares are put in the order of a pseudo-random permutation of
+// their ids drawn from (seed, t); the first `heavy` of them re-run their
+// sweep 1..maxe extra times, the count drawn from SplitMix64 at
+// (seed, t, chare).  The permutation is a four-round Feistel network on
+// the smallest even number of bits covering the chare count, with cycle
+// walking back into [0, nchares), so exactly `heavy` chares are drawn at
+// every step and the draw is fresh at every step (no table, no period).
+struct ImbDev {
+    uint64_t seed;
+    int32_t nchares;
+    int32_t heavy;     // chares drawn per step (0 = no imbalance)
+    int32_t maxe;      // largest number of extra re-runs
+    int32_t pad_;
+};
+
+__host__ __device__ inline uint64_t imb_mix(uint64_t seed, uint64_t idx) {
+    uint64_t z = seed + (idx + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Position of chare c in step t's order (a permutation of [0, nchares)).
+__host__ __device__ inline uint32_t imb_rank(const ImbDev& m, int64_t t, uint32_t c) {
+    int half = 1;
+    while ((1ull << (2 * half)) < (uint64_t)m.nchares) ++half;
+    const uint32_t mask = (1u << half) - 1u;
+    const uint64_t key = imb_mix(m.seed ^ 0x696D62616C616E63ull, (uint64_t)t);
+    uint32_t y = c;
+    do {
+        uint32_t l = y >> half, r = y & mask;
+        for (uint32_t round = 0; round < 4; ++round) {
+            const uint32_t f = (uint32_t)imb_mix(key, ((uint64_t)round << 32) | r) & mask;
+            const uint32_t nl = r;
+            r = l ^ f;
+            l = nl;
+        }
+        y = (l << half) | r;
+    } while (y >= (uint32_t)m.nchares);
+    return y;
+}
+
+// Extra re-runs of chare c's sweep at step t (0 for most chares).
+__host__ __device__ inline int32_t imb_extra(const ImbDev& m, int64_t t, int32_t c) {
+    if (m.heavy <= 0 || m.maxe <= 0) return 0;
+    if (imb_rank(m, t, (uint32_t)c) >= (uint32_t)m.heavy) return 0;
+    const uint64_t h = imb_mix(m.seed ^ 0x6578747261ull, (uint64_t)t * (uint64_t)m.nchares + (uint64_t)c);
+    return 1 + (int32_t)((h >> 32) % (uint64_t)m.maxe);
+}
+
+// hints bit 2: message-driven schedule check.  Seeded delays before each
+// task publishes its finish and before each claim, and seeded start
+// offsets of the per-XCD cursors, perturb the order in which tiles run;
+// every task checks that each tile it reads halos from is within one step
+// of it.  In every message-driven launch a task also checks that its
+// tile's step counter advances by exactly one.  A failed check raises
+// kErrSchedule in the error flag (the launch then ends; no trap).
+constexpr int kHintCheck = 4;
+constexpr unsigned int kErrSchedule = 4u;
+
 // Sweep-kernel variant: tile shape (x, y) compiled in; z extent is per tile.
 struct SweepVariant {
     int tx, ty;
@@ -39,12 +100,12 @@ int sweep_threads(int dtype_bytes, int tx, int ty);
 // Fused sweep over tiles[0..ntiles): one workgroup per tile, reading parity
 // `parity`, writing parity^1.  Residual of tile t goes (atomic max of the
 // value's bit pattern) into res[2*rslot + (parity^1)]; workgroup 0 first
-// zeroes res[2*s + parity] for s in [zero_lo, zero_hi).  `extra` (may be
-// null): per-chare count of extra re-runs of the sweep for this step.
+// zeroes res[2*s + parity] for s in [zero_lo, zero_hi).  `imb`, `step`:
+// the load-imbalance draw of this step (imb.heavy == 0: none).
 hipError_t launch_sweep(int dtype_bytes, int tx, int ty, hipStream_t st, void* arena,
                         const BlockDev* blocks, const TileDev* tiles, int32_t ntiles, int parity,
                         unsigned long long* res, int32_t zero_lo, int32_t zero_hi,
-                        const uint8_t* extra, int hints);
+                        const ImbDev& imb, int64_t step, int hints);
 
 // Persistent cooperative sweep: all `iters` iterations in one launch with a
 // device-wide barrier between them.  dyn != 0: workgroups take tiles from
@@ -54,14 +115,15 @@ hipError_t launch_sweep(int dtype_bytes, int tx, int ty, hipStream_t st, void* a
 // [8..24) tile counters (8 XCD groups x 2 step parities), [32..40) per-XCD
 // barrier arrivals, [40..48) workgroups per XCD; the kernel leaves them
 // zeroed.  Between iterations, one L2 write-back per XCD publishes its
-// workgroups' results (the XCD's workgroups share that L2).  `err` = error flag.  `extra` (may be null): table of
-// [period][nchares] extra re-runs, row (iter_base + it) % period.
+// workgroups' results (the XCD's workgroups share that L2).  `err` = error
+// flag.  `imb`: load-imbalance draw, iteration `it` of the launch is step
+// iter_base + it.
 hipError_t launch_persistent(int dtype_bytes, int tx, int ty, hipStream_t st, int grid,
                              void* arena, const BlockDev* blocks, const TileDev* tiles,
                              int32_t ntiles, int parity, int64_t iters,
                              unsigned long long* res, int32_t nres, unsigned int* bar,
-                             unsigned int* err, const uint8_t* extra, int32_t extra_period,
-                             int32_t nchares, int64_t iter_base, int hints, int dyn, int64_t wait_ticks);
+                             unsigned int* err, const ImbDev& imb, int64_t iter_base, int hints, int dyn,
+                             int64_t wait_ticks);
 // Wall-clock ticks in `seconds` (bound of every device-side wait).
 int64_t device_wait_ticks(double seconds = 10.0);
 // Max co-resident workgroups of a cooperative kernel: kind 0 = persistent
@@ -86,11 +148,11 @@ struct MsgArgs {
     const int32_t* tile_solve;  // serving: solve of each tile
     unsigned long long* res;    // plain grid: 2 slots (step parity); serving: 1 slot per solve
     unsigned int* err;
-    const uint8_t* extra;       // [period][nchares] or null
-    int32_t extra_period;
-    int32_t nchares;
+    ImbDev imb;                 // load-imbalance draw (heavy == 0: none)
     int64_t wait_ticks;         // bound on every device-side wait (wall-clock ticks)
-    int32_t hints;              // od_config.hints
+    int32_t hints;              // od_config.hints (bit 2: schedule check, see kHintCheck)
+    uint64_t seed;              // schedule check: seed of the perturbation
+    int64_t pert_ticks;         // schedule check: largest delay (wall-clock ticks)
     // serving only
     int32_t* solve_count;       // per solve: tiles that finished the current decision step
     int32_t* gate;              // per solve: highest step whose check passed
@@ -128,8 +190,11 @@ struct MsgArgs {
 };
 hipError_t launch_msgdriven(int dtype_bytes, int tx, int ty, hipStream_t st, int grid, const MsgArgs& a);
 // Clear the control words of a dependency-counting message-driven launch
-// (the launch itself lays out and fills its queues).
-hipError_t launch_queue_init(hipStream_t st, const MsgArgs& a);
+// (the launch itself lays out and fills its queues); a plain grid also
+// stores its target step in *target_word and zeroes res_clear[0..2) (both
+// may be null), so no host buffer has to outlive the call.
+hipError_t launch_queue_init(hipStream_t st, const MsgArgs& a, int32_t target = 0, int32_t* target_word = nullptr,
+                             unsigned long long* res_clear = nullptr);
 // Serving: for every launch position q of list[0..n) holding a tile id v
 // (-1 = padding), tpos[v] = q, and sbase[v / stride] = q when v is a
 // solve's first tile (v % stride == 0).  Entries of tiles not in the list
@@ -209,5 +274,10 @@ hipError_t launch_unpack(int dtype_bytes, hipStream_t st, FaceSet in, FaceSet gh
 // kernel variant `variant` (0 .. copy_variant_count()-1).
 int copy_variant_count();
 hipError_t launch_copy(hipStream_t st, void* dst, const void* src, size_t bytes, int variant);
+// The same variants as a read-only (kind 1: loads src, writes nothing; a
+// 4-byte `sink` is written only for a data pattern that does not occur)
+// or write-only (kind 2: stores a pattern to dst) stream; kind 0 = copy.
+hipError_t launch_stream(hipStream_t st, void* dst, const void* src, size_t bytes, int variant, int kind,
+                         uint32_t* sink);
 
 }  // namespace od

@@ -1,7 +1,6 @@
-// Launch-cost microbenchmarks for overdecomposed execution (Section III-A,
+// Launch-cost microbenchmark for overdecomposed execution (Section III-A,
 // "Managing Overdecomposition"): how much of a fine-grained kernel's cost is
-// device-side launch processing, and how fast one process can keep firing
-// kernels from several host threads and streams.
+// device-side launch processing.
 //
 //  - overlap: a fixed amount of work (total_threads threads, `work` dependent
 //    integer multiply-adds each) split into nkernels kernels on a pool of
@@ -14,13 +13,9 @@
 //    multiplexes streams onto a few hardware queues, so a release enqueued
 //    on another stream can sit in the same queue behind a gate and never
 //    run.  Every gate gives up after a bounded wait and reports it.
-//  - rate: host threads each own `chares` streams; a thread fires an empty
-//    full-device kernel on a stream whenever that stream's previous kernel
-//    has completed (event query), for a fixed wall time.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <atomic>
 #include <chrono>
 #include <cstring>
 #include <string>
@@ -69,8 +64,6 @@ __global__ void k_gate(const uint32_t* flag, unsigned long long* stamps, int64_t
         }
     }
 }
-
-__global__ void k_empty() {}
 
 double now_us() {
     return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -223,79 +216,6 @@ od_status od_launch_overlap(void* dev_ws, size_t ws_bytes, int64_t total_threads
         out->enqueue_us = t1 - t0;
         out->host_us = t3 - t2;
         out->makespan_us = st[1] >= st[0] ? (double)(st[1] - st[0]) * 1e3 / (double)khz : 0.0;
-        return OD_OK;
-    } catch (const std::exception& ex) {
-        return od::fail(OD_EINVAL, std::string("internal error: ") + ex.what());
-    } catch (...) {
-        return od::fail(OD_EINVAL, "internal error");
-    }
-}
-
-od_status od_launch_rate(int32_t host_threads, int32_t chares_per_thread, double seconds, int64_t* launches,
-                         double* kernels_per_s) {
-    try {
-        if (!launches || !kernels_per_s) return od::fail(OD_EINVAL, "output pointer is NULL");
-        *launches = 0;
-        *kernels_per_s = 0.0;
-        if (host_threads <= 0 || host_threads > 16) return od::fail(OD_EINVAL, "host_threads must be in [1, 16]");
-        if (chares_per_thread <= 0 || chares_per_thread > 16)
-            return od::fail(OD_EINVAL, "chares_per_thread must be in [1, 16]");
-        if (!(seconds > 0.0) || seconds > 60.0) return od::fail(OD_EINVAL, "seconds must be in (0, 60]");
-        int dev = 0, ncu = 0;
-        OD_HIP_OR_FAIL(hipGetDevice(&dev));
-        OD_HIP_OR_FAIL(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-        const int nst = host_threads * chares_per_thread;
-        Streams S;
-        OD_HIP_OR_FAIL(S.create(nst));
-        std::vector<int64_t> counts(host_threads, 0);
-        std::vector<hipError_t> errs(host_threads, hipSuccess);
-        std::atomic<bool> go{false};
-        std::vector<std::thread> th;
-        const double t_len = seconds * 1e6;
-        double t_start = 0.0;
-        for (int t = 0; t < host_threads; ++t) {
-            th.emplace_back([&, t] {
-                if (hipSetDevice(dev) != hipSuccess) {
-                    errs[t] = hipErrorInvalidDevice;
-                    return;
-                }
-                while (!go.load(std::memory_order_acquire)) std::this_thread::yield();
-                const double t_end = now_us() + t_len;
-                int64_t n = 0;
-                while (now_us() < t_end) {
-                    for (int c = 0; c < chares_per_thread; ++c) {
-                        const int i = t * chares_per_thread + c;
-                        const hipError_t q = hipEventQuery(S.e[i]);
-                        if (q == hipErrorNotReady) continue;
-                        if (q != hipSuccess) {
-                            errs[t] = q;
-                            return;
-                        }
-                        hipLaunchKernelGGL(k_empty, dim3(ncu), dim3(64), 0, S.s[i]);
-                        hipError_t r = hipGetLastError();
-                        if (r == hipSuccess) r = hipEventRecord(S.e[i], S.s[i]);
-                        if (r != hipSuccess) {
-                            errs[t] = r;
-                            return;
-                        }
-                        ++n;
-                    }
-                }
-                counts[t] = n;
-            });
-        }
-        t_start = now_us();
-        go.store(true, std::memory_order_release);
-        for (auto& x : th) x.join();
-        const bool done = wait_events(S.e, 60.0);
-        const double t_stop = now_us();
-        for (int t = 0; t < host_threads; ++t)
-            if (errs[t] != hipSuccess) return od::fail(OD_EHIP, std::string("launch thread: ") + hipGetErrorString(errs[t]));
-        if (!done) return od::fail(OD_ETIMEDOUT, "kernels did not complete within 60 s");
-        int64_t total = 0;
-        for (auto c : counts) total += c;
-        *launches = total;
-        *kernels_per_s = (double)total / ((t_stop - t_start) * 1e-6);
         return OD_OK;
     } catch (const std::exception& ex) {
         return od::fail(OD_EINVAL, std::string("internal error: ") + ex.what());

@@ -41,7 +41,6 @@ uint64_t host_sm64(uint64_t seed, uint64_t idx) {
 namespace {
 
 constexpr int kStreamPool = 16;          // per-chare baseline: non-blocking streams
-constexpr int kImbalancePeriod = 64;     // rows of the imbalance table (steps mod period)
 constexpr int64_t kMaxGraphLen = 1024;   // iterations per captured graph
 
 struct Carver {
@@ -283,8 +282,10 @@ std::string build_layout(const od_config& cfg, Grid& G) {
     G.pb_face.clear();
     G.pb_block.clear();
 
-    // descriptor regions first (sizes known after tiles / pseudo-blocks)
-    // the 2D stencil never reads y neighbours: no y-face buffers (each would
+    // field storage first (chares, face pseudo-blocks, per-chare messages),
+    // then the control regions (descriptors and state), so the control part
+    // can be placed apart from the field storage.
+    // The 2D stencil never reads y neighbours: no y-face buffers (each would
     // be as large as the chare), y ghost slabs point at the tile itself
     const bool flat = cfg.stencil == 5;
     int32_t npb = 0;
@@ -295,81 +296,14 @@ std::string build_layout(const od_config& cfg, Grid& G) {
             else if (cfg.exec == OD_PER_CHARE) ++npb;
             else if (p.multires && p.mr[(size_t)c * 6 + f]) ++npb;
         }
-    const size_t nblocks = (size_t)C + (size_t)npb;
-    const size_t ntiles = p.tiles.size();
-    G.L.blocks = cv.take(nblocks * sizeof(BlockDev));
-    // room for the tiles of any autotune candidate (smallest candidate tile,
-    // plus splits down to the block granularity for explicit blocks)
-    G.tile_cap = ntiles;
-    if (cfg.exec == OD_FUSED || cfg.exec == OD_GRAPH || cfg.exec == OD_PERSISTENT) {
-        int32_t m[3], eymax = 1;
-        for (const Chare& c : p.chares) eymax = std::max(eymax, c.e[1]);
-        tune_min_tile(G.s, eymax, m);
-        size_t cap = 0;
-        for (const Chare& c : p.chares) {
-            size_t k = 1;
-            for (int d = 0; d < 3; ++d) {
-                int32_t md = m[d];
-                if (!p.regular) md = std::min(md, std::max<int32_t>(1, p.gcell));
-                k *= (size_t)ceil_div(c.e[d], md);
-            }
-            cap += k;
-        }
-        G.tile_cap = std::max(ntiles, cap);
-    }
-    G.L.tiles = cv.take(G.tile_cap * sizeof(TileDev));
-    for (int d = 0; d < 3; ++d) G.L.cidx[d] = cv.take((size_t)(p.regular ? p.n[d] : 1) * 4);
-    G.L.owner = cv.take((p.regular ? 1 : p.owner.size()) * 4);
-    G.L.corigin = cv.take((size_t)C * 3 * 4);
-    G.L.ccell = cv.take((size_t)C * 4);
-    G.L.dir_pb = cv.take((size_t)C * 6 * 4);
-    G.L.pb_face = cv.take((size_t)std::max(npb, 1) * 4);
-    G.L.pb_block = cv.take((size_t)std::max(npb, 1) * 4);
-    G.L.bc = cv.take(6 * 8);
-    G.nres = cfg.exec == OD_PER_CHARE ? C : 1;
-    G.L.res = cv.take((size_t)(2 * G.nres + 2) * 8);
-    G.L.bar = cv.take(64 * 4);
-    G.L.err = cv.take(4);
-    G.L.done = cv.take(ntiles * 4);
-    G.L.target = cv.take(4 * 4);
-    // message-driven dependencies
-    G.dep_ptr.clear();
-    G.dep_idx.clear();
-    if (cfg.exec == OD_MSGDRIVEN) {
-        std::string e2 = build_tile_deps(p, G.dep_ptr, G.dep_idx);
-        if (!e2.empty()) return e2;
-    }
-    G.L.xpub = cv.take(cfg.exec == OD_MSGDRIVEN ? ntiles : 1);
-    if (cfg.exec == OD_MSGDRIVEN) {
-        // a queue entry holds a tile index in 24 bits
-        if (ntiles >= ((size_t)1 << 23)) return "message-driven grids are limited to 2^23 - 1 tiles";
-        // dependency counters; per present XCD a ready ring and a cross
-        // list of the next power of two >= its tile count
-        G.L.pend = cv.take(ntiles * 2 * 4);
-        G.L.qslots = cv.take(2 * (2 * ntiles + 8) * 8);   // ready queues, then cross lists
-        G.L.qctl = cv.take(64 * 4);
-    }
-    G.L.dep_ptr = cv.take((G.dep_ptr.size() + 1) * 4);
-    G.L.dep_idx = cv.take((G.dep_idx.size() + 1) * 4);
-    // imbalance table
-    G.extra_h.clear();
+    // load imbalance: drawn per step on the device (ImbDev)
+    G.imb = ImbDev{};
     if (cfg.imbalance_pct > 0 && cfg.imbalance_max_extra > 0) {
-        G.extra_h.assign((size_t)kImbalancePeriod * C, 0);
-        const int32_t m = (int32_t)std::llround(cfg.imbalance_pct / 100.0 * C);
-        std::vector<std::pair<uint64_t, int32_t>> rank((size_t)C);
-        for (int32_t t = 0; t < kImbalancePeriod; ++t) {
-            for (int32_t c = 0; c < C; ++c)
-                rank[(size_t)c] = {host_sm64(cfg.seed ^ 0x696D62616C616E63ull, (uint64_t)t * C + c), c};
-            std::partial_sort(rank.begin(), rank.begin() + m, rank.end());
-            for (int32_t q = 0; q < m; ++q) {
-                const uint64_t h = rank[(size_t)q].first;
-                G.extra_h[(size_t)t * C + rank[(size_t)q].second] =
-                    (uint8_t)(1 + (int)((h >> 32) % (uint64_t)cfg.imbalance_max_extra));
-            }
-        }
+        G.imb.seed = cfg.seed;
+        G.imb.nchares = C;
+        G.imb.heavy = (int32_t)std::llround(cfg.imbalance_pct / 100.0 * C);
+        G.imb.maxe = cfg.imbalance_max_extra;
     }
-    G.extra_period = kImbalancePeriod;
-    G.L.extra = cv.take(G.extra_h.size() + 1);
 
     // ---- field storage (two parities per chare)
     for (int32_t c = 0; c < C; ++c) {
@@ -388,7 +322,6 @@ std::string build_layout(const od_config& cfg, Grid& G) {
         B.ey = ch.e[1];
         B.ez = ch.e[2];
     }
-    G.L.field_end = cv.off;
     // ---- pseudo-blocks
     G.amr_pb.assign((size_t)C * 6, -1);
     for (int32_t c = 0; c < C; ++c) {
@@ -454,9 +387,68 @@ std::string build_layout(const od_config& cfg, Grid& G) {
                 if (t.kind[f] == 0) direct += (int64_t)t.e[0] * t.e[1] * t.e[2] / t.e[f / 2];
         p.halo_cells = direct + reads;
     }
+    // ---- control regions: descriptors and device state
+    G.L.field_end = align_up(cv.off, kAlign);
+    cv.off = G.L.field_end;
+    G.L.ctrl_begin = G.L.field_end;
+    const size_t nblocks = (size_t)C + (size_t)npb;
+    const size_t ntiles = p.tiles.size();
+    G.L.blocks = cv.take(nblocks * sizeof(BlockDev));
+    // room for the tiles of any autotune candidate (smallest candidate tile,
+    // plus splits down to the block granularity for explicit blocks)
+    G.tile_cap = ntiles;
+    if (G.tune_room && (cfg.exec == OD_FUSED || cfg.exec == OD_GRAPH || cfg.exec == OD_PERSISTENT)) {
+        int32_t m[3], eymax = 1;
+        for (const Chare& c : p.chares) eymax = std::max(eymax, c.e[1]);
+        tune_min_tile(G.s, eymax, m);
+        size_t cap = 0;
+        for (const Chare& c : p.chares) {
+            size_t k = 1;
+            for (int d = 0; d < 3; ++d) {
+                int32_t md = m[d];
+                if (!p.regular) md = std::min(md, std::max<int32_t>(1, p.gcell));
+                k *= (size_t)ceil_div(c.e[d], md);
+            }
+            cap += k;
+        }
+        G.tile_cap = std::max(ntiles, cap);
+    }
+    G.L.tiles = cv.take(G.tile_cap * sizeof(TileDev));
+    for (int d = 0; d < 3; ++d) G.L.cidx[d] = cv.take((size_t)(p.regular ? p.n[d] : 1) * 4);
+    G.L.owner = cv.take((p.regular ? 1 : p.owner.size()) * 4);
+    G.L.corigin = cv.take((size_t)C * 3 * 4);
+    G.L.ccell = cv.take((size_t)C * 4);
+    G.L.dir_pb = cv.take((size_t)C * 6 * 4);
+    G.L.pb_face = cv.take((size_t)std::max(npb, 1) * 4);
+    G.L.pb_block = cv.take((size_t)std::max(npb, 1) * 4);
+    G.L.bc = cv.take(6 * 8);
+    G.nres = cfg.exec == OD_PER_CHARE ? C : 1;
+    G.L.res = cv.take((size_t)(2 * G.nres + 2) * 8);
+    G.L.bar = cv.take(64 * 4);
+    G.L.err = cv.take(4);
+    G.L.done = cv.take(ntiles * 4);
+    G.L.target = cv.take(4 * 4);
+    // message-driven dependencies
+    G.dep_ptr.clear();
+    G.dep_idx.clear();
+    if (cfg.exec == OD_MSGDRIVEN) {
+        std::string e2 = build_tile_deps(p, G.dep_ptr, G.dep_idx);
+        if (!e2.empty()) return e2;
+    }
+    G.L.xpub = cv.take(cfg.exec == OD_MSGDRIVEN ? ntiles : 1);
+    if (cfg.exec == OD_MSGDRIVEN) {
+        // a queue entry holds a tile index in 24 bits
+        if (ntiles >= ((size_t)1 << 23)) return "message-driven grids are limited to 2^23 - 1 tiles";
+        // dependency counters; per present XCD a ready ring and a cross
+        // list of the next power of two >= its tile count
+        G.L.pend = cv.take(ntiles * 2 * 4);
+        G.L.qslots = cv.take(2 * (2 * ntiles + 8) * 8);   // ready queues, then cross lists
+        G.L.qctl = cv.take(64 * 4);
+    }
+    G.L.dep_ptr = cv.take((G.dep_ptr.size() + 1) * 4);
+    G.L.dep_idx = cv.take((G.dep_idx.size() + 1) * 4);
     G.L.segs = cv.take(std::max<size_t>(G.segs_h.size(), 1) * sizeof(FillSeg));
     G.L.total = align_up(cv.off, kAlign) + kAlign;
-
     return fill_tile_descs(G);
 }
 
@@ -541,10 +533,10 @@ std::string build_tile_deps(const Plan& p, std::vector<int32_t>& ptr, std::vecto
 // ---------------------------------------------------------------------------
 
 od_status Grid::upload() {
-    char* ws = base;
+    if (!ctrl) ctrl = base + L.ctrl_begin;   // control regions follow the fields in the workspace
     auto put = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
         if (bytes == 0) return hipSuccess;
-        return hipMemcpyAsync(ws + off, src, bytes, hipMemcpyHostToDevice, st);
+        return hipMemcpyAsync(cp(off), src, bytes, hipMemcpyHostToDevice, st);
     };
     const Plan& p = plan;
     const int32_t C = (int32_t)p.chares.size();
@@ -577,33 +569,32 @@ od_status Grid::upload() {
     if (e == hipSuccess) e = put(L.bc, cfg.bc, 6 * 8);
     if (e == hipSuccess) e = put(L.dep_ptr, dep_ptr.data(), dep_ptr.size() * 4);
     if (e == hipSuccess) e = put(L.dep_idx, dep_idx.data(), dep_idx.size() * 4);
-    if (e == hipSuccess) e = put(L.extra, extra_h.data(), extra_h.size());
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("descriptor upload: ") + hipGetErrorString(e));
 
     gdev.arena = base;
-    gdev.blocks = reinterpret_cast<const BlockDev*>(base + L.blocks);
+    gdev.blocks = reinterpret_cast<const BlockDev*>(cp(L.blocks));
     gdev.lk.regular = p.regular ? 1 : 0;
     for (int d = 0; d < 3; ++d) {
         gdev.lk.k[d] = p.k[d];
-        gdev.lk.cidx[d] = reinterpret_cast<const int32_t*>(base + L.cidx[d]);
+        gdev.lk.cidx[d] = reinterpret_cast<const int32_t*>(cp(L.cidx[d]));
         gdev.lk.og[d] = (int32_t)p.og[d];
         gdev.n[d] = p.n[d];
     }
-    gdev.lk.owner = reinterpret_cast<const int32_t*>(base + L.owner);
+    gdev.lk.owner = reinterpret_cast<const int32_t*>(cp(L.owner));
     gdev.lk.gran = p.gran;
-    gdev.lk.corigin = reinterpret_cast<const int32_t*>(base + L.corigin);
-    gdev.lk.dir_pb = reinterpret_cast<const int32_t*>(base + L.dir_pb);
+    gdev.lk.corigin = reinterpret_cast<const int32_t*>(cp(L.corigin));
+    gdev.lk.dir_pb = reinterpret_cast<const int32_t*>(cp(L.dir_pb));
     return OD_OK;
 }
 
 od_status Grid::reset_state() {
     // zero residual slots, barrier, error flag and step counters with a
     // plain fill (not captured into any graph)
-    hipError_t e = hipMemsetAsync(base + L.res, 0, (size_t)(2 * nres + 2) * 8, st);
-    if (e == hipSuccess) e = hipMemsetAsync(base + L.bar, 0, 64 * 4, st);
-    if (e == hipSuccess) e = hipMemsetAsync(base + L.err, 0, 4, st);
-    if (e == hipSuccess) e = hipMemsetAsync(base + L.done, 0, std::max<size_t>(tiles_h.size(), 1) * 4, st);
+    hipError_t e = hipMemsetAsync(cp(L.res), 0, (size_t)(2 * nres + 2) * 8, st);
+    if (e == hipSuccess) e = hipMemsetAsync(cp(L.bar), 0, 64 * 4, st);
+    if (e == hipSuccess) e = hipMemsetAsync(cp(L.err), 0, 4, st);
+    if (e == hipSuccess) e = hipMemsetAsync(cp(L.done), 0, std::max<size_t>(tiles_h.size(), 1) * 4, st);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("state reset: ") + hipGetErrorString(e));
     parity = 0;
     iters = 0;
@@ -613,11 +604,11 @@ od_status Grid::reset_state() {
 
 od_status Grid::init_field() {
     hipError_t e = launch_init(s, st, gdev, (int32_t)plan.chares.size(), cfg.seed, (int32_t)pb_face.size(),
-                               reinterpret_cast<const int32_t*>(base + L.pb_face),
-                               reinterpret_cast<const int32_t*>(base + L.pb_block),
-                               reinterpret_cast<const double*>(base + L.bc), !plan.multires);
+                               reinterpret_cast<const int32_t*>(cp(L.pb_face)),
+                               reinterpret_cast<const int32_t*>(cp(L.pb_block)),
+                               reinterpret_cast<const double*>(cp(L.bc)), !plan.multires);
     if (e == hipSuccess && plan.multires)
-        e = launch_init_cells(s, st, gdev, reinterpret_cast<const int32_t*>(base + L.ccell),
+        e = launch_init_cells(s, st, gdev, reinterpret_cast<const int32_t*>(cp(L.ccell)),
                               (int32_t)plan.chares.size(), cfg.seed);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("init: ") + hipGetErrorString(e));
     return OD_OK;
@@ -645,25 +636,19 @@ od_status Grid::ensure_pinned(size_t bytes) {
 
 // ---- sweeps ------------------------------------------------------------------
 
-unsigned long long* Grid::res_ptr() { return reinterpret_cast<unsigned long long*>(base + L.res); }
-
-const uint8_t* Grid::extra_row(int64_t step) const {
-    if (extra_h.empty()) return nullptr;
-    return reinterpret_cast<const uint8_t*>(base + L.extra) +
-           (size_t)(step % extra_period) * plan.chares.size();
-}
+unsigned long long* Grid::res_ptr() { return reinterpret_cast<unsigned long long*>(cp(L.res)); }
 
 od_status Grid::fused_one(hipStream_t s2, int par, int64_t step) {
     if (!segs_h.empty()) {
-        hipError_t e0 = launch_amr_fill(s, s2, base, reinterpret_cast<const BlockDev*>(base + L.blocks),
-                                        reinterpret_cast<const FillSeg*>(base + L.segs), (int32_t)segs_h.size(),
+        hipError_t e0 = launch_amr_fill(s, s2, base, reinterpret_cast<const BlockDev*>(cp(L.blocks)),
+                                        reinterpret_cast<const FillSeg*>(cp(L.segs)), (int32_t)segs_h.size(),
                                         fill_total, par);
         if (e0 != hipSuccess) return fail(OD_EHIP, std::string("ghost fill launch: ") + hipGetErrorString(e0));
     }
     hipError_t e = launch_sweep(s, plan.tile[0], plan.tile[1], s2, base,
-                                reinterpret_cast<const BlockDev*>(base + L.blocks),
-                                reinterpret_cast<const TileDev*>(base + L.tiles), (int32_t)tiles_h.size(), par,
-                                res_ptr(), 0, 1, extra_row(step), mode());
+                                reinterpret_cast<const BlockDev*>(cp(L.blocks)),
+                                reinterpret_cast<const TileDev*>(cp(L.tiles)), (int32_t)tiles_h.size(), par,
+                                res_ptr(), 0, 1, imb, step, mode());
     if (e != hipSuccess) return fail(OD_EHIP, std::string("sweep launch: ") + hipGetErrorString(e));
     return OD_OK;
 }
@@ -707,12 +692,11 @@ od_status Grid::graph_run(int64_t n) {
 od_status Grid::persistent_run(int64_t n) {
     if (grid_wgs <= 0) return fail(OD_EHIP, "persistent kernel: no co-resident workgroups");
     hipError_t e = launch_persistent(s, plan.tile[0], plan.tile[1], st, grid_wgs, base,
-                                     reinterpret_cast<const BlockDev*>(base + L.blocks),
-                                     reinterpret_cast<const TileDev*>(base + L.tiles), (int32_t)tiles_h.size(),
-                                     parity, n, res_ptr(), 1, reinterpret_cast<unsigned int*>(base + L.bar),
-                                     reinterpret_cast<unsigned int*>(base + L.err),
-                                     extra_h.empty() ? nullptr : reinterpret_cast<const uint8_t*>(base + L.extra),
-                                     extra_period, (int32_t)plan.chares.size(), iters, mode(),
+                                     reinterpret_cast<const BlockDev*>(cp(L.blocks)),
+                                     reinterpret_cast<const TileDev*>(cp(L.tiles)), (int32_t)tiles_h.size(),
+                                     parity, n, res_ptr(), 1, reinterpret_cast<unsigned int*>(cp(L.bar)),
+                                     reinterpret_cast<unsigned int*>(cp(L.err)),
+                                     imb, iters, mode(),
                                      persistent_dyn() ? 1 : 0,
                                      device_wait_ticks(cfg.wait_s > 0 ? cfg.wait_s : 10.0));
     if (e != hipSuccess) return fail(OD_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
@@ -738,38 +722,37 @@ od_status Grid::msgdriven_run(int64_t n) {
 }
 
 od_status Grid::msgdriven_launch(int64_t n) {
-    // target = iters + n ; the final-step residual slot (index 2) is cleared
+    // target = iters + n ; the final-step residual slots (2, 3) are cleared
     const int32_t tgt = (int32_t)(iters + n);
-    hipError_t e = hipMemcpyAsync(base + L.target, &tgt, 4, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemsetAsync(base + L.res + 16, 0, 16, st);
-    if (e != hipSuccess) return fail(OD_EHIP, std::string("msg setup: ") + hipGetErrorString(e));
     MsgArgs a{};
     a.arena = base;
-    a.blocks = reinterpret_cast<const BlockDev*>(base + L.blocks);
-    a.tiles = reinterpret_cast<const TileDev*>(base + L.tiles);
+    a.blocks = reinterpret_cast<const BlockDev*>(cp(L.blocks));
+    a.tiles = reinterpret_cast<const TileDev*>(cp(L.tiles));
     a.ntiles = (int32_t)tiles_h.size();
-    a.dep_ptr = reinterpret_cast<const int32_t*>(base + L.dep_ptr);
-    a.dep_idx = reinterpret_cast<const int32_t*>(base + L.dep_idx);
-    a.done = reinterpret_cast<int32_t*>(base + L.done);
-    a.target = reinterpret_cast<const int32_t*>(base + L.target);
+    a.dep_ptr = reinterpret_cast<const int32_t*>(cp(L.dep_ptr));
+    a.dep_idx = reinterpret_cast<const int32_t*>(cp(L.dep_idx));
+    a.done = reinterpret_cast<int32_t*>(cp(L.done));
+    a.target = reinterpret_cast<const int32_t*>(cp(L.target));
     a.tile_solve = nullptr;
     a.res = res_ptr() + 2;   // slot (final step & 1) of this 2-slot pair
-    a.err = reinterpret_cast<unsigned int*>(base + L.err);
-    a.extra = extra_h.empty() ? nullptr : reinterpret_cast<const uint8_t*>(base + L.extra);
-    a.extra_period = extra_period;
-    a.nchares = (int32_t)plan.chares.size();
+    a.err = reinterpret_cast<unsigned int*>(cp(L.err));
+    a.imb = imb;
     a.wait_ticks = device_wait_ticks(cfg.wait_s > 0 ? cfg.wait_s : 10.0);
     a.hints = mode();
-    a.xpub = reinterpret_cast<uint8_t*>(base + L.xpub);
+    a.seed = cfg.seed;
+    a.pert_ticks = (cfg.hints & kHintCheck) ? device_wait_ticks(20e-6) : 0;
+    a.xpub = reinterpret_cast<uint8_t*>(cp(L.xpub));
     a.tile_pos = nullptr;
-    a.bar = reinterpret_cast<unsigned int*>(base + L.bar);
-    a.pend = reinterpret_cast<int32_t*>(base + L.pend);
-    a.qslots = reinterpret_cast<unsigned long long*>(base + L.qslots);
+    a.bar = reinterpret_cast<unsigned int*>(cp(L.bar));
+    a.pend = reinterpret_cast<int32_t*>(cp(L.pend));
+    a.qslots = reinterpret_cast<unsigned long long*>(cp(L.qslots));
     a.pslots = a.qslots + (2 * tiles_h.size() + 8);
     a.ready = reinterpret_cast<int32_t*>(a.qslots);   // the cursor scheduler uses the ready-queue region
-    a.qhead = reinterpret_cast<unsigned int*>(base + L.qctl);
+    a.qhead = reinterpret_cast<unsigned int*>(cp(L.qctl));
     a.qsteps = (int32_t)n;
-    e = launch_queue_init(st, a);
+    // the init kernel stores the target step and clears the final-step
+    // residual pair (kernel arguments: nothing on the host outlives this call)
+    hipError_t e = launch_queue_init(st, a, tgt, reinterpret_cast<int32_t*>(cp(L.target)), res_ptr() + 2);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("queue init: ") + hipGetErrorString(e));
     e = launch_msgdriven(s, plan.tile[0], plan.tile[1], st, grid_wgs, a);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("msg-driven launch: ") + hipGetErrorString(e));
@@ -854,9 +837,9 @@ od_status Grid::per_chare_run(int64_t n) {
         for (int32_t c = 0; c < C && e == hipSuccess; ++c) {
             hipStream_t s2 = sp(c);
             const int32_t t0 = tile_lo[(size_t)c], t1 = tile_lo[(size_t)c + 1];
-            e = launch_sweep(s, plan.tile[0], plan.tile[1], s2, base, reinterpret_cast<const BlockDev*>(base + L.blocks),
-                             reinterpret_cast<const TileDev*>(base + L.tiles) + t0, t1 - t0, par, res_ptr(), c, c + 1,
-                             extra_row(iters), mode());
+            e = launch_sweep(s, plan.tile[0], plan.tile[1], s2, base, reinterpret_cast<const BlockDev*>(cp(L.blocks)),
+                             reinterpret_cast<const TileDev*>(cp(L.tiles)) + t0, t1 - t0, par, res_ptr(), c, c + 1,
+                             imb, iters, mode());
             if (e == hipSuccess) e = launch_pack_b(s, s2, base, blocks_h[(size_t)c], par ^ 1, face_out(c, par ^ 1));
             if (e == hipSuccess) e = hipEventRecord(packed[(size_t)c], s2);
         }
@@ -906,8 +889,12 @@ od_status Grid::device_error() {
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("sync: ") + hipGetErrorString(e));
     unsigned int err = 0;
-    e = hipMemcpy(&err, base + L.err, 4, hipMemcpyDeviceToHost);
+    e = hipMemcpy(&err, cp(L.err), 4, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("read error flag: ") + hipGetErrorString(e));
+    if (err & kErrSchedule)
+        return fail(OD_ESCHED, "message-driven schedule check failed: a tile's step counter did not advance by one, "
+                               "or a tile ran while a neighbour was not within one step (flag " +
+                                   std::to_string(err) + ")");
     if (err != 0) return fail(OD_ETIMEDOUT, "a device-side wait exceeded its bound (flag " + std::to_string(err) + ")");
     return OD_OK;
 }
@@ -921,7 +908,7 @@ od_status Grid::residual(double* r) {
         return OD_OK;
     }
     std::vector<unsigned long long> v((size_t)(2 * nres + 2));
-    e = hipMemcpy(v.data(), base + L.res, v.size() * 8, hipMemcpyDeviceToHost);
+    e = hipMemcpy(v.data(), cp(L.res), v.size() * 8, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("read residual: ") + hipGetErrorString(e));
     unsigned long long m = 0;
     if (msg_final) {

@@ -215,6 +215,8 @@ od_status od_plan(od_grid* g, od_plan_info* info) {
     info->bytes_per_iter = (int64_t)G.s * (2 * G.plan.interior + G.plan.halo_cells);
     for (int d = 0; d < 3; ++d) info->tile[d] = G.plan.tile[d];
     info->grid_wgs = G.grid_wgs;
+    info->field_bytes = (int64_t)G.L.ctrl_begin;
+    info->control_bytes = (int64_t)(G.L.total - G.L.ctrl_begin);
     return OD_OK;
 }
 
@@ -248,6 +250,15 @@ od_status od_chare_get(od_grid* g, int32_t c, od_block* out) {
     return OD_OK;
 }
 
+od_status od_extra_sweeps(od_grid* g, int64_t step, int32_t* out, int32_t n) {
+    if (!g || !out) return fail(OD_EINVAL, "NULL argument");
+    const Grid& G = g->g;
+    if (n != (int32_t)G.plan.chares.size()) return fail(OD_EINVAL, "n must equal the number of chares");
+    if (step < 0) return fail(OD_EINVAL, "step must be >= 0");
+    for (int32_t c = 0; c < n; ++c) out[c] = od::imb_extra(G.imb, step, c);
+    return OD_OK;
+}
+
 od_status od_destroy(od_grid* g) {
     if (!g) return OD_OK;
     hipError_t e = g->g.base ? hipStreamSynchronize(g->g.st) : hipSuccess;
@@ -256,29 +267,40 @@ od_status od_destroy(od_grid* g) {
     return OD_OK;
 }
 
-od_status od_stream_copy(void* hip_stream, void* dst, const void* src, size_t bytes, int32_t iters, double* seconds) {
-    if (!dst || !src || !seconds || iters < 1 || bytes % 16 != 0 || bytes == 0)
-        return fail(OD_EINVAL, "need non-NULL buffers, bytes a positive multiple of 16, iters >= 1");
+od_status od_stream_bench(void* hip_stream, void* dst, const void* src, size_t bytes, int32_t iters, int32_t kind,
+                          double* seconds, int32_t* variant) {
+    if (!dst || !src || !seconds || iters < 1 || bytes % 16 != 0 || bytes == 0 || kind < 0 || kind > 2)
+        return fail(OD_EINVAL, "need non-NULL buffers, bytes a positive multiple of 16, iters >= 1, kind 0..2");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    uint32_t* sink = static_cast<uint32_t*>(dst);
     hipEvent_t a = nullptr, b = nullptr;
     hipError_t e = hipEventCreate(&a);
     if (e == hipSuccess) e = hipEventCreate(&b);
     double best = 1e30;
+    int32_t best_v = -1;
     for (int v = 0; v < od::copy_variant_count() && e == hipSuccess; ++v) {
-        e = od::launch_copy(st, dst, src, bytes, v);   // warm-up
+        e = od::launch_stream(st, dst, src, bytes, v, kind, sink);   // warm-up
         if (e == hipSuccess) e = hipEventRecord(a, st);
-        for (int32_t i = 0; i < iters && e == hipSuccess; ++i) e = od::launch_copy(st, dst, src, bytes, v);
+        for (int32_t i = 0; i < iters && e == hipSuccess; ++i) e = od::launch_stream(st, dst, src, bytes, v, kind, sink);
         if (e == hipSuccess) e = hipEventRecord(b, st);
         if (e == hipSuccess) e = hipEventSynchronize(b);
         float ms = 0;
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-        if (e == hipSuccess) best = std::min(best, ms * 1e-3);
+        if (e == hipSuccess && ms * 1e-3 < best) {
+            best = ms * 1e-3;
+            best_v = v;
+        }
     }
     if (a) hipEventDestroy(a);
     if (b) hipEventDestroy(b);
-    if (e != hipSuccess) return fail(OD_EHIP, std::string("stream copy: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("stream bench: ") + hipGetErrorString(e));
     *seconds = best;
+    if (variant) *variant = best_v;
     return OD_OK;
+}
+
+od_status od_stream_copy(void* hip_stream, void* dst, const void* src, size_t bytes, int32_t iters, double* seconds) {
+    return od_stream_bench(hip_stream, dst, src, bytes, iters, 0, seconds, nullptr);
 }
 
 od_status od_time_iterate(od_grid* g, int64_t n, double* seconds) {

@@ -21,7 +21,11 @@ uint64_t host_sm64(uint64_t seed, uint64_t idx);
 struct Layout {
     size_t blocks = 0, tiles = 0, cidx[3] = {0, 0, 0}, owner = 0, corigin = 0, dir_pb = 0;
     size_t pb_face = 0, pb_block = 0, bc = 0, res = 0, bar = 0, err = 0, done = 0, target = 0;
-    size_t dep_ptr = 0, dep_idx = 0, extra = 0, field_end = 0, total = 0;
+    size_t dep_ptr = 0, dep_idx = 0, field_end = 0, total = 0;
+    // [0, field_end): field storage (chares, face pseudo-blocks, messages),
+    // addressed from Grid::base; [ctrl_begin, total): descriptors and
+    // device state, addressed through Grid::cp (ctrl_begin == field_end)
+    size_t ctrl_begin = 0;
     size_t ccell = 0, segs = 0, xpub = 0;
     size_t pend = 0, qslots = 0, qctl = 0;   // message-driven dependency counters and XCD queues
 };
@@ -47,11 +51,10 @@ struct Grid {
     std::vector<FillSeg> segs_h;     // multi-resolution ghost fill rectangles
     int64_t fill_total = 0;          // ghost cells filled per iteration
     std::vector<int32_t> dep_ptr, dep_idx;
-    std::vector<uint8_t> extra_h;
-    int32_t extra_period = 1;
+    ImbDev imb{};                    // load-imbalance draw (heavy == 0: none)
     // the persistent form takes tiles from counters (imbalance or uneven
     // blocks) rather than by a fixed stride
-    bool persistent_dyn() const { return !extra_h.empty() || !plan.regular; }
+    bool persistent_dyn() const { return imb.heavy > 0 || !plan.regular; }
     // cooperative-kernel kind for persistent_max_grid
     int coop_kind() const { return cfg.exec == OD_MSGDRIVEN ? 1 : (persistent_dyn() ? 2 : 0); }
     std::vector<MsgBufs> msg;
@@ -61,8 +64,13 @@ struct Grid {
     // device state
     hipStream_t st = nullptr;
     hipStream_t cap_st = nullptr;
-    char* base = nullptr;
+    char* base = nullptr;            // field storage
+    char* ctrl = nullptr;            // control regions (L.ctrl_begin maps here)
     size_t ws_bytes = 0;
+    // build_layout reserves descriptor room for every autotune candidate's
+    // tiles (false: only the planned tiles)
+    bool tune_room = true;
+    char* cp(size_t off) const { return ctrl + (off - L.ctrl_begin); }
     GridDev gdev{};
     int parity = 0;
     int64_t iters = 0;
@@ -88,7 +96,6 @@ struct Grid {
     od_status init_field();
     od_status ensure_pinned(size_t bytes);
     unsigned long long* res_ptr();
-    const uint8_t* extra_row(int64_t step) const;
     od_status fused_one(hipStream_t s2, int par, int64_t step);
     od_status graph_run(int64_t n);
     od_status persistent_run(int64_t n);

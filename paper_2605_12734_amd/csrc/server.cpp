@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -76,7 +77,7 @@ struct Request {
     size_t bytes = 0;
     int32_t state = OD_REQ_QUEUED;
     int32_t slot = -1;
-    double t_submit = 0, t_admit = 0, t_done = 0;
+    double t_arrival = 0, t_submit = 0, t_admit = 0, t_done = 0;
     int64_t iters = 0;
     double residual = 0;
     std::unique_ptr<Grid> grid;
@@ -120,6 +121,10 @@ struct Server {
     std::vector<uint64_t> slot_ticket;
     uint64_t next_ticket = 1;
     int32_t grid_cap = 0;
+    // od_server_set_hints: kernel hints of later epochs (bit 2: schedule
+    // check) and the seed of the schedule perturbation
+    std::atomic<int32_t> hints{0};
+    std::atomic<uint64_t> check_seed{12734};
     std::string fatal;
     od_server_stats stats{};          // guarded by mu
 
@@ -426,6 +431,9 @@ void Server::run() {
         a.pslots = a.qslots + (2 * list.size() + 8);
         a.ready = reinterpret_cast<int32_t*>(a.qslots);   // cursor mode: ready words in the ready-queue region
         a.qhead = reinterpret_cast<unsigned int*>(arena + c_qctl);
+        a.hints = hints.load() & kHintCheck;
+        a.seed = check_seed.load();
+        a.pert_ticks = (a.hints & kHintCheck) ? device_wait_ticks(20e-6) : 0;
         int grid = std::min<int>(grid_cap, (int)list.size());
         if (grid >= kNumXcd) grid -= grid % kNumXcd;
         if (e == hipSuccess) e = launch_queue_init(st, a);
@@ -476,7 +484,9 @@ void Server::run() {
         if (e != hipSuccess || derr != 0) {
             std::lock_guard<std::mutex> lk(mu);
             fatal = e != hipSuccess ? std::string("serving epoch: ") + hipGetErrorString(e)
-                                    : "serving epoch: a device-side wait exceeded its bound";
+                    : (derr & kErrSchedule) ? "serving epoch: schedule check failed (a tile's step counter did not "
+                                              "advance by one, or a tile ran while a neighbour was not within one step)"
+                                            : "serving epoch: a device-side wait exceeded its bound";
             for (Request* R : active) {
                 R->state = OD_REQ_CANCELED;
                 slot_ticket[(size_t)R->slot] = 0;
@@ -592,6 +602,7 @@ od_status validate_request(const od_request* r) {
     if (r->odf < 1) return fail(OD_EINVAL, "request odf must be >= 1");
     if (r->max_iters < 1 || r->max_iters > INT32_MAX) return fail(OD_EINVAL, "request max_iters must be in [1, 2^31)");
     if (r->check_every < 0) return fail(OD_EINVAL, "request check_every must be >= 0");
+    if (!(r->t_arrival >= 0.0)) return fail(OD_EINVAL, "request t_arrival must be >= 0 (0 = submit time)");
     return OD_OK;
 }
 
@@ -707,6 +718,9 @@ od_status od_submit(od_server* sv, const od_request* req, uint64_t* ticket) {
         R->bytes = bytes;
         R->grid = std::move(G);
         R->t_submit = od::now_s();
+        R->t_arrival = req->t_arrival > 0.0 ? req->t_arrival : R->t_submit;
+        if (R->t_arrival > R->t_submit)
+            return fail(OD_EINVAL, "request t_arrival lies in the future of the monotonic clock");
         std::lock_guard<std::mutex> lk(S.mu);
         if (!S.fatal.empty()) return fail(OD_ECANCELED, S.fatal);
         if (bytes > S.arena_bytes - S.data_begin)
@@ -724,6 +738,14 @@ od_status od_submit(od_server* sv, const od_request* req, uint64_t* ticket) {
     } catch (...) {
         return fail(OD_EINVAL, "internal error");
     }
+}
+
+od_status od_server_set_hints(od_server* sv, int32_t hints, uint64_t seed) {
+    if (!sv) return fail(OD_EINVAL, "server is NULL");
+    if (hints & ~od::kHintCheck) return fail(OD_EINVAL, "serving hints: only bit 2 (schedule check) is defined");
+    sv->s.check_seed.store(seed);
+    sv->s.hints.store(hints);
+    return OD_OK;
 }
 
 od_status od_server_step(od_server* sv, int32_t* active, int32_t* queued) {
@@ -759,6 +781,7 @@ od_status od_poll(od_server* sv, uint64_t ticket, od_info* out) {
     out->t_submit = R.t_submit;
     out->t_admit = R.t_admit;
     out->t_done = R.t_done;
+    out->t_arrival = R.t_arrival;
     if (R.state == OD_REQ_DONE) return OD_OK;
     if (R.state == OD_REQ_CANCELED) return fail(OD_ECANCELED, S.fatal.empty() ? "request cancelled" : S.fatal);
     return OD_ENOTREADY;

@@ -96,7 +96,7 @@ od_status Grid::retile(const int32_t tile[3]) {
         fill_tile_descs(*this);
         return fail(OD_EINVAL, e);
     }
-    hipError_t he = hipMemcpyAsync(base + L.tiles, tiles_h.data(), tiles_h.size() * sizeof(TileDev),
+    hipError_t he = hipMemcpyAsync(cp(L.tiles), tiles_h.data(), tiles_h.size() * sizeof(TileDev),
                                    hipMemcpyHostToDevice, st);
     if (he == hipSuccess) he = hipStreamSynchronize(st);
     if (he != hipSuccess) return fail(OD_EHIP, std::string("tile upload: ") + hipGetErrorString(he));
@@ -132,7 +132,7 @@ od_status autotune(Grid& G, int32_t iters, int32_t out_tile[3]) {
     if (he != hipSuccess) return fail(OD_EHIP, std::string("sync: ") + hipGetErrorString(he));
     // keep the residual slots: tuning launches overwrite them
     std::vector<unsigned long long> saved((size_t)(2 * G.nres + 2));
-    he = hipMemcpy(saved.data(), G.base + G.L.res, saved.size() * 8, hipMemcpyDeviceToHost);
+    he = hipMemcpy(saved.data(), G.cp(G.L.res), saved.size() * 8, hipMemcpyDeviceToHost);
     if (he != hipSuccess) return fail(OD_EHIP, std::string("save residual: ") + hipGetErrorString(he));
 
     int32_t emax[3] = {1, 1, 1};
@@ -169,9 +169,9 @@ od_status autotune(Grid& G, int32_t iters, int32_t out_tile[3]) {
         if (G.retile(c.data()) != OD_OK) continue;   // e.g. over the tile capacity
         auto launch = [&]() {
             return launch_sweep(G.s, G.plan.tile[0], G.plan.tile[1], G.st, G.base,
-                                reinterpret_cast<const BlockDev*>(G.base + G.L.blocks),
-                                reinterpret_cast<const TileDev*>(G.base + G.L.tiles), (int32_t)G.tiles_h.size(),
-                                G.parity, G.res_ptr(), 0, 1, nullptr, G.mode());
+                                reinterpret_cast<const BlockDev*>(G.cp(G.L.blocks)),
+                                reinterpret_cast<const TileDev*>(G.cp(G.L.tiles)), (int32_t)G.tiles_h.size(),
+                                G.parity, G.res_ptr(), 0, 1, ImbDev{}, 0, G.mode());
         };
         he = launch();   // warm-up
         if (he == hipSuccess) he = hipEventRecord(a, G.st);
@@ -197,7 +197,7 @@ od_status autotune(Grid& G, int32_t iters, int32_t out_tile[3]) {
     }
     st = G.retile(best.data());
     if (st != OD_OK) return st;
-    he = hipMemcpy(G.base + G.L.res, saved.data(), saved.size() * 8, hipMemcpyHostToDevice);
+    he = hipMemcpy(G.cp(G.L.res), saved.data(), saved.size() * 8, hipMemcpyHostToDevice);
     if (he != hipSuccess) return fail(OD_EHIP, std::string("restore residual: ") + hipGetErrorString(he));
     {
         std::lock_guard<std::mutex> lk(g_cache_mu);

@@ -18,7 +18,9 @@ DEFAULT_BC = (1.0, 0.0, 0.0, 0.0, 0.0, 0.0)
 
 
 def make_request(n: int, dtype: str = "f64", odf: int = 1, tol: float = 1e-6, max_iters: int = 2000,
-                 check_every: int = 10, seed: int = 12734, bc=DEFAULT_BC) -> B.od_request:
+                 check_every: int = 10, seed: int = 12734, bc=DEFAULT_BC, t_arrival: float = 0.0) -> B.od_request:
+    """t_arrival: arrival time on time.monotonic()'s clock (CLOCK_MONOTONIC,
+    the server's clock); 0 = the submit time."""
     r = B.od_request()
     r.n = int(n)
     r.dtype = B.OD_F64 if dtype in ("f64", np.float64) else B.OD_F32
@@ -29,6 +31,7 @@ def make_request(n: int, dtype: str = "f64", odf: int = 1, tol: float = 1e-6, ma
     r.seed = int(seed) & (2**64 - 1)
     for i in range(6):
         r.bc[i] = float(bc[i])
+    r.t_arrival = float(t_arrival)
     return r
 
 
@@ -76,7 +79,8 @@ class Server:
             return None
         check(s, "od_poll")
         return {"state": STATES.get(info.state, info.state), "iters": info.iters, "residual": info.residual,
-                "t_submit": info.t_submit, "t_admit": info.t_admit, "t_done": info.t_done}
+                "t_arrival": info.t_arrival, "t_submit": info.t_submit, "t_admit": info.t_admit,
+                "t_done": info.t_done}
 
     def wait(self, ticket: int, timeout: float = 120.0, interval: float = 1e-3) -> dict:
         t0 = time.monotonic()
@@ -94,6 +98,10 @@ class Server:
         check(lib().od_fetch(self.h, int(ticket), out.ctypes.data, out.nbytes), "od_fetch")
         del self.meta[ticket]
         return out
+
+    def set_hints(self, hints: int, seed: int = 12734) -> None:
+        """Kernel hints of later scheduling epochs (4: schedule check)."""
+        check(lib().od_server_set_hints(self.h, int(hints), int(seed) & (2**64 - 1)), "od_server_set_hints")
 
     def counts(self) -> tuple:
         a, q = ctypes.c_int32(), ctypes.c_int32()

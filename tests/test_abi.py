@@ -96,6 +96,22 @@ def test_launch_overlap_host_checks():
     res = B.od_overlap_result()
     assert L.od_launch_overlap(None, 0, 10, 1, 1, 1, ctypes.byref(res)) == -22
     assert L.od_launch_overlap(ctypes.c_void_p(256), 1 << 20, 10, 11, 1, 1, ctypes.byref(res)) == -22
-    n, r = ctypes.c_int64(), ctypes.c_double()
-    assert L.od_launch_rate(0, 1, 0.1, ctypes.byref(n), ctypes.byref(r)) == -22
-    assert L.od_launch_rate(1, 1, 0.0, ctypes.byref(n), ctypes.byref(r)) == -22
+
+
+def test_request_arrival_stamp():
+    # the arrival stamp is part of the request record and is checked on the
+    # host (od_request_bytes validates without a server or a GPU)
+    from paper_2605_12734_amd import _binding as B
+    from paper_2605_12734_amd.serving import make_request
+    names = [f for f, _ in B.od_request._fields_]
+    assert names[-1] == "t_arrival" and B.od_request.t_arrival.offset == 96
+    assert [f for f, _ in B.od_info._fields_][-1] == "t_arrival"
+    L = B.lib()
+    out = ctypes.c_size_t()
+    r = make_request(16, "f64", odf=8, t_arrival=-1.0)
+    assert L.od_request_bytes(ctypes.byref(r), ctypes.byref(out)) == -22
+    r = make_request(16, "f64", odf=8, t_arrival=float("nan"))
+    assert L.od_request_bytes(ctypes.byref(r), ctypes.byref(out)) == -22
+    r = make_request(16, "f64", odf=8, t_arrival=12.5)
+    assert L.od_request_bytes(ctypes.byref(r), ctypes.byref(out)) == 0 and out.value > 0
+

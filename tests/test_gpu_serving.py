@@ -40,13 +40,20 @@ def _check(res, field, req):
 
 def test_mix_matches_oracle_and_alone():
     with Server(arena_bytes=512 << 20, max_slots=16) as srv:
-        tickets = [srv.submit(**q) for q in MIX]
+        # odd requests carry an arrival stamp taken before submission; the
+        # others arrive at their submit time
+        t_arr = time.monotonic() - 0.25
+        tickets = [srv.submit(**q, t_arrival=t_arr if i % 2 else 0.0) for i, q in enumerate(MIX)]
         mixed = []
-        for t, q in zip(tickets, MIX):
+        for i, (t, q) in enumerate(zip(tickets, MIX)):
             res = srv.wait(t)
             field = srv.fetch(t)
             _check(res, field, q)
-            assert res["t_submit"] <= res["t_admit"] <= res["t_done"]
+            assert res["t_arrival"] <= res["t_submit"] <= res["t_admit"] <= res["t_done"]
+            if i % 2:
+                assert res["t_arrival"] == t_arr
+            else:
+                assert res["t_arrival"] == res["t_submit"]
             mixed.append((res, field))
     # each request alone on a fresh server gives the same bits
     for q, (res_m, field_m) in zip(MIX[:3], mixed[:3]):

@@ -186,3 +186,53 @@ def test_msgdriven_groups_under_imbalance(odf, split):
             assert all(len(s) == odf for s in per_group)
         else:
             assert all(len(s) <= max(1, odf // 8) + 1 for s in per_group)
+
+
+def _llround(x):
+    return int(np.floor(x + 0.5))
+
+
+@pytest.mark.parametrize("n,odf", [(64, 8), (96, 27), (256, 4096), (1024, 32768)])
+def test_imbalance_draw_exact_count_every_step(n, odf):
+    # 10 % of the chares, drawn afresh at every step, each re-running its
+    # sweep 1..4 extra times
+    steps = range(0, 160)
+    D = od.imbalance_draw(steps, n=n, odf=odf, exec="persistent", imbalance_pct=10, imbalance_max_extra=4)
+    C = D.shape[1]
+    assert C == odf
+    m = _llround(0.1 * C)
+    assert ((D > 0).sum(axis=1) == m).all()
+    assert D.min() >= 0 and D.max() <= 4
+    if m * 160 >= 200:
+        assert set(np.unique(D[D > 0])) == {1, 2, 3, 4}
+    heavy = D > 0
+    if C >= 64:
+        # not a table with a short period: the set changes step to step and
+        # does not repeat 64 steps later
+        for t in range(0, 96):
+            assert not np.array_equal(heavy[t], heavy[t + 1])
+            assert not np.array_equal(heavy[t], heavy[t + 64])
+
+
+def test_imbalance_order_is_a_permutation():
+    # for every count h, exactly h chares are drawn: the per-step order is a
+    # bijection of the chare ids (27 chares: pct 0..100 reaches every h)
+    for pct in range(0, 101):
+        D = od.imbalance_draw(range(0, 12), n=96, odf=27, exec="persistent", imbalance_pct=pct,
+                              imbalance_max_extra=3)
+        assert ((D > 0).sum(axis=1) == _llround(pct / 100 * 27)).all()
+
+
+def test_imbalance_draw_frequency_and_seed():
+    # each chare is drawn with frequency ~ p over many steps; another seed
+    # gives another draw; no imbalance gives zeros
+    D = od.imbalance_draw(range(0, 4000), n=64, odf=64, exec="persistent", imbalance_pct=10,
+                          imbalance_max_extra=4)
+    f = (D > 0).mean(axis=0)
+    assert abs(f.mean() - 6 / 64) < 1e-12
+    assert f.min() > 0.05 and f.max() < 0.14
+    E = od.imbalance_draw(range(0, 50), n=64, odf=64, exec="persistent", imbalance_pct=10,
+                          imbalance_max_extra=4, seed=7)
+    assert not np.array_equal(D[:50], E)
+    Z = od.imbalance_draw(range(0, 5), n=64, odf=64, exec="persistent")
+    assert not Z.any()
