@@ -124,7 +124,8 @@ typedef struct {
      * run, and every task checks that each tile it reads halos from is
      * within one step of it (a failure raises the error flag: reads then
      * return OD_ESCHED).  Every message-driven task also checks, in any
-     * mode, that its tile's step counter advances by exactly one.
+     * mode, that its tile's step counter advances by exactly one;
+     * bit 3 (OD_PERSISTENT): record the timeline read by od_timeline.
      * Other bits are ignored. */
     int32_t hints;
     /* 7 (or 0): 3D 7-point stencil.  5: the 2D 5-point stencil of the
@@ -259,6 +260,15 @@ typedef struct {
     int32_t src_kind[6], src[6], src_origin[6][3];
 } od_tile_info;
 od_status od_tile_info_get(struct od_grid* g, int32_t t, od_tile_info* out);
+
+/* Timeline of the last od_iterate of an OD_PERSISTENT grid created with
+ * hints bit 3, for its first min(n, 1024, max_iters) iterations: out[4*i + k]
+ * = microseconds (device wall clock) from the first workgroup's start of
+ * iteration 0 to, for iteration i: k = 0 the first and k = 1 the last
+ * workgroup starting it (leaving the previous barrier), k = 2 the first and
+ * k = 3 the last workgroup finishing its tiles (arriving at the barrier).
+ * *n_iters = iterations reported.  Syncs; OD_EINVAL for other grids. */
+od_status od_timeline(struct od_grid* g, double* out, int32_t max_iters, int32_t* n_iters);
 
 /* The load-imbalance draw of step `step` (0-based count of iterations since
  * od_create): out[c] = extra re-runs of chare c's sweep, for the n ==

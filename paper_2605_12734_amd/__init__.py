@@ -266,6 +266,16 @@ class Grid:
     def tiles(self) -> list:
         return tile_infos(self.h, self.plan()["ntiles"])
 
+    def timeline(self, max_iters: int = 1024) -> np.ndarray:
+        """Persistent grids created with hints bit 3: per iteration of the last
+        od_iterate, microseconds to the first / last workgroup start and the
+        first / last finish of its tiles (rows of 4)."""
+        out = np.zeros((max_iters, 4), dtype=np.float64)
+        n = ctypes.c_int32()
+        check(lib().od_timeline(self.h, out.ctypes.data_as(ctypes.c_void_p), int(max_iters), ctypes.byref(n)),
+              "od_timeline")
+        return out[: n.value]
+
     def autotune(self, iters: int = 3) -> tuple:
         t = (ctypes.c_int32 * 3)()
         check(lib().od_autotune(self.h, int(iters), t), "od_autotune")

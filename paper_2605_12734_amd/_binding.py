@@ -90,6 +90,7 @@ SIGNATURES = {
     "od_plan": (ctypes.c_int, [c_vp, ctypes.POINTER(od_plan_info)]),
     "od_tile_info_get": (ctypes.c_int, [c_vp, c_i32, ctypes.POINTER(od_tile_info)]),
     "od_chare_get": (ctypes.c_int, [c_vp, c_i32, ctypes.POINTER(od_block)]),
+    "od_timeline": (ctypes.c_int, [c_vp, c_vp, c_i32, ctypes.POINTER(c_i32)]),
     "od_extra_sweeps": (ctypes.c_int, [c_vp, c_i64, c_vp, c_i32]),
     "od_destroy": (ctypes.c_int, [c_vp]),
     "od_stream_copy": (ctypes.c_int, [c_vp, c_vp, c_vp, c_sz, c_i32, ctypes.POINTER(c_dbl)]),
@@ -131,6 +132,14 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run python paper_2605_12734_amd/build.py (hipcc, gfx950)")
+    # libod links the HIP runtime by its soname; PyTorch loads its own copy
+    # of that runtime by path.  Load PyTorch first so the dynamic linker
+    # binds libod to the same runtime: two HIP runtimes in one process do
+    # not share the device (the second finds no device).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(L, name)

@@ -459,7 +459,7 @@ __global__ void __launch_bounds__((TX / V16<T>::N) * TY)
 k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDev* __restrict__ tiles,
              int32_t ntiles, int parity, int64_t iters, unsigned long long* __restrict__ res, int32_t nres,
              unsigned int* bar, unsigned int* err, const ImbDev imb, int64_t iter_base, int64_t wait_ticks,
-             int hints) {
+             int hints, unsigned long long* __restrict__ stamps) {
     using S = SW<T, TX, TY>;
     __shared__ T lds[S::LDS];
     __shared__ T red[S::NT / 64];
@@ -489,6 +489,14 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
     }
     for (int64_t it = 0; it < iters; ++it) {
         const int p = parity ^ (int)(it & 1);
+        // timeline (stamps != null): first and last workgroup to start
+        // iteration it, first and last to finish its tiles
+        const bool stamp = stamps && it < kStampIters && threadIdx.x == 0;
+        if (stamp) {
+            const unsigned long long t0 = (unsigned long long)wall_clock64();
+            atomicMin(&stamps[4 * it + 0], t0);
+            atomicMax(&stamps[4 * it + 1], t0);
+        }
         if (blockIdx.x == 0)
             for (int s = (int)threadIdx.x; s < nres; s += S::NT) res[2 * s + p] = 0ull;
         T r = 0;
@@ -510,7 +518,8 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
             if (DYN && threadIdx.x == 0)
                 nxt = (int32_t)__hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const TileDev& t = tiles[ti];
-            const int reps = 1 + imb_extra(imb, iter_base + it, t.blk);
+            // (the static list's balanced last round may hold empty entries)
+            const int reps = t.nz > 0 ? 1 + imb_extra(imb, iter_base + it, t.blk) : 0;
             T rr = 0;
             for (int rep = 0; rep < reps; ++rep) rr = sweep_tile<T, TX, TY>(arena, blocks, t, p, lds, hints);
             if (slot >= 0 && slot != t.rslot) {
@@ -528,6 +537,11 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
             idx = nxt;
         }
         if (slot >= 0) wg_residual<T, S::NT>(r, &res[2 * slot + (p ^ 1)], red);
+        if (stamp) {
+            const unsigned long long t1 = (unsigned long long)wall_clock64();
+            atomicMin(&stamps[4 * it + 2], t1);
+            atomicMax(&stamps[4 * it + 3], t1);
+        }
         if (it + 1 < iters) {
             // the last arrival clears the counters of the step after next
             if (!xcd_barrier(bar, err, wait_ticks, &bar[8 + 8 * (int)((it + 1) & 1)], s_xcd, s_xwgs, s_nxcd))
@@ -1362,14 +1376,14 @@ hipError_t launch_persistent(int dtype_bytes, int tx, int ty, hipStream_t st, in
                              const BlockDev* blocks, const TileDev* tiles, int32_t ntiles, int parity,
                              int64_t iters, unsigned long long* res, int32_t nres, unsigned int* bar,
                              unsigned int* err, const ImbDev& imb, int64_t iter_base, int hints, int dyn,
-                             int64_t wait_ticks) {
+                             int64_t wait_ticks, unsigned long long* stamps) {
     if (iters <= 0) return hipSuccess;
 #define OD_LAUNCH(T, TX, TY)                                                                          \
     if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                      \
         T* ar = reinterpret_cast<T*>(arena);                                                          \
         ImbDev im = imb;                                                                              \
         void* args[] = {&ar, &blocks, &tiles, &ntiles, &parity, &iters, &res, &nres, &bar, &err,      \
-                        &im, &iter_base, &wait_ticks, &hints};                                        \
+                        &im, &iter_base, &wait_ticks, &hints, &stamps};                               \
         const void* fn = dyn ? reinterpret_cast<const void*>(k_persistent<T, TX, TY, true>)           \
                              : reinterpret_cast<const void*>(k_persistent<T, TX, TY, false>);         \
         return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(SW<T, TX, TY>::NT), args, 0, st);      \
@@ -1410,6 +1424,16 @@ hipError_t launch_msgdriven(int dtype_bytes, int tx, int ty, hipStream_t st, int
     OD_VARIANTS_F32(OD_LAUNCH)
 #undef OD_LAUNCH
     return hipErrorInvalidValue;
+}
+
+__global__ void k_stamp_init(unsigned long long* stamps, int32_t n) {
+    const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < 4 * n) stamps[i] = (i & 1) ? 0ull : ~0ull;   // minima start high, maxima low
+}
+
+hipError_t launch_stamp_init(hipStream_t st, unsigned long long* stamps, int32_t n) {
+    hipLaunchKernelGGL(k_stamp_init, dim3((unsigned)((4 * n + 255) / 256)), dim3(256), 0, st, stamps, n);
+    return hipGetLastError();
 }
 
 __global__ void k_queue_init(MsgArgs a, int32_t target, int32_t* target_word, unsigned long long* res_clear) {

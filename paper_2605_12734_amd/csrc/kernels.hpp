@@ -118,12 +118,19 @@ hipError_t launch_sweep(int dtype_bytes, int tx, int ty, hipStream_t st, void* a
 // workgroups' results (the XCD's workgroups share that L2).  `err` = error
 // flag.  `imb`: load-imbalance draw, iteration `it` of the launch is step
 // iter_base + it.
+// `stamps` (may be null): timeline of the first kStampIters iterations, 4
+// wall-clock words per iteration (first / last workgroup to start it,
+// first / last to finish its tiles), prepared by launch_stamp_init.
+constexpr int kStampIters = 1024;
 hipError_t launch_persistent(int dtype_bytes, int tx, int ty, hipStream_t st, int grid,
                              void* arena, const BlockDev* blocks, const TileDev* tiles,
                              int32_t ntiles, int parity, int64_t iters,
                              unsigned long long* res, int32_t nres, unsigned int* bar,
                              unsigned int* err, const ImbDev& imb, int64_t iter_base, int hints, int dyn,
-                             int64_t wait_ticks);
+                             int64_t wait_ticks, unsigned long long* stamps = nullptr);
+hipError_t launch_stamp_init(hipStream_t st, unsigned long long* stamps, int32_t n);
+// hints bit 3 (persistent form): record the timeline above.
+constexpr int kHintTimeline = 8;
 // Wall-clock ticks in `seconds` (bound of every device-side wait).
 int64_t device_wait_ticks(double seconds = 10.0);
 // Max co-resident workgroups of a cooperative kernel: kind 0 = persistent

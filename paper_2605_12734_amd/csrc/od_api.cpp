@@ -413,6 +413,9 @@ std::string build_layout(const od_config& cfg, Grid& G) {
         }
         G.tile_cap = std::max(ntiles, cap);
     }
+    // the persistent form's balanced last round adds up to two entries per
+    // workgroup (balance_last_round); cooperative grids stay below 8192
+    if (cfg.exec == OD_PERSISTENT) G.tile_cap += 2 * 8192;
     G.L.tiles = cv.take(G.tile_cap * sizeof(TileDev));
     for (int d = 0; d < 3; ++d) G.L.cidx[d] = cv.take((size_t)(p.regular ? p.n[d] : 1) * 4);
     G.L.owner = cv.take((p.regular ? 1 : p.owner.size()) * 4);
@@ -445,6 +448,7 @@ std::string build_layout(const od_config& cfg, Grid& G) {
         G.L.qslots = cv.take(2 * (2 * ntiles + 8) * 8);   // ready queues, then cross lists
         G.L.qctl = cv.take(64 * 4);
     }
+    G.L.stamps = cv.take(cfg.exec == OD_PERSISTENT ? (size_t)4 * kStampIters * 8 : 8);
     G.L.dep_ptr = cv.take((G.dep_ptr.size() + 1) * 4);
     G.L.dep_idx = cv.take((G.dep_idx.size() + 1) * 4);
     G.L.segs = cv.take(std::max<size_t>(G.segs_h.size(), 1) * sizeof(FillSeg));
@@ -528,6 +532,108 @@ std::string build_tile_deps(const Plan& p, std::vector<int32_t>& ptr, std::vecto
         }
     }
     return "";
+}
+
+// Persistent form with the static stride: workgroup w sweeps list entries
+// w, w + G, w + 2G, ...  With T tiles and G workgroups, T mod G tiles are
+// left for a last round that only some workgroups run while the others
+// wait at the barrier.  Instead, the planes of those tiles are shared out
+// evenly: within each XCD group g (list positions and workgroups = g mod 8),
+// the remaining tiles' planes are cut into G/8 contiguous runs, one per
+// workgroup, each run covering at most two z-ranges of tiles (sub-tiles:
+// the same box cut along z, the cut faces reading the tile's own planes).
+// The list becomes R full rounds plus two entries per workgroup (the second
+// may be empty, nz = 0).  Sub-tiles compute the same expression at every
+// point, so results are unchanged.
+std::vector<TileHost> balance_last_round(const Plan& p, const std::vector<TileHost>& tiles, int32_t G) {
+    const size_t T = tiles.size();
+    if (G < kNumXcd || G % kNumXcd != 0 || T % (size_t)G == 0) return tiles;
+    const size_t R = T / (size_t)G;
+    const int32_t W = G / kNumXcd;
+    std::vector<TileHost> out(tiles.begin(), tiles.begin() + (std::ptrdiff_t)(R * (size_t)G));
+    out.resize((R + 2) * (size_t)G);
+    auto empty_of = [&](const TileHost& t) {
+        TileHost e = t;
+        e.e[2] = 0;
+        return e;
+    };
+    auto sub = [&](const TileHost& t, int32_t za, int32_t zb) {
+        const Chare& c = p.chares[(size_t)t.chare];
+        TileHost u = t;
+        u.o[2] = t.o[2] + za;
+        u.e[2] = zb - za;
+        for (int f = 0; f < 4; ++f) u.g[f][2] = t.g[f][2] + za;
+        if (za > 0) {   // z- slab: the tile's own plane below
+            u.kind[4] = 2;
+            u.src[4] = t.chare;
+            u.g[4][0] = c.o[0] + t.o[0];
+            u.g[4][1] = c.o[1] + t.o[1];
+            u.g[4][2] = c.o[2] + u.o[2] - 1;
+        }
+        if (zb < t.e[2]) {   // z+ slab: the tile's own plane above
+            u.kind[5] = 2;
+            u.src[5] = t.chare;
+            u.g[5][0] = c.o[0] + t.o[0];
+            u.g[5][1] = c.o[1] + t.o[1];
+            u.g[5][2] = c.o[2] + u.o[2] + u.e[2];
+        }
+        return u;
+    };
+    for (int32_t g = 0; g < kNumXcd; ++g) {
+        std::vector<size_t> rest;
+        int64_t planes = 0;
+        for (size_t q = R * (size_t)G + (size_t)g; q < T; q += kNumXcd) {
+            rest.push_back(q);
+            planes += tiles[q].e[2];
+        }
+        size_t ti = 0;          // current remaining tile
+        int32_t used = 0;       // its planes already given out
+        for (int32_t k = 0; k < W; ++k) {
+            const size_t w = (size_t)g + (size_t)kNumXcd * (size_t)k;
+            int64_t want = planes * (k + 1) / W - planes * k / W;
+            TileHost piece[2];
+            int np = 0;
+            while (want > 0 && ti < rest.size() && np < 2) {
+                const TileHost& t = tiles[rest[ti]];
+                const int32_t take = (int32_t)std::min<int64_t>(want, t.e[2] - used);
+                piece[np++] = sub(t, used, used + take);
+                used += take;
+                want -= take;
+                if (used == t.e[2]) {
+                    ++ti;
+                    used = 0;
+                }
+            }
+            const TileHost& ref = tiles[rest.empty() ? 0 : rest[std::min(ti, rest.size() - 1)]];
+            out[R * (size_t)G + w] = np > 0 ? piece[0] : empty_of(ref);
+            out[(R + 1) * (size_t)G + w] = np > 1 ? piece[1] : empty_of(np > 0 ? piece[0] : ref);
+        }
+    }
+    return out;
+}
+
+od_status Grid::setup_cooperative() {
+    grid_wgs = 0;
+    if (cfg.exec != OD_PERSISTENT && cfg.exec != OD_MSGDRIVEN) return OD_OK;
+    const int cap = persistent_max_grid(s, plan.tile[0], plan.tile[1], coop_kind());
+    int grid = std::min<int>(cap, (int)plan.tiles.size());
+    if (grid >= kNumXcd) grid -= grid % kNumXcd;
+    grid_wgs = grid;
+    if (grid <= 0) return fail(OD_EHIP, "no co-resident workgroups for the cooperative kernel");
+    if (cfg.exec == OD_PERSISTENT && !persistent_dyn()) {
+        std::vector<TileHost> bal = balance_last_round(plan, plan.tiles, grid);
+        if (bal.size() != plan.tiles.size()) {
+            if (bal.size() > tile_cap) return fail(OD_EINVAL, "balanced tile list exceeds the tile capacity");
+            plan.tiles.swap(bal);
+            std::string e = fill_tile_descs(*this);
+            if (!e.empty()) return fail(OD_EINVAL, e);
+            hipError_t he = hipMemcpyAsync(cp(L.tiles), tiles_h.data(), tiles_h.size() * sizeof(TileDev),
+                                           hipMemcpyHostToDevice, st);
+            if (he == hipSuccess) he = hipStreamSynchronize(st);
+            if (he != hipSuccess) return fail(OD_EHIP, std::string("tile upload: ") + hipGetErrorString(he));
+        }
+    }
+    return OD_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -691,6 +797,13 @@ od_status Grid::graph_run(int64_t n) {
 
 od_status Grid::persistent_run(int64_t n) {
     if (grid_wgs <= 0) return fail(OD_EHIP, "persistent kernel: no co-resident workgroups");
+    unsigned long long* stamps = nullptr;
+    if (cfg.hints & kHintTimeline) {
+        stamps = reinterpret_cast<unsigned long long*>(cp(L.stamps));
+        stamp_iters = (int32_t)std::min<int64_t>(n, kStampIters);
+        hipError_t e0 = launch_stamp_init(st, stamps, stamp_iters);
+        if (e0 != hipSuccess) return fail(OD_EHIP, std::string("timeline init: ") + hipGetErrorString(e0));
+    }
     hipError_t e = launch_persistent(s, plan.tile[0], plan.tile[1], st, grid_wgs, base,
                                      reinterpret_cast<const BlockDev*>(cp(L.blocks)),
                                      reinterpret_cast<const TileDev*>(cp(L.tiles)), (int32_t)tiles_h.size(),
@@ -698,7 +811,7 @@ od_status Grid::persistent_run(int64_t n) {
                                      reinterpret_cast<unsigned int*>(cp(L.err)),
                                      imb, iters, mode(),
                                      persistent_dyn() ? 1 : 0,
-                                     device_wait_ticks(cfg.wait_s > 0 ? cfg.wait_s : 10.0));
+                                     device_wait_ticks(cfg.wait_s > 0 ? cfg.wait_s : 10.0), stamps);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
     parity ^= (int)(n & 1);
     iters += n;

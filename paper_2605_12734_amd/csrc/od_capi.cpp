@@ -8,6 +8,7 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "od_runtime.hpp"
 
@@ -94,13 +95,8 @@ od_status od_create(const od_config* cfg, void* hip_stream, void* dev_workspace,
     if (s != OD_OK) return s;
     s = G.init_field();
     if (s != OD_OK) return s;
-    if (G.cfg.exec == OD_PERSISTENT || G.cfg.exec == OD_MSGDRIVEN) {
-        int cap = od::persistent_max_grid(G.s, G.plan.tile[0], G.plan.tile[1], G.coop_kind());
-        int grid = std::min<int>(cap, (int)G.tiles_h.size());
-        if (grid >= od::kNumXcd) grid -= grid % od::kNumXcd;
-        G.grid_wgs = grid;
-        if (grid <= 0) return fail(OD_EHIP, "no co-resident workgroups for the cooperative kernel");
-    }
+    s = G.setup_cooperative();
+    if (s != OD_OK) return s;
     hipError_t e = hipStreamSynchronize(G.st);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("create sync: ") + hipGetErrorString(e));
     *out = h.release();
@@ -248,6 +244,28 @@ od_status od_chare_get(od_grid* g, int32_t c, od_block* out) {
         out->extent[d] = ch.e[d] * ch.h;
     }
     return OD_OK;
+}
+
+od_status od_timeline(od_grid* g, double* out, int32_t max_iters, int32_t* n_iters) {
+    OD_GUARD_BEGIN
+    OD_NEED_DEVICE(g);
+    if (!out || !n_iters || max_iters < 0) return fail(OD_EINVAL, "NULL argument or negative max_iters");
+    Grid& G = g->g;
+    if (G.cfg.exec != OD_PERSISTENT || !(G.cfg.hints & od::kHintTimeline))
+        return fail(OD_EINVAL, "the timeline is recorded by OD_PERSISTENT grids created with hints bit 3");
+    od_status s = G.device_error();
+    if (s != OD_OK) return s;
+    const int32_t n = std::min(G.stamp_iters, max_iters);
+    std::vector<unsigned long long> v((size_t)4 * n);
+    if (n > 0) {
+        hipError_t e = hipMemcpy(v.data(), G.cp(G.L.stamps), v.size() * 8, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return fail(OD_EHIP, std::string("read timeline: ") + hipGetErrorString(e));
+    }
+    const double us_per_tick = 1e6 / (double)od::device_wait_ticks(1.0);
+    for (size_t i = 0; i < v.size(); ++i) out[i] = ((double)v[i] - (double)v[0]) * us_per_tick;
+    *n_iters = n;
+    return OD_OK;
+    OD_GUARD_END
 }
 
 od_status od_extra_sweeps(od_grid* g, int64_t step, int32_t* out, int32_t n) {

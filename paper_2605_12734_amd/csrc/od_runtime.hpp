@@ -28,6 +28,7 @@ struct Layout {
     size_t ctrl_begin = 0;
     size_t ccell = 0, segs = 0, xpub = 0;
     size_t pend = 0, qslots = 0, qctl = 0;   // message-driven dependency counters and XCD queues
+    size_t stamps = 0;                       // persistent timeline (hints bit 3)
 };
 
 // Per-chare baseline message buffers (byte offsets): outgoing face messages
@@ -75,6 +76,7 @@ struct Grid {
     int parity = 0;
     int64_t iters = 0;
     bool msg_final = false;
+    int32_t stamp_iters = 0;         // iterations of the last persistent launch with a timeline
     int grid_wgs = 0;
     std::map<std::pair<int, int64_t>, hipGraphExec_t> graphs;
     // per-chare baseline
@@ -110,6 +112,10 @@ struct Grid {
     od_status read_points(const int64_t* idx, int64_t count, void* host_dst);
     od_status block_io(int32_t b, void* host, size_t bytes, bool to_host);
     od_status retile(const int32_t tile[3]);
+    // Cooperative forms: size the grid (workgroups that are co-resident)
+    // and, for the persistent form with the static stride, rebalance the
+    // last round of tiles (see balance_last_round); uploads the tiles.
+    od_status setup_cooperative();
 };
 
 std::string build_layout(const od_config& cfg, Grid& G);

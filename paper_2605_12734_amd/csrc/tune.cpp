@@ -94,6 +94,9 @@ od_status Grid::retile(const int32_t tile[3]) {
         for (int d = 0; d < 3; ++d) plan.tile[d] = old[d];
         plan_tiles(plan);
         fill_tile_descs(*this);
+        // the cooperative forms' list (and the persistent form's balanced
+        // last round) is rebuilt for the old shape, matching the device copy
+        if (cfg.exec == OD_PERSISTENT || cfg.exec == OD_MSGDRIVEN) setup_cooperative();
         return fail(OD_EINVAL, e);
     }
     hipError_t he = hipMemcpyAsync(cp(L.tiles), tiles_h.data(), tiles_h.size() * sizeof(TileDev),
@@ -102,11 +105,9 @@ od_status Grid::retile(const int32_t tile[3]) {
     if (he != hipSuccess) return fail(OD_EHIP, std::string("tile upload: ") + hipGetErrorString(he));
     for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
     graphs.clear();
-    if (cfg.exec == OD_PERSISTENT) {
-        int cap = persistent_max_grid(s, plan.tile[0], plan.tile[1], coop_kind());
-        int grid = std::min<int>(cap, (int)tiles_h.size());
-        if (grid >= kNumXcd) grid -= grid % kNumXcd;
-        grid_wgs = grid;
+    if (cfg.exec == OD_PERSISTENT || cfg.exec == OD_MSGDRIVEN) {
+        od_status cs = setup_cooperative();
+        if (cs != OD_OK) return cs;
     }
     for (int d = 0; d < 3; ++d) cfg.tile[d] = plan.tile[d];
     return OD_OK;

@@ -4,6 +4,8 @@ element by element, bit-exact (0 ULP) in fp64 and fp32.
 Sizes span several tiles with ragged tails; every execution mode and a
 range of overdecomposition factors must give the oracle's bits.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -237,3 +239,62 @@ def test_hints_keep_bits(hints, exec_):
     U, r, _ = _run((70, 36, 40), 9, odf=64, dtype="f64", exec=exec_, hints=hints, seed=3)
     _assert_same(U, want)
     assert r == r_w
+
+
+@pytest.mark.parametrize("dtype,n,odf,tile,iters", [
+    ("f64", 256, 512, (32, 16, 8), 9),              # 4096 tiles over 1536 workgroups
+    ("f32", 256, 512, (32, 32, 8), 9),              # 2048 tiles
+    ("f64", (200, 136, 72), 64, (32, 16, 4), 12),   # ragged tile depths (4, 4, 4, 4, 2)
+    ("f32", (200, 136, 144), 64, (32, 32, 5), 12),  # ragged tile depths (5 x 7, 1)
+])
+def test_persistent_balanced_last_round(dtype, n, odf, tile, iters):
+    # more tiles than co-resident workgroups, not a multiple of them: the
+    # last round's planes are shared out as z-ranges of tiles; bits must
+    # not change
+    want, _, r_want = _oracle(n, dtype, iters)
+    g = od.Grid(n, odf=odf, dtype=dtype, exec="persistent", tile=tile)
+    try:
+        plan = g.plan()
+        assert plan["grid_wgs"] % 8 == 0 and plan["ntiles"] % plan["grid_wgs"] == 0
+        g.iterate(iters)
+        r = g.residual()
+        U = g.read()
+    finally:
+        g.close()
+    assert r == r_want
+    _assert_same(U, want)
+
+
+def test_library_loaded_before_torch():
+    # libod loaded first (a host-only plan), PyTorch afterwards: one HIP
+    # runtime must serve both (a second runtime would find no device)
+    import subprocess
+    import sys
+    code = ("import paper_2605_12734_amd as od\n"
+            "info = od.host_plan(n=16, odf=1)\n"
+            "g = od.Grid(16, odf=1, exec='fused')\n"
+            "g.iterate(3)\n"
+            "print(g.residual() > 0)\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=240,
+                       cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert r.returncode == 0 and r.stdout.strip().endswith("True"), r.stderr[-2000:]
+
+
+def test_persistent_timeline():
+    # hints bit 3 records, per iteration, when workgroups start it and
+    # finish their tiles; the barrier orders them and bits do not change
+    want, _, r_want = _oracle(64, "f64", 20)
+    g = od.Grid(64, odf=64, dtype="f64", exec="persistent", hints=1 | 8, tile=(16, 8, 8))
+    try:
+        g.iterate(20)
+        r = g.residual()
+        U = g.read()
+        tl = g.timeline()
+    finally:
+        g.close()
+    assert r == r_want
+    _assert_same(U, want)
+    assert tl.shape == (20, 4) and tl[0, 0] == 0.0
+    assert (tl[:, 0] <= tl[:, 1]).all() and (tl[:, 2] <= tl[:, 3]).all() and (tl[:, 0] <= tl[:, 2]).all()
+    # nobody starts iteration i + 1 before the last workgroup finished i
+    assert (tl[1:, 0] >= tl[:-1, 3]).all()
