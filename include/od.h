@@ -182,6 +182,34 @@ od_status od_workspace_bytes(const od_config* cfg, size_t* bytes);
 od_status od_create(const od_config* cfg, void* hip_stream, void* dev_workspace,
                     size_t workspace_bytes, struct od_grid** out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * grid as od_create, but only the field storage is caller memory.
+ * dev_fields (256-byte aligned) holds at least od_plan_info.field_bytes
+ * bytes, the leading part of od_create's workspace; the descriptors and
+ * device state (residual slots, barrier and step counters, queues) live in
+ * a static device array of the library, 16 MiB per GPU, which every GPU the
+ * library runs on holds until the process ends.  This call allocates no
+ * device memory (no hipMalloc, no library allocator); it synchronises the
+ * stream before returning.
+ *   - exec must be OD_FUSED, OD_PERSISTENT or OD_MSGDRIVEN (OD_EINVAL
+ *     otherwise: the graph and per-chare forms create graphs and streams
+ *     when they first iterate).
+ *   - Descriptor room is reserved for the planned tiles only: od_autotune
+ *     then tries only tile shapes with no more tiles than planned.
+ *   - OD_ENOMEM if the grid's control state exceeds 16 MiB (e.g. 512^3 at
+ *     4096 chares needs about 1 MB fused, 3.3 MB persistent) or
+ *     dev_fields is too small.
+ *   - Every call shares its GPU's array, which keeps the last call's
+ *     contents: the call rewrites every descriptor and clears the state it
+ *     needs zeroed.  A grid made earlier on the same GPU by this call is
+ *     superseded: its od_iterate, od_residual and reads return OD_EINVAL.
+ *     Grids of this kind used concurrently on one GPU (other threads) race.
+ * The handle is used and destroyed like od_create's; the field buffer stays
+ * the caller's. */
+od_status od_create_static(const od_config* cfg, void* hip_stream, void* dev_fields, size_t field_bytes,
+                           struct od_grid** out);
+
 /* Enqueue n >= 0 Jacobi iterations on the grid's stream (asynchronous, like
  * a kernel launch).  One iteration is the stencil application's step:
  * every chare exchanges halos with its neighbours and sweeps its block
@@ -241,7 +269,7 @@ typedef struct {
     int32_t tile[3];                /* tile shape in use                              */
     int32_t grid_wgs;               /* workgroups of the persistent / msg-driven launch */
     int64_t field_bytes;            /* leading part of the workspace holding the field
-                                       storage                                        */
+                                       storage (the buffer od_create_static takes)    */
     int64_t control_bytes;          /* rest of the workspace: descriptors and device
                                        state, for this handle's plan                 */
 } od_plan_info;

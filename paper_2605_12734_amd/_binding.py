@@ -80,6 +80,7 @@ SIGNATURES = {
     "od_config_default": (None, [ctypes.POINTER(od_config)]),
     "od_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(od_config), ctypes.POINTER(c_sz)]),
     "od_create": (ctypes.c_int, [ctypes.POINTER(od_config), c_vp, c_vp, c_sz, ctypes.POINTER(c_vp)]),
+    "od_create_static": (ctypes.c_int, [ctypes.POINTER(od_config), c_vp, c_vp, c_sz, ctypes.POINTER(c_vp)]),
     "od_plan_create": (ctypes.c_int, [ctypes.POINTER(od_config), ctypes.POINTER(c_vp)]),
     "od_iterate": (ctypes.c_int, [c_vp, c_i64]),
     "od_residual": (ctypes.c_int, [c_vp, ctypes.POINTER(c_dbl)]),

@@ -3,9 +3,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -19,6 +21,14 @@ struct od_grid {
     Grid g;
 };
 
+// Control regions (descriptors, residual slots, barrier and step counters,
+// queues) of grids made by od_create_static, for callers that cannot
+// allocate device memory.  Each GPU holds its own copy of the array until
+// the process ends; host code addresses it only through the per-device
+// pointer from hipGetSymbolAddress, never through the array's name.
+constexpr size_t kStaticControlBytes = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticControlBytes];
+
 namespace {
 
 od_status plan_only(const od_config* cfg, Grid& G) {
@@ -26,6 +36,33 @@ od_status plan_only(const od_config* cfg, Grid& G) {
     std::string err = od::build_layout(*cfg, G);
     if (!err.empty()) return fail(OD_EINVAL, err);
     return OD_OK;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+char* g_static_ptr[kMaxDevices] = {};
+std::atomic<uint64_t> g_static_gen[kMaxDevices];
+
+// Device address of this device's static control array (looked up once per
+// device, with the device current).
+od_status static_control(int dev, char** out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(OD_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr)
+            return fail(OD_EHIP, std::string("hipGetSymbolAddress(static control array): ") + hipGetErrorString(e));
+        if (reinterpret_cast<uintptr_t>(ptr) % od::kAlign != 0)
+            return fail(OD_EHIP, "static control array is not 256-byte aligned");
+        g_static_ptr[dev] = static_cast<char*>(ptr);
+    }
+    *out = g_static_ptr[dev];
+    return OD_OK;
+}
+
+bool static_superseded(const Grid& G) {
+    return G.static_gen != 0 && g_static_gen[G.static_dev].load(std::memory_order_acquire) != G.static_gen;
 }
 
 #define OD_GUARD_BEGIN try {
@@ -104,6 +141,61 @@ od_status od_create(const od_config* cfg, void* hip_stream, void* dev_workspace,
     OD_GUARD_END
 }
 
+od_status od_create_static(const od_config* cfg, void* hip_stream, void* dev_fields, size_t field_bytes,
+                           od_grid** out) {
+    OD_GUARD_BEGIN
+    if (out == nullptr) return fail(OD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (cfg == nullptr) return fail(OD_EINVAL, "cfg is NULL");
+    if (cfg->exec != OD_FUSED && cfg->exec != OD_PERSISTENT && cfg->exec != OD_MSGDRIVEN)
+        return fail(OD_EINVAL, "od_create_static supports OD_FUSED, OD_PERSISTENT and OD_MSGDRIVEN (the graph "
+                               "and per-chare forms create graphs and streams when they first iterate)");
+    std::unique_ptr<od_grid> h(new od_grid);
+    Grid& G = h->g;
+    G.tune_room = false;   // descriptor room for the planned tiles only
+    od_status s = plan_only(cfg, G);
+    if (s != OD_OK) return s;
+    const size_t ctrl_bytes = G.L.total - G.L.ctrl_begin;
+    if (ctrl_bytes > kStaticControlBytes)
+        return fail(OD_ENOMEM, "grid needs " + std::to_string(ctrl_bytes) +
+                                   " bytes of control state; the static array holds " +
+                                   std::to_string(kStaticControlBytes));
+    if (dev_fields == nullptr) return fail(OD_EINVAL, "field buffer is NULL");
+    if (reinterpret_cast<uintptr_t>(dev_fields) % od::kAlign != 0)
+        return fail(OD_EINVAL, "field buffer must be 256-byte aligned");
+    if (field_bytes < G.L.ctrl_begin)
+        return fail(OD_ENOMEM, "field buffer of " + std::to_string(field_bytes) + " bytes, need " +
+                                   std::to_string(G.L.ctrl_begin));
+    int dev = 0;
+    hipError_t he = hipGetDevice(&dev);
+    if (he != hipSuccess) return fail(OD_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(he));
+    char* ctrl = nullptr;
+    s = static_control(dev, &ctrl);
+    if (s != OD_OK) return s;
+    G.st = static_cast<hipStream_t>(hip_stream);
+    G.base = static_cast<char*>(dev_fields);
+    G.ctrl = ctrl;
+    G.ws_bytes = field_bytes;
+    G.static_dev = dev;
+    G.static_gen = g_static_gen[dev].fetch_add(1, std::memory_order_acq_rel) + 1;
+    // upload writes every descriptor; reset_state clears the residual
+    // slots, barrier words, error flag and step counters the previous user
+    // of the array left behind
+    s = G.upload();
+    if (s != OD_OK) return s;
+    s = G.reset_state();
+    if (s != OD_OK) return s;
+    s = G.init_field();
+    if (s != OD_OK) return s;
+    s = G.setup_cooperative();
+    if (s != OD_OK) return s;
+    he = hipStreamSynchronize(G.st);
+    if (he != hipSuccess) return fail(OD_EHIP, std::string("create sync: ") + hipGetErrorString(he));
+    *out = h.release();
+    return OD_OK;
+    OD_GUARD_END
+}
+
 od_status od_plan_create(const od_config* cfg, od_grid** out) {
     OD_GUARD_BEGIN
     if (out == nullptr) return fail(OD_EINVAL, "out is NULL");
@@ -120,6 +212,8 @@ od_status od_plan_create(const od_config* cfg, od_grid** out) {
     do {                                                                                   \
         if (!(g)) return fail(OD_EINVAL, "grid is NULL");                                  \
         if ((g)->g.base == nullptr) return fail(OD_EINVAL, "host-only plan handle");       \
+        if (static_superseded((g)->g))                                                     \
+            return fail(OD_EINVAL, "grid superseded by a later od_create_static on its device"); \
     } while (0)
 
 od_status od_iterate(od_grid* g, int64_t n) {

@@ -71,6 +71,11 @@ struct Grid {
     // build_layout reserves descriptor room for every autotune candidate's
     // tiles (false: only the planned tiles)
     bool tune_room = true;
+    // grids made by od_create_static: their control regions live in the
+    // device's static array; a later od_create_static on the same device
+    // supersedes them (static_gen no longer current)
+    int static_dev = -1;
+    uint64_t static_gen = 0;
     char* cp(size_t off) const { return ctrl + (off - L.ctrl_begin); }
     GridDev gdev{};
     int parity = 0;

@@ -115,3 +115,24 @@ def test_request_arrival_stamp():
     r = make_request(16, "f64", odf=8, t_arrival=12.5)
     assert L.od_request_bytes(ctypes.byref(r), ctypes.byref(out)) == 0 and out.value > 0
 
+
+def test_create_static_host_checks():
+    # refused before any device work: a form that allocates when it first
+    # iterates, and control state beyond the static array's 16 MiB
+    from paper_2605_12734_amd import _binding as B
+    import paper_2605_12734_amd as od
+    L = B.lib()
+    h = ctypes.c_void_p()
+    cfg, keep = od.make_config(n=32, odf=8, exec="graph")
+    assert L.od_create_static(ctypes.byref(cfg), None, ctypes.c_void_p(256), 1 << 30, ctypes.byref(h)) == -22
+    cfg, keep = od.make_config(n=32, odf=8, exec="per_chare")
+    assert L.od_create_static(ctypes.byref(cfg), None, ctypes.c_void_p(256), 1 << 30, ctypes.byref(h)) == -22
+    p = od._PlanHandle(n=64, odf=8, exec="fused")
+    info = od.plan_info(p.h)
+    p.close()
+    assert info["field_bytes"] > 0 and info["control_bytes"] > 0
+    assert info["field_bytes"] + info["control_bytes"] == od.workspace_bytes(n=64, odf=8, exec="fused")
+    big, keep2 = od.make_config(n=1024, odf=64 ** 3, exec="fused")   # 262144 chares: 32 MiB of tiles
+    assert L.od_create_static(ctypes.byref(big), None, ctypes.c_void_p(256), 1 << 40, ctypes.byref(h)) == -12
+    assert b"static array holds" in L.od_last_error()
+    assert not h.value
