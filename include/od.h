@@ -125,7 +125,11 @@ typedef struct {
      * within one step of it (a failure raises the error flag: reads then
      * return OD_ESCHED).  Every message-driven task also checks, in any
      * mode, that its tile's step counter advances by exactly one;
-     * bit 3 (OD_PERSISTENT): record the timeline read by od_timeline.
+     * bit 3 (OD_PERSISTENT): record the timeline read by od_timeline;
+     * bit 4 (OD_PERSISTENT): take tiles from per-XCD-group counters even
+     * for uniform work (default there: a fixed stride per workgroup);
+     * bit 5 (OD_PERSISTENT): counters, with each XCD group's last tiles
+     * cut into z-ranges so the end of an iteration waits less.
      * Other bits are ignored. */
     int32_t hints;
     /* 7 (or 0): 3D 7-point stencil.  5: the 2D 5-point stencil of the

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <string>
 
 #include "kernels.hpp"
 
@@ -402,13 +403,22 @@ __device__ __forceinline__ bool grid_barrier(unsigned int* bar, unsigned int* er
 // hwreg(HW_REG_XCC_ID, 0, 4): the XCD this wave runs on
 constexpr int kXccIdReg = ((4 - 1) << 11) | (0 << 6) | 20;
 
+// Tile counters of the persistent form's dynamic schedule: per step parity
+// and XCD group one word, each on a 128-byte line of its own (counters of
+// different groups never contend for one line).
+constexpr int kCtrBase = 64, kCtrStride = 32;
+__device__ __forceinline__ unsigned int* tile_ctr(unsigned int* bar, int par, int g) {
+    return &bar[kCtrBase + kCtrStride * (8 * par + g)];
+}
+
 // Device-wide barrier with one L2 write-back per XCD.  The workgroups of an
 // XCD share its L2: each drains its stores into it and arrives on the XCD's
 // counter (relaxed); the last of them publishes for all of them with one
 // release (write-back of that L2) on the device counter; the last XCD bumps
 // the generation.  Bounded wait as in grid_barrier.  bar[32 + x]: arrivals
 // of XCD x (zeroed by its last arrival), `xcd_wgs` workgroups on this XCD,
-// `nxcd` XCDs with workgroups.
+// `nxcd` XCDs with workgroups.  `reset` (may be null): 8 counters,
+// kCtrStride words apart, that the releasing workgroup zeroes.
 __device__ __forceinline__ bool xcd_barrier(unsigned int* bar, unsigned int* err, int64_t wait_ticks,
                                             unsigned int* reset, int xcd, unsigned int xcd_wgs,
                                             unsigned int nxcd) {
@@ -426,7 +436,7 @@ __device__ __forceinline__ bool xcd_barrier(unsigned int* bar, unsigned int* err
                 __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (reset)
                     for (int x = 0; x < 8; ++x)
-                        __hip_atomic_store(&reset[x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&reset[x * kCtrStride], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                 released = true;
             }
@@ -504,13 +514,14 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
         // DYN: tiles of this workgroup's XCD group, taken one at a time from
         // the group's counter (the next index is requested while a tile
         // sweeps); otherwise the fixed stride w, w + G, w + 2G, ...
-        unsigned int* ctr = &bar[8 + 8 * (int)(it & 1) + xg];
+        unsigned int* ctr = tile_ctr(bar, (int)(it & 1), xg);
         if (DYN) {
             if (threadIdx.x == 0)
                 s_idx = (int32_t)__hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __syncthreads();
         }
-        int32_t idx = DYN ? s_idx : (int32_t)blockIdx.x;
+        // uniform by construction: the tile descriptor stays in scalar registers
+        int32_t idx = DYN ? __builtin_amdgcn_readfirstlane(s_idx) : (int32_t)blockIdx.x;
         for (;;) {
             const int32_t ti = DYN ? xg + ng * idx : idx;
             if (ti >= ntiles) break;
@@ -532,7 +543,7 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
                 __syncthreads();
                 if (threadIdx.x == 0) s_idx = nxt;
                 __syncthreads();
-                nxt = s_idx;
+                nxt = __builtin_amdgcn_readfirstlane(s_idx);
             }
             idx = nxt;
         }
@@ -544,7 +555,7 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
         }
         if (it + 1 < iters) {
             // the last arrival clears the counters of the step after next
-            if (!xcd_barrier(bar, err, wait_ticks, &bar[8 + 8 * (int)((it + 1) & 1)], s_xcd, s_xwgs, s_nxcd))
+            if (!xcd_barrier(bar, err, wait_ticks, tile_ctr(bar, (int)((it + 1) & 1), 0), s_xcd, s_xwgs, s_nxcd))
                 return;
         }
     }
@@ -553,7 +564,8 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
     if (threadIdx.x == 0) {
         const unsigned int prev = __hip_atomic_fetch_add(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (prev == gridDim.x - 1) {
-            for (int x = 8; x < 24; ++x) __hip_atomic_store(&bar[x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int x = 0; x < 16; ++x)
+                __hip_atomic_store(tile_ctr(bar, x >> 3, x & 7), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             for (int x = 32; x < 48; ++x) __hip_atomic_store(&bar[x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&bar[2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -1333,25 +1345,43 @@ int64_t device_wait_ticks(double seconds) {
     return (int64_t)(seconds * 1e3 * (double)khz);
 }
 
-// Co-resident workgroups per CU of a cooperative kernel with `threads` per
-// workgroup, from the occupancy query `per`, capped at `max_waves` (at most
-// 6) waves per SIMD.
-// The query counts SGPRs more generously than gfx950 places waves:
-// measured with 256-thread workgroups at 64-72 VGPRs, kernels using 78
-// SGPRs hold 8 waves per SIMD, 86 hold 7, and 99-108 hold only 6 where the
-// query reports 7 or 8 (the cooperative kernels here use 106).  A
-// cooperative grid larger than what is resident never completes its first
-// device-wide barrier.
-static int coop_per_cu(int per, int threads, int max_waves = 6) {
-    const int waves = (threads + 63) / 64;
-    const int cap = (max_waves * 4) / waves;   // 4 SIMDs per CU
+// Co-resident workgroups per CU of a cooperative kernel: the occupancy
+// query `per` (exact for VGPRs and LDS), limited by what the kernel's scalar
+// registers allow (waves_by_sgprs of the count the compiler recorded for
+// this build; a kernel missing from the record is taken as 5 waves per
+// SIMD) and by `max_waves` waves per SIMD (a scheduling choice).  A
+// cooperative grid larger than what is resident would never complete its
+// first device-wide barrier.
+static int coop_per_cu(int per, int threads, const char* name, int max_waves) {
+    int sg = 0;
+    const int w_sgpr = kernel_resources(name, &sg, nullptr, nullptr) ? waves_by_sgprs(sg) : 5;
+    const int w = max_waves > 0 && max_waves < w_sgpr ? max_waves : w_sgpr;
+    const int wpw = (threads + 63) / 64;
+    const int cap = (4 * w) / wpw;   // 4 SIMDs per CU
     return per < cap ? per : cap;
 }
 
-int persistent_max_grid(int dtype_bytes, int tx, int ty, int kind) {
+static std::string kernel_name(const char* base, int dtype_bytes, int tx, int ty, const char* extra) {
+    return std::string("od::") + base + "<" + (dtype_bytes == 8 ? "double" : "float") + ", " + std::to_string(tx) +
+           ", " + std::to_string(ty) + (extra ? extra : "") + ">";
+}
+
+int coop_waves_limit(int dtype_bytes, int tx, int ty, int kind) {
+    const std::string name = kind == 1 ? kernel_name("k_msgdriven", dtype_bytes, tx, ty, nullptr)
+                                       : kernel_name("k_persistent", dtype_bytes, tx, ty, kind == 2 ? ", true" : ", false");
+    int sg = 0;
+    return kernel_resources(name.c_str(), &sg, nullptr, nullptr) ? waves_by_sgprs(sg) : 5;
+}
+
+int persistent_max_grid(int dtype_bytes, int tx, int ty, int kind, int max_waves) {
     int dev = 0, ncu = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    // default choice: the counter form (imbalance, uneven blocks) measured
+    // faster at 5 waves per SIMD than at 6
+    if (max_waves <= 0) max_waves = kind == 2 ? 5 : 8;
+    const std::string name = kind == 1 ? kernel_name("k_msgdriven", dtype_bytes, tx, ty, nullptr)
+                                       : kernel_name("k_persistent", dtype_bytes, tx, ty, kind == 2 ? ", true" : ", false");
 #define OD_OCC(T, TX, TY)                                                                             \
     if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                      \
         hipError_t e = kind == 0                                                                      \
@@ -1363,8 +1393,7 @@ int persistent_max_grid(int dtype_bytes, int tx, int ty, int kind) {
             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_msgdriven<T, TX, TY>,              \
                                                            SW<T, TX, TY>::NT, 0);                     \
         if (e != hipSuccess) return 0;                                                                \
-        /* the counter form (imbalance, uneven blocks) measured faster at 5 */                         \
-        return coop_per_cu(per, SW<T, TX, TY>::NT, kind == 2 ? 5 : 6) * ncu;                          \
+        return coop_per_cu(per, SW<T, TX, TY>::NT, name.c_str(), max_waves) * ncu;                   \
     }
     OD_VARIANTS_F64(OD_OCC)
     OD_VARIANTS_F32(OD_OCC)
@@ -1401,7 +1430,9 @@ int serve_max_grid() {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_serve<kServeTx8, kServeTy8, kServeTx4, kServeTy4>,
                                                      SW<double, kServeTx8, kServeTy8>::NT, 0) != hipSuccess)
         return 0;
-    return coop_per_cu(per, SW<double, kServeTx8, kServeTy8>::NT) * ncu;
+    const std::string name = "od::k_serve<" + std::to_string(kServeTx8) + ", " + std::to_string(kServeTy8) + ", " +
+                             std::to_string(kServeTx4) + ", " + std::to_string(kServeTy4) + ">";
+    return coop_per_cu(per, SW<double, kServeTx8, kServeTy8>::NT, name.c_str(), 8) * ncu;
 }
 
 hipError_t launch_serve(hipStream_t st, int grid, const MsgArgs& a) {

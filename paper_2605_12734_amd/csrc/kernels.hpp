@@ -111,10 +111,10 @@ hipError_t launch_sweep(int dtype_bytes, int tx, int ty, hipStream_t st, void* a
 // device-wide barrier between them.  dyn != 0: workgroups take tiles from
 // per-XCD-group counters (load balance under imbalance and uneven blocks);
 // dyn == 0: workgroup w takes tiles w, w + grid, ... (uniform work).
-// `bar` = 64 zeroed uint32: [0] arrivals, [1] generation, [2] exits,
-// [8..24) tile counters (8 XCD groups x 2 step parities), [32..40) per-XCD
-// barrier arrivals, [40..48) workgroups per XCD; the kernel leaves them
-// zeroed.  Between iterations, one L2 write-back per XCD publishes its
+// `bar` = kBarWords zeroed uint32: [0] arrivals, [1] generation, [2] exits,
+// [32..40) per-XCD barrier arrivals, [40..48) workgroups per XCD, from
+// word 64 the tile counters (8 XCD groups x 2 step parities, 32 words
+// apart); the kernel leaves them zeroed.  Between iterations, one L2 write-back per XCD publishes its
 // workgroups' results (the XCD's workgroups share that L2).  `err` = error
 // flag.  `imb`: load-imbalance draw, iteration `it` of the launch is step
 // iter_base + it.
@@ -122,6 +122,7 @@ hipError_t launch_sweep(int dtype_bytes, int tx, int ty, hipStream_t st, void* a
 // wall-clock words per iteration (first / last workgroup to start it,
 // first / last to finish its tiles), prepared by launch_stamp_init.
 constexpr int kStampIters = 1024;
+constexpr int kBarWords = 1024;
 hipError_t launch_persistent(int dtype_bytes, int tx, int ty, hipStream_t st, int grid,
                              void* arena, const BlockDev* blocks, const TileDev* tiles,
                              int32_t ntiles, int parity, int64_t iters,
@@ -131,12 +132,28 @@ hipError_t launch_persistent(int dtype_bytes, int tx, int ty, hipStream_t st, in
 hipError_t launch_stamp_init(hipStream_t st, unsigned long long* stamps, int32_t n);
 // hints bit 3 (persistent form): record the timeline above.
 constexpr int kHintTimeline = 8;
+// Register usage of a kernel of this build (demangled name without the
+// return type and parameters); false if the build recorded none.
+bool kernel_resources(const char* name, int* sgprs, int* vgprs, int* lds);
+// Waves per SIMD that a kernel's scalar registers allow on gfx950: residency
+// probes (256-thread workgroups holding their CU) held 8 waves at 78 SGPRs,
+// 7 at 86 and 6 at 99-108, which a budget of 704 SGPRs per SIMD at a
+// granularity of 16 reproduces (the occupancy query counts SGPRs more
+// generously; VGPRs and LDS it counts exactly).
+inline int waves_by_sgprs(int sgprs) {
+    const int a = (sgprs + 15) / 16 * 16;
+    const int w = a > 0 ? 704 / a : 8;
+    return w > 8 ? 8 : (w < 1 ? 1 : w);
+}
 // Wall-clock ticks in `seconds` (bound of every device-side wait).
 int64_t device_wait_ticks(double seconds = 10.0);
 // Max co-resident workgroups of a cooperative kernel: kind 0 = persistent
 // with the static tile stride, 2 = persistent with tile counters (dyn),
-// 1 = message-driven.
-int persistent_max_grid(int dtype_bytes, int tx, int ty, int kind);
+// 1 = message-driven; at most max_waves waves per SIMD (0 = the default
+// choice: 5 for kind 2, else as many as the registers allow).
+int persistent_max_grid(int dtype_bytes, int tx, int ty, int kind, int max_waves = 0);
+// Waves per SIMD the kernel's recorded scalar registers allow.
+int coop_waves_limit(int dtype_bytes, int tx, int ty, int kind);
 
 // Message-driven cooperative sweep: per-tile step counters `done`,
 // dependency lists (CSR: dep_ptr[ntiles+1], dep_idx; symmetric), counters

@@ -413,9 +413,9 @@ std::string build_layout(const od_config& cfg, Grid& G) {
         }
         G.tile_cap = std::max(ntiles, cap);
     }
-    // the persistent form's balanced last round adds up to two entries per
-    // workgroup (balance_last_round); cooperative grids stay below 8192
-    if (cfg.exec == OD_PERSISTENT) G.tile_cap += 2 * 8192;
+    // the persistent form's guided tail adds up to three entries per
+    // workgroup plus padding (guided_tail); cooperative grids stay below 8192
+    if (cfg.exec == OD_PERSISTENT) G.tile_cap += 3 * 8192 + kNumXcd;
     G.L.tiles = cv.take(G.tile_cap * sizeof(TileDev));
     for (int d = 0; d < 3; ++d) G.L.cidx[d] = cv.take((size_t)(p.regular ? p.n[d] : 1) * 4);
     G.L.owner = cv.take((p.regular ? 1 : p.owner.size()) * 4);
@@ -427,7 +427,7 @@ std::string build_layout(const od_config& cfg, Grid& G) {
     G.L.bc = cv.take(6 * 8);
     G.nres = cfg.exec == OD_PER_CHARE ? C : 1;
     G.L.res = cv.take((size_t)(2 * G.nres + 2) * 8);
-    G.L.bar = cv.take(64 * 4);
+    G.L.bar = cv.take(kBarWords * 4);
     G.L.err = cv.take(4);
     G.L.done = cv.take(ntiles * 4);
     G.L.target = cv.take(4 * 4);
@@ -534,29 +534,16 @@ std::string build_tile_deps(const Plan& p, std::vector<int32_t>& ptr, std::vecto
     return "";
 }
 
-// Persistent form with the static stride: workgroup w sweeps list entries
-// w, w + G, w + 2G, ...  With T tiles and G workgroups, T mod G tiles are
-// left for a last round that only some workgroups run while the others
-// wait at the barrier.  Instead, the planes of those tiles are shared out
-// evenly: within each XCD group g (list positions and workgroups = g mod 8),
-// the remaining tiles' planes are cut into G/8 contiguous runs, one per
-// workgroup, each run covering at most two z-ranges of tiles (sub-tiles:
-// the same box cut along z, the cut faces reading the tile's own planes).
-// The list becomes R full rounds plus two entries per workgroup (the second
-// may be empty, nz = 0).  Sub-tiles compute the same expression at every
-// point, so results are unchanged.
-std::vector<TileHost> balance_last_round(const Plan& p, const std::vector<TileHost>& tiles, int32_t G) {
-    const size_t T = tiles.size();
-    if (G < kNumXcd || G % kNumXcd != 0 || T % (size_t)G == 0) return tiles;
-    const size_t R = T / (size_t)G;
-    const int32_t W = G / kNumXcd;
-    std::vector<TileHost> out(tiles.begin(), tiles.begin() + (std::ptrdiff_t)(R * (size_t)G));
-    out.resize((R + 2) * (size_t)G);
-    auto empty_of = [&](const TileHost& t) {
-        TileHost e = t;
-        e.e[2] = 0;
-        return e;
-    };
+// Persistent form with tile counters: the workgroups of XCD group g claim
+// list positions g, g + 8, g + 16, ... in order.  The last claims of an
+// iteration leave workgroups idle until the slowest tile ends, so the last
+// `tail` tiles of each group are cut into `pieces` z-ranges (sub-tiles: the
+// same box cut along z, a cut face reading the tile's own plane) and
+// claimed last, shortening that wait to about one piece.  Groups are padded
+// to one length with empty entries (nz = 0).  Sub-tiles compute the same
+// expression at every point, so results are unchanged.
+std::vector<TileHost> guided_tail(const Plan& p, const std::vector<TileHost>& tiles, int32_t tail, int32_t pieces) {
+    if (tiles.size() < (size_t)kNumXcd || tail <= 0 || pieces <= 1) return tiles;
     auto sub = [&](const TileHost& t, int32_t za, int32_t zb) {
         const Chare& c = p.chares[(size_t)t.chare];
         TileHost u = t;
@@ -579,52 +566,53 @@ std::vector<TileHost> balance_last_round(const Plan& p, const std::vector<TileHo
         }
         return u;
     };
-    for (int32_t g = 0; g < kNumXcd; ++g) {
-        std::vector<size_t> rest;
-        int64_t planes = 0;
-        for (size_t q = R * (size_t)G + (size_t)g; q < T; q += kNumXcd) {
-            rest.push_back(q);
-            planes += tiles[q].e[2];
-        }
-        size_t ti = 0;          // current remaining tile
-        int32_t used = 0;       // its planes already given out
-        for (int32_t k = 0; k < W; ++k) {
-            const size_t w = (size_t)g + (size_t)kNumXcd * (size_t)k;
-            int64_t want = planes * (k + 1) / W - planes * k / W;
-            TileHost piece[2];
-            int np = 0;
-            while (want > 0 && ti < rest.size() && np < 2) {
-                const TileHost& t = tiles[rest[ti]];
-                const int32_t take = (int32_t)std::min<int64_t>(want, t.e[2] - used);
-                piece[np++] = sub(t, used, used + take);
-                used += take;
-                want -= take;
-                if (used == t.e[2]) {
-                    ++ti;
-                    used = 0;
-                }
+    std::vector<std::vector<TileHost>> seq((size_t)kNumXcd);
+    size_t len = 0;
+    for (int g = 0; g < kNumXcd; ++g) {
+        std::vector<TileHost>& q = seq[(size_t)g];
+        for (size_t i = (size_t)g; i < tiles.size(); i += kNumXcd) q.push_back(tiles[i]);
+        const size_t keep = q.size() > (size_t)tail ? q.size() - (size_t)tail : 0;
+        std::vector<TileHost> cut(q.begin(), q.begin() + (std::ptrdiff_t)keep);
+        for (size_t i = keep; i < q.size(); ++i) {
+            const TileHost& t = q[i];
+            const int32_t np = std::max<int32_t>(1, std::min<int32_t>(pieces, t.e[2] / 4));
+            for (int32_t k = 0; k < np; ++k) {
+                const int32_t za = (int32_t)((int64_t)t.e[2] * k / np), zb = (int32_t)((int64_t)t.e[2] * (k + 1) / np);
+                cut.push_back(sub(t, za, zb));
             }
-            const TileHost& ref = tiles[rest.empty() ? 0 : rest[std::min(ti, rest.size() - 1)]];
-            out[R * (size_t)G + w] = np > 0 ? piece[0] : empty_of(ref);
-            out[(R + 1) * (size_t)G + w] = np > 1 ? piece[1] : empty_of(np > 0 ? piece[0] : ref);
         }
+        q.swap(cut);
+        len = std::max(len, q.size());
     }
+    std::vector<TileHost> out(len * kNumXcd);
+    for (size_t k = 0; k < len; ++k)
+        for (int g = 0; g < kNumXcd; ++g) {
+            const std::vector<TileHost>& q = seq[(size_t)g];
+            if (k < q.size()) {
+                out[k * kNumXcd + (size_t)g] = q[k];
+            } else {
+                TileHost e = q.empty() ? tiles[0] : q.back();
+                e.e[2] = 0;
+                out[k * kNumXcd + (size_t)g] = e;
+            }
+        }
     return out;
 }
 
-od_status Grid::setup_cooperative() {
+od_status Grid::setup_cooperative(bool fresh_plan) {
     grid_wgs = 0;
     if (cfg.exec != OD_PERSISTENT && cfg.exec != OD_MSGDRIVEN) return OD_OK;
-    const int cap = persistent_max_grid(s, plan.tile[0], plan.tile[1], coop_kind());
-    int grid = std::min<int>(cap, (int)plan.tiles.size());
+    if (fresh_plan || base_tiles.empty()) base_tiles = plan.tiles;
+    const int cap = persistent_max_grid(s, plan.tile[0], plan.tile[1], coop_kind(), persist_waves);
+    int grid = std::min<int>(cap, (int)base_tiles.size());
     if (grid >= kNumXcd) grid -= grid % kNumXcd;
     grid_wgs = grid;
     if (grid <= 0) return fail(OD_EHIP, "no co-resident workgroups for the cooperative kernel");
-    if (cfg.exec == OD_PERSISTENT && !persistent_dyn()) {
-        std::vector<TileHost> bal = balance_last_round(plan, plan.tiles, grid);
-        if (bal.size() != plan.tiles.size()) {
-            if (bal.size() > tile_cap) return fail(OD_EINVAL, "balanced tile list exceeds the tile capacity");
-            plan.tiles.swap(bal);
+    if (cfg.exec == OD_PERSISTENT) {
+        std::vector<TileHost> list = sched() == 3 ? guided_tail(plan, base_tiles, grid / kNumXcd, 4) : base_tiles;
+        if (list.size() > tile_cap) return fail(OD_EINVAL, "cut tile list exceeds the tile capacity");
+        if (list.size() != plan.tiles.size() || !fresh_plan) {
+            plan.tiles.swap(list);
             std::string e = fill_tile_descs(*this);
             if (!e.empty()) return fail(OD_EINVAL, e);
             hipError_t he = hipMemcpyAsync(cp(L.tiles), tiles_h.data(), tiles_h.size() * sizeof(TileDev),
@@ -698,7 +686,7 @@ od_status Grid::reset_state() {
     // zero residual slots, barrier, error flag and step counters with a
     // plain fill (not captured into any graph)
     hipError_t e = hipMemsetAsync(cp(L.res), 0, (size_t)(2 * nres + 2) * 8, st);
-    if (e == hipSuccess) e = hipMemsetAsync(cp(L.bar), 0, 64 * 4, st);
+    if (e == hipSuccess) e = hipMemsetAsync(cp(L.bar), 0, kBarWords * 4, st);
     if (e == hipSuccess) e = hipMemsetAsync(cp(L.err), 0, 4, st);
     if (e == hipSuccess) e = hipMemsetAsync(cp(L.done), 0, std::max<size_t>(tiles_h.size(), 1) * 4, st);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("state reset: ") + hipGetErrorString(e));

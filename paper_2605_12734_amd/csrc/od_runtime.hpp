@@ -53,11 +53,23 @@ struct Grid {
     int64_t fill_total = 0;          // ghost cells filled per iteration
     std::vector<int32_t> dep_ptr, dep_idx;
     ImbDev imb{};                    // load-imbalance draw (heavy == 0: none)
-    // the persistent form takes tiles from counters (imbalance or uneven
-    // blocks) rather than by a fixed stride
-    bool persistent_dyn() const { return imb.heavy > 0 || !plan.regular; }
+    // Persistent schedule: 0 = automatic (counters under imbalance or with
+    // uneven blocks, else the fixed stride), 1 = fixed stride, 2 = tiles
+    // from per-XCD-group counters, 3 = counters with the last tiles of each
+    // group cut into z-ranges (guided_tail).  hints bits 4 and 5 force 2
+    // and 3; the autotuner may choose.
+    int persist_sched = 0;
+    int persist_waves = 0;           // cooperative waves per SIMD cap (0 = default)
+    int sched() const {
+        if (cfg.hints & 32) return 3;
+        if (cfg.hints & 16) return 2;
+        if (persist_sched) return persist_sched;
+        return (imb.heavy > 0 || !plan.regular) ? 2 : 1;
+    }
+    bool persistent_dyn() const { return sched() >= 2; }
     // cooperative-kernel kind for persistent_max_grid
     int coop_kind() const { return cfg.exec == OD_MSGDRIVEN ? 1 : (persistent_dyn() ? 2 : 0); }
+    std::vector<TileHost> base_tiles;   // the planner's tile list before schedule-specific cuts
     std::vector<MsgBufs> msg;
     int32_t nres = 1;
     size_t tile_cap = 0;             // tile descriptors the workspace has room for
@@ -118,9 +130,11 @@ struct Grid {
     od_status block_io(int32_t b, void* host, size_t bytes, bool to_host);
     od_status retile(const int32_t tile[3]);
     // Cooperative forms: size the grid (workgroups that are co-resident)
-    // and, for the persistent form with the static stride, rebalance the
-    // last round of tiles (see balance_last_round); uploads the tiles.
-    od_status setup_cooperative();
+    // and build the persistent form's tile list for its schedule (the
+    // guided tail cuts the last tiles of each XCD group, see guided_tail);
+    // uploads the tiles.  fresh_plan: plan.tiles was just planned (else the
+    // list is rebuilt from base_tiles, e.g. after a schedule change).
+    od_status setup_cooperative(bool fresh_plan = true);
 };
 
 std::string build_layout(const od_config& cfg, Grid& G);

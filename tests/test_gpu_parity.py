@@ -247,15 +247,17 @@ def test_hints_keep_bits(hints, exec_):
     ("f64", (200, 136, 72), 64, (32, 16, 4), 12),   # ragged tile depths (4, 4, 4, 4, 2)
     ("f32", (200, 136, 144), 64, (32, 32, 5), 12),  # ragged tile depths (5 x 7, 1)
 ])
-def test_persistent_balanced_last_round(dtype, n, odf, tile, iters):
-    # more tiles than co-resident workgroups, not a multiple of them: the
-    # last round's planes are shared out as z-ranges of tiles; bits must
-    # not change
+@pytest.mark.parametrize("sched", [0, 16, 32])
+def test_persistent_schedules(dtype, n, odf, tile, iters, sched):
+    # fixed stride (0), tiles from per-XCD counters (16), and counters with
+    # each XCD group's last tiles cut into z-ranges (32): bits must not change
     want, _, r_want = _oracle(n, dtype, iters)
-    g = od.Grid(n, odf=odf, dtype=dtype, exec="persistent", tile=tile)
+    g = od.Grid(n, odf=odf, dtype=dtype, exec="persistent", tile=tile, hints=1 | sched)
     try:
         plan = g.plan()
-        assert plan["grid_wgs"] % 8 == 0 and plan["ntiles"] % plan["grid_wgs"] == 0
+        assert plan["grid_wgs"] % 8 == 0
+        if sched == 32:
+            assert plan["ntiles"] % 8 == 0
         g.iterate(iters)
         r = g.residual()
         U = g.read()
