@@ -89,6 +89,9 @@ def load_traffic(key: str):
     return e.get("bytes_per_launch")
 
 
+SCHEDULES = {1: "stride", 2: "counters", 3: "counters+guided-tail"}
+
+
 def msg_tile(tile):
     """Message-driven tile from a tuned fused tile: z extent at most 32."""
     return (tile[0], tile[1], min(tile[2], 32))
@@ -198,7 +201,8 @@ def cpu_baseline(n, dtype, target_s=15.0, max_iters=200, chunk=10):
 
 def odf_sweep(n, iters, persistent=True):
     """Per dtype and ODF: graph-captured fused launches (tile autotuned),
-    the persistent cooperative form (same tile), per-chare launches.  Each
+    the persistent cooperative form (tile and schedule autotuned on its own
+    kernel), per-chare launches (the graph's tile).  Each
     batched form's roofline fraction divides the algorithmic bytes per
     iteration by its own kernel time per iteration (HIP events)."""
     rows = []
@@ -213,8 +217,11 @@ def odf_sweep(n, iters, persistent=True):
                    "batched_hbm_gbps": round(bp / b["launch_s"] / 1e9, 1),
                    "batched_frac": round(bp / b["launch_s"] / 1e9 / PEAK_HBM_GBPS, 4)}
             if persistent:
-                q = grid_leg(n, odf, dtype, "persistent", iters, 2, 1, tile=tile)
-                row.update({"persistent_glups": round(q["glups"], 2),
+                # tile and schedule tuned on the persistent kernel itself
+                q = grid_leg(n, odf, dtype, "persistent", iters, 2, 1)
+                row.update({"persistent_tile": list(q["plan"]["tile"]),
+                            "persistent_schedule": SCHEDULES.get(q["plan"]["schedule"], q["plan"]["schedule"]),
+                            "persistent_glups": round(q["glups"], 2),
                             "persistent_hbm_gbps": round(bp / q["launch_s"] / 1e9, 1),
                             "persistent_frac": round(bp / q["launch_s"] / 1e9 / PEAK_HBM_GBPS, 4),
                             "persistent_us_per_iter": round(q["launch_s"] * 1e6, 2),
@@ -469,6 +476,8 @@ def main():
     ap.add_argument("--no-imbalance", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--imb-iters", type=int, default=1000)
+    ap.add_argument("--amr-iters", type=int, default=500)
+    ap.add_argument("--amr", action="store_true", help="with --quick: run the octree leg too")
     ap.add_argument("--jacobi2d", action="store_true")
     ap.add_argument("--launch", action="store_true")
     ap.add_argument("--serving-count", type=int, default=128)
@@ -537,10 +546,10 @@ def main():
     if ceil:
         out["hbm_ceilings"] = ceil
     legs = []
-    if not args.no_sweep:
+    if not args.no_sweep and not args.quick:
         legs.append(("odf_sweep", lambda: odf_sweep(args.n, args.iters)))
-    if not args.quick and not args.no_amr:
-        legs.append(("amr_octree_768", amr_leg))
+    if (args.amr or not args.quick) and not args.no_amr:
+        legs.append(("amr_octree_768", lambda: amr_leg(args.amr_iters)))
     if not args.quick and not args.no_imbalance:
         legs.append(("imbalance_1024", lambda: imbalance_leg(args.imb_iters)))
     if not args.quick and not args.no_serving:

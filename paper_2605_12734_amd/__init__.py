@@ -117,6 +117,7 @@ def plan_info(handle) -> dict:
     return {"nchares": info.nchares, "ntiles": info.ntiles, "npseudo": info.npseudo,
             "interior": info.interior, "halo_cells": info.halo_cells,
             "bytes_per_iter": info.bytes_per_iter, "tile": tuple(info.tile), "grid_wgs": info.grid_wgs,
+            "schedule": info.schedule, "coop_waves": info.coop_waves,
             "field_bytes": info.field_bytes, "control_bytes": info.control_bytes}
 
 

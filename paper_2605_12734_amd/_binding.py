@@ -48,7 +48,7 @@ class od_config(ctypes.Structure):
 class od_plan_info(ctypes.Structure):
     _fields_ = [("nchares", c_i32), ("ntiles", c_i32), ("npseudo", c_i32), ("interior", c_i64),
                 ("halo_cells", c_i64), ("bytes_per_iter", c_i64), ("tile", c_i32 * 3), ("grid_wgs", c_i32),
-                ("field_bytes", c_i64), ("control_bytes", c_i64)]
+                ("schedule", c_i32), ("coop_waves", c_i32), ("field_bytes", c_i64), ("control_bytes", c_i64)]
 
 
 class od_tile_info(ctypes.Structure):

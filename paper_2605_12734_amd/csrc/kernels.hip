@@ -464,8 +464,17 @@ __device__ __forceinline__ bool xcd_barrier(unsigned int* bar, unsigned int* err
 // static form's tile index is uniform by construction, so its tile
 // descriptors stay in scalar registers (fewer VGPRs, more waves per SIMD);
 // the counter form keeps its own register allocation and occupancy.
+// Occupancy the persistent kernel is compiled for: without a request the
+// compiler took 106 SGPRs and 73-88 VGPRs (6 or 5 waves per SIMD); asking
+// for 7 (fp64) or 8 (fp32) waves fits it in 94 / 78 SGPRs and 70 / 64
+// VGPRs without spilling.
+template <typename T>
+struct PersistWaves {
+    static constexpr int value = sizeof(T) == 8 ? 7 : 8;
+};
+
 template <typename T, int TX, int TY, bool DYN>
-__global__ void __launch_bounds__((TX / V16<T>::N) * TY)
+__global__ void __launch_bounds__((TX / V16<T>::N) * TY) __attribute__((amdgpu_waves_per_eu(PersistWaves<T>::value, 8)))
 k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDev* __restrict__ tiles,
              int32_t ntiles, int parity, int64_t iters, unsigned long long* __restrict__ res, int32_t nres,
              unsigned int* bar, unsigned int* err, const ImbDev imb, int64_t iter_base, int64_t wait_ticks,
@@ -856,7 +865,8 @@ __device__ __forceinline__ void queue_loop(const MsgArgs& a, SweepFn sweep, doub
     const int x = (int)(__builtin_amdgcn_s_getreg(kXccIdReg) & 7);
     // every tile starts the launch at step d0 and ends it at tgt
     const int32_t tgt = ld_rlx(&a.target[0]), d0 = tgt - a.qsteps;
-    const bool cursor = use_cursor(a.ntiles, G);
+    const int claim_mode = a.sched & 3, pub_mode = (a.sched >> 2) & 3;
+    const bool cursor = claim_mode == 0 ? use_cursor(a.ntiles, G) : claim_mode == 1;
     // launch start: find the XCDs this launch runs on (and how many
     // workgroups each has), lay out the queues, mark the cross tiles and
     // queue every tile for its next step
@@ -897,8 +907,9 @@ __device__ __forceinline__ void queue_loop(const MsgArgs& a, SweepFn sweep, doub
                                                (uint64_t)s_m.n[threadIdx.x]);
     if (!grid_barrier(a.bar, a.err, a.wait_ticks)) return;
 
-    const bool haspub = use_publisher(__hip_atomic_load(&qc[kQcWgs + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                                      (uint32_t)s_m.n[x]);
+    const uint32_t xwgs = __hip_atomic_load(&qc[kQcWgs + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // a publisher needs at least one worker beside it on its XCD
+    const bool haspub = pub_mode == 0 ? use_publisher(xwgs, (uint32_t)s_m.n[x]) : (pub_mode == 1 && xwgs >= 2u);
     if (haspub && s_role) {
         if (threadIdx.x >= 64 || a.qsteps < 2) return;
         const uint32_t ncross = __hip_atomic_load(&qc[kQcCross + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1889,13 +1900,59 @@ __global__ void __launch_bounds__(256) k_stream(const u32x4* __restrict__ src, u
     }
 }
 
+// Chunked form: workgroup b streams its own contiguous range of `chunk`
+// vectors (a few large sequential streams, which HBM serves faster than an
+// interleaved grid stride), U accesses in flight per thread.
+template <int U, bool NT, int KIND>
+__global__ void __launch_bounds__(1024) k_stream_chunk(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
+                                                       int64_t n, int64_t chunk, uint32_t key,
+                                                       uint32_t* __restrict__ sink) {
+    const int64_t b0 = (int64_t)blockIdx.x * chunk;
+    const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
+    const int nt = blockDim.x;
+    u32x4 acc = {0u, 0u, 0u, 0u};
+    for (int64_t e = b0 + threadIdx.x; e < b1; e += (int64_t)U * nt) {
+        u32x4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t q = e + (int64_t)u * nt;
+            if (q < b1) {
+                if (KIND != 2) {
+                    v[u] = NT ? __builtin_nontemporal_load(src + q) : src[q];
+                } else {
+                    const uint32_t x = (uint32_t)q;
+                    v[u] = u32x4{x, x ^ key, x + key, ~x};
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t q = e + (int64_t)u * nt;
+            if (q < b1) {
+                if (KIND == 1)
+                    acc ^= v[u];
+                else if (NT)
+                    __builtin_nontemporal_store(v[u], dst + q);
+                else
+                    dst[q] = v[u];
+            }
+        }
+    }
+    if (KIND == 1) {
+        const uint32_t f = acc[0] ^ acc[1] ^ acc[2] ^ acc[3];
+        if (f == key) atomicOr(sink, 1u);
+    }
+}
+
 struct CopyVariant {
     int blocks_per_cu, unroll;
     bool nt;
+    int chunk_threads;   // 0: grid-stride, 256 threads; else chunked with this many threads
 };
-static const CopyVariant kCopyVariants[] = {{32, 1, false}, {16, 4, false}, {16, 4, true}, {64, 2, false},
-                                            {64, 2, true},  {8, 8, true},   {8, 8, false}, {32, 4, false},
-                                            {32, 4, true},  {4, 8, true}};
+static const CopyVariant kCopyVariants[] = {
+    {32, 1, false, 0}, {16, 4, false, 0}, {16, 4, true, 0},  {64, 2, false, 0},   {64, 2, true, 0},
+    {8, 8, true, 0},   {8, 8, false, 0},  {32, 4, false, 0}, {32, 4, true, 0},    {4, 8, true, 0},
+    {1, 8, true, 1024}, {2, 8, true, 1024}, {4, 4, true, 1024}, {8, 8, true, 512}, {1, 4, false, 1024}};
 
 int copy_variant_count() { return (int)(sizeof(kCopyVariants) / sizeof(kCopyVariants[0])); }
 
@@ -1907,6 +1964,28 @@ hipError_t launch_stream(hipStream_t st, void* dst, const void* src, size_t byte
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         ncu = 256;
     const CopyVariant& cv = kCopyVariants[variant % copy_variant_count()];
+    const uint32_t key0 = 0x9E3779B9u;
+    if (cv.chunk_threads > 0) {
+        int64_t grid = (int64_t)ncu * cv.blocks_per_cu;
+        const int64_t chunk = (n + grid - 1) / grid;
+        grid = (n + chunk - 1) / chunk;
+        if (grid < 1) grid = 1;
+        const u32x4* s4 = reinterpret_cast<const u32x4*>(src);
+        u32x4* d4 = reinterpret_cast<u32x4*>(dst);
+#define OD_CHUNK(UU, NTT, K)                                                                                   \
+        if (cv.unroll == UU && cv.nt == NTT && kind == K) {                                                    \
+            hipLaunchKernelGGL((k_stream_chunk<UU, NTT, K>), dim3((unsigned)grid), dim3(cv.chunk_threads), 0, st, \
+                               s4, d4, n, chunk, key0, sink);                                                  \
+            return hipGetLastError();                                                                          \
+        }
+#define OD_CHUNK_K(UU, NTT) OD_CHUNK(UU, NTT, 0) OD_CHUNK(UU, NTT, 1) OD_CHUNK(UU, NTT, 2)
+        OD_CHUNK_K(8, true)
+        OD_CHUNK_K(4, true)
+        OD_CHUNK_K(4, false)
+#undef OD_CHUNK_K
+#undef OD_CHUNK
+        return hipErrorInvalidValue;
+    }
     int64_t grid = (n + 255) / 256;
     const int64_t cap = (int64_t)ncu * cv.blocks_per_cu;
     if (grid > cap) grid = cap;

@@ -175,6 +175,10 @@ struct MsgArgs {
     ImbDev imb;                 // load-imbalance draw (heavy == 0: none)
     int64_t wait_ticks;         // bound on every device-side wait (wall-clock ticks)
     int32_t hints;              // od_config.hints (bit 2: schedule check, see kHintCheck)
+    // plain grids: scheduler choice, bits 0-1 claim mode (0 = automatic,
+    // 1 = cursor, 2 = ready queues), bits 2-3 publisher (0 = automatic,
+    // 1 = one per XCD with at least two workgroups, 2 = none)
+    int32_t sched;
     uint64_t seed;              // schedule check: seed of the perturbation
     int64_t pert_ticks;         // schedule check: largest delay (wall-clock ticks)
     // serving only

@@ -842,6 +842,7 @@ od_status Grid::msgdriven_launch(int64_t n) {
     a.hints = mode();
     a.seed = cfg.seed;
     a.pert_ticks = (cfg.hints & kHintCheck) ? device_wait_ticks(20e-6) : 0;
+    a.sched = msg_sched_bits();
     a.xpub = reinterpret_cast<uint8_t*>(cp(L.xpub));
     a.tile_pos = nullptr;
     a.bar = reinterpret_cast<unsigned int*>(cp(L.bar));

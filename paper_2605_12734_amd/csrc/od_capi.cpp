@@ -305,6 +305,8 @@ od_status od_plan(od_grid* g, od_plan_info* info) {
     info->bytes_per_iter = (int64_t)G.s * (2 * G.plan.interior + G.plan.halo_cells);
     for (int d = 0; d < 3; ++d) info->tile[d] = G.plan.tile[d];
     info->grid_wgs = G.grid_wgs;
+    info->schedule = G.cfg.exec == OD_PERSISTENT ? G.sched() : (G.cfg.exec == OD_MSGDRIVEN ? G.msg_sched_bits() : 0);
+    info->coop_waves = G.persist_waves;
     info->field_bytes = (int64_t)G.L.ctrl_begin;
     info->control_bytes = (int64_t)(G.L.total - G.L.ctrl_begin);
     return OD_OK;

@@ -60,6 +60,7 @@ struct Grid {
     // and 3; the autotuner may choose.
     int persist_sched = 0;
     int persist_waves = 0;           // cooperative waves per SIMD cap (0 = default)
+    int msg_sched = 0;               // message-driven scheduler choice (MsgArgs::sched)
     int sched() const {
         if (cfg.hints & 32) return 3;
         if (cfg.hints & 16) return 2;
@@ -109,7 +110,15 @@ struct Grid {
 
     ~Grid();
     // kernel mode bits: od_config.hints, plus bit 8 for the 5-point stencil
-    int mode() const { return cfg.hints | (cfg.stencil == 5 ? 0x100 : 0); }
+    int mode() const { return (cfg.hints & ~0x100) | (cfg.stencil == 5 ? 0x100 : 0); }
+    // message-driven scheduler bits (MsgArgs::sched): hints bits 6/7 force
+    // cursor / ready-queue claims, bits 9/10 a publisher on / off; else the
+    // tuner's choice (0 = automatic)
+    int msg_sched_bits() const {
+        int claim = (cfg.hints & 64) ? 1 : ((cfg.hints & 128) ? 2 : (msg_sched & 3));
+        int pub = (cfg.hints & 512) ? 1 : ((cfg.hints & 1024) ? 2 : ((msg_sched >> 2) & 3));
+        return claim | (pub << 2);
+    }
     od_status upload();
     od_status reset_state();
     od_status init_field();

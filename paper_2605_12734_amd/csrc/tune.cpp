@@ -1,13 +1,18 @@
-// Tile-shape autotuner for the fused sweep.
+// Autotuner: tile shape and, for the cooperative forms, the schedule.
 //
-// A candidate is a compiled (TX, TY) kernel variant plus a z-column length
-// TZ.  Every candidate evaluates each lattice point with the same
+// A tile candidate is a compiled (TX, TY) kernel variant plus a z-column
+// length TZ.  Every candidate evaluates each lattice point with the same
 // expression in the same order, so tuning can change the time but never a
-// bit of the result.  Candidates are timed on the grid itself by repeating
-// one sweep from the current parity into the spare parity (the current
-// field is never overwritten).  Results are cached per (dtype, exec mode,
-// chare-shape histogram) in the process and, if OD_TUNE_CACHE names a file,
-// on disk.
+// bit of the result.  Fused and graph grids time their fused sweep,
+// persistent grids their persistent kernel (one sweep per launch) under
+// each schedule (fixed stride, counters, counters with a guided tail) and
+// waves-per-SIMD cap (the kernel's register limit or one less); both repeat
+// one sweep from the current parity into the spare parity, so the field is
+// never overwritten.  Message-driven grids keep their tile (the dependency
+// lists are built for it) and time their scheduler choices over real steps
+// (the state is saved and restored).  Results are cached per (dtype, exec
+// mode, grid and chare-shape histogram) in the process and, if
+// OD_TUNE_CACHE names a file, on disk.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,7 +34,7 @@ namespace od {
 namespace {
 
 std::mutex g_cache_mu;
-std::map<std::string, std::array<int32_t, 3>> g_cache;
+std::map<std::string, std::array<int32_t, 5>> g_cache;   // tile x, y, z, schedule, waves cap
 bool g_cache_loaded = false;
 
 const int32_t kTz[] = {8, 16, 32, 64, 128};
@@ -42,6 +47,10 @@ std::string signature(const Grid& G) {
     std::ostringstream os;
     os << "s" << G.s << "/e" << (int)G.cfg.exec << "/n" << G.plan.n[0] << "x" << G.plan.n[1] << "x" << G.plan.n[2];
     for (const auto& kv : hist) os << "/" << kv.first[0] << "x" << kv.first[1] << "x" << kv.first[2] << ":" << kv.second;
+    // message-driven grids tune the scheduler at their own tile; schedule
+    // checks and load imbalance change what is timed
+    if (G.cfg.exec == OD_MSGDRIVEN) os << "/t" << G.plan.tile[0] << "x" << G.plan.tile[1] << "x" << G.plan.tile[2];
+    os << "/h" << (G.cfg.hints & ~1) << "/i" << G.cfg.imbalance_pct << "x" << G.cfg.imbalance_max_extra;
     return os.str();
 }
 
@@ -51,16 +60,22 @@ void load_file_cache() {
     const char* path = std::getenv("OD_TUNE_CACHE");
     if (!path) return;
     std::ifstream in(path);
-    std::string key;
-    int32_t a, b, c;
-    while (in >> key >> a >> b >> c) g_cache[key] = {a, b, c};
+    std::string line;
+    while (std::getline(in, line)) {
+        std::istringstream ls(line);
+        std::string key;
+        std::array<int32_t, 5> v = {0, 0, 0, 0, 0};
+        if (!(ls >> key >> v[0] >> v[1] >> v[2])) continue;
+        ls >> v[3] >> v[4];   // schedule and waves cap (absent in older entries: 0 = automatic)
+        g_cache[key] = v;
+    }
 }
 
-void store_file_cache(const std::string& key, const std::array<int32_t, 3>& t) {
+void store_file_cache(const std::string& key, const std::array<int32_t, 5>& t) {
     const char* path = std::getenv("OD_TUNE_CACHE");
     if (!path) return;
     std::ofstream out(path, std::ios::app);
-    out << key << " " << t[0] << " " << t[1] << " " << t[2] << "\n";
+    out << key << " " << t[0] << " " << t[1] << " " << t[2] << " " << t[3] << " " << t[4] << "\n";
 }
 
 }  // namespace
@@ -113,21 +128,109 @@ od_status Grid::retile(const int32_t tile[3]) {
     return OD_OK;
 }
 
+// Schedule state of a grid (persistent: schedule and waves cap;
+// message-driven: scheduler bits and waves cap) as cached.
+static void apply_schedule(Grid& G, int32_t sched, int32_t waves) {
+    if (G.cfg.exec == OD_MSGDRIVEN)
+        G.msg_sched = sched;
+    else
+        G.persist_sched = sched;
+    G.persist_waves = waves;
+}
+
+// Message-driven grids: the scheduler choices (claims from the per-XCD
+// cursor or from ready queues; a publisher workgroup per XCD or none) and
+// the waves-per-SIMD cap, at the grid's tile.  Each candidate runs a launch
+// of 2 * iters steps on the grid itself, so the field storage, the control
+// state and the iteration count are saved to host memory first and
+// restored afterwards.
+static od_status tune_msgdriven(Grid& G, int32_t iters, std::array<int32_t, 5>& best) {
+    hipError_t he = hipStreamSynchronize(G.st);
+    if (he != hipSuccess) return fail(OD_EHIP, std::string("sync: ") + hipGetErrorString(he));
+    const size_t fbytes = G.L.field_end, cbytes = G.L.total - G.L.ctrl_begin;
+    std::vector<char> ctrl_saved(cbytes);
+    od_status st = G.ensure_pinned(fbytes);
+    if (st != OD_OK) return st;
+    he = hipMemcpy(G.pinned, G.base, fbytes, hipMemcpyDeviceToHost);
+    if (he == hipSuccess) he = hipMemcpy(ctrl_saved.data(), G.ctrl, cbytes, hipMemcpyDeviceToHost);
+    if (he != hipSuccess) return fail(OD_EHIP, std::string("save state: ") + hipGetErrorString(he));
+    const int64_t iters0 = G.iters;
+    const int parity0 = G.parity;
+    const bool final0 = G.msg_final;
+    const int limit = coop_waves_limit(G.s, G.plan.tile[0], G.plan.tile[1], 1);
+    hipEvent_t a = nullptr, b = nullptr;
+    he = hipEventCreate(&a);
+    if (he == hipSuccess) he = hipEventCreate(&b);
+    float best_ms = 1e30f;
+    for (int claim = 1; claim <= 2 && he == hipSuccess && st == OD_OK; ++claim)
+        for (int pub = 1; pub <= 2 && he == hipSuccess && st == OD_OK; ++pub)
+            for (int w = limit; w >= std::max(1, limit - 1) && he == hipSuccess && st == OD_OK; --w) {
+                apply_schedule(G, claim | (pub << 2), w);
+                st = G.setup_cooperative(false);
+                if (st != OD_OK) break;
+                st = G.msgdriven_run(2);   // warm-up
+                if (st != OD_OK) break;
+                he = hipEventRecord(a, G.st);
+                if (he == hipSuccess) st = G.msgdriven_run(2 * (int64_t)iters);
+                if (he == hipSuccess && st == OD_OK) he = hipEventRecord(b, G.st);
+                if (he == hipSuccess && st == OD_OK) he = hipEventSynchronize(b);
+                float ms = 0;
+                if (he == hipSuccess && st == OD_OK) he = hipEventElapsedTime(&ms, a, b);
+                if (he == hipSuccess && st == OD_OK) st = G.device_error();
+                if (he == hipSuccess && st == OD_OK && ms < best_ms) {
+                    best_ms = ms;
+                    best = {G.plan.tile[0], G.plan.tile[1], G.plan.tile[2], claim | (pub << 2), w};
+                }
+            }
+    if (a) hipEventDestroy(a);
+    if (b) hipEventDestroy(b);
+    // restore the grid as it was, with the chosen schedule
+    hipError_t he2 = hipStreamSynchronize(G.st);
+    if (he2 == hipSuccess) he2 = hipMemcpy(G.base, G.pinned, fbytes, hipMemcpyHostToDevice);
+    if (he2 == hipSuccess) he2 = hipMemcpy(G.ctrl, ctrl_saved.data(), cbytes, hipMemcpyHostToDevice);
+    G.iters = iters0;
+    G.parity = parity0;
+    G.msg_final = final0;
+    if (he != hipSuccess) return fail(OD_EHIP, std::string("tuning launch: ") + hipGetErrorString(he));
+    if (he2 != hipSuccess) return fail(OD_EHIP, std::string("restore state: ") + hipGetErrorString(he2));
+    if (st != OD_OK) return st;
+    apply_schedule(G, best[3], best[4]);
+    return G.setup_cooperative(false);
+}
+
 od_status autotune(Grid& G, int32_t iters, int32_t out_tile[3]) {
-    if (G.cfg.exec != OD_FUSED && G.cfg.exec != OD_GRAPH && G.cfg.exec != OD_PERSISTENT)
-        return fail(OD_EINVAL, "autotune applies to OD_FUSED, OD_GRAPH and OD_PERSISTENT grids; create other "
-                               "modes with cfg.tile set to a tuned shape");
+    if (G.cfg.exec == OD_PER_CHARE)
+        return fail(OD_EINVAL, "autotune does not apply to OD_PER_CHARE grids; create them with cfg.tile set to a "
+                               "tuned shape");
+    if (iters < 1) return fail(OD_EINVAL, "iters must be >= 1");
     const std::string key = signature(G);
     {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         load_file_cache();
         auto it = g_cache.find(key);
         if (it != g_cache.end()) {
-            od_status s = G.retile(it->second.data());
+            const std::array<int32_t, 5> c = it->second;
+            apply_schedule(G, c[3], c[4]);
+            od_status s = G.cfg.exec == OD_MSGDRIVEN ? G.setup_cooperative(false) : G.retile(c.data());
             if (s == OD_OK && out_tile)
                 for (int d = 0; d < 3; ++d) out_tile[d] = G.plan.tile[d];
             return s;
         }
+    }
+    if (G.cfg.exec == OD_MSGDRIVEN) {
+        // the dependency lists are built for the planned tiles: the tile
+        // stays, the scheduler is tuned
+        std::array<int32_t, 5> best = {G.plan.tile[0], G.plan.tile[1], G.plan.tile[2], 0, 0};
+        od_status s = tune_msgdriven(G, iters, best);
+        if (s != OD_OK) return s;
+        {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            g_cache[key] = best;
+            store_file_cache(key, best);
+        }
+        if (out_tile)
+            for (int d = 0; d < 3; ++d) out_tile[d] = G.plan.tile[d];
+        return OD_OK;
     }
     hipError_t he = hipStreamSynchronize(G.st);
     if (he != hipSuccess) return fail(OD_EHIP, std::string("sync: ") + hipGetErrorString(he));
@@ -163,39 +266,71 @@ od_status autotune(Grid& G, int32_t iters, int32_t out_tile[3]) {
     if (he == hipSuccess) he = hipEventCreate(&b);
     if (he != hipSuccess) return fail(OD_EHIP, std::string("event: ") + hipGetErrorString(he));
     const int32_t start_tile[3] = {G.plan.tile[0], G.plan.tile[1], G.plan.tile[2]};
+    const int32_t start_sched = G.persist_sched, start_waves = G.persist_waves;
     float best_ms = 1e30f;
-    std::array<int32_t, 3> best = {start_tile[0], start_tile[1], start_tile[2]};
+    std::array<int32_t, 5> best = {start_tile[0], start_tile[1], start_tile[2], start_sched, start_waves};
     od_status st = OD_OK;
-    for (const auto& c : cands) {
-        if (G.retile(c.data()) != OD_OK) continue;   // e.g. over the tile capacity
+    const bool pers = G.cfg.exec == OD_PERSISTENT;
+    // persistent schedules: fixed stride (1), counters (2), counters with a
+    // guided tail (3); hints bits 4/5 fix the schedule
+    std::vector<int32_t> scheds = {0};
+    if (pers) scheds = (G.cfg.hints & 48) ? std::vector<int32_t>{0} : std::vector<int32_t>{1, 2, 3};
+    auto time_it = [&](float* ms_out) -> hipError_t {
         auto launch = [&]() {
+            if (pers)   // one sweep per launch (no barrier): the field stays as it is
+                return launch_persistent(G.s, G.plan.tile[0], G.plan.tile[1], G.st, G.grid_wgs, G.base,
+                                         reinterpret_cast<const BlockDev*>(G.cp(G.L.blocks)),
+                                         reinterpret_cast<const TileDev*>(G.cp(G.L.tiles)), (int32_t)G.tiles_h.size(),
+                                         G.parity, 1, G.res_ptr(), 1, reinterpret_cast<unsigned int*>(G.cp(G.L.bar)),
+                                         reinterpret_cast<unsigned int*>(G.cp(G.L.err)), G.imb, G.iters, G.mode(),
+                                         G.persistent_dyn() ? 1 : 0, device_wait_ticks(10.0));
             return launch_sweep(G.s, G.plan.tile[0], G.plan.tile[1], G.st, G.base,
                                 reinterpret_cast<const BlockDev*>(G.cp(G.L.blocks)),
                                 reinterpret_cast<const TileDev*>(G.cp(G.L.tiles)), (int32_t)G.tiles_h.size(),
                                 G.parity, G.res_ptr(), 0, 1, ImbDev{}, 0, G.mode());
         };
-        he = launch();   // warm-up
-        if (he == hipSuccess) he = hipEventRecord(a, G.st);
-        for (int32_t i = 0; i < iters && he == hipSuccess; ++i) he = launch();
-        if (he == hipSuccess) he = hipEventRecord(b, G.st);
-        if (he == hipSuccess) he = hipEventSynchronize(b);
-        float ms = 0;
-        if (he == hipSuccess) he = hipEventElapsedTime(&ms, a, b);
-        if (he != hipSuccess) {
-            st = fail(OD_EHIP, std::string("tuning launch: ") + hipGetErrorString(he));
-            break;
+        hipError_t e = launch();   // warm-up
+        if (e == hipSuccess) e = hipEventRecord(a, G.st);
+        for (int32_t i = 0; i < iters && e == hipSuccess; ++i) e = launch();
+        if (e == hipSuccess) e = hipEventRecord(b, G.st);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        if (e == hipSuccess) e = hipEventElapsedTime(ms_out, a, b);
+        return e;
+    };
+    for (const auto& c : cands) {
+        if (G.retile(c.data()) != OD_OK) continue;   // e.g. over the tile capacity
+        for (int32_t sc : scheds) {
+            const int kind = sc >= 2 ? 2 : 0;
+            const int limit = pers ? coop_waves_limit(G.s, G.plan.tile[0], G.plan.tile[1], kind) : 0;
+            for (int w = limit; w >= (pers ? std::max(1, limit - 1) : 0); --w) {
+                if (pers) {
+                    apply_schedule(G, sc, w);
+                    if (G.setup_cooperative(false) != OD_OK) continue;
+                }
+                float ms = 0;
+                he = time_it(&ms);
+                if (he != hipSuccess) {
+                    st = fail(OD_EHIP, std::string("tuning launch: ") + hipGetErrorString(he));
+                    break;
+                }
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = {c[0], c[1], c[2], pers ? sc : 0, pers ? w : 0};
+                }
+                if (!pers) break;
+            }
+            if (st != OD_OK) break;
         }
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = c;
-        }
+        if (st != OD_OK) break;
     }
     hipEventDestroy(a);
     hipEventDestroy(b);
     if (st != OD_OK) {
+        apply_schedule(G, start_sched, start_waves);
         G.retile(start_tile);
         return st;
     }
+    apply_schedule(G, best[3], best[4]);
     st = G.retile(best.data());
     if (st != OD_OK) return st;
     he = hipMemcpy(G.cp(G.L.res), saved.data(), saved.size() * 8, hipMemcpyHostToDevice);
