@@ -89,7 +89,7 @@ def load_traffic(key: str):
     return e.get("bytes_per_launch")
 
 
-SCHEDULES = {1: "stride", 2: "counters", 3: "counters+guided-tail"}
+SCHEDULES = {1: "stride", 2: "counters", 3: "counters+guided-tail", 4: "runs"}
 
 
 def msg_tile(tile):
@@ -238,12 +238,12 @@ def odf_sweep(n, iters, persistent=True):
     return rows
 
 
-def amr_leg(iters=500):
+def amr_leg(iters=500, multires_only=False):
     import workloads
 
     blocks = workloads.octree_blocks(n=768, root=128, min_edge=16, p_refine=0.4, seed=12734)
     out = {"blocks": len(blocks), "edges": sorted({e[0] for _, e in blocks})}
-    for exec_ in ("graph", "persistent"):
+    for exec_ in () if multires_only else ("graph", "persistent"):
         g = make_grid(768, blocks=blocks, dtype="f64", exec_=exec_)
         try:
             plan = g.plan()
@@ -478,6 +478,8 @@ def main():
     ap.add_argument("--imb-iters", type=int, default=1000)
     ap.add_argument("--amr-iters", type=int, default=500)
     ap.add_argument("--amr", action="store_true", help="with --quick: run the octree leg too")
+    ap.add_argument("--amr-multires-only", action="store_true",
+                    help="octree leg: only the multi-resolution grid")
     ap.add_argument("--jacobi2d", action="store_true")
     ap.add_argument("--launch", action="store_true")
     ap.add_argument("--serving-count", type=int, default=128)
@@ -549,7 +551,7 @@ def main():
     if not args.no_sweep and not args.quick:
         legs.append(("odf_sweep", lambda: odf_sweep(args.n, args.iters)))
     if (args.amr or not args.quick) and not args.no_amr:
-        legs.append(("amr_octree_768", lambda: amr_leg(args.amr_iters)))
+        legs.append(("amr_octree_768", lambda: amr_leg(args.amr_iters, args.amr_multires_only)))
     if not args.quick and not args.no_imbalance:
         legs.append(("imbalance_1024", lambda: imbalance_leg(args.imb_iters)))
     if not args.quick and not args.no_serving:

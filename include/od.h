@@ -134,7 +134,9 @@ typedef struct {
      * from ready queues (default: cursor with >= 4 tiles per workgroup);
      * bits 9 / 10 (OD_MSGDRIVEN): one publisher workgroup per XCD / none
      * (default: a publisher on XCDs with >= 8 workgroups and >= 2 tasks
-     * per workgroup and step).  Bit 8 is reserved.
+     * per workgroup and step);
+     * bit 11 (OD_PERSISTENT): fixed schedule with contiguous runs of each
+     * XCD group's tiles per workgroup.  Bit 8 is reserved.
      * Other bits are ignored. */
     int32_t hints;
     /* 7 (or 0): 3D 7-point stencil.  5: the 2D 5-point stencil of the
@@ -278,7 +280,8 @@ typedef struct {
     int32_t tile[3];                /* tile shape in use                              */
     int32_t grid_wgs;               /* workgroups of the persistent / msg-driven launch */
     int32_t schedule;               /* OD_PERSISTENT: 1 fixed stride, 2 per-XCD counters,
-                                       3 counters with a guided tail; OD_MSGDRIVEN:
+                                       3 counters with a guided tail, 4 fixed
+                                       contiguous runs; OD_MSGDRIVEN:
                                        bits 0-1 claims (0 automatic, 1 cursor, 2 ready
                                        queues), bits 2-3 publisher (0 automatic, 1 on,
                                        2 off); else 0                                  */
@@ -392,15 +395,15 @@ od_status od_launch_overlap(void* dev_ws, size_t ws_bytes, int64_t total_threads
  * Autotuning: tile shape and schedule.  Every candidate computes the same
  * arithmetic; only the tile shape, the schedule and the launch shape
  * differ.  OD_FUSED and OD_GRAPH grids time `iters` fused sweeps per tile
- * candidate; OD_PERSISTENT grids time their persistent kernel (one sweep
- * per launch) for every tile candidate under each schedule (fixed stride,
- * per-XCD counters, counters with a guided tail) and waves-per-SIMD cap
- * (the kernel's register limit or one less); these sweeps write only the
- * spare parity, so the field is unchanged.  OD_MSGDRIVEN grids keep their
- * tile and time their scheduler choices (cursor or ready-queue claims,
- * publisher or none, waves cap) over 2 * iters real steps each, with the
- * field, device state and iteration count saved to host memory and
- * restored.  The fastest choice is applied and cached per (dtype, mode,
+ * candidate (each writes only the spare parity, so the field is
+ * unchanged).  OD_PERSISTENT grids time a launch of 2 * iters iterations
+ * for every tile candidate under each schedule (fixed stride, fixed runs,
+ * per-XCD counters, counters with a guided tail) and waves-per-SIMD cap (the
+ * kernel's register limit or one less).  OD_MSGDRIVEN grids keep their tile
+ * and time their scheduler choices (cursor or ready-queue claims,
+ * publisher or none, waves cap) over 2 * iters steps each.  For these two,
+ * the field, the device state and the iteration count are saved to pinned
+ * host memory first and restored afterwards.  The fastest choice is applied and cached per (dtype, mode,
  * grid and chare shapes, hints, imbalance).  OD_PER_CHARE: OD_EINVAL.
  * `out_tile` receives the chosen shape; od_plan reports the schedule. */
 od_status od_autotune(struct od_grid* g, int32_t iters, int32_t out_tile[3]);

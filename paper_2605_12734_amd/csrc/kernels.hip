@@ -107,10 +107,12 @@ struct SW {
     static_assert(NT % 64 == 0 && NT <= 1024, "threads must be whole waves");
 };
 
-template <typename T, int TX, int TY>
+// XEXP: also write the tile's new x = 0 / x = ex - 1 column into the
+// chare's x-column exports (multi-resolution grids; XExpDev).
+template <typename T, int TX, int TY, bool XEXP = false>
 __device__ __forceinline__ T sweep_tile(T* __restrict__ arena, const BlockDev* __restrict__ blocks,
                                         const TileDev& t, const int parity, T* __restrict__ lds,
-                                        const int hints) {
+                                        const int hints, const XExpDev* __restrict__ xexp = nullptr) {
     using S = SW<T, TX, TY>;
     using VT = typename V16<T>::t;
     constexpr int VX = S::VX;
@@ -147,6 +149,17 @@ __device__ __forceinline__ T sweep_tile(T* __restrict__ arena, const BlockDev* _
     const char* own_b = ab + ((parity ? B->off[1] : B->off[0]) + tile_el) * ES;
     char* dst_b = reinterpret_cast<char*>(arena) + ((parity ? B->off[0] : B->off[1]) + tile_el) * ES;
     const uint32_t o_own = (uint32_t)((xc + (int64_t)lc * own_py) * ES);
+    // x-column exports of the parity this sweep writes (uniform per tile)
+    T* xe_m = nullptr;
+    T* xe_p = nullptr;
+    int64_t xe_ey = 0;
+    if constexpr (XEXP) {
+        const XExpDev& X = xexp[t.blk];
+        const int64_t om = parity ? X.off[0][0] : X.off[0][1], op = parity ? X.off[1][0] : X.off[1][1];
+        if (t.x0 == 0 && om >= 0) xe_m = arena + om;
+        if (t.x0 + t.nx == B->ex && op >= 0) xe_p = arena + op;
+        xe_ey = B->ey;
+    }
 
     // face f: uniform base at its ghost slab's first cell, uniform plane pitch
     auto face = [&](const FaceDev& f, int64_t* fpy, int64_t* fpz) -> const char* {
@@ -302,6 +315,17 @@ __device__ __forceinline__ T sweep_tile(T* __restrict__ arena, const BlockDev* _
                     if (d > r) r = d;
                 }
             }
+            if constexpr (XEXP) {
+                const int64_t e = (int64_t)(t.y0 + ly) + (int64_t)(t.z0 + z) * xe_ey;
+                if (xe_m && lx == 0) xe_m[e] = out[0];
+                if (xe_p && x + VX > nx - 1) {
+                    T v = out[0];
+#pragma unroll
+                    for (int i = 1; i < VX; ++i)
+                        if (i == nx - 1 - x) v = out[i];
+                    xe_p[e] = v;
+                }
+            }
             // a partial vector only occurs at the chare's row end, where the
             // lanes past nx land in the row's padding: store the whole vector
             VT* o = reinterpret_cast<VT*>(dst_b + (int64_t)z * own_pz * ES + o_own);
@@ -327,11 +351,11 @@ __device__ __forceinline__ T sweep_tile(T* __restrict__ arena, const BlockDev* _
     return r;
 }
 
-template <typename T, int TX, int TY>
+template <typename T, int TX, int TY, bool XEXP = false>
 __global__ void __launch_bounds__((TX / V16<T>::N) * TY)
 k_sweep(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDev* __restrict__ tiles,
         int parity, unsigned long long* __restrict__ res, int zero_lo, int zero_hi,
-        const ImbDev imb, int64_t step, int hints) {
+        const ImbDev imb, int64_t step, int hints, const XExpDev* __restrict__ xexp) {
     using S = SW<T, TX, TY>;
     __shared__ T lds[S::LDS];
     __shared__ T red[S::NT / 64];
@@ -340,7 +364,8 @@ k_sweep(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDe
     const TileDev& t = tiles[blockIdx.x];
     const int reps = 1 + imb_extra(imb, step, t.blk);
     T r = 0;
-    for (int rep = 0; rep < reps; ++rep) r = sweep_tile<T, TX, TY>(arena, blocks, t, parity, lds, hints);
+    for (int rep = 0; rep < reps; ++rep)
+        r = sweep_tile<T, TX, TY, XEXP>(arena, blocks, t, parity, lds, hints, xexp);
     wg_residual<T, S::NT>(r, &res[2 * t.rslot + (parity ^ 1)], red);
 }
 
@@ -478,15 +503,32 @@ __global__ void __launch_bounds__((TX / V16<T>::N) * TY) __attribute__((amdgpu_w
 k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDev* __restrict__ tiles,
              int32_t ntiles, int parity, int64_t iters, unsigned long long* __restrict__ res, int32_t nres,
              unsigned int* bar, unsigned int* err, const ImbDev imb, int64_t iter_base, int64_t wait_ticks,
-             int hints, unsigned long long* __restrict__ stamps) {
+             int hints, unsigned long long* __restrict__ stamps, int chunked) {
     using S = SW<T, TX, TY>;
     __shared__ T lds[S::LDS];
     __shared__ T red[S::NT / 64];
     __shared__ int32_t s_idx;
-    // XCD groups: launch index w runs on XCD w % 8 and takes tiles of list
-    // positions = w (mod 8), the spatial chunk the planner gave that XCD
+    // XCD groups: launch index w runs on XCD w % 8 (cooperative launches
+    // place workgroups like plain ones; checked with HW_REG_XCC_ID) and takes
+    // tiles of list positions = w (mod 8), the spatial chunk the planner gave
+    // that XCD.  Slots are taken in launch order (w / 8, then + G / 8):
+    // assigning them in the order workgroups registered instead measured
+    // 20 % more HBM reads.
     const int ng = (gridDim.x >= 8 && gridDim.x % 8 == 0) ? 8 : 1;
     const int xg = (int)(blockIdx.x % ng);
+    int32_t first = (int32_t)(blockIdx.x / ng);
+    int32_t step_w = (int32_t)(gridDim.x / ng);
+    // chunked static schedule: slot k of the group's W slots takes a
+    // contiguous run of the group's positions (spatial neighbours in a row)
+    int32_t last = INT32_MAX;
+    if (!DYN && chunked) {
+        const int32_t W = (int32_t)(gridDim.x / ng);
+        const int32_t npos = ntiles > xg ? (ntiles - xg + ng - 1) / ng : 0;
+        const int32_t k = (int32_t)(blockIdx.x / ng);
+        first = (int32_t)((int64_t)npos * k / W);
+        last = (int32_t)((int64_t)npos * (k + 1) / W);
+        step_w = 1;
+    }
     // register on this workgroup's XCD (bar[40 + x] counts them), then one
     // full barrier so every count is final
     __shared__ int s_xcd;
@@ -529,12 +571,13 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
                 s_idx = (int32_t)__hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __syncthreads();
         }
-        // uniform by construction: the tile descriptor stays in scalar registers
-        int32_t idx = DYN ? __builtin_amdgcn_readfirstlane(s_idx) : (int32_t)blockIdx.x;
+        // uniform by construction: the tile descriptor stays in scalar
+        // registers.  idx counts group slots: list position xg + ng * idx
+        int32_t idx = DYN ? __builtin_amdgcn_readfirstlane(s_idx) : first;
         for (;;) {
-            const int32_t ti = DYN ? xg + ng * idx : idx;
-            if (ti >= ntiles) break;
-            int32_t nxt = idx + (int32_t)gridDim.x;
+            const int32_t ti = xg + ng * idx;
+            if (ti >= ntiles || idx >= last) break;
+            int32_t nxt = idx + step_w;
             if (DYN && threadIdx.x == 0)
                 nxt = (int32_t)__hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const TileDev& t = tiles[ti];
@@ -1333,13 +1376,19 @@ int sweep_threads(int dtype_bytes, int tx, int ty) {
 
 hipError_t launch_sweep(int dtype_bytes, int tx, int ty, hipStream_t st, void* arena, const BlockDev* blocks,
                         const TileDev* tiles, int32_t ntiles, int parity, unsigned long long* res,
-                        int32_t zero_lo, int32_t zero_hi, const ImbDev& imb, int64_t step, int hints) {
+                        int32_t zero_lo, int32_t zero_hi, const ImbDev& imb, int64_t step, int hints,
+                        const XExpDev* xexp) {
     if (ntiles <= 0) return hipSuccess;
 #define OD_LAUNCH(T, TX, TY)                                                                          \
     if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                      \
-        hipLaunchKernelGGL((k_sweep<T, TX, TY>), dim3(ntiles), dim3(SW<T, TX, TY>::NT), 0, st,       \
-                           reinterpret_cast<T*>(arena), blocks, tiles, parity, res, zero_lo, zero_hi, \
-                           imb, step, hints);                                                         \
+        if (xexp)                                                                                     \
+            hipLaunchKernelGGL((k_sweep<T, TX, TY, true>), dim3(ntiles), dim3(SW<T, TX, TY>::NT), 0, st, \
+                               reinterpret_cast<T*>(arena), blocks, tiles, parity, res, zero_lo, zero_hi, \
+                               imb, step, hints, xexp);                                               \
+        else                                                                                          \
+            hipLaunchKernelGGL((k_sweep<T, TX, TY, false>), dim3(ntiles), dim3(SW<T, TX, TY>::NT), 0, st, \
+                               reinterpret_cast<T*>(arena), blocks, tiles, parity, res, zero_lo, zero_hi, \
+                               imb, step, hints, xexp);                                               \
         return hipGetLastError();                                                                     \
     }
     OD_VARIANTS_F64(OD_LAUNCH)
@@ -1416,14 +1465,14 @@ hipError_t launch_persistent(int dtype_bytes, int tx, int ty, hipStream_t st, in
                              const BlockDev* blocks, const TileDev* tiles, int32_t ntiles, int parity,
                              int64_t iters, unsigned long long* res, int32_t nres, unsigned int* bar,
                              unsigned int* err, const ImbDev& imb, int64_t iter_base, int hints, int dyn,
-                             int64_t wait_ticks, unsigned long long* stamps) {
+                             int64_t wait_ticks, unsigned long long* stamps, int chunked) {
     if (iters <= 0) return hipSuccess;
 #define OD_LAUNCH(T, TX, TY)                                                                          \
     if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                      \
         T* ar = reinterpret_cast<T*>(arena);                                                          \
         ImbDev im = imb;                                                                              \
         void* args[] = {&ar, &blocks, &tiles, &ntiles, &parity, &iters, &res, &nres, &bar, &err,      \
-                        &im, &iter_base, &wait_ticks, &hints, &stamps};                               \
+                        &im, &iter_base, &wait_ticks, &hints, &stamps, &chunked};                     \
         const void* fn = dyn ? reinterpret_cast<const void*>(k_persistent<T, TX, TY, true>)           \
                              : reinterpret_cast<const void*>(k_persistent<T, TX, TY, false>);         \
         return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(SW<T, TX, TY>::NT), args, 0, st);      \
@@ -1569,8 +1618,12 @@ k_amr_fill(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const Fil
         const FillSeg& S = segs[sg];
         const int d = S.d, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
         const BlockDev& N = blocks[S.src];
-        const int64_t nb = (parity ? N.off[1] : N.off[0]) + (int64_t)S.lay * (d == 0 ? 1 : d == 1 ? N.py : N.pz);
-        const int64_t s1 = t1 == 0 ? 1 : N.py, s2 = t2 == 1 ? N.py : N.pz;
+        const int64_t eo = parity ? S.eoff[1] : S.eoff[0];
+        // x-normal faces read the neighbour's exported column when it has one
+        const int64_t nb = eo >= 0 ? eo
+                                   : (parity ? N.off[1] : N.off[0]) + (int64_t)S.lay * (d == 0 ? 1 : d == 1 ? N.py : N.pz);
+        const int64_t s1 = eo >= 0 ? 1 : (t1 == 0 ? 1 : N.py);
+        const int64_t s2 = eo >= 0 ? (int64_t)S.ey : (t2 == 1 ? N.py : N.pz);
         const BlockDev& D = blocks[S.dst];
         const int64_t ds1 = t1 == 0 ? 1 : D.py, ds2 = t2 == 1 ? D.py : D.pz;
         const int32_t rr = S.hc >> S.lhn, r = rr > 1 ? rr : 1, R = r * r;
@@ -1722,6 +1775,36 @@ hipError_t launch_init_cells(int dtype_bytes, hipStream_t st, const GridDev& g, 
         hipLaunchKernelGGL(k_init_cells<double>, grid, dim3(256), 0, st, g, ccell, nchares, seed);
     else
         hipLaunchKernelGGL(k_init_cells<float>, grid, dim3(256), 0, st, g, ccell, nchares, seed);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_xexp_refresh(T* __restrict__ arena, const BlockDev* __restrict__ blocks,
+                               const XExpDev* __restrict__ xexp, int32_t nchares, int parity) {
+    for (int32_t q = blockIdx.y; q < 2 * nchares; q += gridDim.y) {
+        const int32_t c = q >> 1, side = q & 1;
+        const int64_t eo = xexp[c].off[side][parity];
+        if (eo < 0) continue;
+        const BlockDev& B = blocks[c];
+        const int64_t base = (parity ? B.off[1] : B.off[0]) + (side ? B.ex - 1 : 0);
+        const int64_t cnt = (int64_t)B.ey * B.ez;
+        for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * blockDim.x) {
+            const int64_t y = e % B.ey, z = e / B.ey;
+            arena[eo + e] = arena[base + y * B.py + z * B.pz];
+        }
+    }
+}
+
+hipError_t launch_xexp_refresh(int dtype_bytes, hipStream_t st, void* arena, const BlockDev* blocks,
+                               const XExpDev* xexp, int32_t nchares, int parity) {
+    if (!xexp || nchares <= 0) return hipSuccess;
+    const dim3 grid(4, (unsigned)std::min<int32_t>(2 * nchares, 65535));
+    if (dtype_bytes == 8)
+        hipLaunchKernelGGL(k_xexp_refresh<double>, grid, dim3(256), 0, st, reinterpret_cast<double*>(arena), blocks,
+                           xexp, nchares, parity);
+    else
+        hipLaunchKernelGGL(k_xexp_refresh<float>, grid, dim3(256), 0, st, reinterpret_cast<float*>(arena), blocks,
+                           xexp, nchares, parity);
     return hipGetLastError();
 }
 

@@ -102,10 +102,12 @@ int sweep_threads(int dtype_bytes, int tx, int ty);
 // value's bit pattern) into res[2*rslot + (parity^1)]; workgroup 0 first
 // zeroes res[2*s + parity] for s in [zero_lo, zero_hi).  `imb`, `step`:
 // the load-imbalance draw of this step (imb.heavy == 0: none).
+// xexp (may be null): multi-resolution x-column exports (XExpDev, per chare).
+struct XExpDev;
 hipError_t launch_sweep(int dtype_bytes, int tx, int ty, hipStream_t st, void* arena,
                         const BlockDev* blocks, const TileDev* tiles, int32_t ntiles, int parity,
                         unsigned long long* res, int32_t zero_lo, int32_t zero_hi,
-                        const ImbDev& imb, int64_t step, int hints);
+                        const ImbDev& imb, int64_t step, int hints, const XExpDev* xexp = nullptr);
 
 // Persistent cooperative sweep: all `iters` iterations in one launch with a
 // device-wide barrier between them.  dyn != 0: workgroups take tiles from
@@ -118,6 +120,8 @@ hipError_t launch_sweep(int dtype_bytes, int tx, int ty, hipStream_t st, void* a
 // workgroups' results (the XCD's workgroups share that L2).  `err` = error
 // flag.  `imb`: load-imbalance draw, iteration `it` of the launch is step
 // iter_base + it.
+// chunked (fixed-stride form): each workgroup takes a contiguous run of its
+// XCD group's positions instead of every G/8-th one.
 // `stamps` (may be null): timeline of the first kStampIters iterations, 4
 // wall-clock words per iteration (first / last workgroup to start it,
 // first / last to finish its tiles), prepared by launch_stamp_init.
@@ -128,7 +132,7 @@ hipError_t launch_persistent(int dtype_bytes, int tx, int ty, hipStream_t st, in
                              int32_t ntiles, int parity, int64_t iters,
                              unsigned long long* res, int32_t nres, unsigned int* bar,
                              unsigned int* err, const ImbDev& imb, int64_t iter_base, int hints, int dyn,
-                             int64_t wait_ticks, unsigned long long* stamps = nullptr);
+                             int64_t wait_ticks, unsigned long long* stamps = nullptr, int chunked = 0);
 hipError_t launch_stamp_init(hipStream_t st, unsigned long long* stamps, int32_t n);
 // hints bit 3 (persistent form): record the timeline above.
 constexpr int kHintTimeline = 8;
@@ -256,8 +260,28 @@ struct FillSeg {
     int32_t r1, r2;         // neighbour-relative unit offset of ghost cell (a1, a2)
     int32_t hc, lhn;        // ghost cell edge (units), log2 neighbour cell edge
     int64_t first;          // index of the rectangle's first ghost cell over all rectangles
+    // x-normal faces (d == 0): the neighbour's exported column of layer
+    // `lay` for each parity (element offsets, see XExpDev) and its y extent;
+    // the values are read from there, y fastest, instead of one per row of
+    // the neighbour's storage
+    int64_t eoff[2];
+    int32_t ey, pad_;
 };
-static_assert(sizeof(FillSeg) == 56, "FillSeg layout");
+static_assert(sizeof(FillSeg) == 80, "FillSeg layout");
+
+// Multi-resolution grids: a chare's boundary x-column (x = 0 or ex - 1)
+// that a neighbour of another cell size fills its ghosts from.  The fused
+// sweep writes it, for the parity it produces, into a contiguous (y, z)
+// array (y fastest) while the values are in registers, so the ghost fill
+// reads whole sectors instead of one value per 64-byte row.  Element
+// offsets from the arena base, -1 where no neighbour reads that column.
+struct XExpDev {
+    int64_t off[2][2];   // [side: 0 = x-, 1 = x+][parity]
+};
+// Copy the x-columns of parity `parity` into their exports (after the field
+// is initialised or written from the host).
+hipError_t launch_xexp_refresh(int dtype_bytes, hipStream_t st, void* arena, const BlockDev* blocks,
+                               const XExpDev* xexp, int32_t nchares, int parity);
 
 // Fill every resolution-change ghost buffer from parity `parity` of the
 // chares: one single-wave workgroup per rectangle segs[0..nseg); `total` (ghost cells

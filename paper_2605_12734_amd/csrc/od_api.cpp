@@ -144,6 +144,7 @@ int64_t build_fill_segments(Grid& G) {
                         S.hc = c.h;
                         S.lhn = log2i(N.h);
                         S.first = G.fill_total;
+                        S.eoff[0] = S.eoff[1] = -1;   // no export (set by build_layout)
                         const int64_t cells = (int64_t)S.n1 * S.n2;
                         G.fill_total += cells;
                         const int64_t r = N.h < c.h ? c.h / N.h : 1;
@@ -387,6 +388,24 @@ std::string build_layout(const od_config& cfg, Grid& G) {
                 if (t.kind[f] == 0) direct += (int64_t)t.e[0] * t.e[1] * t.e[2] / t.e[f / 2];
         p.halo_cells = direct + reads;
     }
+    // ---- x-column exports of the chares a resolution-change x face reads:
+    // per (chare, side) one (y, z) array per parity, written by the sweep
+    G.xexp_h.clear();
+    if (!G.segs_h.empty()) {
+        G.xexp_h.assign((size_t)C, XExpDev{{{-1, -1}, {-1, -1}}});
+        for (FillSeg& S : G.segs_h) {
+            if (S.d != 0) continue;
+            const Chare& N = p.chares[(size_t)S.src];
+            const int side = S.lay == 0 ? 0 : (S.lay == N.e[0] - 1 ? 1 : -1);
+            if (side < 0) continue;
+            XExpDev& X = G.xexp_h[(size_t)S.src];
+            if (X.off[side][0] < 0)
+                for (int q = 0; q < 2; ++q) X.off[side][q] = (int64_t)(cv.take((size_t)N.e[1] * N.e[2] * s) / s);
+            S.eoff[0] = X.off[side][0];
+            S.eoff[1] = X.off[side][1];
+            S.ey = N.e[1];
+        }
+    }
     // ---- control regions: descriptors and device state
     G.L.field_end = align_up(cv.off, kAlign);
     cv.off = G.L.field_end;
@@ -452,6 +471,7 @@ std::string build_layout(const od_config& cfg, Grid& G) {
     G.L.dep_ptr = cv.take((G.dep_ptr.size() + 1) * 4);
     G.L.dep_idx = cv.take((G.dep_idx.size() + 1) * 4);
     G.L.segs = cv.take(std::max<size_t>(G.segs_h.size(), 1) * sizeof(FillSeg));
+    G.L.xexp = cv.take(std::max<size_t>(G.xexp_h.size(), 1) * sizeof(XExpDev));
     G.L.total = align_up(cv.off, kAlign) + kAlign;
     return fill_tile_descs(G);
 }
@@ -657,6 +677,7 @@ od_status Grid::upload() {
     if (e == hipSuccess) e = put(L.corigin, corigin.data(), corigin.size() * 4);
     if (e == hipSuccess) e = put(L.ccell, ccell.data(), ccell.size() * 4);
     if (e == hipSuccess) e = put(L.segs, segs_h.data(), segs_h.size() * sizeof(FillSeg));
+    if (e == hipSuccess) e = put(L.xexp, xexp_h.data(), xexp_h.size() * sizeof(XExpDev));
     if (e == hipSuccess) e = put(L.dir_pb, dir_pb.data(), dir_pb.size() * 4);
     if (e == hipSuccess) e = put(L.pb_face, pb_face.data(), pb_face.size() * 4);
     if (e == hipSuccess) e = put(L.pb_block, pb_block.data(), pb_block.size() * 4);
@@ -705,6 +726,20 @@ od_status Grid::init_field() {
         e = launch_init_cells(s, st, gdev, reinterpret_cast<const int32_t*>(cp(L.ccell)),
                               (int32_t)plan.chares.size(), cfg.seed);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("init: ") + hipGetErrorString(e));
+    return refresh_xexp(0);
+}
+
+const XExpDev* Grid::xexp_dev() {
+    return xexp_h.empty() ? nullptr : reinterpret_cast<const XExpDev*>(cp(L.xexp));
+}
+
+// Copy the exported x-columns of field `par` from the chares (after the
+// field was written other than by a sweep: initialisation, block writes).
+od_status Grid::refresh_xexp(int par) {
+    if (xexp_h.empty()) return OD_OK;
+    hipError_t e = launch_xexp_refresh(s, st, base, reinterpret_cast<const BlockDev*>(cp(L.blocks)), xexp_dev(),
+                                       (int32_t)plan.chares.size(), par);
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("x-column export refresh: ") + hipGetErrorString(e));
     return OD_OK;
 }
 
@@ -742,7 +777,7 @@ od_status Grid::fused_one(hipStream_t s2, int par, int64_t step) {
     hipError_t e = launch_sweep(s, plan.tile[0], plan.tile[1], s2, base,
                                 reinterpret_cast<const BlockDev*>(cp(L.blocks)),
                                 reinterpret_cast<const TileDev*>(cp(L.tiles)), (int32_t)tiles_h.size(), par,
-                                res_ptr(), 0, 1, imb, step, mode());
+                                res_ptr(), 0, 1, imb, step, mode(), xexp_dev());
     if (e != hipSuccess) return fail(OD_EHIP, std::string("sweep launch: ") + hipGetErrorString(e));
     return OD_OK;
 }
@@ -799,7 +834,8 @@ od_status Grid::persistent_run(int64_t n) {
                                      reinterpret_cast<unsigned int*>(cp(L.err)),
                                      imb, iters, mode(),
                                      persistent_dyn() ? 1 : 0,
-                                     device_wait_ticks(cfg.wait_s > 0 ? cfg.wait_s : 10.0), stamps);
+                                     device_wait_ticks(cfg.wait_s > 0 ? cfg.wait_s : 10.0), stamps,
+                                     sched() == 4 ? 1 : 0);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
     parity ^= (int)(n & 1);
     iters += n;
@@ -1104,6 +1140,8 @@ od_status Grid::block_io(int32_t b, void* host, size_t bytes, bool to_host) {
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return fail(OD_EHIP, std::string("write block: ") + hipGetErrorString(e));
         faces_packed = false;
+        od_status rs = refresh_xexp(parity);
+        if (rs != OD_OK) return rs;
     }
     return OD_OK;
 }

@@ -26,7 +26,7 @@ struct Layout {
     // addressed from Grid::base; [ctrl_begin, total): descriptors and
     // device state, addressed through Grid::cp (ctrl_begin == field_end)
     size_t ctrl_begin = 0;
-    size_t ccell = 0, segs = 0, xpub = 0;
+    size_t ccell = 0, segs = 0, xpub = 0, xexp = 0;
     size_t pend = 0, qslots = 0, qctl = 0;   // message-driven dependency counters and XCD queues
     size_t stamps = 0;                       // persistent timeline (hints bit 3)
 };
@@ -51,23 +51,26 @@ struct Grid {
     std::vector<int32_t> amr_pb;     // multi-resolution ghost buffer of (chare, face), -1 if none
     std::vector<FillSeg> segs_h;     // multi-resolution ghost fill rectangles
     int64_t fill_total = 0;          // ghost cells filled per iteration
+    std::vector<XExpDev> xexp_h;     // per-chare x-column exports (empty: none)
     std::vector<int32_t> dep_ptr, dep_idx;
     ImbDev imb{};                    // load-imbalance draw (heavy == 0: none)
     // Persistent schedule: 0 = automatic (counters under imbalance or with
     // uneven blocks, else the fixed stride), 1 = fixed stride, 2 = tiles
     // from per-XCD-group counters, 3 = counters with the last tiles of each
-    // group cut into z-ranges (guided_tail).  hints bits 4 and 5 force 2
-    // and 3; the autotuner may choose.
+    // group cut into z-ranges (guided_tail), 4 = fixed contiguous runs per
+    // workgroup.  hints bits 4, 5 and 11 force 2, 3 and 4; the autotuner
+    // may choose.
     int persist_sched = 0;
     int persist_waves = 0;           // cooperative waves per SIMD cap (0 = default)
     int msg_sched = 0;               // message-driven scheduler choice (MsgArgs::sched)
     int sched() const {
+        if (cfg.hints & 2048) return 4;
         if (cfg.hints & 32) return 3;
         if (cfg.hints & 16) return 2;
         if (persist_sched) return persist_sched;
         return (imb.heavy > 0 || !plan.regular) ? 2 : 1;
     }
-    bool persistent_dyn() const { return sched() >= 2; }
+    bool persistent_dyn() const { return sched() == 2 || sched() == 3; }
     // cooperative-kernel kind for persistent_max_grid
     int coop_kind() const { return cfg.exec == OD_MSGDRIVEN ? 1 : (persistent_dyn() ? 2 : 0); }
     std::vector<TileHost> base_tiles;   // the planner's tile list before schedule-specific cuts
@@ -122,6 +125,8 @@ struct Grid {
     od_status upload();
     od_status reset_state();
     od_status init_field();
+    od_status refresh_xexp(int par);   // x-column exports of field par from the chares
+    const XExpDev* xexp_dev();         // device export table, nullptr without exports
     od_status ensure_pinned(size_t bytes);
     unsigned long long* res_ptr();
     od_status fused_one(hipStream_t s2, int par, int64_t step);

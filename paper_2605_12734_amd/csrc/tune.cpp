@@ -4,13 +4,14 @@
 // length TZ.  Every candidate evaluates each lattice point with the same
 // expression in the same order, so tuning can change the time but never a
 // bit of the result.  Fused and graph grids time their fused sweep,
-// persistent grids their persistent kernel (one sweep per launch) under
-// each schedule (fixed stride, counters, counters with a guided tail) and
-// waves-per-SIMD cap (the kernel's register limit or one less); both repeat
-// one sweep from the current parity into the spare parity, so the field is
-// never overwritten.  Message-driven grids keep their tile (the dependency
-// lists are built for it) and time their scheduler choices over real steps
-// (the state is saved and restored).  Results are cached per (dtype, exec
+// repeating one sweep from the current parity into the spare parity (the
+// field is never overwritten).  Persistent grids time real multi-iteration
+// launches of their persistent kernel under each schedule (fixed stride,
+// counters, counters with a guided tail) and waves-per-SIMD cap (the
+// kernel's register limit or one less); message-driven grids keep their
+// tile (the dependency lists are built for it) and time their scheduler
+// choices over real steps.  For both, the grid's state is saved to host
+// memory before the search and restored after it.  Results are cached per (dtype, exec
 // mode, grid and chare-shape histogram) in the process and, if
 // OD_TUNE_CACHE names a file, on disk.
 #include <hip/hip_runtime.h>
@@ -138,25 +139,53 @@ static void apply_schedule(Grid& G, int32_t sched, int32_t waves) {
     G.persist_waves = waves;
 }
 
+// The grid's whole device state (field storage and control regions) and
+// its iteration state, kept in host memory while tuning candidates run real
+// iterations on the grid, then put back.
+struct SavedState {
+    std::vector<char> ctrl;
+    size_t fbytes = 0;
+    int64_t iters = 0;
+    int parity = 0;
+    bool msg_final = false;
+};
+
+static od_status save_state(Grid& G, SavedState& S) {
+    hipError_t he = hipStreamSynchronize(G.st);
+    if (he != hipSuccess) return fail(OD_EHIP, std::string("sync: ") + hipGetErrorString(he));
+    S.fbytes = G.L.field_end;
+    S.ctrl.resize(G.L.total - G.L.ctrl_begin);
+    od_status st = G.ensure_pinned(S.fbytes);
+    if (st != OD_OK) return st;
+    he = hipMemcpy(G.pinned, G.base, S.fbytes, hipMemcpyDeviceToHost);
+    if (he == hipSuccess) he = hipMemcpy(S.ctrl.data(), G.ctrl, S.ctrl.size(), hipMemcpyDeviceToHost);
+    if (he != hipSuccess) return fail(OD_EHIP, std::string("save state: ") + hipGetErrorString(he));
+    S.iters = G.iters;
+    S.parity = G.parity;
+    S.msg_final = G.msg_final;
+    return OD_OK;
+}
+
+static hipError_t restore_state(Grid& G, const SavedState& S) {
+    hipError_t he = hipStreamSynchronize(G.st);
+    if (he == hipSuccess) he = hipMemcpy(G.base, G.pinned, S.fbytes, hipMemcpyHostToDevice);
+    if (he == hipSuccess) he = hipMemcpy(G.ctrl, S.ctrl.data(), S.ctrl.size(), hipMemcpyHostToDevice);
+    G.iters = S.iters;
+    G.parity = S.parity;
+    G.msg_final = S.msg_final;
+    return he;
+}
+
 // Message-driven grids: the scheduler choices (claims from the per-XCD
 // cursor or from ready queues; a publisher workgroup per XCD or none) and
 // the waves-per-SIMD cap, at the grid's tile.  Each candidate runs a launch
-// of 2 * iters steps on the grid itself, so the field storage, the control
-// state and the iteration count are saved to host memory first and
-// restored afterwards.
+// of 2 * iters steps on the grid itself, between save_state and
+// restore_state.
 static od_status tune_msgdriven(Grid& G, int32_t iters, std::array<int32_t, 5>& best) {
-    hipError_t he = hipStreamSynchronize(G.st);
-    if (he != hipSuccess) return fail(OD_EHIP, std::string("sync: ") + hipGetErrorString(he));
-    const size_t fbytes = G.L.field_end, cbytes = G.L.total - G.L.ctrl_begin;
-    std::vector<char> ctrl_saved(cbytes);
-    od_status st = G.ensure_pinned(fbytes);
+    SavedState S;
+    od_status st = save_state(G, S);
     if (st != OD_OK) return st;
-    he = hipMemcpy(G.pinned, G.base, fbytes, hipMemcpyDeviceToHost);
-    if (he == hipSuccess) he = hipMemcpy(ctrl_saved.data(), G.ctrl, cbytes, hipMemcpyDeviceToHost);
-    if (he != hipSuccess) return fail(OD_EHIP, std::string("save state: ") + hipGetErrorString(he));
-    const int64_t iters0 = G.iters;
-    const int parity0 = G.parity;
-    const bool final0 = G.msg_final;
+    hipError_t he = hipSuccess;
     const int limit = coop_waves_limit(G.s, G.plan.tile[0], G.plan.tile[1], 1);
     hipEvent_t a = nullptr, b = nullptr;
     he = hipEventCreate(&a);
@@ -185,12 +214,7 @@ static od_status tune_msgdriven(Grid& G, int32_t iters, std::array<int32_t, 5>& 
     if (a) hipEventDestroy(a);
     if (b) hipEventDestroy(b);
     // restore the grid as it was, with the chosen schedule
-    hipError_t he2 = hipStreamSynchronize(G.st);
-    if (he2 == hipSuccess) he2 = hipMemcpy(G.base, G.pinned, fbytes, hipMemcpyHostToDevice);
-    if (he2 == hipSuccess) he2 = hipMemcpy(G.ctrl, ctrl_saved.data(), cbytes, hipMemcpyHostToDevice);
-    G.iters = iters0;
-    G.parity = parity0;
-    G.msg_final = final0;
+    hipError_t he2 = restore_state(G, S);
     if (he != hipSuccess) return fail(OD_EHIP, std::string("tuning launch: ") + hipGetErrorString(he));
     if (he2 != hipSuccess) return fail(OD_EHIP, std::string("restore state: ") + hipGetErrorString(he2));
     if (st != OD_OK) return st;
@@ -265,29 +289,46 @@ od_status autotune(Grid& G, int32_t iters, int32_t out_tile[3]) {
     he = hipEventCreate(&a);
     if (he == hipSuccess) he = hipEventCreate(&b);
     if (he != hipSuccess) return fail(OD_EHIP, std::string("event: ") + hipGetErrorString(he));
+    od_status st = OD_OK;
     const int32_t start_tile[3] = {G.plan.tile[0], G.plan.tile[1], G.plan.tile[2]};
     const int32_t start_sched = G.persist_sched, start_waves = G.persist_waves;
     float best_ms = 1e30f;
     std::array<int32_t, 5> best = {start_tile[0], start_tile[1], start_tile[2], start_sched, start_waves};
-    od_status st = OD_OK;
+    st = OD_OK;
     const bool pers = G.cfg.exec == OD_PERSISTENT;
     // persistent schedules: fixed stride (1), counters (2), counters with a
     // guided tail (3); hints bits 4/5 fix the schedule
     std::vector<int32_t> scheds = {0};
-    if (pers) scheds = (G.cfg.hints & 48) ? std::vector<int32_t>{0} : std::vector<int32_t>{1, 2, 3};
+    if (pers) scheds = (G.cfg.hints & (48 | 2048)) ? std::vector<int32_t>{0} : std::vector<int32_t>{1, 2, 3, 4};
+    // persistent candidates run real launches of 2 * iters iterations (the
+    // barriers and counter resets are part of what is timed), so the grid's
+    // state is saved first and restored after the search
+    SavedState saved_state;
+    if (pers) {
+        st = save_state(G, saved_state);
+        if (st != OD_OK) {
+            hipEventDestroy(a);
+            hipEventDestroy(b);
+            return st;
+        }
+    }
     auto time_it = [&](float* ms_out) -> hipError_t {
+        if (pers) {
+            od_status ps = G.persistent_run(2);   // warm-up
+            hipError_t e = ps == OD_OK ? hipEventRecord(a, G.st) : hipErrorLaunchFailure;
+            if (e == hipSuccess) ps = G.persistent_run(2 * (int64_t)iters);
+            if (ps != OD_OK) return hipErrorLaunchFailure;
+            e = hipEventRecord(b, G.st);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            if (e == hipSuccess) e = hipEventElapsedTime(ms_out, a, b);
+            if (e == hipSuccess && G.device_error() != OD_OK) e = hipErrorLaunchFailure;
+            return e;
+        }
         auto launch = [&]() {
-            if (pers)   // one sweep per launch (no barrier): the field stays as it is
-                return launch_persistent(G.s, G.plan.tile[0], G.plan.tile[1], G.st, G.grid_wgs, G.base,
-                                         reinterpret_cast<const BlockDev*>(G.cp(G.L.blocks)),
-                                         reinterpret_cast<const TileDev*>(G.cp(G.L.tiles)), (int32_t)G.tiles_h.size(),
-                                         G.parity, 1, G.res_ptr(), 1, reinterpret_cast<unsigned int*>(G.cp(G.L.bar)),
-                                         reinterpret_cast<unsigned int*>(G.cp(G.L.err)), G.imb, G.iters, G.mode(),
-                                         G.persistent_dyn() ? 1 : 0, device_wait_ticks(10.0));
             return launch_sweep(G.s, G.plan.tile[0], G.plan.tile[1], G.st, G.base,
                                 reinterpret_cast<const BlockDev*>(G.cp(G.L.blocks)),
                                 reinterpret_cast<const TileDev*>(G.cp(G.L.tiles)), (int32_t)G.tiles_h.size(),
-                                G.parity, G.res_ptr(), 0, 1, ImbDev{}, 0, G.mode());
+                                G.parity, G.res_ptr(), 0, 1, ImbDev{}, 0, G.mode(), G.xexp_dev());
         };
         hipError_t e = launch();   // warm-up
         if (e == hipSuccess) e = hipEventRecord(a, G.st);
@@ -300,7 +341,7 @@ od_status autotune(Grid& G, int32_t iters, int32_t out_tile[3]) {
     for (const auto& c : cands) {
         if (G.retile(c.data()) != OD_OK) continue;   // e.g. over the tile capacity
         for (int32_t sc : scheds) {
-            const int kind = sc >= 2 ? 2 : 0;
+            const int kind = (sc == 2 || sc == 3) ? 2 : 0;
             const int limit = pers ? coop_waves_limit(G.s, G.plan.tile[0], G.plan.tile[1], kind) : 0;
             for (int w = limit; w >= (pers ? std::max(1, limit - 1) : 0); --w) {
                 if (pers) {
@@ -325,6 +366,10 @@ od_status autotune(Grid& G, int32_t iters, int32_t out_tile[3]) {
     }
     hipEventDestroy(a);
     hipEventDestroy(b);
+    if (pers) {
+        he = restore_state(G, saved_state);
+        if (he != hipSuccess && st == OD_OK) st = fail(OD_EHIP, std::string("restore state: ") + hipGetErrorString(he));
+    }
     if (st != OD_OK) {
         apply_schedule(G, start_sched, start_waves);
         G.retile(start_tile);

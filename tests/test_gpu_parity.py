@@ -247,10 +247,11 @@ def test_hints_keep_bits(hints, exec_):
     ("f64", (200, 136, 72), 64, (32, 16, 4), 12),   # ragged tile depths (4, 4, 4, 4, 2)
     ("f32", (200, 136, 144), 64, (32, 32, 5), 12),  # ragged tile depths (5 x 7, 1)
 ])
-@pytest.mark.parametrize("sched", [0, 16, 32])
+@pytest.mark.parametrize("sched", [0, 16, 32, 2048])
 def test_persistent_schedules(dtype, n, odf, tile, iters, sched):
-    # fixed stride (0), tiles from per-XCD counters (16), and counters with
-    # each XCD group's last tiles cut into z-ranges (32): bits must not change
+    # fixed stride (0), tiles from per-XCD counters (16), counters with each
+    # XCD group's last tiles cut into z-ranges (32), fixed contiguous runs
+    # (2048): bits must not change
     want, _, r_want = _oracle(n, dtype, iters)
     g = od.Grid(n, odf=odf, dtype=dtype, exec="persistent", tile=tile, hints=1 | sched)
     try:

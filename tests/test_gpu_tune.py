@@ -30,7 +30,7 @@ def test_persistent_autotune_keeps_bits(dtype, n, odf):
         g.iterate(3)
         g.autotune(1)
         plan = g.plan()
-        assert plan["schedule"] in (1, 2, 3) and plan["grid_wgs"] > 0
+        assert plan["schedule"] in (1, 2, 3, 4) and plan["grid_wgs"] > 0
         _check(n, dtype, g, 3, 9)
     finally:
         g.close()
