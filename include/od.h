@@ -136,8 +136,15 @@ typedef struct {
      * (default: a publisher on XCDs with >= 8 workgroups and >= 2 tasks
      * per workgroup and step);
      * bit 11 (OD_PERSISTENT): fixed schedule with contiguous runs of each
-     * XCD group's tiles per workgroup.  Bit 8 is reserved.
-     * Other bits are ignored. */
+     * XCD group's tiles per workgroup;
+     * bit 12 (OD_FUSED, OD_GRAPH): one step per pass.  By default these
+     * forms run iterations in pairs where they can (regular blocks at one
+     * resolution, 3D stencil, no imbalance, a tile shape with a two-step
+     * variant): one pass reads the field once and writes it two steps
+     * later, the first step kept on chip (the same values as two single
+     * sweeps, bit for bit); od_iterate(n) with odd n ends with a single
+     * sweep.  od_plan_info.steps_per_pass tells which is in use.
+     * Bit 8 is reserved.  Other bits are ignored. */
     int32_t hints;
     /* 7 (or 0): 3D 7-point stencil.  5: the 2D 5-point stencil of the
      * paper's Jacobi2D workload, u' = (((u[i-1] + u[i+1]) + u[k-1]) + u[k+1]) / 4,
@@ -291,6 +298,11 @@ typedef struct {
                                        storage (the buffer od_create_static takes)    */
     int64_t control_bytes;          /* rest of the workspace: descriptors and device
                                        state, for this handle's plan                 */
+    int32_t steps_per_pass;         /* 2: OD_FUSED / OD_GRAPH run iterations in pairs
+                                       (hints bit 12); else 1                         */
+    int64_t bytes_per_pass;         /* algorithmic HBM bytes of one pass: one sweep, or
+                                       with two steps per pass s * (2*interior + cells
+                                       of other chares within two steps' reach)       */
 } od_plan_info;
 od_status od_plan(struct od_grid* g, od_plan_info* info);
 

@@ -20,6 +20,8 @@ import numpy as np
 from . import _binding as B
 from ._binding import ODError, check, lib
 
+HINT_ONE_STEP = B.HINT_ONE_STEP   # od_config.hints bit 12: one step per pass
+
 __all__ = ["Grid", "Grid2D", "ODError", "DEFAULT_BC", "stream_copy_seconds", "plan_info", "tile_infos", "lib",
            "Server", "launch_overlap"]
 
@@ -118,7 +120,8 @@ def plan_info(handle) -> dict:
             "interior": info.interior, "halo_cells": info.halo_cells,
             "bytes_per_iter": info.bytes_per_iter, "tile": tuple(info.tile), "grid_wgs": info.grid_wgs,
             "schedule": info.schedule, "coop_waves": info.coop_waves,
-            "field_bytes": info.field_bytes, "control_bytes": info.control_bytes}
+            "field_bytes": info.field_bytes, "control_bytes": info.control_bytes,
+            "steps_per_pass": info.steps_per_pass, "bytes_per_pass": info.bytes_per_pass}
 
 
 def tile_infos(handle, count: int) -> list:

@@ -25,6 +25,7 @@ OD_EHIP = -1000
 STATUS_NAMES = {0: "OD_OK", -22: "OD_EINVAL", -12: "OD_ENOMEM", -11: "OD_EAGAIN", -61: "OD_ENOTREADY",
                 -125: "OD_ECANCELED", -110: "OD_ETIMEDOUT", -71: "OD_ESCHED", -1000: "OD_EHIP"}
 HINT_NONTEMPORAL, HINT_SPATIAL_ORDER, HINT_SCHEDULE_CHECK = 1, 2, 4
+HINT_ONE_STEP = 4096
 
 OD_F32, OD_F64 = 4, 8
 EXEC = {"per_chare": 0, "fused": 1, "graph": 2, "persistent": 3, "msgdriven": 4}
@@ -48,7 +49,8 @@ class od_config(ctypes.Structure):
 class od_plan_info(ctypes.Structure):
     _fields_ = [("nchares", c_i32), ("ntiles", c_i32), ("npseudo", c_i32), ("interior", c_i64),
                 ("halo_cells", c_i64), ("bytes_per_iter", c_i64), ("tile", c_i32 * 3), ("grid_wgs", c_i32),
-                ("schedule", c_i32), ("coop_waves", c_i32), ("field_bytes", c_i64), ("control_bytes", c_i64)]
+                ("schedule", c_i32), ("coop_waves", c_i32), ("field_bytes", c_i64), ("control_bytes", c_i64),
+                ("steps_per_pass", c_i32), ("bytes_per_pass", c_i64)]
 
 
 class od_tile_info(ctypes.Structure):

@@ -370,6 +370,294 @@ k_sweep(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDe
 }
 
 // ---------------------------------------------------------------------------
+// Two Jacobi steps per pass over memory.  Step t+1 is never stored: a tile
+// computes it on itself and on the one-cell ring around it (the cells the
+// second step's stencil reads), from time-t values up to two cells out
+// (the face slabs one and two deep, the four (x, y) corner columns, and the
+// ring's rows just above and below the tile), then computes step t+2 on the
+// tile and writes it.  Every value of either step is the same expression in
+// the same order as in a single step, so the result is bit-identical; a
+// Dirichlet face's first step is its boundary value.
+//
+// z-march: iteration j in [-1, nz] stages time-t plane j (with its two-cell
+// ring) in LDS, computes the first step of plane j (the tile; the ring's
+// four arms for 0 <= j < nz) and stages it, then computes the second step
+// of plane j - 1 from the staged first-step plane j - 1 and the first-step
+// planes j - 2 and j held in registers.  Both LDS planes are double
+// buffered, so one barrier per iteration orders every write and read.
+//
+// Lanes: as in the single step (row ly, VX cells from x = lx * VX) for the
+// tile.  The ring is dealt out one cell per lane: lane k < 2 (nx + ny)
+// holds one cell of the one-cell ring (x- arm rows, x+ arm rows, y- arm
+// cells, y+ arm cells, in that order), keeps its time-t column (planes
+// j-1 .. j+1) and computes its first step; lane k < 2 (nx + ny) + 4 also
+// loads one cell two out (the same order, then the four corner columns).
+// Every lane issues every load (lanes without a ring cell load a valid
+// cell of their own and discard it), so no load sits behind a branch.
+template <typename T, int TX, int TY>
+struct SW2 {
+    static constexpr int VX = V16<T>::N;
+    static constexpr int LX = TX / VX;
+    static constexpr int NT = LX * TY;
+    static constexpr int LP = TX + 2 * VX;   // row pitch: column VX + x holds x in [-2, TX + 1]
+    static constexpr int TR = TY + 4;        // time-t plane: row y + 2 holds y in [-2, TY + 1]
+    static constexpr int UR = TY + 2;        // first-step plane: row y + 1 holds y in [-1, TY]
+    static constexpr int LDS = 2 * LP * (TR + UR);
+    static_assert(TX % VX == 0 && VX >= 2 && TY >= 2, "two-step tiles need vectors of >= 2 cells and >= 2 rows");
+    static_assert(NT >= 2 * (TX + TY) + 4, "one lane per ring cell");
+    static_assert(NT % 64 == 0 && NT <= 1024, "threads must be whole waves");
+};
+
+template <typename T, int TX, int TY>
+__device__ __forceinline__ T sweep2_tile(T* __restrict__ arena, const BlockDev* __restrict__ blocks,
+                                         const TileDev& t, const Tile2Dev& t2, const int parity,
+                                         T* __restrict__ lds, const int hints) {
+    using S = SW2<T, TX, TY>;
+    using VT = typename V16<T>::t;
+    constexpr int VX = S::VX, LX = S::LX, LP = S::LP;
+    constexpr int64_t ES = (int64_t)sizeof(T);
+    const int tid = threadIdx.x;
+    const int lx = tid % LX, ly = tid / LX, x = lx * VX;
+    const int nx = t.nx, ny = t.ny, nz = t.nz;
+    const bool rowok = ly < ny;
+    int nv = nx - x;
+    nv = nv < 0 ? 0 : (nv > VX ? VX : nv);
+    if (!rowok) nv = 0;
+    const bool act = nv > 0;
+    const int xc = x < nx ? x : ((nx - 1) / VX) * VX;
+    const int lc = ly < ny ? ly : ny - 1;
+    const int dir = t2.dir;
+    const char* __restrict__ ab = reinterpret_cast<const char*>(arena);
+
+    // interior: uniform bases, 32-bit per-lane byte offsets
+    const BlockDev* __restrict__ B = blocks + t.blk;
+    const int64_t own_py = B->py, own_pz = B->pz;
+    const int64_t tile_el = t.x0 + (int64_t)t.y0 * own_py + (int64_t)t.z0 * own_pz;
+    const char* own_b = ab + ((parity ? B->off[1] : B->off[0]) + tile_el) * ES;
+    char* dst_b = reinterpret_cast<char*>(arena) + ((parity ? B->off[0] : B->off[1]) + tile_el) * ES;
+    const uint32_t o_own = (uint32_t)((xc + (int64_t)lc * own_py) * ES);
+    auto at = [&](const FaceDev& f, int64_t* py, int64_t* pz) -> const char* {
+        const BlockDev* __restrict__ F = blocks + f.src;
+        *py = F->py;
+        *pz = F->pz;
+        return ab + ((parity ? F->off[1] : F->off[0]) + f.sx + (int64_t)f.sy * F->py + (int64_t)f.sz * F->pz) * ES;
+    };
+    int64_t py, pz;
+    const char* zm_b = at(t.f[4], &py, &pz);
+    const uint32_t o_zm = (uint32_t)((xc + lc * py) * ES);
+    const char* zp_b = at(t.f[5], &py, &pz);
+    const uint32_t o_zp = (uint32_t)((xc + lc * py) * ES);
+    const char* zm2_b = at(t2.r2[4], &py, &pz);
+    const uint32_t o_zm2 = (uint32_t)((xc + lc * py) * ES);
+    const char* zp2_b = at(t2.r2[5], &py, &pz);
+    const uint32_t o_zp2 = (uint32_t)((xc + lc * py) * ES);
+
+    // this lane's ring cells: kind 0..3 = x- arm, x+ arm, y- arm, y+ arm
+    // (position p along it), kind 4 = corner p; -1 = none
+    auto ring_cell = [&](int k, int* kind, int* p) {
+        if (k < ny) {
+            *kind = 0;
+            *p = k;
+        } else if (k < 2 * ny) {
+            *kind = 1;
+            *p = k - ny;
+        } else if (k < 2 * ny + nx) {
+            *kind = 2;
+            *p = k - 2 * ny;
+        } else if (k < 2 * (ny + nx)) {
+            *kind = 3;
+            *p = k - 2 * ny - nx;
+        } else if (k < 2 * (ny + nx) + 4) {
+            *kind = 4;
+            *p = k - 2 * (ny + nx);
+        } else {
+            *kind = -1;
+            *p = 0;
+        }
+    };
+    int k1, p1, k2, p2;
+    ring_cell(tid, &k1, &p1);
+    ring_cell(tid, &k2, &p2);
+    const bool r1 = k1 >= 0 && k1 < 4;   // holds a one-out cell
+    const bool r2 = k2 >= 0;             // holds a two-out or corner cell
+    // one-out cell: LDS position, face (Dirichlet bit), column pointers
+    int r1y = 0, r1c = 0, r1f = 0;
+    const char* r1_b = own_b;            // planes 0 .. nz-1
+    const char* r1_lo = own_b;           // plane -1
+    const char* r1_hi = own_b;           // plane nz
+    int64_t r1_pz = own_pz * ES;
+    if (r1) {
+        const int side = k1 & 1, along = k1 >> 1;   // along: 0 = x arm (p = row), 1 = y arm (p = x)
+        r1f = k1;
+        r1y = along ? (side ? ny : -1) : p1;
+        r1c = along ? VX + p1 : (side ? VX + nx : VX - 1);
+        int64_t lpy, lpz;
+        const char* b = at(t.f[k1], &lpy, &lpz);
+        r1_b = b + (along ? (int64_t)p1 : p1 * lpy) * ES;
+        r1_pz = lpz * ES;
+        const char* lo = at(t2.e[along ? 8 + side : 4 + side], &lpy, &lpz);
+        r1_lo = lo + (along ? (int64_t)p1 : p1 * lpy) * ES;
+        const char* hi = at(t2.e[along ? 10 + side : 6 + side], &lpy, &lpz);
+        r1_hi = hi + (along ? (int64_t)p1 : p1 * lpy) * ES;
+    }
+    // two-out or corner cell
+    int r2y = 0, r2c = 0;
+    const char* r2_b = own_b;
+    int64_t r2_pz = own_pz * ES;
+    if (r2) {
+        int64_t lpy, lpz;
+        if (k2 < 4) {
+            const int side = k2 & 1, along = k2 >> 1;
+            r2y = along ? (side ? ny + 1 : -2) : p2;
+            r2c = along ? VX + p2 : (side ? VX + nx + 1 : VX - 2);
+            r2_b = at(t2.r2[k2], &lpy, &lpz) + (along ? (int64_t)p2 : p2 * lpy) * ES;
+        } else {
+            r2y = (p2 & 2) ? ny : -1;
+            r2c = (p2 & 1) ? VX + nx : VX - 1;
+            r2_b = at(t2.e[p2], &lpy, &lpz);
+        }
+        r2_pz = lpz * ES;
+    }
+    const bool r1dir = r1 && ((dir >> r1f) & 1);
+
+    auto ldv = [](const char* p) -> VT { return *reinterpret_cast<const VT*>(p); };
+    auto lds1 = [](const char* p) -> T { return *reinterpret_cast<const T*>(p); };
+    auto tpl = [&](int q) -> VT {   // interior plane q in [-2, nz + 1] (uniform)
+        if (q >= 0 && q < nz) return ldv(own_b + q * own_pz * ES + o_own);
+        if (q == -1) return ldv(zm_b + o_zm);
+        if (q == -2) return ldv(zm2_b + o_zm2);
+        if (q == nz) return ldv(zp_b + o_zp);
+        return ldv(zp2_b + o_zp2);
+    };
+    auto rl1 = [&](int q) -> T {   // one-out cell, plane q in [-1, nz]
+        return lds1(q < 0 ? r1_lo : (q >= nz ? r1_hi : r1_b + q * r1_pz));
+    };
+    auto lim = [&](int q) { return q < 0 ? 0 : (q > nz - 1 ? nz - 1 : q); };
+
+    T* TL = lds;                      // [2][TR][LP]
+    T* UL = lds + 2 * S::TR * LP;     // [2][UR][LP]
+    auto tl = [&](int b, int y, int c) -> T& { return TL[(b * S::TR + y + 2) * LP + c]; };
+    auto ul = [&](int b, int y, int c) -> T& { return UL[(b * S::UR + y + 1) * LP + c]; };
+
+    constexpr int PF = OD_PREFETCH;
+    VT tz[PF + 3];   // time-t column of the lane's cells: planes j-1 .. j+PF+1
+#pragma unroll
+    for (int k = 0; k < PF + 2; ++k) tz[k] = tpl(-2 + k <= nz + 1 ? -2 + k : nz + 1);
+    T rc[4];         // one-out cell's column: planes j-1 .. j+2
+    rc[0] = rl1(-1);
+    rc[1] = rl1(-1);
+    rc[2] = rl1(0);
+    T c2 = lds1(r2_b);   // two-out / corner cell of plane j
+    VT um1, um2;         // first step of planes j-1, j-2
+    T r = 0;
+
+    for (int j = -1; j <= nz; ++j) {
+        const int b = j & 1;
+        const bool inz = j >= 0 && j < nz;
+        // loads for later planes
+        tz[PF + 2] = tpl(j + PF + 1 <= nz + 1 ? j + PF + 1 : nz + 1);
+        rc[3] = rl1(j + 2 > nz ? nz : j + 2);
+        const T c2n = lds1(r2_b + lim(j + 1) * r2_pz);
+
+        // stage time-t plane j
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < VX; ++i)
+                if (i < nv) tl(b, ly, VX + x + i) = tz[1][i];
+        }
+        if (r1) tl(b, r1y, r1c) = rc[1];
+        if (r2 && inz) tl(b, r2y, r2c) = c2;
+        __syncthreads();
+
+        // first step of plane j on the tile (Dirichlet z plane: its value)
+        const bool zfix = (j < 0 && (dir & 16)) || (j >= nz && (dir & 32));
+        VT u;
+#pragma unroll
+        for (int i = 0; i < VX; ++i) {
+            const T xm = i > 0 ? tz[1][i - 1] : tl(b, ly, VX + x - 1);
+            const T xp = (i < VX - 1 && i + 1 < nv) ? tz[1][i + 1] : tl(b, ly, VX + x + i + 1);
+            T s = xm;
+            s = s + xp;
+            s = s + tl(b, ly - 1, VX + x + i);
+            s = s + tl(b, ly + 1, VX + x + i);
+            s = s + tz[0][i];
+            s = s + tz[2][i];
+            u[i] = zfix ? tz[1][i] : s / (T)6;
+        }
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < VX; ++i)
+                if (i < nv) ul(b, ly, VX + x + i) = u[i];
+        }
+        // first step of the one-out cell (Dirichlet face: its value)
+        if (inz && r1) {
+            T s = tl(b, r1y, r1c - 1);
+            s = s + tl(b, r1y, r1c + 1);
+            s = s + tl(b, r1y - 1, r1c);
+            s = s + tl(b, r1y + 1, r1c);
+            s = s + rc[0];
+            s = s + rc[2];
+            ul(b, r1y, r1c) = r1dir ? rc[1] : s / (T)6;
+        }
+
+        // second step of plane j - 1
+        if (j >= 1) {
+            const int c = b ^ 1;
+            VT out;
+#pragma unroll
+            for (int i = 0; i < VX; ++i) {
+                const T xm = i > 0 ? um1[i - 1] : ul(c, ly, VX + x - 1);
+                const T xp = (i < VX - 1 && i + 1 < nv) ? um1[i + 1] : ul(c, ly, VX + x + i + 1);
+                T s = xm;
+                s = s + xp;
+                s = s + ul(c, ly - 1, VX + x + i);
+                s = s + ul(c, ly + 1, VX + x + i);
+                s = s + um2[i];
+                s = s + u[i];
+                const T v = s / (T)6;
+                out[i] = v;
+                if (i < nv) {
+                    T d = v - um1[i];
+                    if (d < (T)0) d = -d;
+                    if (d > r) r = d;
+                }
+            }
+            if (act) {
+                VT* o = reinterpret_cast<VT*>(dst_b + (int64_t)(j - 1) * own_pz * ES + o_own);
+                if (hints & 1)
+                    __builtin_nontemporal_store(out, o);
+                else
+                    *o = out;
+            }
+        }
+        um2 = um1;
+        um1 = u;
+#pragma unroll
+        for (int k = 0; k < PF + 2; ++k) tz[k] = tz[k + 1];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) rc[k] = rc[k + 1];
+        c2 = c2n;
+    }
+    __syncthreads();   // LDS planes are reused by the next tile
+    return r;
+}
+
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__((TX / V16<T>::N) * TY)
+k_sweep2(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDev* __restrict__ tiles,
+         const Tile2Dev* __restrict__ tiles2, int parity, unsigned long long* __restrict__ res, int zero_lo,
+         int zero_hi, int hints) {
+    using S = SW2<T, TX, TY>;
+    __shared__ T lds[S::LDS];
+    __shared__ T red[S::NT / 64];
+    if (blockIdx.x == 0)
+        for (int s = zero_lo + (int)threadIdx.x; s < zero_hi; s += S::NT) res[2 * s + parity] = 0ull;
+    const TileDev& t = tiles[blockIdx.x];
+    const T r = sweep2_tile<T, TX, TY>(arena, blocks, t, tiles2[blockIdx.x], parity, lds, hints);
+    wg_residual<T, S::NT>(r, &res[2 * t.rslot + (parity ^ 1)], red);
+}
+
+// ---------------------------------------------------------------------------
 // Synchronisation between workgroups.  On gfx950 an agent-scope release
 // writes back the XCD's L2 and an agent-scope acquire invalidates caches, so
 // both are issued once per workgroup, never per wave and never inside a
@@ -1394,6 +1682,36 @@ hipError_t launch_sweep(int dtype_bytes, int tx, int ty, hipStream_t st, void* a
     OD_VARIANTS_F64(OD_LAUNCH)
     OD_VARIANTS_F32(OD_LAUNCH)
 #undef OD_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+#define OD_VARIANTS2_F64(X) X(double, 32, 32) X(double, 32, 16) X(double, 32, 8) X(double, 64, 8) \
+    X(double, 64, 16) X(double, 16, 16)
+#define OD_VARIANTS2_F32(X) X(float, 32, 32) X(float, 32, 16) X(float, 64, 16)
+
+bool sweep2_variant_ok(int dtype_bytes, int tx, int ty) {
+#define OD_OK2(T, TX, TY) \
+    if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) return true;
+    OD_VARIANTS2_F64(OD_OK2)
+    OD_VARIANTS2_F32(OD_OK2)
+#undef OD_OK2
+    return false;
+}
+
+hipError_t launch_sweep2(int dtype_bytes, int tx, int ty, hipStream_t st, void* arena, const BlockDev* blocks,
+                         const TileDev* tiles, const Tile2Dev* tiles2, int32_t ntiles, int parity,
+                         unsigned long long* res, int32_t zero_lo, int32_t zero_hi, int hints) {
+    if (ntiles <= 0) return hipSuccess;
+#define OD_LAUNCH2(T, TX, TY)                                                                            \
+    if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                         \
+        hipLaunchKernelGGL((k_sweep2<T, TX, TY>), dim3(ntiles), dim3(SW2<T, TX, TY>::NT), 0, st,        \
+                           reinterpret_cast<T*>(arena), blocks, tiles, tiles2, parity, res, zero_lo, zero_hi, \
+                           hints);                                                                       \
+        return hipGetLastError();                                                                        \
+    }
+    OD_VARIANTS2_F64(OD_LAUNCH2)
+    OD_VARIANTS2_F32(OD_LAUNCH2)
+#undef OD_LAUNCH2
     return hipErrorInvalidValue;
 }
 

@@ -109,6 +109,35 @@ hipError_t launch_sweep(int dtype_bytes, int tx, int ty, hipStream_t st, void* a
                         unsigned long long* res, int32_t zero_lo, int32_t zero_hi,
                         const ImbDev& imb, int64_t step, int hints, const XExpDev* xexp = nullptr);
 
+// Two Jacobi steps per pass (regular grids at one resolution, 3D 7-point
+// stencil): each tile reads the time-t field once, computes the first step
+// on itself and on a one-cell ring around it in registers and LDS, and
+// writes only the second step.  Besides the six face slabs (TileDev::f) it
+// reads the slabs two cells out and the cells of twelve lines around the
+// tile, each given like a FaceDev (block and local coordinates of its first
+// cell; a ghost-shell cell maps to the Dirichlet pseudo-block of its face,
+// any cell of which holds the face's value; a cell that is never read maps
+// to the tile's own chare):
+//   r2[f]     slab of face f two cells out (x-, x+, y-, y+, z-, z+)
+//   e[0..3]   (x, y) = (-1,-1), (nx,-1), (-1,ny), (nx,ny), z = 0..nz-1 (along z)
+//   e[4..7]   x = -1 / nx, z = -1: e[4] x-, e[5] x+; z = nz: e[6] x-, e[7] x+ (along y)
+//   e[8..11]  y = -1 / ny, z = -1: e[8] y-, e[9] y+; z = nz: e[10] y-, e[11] y+ (along x)
+// dir: bit f set when face f of the tile is a Dirichlet face of the domain
+// (its first step is the boundary value itself).
+struct Tile2Dev {
+    FaceDev e[12];
+    FaceDev r2[6];
+    int32_t dir, pad_[3];
+};
+static_assert(sizeof(Tile2Dev) == 304, "Tile2Dev layout");
+// Two-step variants compiled for a dtype (tile x extent >= 2 vectors, y >= 2).
+bool sweep2_variant_ok(int dtype_bytes, int tx, int ty);
+// Reads parity `parity`, writes the field two steps later into parity^1;
+// the residual (of the second step) and res zeroing as launch_sweep.
+hipError_t launch_sweep2(int dtype_bytes, int tx, int ty, hipStream_t st, void* arena, const BlockDev* blocks,
+                         const TileDev* tiles, const Tile2Dev* tiles2, int32_t ntiles, int parity,
+                         unsigned long long* res, int32_t zero_lo, int32_t zero_hi, int hints);
+
 // Persistent cooperative sweep: all `iters` iterations in one launch with a
 // device-wide barrier between them.  dyn != 0: workgroups take tiles from
 // per-XCD-group counters (load balance under imbalance and uneven blocks);

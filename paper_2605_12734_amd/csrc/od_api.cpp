@@ -159,6 +159,111 @@ int64_t build_fill_segments(Grid& G) {
 
 }  // namespace
 
+// ---- two steps per pass ------------------------------------------------------
+
+namespace {
+
+// Pairs of iterations in one pass need a regular decomposition at one
+// resolution (every line of cells around a tile lies in one block), the 3D
+// stencil, no imbalance (a re-run chare would have to repeat both steps),
+// and a tile shape with a two-step variant.
+bool two_step_possible(const Grid& G) {
+    const od_config& cfg = G.cfg;
+    const Plan& p = G.plan;
+    return (cfg.exec == OD_FUSED || cfg.exec == OD_GRAPH) && !(cfg.hints & 4096) && p.regular && !p.multires &&
+           cfg.stencil != 5 && G.imb.heavy == 0;
+}
+
+// Block and local coordinates of global cell (x, y, z) as a FaceDev: its
+// chare, or for a cell of the domain's ghost shell the Dirichlet
+// pseudo-block of that face (normal coordinate 0; every cell of it holds
+// the face's value); `other` for a cell outside the domain along two or
+// more axes (never read).
+FaceDev cell_src(const Grid& G, int64_t x, int64_t y, int64_t z, const FaceDev& other) {
+    const Plan& p = G.plan;
+    int64_t v[3] = {x, y, z};
+    int outs = 0, f = -1;
+    for (int d = 0; d < 3; ++d) {
+        if (v[d] < 0) {
+            ++outs;
+            f = 2 * d;
+            v[d] = 0;
+        } else if (v[d] >= p.n[d]) {
+            ++outs;
+            f = 2 * d + 1;
+            v[d] = p.n[d] - 1;
+        }
+    }
+    if (outs >= 2) return other;
+    const int32_t c = plan_owner(p, v[0], v[1], v[2]);
+    const Chare& ch = p.chares[(size_t)c];
+    int32_t l[3];
+    for (int d = 0; d < 3; ++d) l[d] = (int32_t)(v[d] - ch.u[d]);
+    FaceDev out{};
+    out.src = c;
+    if (outs == 1) {
+        out.src = G.dir_pb[(size_t)c * 6 + f];
+        l[f / 2] = 0;
+    }
+    out.sx = l[0];
+    out.sy = l[1];
+    out.sz = l[2];
+    return out;
+}
+
+void fill_tile2(const Grid& G, const TileHost& th, Tile2Dev& t2) {
+    const Chare& ch = G.plan.chares[(size_t)th.chare];
+    const int64_t X0 = (int64_t)ch.u[0] + th.o[0], Y0 = (int64_t)ch.u[1] + th.o[1], Z0 = (int64_t)ch.u[2] + th.o[2];
+    const int64_t nx = th.e[0], ny = th.e[1], nz = th.e[2];
+    const FaceDev own{th.chare, th.o[0], th.o[1], th.o[2]};
+    t2 = Tile2Dev{};
+    for (int f = 0; f < 6; ++f)
+        if (th.kind[f] == 1) t2.dir |= 1 << f;
+    const int64_t xs[2] = {X0 - 1, X0 + nx}, ys[2] = {Y0 - 1, Y0 + ny}, zs[2] = {Z0 - 1, Z0 + nz};
+    for (int k = 0; k < 4; ++k) {
+        t2.e[k] = cell_src(G, xs[k & 1], ys[k >> 1], Z0, own);
+        t2.e[4 + k] = cell_src(G, xs[k & 1], Y0, zs[k >> 1], own);
+        t2.e[8 + k] = cell_src(G, X0, ys[k & 1], zs[k >> 1], own);
+    }
+    t2.r2[0] = cell_src(G, X0 - 2, Y0, Z0, own);
+    t2.r2[1] = cell_src(G, X0 + nx + 1, Y0, Z0, own);
+    t2.r2[2] = cell_src(G, X0, Y0 - 2, Z0, own);
+    t2.r2[3] = cell_src(G, X0, Y0 + ny + 1, Z0, own);
+    t2.r2[4] = cell_src(G, X0, Y0, Z0 - 2, own);
+    t2.r2[5] = cell_src(G, X0, Y0, Z0 + nz + 1, own);
+}
+
+// Cells of other chares within two stencil steps of each chare (L1
+// distance <= 2, inside the domain): each face's two layers and the cells
+// diagonal to each edge, summed over the chares.
+int64_t halo2_count(const Plan& p) {
+    int64_t g = 0;
+    for (const Chare& c : p.chares) {
+        auto inside = [&](int d, int64_t v) { return v >= 0 && v < p.n[d]; };
+        int64_t r1[6];
+        for (int f = 0; f < 6; ++f) {
+            const int d = f / 2;
+            const int64_t area = (int64_t)c.e[(d + 1) % 3] * c.e[(d + 2) % 3];
+            r1[f] = (f % 2) ? (int64_t)c.u[d] + c.e[d] : (int64_t)c.u[d] - 1;
+            const int64_t r2 = (f % 2) ? r1[f] + 1 : r1[f] - 1;
+            if (inside(d, r1[f])) g += area;
+            if (inside(d, r2)) g += area;
+        }
+        for (int d1 = 0; d1 < 3; ++d1)
+            for (int d2 = d1 + 1; d2 < 3; ++d2)
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 2; ++b)
+                        if (inside(d1, r1[2 * d1 + a]) && inside(d2, r1[2 * d2 + b])) g += c.e[3 - d1 - d2];
+    }
+    return g;
+}
+
+}  // namespace
+
+int64_t Grid::bytes_per_pass() const {
+    return two_step ? (int64_t)s * (2 * plan.interior + halo2_cells) : (int64_t)s * (2 * plan.interior + plan.halo_cells);
+}
+
 // Device descriptors of every tile: owning chare, box, and for each face
 // the block (chare or face pseudo-block) its ghost slab is read from.
 std::string fill_tile_descs(Grid& G) {
@@ -215,6 +320,12 @@ std::string fill_tile_descs(Grid& G) {
                 fd.sz = sxyz[2];
             }
         }
+    }
+    G.two_step = two_step_possible(G) && sweep2_variant_ok(G.s, p.tile[0], p.tile[1]);
+    G.tiles2_h.clear();
+    if (G.two_step) {
+        G.tiles2_h.resize(ntiles);
+        for (size_t i = 0; i < ntiles; ++i) fill_tile2(G, p.tiles[i], G.tiles2_h[i]);
     }
     return "";
 }
@@ -436,6 +547,8 @@ std::string build_layout(const od_config& cfg, Grid& G) {
     // workgroup plus padding (guided_tail); cooperative grids stay below 8192
     if (cfg.exec == OD_PERSISTENT) G.tile_cap += 3 * 8192 + kNumXcd;
     G.L.tiles = cv.take(G.tile_cap * sizeof(TileDev));
+    G.halo2_cells = two_step_possible(G) ? halo2_count(p) : 0;
+    G.L.tiles2 = cv.take((two_step_possible(G) ? G.tile_cap : 1) * sizeof(Tile2Dev));
     for (int d = 0; d < 3; ++d) G.L.cidx[d] = cv.take((size_t)(p.regular ? p.n[d] : 1) * 4);
     G.L.owner = cv.take((p.regular ? 1 : p.owner.size()) * 4);
     G.L.corigin = cv.take((size_t)C * 3 * 4);
@@ -663,6 +776,7 @@ od_status Grid::upload() {
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = put(L.blocks, blocks_h.data(), blocks_h.size() * sizeof(BlockDev));
     if (e == hipSuccess) e = put(L.tiles, tiles_h.data(), tiles_h.size() * sizeof(TileDev));
+    if (e == hipSuccess) e = put(L.tiles2, tiles2_h.data(), tiles2_h.size() * sizeof(Tile2Dev));
     std::vector<int32_t> cidx[3];
     if (p.regular) {
         for (int d = 0; d < 3; ++d) {
@@ -782,6 +896,25 @@ od_status Grid::fused_one(hipStream_t s2, int par, int64_t step) {
     return OD_OK;
 }
 
+od_status Grid::fused_two(hipStream_t s2, int par) {
+    hipError_t e = launch_sweep2(s, plan.tile[0], plan.tile[1], s2, base, reinterpret_cast<const BlockDev*>(cp(L.blocks)),
+                                 reinterpret_cast<const TileDev*>(cp(L.tiles)),
+                                 reinterpret_cast<const Tile2Dev*>(cp(L.tiles2)), (int32_t)tiles_h.size(), par,
+                                 res_ptr(), 0, 1, mode());
+    if (e != hipSuccess) return fail(OD_EHIP, std::string("two-step sweep launch: ") + hipGetErrorString(e));
+    return OD_OK;
+}
+
+od_status Grid::upload_tiles() {
+    hipError_t he = hipMemcpyAsync(cp(L.tiles), tiles_h.data(), tiles_h.size() * sizeof(TileDev),
+                                   hipMemcpyHostToDevice, st);
+    if (he == hipSuccess && !tiles2_h.empty())
+        he = hipMemcpyAsync(cp(L.tiles2), tiles2_h.data(), tiles2_h.size() * sizeof(Tile2Dev), hipMemcpyHostToDevice, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he != hipSuccess) return fail(OD_EHIP, std::string("tile upload: ") + hipGetErrorString(he));
+    return OD_OK;
+}
+
 od_status Grid::graph_run(int64_t n) {
     while (n > 0) {
         const int64_t m = std::min(n, kMaxGraphLen);
@@ -796,7 +929,16 @@ od_status Grid::graph_run(int64_t n) {
             hipError_t e = hipStreamBeginCapture(cap_st, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return fail(OD_EHIP, std::string("begin capture: ") + hipGetErrorString(e));
             od_status os = OD_OK;
-            for (int64_t i = 0; i < m && os == OD_OK; ++i) os = fused_one(cap_st, parity ^ (int)(i & 1), iters + i);
+            int par = parity;
+            for (int64_t i = 0; i < m && os == OD_OK; par ^= 1) {
+                if (two_step && m - i >= 2) {
+                    os = fused_two(cap_st, par);
+                    i += 2;
+                } else {
+                    os = fused_one(cap_st, par, iters + i);
+                    i += 1;
+                }
+            }
             e = hipStreamEndCapture(cap_st, &graph);
             if (os != OD_OK) {
                 if (graph) hipGraphDestroy(graph);
@@ -811,7 +953,7 @@ od_status Grid::graph_run(int64_t n) {
         }
         hipError_t e = hipGraphLaunch(it->second, st);
         if (e != hipSuccess) return fail(OD_EHIP, std::string("graph launch: ") + hipGetErrorString(e));
-        parity ^= (int)(m & 1);
+        parity ^= (int)((two_step ? m / 2 + m % 2 : m) & 1);   // one flip per pass
         iters += m;
         n -= m;
     }
@@ -1000,11 +1142,13 @@ od_status Grid::iterate(int64_t n) {
     switch (cfg.exec) {
         case OD_FUSED: {
             msg_final = false;
-            for (int64_t i = 0; i < n; ++i) {
-                od_status os = fused_one(st, parity, iters);
+            for (int64_t i = 0; i < n;) {
+                const int k = two_step && n - i >= 2 ? 2 : 1;
+                od_status os = k == 2 ? fused_two(st, parity) : fused_one(st, parity, iters);
                 if (os != OD_OK) return os;
                 parity ^= 1;
-                ++iters;
+                iters += k;
+                i += k;
             }
             return OD_OK;
         }

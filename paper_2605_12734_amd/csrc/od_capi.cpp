@@ -309,6 +309,8 @@ od_status od_plan(od_grid* g, od_plan_info* info) {
     info->coop_waves = G.persist_waves;
     info->field_bytes = (int64_t)G.L.ctrl_begin;
     info->control_bytes = (int64_t)(G.L.total - G.L.ctrl_begin);
+    info->steps_per_pass = G.two_step ? 2 : 1;
+    info->bytes_per_pass = G.bytes_per_pass();
     return OD_OK;
 }
 

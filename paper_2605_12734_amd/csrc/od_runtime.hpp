@@ -26,7 +26,7 @@ struct Layout {
     // addressed from Grid::base; [ctrl_begin, total): descriptors and
     // device state, addressed through Grid::cp (ctrl_begin == field_end)
     size_t ctrl_begin = 0;
-    size_t ccell = 0, segs = 0, xpub = 0, xexp = 0;
+    size_t ccell = 0, segs = 0, xpub = 0, xexp = 0, tiles2 = 0;
     size_t pend = 0, qslots = 0, qctl = 0;   // message-driven dependency counters and XCD queues
     size_t stamps = 0;                       // persistent timeline (hints bit 3)
 };
@@ -52,6 +52,11 @@ struct Grid {
     std::vector<FillSeg> segs_h;     // multi-resolution ghost fill rectangles
     int64_t fill_total = 0;          // ghost cells filled per iteration
     std::vector<XExpDev> xexp_h;     // per-chare x-column exports (empty: none)
+    // two steps per pass (OD_FUSED / OD_GRAPH, see two_step_ok): decided
+    // with the tile list; the tiles' extra line descriptors
+    bool two_step = false;
+    std::vector<Tile2Dev> tiles2_h;
+    int64_t halo2_cells = 0;         // cells of other chares within two steps of each chare
     std::vector<int32_t> dep_ptr, dep_idx;
     ImbDev imb{};                    // load-imbalance draw (heavy == 0: none)
     // Persistent schedule: 0 = automatic (counters under imbalance or with
@@ -130,6 +135,9 @@ struct Grid {
     od_status ensure_pinned(size_t bytes);
     unsigned long long* res_ptr();
     od_status fused_one(hipStream_t s2, int par, int64_t step);
+    od_status fused_two(hipStream_t s2, int par);   // two steps, parity par -> par ^ 1
+    od_status upload_tiles();                      // tile descriptors (and two-step lines) to the device
+    int64_t bytes_per_pass() const;
     od_status graph_run(int64_t n);
     od_status persistent_run(int64_t n);
     od_status msgdriven_run(int64_t n);

@@ -115,10 +115,8 @@ od_status Grid::retile(const int32_t tile[3]) {
         if (cfg.exec == OD_PERSISTENT || cfg.exec == OD_MSGDRIVEN) setup_cooperative();
         return fail(OD_EINVAL, e);
     }
-    hipError_t he = hipMemcpyAsync(cp(L.tiles), tiles_h.data(), tiles_h.size() * sizeof(TileDev),
-                                   hipMemcpyHostToDevice, st);
-    if (he == hipSuccess) he = hipStreamSynchronize(st);
-    if (he != hipSuccess) return fail(OD_EHIP, std::string("tile upload: ") + hipGetErrorString(he));
+    od_status us = upload_tiles();
+    if (us != OD_OK) return us;
     for (auto& kv : graphs) hipGraphExecDestroy(kv.second);
     graphs.clear();
     if (cfg.exec == OD_PERSISTENT || cfg.exec == OD_MSGDRIVEN) {

@@ -1,0 +1,116 @@
+"""Two Jacobi steps per pass (OD_FUSED / OD_GRAPH default on regular grids):
+the pass reads the field once, keeps the first step on chip and writes the
+second.  Every case is compared with the CPU oracle bit for bit (0 ULP),
+with odd and even iteration counts (an odd count ends with a single sweep),
+ragged tiles, tiles of extent 1, chares of extent 1 (the cells two steps
+out then lie two chares away), distinct Dirichlet values on all six faces
+(the first step of a boundary ring is the boundary value), and every
+compiled two-step tile shape."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2605_12734_amd as od
+
+pytestmark = pytest.mark.gpu
+
+DT = {"f64": np.float64, "f32": np.float32}
+BC6 = (1.0, 0.5, 0.25, 0.125, 2.0, 3.0)
+VARIANTS = {"f64": [(32, 32), (32, 16), (32, 8), (64, 8), (64, 16), (16, 16)],
+            "f32": [(32, 32), (32, 16), (64, 16)]}
+
+
+def _same(U, want):
+    if not np.array_equal(U, want):
+        d = np.argwhere(U != want)
+        k, j, i = d[0]
+        raise AssertionError(f"{len(d)} cells differ; first at padded (k,j,i)=({k},{j},{i}): "
+                             f"{U[k, j, i]!r} vs {want[k, j, i]!r}")
+
+
+def _case(n, odf, dtype, iters, exec_="fused", tile=None, bc=od.DEFAULT_BC, seed=12734, hints=1):
+    want, it_w, r_w = oracle.solve(n, DT[dtype], seed=seed, iters=iters, bc=bc)
+    kw = {"tile": tile} if tile else {}
+    g = od.Grid(n, odf=odf, dtype=dtype, exec=exec_, bc=bc, seed=seed, hints=hints, **kw)
+    try:
+        plan = g.plan()
+        g.iterate(iters)
+        r = g.residual()
+        U = g.read()
+        it = g.iterations()
+    finally:
+        g.close()
+    _same(U, want)
+    assert it == it_w == iters and r == r_w
+    return plan
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("iters", [1, 2, 5, 12])
+@pytest.mark.parametrize("exec_", ["fused", "graph"])
+def test_64cubed_2x2x2(dtype, iters, exec_):
+    plan = _case(64, 8, dtype, iters, exec_)
+    assert plan["steps_per_pass"] == 2
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n,odf", [((37, 21, 19), 8), ((150, 90, 70), 27), ((12, 6, 5), 27), ((9, 8, 7), 27),
+                                   ((1, 1, 1), 1), ((2, 2, 2), 8), ((3, 1, 4), 1), ((40, 3, 33), 8)])
+def test_ragged_and_tiny_six_boundary_values(dtype, n, odf):
+    plan = _case(n, odf, dtype, 7, tile=(32, 16, 8), bc=BC6, seed=5)
+    assert plan["steps_per_pass"] == 2
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_every_two_step_variant(dtype):
+    # 70 x 45 x 33 over 8 chares: ragged tiles of every shape, z tiles of 1
+    for tx, ty in VARIANTS[dtype]:
+        for tz in (16, 34):
+            plan = _case((70, 45, 33), 8, dtype, 6, tile=(tx, ty, tz), bc=BC6, seed=3)
+            assert plan["steps_per_pass"] == 2 and tuple(plan["tile"]) == (tx, ty, tz)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_tile_extent_one_on_every_axis(dtype):
+    # chares of 33 x 17 x 9 with tiles (32, 16, 8): a last tile of extent 1
+    # along each axis, whose ring two cells out lies in the next chare
+    _case((66, 34, 18), 8, dtype, 5, tile=(32, 16, 8), bc=BC6, seed=11)
+
+
+@pytest.mark.parametrize("exec_", ["fused", "graph"])
+def test_one_step_hint_and_pairs_identical_at_256(exec_):
+    out = []
+    for hints in (1, 1 | od.HINT_ONE_STEP):
+        g = od.Grid(256, odf=512, dtype="f64", exec=exec_, hints=hints, tile=(32, 32, 32))
+        try:
+            g.iterate(9)
+            out.append((g.read(), g.residual(), g.plan()["steps_per_pass"]))
+        finally:
+            g.close()
+    (a, ra, sa), (b, rb, sb) = out
+    assert sa == 2 and sb == 1
+    assert np.array_equal(a, b) and ra == rb
+
+
+def test_not_used_where_unsupported():
+    # imbalance, 2D stencil and persistent grids keep one step per pass
+    for kw in ({"exec": "fused", "imbalance_pct": 10, "imbalance_max_extra": 2},
+               {"exec": "persistent"}, {"exec": "msgdriven"}, {"exec": "per_chare"}):
+        g = od.Grid(64, odf=8, dtype="f64", **kw)
+        try:
+            assert g.plan()["steps_per_pass"] == 1
+        finally:
+            g.close()
+
+
+def test_bytes_per_pass_counts_two_step_reach():
+    # 64^3 as 2x2x2 chares of 32^3: every chare has 3 inner faces (two
+    # layers each) and 3 inner edges
+    g = od.Grid(64, odf=8, dtype="f64", exec="fused")
+    try:
+        p = g.plan()
+    finally:
+        g.close()
+    per_chare = 3 * 2 * 32 * 32 + 3 * 32
+    assert p["bytes_per_pass"] == 8 * (2 * 64 ** 3 + 8 * per_chare)
+    assert p["bytes_per_iter"] == 8 * (2 * 64 ** 3 + 8 * 3 * 32 * 32)

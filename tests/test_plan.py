@@ -236,3 +236,46 @@ def test_imbalance_draw_frequency_and_seed():
     assert not np.array_equal(D[:50], E)
     Z = od.imbalance_draw(range(0, 5), n=64, odf=64, exec="persistent")
     assert not Z.any()
+
+
+def _reach2_brute(n, chares):
+    """Cells of other chares within two stencil steps (L1 distance <= 2) of
+    each chare, inside the domain, counted cell by cell."""
+    nx, ny, nz = n
+    total = 0
+    for (o, e) in chares:
+        lo = [max(o[d] - 2, 0) for d in range(3)]
+        hi = [min(o[d] + e[d] + 2, n[d]) for d in range(3)]
+        for z in range(lo[2], hi[2]):
+            for y in range(lo[1], hi[1]):
+                for x in range(lo[0], hi[0]):
+                    dist = 0
+                    for d, v in enumerate((x, y, z)):
+                        dist += max(o[d] - v, 0, v - (o[d] + e[d] - 1))
+                    if 0 < dist <= 2:
+                        total += 1
+    return total
+
+
+@pytest.mark.parametrize("n,odf", [((13, 11, 9), 8), ((12, 6, 5), 27), ((9, 9, 9), 1), ((10, 10, 10), 27),
+                                   ((33, 4, 5), 8), ((64, 64, 64), 8)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_two_step_pass_bytes_brute_force(n, odf, dtype):
+    plan = od.host_plan(n=n, odf=odf, dtype=dtype, exec="fused")
+    s = 8 if dtype == "f64" else 4
+    assert plan["steps_per_pass"] == 2
+    g2 = _reach2_brute(n, plan["chares"])
+    assert plan["bytes_per_pass"] == s * (2 * plan["interior"] + g2)
+    assert plan["bytes_per_iter"] == s * (2 * plan["interior"] + plan["halo_cells"])
+
+
+@pytest.mark.parametrize("kw", [{"exec": "persistent"}, {"exec": "msgdriven"}, {"exec": "per_chare"},
+                                {"exec": "fused", "hints": 4096},
+                                {"exec": "fused", "imbalance_pct": 10, "imbalance_max_extra": 2},
+                                {"exec": "fused", "tile": (128, 4, 8)}])
+def test_two_step_only_where_supported(kw):
+    # other forms, the one-step hint, imbalance and tile shapes without a
+    # two-step variant keep one step per pass
+    plan = od.host_plan(n=(64, 64, 64), odf=8, dtype="f64", **kw)
+    assert plan["steps_per_pass"] == 1
+    assert plan["bytes_per_pass"] == plan["bytes_per_iter"]
