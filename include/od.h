@@ -406,9 +406,10 @@ od_status od_launch_overlap(void* dev_ws, size_t ws_bytes, int64_t total_threads
 /* -------------------------------------------------------------------------
  * Autotuning: tile shape and schedule.  Every candidate computes the same
  * arithmetic; only the tile shape, the schedule and the launch shape
- * differ.  OD_FUSED and OD_GRAPH grids time `iters` fused sweeps per tile
- * candidate (each writes only the spare parity, so the field is
- * unchanged).  OD_PERSISTENT grids time a launch of 2 * iters iterations
+ * differ.  OD_FUSED and OD_GRAPH grids time `iters` fused passes per tile
+ * candidate, per step (a shape with a two-step variant is timed as pairs
+ * of steps, as the grid would run it; each pass writes only the spare
+ * parity, so the field is unchanged).  OD_PERSISTENT grids time a launch of 2 * iters iterations
  * for every tile candidate under each schedule (fixed stride, fixed runs,
  * per-XCD counters, counters with a guided tail) and waves-per-SIMD cap (the
  * kernel's register limit or one less).  OD_MSGDRIVEN grids keep their tile

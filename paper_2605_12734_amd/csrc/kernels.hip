@@ -773,6 +773,41 @@ __device__ __forceinline__ bool xcd_barrier(unsigned int* bar, unsigned int* err
     return ok != 0;
 }
 
+// Persistent launches: each workgroup registers on its XCD (bar[40 + x]
+// counts them), then one full barrier makes every count final.
+__device__ __forceinline__ bool persist_register(unsigned int* bar, unsigned int* err, int64_t wait_ticks,
+                                                 int* s_xcd, unsigned int* s_xwgs, unsigned int* s_nxcd) {
+    if (threadIdx.x == 0) {
+        *s_xcd = (int)(__builtin_amdgcn_s_getreg(kXccIdReg) & 7);
+        __hip_atomic_fetch_add(&bar[40 + *s_xcd], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (!grid_barrier(bar, err, wait_ticks)) return false;
+    if (threadIdx.x == 0) {
+        *s_xwgs = __hip_atomic_load(&bar[40 + *s_xcd], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned int nx = 0;
+        for (int x = 0; x < 8; ++x)
+            nx += __hip_atomic_load(&bar[40 + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1u : 0u;
+        *s_nxcd = nx;
+    }
+    __syncthreads();
+    return true;
+}
+
+// The last workgroup to leave a persistent launch clears the tile counters
+// and the per-XCD barrier words for the next launch.
+__device__ __forceinline__ void persist_cleanup(unsigned int* bar) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned int prev = __hip_atomic_fetch_add(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == gridDim.x - 1) {
+            for (int x = 0; x < 16; ++x)
+                __hip_atomic_store(tile_ctr(bar, x >> 3, x & 7), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int x = 32; x < 48; ++x) __hip_atomic_store(&bar[x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&bar[2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 // DYN (a separate instantiation): tiles from per-XCD-group counters.  The
 // static form's tile index is uniform by construction, so its tile
 // descriptors stay in scalar registers (fewer VGPRs, more waves per SIMD);
@@ -817,25 +852,9 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
         last = (int32_t)((int64_t)npos * (k + 1) / W);
         step_w = 1;
     }
-    // register on this workgroup's XCD (bar[40 + x] counts them), then one
-    // full barrier so every count is final
     __shared__ int s_xcd;
     __shared__ unsigned int s_xwgs, s_nxcd;
-    if (iters > 1) {
-        if (threadIdx.x == 0) {
-            s_xcd = (int)(__builtin_amdgcn_s_getreg(kXccIdReg) & 7);
-            __hip_atomic_fetch_add(&bar[40 + s_xcd], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (!grid_barrier(bar, err, wait_ticks)) return;
-        if (threadIdx.x == 0) {
-            s_xwgs = __hip_atomic_load(&bar[40 + s_xcd], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            unsigned int nx = 0;
-            for (int x = 0; x < 8; ++x)
-                nx += __hip_atomic_load(&bar[40 + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1u : 0u;
-            s_nxcd = nx;
-        }
-        __syncthreads();
-    }
+    if (iters > 1 && !persist_register(bar, err, wait_ticks, &s_xcd, &s_xwgs, &s_nxcd)) return;
     for (int64_t it = 0; it < iters; ++it) {
         const int p = parity ^ (int)(it & 1);
         // timeline (stamps != null): first and last workgroup to start
@@ -899,17 +918,53 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
                 return;
         }
     }
-    // the last workgroup to leave clears the counters for the next launch
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned int prev = __hip_atomic_fetch_add(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == gridDim.x - 1) {
-            for (int x = 0; x < 16; ++x)
-                __hip_atomic_store(tile_ctr(bar, x >> 3, x & 7), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            for (int x = 32; x < 48; ++x) __hip_atomic_store(&bar[x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&bar[2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    persist_cleanup(bar);
+}
+
+// Persistent form of the two-step pass (uniform work: regular blocks, no
+// imbalance): `passes` passes of two steps each in one cooperative launch,
+// workgroup w sweeping tiles w, w + G, ... of its XCD group, the same
+// per-XCD barrier between passes as k_persistent.
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__((TX / V16<T>::N) * TY) __attribute__((amdgpu_waves_per_eu(6, 8)))
+k_persistent2(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDev* __restrict__ tiles,
+              const Tile2Dev* __restrict__ tiles2, int32_t ntiles, int parity, int64_t passes,
+              unsigned long long* __restrict__ res, int32_t nres, unsigned int* bar, unsigned int* err,
+              int64_t wait_ticks, int hints) {
+    using S = SW2<T, TX, TY>;
+    __shared__ T lds[S::LDS];
+    __shared__ T red[S::NT / 64];
+    const int ng = (gridDim.x >= 8 && gridDim.x % 8 == 0) ? 8 : 1;
+    const int xg = (int)(blockIdx.x % ng);
+    const int32_t first = (int32_t)(blockIdx.x / ng), step_w = (int32_t)(gridDim.x / ng);
+    __shared__ int s_xcd;
+    __shared__ unsigned int s_xwgs, s_nxcd;
+    if (passes > 1 && !persist_register(bar, err, wait_ticks, &s_xcd, &s_xwgs, &s_nxcd)) return;
+    for (int64_t it = 0; it < passes; ++it) {
+        const int p = parity ^ (int)(it & 1);
+        if (blockIdx.x == 0)
+            for (int s = (int)threadIdx.x; s < nres; s += S::NT) res[2 * s + p] = 0ull;
+        T r = 0;
+        int slot = -1;
+        for (int32_t idx = first;; idx += step_w) {
+            const int32_t ti = xg + ng * idx;
+            if (ti >= ntiles) break;
+            const TileDev& t = tiles[ti];
+            const T rr = t.nz > 0 ? sweep2_tile<T, TX, TY>(arena, blocks, t, tiles2[ti], p, lds, hints) : (T)0;
+            if (slot >= 0 && slot != t.rslot) {
+                wg_residual<T, S::NT>(r, &res[2 * slot + (p ^ 1)], red);
+                r = 0;
+            }
+            slot = t.rslot;
+            r = rr > r ? rr : r;
+        }
+        if (slot >= 0) wg_residual<T, S::NT>(r, &res[2 * slot + (p ^ 1)], red);
+        if (it + 1 < passes) {
+            if (!xcd_barrier(bar, err, wait_ticks, tile_ctr(bar, (int)((it + 1) & 1), 0), s_xcd, s_xwgs, s_nxcd))
+                return;
         }
     }
+    persist_cleanup(bar);
 }
 
 // ---------------------------------------------------------------------------
@@ -1744,9 +1799,14 @@ static std::string kernel_name(const char* base, int dtype_bytes, int tx, int ty
            ", " + std::to_string(ty) + (extra ? extra : "") + ">";
 }
 
+static std::string coop_name(int dtype_bytes, int tx, int ty, int kind) {
+    return kind == 1   ? kernel_name("k_msgdriven", dtype_bytes, tx, ty, nullptr)
+           : kind == 3 ? kernel_name("k_persistent2", dtype_bytes, tx, ty, nullptr)
+                       : kernel_name("k_persistent", dtype_bytes, tx, ty, kind == 2 ? ", true" : ", false");
+}
+
 int coop_waves_limit(int dtype_bytes, int tx, int ty, int kind) {
-    const std::string name = kind == 1 ? kernel_name("k_msgdriven", dtype_bytes, tx, ty, nullptr)
-                                       : kernel_name("k_persistent", dtype_bytes, tx, ty, kind == 2 ? ", true" : ", false");
+    const std::string name = coop_name(dtype_bytes, tx, ty, kind);
     int sg = 0;
     return kernel_resources(name.c_str(), &sg, nullptr, nullptr) ? waves_by_sgprs(sg) : 5;
 }
@@ -1758,8 +1818,20 @@ int persistent_max_grid(int dtype_bytes, int tx, int ty, int kind, int max_waves
     // default choice: the counter form (imbalance, uneven blocks) measured
     // faster at 5 waves per SIMD than at 6
     if (max_waves <= 0) max_waves = kind == 2 ? 5 : 8;
-    const std::string name = kind == 1 ? kernel_name("k_msgdriven", dtype_bytes, tx, ty, nullptr)
-                                       : kernel_name("k_persistent", dtype_bytes, tx, ty, kind == 2 ? ", true" : ", false");
+    const std::string name = coop_name(dtype_bytes, tx, ty, kind);
+    if (kind == 3) {
+#define OD_OCC2(T, TX, TY)                                                                            \
+        if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                  \
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent2<T, TX, TY>,          \
+                                                             SW2<T, TX, TY>::NT, 0) != hipSuccess)    \
+                return 0;                                                                             \
+            return coop_per_cu(per, SW2<T, TX, TY>::NT, name.c_str(), max_waves) * ncu;              \
+        }
+        OD_VARIANTS2_F64(OD_OCC2)
+        OD_VARIANTS2_F32(OD_OCC2)
+#undef OD_OCC2
+        return 0;
+    }
 #define OD_OCC(T, TX, TY)                                                                             \
     if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                      \
         hipError_t e = kind == 0                                                                      \
@@ -1798,6 +1870,25 @@ hipError_t launch_persistent(int dtype_bytes, int tx, int ty, hipStream_t st, in
     OD_VARIANTS_F64(OD_LAUNCH)
     OD_VARIANTS_F32(OD_LAUNCH)
 #undef OD_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_persistent2(int dtype_bytes, int tx, int ty, hipStream_t st, int grid, void* arena,
+                              const BlockDev* blocks, const TileDev* tiles, const Tile2Dev* tiles2, int32_t ntiles,
+                              int parity, int64_t passes, unsigned long long* res, int32_t nres, unsigned int* bar,
+                              unsigned int* err, int hints, int64_t wait_ticks) {
+    if (passes <= 0) return hipSuccess;
+#define OD_LAUNCH2(T, TX, TY)                                                                         \
+    if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                      \
+        T* ar = reinterpret_cast<T*>(arena);                                                          \
+        void* args[] = {&ar, &blocks, &tiles, &tiles2, &ntiles, &parity, &passes, &res, &nres, &bar,  \
+                        &err, &wait_ticks, &hints};                                                   \
+        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_persistent2<T, TX, TY>),    \
+                                          dim3(grid), dim3(SW2<T, TX, TY>::NT), args, 0, st);         \
+    }
+    OD_VARIANTS2_F64(OD_LAUNCH2)
+    OD_VARIANTS2_F32(OD_LAUNCH2)
+#undef OD_LAUNCH2
     return hipErrorInvalidValue;
 }
 

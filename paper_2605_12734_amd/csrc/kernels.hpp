@@ -138,6 +138,14 @@ hipError_t launch_sweep2(int dtype_bytes, int tx, int ty, hipStream_t st, void* 
                          const TileDev* tiles, const Tile2Dev* tiles2, int32_t ntiles, int parity,
                          unsigned long long* res, int32_t zero_lo, int32_t zero_hi, int hints);
 
+// Persistent form of the two-step pass: `passes` passes (2 * passes steps)
+// in one cooperative launch of `grid` workgroups, fixed stride, the
+// per-XCD barrier between passes; bar / err as launch_persistent.
+hipError_t launch_persistent2(int dtype_bytes, int tx, int ty, hipStream_t st, int grid, void* arena,
+                              const BlockDev* blocks, const TileDev* tiles, const Tile2Dev* tiles2, int32_t ntiles,
+                              int parity, int64_t passes, unsigned long long* res, int32_t nres, unsigned int* bar,
+                              unsigned int* err, int hints, int64_t wait_ticks);
+
 // Persistent cooperative sweep: all `iters` iterations in one launch with a
 // device-wide barrier between them.  dyn != 0: workgroups take tiles from
 // per-XCD-group counters (load balance under imbalance and uneven blocks);
@@ -182,7 +190,8 @@ inline int waves_by_sgprs(int sgprs) {
 int64_t device_wait_ticks(double seconds = 10.0);
 // Max co-resident workgroups of a cooperative kernel: kind 0 = persistent
 // with the static tile stride, 2 = persistent with tile counters (dyn),
-// 1 = message-driven; at most max_waves waves per SIMD (0 = the default
+// 1 = message-driven, 3 = persistent two-step passes; at most max_waves
+// waves per SIMD (0 = the default
 // choice: 5 for kind 2, else as many as the registers allow).
 int persistent_max_grid(int dtype_bytes, int tx, int ty, int kind, int max_waves = 0);
 // Waves per SIMD the kernel's recorded scalar registers allow.

@@ -166,12 +166,24 @@ namespace {
 // Pairs of iterations in one pass need a regular decomposition at one
 // resolution (every line of cells around a tile lies in one block), the 3D
 // stencil, no imbalance (a re-run chare would have to repeat both steps),
-// and a tile shape with a two-step variant.
+// and a tile shape with a two-step variant; the persistent form also its
+// fixed-stride schedule and no timeline.
 bool two_step_possible(const Grid& G) {
     const od_config& cfg = G.cfg;
     const Plan& p = G.plan;
-    return (cfg.exec == OD_FUSED || cfg.exec == OD_GRAPH) && !(cfg.hints & 4096) && p.regular && !p.multires &&
-           cfg.stencil != 5 && G.imb.heavy == 0;
+    const bool form = cfg.exec == OD_FUSED || cfg.exec == OD_GRAPH ||
+                      (cfg.exec == OD_PERSISTENT && G.sched() == 1 && !(cfg.hints & kHintTimeline));
+    return form && !(cfg.hints & 4096) && p.regular && !p.multires && cfg.stencil != 5 && G.imb.heavy == 0;
+}
+
+// Room for two-step descriptors: the forms that can pair steps under any
+// schedule the autotuner may choose.
+bool two_step_room(const Grid& G) {
+    const od_config& cfg = G.cfg;
+    const Plan& p = G.plan;
+    const bool form = cfg.exec == OD_FUSED || cfg.exec == OD_GRAPH ||
+                      (cfg.exec == OD_PERSISTENT && !(cfg.hints & (kHintTimeline | 16 | 32 | 2048)));
+    return form && !(cfg.hints & 4096) && p.regular && !p.multires && cfg.stencil != 5 && G.imb.heavy == 0;
 }
 
 // Block and local coordinates of global cell (x, y, z) as a FaceDev: its
@@ -321,13 +333,20 @@ std::string fill_tile_descs(Grid& G) {
             }
         }
     }
+    decide_two_step(G);
+    return "";
+}
+
+// Pair steps where the grid's form, schedule and tile allow it; the tiles'
+// line descriptors follow the tile list.
+void decide_two_step(Grid& G) {
+    const Plan& p = G.plan;
     G.two_step = two_step_possible(G) && sweep2_variant_ok(G.s, p.tile[0], p.tile[1]);
     G.tiles2_h.clear();
     if (G.two_step) {
-        G.tiles2_h.resize(ntiles);
-        for (size_t i = 0; i < ntiles; ++i) fill_tile2(G, p.tiles[i], G.tiles2_h[i]);
+        G.tiles2_h.resize(p.tiles.size());
+        for (size_t i = 0; i < p.tiles.size(); ++i) fill_tile2(G, p.tiles[i], G.tiles2_h[i]);
     }
-    return "";
 }
 
 // ---------------------------------------------------------------------------
@@ -547,8 +566,8 @@ std::string build_layout(const od_config& cfg, Grid& G) {
     // workgroup plus padding (guided_tail); cooperative grids stay below 8192
     if (cfg.exec == OD_PERSISTENT) G.tile_cap += 3 * 8192 + kNumXcd;
     G.L.tiles = cv.take(G.tile_cap * sizeof(TileDev));
-    G.halo2_cells = two_step_possible(G) ? halo2_count(p) : 0;
-    G.L.tiles2 = cv.take((two_step_possible(G) ? G.tile_cap : 1) * sizeof(Tile2Dev));
+    G.halo2_cells = two_step_room(G) ? halo2_count(p) : 0;
+    G.L.tiles2 = cv.take((two_step_room(G) ? G.tile_cap : 1) * sizeof(Tile2Dev));
     for (int d = 0; d < 3; ++d) G.L.cidx[d] = cv.take((size_t)(p.regular ? p.n[d] : 1) * 4);
     G.L.owner = cv.take((p.regular ? 1 : p.owner.size()) * 4);
     G.L.corigin = cv.take((size_t)C * 3 * 4);
@@ -736,6 +755,9 @@ od_status Grid::setup_cooperative(bool fresh_plan) {
     grid_wgs = 0;
     if (cfg.exec != OD_PERSISTENT && cfg.exec != OD_MSGDRIVEN) return OD_OK;
     if (fresh_plan || base_tiles.empty()) base_tiles = plan.tiles;
+    // the schedule may have changed since the tile list was built: the
+    // kernel (and with it the co-resident grid) follows it
+    if (cfg.exec == OD_PERSISTENT) two_step = two_step_possible(*this) && sweep2_variant_ok(s, plan.tile[0], plan.tile[1]);
     const int cap = persistent_max_grid(s, plan.tile[0], plan.tile[1], coop_kind(), persist_waves);
     int grid = std::min<int>(cap, (int)base_tiles.size());
     if (grid >= kNumXcd) grid -= grid % kNumXcd;
@@ -744,14 +766,12 @@ od_status Grid::setup_cooperative(bool fresh_plan) {
     if (cfg.exec == OD_PERSISTENT) {
         std::vector<TileHost> list = sched() == 3 ? guided_tail(plan, base_tiles, grid / kNumXcd, 4) : base_tiles;
         if (list.size() > tile_cap) return fail(OD_EINVAL, "cut tile list exceeds the tile capacity");
-        if (list.size() != plan.tiles.size() || !fresh_plan) {
+        if (list.size() != plan.tiles.size() || !fresh_plan || two_step) {
             plan.tiles.swap(list);
-            std::string e = fill_tile_descs(*this);
+            std::string e = fill_tile_descs(*this);   // also the two-step lines of the final list
             if (!e.empty()) return fail(OD_EINVAL, e);
-            hipError_t he = hipMemcpyAsync(cp(L.tiles), tiles_h.data(), tiles_h.size() * sizeof(TileDev),
-                                           hipMemcpyHostToDevice, st);
-            if (he == hipSuccess) he = hipStreamSynchronize(st);
-            if (he != hipSuccess) return fail(OD_EHIP, std::string("tile upload: ") + hipGetErrorString(he));
+            od_status us = upload_tiles();
+            if (us != OD_OK) return us;
         }
     }
     return OD_OK;
@@ -962,6 +982,27 @@ od_status Grid::graph_run(int64_t n) {
 
 od_status Grid::persistent_run(int64_t n) {
     if (grid_wgs <= 0) return fail(OD_EHIP, "persistent kernel: no co-resident workgroups");
+    if (two_step) {
+        // n / 2 two-step passes in one launch, an odd last step as a single sweep
+        const int64_t passes = n / 2;
+        hipError_t e = launch_persistent2(s, plan.tile[0], plan.tile[1], st, grid_wgs, base,
+                                          reinterpret_cast<const BlockDev*>(cp(L.blocks)),
+                                          reinterpret_cast<const TileDev*>(cp(L.tiles)),
+                                          reinterpret_cast<const Tile2Dev*>(cp(L.tiles2)), (int32_t)tiles_h.size(),
+                                          parity, passes, res_ptr(), 1, reinterpret_cast<unsigned int*>(cp(L.bar)),
+                                          reinterpret_cast<unsigned int*>(cp(L.err)), mode(),
+                                          device_wait_ticks(cfg.wait_s > 0 ? cfg.wait_s : 10.0));
+        if (e != hipSuccess) return fail(OD_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
+        parity ^= (int)(passes & 1);
+        iters += 2 * passes;
+        if (n & 1) {
+            od_status os = fused_one(st, parity, iters);
+            if (os != OD_OK) return os;
+            parity ^= 1;
+            iters += 1;
+        }
+        return OD_OK;
+    }
     unsigned long long* stamps = nullptr;
     if (cfg.hints & kHintTimeline) {
         stamps = reinterpret_cast<unsigned long long*>(cp(L.stamps));

@@ -77,7 +77,9 @@ struct Grid {
     }
     bool persistent_dyn() const { return sched() == 2 || sched() == 3; }
     // cooperative-kernel kind for persistent_max_grid
-    int coop_kind() const { return cfg.exec == OD_MSGDRIVEN ? 1 : (persistent_dyn() ? 2 : 0); }
+    int coop_kind() const {
+        return cfg.exec == OD_MSGDRIVEN ? 1 : (two_step ? 3 : (persistent_dyn() ? 2 : 0));
+    }
     std::vector<TileHost> base_tiles;   // the planner's tile list before schedule-specific cuts
     std::vector<MsgBufs> msg;
     int32_t nres = 1;
@@ -161,6 +163,7 @@ struct Grid {
 
 std::string build_layout(const od_config& cfg, Grid& G);
 std::string fill_tile_descs(Grid& G);
+void decide_two_step(Grid& G);
 // Smallest tile extents any autotune candidate uses for a dtype.
 void tune_min_tile(int dtype_bytes, int32_t ey_max, int32_t m[3]);
 od_status autotune(Grid& G, int32_t iters, int32_t out_tile[3]);

@@ -92,10 +92,39 @@ def test_one_step_hint_and_pairs_identical_at_256(exec_):
     assert np.array_equal(a, b) and ra == rb
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("iters", [1, 2, 7, 12])
+def test_persistent_pairs(dtype, iters):
+    plan = _case(64, 8, dtype, iters, exec_="persistent")
+    assert plan["steps_per_pass"] == 2 and plan["schedule"] == 1
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_persistent_pairs_ragged(dtype):
+    plan = _case((150, 90, 70), 27, dtype, 9, exec_="persistent", tile=(32, 16, 16), bc=BC6, seed=7)
+    assert plan["steps_per_pass"] == 2
+
+
+def test_persistent_pairs_then_single_steps_resume():
+    # a persistent grid run in pieces (pairs, then an odd step, then pairs)
+    # ends on the oracle's bits
+    want, _, r_w = oracle.solve(64, np.float64, seed=12734, iters=11, bc=od.DEFAULT_BC)
+    g = od.Grid(64, odf=64, dtype="f64", exec="persistent", hints=1)
+    try:
+        for k in (4, 3, 4):
+            g.iterate(k)
+        U, r = g.read(), g.residual()
+    finally:
+        g.close()
+    _same(U, want)
+    assert r == r_w
+
+
 def test_not_used_where_unsupported():
-    # imbalance, 2D stencil and persistent grids keep one step per pass
+    # imbalance, a forced persistent schedule and the message-driven and
+    # per-chare forms keep one step per pass
     for kw in ({"exec": "fused", "imbalance_pct": 10, "imbalance_max_extra": 2},
-               {"exec": "persistent"}, {"exec": "msgdriven"}, {"exec": "per_chare"}):
+               {"exec": "persistent", "hints": 16}, {"exec": "msgdriven"}, {"exec": "per_chare"}):
         g = od.Grid(64, odf=8, dtype="f64", **kw)
         try:
             assert g.plan()["steps_per_pass"] == 1

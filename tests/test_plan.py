@@ -269,7 +269,9 @@ def test_two_step_pass_bytes_brute_force(n, odf, dtype):
     assert plan["bytes_per_iter"] == s * (2 * plan["interior"] + plan["halo_cells"])
 
 
-@pytest.mark.parametrize("kw", [{"exec": "persistent"}, {"exec": "msgdriven"}, {"exec": "per_chare"},
+@pytest.mark.parametrize("kw", [{"exec": "persistent", "hints": 16}, {"exec": "persistent", "hints": 32},
+                                {"exec": "persistent", "hints": 2048}, {"exec": "persistent", "hints": 8},
+                                {"exec": "msgdriven"}, {"exec": "per_chare"},
                                 {"exec": "fused", "hints": 4096},
                                 {"exec": "fused", "imbalance_pct": 10, "imbalance_max_extra": 2},
                                 {"exec": "fused", "tile": (128, 4, 8)}])
@@ -279,3 +281,9 @@ def test_two_step_only_where_supported(kw):
     plan = od.host_plan(n=(64, 64, 64), odf=8, dtype="f64", **kw)
     assert plan["steps_per_pass"] == 1
     assert plan["bytes_per_pass"] == plan["bytes_per_iter"]
+
+
+@pytest.mark.parametrize("exec_", ["fused", "graph", "persistent"])
+def test_two_step_default_forms(exec_):
+    plan = od.host_plan(n=(64, 64, 64), odf=8, dtype="f64", exec=exec_)
+    assert plan["steps_per_pass"] == 2
