@@ -538,6 +538,9 @@ __device__ __forceinline__ T sweep2_tile(T* __restrict__ arena, const BlockDev* 
     T* UL = lds + 2 * S::TR * LP;     // [2][UR][LP]
     auto tl = [&](int b, int y, int c) -> T& { return TL[(b * S::TR + y + 2) * LP + c]; };
     auto ul = [&](int b, int y, int c) -> T& { return UL[(b * S::UR + y + 1) * LP + c]; };
+    // whole-vector LDS accesses at a lane's cells (16-byte aligned: the
+    // row pitch and the interior's first column are multiples of VX)
+    auto vref = [](T& e) -> VT& { return *reinterpret_cast<VT*>(&e); };
 
     constexpr int PF = OD_PREFETCH;
     VT tz[PF + 3];   // time-t column of the lane's cells: planes j-1 .. j+PF+1
@@ -560,7 +563,9 @@ __device__ __forceinline__ T sweep2_tile(T* __restrict__ arena, const BlockDev* 
         const T c2n = lds1(r2_b + lim(j + 1) * r2_pz);
 
         // stage time-t plane j
-        if (act) {
+        if (nv == VX) {
+            vref(tl(b, ly, VX + x)) = tz[1];
+        } else if (act) {
 #pragma unroll
             for (int i = 0; i < VX; ++i)
                 if (i < nv) tl(b, ly, VX + x + i) = tz[1][i];
@@ -572,19 +577,24 @@ __device__ __forceinline__ T sweep2_tile(T* __restrict__ arena, const BlockDev* 
         // first step of plane j on the tile (Dirichlet z plane: its value)
         const bool zfix = (j < 0 && (dir & 16)) || (j >= nz && (dir & 32));
         VT u;
+        {
+            const VT ym = vref(tl(b, ly - 1, VX + x)), yp = vref(tl(b, ly + 1, VX + x));
 #pragma unroll
-        for (int i = 0; i < VX; ++i) {
-            const T xm = i > 0 ? tz[1][i - 1] : tl(b, ly, VX + x - 1);
-            const T xp = (i < VX - 1 && i + 1 < nv) ? tz[1][i + 1] : tl(b, ly, VX + x + i + 1);
-            T s = xm;
-            s = s + xp;
-            s = s + tl(b, ly - 1, VX + x + i);
-            s = s + tl(b, ly + 1, VX + x + i);
-            s = s + tz[0][i];
-            s = s + tz[2][i];
-            u[i] = zfix ? tz[1][i] : s / (T)6;
+            for (int i = 0; i < VX; ++i) {
+                const T xm = i > 0 ? tz[1][i - 1] : tl(b, ly, VX + x - 1);
+                const T xp = (i < VX - 1 && i + 1 < nv) ? tz[1][i + 1] : tl(b, ly, VX + x + i + 1);
+                T s = xm;
+                s = s + xp;
+                s = s + ym[i];
+                s = s + yp[i];
+                s = s + tz[0][i];
+                s = s + tz[2][i];
+                u[i] = zfix ? tz[1][i] : s / (T)6;
+            }
         }
-        if (act) {
+        if (nv == VX) {
+            vref(ul(b, ly, VX + x)) = u;
+        } else if (act) {
 #pragma unroll
             for (int i = 0; i < VX; ++i)
                 if (i < nv) ul(b, ly, VX + x + i) = u[i];
@@ -604,14 +614,15 @@ __device__ __forceinline__ T sweep2_tile(T* __restrict__ arena, const BlockDev* 
         if (j >= 1) {
             const int c = b ^ 1;
             VT out;
+            const VT ym = vref(ul(c, ly - 1, VX + x)), yp = vref(ul(c, ly + 1, VX + x));
 #pragma unroll
             for (int i = 0; i < VX; ++i) {
                 const T xm = i > 0 ? um1[i - 1] : ul(c, ly, VX + x - 1);
                 const T xp = (i < VX - 1 && i + 1 < nv) ? um1[i + 1] : ul(c, ly, VX + x + i + 1);
                 T s = xm;
                 s = s + xp;
-                s = s + ul(c, ly - 1, VX + x + i);
-                s = s + ul(c, ly + 1, VX + x + i);
+                s = s + ym[i];
+                s = s + yp[i];
                 s = s + um2[i];
                 s = s + u[i];
                 const T v = s / (T)6;
@@ -648,7 +659,7 @@ k_sweep2(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileD
          const Tile2Dev* __restrict__ tiles2, int parity, unsigned long long* __restrict__ res, int zero_lo,
          int zero_hi, int hints) {
     using S = SW2<T, TX, TY>;
-    __shared__ T lds[S::LDS];
+    __shared__ __align__(16) T lds[S::LDS];
     __shared__ T red[S::NT / 64];
     if (blockIdx.x == 0)
         for (int s = zero_lo + (int)threadIdx.x; s < zero_hi; s += S::NT) res[2 * s + parity] = 0ull;
@@ -932,7 +943,7 @@ k_persistent2(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const 
               unsigned long long* __restrict__ res, int32_t nres, unsigned int* bar, unsigned int* err,
               int64_t wait_ticks, int hints) {
     using S = SW2<T, TX, TY>;
-    __shared__ T lds[S::LDS];
+    __shared__ __align__(16) T lds[S::LDS];
     __shared__ T red[S::NT / 64];
     const int ng = (gridDim.x >= 8 && gridDim.x % 8 == 0) ? 8 : 1;
     const int xg = (int)(blockIdx.x % ng);
@@ -2013,8 +2024,9 @@ __global__ void k_init_cells(GridDev g, const int32_t* __restrict__ ccell, int32
 // takes every 64th ghost cell of the batch, sums its R values in the fixed
 // order (q2 outer, q1 inner) and stores the mean.  (Summing in each lane straight from memory serialised
 // the loads: r = 8 cells took 64 dependent loads each.  Batches of 1024
-// values were slower: fewer waves fit.  What remains is mostly the x-normal
-// faces, whose source values are one per row of the neighbour.)
+// values were slower: fewer waves fit.)  x-normal faces read the source
+// chare's exported column (FillSeg::eoff, written by the sweep) instead of
+// one value per row of its storage.
 constexpr int kFillLanes = 64, kFillBatch = 256;
 
 template <typename T>
