@@ -229,11 +229,14 @@ def odf_sweep(n, iters, persistent=True):
             if persistent:
                 # tile and schedule tuned on the persistent kernel itself
                 q = grid_leg(n, odf, dtype, "persistent", iters, 2, 1)
+                gq = pass_gbps(q["plan"], q["launch_s"])
                 row.update({"persistent_tile": list(q["plan"]["tile"]),
                             "persistent_schedule": SCHEDULES.get(q["plan"]["schedule"], q["plan"]["schedule"]),
+                            "persistent_steps_per_pass": q["plan"]["steps_per_pass"],
                             "persistent_glups": round(q["glups"], 2),
-                            "persistent_hbm_gbps": round(bp / q["launch_s"] / 1e9, 1),
-                            "persistent_frac": round(bp / q["launch_s"] / 1e9 / PEAK_HBM_GBPS, 4),
+                            "persistent_hbm_gbps": round(gq, 1),
+                            "persistent_frac": round(gq / PEAK_HBM_GBPS, 4),
+                            "persistent_step_bytes_frac": round(bp / q["launch_s"] / 1e9 / PEAK_HBM_GBPS, 4),
                             "persistent_us_per_iter": round(q["launch_s"] * 1e6, 2),
                             "persistent_grid_wgs": q["plan"]["grid_wgs"]})
             pc_iters = 10 if odf <= 64 else (4 if odf <= 512 else 2)
@@ -261,9 +264,12 @@ def amr_leg(iters=500, multires_only=False):
         finally:
             g.close()
         bp = plan["bytes_per_iter"]
+        gb = pass_gbps(plan, t["dev_s"] / iters)
         out[exec_] = {"glups": round(plan["interior"] * iters / t["wall_s"] / 1e9, 2),
-                      "hbm_gbps": round(bp * iters / t["dev_s"] / 1e9, 1),
-                      "frac": round(bp * iters / t["dev_s"] / 1e9 / PEAK_HBM_GBPS, 4),
+                      "steps_per_pass": plan["steps_per_pass"],
+                      "hbm_gbps": round(gb, 1),
+                      "frac": round(gb / PEAK_HBM_GBPS, 4),
+                      "step_bytes_frac": round(bp * iters / t["dev_s"] / 1e9 / PEAK_HBM_GBPS, 4),
                       "tile": list(plan["tile"]), "tiles": plan["ntiles"], "iters": iters}
         log("amr:", exec_, out[exec_])
     # multi-resolution reading: the same octree, 16 cells per leaf edge

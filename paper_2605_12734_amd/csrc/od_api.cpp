@@ -163,17 +163,18 @@ int64_t build_fill_segments(Grid& G) {
 
 namespace {
 
-// Pairs of iterations in one pass need a regular decomposition at one
-// resolution (every line of cells around a tile lies in one block), the 3D
-// stencil, no imbalance (a re-run chare would have to repeat both steps),
-// and a tile shape with a two-step variant; the persistent form also its
-// fixed-stride schedule and no timeline.
+// Pairs of iterations in one pass need blocks at one resolution (every
+// line of cells around a tile in one block: so in a regular decomposition;
+// explicit blocks have their tiles split until it holds), the 3D stencil,
+// no imbalance (a re-run chare would have to repeat both steps), and a tile
+// shape with a two-step variant; the persistent form also its fixed-stride
+// schedule and no timeline.
 bool two_step_possible(const Grid& G) {
     const od_config& cfg = G.cfg;
     const Plan& p = G.plan;
     const bool form = cfg.exec == OD_FUSED || cfg.exec == OD_GRAPH ||
                       (cfg.exec == OD_PERSISTENT && G.sched() == 1 && !(cfg.hints & kHintTimeline));
-    return form && !(cfg.hints & 4096) && p.regular && !p.multires && cfg.stencil != 5 && G.imb.heavy == 0;
+    return form && !(cfg.hints & 4096) && !p.multires && cfg.stencil != 5 && G.imb.heavy == 0;
 }
 
 // Room for two-step descriptors: the forms that can pair steps under any
@@ -183,7 +184,8 @@ bool two_step_room(const Grid& G) {
     const Plan& p = G.plan;
     const bool form = cfg.exec == OD_FUSED || cfg.exec == OD_GRAPH ||
                       (cfg.exec == OD_PERSISTENT && !(cfg.hints & (kHintTimeline | 16 | 32 | 2048)));
-    return form && !(cfg.hints & 4096) && p.regular && !p.multires && cfg.stencil != 5 && G.imb.heavy == 0;
+    const bool imbalance = cfg.imbalance_pct > 0 && cfg.imbalance_max_extra > 0;
+    return form && !(cfg.hints & 4096) && !p.multires && cfg.stencil != 5 && !imbalance;
 }
 
 // Block and local coordinates of global cell (x, y, z) as a FaceDev: its
@@ -393,6 +395,7 @@ std::string build_layout(const od_config& cfg, Grid& G) {
     p.xcd_split_chares = p.xcd_boxes && cfg.imbalance_pct > 0 && p.chares.size() < (size_t)OD_SPLIT_CHARES_BELOW;
     if (!sweep_variant_ok(G.s, p.tile[0], p.tile[1]))
         return "tile (" + std::to_string(p.tile[0]) + "," + std::to_string(p.tile[1]) + ") is not a compiled variant";
+    p.two_step_lines = !p.regular && two_step_room(G);
     err = plan_tiles(p);
     if (!err.empty()) return err;
     if (cfg.exec == OD_PER_CHARE) {

@@ -92,6 +92,10 @@ struct Plan {
     bool multires = false;               // some chare has h != 1
     std::vector<uint8_t> mr;             // per (chare, face): the face borders another cell size
     int32_t gcell = 0;                   // gcd of chare origins / extents in own cells (tile splits)
+    // explicit blocks at one resolution that may run two steps per pass:
+    // tiles are also split until every line of cells the pair reads beyond
+    // the face slabs lies in one block
+    bool two_step_lines = false;
 };
 
 // Build the decomposition (chares + owner lookup).  Returns "" or an error.

@@ -60,7 +60,8 @@ struct Grid {
     std::vector<int32_t> dep_ptr, dep_idx;
     ImbDev imb{};                    // load-imbalance draw (heavy == 0: none)
     // Persistent schedule: 0 = automatic (counters under imbalance or with
-    // uneven blocks, else the fixed stride), 1 = fixed stride, 2 = tiles
+    // uneven blocks that keep one step per pass, else the fixed stride),
+    // 1 = fixed stride, 2 = tiles
     // from per-XCD-group counters, 3 = counters with the last tiles of each
     // group cut into z-ranges (guided_tail), 4 = fixed contiguous runs per
     // workgroup.  hints bits 4, 5 and 11 force 2, 3 and 4; the autotuner
@@ -73,7 +74,9 @@ struct Grid {
         if (cfg.hints & 32) return 3;
         if (cfg.hints & 16) return 2;
         if (persist_sched) return persist_sched;
-        return (imb.heavy > 0 || !plan.regular) ? 2 : 1;
+        // uneven blocks take tiles from counters, unless they run two steps
+        // per pass (the fixed stride then, the only two-step schedule)
+        return (imb.heavy > 0 || (!plan.regular && !plan.two_step_lines)) ? 2 : 1;
     }
     bool persistent_dyn() const { return sched() == 2 || sched() == 3; }
     // cooperative-kernel kind for persistent_max_grid

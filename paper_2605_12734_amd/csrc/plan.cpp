@@ -337,6 +337,61 @@ int32_t slab_owner(const Plan& p, const Box& b, int* split_dim, int64_t* split_a
 
 }  // namespace
 
+// Two steps per pass read, beyond a tile's face slabs, the slabs two cells
+// out, the four (x, y) corner columns and the one-cell ring's rows just
+// below and above the tile.  Each must lie in one block (a box in the
+// domain's ghost shell along one axis: in the face buffer of one block,
+// i.e. its projection onto the boundary layer in one block; along two axes
+// it is never read).  Returns true with a cut (*split_dim, *split_at, a
+// global coordinate along one of the tile's extents) if one does not.
+static bool two_step_straddle(const Plan& p, const Chare& c, const TileHost& t, int* split_dim, int64_t* split_at) {
+    Box tb;
+    for (int d = 0; d < 3; ++d) {
+        tb.lo[d] = (int64_t)c.u[d] + (int64_t)t.o[d] * c.h;
+        tb.hi[d] = tb.lo[d] + (int64_t)t.e[d] * c.h;
+    }
+    std::vector<Box> boxes;
+    for (int f = 0; f < 6; ++f) {   // slabs two cells out
+        Box b = tb;
+        const int d = f / 2;
+        b.lo[d] = (f % 2) ? tb.hi[d] + 1 : tb.lo[d] - 2;
+        b.hi[d] = b.lo[d] + 1;
+        boxes.push_back(b);
+    }
+    const int64_t xs[2] = {tb.lo[0] - 1, tb.hi[0]}, ys[2] = {tb.lo[1] - 1, tb.hi[1]}, zs[2] = {tb.lo[2] - 1, tb.hi[2]};
+    for (int k = 0; k < 4; ++k) {
+        Box cz = tb, ax = tb, ay = tb;   // corner column along z; x-arm row along y; y-arm row along x
+        cz.lo[0] = xs[k & 1];
+        cz.lo[1] = ys[k >> 1];
+        ax.lo[0] = xs[k & 1];
+        ax.lo[2] = zs[k >> 1];
+        ay.lo[1] = ys[k & 1];
+        ay.lo[2] = zs[k >> 1];
+        cz.hi[0] = cz.lo[0] + 1;
+        cz.hi[1] = cz.lo[1] + 1;
+        ax.hi[0] = ax.lo[0] + 1;
+        ax.hi[2] = ax.lo[2] + 1;
+        ay.hi[1] = ay.lo[1] + 1;
+        ay.hi[2] = ay.lo[2] + 1;
+        boxes.push_back(cz);
+        boxes.push_back(ax);
+        boxes.push_back(ay);
+    }
+    for (Box b : boxes) {
+        int outs = 0;
+        for (int d = 0; d < 3; ++d) {
+            if (b.hi[d] <= 0 || b.lo[d] >= p.n[d]) {
+                ++outs;
+                b.lo[d] = b.lo[d] < 0 ? 0 : p.n[d] - 1;
+                b.hi[d] = b.lo[d] + 1;
+            }
+        }
+        if (outs >= 2) continue;
+        if (slab_owner(p, b, split_dim, split_at) == -2) return true;
+    }
+    return false;
+}
+
 std::string plan_tiles(Plan& p) {
     for (int d = 0; d < 3; ++d)
         if (p.tile[d] < 1) return "tile extents must be >= 1";
@@ -396,6 +451,21 @@ std::string plan_tiles(Plan& p) {
                     }
                 }
                 for (int q = 0; q < 3; ++q) t.g[f][q] = (int32_t)(b.lo[q] >= 0 ? b.lo[q] / c.h : -1);
+            }
+            if (!split && p.two_step_lines) {
+                int sd = -1;
+                int64_t sat = 0;
+                if (two_step_straddle(p, c, t, &sd, &sat)) {
+                    int64_t cut = (sat - c.u[sd]) / c.h - t.o[sd];
+                    if (cut <= 0 || cut >= t.e[sd]) return "internal error: bad two-step tile split";
+                    TileHost a = t, bb = t;
+                    a.e[sd] = (int32_t)cut;
+                    bb.o[sd] = t.o[sd] + (int32_t)cut;
+                    bb.e[sd] = t.e[sd] - (int32_t)cut;
+                    work.push_back(bb);
+                    work.push_back(a);
+                    split = true;
+                }
             }
             if (split) continue;
             for (int f = 0; f < 6; ++f)

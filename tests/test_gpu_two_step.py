@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 import paper_2605_12734_amd as od
+import workloads
 
 pytestmark = pytest.mark.gpu
 
@@ -143,3 +144,24 @@ def test_bytes_per_pass_counts_two_step_reach():
     per_chare = 3 * 2 * 32 * 32 + 3 * 32
     assert p["bytes_per_pass"] == 8 * (2 * 64 ** 3 + 8 * per_chare)
     assert p["bytes_per_iter"] == 8 * (2 * 64 ** 3 + 8 * 3 * 32 * 32)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("exec_", ["fused", "graph", "persistent"])
+@pytest.mark.parametrize("tile", [(16, 16, 8), (32, 16, 16), (32, 32, 32)])
+def test_uneven_octree_pairs(dtype, exec_, tile):
+    # explicit blocks at one resolution: tiles are cut until every line of
+    # cells a pair reads lies in one block
+    if dtype == "f32" and tile == (16, 16, 8):
+        tile = (32, 16, 8)
+    blocks = workloads.octree_blocks(n=96, root=32, min_edge=8, p_refine=0.5, seed=7)
+    want, _, r_w = oracle.solve(96, DT[dtype], seed=3, iters=9, bc=BC6)
+    g = od.Grid(96, blocks=blocks, dtype=dtype, exec=exec_, tile=tile, bc=BC6, seed=3, hints=1)
+    try:
+        assert g.plan()["steps_per_pass"] == 2
+        g.iterate(9)
+        U, r = g.read(), g.residual()
+    finally:
+        g.close()
+    _same(U, want)
+    assert r == r_w

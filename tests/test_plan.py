@@ -287,3 +287,54 @@ def test_two_step_only_where_supported(kw):
 def test_two_step_default_forms(exec_):
     plan = od.host_plan(n=(64, 64, 64), odf=8, dtype="f64", exec=exec_)
     assert plan["steps_per_pass"] == 2
+
+
+def _two_step_boxes(o, e, n):
+    """Boxes of cells a pair of steps reads beyond a tile's face slabs
+    (tile origin o, extent e): slabs two out, (x, y) corner columns, the
+    one-out ring's rows below and above; a box outside the domain along one
+    axis is projected onto the boundary layer, along two it is dropped."""
+    lo = list(o)
+    hi = [o[d] + e[d] for d in range(3)]
+    out = []
+    for f in range(6):
+        d = f // 2
+        a, b = list(lo), list(hi)
+        a[d] = hi[d] + 1 if f % 2 else lo[d] - 2
+        b[d] = a[d] + 1
+        out.append((a, b))
+    xs, ys, zs = (lo[0] - 1, hi[0]), (lo[1] - 1, hi[1]), (lo[2] - 1, hi[2])
+    for k in range(4):
+        for fix in ({0: xs[k & 1], 1: ys[k >> 1]}, {0: xs[k & 1], 2: zs[k >> 1]}, {1: ys[k & 1], 2: zs[k >> 1]}):
+            a, b = list(lo), list(hi)
+            for d, v in fix.items():
+                a[d], b[d] = v, v + 1
+            out.append((a, b))
+    res = []
+    for a, b in out:
+        outs = [d for d in range(3) if b[d] <= 0 or a[d] >= n[d]]
+        if len(outs) >= 2:
+            continue
+        for d in outs:
+            a[d] = 0 if a[d] < 0 else n[d] - 1
+            b[d] = a[d] + 1
+        res.append((a, b))
+    return res
+
+
+@pytest.mark.parametrize("tile", [(16, 16, 8), (32, 16, 16), (32, 32, 32)])
+def test_two_step_octree_tiles_read_single_blocks(tile):
+    # explicit blocks: the planner cuts tiles until every box of cells a
+    # pair of steps reads beyond the face slabs lies in one block
+    blocks = workloads.octree_blocks(n=96, root=32, min_edge=8, p_refine=0.5, seed=7)
+    plan = od.host_plan(n=96, blocks=blocks, dtype="f64", exec="fused", tile=tile)
+    assert plan["steps_per_pass"] == 2
+    n = (96, 96, 96)
+    own = _owner_map(n, plan["chares"])
+    _check_plan(n, plan)
+    for t in plan["tiles"]:
+        co, _ = plan["chares"][t["chare"]]
+        o = [co[d] + t["origin"][d] for d in range(3)]
+        for a, b in _two_step_boxes(o, t["extent"], n):
+            ids = np.unique(own[a[2]:b[2], a[1]:b[1], a[0]:b[0]])
+            assert len(ids) == 1, (t, a, b, ids)
