@@ -137,13 +137,16 @@ typedef struct {
      * per workgroup and step);
      * bit 11 (OD_PERSISTENT): fixed schedule with contiguous runs of each
      * XCD group's tiles per workgroup;
-     * bit 12 (OD_FUSED, OD_GRAPH): one step per pass.  By default these
-     * forms run iterations in pairs where they can (regular blocks at one
-     * resolution, 3D stencil, no imbalance, a tile shape with a two-step
-     * variant): one pass reads the field once and writes it two steps
+     * bit 12 (OD_FUSED, OD_GRAPH, OD_PERSISTENT): one step per pass.  By
+     * default these forms run iterations in pairs where they can (blocks
+     * at one resolution, 3D stencil, no imbalance, a tile shape with a
+     * two-step variant; OD_PERSISTENT with its fixed-stride schedule and
+     * no timeline): one pass reads the field once and writes it two steps
      * later, the first step kept on chip (the same values as two single
      * sweeps, bit for bit); od_iterate(n) with odd n ends with a single
-     * sweep.  od_plan_info.steps_per_pass tells which is in use.
+     * sweep.  With explicit blocks the tiles are also cut so that every
+     * line of cells a pair reads lies in one block.
+     * od_plan_info.steps_per_pass tells which is in use.
      * Bit 8 is reserved.  Other bits are ignored. */
     int32_t hints;
     /* 7 (or 0): 3D 7-point stencil.  5: the 2D 5-point stencil of the
@@ -233,7 +236,9 @@ od_status od_create_static(const od_config* cfg, void* hip_stream, void* dev_fie
  * every chare exchanges halos with its neighbours and sweeps its block
  * (Section V, Jacobi2D, here with the 3D 7-point stencil), in the form
  * cfg.exec names (Section III for the per-chare form and the fused and
- * graph-captured mitigations cited in Section I).  Allocates nothing and
+ * graph-captured mitigations cited in Section I).  Where the grid runs
+ * iterations in pairs (od_plan_info.steps_per_pass == 2, hints bit 12) a
+ * pass does two of them, with identical results.  Allocates nothing and
  * does not synchronise, except in OD_PER_CHARE mode whose host loop itself
  * issues the work. */
 od_status od_iterate(struct od_grid* g, int64_t n);
@@ -298,8 +303,8 @@ typedef struct {
                                        storage (the buffer od_create_static takes)    */
     int64_t control_bytes;          /* rest of the workspace: descriptors and device
                                        state, for this handle's plan                 */
-    int32_t steps_per_pass;         /* 2: OD_FUSED / OD_GRAPH run iterations in pairs
-                                       (hints bit 12); else 1                         */
+    int32_t steps_per_pass;         /* 2: iterations run in pairs (OD_FUSED, OD_GRAPH,
+                                       OD_PERSISTENT; hints bit 12); else 1           */
     int64_t bytes_per_pass;         /* algorithmic HBM bytes of one pass: one sweep, or
                                        with two steps per pass s * (2*interior + cells
                                        of other chares within two steps' reach)       */

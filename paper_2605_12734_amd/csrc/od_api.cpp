@@ -343,7 +343,8 @@ std::string fill_tile_descs(Grid& G) {
 // line descriptors follow the tile list.
 void decide_two_step(Grid& G) {
     const Plan& p = G.plan;
-    G.two_step = two_step_possible(G) && sweep2_variant_ok(G.s, p.tile[0], p.tile[1]);
+    G.two_step = two_step_possible(G) && sweep2_variant_ok(G.s, p.tile[0], p.tile[1]) &&
+                 p.tiles.size() <= G.tile2_cap;
     G.tiles2_h.clear();
     if (G.two_step) {
         G.tiles2_h.resize(p.tiles.size());
@@ -567,10 +568,20 @@ std::string build_layout(const od_config& cfg, Grid& G) {
     }
     // the persistent form's guided tail adds up to three entries per
     // workgroup plus padding (guided_tail); cooperative grids stay below 8192
+    // two-step line descriptors: room for the planned tiles and for
+    // autotune candidates down to (32, 8, 16) tiles (finer candidates run
+    // one step per pass); two-step lists are never cut by a guided tail
+    G.tile2_cap = 0;
+    if (two_step_room(G)) {
+        size_t cap2 = 0;
+        for (const Chare& c : p.chares)
+            cap2 += (size_t)ceil_div(c.e[0], 32) * (size_t)ceil_div(c.e[1], 8) * (size_t)ceil_div(c.e[2], 16);
+        G.tile2_cap = std::min(G.tile_cap, std::max(ntiles, G.tune_room ? cap2 * (p.regular ? 1 : 2) : ntiles));
+    }
     if (cfg.exec == OD_PERSISTENT) G.tile_cap += 3 * 8192 + kNumXcd;
     G.L.tiles = cv.take(G.tile_cap * sizeof(TileDev));
     G.halo2_cells = two_step_room(G) ? halo2_count(p) : 0;
-    G.L.tiles2 = cv.take((two_step_room(G) ? G.tile_cap : 1) * sizeof(Tile2Dev));
+    G.L.tiles2 = cv.take(std::max<size_t>(G.tile2_cap, 1) * sizeof(Tile2Dev));
     for (int d = 0; d < 3; ++d) G.L.cidx[d] = cv.take((size_t)(p.regular ? p.n[d] : 1) * 4);
     G.L.owner = cv.take((p.regular ? 1 : p.owner.size()) * 4);
     G.L.corigin = cv.take((size_t)C * 3 * 4);
@@ -760,7 +771,9 @@ od_status Grid::setup_cooperative(bool fresh_plan) {
     if (fresh_plan || base_tiles.empty()) base_tiles = plan.tiles;
     // the schedule may have changed since the tile list was built: the
     // kernel (and with it the co-resident grid) follows it
-    if (cfg.exec == OD_PERSISTENT) two_step = two_step_possible(*this) && sweep2_variant_ok(s, plan.tile[0], plan.tile[1]);
+    if (cfg.exec == OD_PERSISTENT)
+        two_step = two_step_possible(*this) && sweep2_variant_ok(s, plan.tile[0], plan.tile[1]) &&
+                   base_tiles.size() <= tile2_cap;
     const int cap = persistent_max_grid(s, plan.tile[0], plan.tile[1], coop_kind(), persist_waves);
     int grid = std::min<int>(cap, (int)base_tiles.size());
     if (grid >= kNumXcd) grid -= grid % kNumXcd;

@@ -87,6 +87,7 @@ struct Grid {
     std::vector<MsgBufs> msg;
     int32_t nres = 1;
     size_t tile_cap = 0;             // tile descriptors the workspace has room for
+    size_t tile2_cap = 0;            // two-step line descriptors it has room for
 
     // device state
     hipStream_t st = nullptr;
