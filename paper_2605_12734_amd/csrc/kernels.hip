@@ -932,11 +932,15 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
     persist_cleanup(bar);
 }
 
-// Persistent form of the two-step pass (uniform work: regular blocks, no
-// imbalance): `passes` passes of two steps each in one cooperative launch,
-// workgroup w sweeping tiles w, w + G, ... of its XCD group, the same
-// per-XCD barrier between passes as k_persistent.
-template <typename T, int TX, int TY>
+// Persistent form of the two-step pass (uniform work: blocks at one
+// resolution, no imbalance): `passes` passes of two steps each in one
+// cooperative launch, the same per-XCD barrier between passes as
+// k_persistent.  Workgroup w sweeps tiles w, w + G, ... of its XCD group,
+// or with DYN takes them one at a time from the group's counter (as
+// k_persistent: the tiles in flight then stay a contiguous run of the
+// group's spatial order, so neighbours share their halo lines in L2 even
+// when workgroups drift apart).
+template <typename T, int TX, int TY, bool DYN>
 __global__ void __launch_bounds__((TX / V16<T>::N) * TY) __attribute__((amdgpu_waves_per_eu(6, 8)))
 k_persistent2(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDev* __restrict__ tiles,
               const Tile2Dev* __restrict__ tiles2, int32_t ntiles, int parity, int64_t passes,
@@ -945,6 +949,7 @@ k_persistent2(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const 
     using S = SW2<T, TX, TY>;
     __shared__ __align__(16) T lds[S::LDS];
     __shared__ T red[S::NT / 64];
+    __shared__ int32_t s_idx;
     const int ng = (gridDim.x >= 8 && gridDim.x % 8 == 0) ? 8 : 1;
     const int xg = (int)(blockIdx.x % ng);
     const int32_t first = (int32_t)(blockIdx.x / ng), step_w = (int32_t)(gridDim.x / ng);
@@ -957,9 +962,19 @@ k_persistent2(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const 
             for (int s = (int)threadIdx.x; s < nres; s += S::NT) res[2 * s + p] = 0ull;
         T r = 0;
         int slot = -1;
-        for (int32_t idx = first;; idx += step_w) {
+        unsigned int* ctr = tile_ctr(bar, (int)(it & 1), xg);
+        if (DYN) {
+            if (threadIdx.x == 0)
+                s_idx = (int32_t)__hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __syncthreads();
+        }
+        int32_t idx = DYN ? __builtin_amdgcn_readfirstlane(s_idx) : first;
+        for (;;) {
             const int32_t ti = xg + ng * idx;
             if (ti >= ntiles) break;
+            int32_t nxt = idx + step_w;
+            if (DYN && threadIdx.x == 0)
+                nxt = (int32_t)__hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const TileDev& t = tiles[ti];
             const T rr = t.nz > 0 ? sweep2_tile<T, TX, TY>(arena, blocks, t, tiles2[ti], p, lds, hints) : (T)0;
             if (slot >= 0 && slot != t.rslot) {
@@ -968,6 +983,13 @@ k_persistent2(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const 
             }
             slot = t.rslot;
             r = rr > r ? rr : r;
+            if (DYN) {
+                __syncthreads();
+                if (threadIdx.x == 0) s_idx = nxt;
+                __syncthreads();
+                nxt = __builtin_amdgcn_readfirstlane(s_idx);
+            }
+            idx = nxt;
         }
         if (slot >= 0) wg_residual<T, S::NT>(r, &res[2 * slot + (p ^ 1)], red);
         if (it + 1 < passes) {
@@ -1812,7 +1834,7 @@ static std::string kernel_name(const char* base, int dtype_bytes, int tx, int ty
 
 static std::string coop_name(int dtype_bytes, int tx, int ty, int kind) {
     return kind == 1   ? kernel_name("k_msgdriven", dtype_bytes, tx, ty, nullptr)
-           : kind == 3 ? kernel_name("k_persistent2", dtype_bytes, tx, ty, nullptr)
+           : kind >= 3 ? kernel_name("k_persistent2", dtype_bytes, tx, ty, kind == 4 ? ", true" : ", false")
                        : kernel_name("k_persistent", dtype_bytes, tx, ty, kind == 2 ? ", true" : ", false");
 }
 
@@ -1830,12 +1852,15 @@ int persistent_max_grid(int dtype_bytes, int tx, int ty, int kind, int max_waves
     // faster at 5 waves per SIMD than at 6
     if (max_waves <= 0) max_waves = kind == 2 ? 5 : 8;
     const std::string name = coop_name(dtype_bytes, tx, ty, kind);
-    if (kind == 3) {
+    if (kind >= 3) {
 #define OD_OCC2(T, TX, TY)                                                                            \
         if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                  \
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent2<T, TX, TY>,          \
-                                                             SW2<T, TX, TY>::NT, 0) != hipSuccess)    \
-                return 0;                                                                             \
+            const hipError_t e = kind == 4                                                            \
+                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent2<T, TX, TY, true>,  \
+                                                               SW2<T, TX, TY>::NT, 0)                 \
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent2<T, TX, TY, false>, \
+                                                               SW2<T, TX, TY>::NT, 0);                \
+            if (e != hipSuccess) return 0;                                                            \
             return coop_per_cu(per, SW2<T, TX, TY>::NT, name.c_str(), max_waves) * ncu;              \
         }
         OD_VARIANTS2_F64(OD_OCC2)
@@ -1887,15 +1912,16 @@ hipError_t launch_persistent(int dtype_bytes, int tx, int ty, hipStream_t st, in
 hipError_t launch_persistent2(int dtype_bytes, int tx, int ty, hipStream_t st, int grid, void* arena,
                               const BlockDev* blocks, const TileDev* tiles, const Tile2Dev* tiles2, int32_t ntiles,
                               int parity, int64_t passes, unsigned long long* res, int32_t nres, unsigned int* bar,
-                              unsigned int* err, int hints, int64_t wait_ticks) {
+                              unsigned int* err, int hints, int64_t wait_ticks, int dyn) {
     if (passes <= 0) return hipSuccess;
 #define OD_LAUNCH2(T, TX, TY)                                                                         \
     if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                      \
         T* ar = reinterpret_cast<T*>(arena);                                                          \
         void* args[] = {&ar, &blocks, &tiles, &tiles2, &ntiles, &parity, &passes, &res, &nres, &bar,  \
                         &err, &wait_ticks, &hints};                                                   \
-        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_persistent2<T, TX, TY>),    \
-                                          dim3(grid), dim3(SW2<T, TX, TY>::NT), args, 0, st);         \
+        const void* fn = dyn ? reinterpret_cast<const void*>(k_persistent2<T, TX, TY, true>)          \
+                             : reinterpret_cast<const void*>(k_persistent2<T, TX, TY, false>);        \
+        return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(SW2<T, TX, TY>::NT), args, 0, st);     \
     }
     OD_VARIANTS2_F64(OD_LAUNCH2)
     OD_VARIANTS2_F32(OD_LAUNCH2)

@@ -139,12 +139,13 @@ hipError_t launch_sweep2(int dtype_bytes, int tx, int ty, hipStream_t st, void* 
                          unsigned long long* res, int32_t zero_lo, int32_t zero_hi, int hints);
 
 // Persistent form of the two-step pass: `passes` passes (2 * passes steps)
-// in one cooperative launch of `grid` workgroups, fixed stride, the
-// per-XCD barrier between passes; bar / err as launch_persistent.
+// in one cooperative launch of `grid` workgroups, the per-XCD barrier
+// between passes; dyn != 0: tiles from per-XCD-group counters, else the
+// fixed stride; bar / err as launch_persistent.
 hipError_t launch_persistent2(int dtype_bytes, int tx, int ty, hipStream_t st, int grid, void* arena,
                               const BlockDev* blocks, const TileDev* tiles, const Tile2Dev* tiles2, int32_t ntiles,
                               int parity, int64_t passes, unsigned long long* res, int32_t nres, unsigned int* bar,
-                              unsigned int* err, int hints, int64_t wait_ticks);
+                              unsigned int* err, int hints, int64_t wait_ticks, int dyn);
 
 // Persistent cooperative sweep: all `iters` iterations in one launch with a
 // device-wide barrier between them.  dyn != 0: workgroups take tiles from
@@ -190,8 +191,8 @@ inline int waves_by_sgprs(int sgprs) {
 int64_t device_wait_ticks(double seconds = 10.0);
 // Max co-resident workgroups of a cooperative kernel: kind 0 = persistent
 // with the static tile stride, 2 = persistent with tile counters (dyn),
-// 1 = message-driven, 3 = persistent two-step passes; at most max_waves
-// waves per SIMD (0 = the default
+// 1 = message-driven, 3 / 4 = persistent two-step passes with the static
+// stride / with counters; at most max_waves waves per SIMD (0 = the default
 // choice: 5 for kind 2, else as many as the registers allow).
 int persistent_max_grid(int dtype_bytes, int tx, int ty, int kind, int max_waves = 0);
 // Waves per SIMD the kernel's recorded scalar registers allow.

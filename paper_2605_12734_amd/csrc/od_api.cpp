@@ -167,13 +167,14 @@ namespace {
 // line of cells around a tile in one block: so in a regular decomposition;
 // explicit blocks have their tiles split until it holds), the 3D stencil,
 // no imbalance (a re-run chare would have to repeat both steps), and a tile
-// shape with a two-step variant; the persistent form also its fixed-stride
-// schedule and no timeline.
+// shape with a two-step variant; the persistent form also the fixed-stride
+// or counter schedule and no timeline.
 bool two_step_possible(const Grid& G) {
     const od_config& cfg = G.cfg;
     const Plan& p = G.plan;
     const bool form = cfg.exec == OD_FUSED || cfg.exec == OD_GRAPH ||
-                      (cfg.exec == OD_PERSISTENT && G.sched() == 1 && !(cfg.hints & kHintTimeline));
+                      (cfg.exec == OD_PERSISTENT && (G.sched() == 1 || G.sched() == 2) &&
+                       !(cfg.hints & kHintTimeline));
     return form && !(cfg.hints & 4096) && !p.multires && cfg.stencil != 5 && G.imb.heavy == 0;
 }
 
@@ -183,7 +184,7 @@ bool two_step_room(const Grid& G) {
     const od_config& cfg = G.cfg;
     const Plan& p = G.plan;
     const bool form = cfg.exec == OD_FUSED || cfg.exec == OD_GRAPH ||
-                      (cfg.exec == OD_PERSISTENT && !(cfg.hints & (kHintTimeline | 16 | 32 | 2048)));
+                      (cfg.exec == OD_PERSISTENT && !(cfg.hints & (kHintTimeline | 32 | 2048)));
     const bool imbalance = cfg.imbalance_pct > 0 && cfg.imbalance_max_extra > 0;
     return form && !(cfg.hints & 4096) && !p.multires && cfg.stencil != 5 && !imbalance;
 }
@@ -1007,7 +1008,8 @@ od_status Grid::persistent_run(int64_t n) {
                                           reinterpret_cast<const Tile2Dev*>(cp(L.tiles2)), (int32_t)tiles_h.size(),
                                           parity, passes, res_ptr(), 1, reinterpret_cast<unsigned int*>(cp(L.bar)),
                                           reinterpret_cast<unsigned int*>(cp(L.err)), mode(),
-                                          device_wait_ticks(cfg.wait_s > 0 ? cfg.wait_s : 10.0));
+                                          device_wait_ticks(cfg.wait_s > 0 ? cfg.wait_s : 10.0),
+                                          persistent_dyn() ? 1 : 0);
         if (e != hipSuccess) return fail(OD_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
         parity ^= (int)(passes & 1);
         iters += 2 * passes;

@@ -101,6 +101,15 @@ def test_persistent_pairs(dtype, iters):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("iters", [2, 7])
+def test_persistent_pairs_counters(dtype, iters):
+    # hints bit 4: tiles taken from per-XCD counters, pass by pass
+    plan = _case((150, 90, 70), 27, dtype, iters, exec_="persistent", tile=(32, 16, 16), bc=BC6, seed=9,
+                 hints=1 | 16)
+    assert plan["steps_per_pass"] == 2 and plan["schedule"] == 2
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_persistent_pairs_ragged(dtype):
     plan = _case((150, 90, 70), 27, dtype, 9, exec_="persistent", tile=(32, 16, 16), bc=BC6, seed=7)
     assert plan["steps_per_pass"] == 2
@@ -125,7 +134,7 @@ def test_not_used_where_unsupported():
     # imbalance, a forced persistent schedule and the message-driven and
     # per-chare forms keep one step per pass
     for kw in ({"exec": "fused", "imbalance_pct": 10, "imbalance_max_extra": 2},
-               {"exec": "persistent", "hints": 16}, {"exec": "msgdriven"}, {"exec": "per_chare"}):
+               {"exec": "persistent", "hints": 32}, {"exec": "msgdriven"}, {"exec": "per_chare"}):
         g = od.Grid(64, odf=8, dtype="f64", **kw)
         try:
             assert g.plan()["steps_per_pass"] == 1
