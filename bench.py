@@ -340,9 +340,12 @@ def jacobi2d_leg(n=32768, iters=100, odfs=(1, 4, 16, 64, 256, 1024)):
             glups = plan["interior"] * it * steps / tm["wall_s"] / 1e9
             row[exec_ + "_glups"] = round(glups, 2)
             if exec_ == "graph":
-                gbps = plan["bytes_per_iter"] * it * steps / tm["dev_s"] / 1e9
+                gbps = pass_gbps(plan, tm["dev_s"] / (it * steps))
+                row["graph_steps_per_pass"] = plan["steps_per_pass"]
                 row["graph_hbm_gbps"] = round(gbps, 1)
                 row["graph_frac"] = round(gbps / PEAK_HBM_GBPS, 4)
+                row["graph_step_bytes_frac"] = round(
+                    plan["bytes_per_iter"] * it * steps / tm["dev_s"] / 1e9 / PEAK_HBM_GBPS, 4)
                 row["graph_ms_per_100_iters"] = round(tm["wall_s"] / (it * steps) * 100 * 1e3, 2)
         row["speedup_batched_vs_per_chare"] = round(row["graph_glups"] / row["per_chare_glups"], 1)
         log("jacobi2d:", row)

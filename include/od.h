@@ -139,9 +139,9 @@ typedef struct {
      * XCD group's tiles per workgroup;
      * bit 12 (OD_FUSED, OD_GRAPH, OD_PERSISTENT): one step per pass.  By
      * default these forms run iterations in pairs where they can (blocks
-     * at one resolution, 3D stencil, no imbalance, a tile shape with a
-     * two-step variant; OD_PERSISTENT with the fixed-stride or counter
-     * schedule and no timeline): one pass reads the field once and writes it two steps
+     * at one resolution, no imbalance, a tile shape with a two-step
+     * variant; OD_PERSISTENT with the 3D stencil, the fixed-stride or
+     * counter schedule and no timeline): one pass reads the field once and writes it two steps
      * later, the first step kept on chip (the same values as two single
      * sweeps, bit for bit); od_iterate(n) with odd n ends with a single
      * sweep.  With explicit blocks the tiles are also cut so that every

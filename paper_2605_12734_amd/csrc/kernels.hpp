@@ -130,10 +130,12 @@ struct Tile2Dev {
     int32_t dir, pad_[3];
 };
 static_assert(sizeof(Tile2Dev) == 304, "Tile2Dev layout");
-// Two-step variants compiled for a dtype (tile x extent >= 2 vectors, y >= 2).
-bool sweep2_variant_ok(int dtype_bytes, int tx, int ty);
+// Two-step variants compiled for a dtype: 3D tiles (x extent >= 2 vectors,
+// y >= 2), or with `flat` the 2D 5-point stencil's row tiles (ty == 1).
+bool sweep2_variant_ok(int dtype_bytes, int tx, int ty, bool flat = false);
 // Reads parity `parity`, writes the field two steps later into parity^1;
 // the residual (of the second step) and res zeroing as launch_sweep.
+// hints bit 8 (the 2D stencil) selects the row kernel.
 hipError_t launch_sweep2(int dtype_bytes, int tx, int ty, hipStream_t st, void* arena, const BlockDev* blocks,
                          const TileDev* tiles, const Tile2Dev* tiles2, int32_t ntiles, int parity,
                          unsigned long long* res, int32_t zero_lo, int32_t zero_hi, int hints);

@@ -165,17 +165,18 @@ namespace {
 
 // Pairs of iterations in one pass need blocks at one resolution (every
 // line of cells around a tile in one block: so in a regular decomposition;
-// explicit blocks have their tiles split until it holds), the 3D stencil,
-// no imbalance (a re-run chare would have to repeat both steps), and a tile
-// shape with a two-step variant; the persistent form also the fixed-stride
-// or counter schedule and no timeline.
+// explicit blocks have their tiles split until it holds), no imbalance (a
+// re-run chare would have to repeat both steps), and a tile shape with a
+// two-step variant (3D tiles, or the 2D stencil's row tiles);
+// the persistent form also the 3D stencil, the fixed-stride or counter
+// schedule and no timeline.
 bool two_step_possible(const Grid& G) {
     const od_config& cfg = G.cfg;
     const Plan& p = G.plan;
     const bool form = cfg.exec == OD_FUSED || cfg.exec == OD_GRAPH ||
-                      (cfg.exec == OD_PERSISTENT && (G.sched() == 1 || G.sched() == 2) &&
+                      (cfg.exec == OD_PERSISTENT && cfg.stencil != 5 && (G.sched() == 1 || G.sched() == 2) &&
                        !(cfg.hints & kHintTimeline));
-    return form && !(cfg.hints & 4096) && !p.multires && cfg.stencil != 5 && G.imb.heavy == 0;
+    return form && !(cfg.hints & 4096) && !p.multires && G.imb.heavy == 0;
 }
 
 // Room for two-step descriptors: the forms that can pair steps under any
@@ -184,9 +185,9 @@ bool two_step_room(const Grid& G) {
     const od_config& cfg = G.cfg;
     const Plan& p = G.plan;
     const bool form = cfg.exec == OD_FUSED || cfg.exec == OD_GRAPH ||
-                      (cfg.exec == OD_PERSISTENT && !(cfg.hints & (kHintTimeline | 32 | 2048)));
+                      (cfg.exec == OD_PERSISTENT && cfg.stencil != 5 && !(cfg.hints & (kHintTimeline | 32 | 2048)));
     const bool imbalance = cfg.imbalance_pct > 0 && cfg.imbalance_max_extra > 0;
-    return form && !(cfg.hints & 4096) && !p.multires && cfg.stencil != 5 && !imbalance;
+    return form && !(cfg.hints & 4096) && !p.multires && !imbalance;
 }
 
 // Block and local coordinates of global cell (x, y, z) as a FaceDev: its
@@ -218,6 +219,7 @@ FaceDev cell_src(const Grid& G, int64_t x, int64_t y, int64_t z, const FaceDev& 
     out.src = c;
     if (outs == 1) {
         out.src = G.dir_pb[(size_t)c * 6 + f];
+        if (out.src < 0) return other;   // a face without a boundary buffer (the 2D grid's y faces): never read
         l[f / 2] = 0;
     }
     out.sx = l[0];
@@ -344,7 +346,7 @@ std::string fill_tile_descs(Grid& G) {
 // line descriptors follow the tile list.
 void decide_two_step(Grid& G) {
     const Plan& p = G.plan;
-    G.two_step = two_step_possible(G) && sweep2_variant_ok(G.s, p.tile[0], p.tile[1]) &&
+    G.two_step = two_step_possible(G) && sweep2_variant_ok(G.s, p.tile[0], p.tile[1], G.cfg.stencil == 5) &&
                  p.tiles.size() <= G.tile2_cap;
     G.tiles2_h.clear();
     if (G.two_step) {
