@@ -102,14 +102,14 @@ def make_grid(n, odf=None, blocks=None, dtype="f64", exec_="graph", tile=None, h
 
     if autotune and tile is None and exec_ in ("graph", "fused", "persistent"):
         g = od.Grid(n, odf=odf or 1, blocks=blocks, dtype=dtype, exec=exec_, hints=hints, **kw)
-        g.autotune(2)
+        g.autotune(TUNE_ITERS)
         return g
     if autotune and tile is None and exec_ in ("msgdriven", "per_chare"):
         # these modes take the shape tuned on a fused grid of the same
         # decomposition; message-driven tasks are tiles, so their z extent
         # is capped at 32 (deep tiles leave too few tasks to overlap)
         t = od.Grid(n, odf=odf or 1, blocks=blocks, dtype=dtype, exec="fused", hints=hints)
-        tile = msg_tile(t.autotune(2)) if exec_ == "msgdriven" else t.autotune(2)
+        tile = msg_tile(t.autotune(TUNE_ITERS)) if exec_ == "msgdriven" else t.autotune(TUNE_ITERS)
         t.close()
     return od.Grid(n, odf=odf or 1, blocks=blocks, dtype=dtype, exec=exec_, tile=tile, hints=hints, **kw)
 
@@ -133,6 +133,11 @@ def timed(g, iters, steps, warmup):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     return {"wall_s": t1 - t0, "dev_s": ev0.elapsed_time(ev1) * 1e-3, "residual": r}
+
+
+# passes timed per autotune candidate (2 measured within a few percent of
+# noise; 6 separates candidates that close)
+TUNE_ITERS = 6
 
 
 def pass_gbps(plan, launch_s):
@@ -326,7 +331,7 @@ def jacobi2d_leg(n=32768, iters=100, odfs=(1, 4, 16, 64, 256, 1024)):
     for odf in odfs:
         t = od.Grid2D(n, odf=odf, dtype="f64", exec="fused", hints=1)
         try:
-            tile = t.autotune(2)
+            tile = t.autotune(TUNE_ITERS)
         finally:
             t.close()
         row = {"n": n, "odf": odf, "tile": list(tile)}
