@@ -668,207 +668,6 @@ k_sweep2(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileD
     wg_residual<T, S::NT>(r, &res[2 * t.rslot + (parity ^ 1)], red);
 }
 
-// Two steps per pass of the 2D 5-point stencil (Jacobi2D on the (x, z)
-// plane, y extent 1): the same scheme as sweep2_tile on rows instead of
-// planes.  The ring around a tile is one cell on each side along x (and
-// the rows just below and above it), so four lanes hold the ring: lanes 0
-// and 1 the cells one out (x = -1, nx) with their three-row columns, lanes
-// 2 and 3 the cells two out (x = -2, nx + 1).
-template <typename T, int TX>
-struct SW2D {
-    static constexpr int VX = V16<T>::N;
-    static constexpr int LX = TX / VX;
-    static constexpr int NT = LX;
-    static constexpr int LP = TX + 2 * VX;   // column VX + x holds x in [-2, TX + 1]
-    static constexpr int LDS = 4 * LP;       // time-t rows and first-step rows, double buffered
-    static_assert(TX % VX == 0 && VX >= 2 && LX >= 4, "four ring lanes");
-    static_assert(NT % 64 == 0 && NT <= 1024, "threads must be whole waves");
-};
-
-template <typename T, int TX>
-__device__ __forceinline__ T sweep2d_tile(T* __restrict__ arena, const BlockDev* __restrict__ blocks,
-                                          const TileDev& t, const Tile2Dev& t2, const int parity,
-                                          T* __restrict__ lds, const int hints) {
-    using S = SW2D<T, TX>;
-    using VT = typename V16<T>::t;
-    constexpr int VX = S::VX, LP = S::LP;
-    constexpr int64_t ES = (int64_t)sizeof(T);
-    const int lx = threadIdx.x, x = lx * VX;
-    const int nx = t.nx, nz = t.nz;
-    int nv = nx - x;
-    nv = nv < 0 ? 0 : (nv > VX ? VX : nv);
-    const bool act = nv > 0;
-    const int xc = x < nx ? x : ((nx - 1) / VX) * VX;
-    const int dir = t2.dir;
-    const char* __restrict__ ab = reinterpret_cast<const char*>(arena);
-
-    const BlockDev* __restrict__ B = blocks + t.blk;
-    const int64_t own_pz = B->pz;
-    const int64_t tile_el = t.x0 + (int64_t)t.y0 * B->py + (int64_t)t.z0 * own_pz;
-    const char* own_b = ab + ((parity ? B->off[1] : B->off[0]) + tile_el) * ES;
-    char* dst_b = reinterpret_cast<char*>(arena) + ((parity ? B->off[0] : B->off[1]) + tile_el) * ES;
-    const uint32_t o_own = (uint32_t)(xc * ES);
-    auto at = [&](const FaceDev& f, int64_t* pz) -> const char* {
-        const BlockDev* __restrict__ F = blocks + f.src;
-        *pz = F->pz;
-        return ab + ((parity ? F->off[1] : F->off[0]) + f.sx + (int64_t)f.sy * F->py + (int64_t)f.sz * F->pz) * ES;
-    };
-    int64_t pz;
-    const char* zm_b = at(t.f[4], &pz);
-    const char* zp_b = at(t.f[5], &pz);
-    const char* zm2_b = at(t2.r2[4], &pz);
-    const char* zp2_b = at(t2.r2[5], &pz);
-
-    // ring lanes: 0 / 1 the cell one out on the x- / x+ side, 2 / 3 the cell two out
-    const int side = lx & 1;
-    const bool r1 = lx < 2, r2 = lx >= 2 && lx < 4;
-    const int r1c = side ? VX + nx : VX - 1, r2c = side ? VX + nx + 1 : VX - 2;
-    int64_t r1_pz = own_pz * ES, r2_pz = own_pz * ES;
-    const char* r1_b = own_b;
-    const char* r1_lo = own_b;
-    const char* r1_hi = own_b;
-    const char* r2_b = own_b;
-    if (r1) {
-        r1_b = at(t.f[side], &pz);
-        r1_pz = pz * ES;
-        r1_lo = at(t2.e[4 + side], &pz);
-        r1_hi = at(t2.e[6 + side], &pz);
-    } else if (r2) {
-        r2_b = at(t2.r2[side], &pz);
-        r2_pz = pz * ES;
-    }
-    const bool r1dir = r1 && ((dir >> side) & 1);
-
-    auto ldv = [](const char* p) -> VT { return *reinterpret_cast<const VT*>(p); };
-    auto lds1 = [](const char* p) -> T { return *reinterpret_cast<const T*>(p); };
-    auto tpl = [&](int q) -> VT {   // row q in [-2, nz + 1] (uniform)
-        if (q >= 0 && q < nz) return ldv(own_b + q * own_pz * ES + o_own);
-        if (q == -1) return ldv(zm_b + o_own);
-        if (q == -2) return ldv(zm2_b + o_own);
-        if (q == nz) return ldv(zp_b + o_own);
-        return ldv(zp2_b + o_own);
-    };
-    auto rl1 = [&](int q) -> T { return lds1(q < 0 ? r1_lo : (q >= nz ? r1_hi : r1_b + q * r1_pz)); };
-    auto lim = [&](int q) { return q < 0 ? 0 : (q > nz - 1 ? nz - 1 : q); };
-    auto tl = [&](int b, int c) -> T& { return lds[b * LP + c]; };
-    auto ul = [&](int b, int c) -> T& { return lds[(2 + b) * LP + c]; };
-    auto vref = [](T& e) -> VT& { return *reinterpret_cast<VT*>(&e); };
-
-    constexpr int PF = OD_PREFETCH;
-    VT tz[PF + 3];   // rows j-1 .. j+PF+1 of the lane's cells
-#pragma unroll
-    for (int k = 0; k < PF + 2; ++k) tz[k] = tpl(-2 + k <= nz + 1 ? -2 + k : nz + 1);
-    T rc[4];         // ring cell one out: rows j-1 .. j+2
-    rc[0] = rl1(-1);
-    rc[1] = rl1(-1);
-    rc[2] = rl1(0);
-    T c2 = lds1(r2_b);   // ring cell two out, row j
-    VT um1, um2;
-    T r = 0;
-
-    for (int j = -1; j <= nz; ++j) {
-        const int b = j & 1;
-        const bool inz = j >= 0 && j < nz;
-        tz[PF + 2] = tpl(j + PF + 1 <= nz + 1 ? j + PF + 1 : nz + 1);
-        rc[3] = rl1(j + 2 > nz ? nz : j + 2);
-        const T c2n = lds1(r2_b + lim(j + 1) * r2_pz);
-
-        // stage time-t row j
-        if (nv == VX) {
-            vref(tl(b, VX + x)) = tz[1];
-        } else if (act) {
-#pragma unroll
-            for (int i = 0; i < VX; ++i)
-                if (i < nv) tl(b, VX + x + i) = tz[1][i];
-        }
-        if (r1) tl(b, r1c) = rc[1];
-        if (r2 && inz) tl(b, r2c) = c2;
-        __syncthreads();
-
-        // first step of row j (Dirichlet z row: its value)
-        const bool zfix = (j < 0 && (dir & 16)) || (j >= nz && (dir & 32));
-        VT u;
-#pragma unroll
-        for (int i = 0; i < VX; ++i) {
-            const T xm = i > 0 ? tz[1][i - 1] : tl(b, VX + x - 1);
-            const T xp = (i < VX - 1 && i + 1 < nv) ? tz[1][i + 1] : tl(b, VX + x + i + 1);
-            T s = xm;
-            s = s + xp;
-            s = s + tz[0][i];
-            s = s + tz[2][i];
-            u[i] = zfix ? tz[1][i] : s / (T)4;
-        }
-        if (nv == VX) {
-            vref(ul(b, VX + x)) = u;
-        } else if (act) {
-#pragma unroll
-            for (int i = 0; i < VX; ++i)
-                if (i < nv) ul(b, VX + x + i) = u[i];
-        }
-        // first step of the ring cell one out (Dirichlet face: its value)
-        if (inz && r1) {
-            T s = tl(b, r1c - 1);
-            s = s + tl(b, r1c + 1);
-            s = s + rc[0];
-            s = s + rc[2];
-            ul(b, r1c) = r1dir ? rc[1] : s / (T)4;
-        }
-
-        // second step of row j - 1
-        if (j >= 1) {
-            const int c = b ^ 1;
-            VT out;
-#pragma unroll
-            for (int i = 0; i < VX; ++i) {
-                const T xm = i > 0 ? um1[i - 1] : ul(c, VX + x - 1);
-                const T xp = (i < VX - 1 && i + 1 < nv) ? um1[i + 1] : ul(c, VX + x + i + 1);
-                T s = xm;
-                s = s + xp;
-                s = s + um2[i];
-                s = s + u[i];
-                const T v = s / (T)4;
-                out[i] = v;
-                if (i < nv) {
-                    T d = v - um1[i];
-                    if (d < (T)0) d = -d;
-                    if (d > r) r = d;
-                }
-            }
-            if (act) {
-                VT* o = reinterpret_cast<VT*>(dst_b + (int64_t)(j - 1) * own_pz * ES + o_own);
-                if (hints & 1)
-                    __builtin_nontemporal_store(out, o);
-                else
-                    *o = out;
-            }
-        }
-        um2 = um1;
-        um1 = u;
-#pragma unroll
-        for (int k = 0; k < PF + 2; ++k) tz[k] = tz[k + 1];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) rc[k] = rc[k + 1];
-        c2 = c2n;
-    }
-    __syncthreads();   // LDS rows are reused by the next tile
-    return r;
-}
-
-template <typename T, int TX>
-__global__ void __launch_bounds__(TX / V16<T>::N)
-k_sweep2d(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDev* __restrict__ tiles,
-          const Tile2Dev* __restrict__ tiles2, int parity, unsigned long long* __restrict__ res, int zero_lo,
-          int zero_hi, int hints) {
-    using S = SW2D<T, TX>;
-    __shared__ __align__(16) T lds[S::LDS];
-    __shared__ T red[S::NT / 64];
-    if (blockIdx.x == 0)
-        for (int s = zero_lo + (int)threadIdx.x; s < zero_hi; s += S::NT) res[2 * s + parity] = 0ull;
-    const TileDev& t = tiles[blockIdx.x];
-    const T r = sweep2d_tile<T, TX>(arena, blocks, t, tiles2[blockIdx.x], parity, lds, hints);
-    wg_residual<T, S::NT>(r, &res[2 * t.rslot + (parity ^ 1)], red);
-}
-
 // ---------------------------------------------------------------------------
 // Synchronisation between workgroups.  On gfx950 an agent-scope release
 // writes back the XCD's L2 and an agent-scope acquire invalidates caches, so
@@ -1916,6 +1715,208 @@ __global__ void __launch_bounds__((TX8 / 2) * TY8) OD_SCHED_OCC k_serve(MsgArgs 
                                                    reinterpret_cast<float*>(lds_raw), a.hints);
     };
     serve_loop<S8::NT>(a, sweep, red);
+}
+
+// ---------------------------------------------------------------------------
+// Two steps per pass of the 2D 5-point stencil (Jacobi2D on the (x, z)
+// plane, y extent 1): the same scheme as sweep2_tile on rows instead of
+// planes.  The ring around a tile is one cell on each side along x (and
+// the rows just below and above it), so four lanes hold the ring: lanes 0
+// and 1 the cells one out (x = -1, nx) with their three-row columns, lanes
+// 2 and 3 the cells two out (x = -2, nx + 1).
+template <typename T, int TX>
+struct SW2D {
+    static constexpr int VX = V16<T>::N;
+    static constexpr int LX = TX / VX;
+    static constexpr int NT = LX;
+    static constexpr int LP = TX + 2 * VX;   // column VX + x holds x in [-2, TX + 1]
+    static constexpr int LDS = 4 * LP;       // time-t rows and first-step rows, double buffered
+    static_assert(TX % VX == 0 && VX >= 2 && LX >= 4, "four ring lanes");
+    static_assert(NT % 64 == 0 && NT <= 1024, "threads must be whole waves");
+};
+
+template <typename T, int TX>
+__device__ __forceinline__ T sweep2d_tile(T* __restrict__ arena, const BlockDev* __restrict__ blocks,
+                                          const TileDev& t, const Tile2Dev& t2, const int parity,
+                                          T* __restrict__ lds, const int hints) {
+    using S = SW2D<T, TX>;
+    using VT = typename V16<T>::t;
+    constexpr int VX = S::VX, LP = S::LP;
+    constexpr int64_t ES = (int64_t)sizeof(T);
+    const int lx = threadIdx.x, x = lx * VX;
+    const int nx = t.nx, nz = t.nz;
+    int nv = nx - x;
+    nv = nv < 0 ? 0 : (nv > VX ? VX : nv);
+    const bool act = nv > 0;
+    const int xc = x < nx ? x : ((nx - 1) / VX) * VX;
+    const int dir = t2.dir;
+    const char* __restrict__ ab = reinterpret_cast<const char*>(arena);
+
+    const BlockDev* __restrict__ B = blocks + t.blk;
+    const int64_t own_pz = B->pz;
+    const int64_t tile_el = t.x0 + (int64_t)t.y0 * B->py + (int64_t)t.z0 * own_pz;
+    const char* own_b = ab + ((parity ? B->off[1] : B->off[0]) + tile_el) * ES;
+    char* dst_b = reinterpret_cast<char*>(arena) + ((parity ? B->off[0] : B->off[1]) + tile_el) * ES;
+    const uint32_t o_own = (uint32_t)(xc * ES);
+    auto at = [&](const FaceDev& f, int64_t* pz) -> const char* {
+        const BlockDev* __restrict__ F = blocks + f.src;
+        *pz = F->pz;
+        return ab + ((parity ? F->off[1] : F->off[0]) + f.sx + (int64_t)f.sy * F->py + (int64_t)f.sz * F->pz) * ES;
+    };
+    int64_t pz;
+    const char* zm_b = at(t.f[4], &pz);
+    const char* zp_b = at(t.f[5], &pz);
+    const char* zm2_b = at(t2.r2[4], &pz);
+    const char* zp2_b = at(t2.r2[5], &pz);
+
+    // ring lanes: 0 / 1 the cell one out on the x- / x+ side, 2 / 3 the cell two out
+    const int side = lx & 1;
+    const bool r1 = lx < 2, r2 = lx >= 2 && lx < 4;
+    const int r1c = side ? VX + nx : VX - 1, r2c = side ? VX + nx + 1 : VX - 2;
+    int64_t r1_pz = own_pz * ES, r2_pz = own_pz * ES;
+    const char* r1_b = own_b;
+    const char* r1_lo = own_b;
+    const char* r1_hi = own_b;
+    const char* r2_b = own_b;
+    if (r1) {
+        r1_b = at(t.f[side], &pz);
+        r1_pz = pz * ES;
+        r1_lo = at(t2.e[4 + side], &pz);
+        r1_hi = at(t2.e[6 + side], &pz);
+    } else if (r2) {
+        r2_b = at(t2.r2[side], &pz);
+        r2_pz = pz * ES;
+    }
+    const bool r1dir = r1 && ((dir >> side) & 1);
+
+    auto ldv = [](const char* p) -> VT { return *reinterpret_cast<const VT*>(p); };
+    auto lds1 = [](const char* p) -> T { return *reinterpret_cast<const T*>(p); };
+    auto tpl = [&](int q) -> VT {   // row q in [-2, nz + 1] (uniform)
+        if (q >= 0 && q < nz) return ldv(own_b + q * own_pz * ES + o_own);
+        if (q == -1) return ldv(zm_b + o_own);
+        if (q == -2) return ldv(zm2_b + o_own);
+        if (q == nz) return ldv(zp_b + o_own);
+        return ldv(zp2_b + o_own);
+    };
+    auto rl1 = [&](int q) -> T { return lds1(q < 0 ? r1_lo : (q >= nz ? r1_hi : r1_b + q * r1_pz)); };
+    auto lim = [&](int q) { return q < 0 ? 0 : (q > nz - 1 ? nz - 1 : q); };
+    auto tl = [&](int b, int c) -> T& { return lds[b * LP + c]; };
+    auto ul = [&](int b, int c) -> T& { return lds[(2 + b) * LP + c]; };
+    auto vref = [](T& e) -> VT& { return *reinterpret_cast<VT*>(&e); };
+
+    constexpr int PF = OD_PREFETCH;
+    VT tz[PF + 3];   // rows j-1 .. j+PF+1 of the lane's cells
+#pragma unroll
+    for (int k = 0; k < PF + 2; ++k) tz[k] = tpl(-2 + k <= nz + 1 ? -2 + k : nz + 1);
+    T rc[4];         // ring cell one out: rows j-1 .. j+2
+    rc[0] = rl1(-1);
+    rc[1] = rl1(-1);
+    rc[2] = rl1(0);
+    T c2 = lds1(r2_b);   // ring cell two out, row j
+    VT um1, um2;
+    T r = 0;
+
+    for (int j = -1; j <= nz; ++j) {
+        const int b = j & 1;
+        const bool inz = j >= 0 && j < nz;
+        tz[PF + 2] = tpl(j + PF + 1 <= nz + 1 ? j + PF + 1 : nz + 1);
+        rc[3] = rl1(j + 2 > nz ? nz : j + 2);
+        const T c2n = lds1(r2_b + lim(j + 1) * r2_pz);
+
+        // stage time-t row j
+        if (nv == VX) {
+            vref(tl(b, VX + x)) = tz[1];
+        } else if (act) {
+#pragma unroll
+            for (int i = 0; i < VX; ++i)
+                if (i < nv) tl(b, VX + x + i) = tz[1][i];
+        }
+        if (r1) tl(b, r1c) = rc[1];
+        if (r2 && inz) tl(b, r2c) = c2;
+        __syncthreads();
+
+        // first step of row j (Dirichlet z row: its value)
+        const bool zfix = (j < 0 && (dir & 16)) || (j >= nz && (dir & 32));
+        VT u;
+#pragma unroll
+        for (int i = 0; i < VX; ++i) {
+            const T xm = i > 0 ? tz[1][i - 1] : tl(b, VX + x - 1);
+            const T xp = (i < VX - 1 && i + 1 < nv) ? tz[1][i + 1] : tl(b, VX + x + i + 1);
+            T s = xm;
+            s = s + xp;
+            s = s + tz[0][i];
+            s = s + tz[2][i];
+            u[i] = zfix ? tz[1][i] : s / (T)4;
+        }
+        if (nv == VX) {
+            vref(ul(b, VX + x)) = u;
+        } else if (act) {
+#pragma unroll
+            for (int i = 0; i < VX; ++i)
+                if (i < nv) ul(b, VX + x + i) = u[i];
+        }
+        // first step of the ring cell one out (Dirichlet face: its value)
+        if (inz && r1) {
+            T s = tl(b, r1c - 1);
+            s = s + tl(b, r1c + 1);
+            s = s + rc[0];
+            s = s + rc[2];
+            ul(b, r1c) = r1dir ? rc[1] : s / (T)4;
+        }
+
+        // second step of row j - 1
+        if (j >= 1) {
+            const int c = b ^ 1;
+            VT out;
+#pragma unroll
+            for (int i = 0; i < VX; ++i) {
+                const T xm = i > 0 ? um1[i - 1] : ul(c, VX + x - 1);
+                const T xp = (i < VX - 1 && i + 1 < nv) ? um1[i + 1] : ul(c, VX + x + i + 1);
+                T s = xm;
+                s = s + xp;
+                s = s + um2[i];
+                s = s + u[i];
+                const T v = s / (T)4;
+                out[i] = v;
+                if (i < nv) {
+                    T d = v - um1[i];
+                    if (d < (T)0) d = -d;
+                    if (d > r) r = d;
+                }
+            }
+            if (act) {
+                VT* o = reinterpret_cast<VT*>(dst_b + (int64_t)(j - 1) * own_pz * ES + o_own);
+                if (hints & 1)
+                    __builtin_nontemporal_store(out, o);
+                else
+                    *o = out;
+            }
+        }
+        um2 = um1;
+        um1 = u;
+#pragma unroll
+        for (int k = 0; k < PF + 2; ++k) tz[k] = tz[k + 1];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) rc[k] = rc[k + 1];
+        c2 = c2n;
+    }
+    __syncthreads();   // LDS rows are reused by the next tile
+    return r;
+}
+
+template <typename T, int TX>
+__global__ void __launch_bounds__(TX / V16<T>::N)
+k_sweep2d(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDev* __restrict__ tiles,
+          const Tile2Dev* __restrict__ tiles2, int parity, unsigned long long* __restrict__ res, int zero_lo,
+          int zero_hi, int hints) {
+    using S = SW2D<T, TX>;
+    __shared__ __align__(16) T lds[S::LDS];
+    __shared__ T red[S::NT / 64];
+    if (blockIdx.x == 0)
+        for (int s = zero_lo + (int)threadIdx.x; s < zero_hi; s += S::NT) res[2 * s + parity] = 0ull;
+    const TileDev& t = tiles[blockIdx.x];
+    const T r = sweep2d_tile<T, TX>(arena, blocks, t, tiles2[blockIdx.x], parity, lds, hints);
+    wg_residual<T, S::NT>(r, &res[2 * t.rslot + (parity ^ 1)], red);
 }
 
 // ---------------------------------------------------------------------------
