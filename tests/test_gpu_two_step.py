@@ -174,3 +174,25 @@ def test_uneven_octree_pairs(dtype, exec_, tile):
         g.close()
     _same(U, want)
     assert r == r_w
+
+
+@pytest.mark.parametrize("exec_", ["graph", "persistent"])
+def test_1024_odf32768_pairs_sampled(exec_):
+    # full size: 1024^3 fp64 as 32768 chares of 32^3, 13 iterations (six
+    # pairs and a single step), points in chare interiors and on chare
+    # faces, edges and corners, where the pairs read diagonal neighbours
+    n = (1024, 1024, 1024)
+    iters = 13
+    rng = np.random.default_rng(21)
+    pts = [tuple(int(v) for v in rng.integers(0, 1024, 3)) for _ in range(24)]
+    for c in (31, 32, 63, 64, 511, 512, 991, 992):
+        pts += [(c, c, c), (c, c, 100), (c, 7, c), (300, c, c), (0, c, c), (c, 1023, 0)]
+    g = od.Grid(n, odf=32768, dtype="f64", exec=exec_, tile=(32, 32, 32), hints=1)
+    try:
+        assert g.plan()["steps_per_pass"] == 2
+        g.iterate(iters)
+        got = g.read_points(np.array([(k * n[1] + j) * n[0] + i for (i, j, k) in pts], dtype=np.int64))
+    finally:
+        g.close()
+    want = oracle.point_values(n, pts, iters, np.float64)
+    assert np.array_equal(got, want)
