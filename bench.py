@@ -541,7 +541,9 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBPS, 4),
             "traffic": load_traffic(workload) if args.exec in ("graph", "fused") else None,
-            "kernel": ("k_sweep2 (two fused 7-point steps per pass + halo reads)" if spp == 2
+            "kernel": (("k_persistent2 (every pass of two fused 7-point steps in one cooperative launch; "
+                        "time per pass)" if args.exec == "persistent"
+                        else "k_sweep2 (two fused 7-point steps per pass + halo reads)") if spp == 2
                        else KERNEL_OF_EXEC.get(args.exec, args.exec)),
             "steps_per_launch": spp,
             "alg_bytes_per_launch": plan["bytes_per_pass"],

@@ -126,8 +126,10 @@ typedef struct {
      * return OD_ESCHED).  Every message-driven task also checks, in any
      * mode, that its tile's step counter advances by exactly one;
      * bit 3 (OD_PERSISTENT): record the timeline read by od_timeline;
-     * bit 4 (OD_PERSISTENT): take tiles from per-XCD-group counters even
-     * for uniform work (default there: a fixed stride per workgroup);
+     * bit 4 (OD_PERSISTENT): take tiles from per-XCD-group counters, each
+     * workgroup its next tile when the current one ends (the default for
+     * two-step passes, under imbalance and with uneven blocks); uniform
+     * one-step work defaults to a fixed stride per workgroup;
      * bit 5 (OD_PERSISTENT): counters, with each XCD group's last tiles
      * cut into z-ranges so the end of an iteration waits less;
      * bits 6 / 7 (OD_MSGDRIVEN): claim ready tiles from each XCD's cursor /
@@ -137,6 +139,8 @@ typedef struct {
      * per workgroup and step);
      * bit 11 (OD_PERSISTENT): fixed schedule with contiguous runs of each
      * XCD group's tiles per workgroup;
+     * bit 13 (OD_PERSISTENT): the fixed stride per workgroup, also where
+     * counters are the default;
      * bit 12 (OD_FUSED, OD_GRAPH, OD_PERSISTENT): one step per pass.  By
      * default these forms run iterations in pairs where they can (blocks
      * at one resolution, no imbalance, a tile shape with a two-step

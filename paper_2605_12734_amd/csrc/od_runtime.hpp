@@ -59,24 +59,29 @@ struct Grid {
     int64_t halo2_cells = 0;         // cells of other chares within two steps of each chare
     std::vector<int32_t> dep_ptr, dep_idx;
     ImbDev imb{};                    // load-imbalance draw (heavy == 0: none)
-    // Persistent schedule: 0 = automatic (counters under imbalance or with
-    // uneven blocks that keep one step per pass, else the fixed stride),
-    // 1 = fixed stride, 2 = tiles
+    // Persistent schedule: 0 = automatic (counters for two-step passes,
+    // under imbalance and with uneven blocks that keep one step per pass;
+    // the fixed stride for other uniform one-step work), 1 = fixed
+    // stride, 2 = tiles
     // from per-XCD-group counters, 3 = counters with the last tiles of each
     // group cut into z-ranges (guided_tail), 4 = fixed contiguous runs per
-    // workgroup.  hints bits 4, 5 and 11 force 2, 3 and 4; the autotuner
-    // may choose.
+    // workgroup.  hints bits 4, 5, 11 and 13 force 2, 3, 4 and 1; the
+    // autotuner may choose.
     int persist_sched = 0;
     int persist_waves = 0;           // cooperative waves per SIMD cap (0 = default)
     int msg_sched = 0;               // message-driven scheduler choice (MsgArgs::sched)
     int sched() const {
         if (cfg.hints & 2048) return 4;
+        if (cfg.hints & 8192) return 1;
         if (cfg.hints & 32) return 3;
         if (cfg.hints & 16) return 2;
         if (persist_sched) return persist_sched;
-        // uneven blocks take tiles from counters, unless they run two steps
-        // per pass (the fixed stride then, the only two-step schedule)
-        return (imb.heavy > 0 || (!plan.regular && !plan.two_step_lines)) ? 2 : 1;
+        // counters, claimed as each tile ends, measured faster than the
+        // stride for two-step passes at every ODF (512^3 fp64: 278-287 vs
+        // 288-308 us per iteration) and under imbalance; the stride stays
+        // for uniform one-step work
+        if (imb.heavy > 0 || (!plan.regular && !plan.two_step_lines)) return 2;
+        return two_step ? 2 : 1;
     }
     bool persistent_dyn() const { return sched() == 2 || sched() == 3; }
     // cooperative-kernel kind for persistent_max_grid

@@ -95,9 +95,12 @@ def test_one_step_hint_and_pairs_identical_at_256(exec_):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("iters", [1, 2, 7, 12])
-def test_persistent_pairs(dtype, iters):
-    plan = _case(64, 8, dtype, iters, exec_="persistent")
-    assert plan["steps_per_pass"] == 2 and plan["schedule"] == 1
+@pytest.mark.parametrize("hints,sched", [(1, 2), (1 | 8192, 1)])
+def test_persistent_pairs(dtype, iters, hints, sched):
+    # default: tiles from per-XCD counters claimed as each tile ends;
+    # hints bit 13: the fixed stride
+    plan = _case(64, 8, dtype, iters, exec_="persistent", hints=hints)
+    assert plan["steps_per_pass"] == 2 and plan["schedule"] == sched
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
