@@ -131,7 +131,8 @@ typedef struct {
      * two-step passes, under imbalance and with uneven blocks); uniform
      * one-step work defaults to a fixed stride per workgroup;
      * bit 5 (OD_PERSISTENT): counters, with each XCD group's last tiles
-     * cut into z-ranges so the end of an iteration waits less;
+     * cut into z-ranges so the end of an iteration waits less (with two
+     * steps per pass only the group's partial last round of tiles);
      * bits 6 / 7 (OD_MSGDRIVEN): claim ready tiles from each XCD's cursor /
      * from ready queues (default: cursor with >= 4 tiles per workgroup);
      * bits 9 / 10 (OD_MSGDRIVEN): one publisher workgroup per XCD / none
@@ -145,7 +146,8 @@ typedef struct {
      * default these forms run iterations in pairs where they can (blocks
      * at one resolution, no imbalance, a tile shape with a two-step
      * variant; OD_PERSISTENT with the 3D stencil, the fixed-stride or
-     * counter schedule and no timeline): one pass reads the field once and writes it two steps
+     * counter schedule, with or without the guided tail, and no
+     * timeline): one pass reads the field once and writes it two steps
      * later, the first step kept on chip (the same values as two single
      * sweeps, bit for bit); od_iterate(n) with odd n ends with a single
      * sweep.  With explicit blocks the tiles are also cut so that every

@@ -169,12 +169,12 @@ namespace {
 // re-run chare would have to repeat both steps), and a tile shape with a
 // two-step variant (3D tiles, or the 2D stencil's row tiles);
 // the persistent form also the 3D stencil, the fixed-stride or counter
-// schedule and no timeline.
+// schedule (with or without the guided tail) and no timeline.
 bool two_step_possible(const Grid& G) {
     const od_config& cfg = G.cfg;
     const Plan& p = G.plan;
     const bool form = cfg.exec == OD_FUSED || cfg.exec == OD_GRAPH ||
-                      (cfg.exec == OD_PERSISTENT && cfg.stencil != 5 && (G.sched() == 1 || G.sched() == 2) &&
+                      (cfg.exec == OD_PERSISTENT && cfg.stencil != 5 && G.sched() >= 1 && G.sched() <= 3 &&
                        !(cfg.hints & kHintTimeline));
     return form && !(cfg.hints & 4096) && !p.multires && G.imb.heavy == 0;
 }
@@ -185,7 +185,7 @@ bool two_step_room(const Grid& G) {
     const od_config& cfg = G.cfg;
     const Plan& p = G.plan;
     const bool form = cfg.exec == OD_FUSED || cfg.exec == OD_GRAPH ||
-                      (cfg.exec == OD_PERSISTENT && cfg.stencil != 5 && !(cfg.hints & (kHintTimeline | 32 | 2048)));
+                      (cfg.exec == OD_PERSISTENT && cfg.stencil != 5 && !(cfg.hints & (kHintTimeline | 2048)));
     const bool imbalance = cfg.imbalance_pct > 0 && cfg.imbalance_max_extra > 0;
     return form && !(cfg.hints & 4096) && !p.multires && !imbalance;
 }
@@ -573,13 +573,14 @@ std::string build_layout(const od_config& cfg, Grid& G) {
     // workgroup plus padding (guided_tail); cooperative grids stay below 8192
     // two-step line descriptors: room for the planned tiles and for
     // autotune candidates down to (32, 8, 16) tiles (finer candidates run
-    // one step per pass); two-step lists are never cut by a guided tail
+    // one step per pass), plus the persistent guided tail's entries
     G.tile2_cap = 0;
     if (two_step_room(G)) {
         size_t cap2 = 0;
         for (const Chare& c : p.chares)
             cap2 += (size_t)ceil_div(c.e[0], 32) * (size_t)ceil_div(c.e[1], 8) * (size_t)ceil_div(c.e[2], 16);
         G.tile2_cap = std::min(G.tile_cap, std::max(ntiles, G.tune_room ? cap2 * (p.regular ? 1 : 2) : ntiles));
+        if (cfg.exec == OD_PERSISTENT) G.tile2_cap += 3 * 8192 + kNumXcd;
     }
     if (cfg.exec == OD_PERSISTENT) G.tile_cap += 3 * 8192 + kNumXcd;
     G.L.tiles = cv.take(G.tile_cap * sizeof(TileDev));
@@ -783,8 +784,18 @@ od_status Grid::setup_cooperative(bool fresh_plan) {
     grid_wgs = grid;
     if (grid <= 0) return fail(OD_EHIP, "no co-resident workgroups for the cooperative kernel");
     if (cfg.exec == OD_PERSISTENT) {
-        std::vector<TileHost> list = sched() == 3 ? guided_tail(plan, base_tiles, grid / kNumXcd, 4) : base_tiles;
-        if (list.size() > tile_cap) return fail(OD_EINVAL, "cut tile list exceeds the tile capacity");
+        std::vector<TileHost> list = base_tiles;
+        if (sched() == 3 && two_step) {
+            // uniform passes: only the partial last round of each XCD group
+            // is cut, into enough z-ranges to occupy the group's workgroups
+            const int32_t W = grid / kNumXcd, per = (int32_t)(base_tiles.size() / kNumXcd);
+            const int32_t rem = W > 0 ? per % W : 0;
+            if (rem > 0) list = guided_tail(plan, base_tiles, rem, std::min<int32_t>(4, (W + rem - 1) / rem));
+        } else if (sched() == 3) {
+            list = guided_tail(plan, base_tiles, grid / kNumXcd, 4);
+        }
+        if (list.size() > tile_cap || (two_step && list.size() > tile2_cap))
+            return fail(OD_EINVAL, "cut tile list exceeds the tile capacity");
         if (list.size() != plan.tiles.size() || !fresh_plan || two_step) {
             plan.tiles.swap(list);
             std::string e = fill_tile_descs(*this);   // also the two-step lines of the final list

@@ -118,6 +118,26 @@ def test_persistent_pairs_ragged(dtype):
     assert plan["steps_per_pass"] == 2
 
 
+@pytest.mark.parametrize("iters", [6, 7])
+def test_persistent_pairs_guided_tail(iters):
+    # hints bit 5 with two steps per pass: each XCD group's partial last
+    # round of tiles is cut into z-ranges (384^3 as 1728 chares of 32^3:
+    # 216 tiles per group on 96 workgroups, the last 24 cut into 4 pieces)
+    n = 384
+    want, _, r_w = oracle.solve(n, np.float64, seed=5, iters=iters, bc=od.DEFAULT_BC)
+    g = od.Grid(n, odf=1728, dtype="f64", exec="persistent", tile=(32, 32, 32), hints=1 | 32, seed=5)
+    try:
+        p = g.plan()
+        g.iterate(iters)
+        U, r = g.read(), g.residual()
+    finally:
+        g.close()
+    assert p["steps_per_pass"] == 2 and p["schedule"] == 3
+    assert p["ntiles"] > 1728
+    _same(U, want)
+    assert r == r_w
+
+
 def test_persistent_pairs_then_single_steps_resume():
     # a persistent grid run in pieces (pairs, then an odd step, then pairs)
     # ends on the oracle's bits
@@ -137,7 +157,7 @@ def test_not_used_where_unsupported():
     # imbalance, a forced persistent schedule and the message-driven and
     # per-chare forms keep one step per pass
     for kw in ({"exec": "fused", "imbalance_pct": 10, "imbalance_max_extra": 2},
-               {"exec": "persistent", "hints": 32}, {"exec": "msgdriven"}, {"exec": "per_chare"}):
+               {"exec": "persistent", "hints": 2048}, {"exec": "msgdriven"}, {"exec": "per_chare"}):
         g = od.Grid(64, odf=8, dtype="f64", **kw)
         try:
             assert g.plan()["steps_per_pass"] == 1

@@ -269,8 +269,7 @@ def test_two_step_pass_bytes_brute_force(n, odf, dtype):
     assert plan["bytes_per_iter"] == s * (2 * plan["interior"] + plan["halo_cells"])
 
 
-@pytest.mark.parametrize("kw", [{"exec": "persistent", "hints": 32},
-                                {"exec": "persistent", "hints": 2048}, {"exec": "persistent", "hints": 8},
+@pytest.mark.parametrize("kw", [{"exec": "persistent", "hints": 2048}, {"exec": "persistent", "hints": 8},
                                 {"exec": "msgdriven"}, {"exec": "per_chare"},
                                 {"exec": "fused", "hints": 4096},
                                 {"exec": "fused", "imbalance_pct": 10, "imbalance_max_extra": 2},
@@ -283,7 +282,8 @@ def test_two_step_only_where_supported(kw):
     assert plan["bytes_per_pass"] == plan["bytes_per_iter"]
 
 
-@pytest.mark.parametrize("exec_,hints", [("fused", 0), ("graph", 0), ("persistent", 0), ("persistent", 16)])
+@pytest.mark.parametrize("exec_,hints", [("fused", 0), ("graph", 0), ("persistent", 0), ("persistent", 16),
+                                         ("persistent", 32), ("persistent", 8192)])
 def test_two_step_default_forms(exec_, hints):
     plan = od.host_plan(n=(64, 64, 64), odf=8, dtype="f64", exec=exec_, hints=hints)
     assert plan["steps_per_pass"] == 2
