@@ -310,7 +310,8 @@ typedef struct {
     int64_t control_bytes;          /* rest of the workspace: descriptors and device
                                        state, for this handle's plan                 */
     int32_t steps_per_pass;         /* 2: iterations run in pairs (OD_FUSED, OD_GRAPH,
-                                       OD_PERSISTENT; hints bit 12); else 1           */
+                                       OD_PERSISTENT, OD_MSGDRIVEN; hints bit 12);
+                                       else 1                                          */
     int64_t bytes_per_pass;         /* algorithmic HBM bytes of one pass: one sweep, or
                                        with two steps per pass s * (2*interior + cells
                                        of other chares within two steps' reach)       */
@@ -330,6 +331,15 @@ typedef struct {
     int32_t src_kind[6], src[6], src_origin[6][3];
 } od_tile_info;
 od_status od_tile_info_get(struct od_grid* g, int32_t t, od_tile_info* out);
+
+/* Dependency list of tile t of an OD_MSGDRIVEN grid or plan (host data):
+ * the tiles whose cells tile t's task reads, which are also the tiles that
+ * read tile t's cells (the relation is symmetric): every other tile within
+ * one cell (tasks of one step) or two cells in L1 distance (two-step tasks,
+ * od_plan_info.steps_per_pass == 2) of the tile's box.  Up to cap indices
+ * are written to out (ascending); *count = the list's length.  OD_EINVAL for
+ * other exec modes or t out of range. */
+od_status od_tile_deps(struct od_grid* g, int32_t t, int32_t* out, int32_t cap, int32_t* count);
 
 /* Timeline of the last od_iterate of an OD_PERSISTENT grid created with
  * hints bit 3, for its first min(n, 1024, max_iters) iterations: out[4*i + k]

@@ -135,6 +135,18 @@ def tile_infos(handle, count: int) -> list:
     return out
 
 
+def tile_deps(handle, count: int) -> list:
+    """Message-driven dependency list of every tile (host data)."""
+    out = []
+    n = ctypes.c_int32()
+    for t in range(count):
+        check(lib().od_tile_deps(handle, t, None, 0, ctypes.byref(n)), "od_tile_deps")
+        buf = (ctypes.c_int32 * max(1, n.value))()
+        check(lib().od_tile_deps(handle, t, buf, n.value, ctypes.byref(n)), "od_tile_deps")
+        out.append(tuple(buf[:n.value]))
+    return out
+
+
 def chare_boxes(handle, count: int) -> list:
     out = []
     b = B.od_block()
@@ -170,6 +182,8 @@ def host_plan(**kw) -> dict:
         info = plan_info(p.h)
         info["tiles"] = tile_infos(p.h, info["ntiles"])
         info["chares"] = chare_boxes(p.h, info["nchares"])
+        if kw.get("exec") == "msgdriven":
+            info["deps"] = tile_deps(p.h, info["ntiles"])
         return info
     finally:
         p.close()

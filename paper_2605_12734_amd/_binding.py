@@ -92,6 +92,7 @@ SIGNATURES = {
     "od_read_points": (ctypes.c_int, [c_vp, c_vp, c_i64, c_vp]),
     "od_plan": (ctypes.c_int, [c_vp, ctypes.POINTER(od_plan_info)]),
     "od_tile_info_get": (ctypes.c_int, [c_vp, c_i32, ctypes.POINTER(od_tile_info)]),
+    "od_tile_deps": (ctypes.c_int, [c_vp, c_i32, ctypes.POINTER(c_i32), c_i32, ctypes.POINTER(c_i32)]),
     "od_chare_get": (ctypes.c_int, [c_vp, c_i32, ctypes.POINTER(od_block)]),
     "od_timeline": (ctypes.c_int, [c_vp, c_vp, c_i32, ctypes.POINTER(c_i32)]),
     "od_extra_sweeps": (ctypes.c_int, [c_vp, c_i64, c_vp, c_i32]),

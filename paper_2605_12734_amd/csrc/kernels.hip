@@ -1688,6 +1688,24 @@ __global__ void __launch_bounds__((TX / V16<T>::N) * TY) OD_MSG_OCC k_msgdriven(
     queue_loop<S::NT>(a, sweep, red);
 }
 
+// Message-driven tasks of two steps (grids at one resolution without
+// imbalance): the same scheduler, each task one two-step pass of its tile.
+// A scheduler step is a pass (the field's parity flips once per step), and
+// the dependency lists reach every tile within two cells (face slabs two
+// deep and the edge lines), so a tile still runs step k once everything it
+// reads has finished step k - 1 and nothing that reads it still needs k - 1.
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__((TX / V16<T>::N) * TY) OD_MSG_OCC k_msgdriven2(MsgArgs a) {
+    using S = SW2<T, TX, TY>;
+    __shared__ __align__(16) T lds[S::LDS];
+    __shared__ double red[S::NT / 64];
+    T* arena = reinterpret_cast<T*>(a.arena);
+    auto sweep = [&](int32_t gid, int32_t step) -> double {
+        return (double)sweep2_tile<T, TX, TY>(arena, a.blocks, a.tiles[gid], a.tiles2[gid], step & 1, lds, a.hints);
+    };
+    queue_loop<S::NT>(a, sweep, red);
+}
+
 // Serving: tiles of independent fp64 and fp32 solves in one launch.  The two
 // tile variants have the same thread count; each task runs the variant of
 // its solve's dtype on a shared LDS buffer.  Block offsets are in elements
@@ -2029,19 +2047,31 @@ int64_t device_wait_ticks(double seconds) {
     return (int64_t)(seconds * 1e3 * (double)khz);
 }
 
+// LDS per CU and the granule a workgroup's LDS is allocated in on gfx950.
+// A residency probe (plain launches of 128-thread workgroups that hold their
+// CU for 2 ms; two rounds take twice as long) fit 12 per CU at 12 800 bytes
+// each and not at 12 801, while the occupancy query still allowed 12 up to
+// 13 653 bytes (and 13 at 12 288): it rounds to a finer granule.
+constexpr int kLdsPerCu = 160 * 1024, kLdsGranule = 1280;
+
 // Co-resident workgroups per CU of a cooperative kernel: the occupancy
-// query `per` (exact for VGPRs and LDS), limited by what the kernel's scalar
-// registers allow (waves_by_sgprs of the count the compiler recorded for
-// this build; a kernel missing from the record is taken as 5 waves per
-// SIMD) and by `max_waves` waves per SIMD (a scheduling choice).  A
-// cooperative grid larger than what is resident would never complete its
-// first device-wide barrier.
+// query `per` (exact for VGPRs), limited by the kernel's LDS in whole
+// granules and by what its scalar registers allow (both from what the
+// compiler recorded for this build; a kernel missing from the record is
+// taken as 5 waves per SIMD), and by `max_waves` waves per SIMD (a
+// scheduling choice).  A cooperative grid larger than what is resident
+// would never complete its first device-wide barrier.
 static int coop_per_cu(int per, int threads, const char* name, int max_waves) {
-    int sg = 0;
-    const int w_sgpr = kernel_resources(name, &sg, nullptr, nullptr) ? waves_by_sgprs(sg) : 5;
+    int sg = 0, lds = 0;
+    const bool rec = kernel_resources(name, &sg, nullptr, &lds);
+    const int w_sgpr = rec ? waves_by_sgprs(sg) : 5;
     const int w = max_waves > 0 && max_waves < w_sgpr ? max_waves : w_sgpr;
     const int wpw = (threads + 63) / 64;
-    const int cap = (4 * w) / wpw;   // 4 SIMDs per CU
+    int cap = (4 * w) / wpw;   // 4 SIMDs per CU
+    if (rec && lds > 0) {
+        const int by_lds = kLdsPerCu / ((lds + kLdsGranule - 1) / kLdsGranule * kLdsGranule);
+        cap = by_lds < cap ? by_lds : cap;
+    }
     return per < cap ? per : cap;
 }
 
@@ -2052,6 +2082,7 @@ static std::string kernel_name(const char* base, int dtype_bytes, int tx, int ty
 
 static std::string coop_name(int dtype_bytes, int tx, int ty, int kind) {
     return kind == 1   ? kernel_name("k_msgdriven", dtype_bytes, tx, ty, nullptr)
+           : kind == 5 ? kernel_name("k_msgdriven2", dtype_bytes, tx, ty, nullptr)
            : kind >= 3 ? kernel_name("k_persistent2", dtype_bytes, tx, ty, kind == 4 ? ", true" : ", false")
                        : kernel_name("k_persistent", dtype_bytes, tx, ty, kind == 2 ? ", true" : ", false");
 }
@@ -2073,7 +2104,10 @@ int persistent_max_grid(int dtype_bytes, int tx, int ty, int kind, int max_waves
     if (kind >= 3) {
 #define OD_OCC2(T, TX, TY)                                                                            \
         if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                  \
-            const hipError_t e = kind == 4                                                            \
+            const hipError_t e = kind == 5                                                            \
+                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_msgdriven2<T, TX, TY>,         \
+                                                               SW2<T, TX, TY>::NT, 0)                 \
+                : kind == 4                                                                           \
                 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent2<T, TX, TY, true>,  \
                                                                SW2<T, TX, TY>::NT, 0)                 \
                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent2<T, TX, TY, false>, \
@@ -2178,6 +2212,21 @@ hipError_t launch_msgdriven(int dtype_bytes, int tx, int ty, hipStream_t st, int
     OD_VARIANTS_F64(OD_LAUNCH)
     OD_VARIANTS_F32(OD_LAUNCH)
 #undef OD_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_msgdriven2(int dtype_bytes, int tx, int ty, hipStream_t st, int grid, const MsgArgs& a) {
+    if (a.tiles2 == nullptr) return hipErrorInvalidValue;
+    MsgArgs ac = a;
+#define OD_LAUNCH2(T, TX, TY)                                                                         \
+    if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                      \
+        void* args[] = {&ac};                                                                         \
+        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_msgdriven2<T, TX, TY>),    \
+                                          dim3(grid), dim3(SW2<T, TX, TY>::NT), args, 0, st);         \
+    }
+    OD_VARIANTS2_F64(OD_LAUNCH2)
+    OD_VARIANTS2_F32(OD_LAUNCH2)
+#undef OD_LAUNCH2
     return hipErrorInvalidValue;
 }
 

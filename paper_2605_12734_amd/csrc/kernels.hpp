@@ -194,8 +194,9 @@ int64_t device_wait_ticks(double seconds = 10.0);
 // Max co-resident workgroups of a cooperative kernel: kind 0 = persistent
 // with the static tile stride, 2 = persistent with tile counters (dyn),
 // 1 = message-driven, 3 / 4 = persistent two-step passes with the static
-// stride / with counters; at most max_waves waves per SIMD (0 = the default
-// choice: 5 for kind 2, else as many as the registers allow).
+// stride / with counters, 5 = message-driven two-step tasks; at most
+// max_waves waves per SIMD (0 = the default choice: 5 for kind 2, else as
+// many as the registers allow).
 int persistent_max_grid(int dtype_bytes, int tx, int ty, int kind, int max_waves = 0);
 // Waves per SIMD the kernel's recorded scalar registers allow.
 int coop_waves_limit(int dtype_bytes, int tx, int ty, int kind);
@@ -209,6 +210,7 @@ struct MsgArgs {
     void* arena;
     const BlockDev* blocks;
     const TileDev* tiles;
+    const Tile2Dev* tiles2;     // plain grid with two-step tasks: each tile's extra lines
     int32_t ntiles;             // launch positions (plain grid: tiles)
     const int32_t* dep_ptr;
     const int32_t* dep_idx;
@@ -262,6 +264,9 @@ struct MsgArgs {
     int32_t qsteps;
 };
 hipError_t launch_msgdriven(int dtype_bytes, int tx, int ty, hipStream_t st, int grid, const MsgArgs& a);
+// The same scheduler with tasks of two steps (a.tiles2 set; a scheduler
+// step is one two-step pass: the field's parity flips once per step).
+hipError_t launch_msgdriven2(int dtype_bytes, int tx, int ty, hipStream_t st, int grid, const MsgArgs& a);
 // Clear the control words of a dependency-counting message-driven launch
 // (the launch itself lays out and fills its queues); a plain grid also
 // stores its target step in *target_word and zeroes res_clear[0..2) (both

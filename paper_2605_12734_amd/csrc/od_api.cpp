@@ -169,13 +169,15 @@ namespace {
 // re-run chare would have to repeat both steps), and a tile shape with a
 // two-step variant (3D tiles, or the 2D stencil's row tiles);
 // the persistent form also the 3D stencil, the fixed-stride or counter
-// schedule (with or without the guided tail) and no timeline.
+// schedule (with or without the guided tail) and no timeline; the
+// message-driven form the 3D stencil.
 bool two_step_possible(const Grid& G) {
     const od_config& cfg = G.cfg;
     const Plan& p = G.plan;
     const bool form = cfg.exec == OD_FUSED || cfg.exec == OD_GRAPH ||
                       (cfg.exec == OD_PERSISTENT && cfg.stencil != 5 && G.sched() >= 1 && G.sched() <= 3 &&
-                       !(cfg.hints & kHintTimeline));
+                       !(cfg.hints & kHintTimeline)) ||
+                      (cfg.exec == OD_MSGDRIVEN && cfg.stencil != 5);
     return form && !(cfg.hints & 4096) && !p.multires && G.imb.heavy == 0;
 }
 
@@ -185,7 +187,8 @@ bool two_step_room(const Grid& G) {
     const od_config& cfg = G.cfg;
     const Plan& p = G.plan;
     const bool form = cfg.exec == OD_FUSED || cfg.exec == OD_GRAPH ||
-                      (cfg.exec == OD_PERSISTENT && cfg.stencil != 5 && !(cfg.hints & (kHintTimeline | 2048)));
+                      (cfg.exec == OD_PERSISTENT && cfg.stencil != 5 && !(cfg.hints & (kHintTimeline | 2048))) ||
+                      (cfg.exec == OD_MSGDRIVEN && cfg.stencil != 5);
     const bool imbalance = cfg.imbalance_pct > 0 && cfg.imbalance_max_extra > 0;
     return form && !(cfg.hints & 4096) && !p.multires && !imbalance;
 }
@@ -604,7 +607,11 @@ std::string build_layout(const od_config& cfg, Grid& G) {
     G.dep_ptr.clear();
     G.dep_idx.clear();
     if (cfg.exec == OD_MSGDRIVEN) {
-        std::string e2 = build_tile_deps(p, G.dep_ptr, G.dep_idx);
+        // two-step tasks (decided with the tile list, as decide_two_step
+        // will) read tiles up to two cells away
+        const bool reach2 = two_step_possible(G) && sweep2_variant_ok(G.s, p.tile[0], p.tile[1]) &&
+                            p.tiles.size() <= G.tile2_cap;
+        std::string e2 = build_tile_deps(p, G.dep_ptr, G.dep_idx, reach2);
         if (!e2.empty()) return e2;
     }
     G.L.xpub = cv.take(cfg.exec == OD_MSGDRIVEN ? ntiles : 1);
@@ -628,7 +635,7 @@ std::string build_layout(const od_config& cfg, Grid& G) {
 
 // Tiles whose box intersects a ghost slab of tile t (face neighbours through
 // which halos are read), as CSR lists.
-std::string build_tile_deps(const Plan& p, std::vector<int32_t>& ptr, std::vector<int32_t>& idx) {
+std::string build_tile_deps(const Plan& p, std::vector<int32_t>& ptr, std::vector<int32_t>& idx, bool reach2) {
     const size_t T = p.tiles.size();
     // per chare: regular cut index -> tile ids
     struct Key {
@@ -650,15 +657,8 @@ std::string build_tile_deps(const Plan& p, std::vector<int32_t>& ptr, std::vecto
     for (size_t i = 0; i < T; ++i) {
         const TileHost& t = p.tiles[i];
         std::vector<int32_t> deps;
-        for (int f = 0; f < 6; ++f) {
-            if (t.kind[f] == 1) continue;
-            const int32_t sc = t.kind[f] == 2 ? t.chare : t.src[f];
-            const Chare& c = p.chares[(size_t)sc];
-            int64_t lo[3], hi[3];
-            for (int d = 0; d < 3; ++d) {
-                lo[d] = t.g[f][d] - c.o[d];
-                hi[d] = lo[d] + (d == f / 2 ? 1 : t.e[d]);
-            }
+        // tiles of chare sc overlapping the box [lo, hi) (chare-local)
+        auto add_box = [&](int32_t sc, const int64_t lo[3], const int64_t hi[3]) {
             for (int64_t iz = lo[2] / p.tile[2]; iz <= (hi[2] - 1) / p.tile[2]; ++iz)
                 for (int64_t iy = lo[1] / p.tile[1]; iy <= (hi[1] - 1) / p.tile[1]; ++iy)
                     for (int64_t ix = lo[0] / p.tile[0]; ix <= (hi[0] - 1) / p.tile[0]; ++ix) {
@@ -672,6 +672,63 @@ std::string build_tile_deps(const Plan& p, std::vector<int32_t>& ptr, std::vecto
                             if (hit && o != (int32_t)i) deps.push_back(o);
                         }
                     }
+        };
+        for (int f = 0; f < 6; ++f) {
+            if (t.kind[f] == 1) continue;
+            const int32_t sc = t.kind[f] == 2 ? t.chare : t.src[f];
+            const Chare& c = p.chares[(size_t)sc];
+            int64_t lo[3], hi[3];
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = t.g[f][d] - c.o[d];
+                hi[d] = lo[d] + (d == f / 2 ? 1 : t.e[d]);
+            }
+            add_box(sc, lo, hi);
+        }
+        if (reach2) {
+            // a pass of two steps also reads the slabs two out and the
+            // cells diagonal to each edge (every such box lies in one
+            // chare: the two-step lines' condition); boxes outside the
+            // domain are boundary values
+            const Chare& own = p.chares[(size_t)t.chare];
+            int64_t g0[3], g1[3];
+            for (int d = 0; d < 3; ++d) {
+                g0[d] = (int64_t)own.u[d] + t.o[d];
+                g1[d] = g0[d] + t.e[d];
+            }
+            std::vector<std::array<int64_t, 6>> boxes;   // global lo[3], hi[3]
+            for (int f = 0; f < 6; ++f) {
+                const int d = f / 2;
+                std::array<int64_t, 6> b{g0[0], g0[1], g0[2], g1[0], g1[1], g1[2]};
+                b[(size_t)d] = (f & 1) ? g1[d] + 1 : g0[d] - 2;
+                b[(size_t)d + 3] = b[(size_t)d] + 1;
+                boxes.push_back(b);
+            }
+            for (int d1 = 0; d1 < 3; ++d1)
+                for (int d2 = d1 + 1; d2 < 3; ++d2)
+                    for (int s1 = 0; s1 < 2; ++s1)
+                        for (int s2 = 0; s2 < 2; ++s2) {
+                            std::array<int64_t, 6> b{g0[0], g0[1], g0[2], g1[0], g1[1], g1[2]};
+                            b[(size_t)d1] = s1 ? g1[d1] : g0[d1] - 1;
+                            b[(size_t)d1 + 3] = b[(size_t)d1] + 1;
+                            b[(size_t)d2] = s2 ? g1[d2] : g0[d2] - 1;
+                            b[(size_t)d2 + 3] = b[(size_t)d2] + 1;
+                            boxes.push_back(b);
+                        }
+            for (const auto& b : boxes) {
+                bool inside = true;
+                for (int d = 0; d < 3; ++d) inside = inside && b[(size_t)d] >= 0 && b[(size_t)d + 3] <= p.n[d];
+                if (!inside) continue;
+                const int32_t sc = plan_owner(p, b[0], b[1], b[2]);
+                if (sc != plan_owner(p, b[3] - 1, b[4] - 1, b[5] - 1))
+                    return std::string("internal error: a two-step box spans chares");
+                const Chare& c = p.chares[(size_t)sc];
+                int64_t lo[3], hi[3];
+                for (int d = 0; d < 3; ++d) {
+                    lo[d] = b[(size_t)d] - c.u[d];
+                    hi[d] = b[(size_t)d + 3] - c.u[d];
+                }
+                add_box(sc, lo, hi);
+            }
         }
         std::sort(deps.begin(), deps.end());
         deps.erase(std::unique(deps.begin(), deps.end()), deps.end());
@@ -778,7 +835,11 @@ od_status Grid::setup_cooperative(bool fresh_plan) {
     if (cfg.exec == OD_PERSISTENT)
         two_step = two_step_possible(*this) && sweep2_variant_ok(s, plan.tile[0], plan.tile[1]) &&
                    base_tiles.size() <= tile2_cap;
-    const int cap = persistent_max_grid(s, plan.tile[0], plan.tile[1], coop_kind(), persist_waves);
+    int cap = persistent_max_grid(s, plan.tile[0], plan.tile[1], coop_kind(), persist_waves);
+    // a message-driven grid with two-step tasks runs an odd last iteration
+    // with the one-step kernel on the same grid
+    if (cfg.exec == OD_MSGDRIVEN && two_step)
+        cap = std::min(cap, persistent_max_grid(s, plan.tile[0], plan.tile[1], 1, persist_waves));
     int grid = std::min<int>(cap, (int)base_tiles.size());
     if (grid >= kNumXcd) grid -= grid % kNumXcd;
     grid_wgs = grid;
@@ -877,6 +938,7 @@ od_status Grid::reset_state() {
     if (e != hipSuccess) return fail(OD_EHIP, std::string("state reset: ") + hipGetErrorString(e));
     parity = 0;
     iters = 0;
+    flips = 0;
     faces_packed = false;
     return OD_OK;
 }
@@ -1064,21 +1126,27 @@ od_status Grid::msgdriven_run(int64_t n) {
     // 24-bit slot sequences never alias and finish counters never wrap.
     const int64_t per = std::max<int64_t>(1, std::min<int64_t>(((int64_t)1 << 16) - 1,
                                                                ((int64_t)1 << 23) / std::max<size_t>(tiles_h.size(), 1)));
-    while (n > per) {
-        od_status st2 = msgdriven_launch(per);
+    // two-step tasks: n / 2 passes, an odd last iteration as a one-step launch
+    int64_t m = two_step ? n / 2 : n;
+    while (m > 0) {
+        const int64_t k = std::min(m, per);
+        od_status st2 = msgdriven_launch(k, two_step);
         if (st2 != OD_OK) return st2;
-        n -= per;
+        m -= k;
     }
-    return msgdriven_launch(n);
+    if (two_step && (n & 1)) return msgdriven_launch(1, false);
+    return OD_OK;
 }
 
-od_status Grid::msgdriven_launch(int64_t n) {
-    // target = iters + n ; the final-step residual slots (2, 3) are cleared
-    const int32_t tgt = (int32_t)(iters + n);
+od_status Grid::msgdriven_launch(int64_t n, bool pairs) {
+    // target = flips + n scheduler steps; the final-step residual slots
+    // (2, 3) are cleared
+    const int32_t tgt = (int32_t)(flips + n);
     MsgArgs a{};
     a.arena = base;
     a.blocks = reinterpret_cast<const BlockDev*>(cp(L.blocks));
     a.tiles = reinterpret_cast<const TileDev*>(cp(L.tiles));
+    a.tiles2 = pairs ? reinterpret_cast<const Tile2Dev*>(cp(L.tiles2)) : nullptr;
     a.ntiles = (int32_t)tiles_h.size();
     a.dep_ptr = reinterpret_cast<const int32_t*>(cp(L.dep_ptr));
     a.dep_idx = reinterpret_cast<const int32_t*>(cp(L.dep_idx));
@@ -1106,10 +1174,12 @@ od_status Grid::msgdriven_launch(int64_t n) {
     // residual pair (kernel arguments: nothing on the host outlives this call)
     hipError_t e = launch_queue_init(st, a, tgt, reinterpret_cast<int32_t*>(cp(L.target)), res_ptr() + 2);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("queue init: ") + hipGetErrorString(e));
-    e = launch_msgdriven(s, plan.tile[0], plan.tile[1], st, grid_wgs, a);
+    e = pairs ? launch_msgdriven2(s, plan.tile[0], plan.tile[1], st, grid_wgs, a)
+              : launch_msgdriven(s, plan.tile[0], plan.tile[1], st, grid_wgs, a);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("msg-driven launch: ") + hipGetErrorString(e));
     parity = tgt & 1;
-    iters += n;
+    flips = tgt;
+    iters += pairs ? 2 * n : n;
     msg_final = true;
     return OD_OK;
 }

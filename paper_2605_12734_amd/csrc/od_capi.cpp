@@ -332,6 +332,18 @@ od_status od_tile_info_get(od_grid* g, int32_t t, od_tile_info* out) {
     return OD_OK;
 }
 
+od_status od_tile_deps(od_grid* g, int32_t t, int32_t* out, int32_t cap, int32_t* count) {
+    if (!g || !count || (cap > 0 && !out)) return fail(OD_EINVAL, "NULL argument");
+    const Grid& G = g->g;
+    if (G.cfg.exec != OD_MSGDRIVEN) return fail(OD_EINVAL, "dependency lists exist for OD_MSGDRIVEN grids only");
+    if (t < 0 || t >= (int32_t)G.plan.tiles.size() || (size_t)t + 1 >= G.dep_ptr.size())
+        return fail(OD_EINVAL, "tile index out of range");
+    const int32_t lo = G.dep_ptr[(size_t)t], hi = G.dep_ptr[(size_t)t + 1];
+    *count = hi - lo;
+    for (int32_t i = 0; i < hi - lo && i < cap; ++i) out[i] = G.dep_idx[(size_t)(lo + i)];
+    return OD_OK;
+}
+
 od_status od_chare_get(od_grid* g, int32_t c, od_block* out) {
     if (!g || !out) return fail(OD_EINVAL, "NULL argument");
     const Grid& G = g->g;

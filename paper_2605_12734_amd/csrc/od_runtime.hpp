@@ -52,8 +52,9 @@ struct Grid {
     std::vector<FillSeg> segs_h;     // multi-resolution ghost fill rectangles
     int64_t fill_total = 0;          // ghost cells filled per iteration
     std::vector<XExpDev> xexp_h;     // per-chare x-column exports (empty: none)
-    // two steps per pass (OD_FUSED / OD_GRAPH, see two_step_ok): decided
-    // with the tile list; the tiles' extra line descriptors
+    // two steps per pass (fused, graph, persistent and message-driven
+    // forms, see two_step_possible): decided with the tile list; the
+    // tiles' extra line descriptors
     bool two_step = false;
     std::vector<Tile2Dev> tiles2_h;
     int64_t halo2_cells = 0;         // cells of other chares within two steps of each chare
@@ -86,7 +87,8 @@ struct Grid {
     bool persistent_dyn() const { return sched() == 2 || sched() == 3; }
     // cooperative-kernel kind for persistent_max_grid
     int coop_kind() const {
-        return cfg.exec == OD_MSGDRIVEN ? 1 : (two_step ? (persistent_dyn() ? 4 : 3) : (persistent_dyn() ? 2 : 0));
+        return cfg.exec == OD_MSGDRIVEN ? (two_step ? 5 : 1)
+                                        : (two_step ? (persistent_dyn() ? 4 : 3) : (persistent_dyn() ? 2 : 0));
     }
     std::vector<TileHost> base_tiles;   // the planner's tile list before schedule-specific cuts
     std::vector<MsgBufs> msg;
@@ -112,6 +114,10 @@ struct Grid {
     GridDev gdev{};
     int parity = 0;
     int64_t iters = 0;
+    // message-driven grids: scheduler steps run so far, the value every
+    // tile's step counter holds between launches (a two-step task is one
+    // step), so parity == flips & 1
+    int64_t flips = 0;
     bool msg_final = false;
     int32_t stamp_iters = 0;         // iterations of the last persistent launch with a timeline
     int grid_wgs = 0;
@@ -152,7 +158,7 @@ struct Grid {
     od_status graph_run(int64_t n);
     od_status persistent_run(int64_t n);
     od_status msgdriven_run(int64_t n);
-    od_status msgdriven_launch(int64_t n);
+    od_status msgdriven_launch(int64_t n, bool pairs);   // n scheduler steps (pairs: two-step tasks)
     od_status per_chare_run(int64_t n);
     od_status iterate(int64_t n);
     od_status residual(double* r);
@@ -176,6 +182,6 @@ void decide_two_step(Grid& G);
 // Smallest tile extents any autotune candidate uses for a dtype.
 void tune_min_tile(int dtype_bytes, int32_t ey_max, int32_t m[3]);
 od_status autotune(Grid& G, int32_t iters, int32_t out_tile[3]);
-std::string build_tile_deps(const Plan& p, std::vector<int32_t>& ptr, std::vector<int32_t>& idx);
+std::string build_tile_deps(const Plan& p, std::vector<int32_t>& ptr, std::vector<int32_t>& idx, bool reach2 = false);
 
 }  // namespace od

@@ -50,7 +50,8 @@ std::string signature(const Grid& G) {
     for (const auto& kv : hist) os << "/" << kv.first[0] << "x" << kv.first[1] << "x" << kv.first[2] << ":" << kv.second;
     // message-driven grids tune the scheduler at their own tile; schedule
     // checks and load imbalance change what is timed
-    if (G.cfg.exec == OD_MSGDRIVEN) os << "/t" << G.plan.tile[0] << "x" << G.plan.tile[1] << "x" << G.plan.tile[2];
+    if (G.cfg.exec == OD_MSGDRIVEN)
+        os << "/t" << G.plan.tile[0] << "x" << G.plan.tile[1] << "x" << G.plan.tile[2] << (G.two_step ? "/p2" : "");
     os << "/h" << (G.cfg.hints & ~1) << "/i" << G.cfg.imbalance_pct << "x" << G.cfg.imbalance_max_extra;
     return os.str();
 }
@@ -143,7 +144,7 @@ static void apply_schedule(Grid& G, int32_t sched, int32_t waves) {
 struct SavedState {
     std::vector<char> ctrl;
     size_t fbytes = 0;
-    int64_t iters = 0;
+    int64_t iters = 0, flips = 0;
     int parity = 0;
     bool msg_final = false;
 };
@@ -159,6 +160,7 @@ static od_status save_state(Grid& G, SavedState& S) {
     if (he == hipSuccess) he = hipMemcpy(S.ctrl.data(), G.ctrl, S.ctrl.size(), hipMemcpyDeviceToHost);
     if (he != hipSuccess) return fail(OD_EHIP, std::string("save state: ") + hipGetErrorString(he));
     S.iters = G.iters;
+    S.flips = G.flips;
     S.parity = G.parity;
     S.msg_final = G.msg_final;
     return OD_OK;
@@ -169,6 +171,7 @@ static hipError_t restore_state(Grid& G, const SavedState& S) {
     if (he == hipSuccess) he = hipMemcpy(G.base, G.pinned, S.fbytes, hipMemcpyHostToDevice);
     if (he == hipSuccess) he = hipMemcpy(G.ctrl, S.ctrl.data(), S.ctrl.size(), hipMemcpyHostToDevice);
     G.iters = S.iters;
+    G.flips = S.flips;
     G.parity = S.parity;
     G.msg_final = S.msg_final;
     return he;
@@ -184,7 +187,7 @@ static od_status tune_msgdriven(Grid& G, int32_t iters, std::array<int32_t, 5>& 
     od_status st = save_state(G, S);
     if (st != OD_OK) return st;
     hipError_t he = hipSuccess;
-    const int limit = coop_waves_limit(G.s, G.plan.tile[0], G.plan.tile[1], 1);
+    const int limit = coop_waves_limit(G.s, G.plan.tile[0], G.plan.tile[1], G.coop_kind());
     hipEvent_t a = nullptr, b = nullptr;
     he = hipEventCreate(&a);
     if (he == hipSuccess) he = hipEventCreate(&b);

@@ -1,4 +1,5 @@
-"""Two Jacobi steps per pass (OD_FUSED / OD_GRAPH default on regular grids):
+"""Two Jacobi steps per pass (the fused, graph, persistent and message-driven
+forms' default where blocks are at one resolution and there is no imbalance):
 the pass reads the field once, keeps the first step on chip and writes the
 second.  Every case is compared with the CPU oracle bit for bit (0 ULP),
 with odd and even iteration counts (an odd count ends with a single sweep),
@@ -157,7 +158,8 @@ def test_not_used_where_unsupported():
     # imbalance, a forced persistent schedule and the message-driven and
     # per-chare forms keep one step per pass
     for kw in ({"exec": "fused", "imbalance_pct": 10, "imbalance_max_extra": 2},
-               {"exec": "persistent", "hints": 2048}, {"exec": "msgdriven"}, {"exec": "per_chare"}):
+               {"exec": "persistent", "hints": 2048},
+               {"exec": "msgdriven", "imbalance_pct": 10, "imbalance_max_extra": 2}, {"exec": "per_chare"}):
         g = od.Grid(64, odf=8, dtype="f64", **kw)
         try:
             assert g.plan()["steps_per_pass"] == 1
@@ -211,6 +213,62 @@ def test_1024_odf32768_pairs_sampled(exec_):
     for c in (31, 32, 63, 64, 511, 512, 991, 992):
         pts += [(c, c, c), (c, c, 100), (c, 7, c), (300, c, c), (0, c, c), (c, 1023, 0)]
     g = od.Grid(n, odf=32768, dtype="f64", exec=exec_, tile=(32, 32, 32), hints=1)
+    try:
+        assert g.plan()["steps_per_pass"] == 2
+        g.iterate(iters)
+        got = g.read_points(np.array([(k * n[1] + j) * n[0] + i for (i, j, k) in pts], dtype=np.int64))
+    finally:
+        g.close()
+    want = oracle.point_values(n, pts, iters, np.float64)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("iters", [1, 2, 7, 12])
+def test_msgdriven_pairs(dtype, iters):
+    # message-driven tasks of two steps (an odd count ends with a one-step
+    # launch on the same grid)
+    plan = _case(64, 8, dtype, iters, exec_="msgdriven")
+    assert plan["steps_per_pass"] == 2
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_msgdriven_pairs_ragged(dtype):
+    plan = _case((150, 90, 70), 27, dtype, 9, exec_="msgdriven", tile=(32, 16, 16), bc=BC6, seed=7)
+    assert plan["steps_per_pass"] == 2
+
+
+@pytest.mark.parametrize("hints", [1 | 64, 1 | 128, 1 | 128 | 512, 1 | 64 | 1024, 1 | 4])
+def test_msgdriven_pairs_schedulers(hints):
+    # cursor and ready-queue claims, publisher on and off, and the seeded
+    # schedule perturbation with its step-window check
+    plan = _case(128, 64, "f64", 10, exec_="msgdriven", tile=(16, 16, 16), hints=hints, seed=3)
+    assert plan["steps_per_pass"] == 2
+
+
+def test_msgdriven_pairs_then_single_steps_resume():
+    # pairs, a single step, pairs: the tiles' step counters follow both kernels
+    want, _, r_w = oracle.solve((96, 64, 48), np.float64, seed=31, iters=9, bc=BC6)
+    g = od.Grid((96, 64, 48), odf=27, dtype="f64", exec="msgdriven", bc=BC6, seed=31, hints=1)
+    try:
+        for k in (3, 4, 2):
+            g.iterate(k)
+        U, r, it = g.read(), g.residual(), g.iterations()
+        assert g.plan()["steps_per_pass"] == 2
+    finally:
+        g.close()
+    _same(U, want)
+    assert r == r_w and it == 9
+
+
+def test_512_odf4096_msgdriven_pairs_sampled():
+    n = (512, 512, 512)
+    iters = 20
+    rng = np.random.default_rng(5)
+    pts = [tuple(int(v) for v in rng.integers(0, 512, 3)) for _ in range(24)]
+    for c in (31, 32, 255, 256, 480, 511):
+        pts += [(c, c, c), (c, 0, c), (0, c, 100), (c, 511, 7)]
+    g = od.Grid(n, odf=4096, dtype="f64", exec="msgdriven", tile=(32, 16, 32), hints=1)
     try:
         assert g.plan()["steps_per_pass"] == 2
         g.iterate(iters)

@@ -270,20 +270,25 @@ def test_two_step_pass_bytes_brute_force(n, odf, dtype):
 
 
 @pytest.mark.parametrize("kw", [{"exec": "persistent", "hints": 2048}, {"exec": "persistent", "hints": 8},
-                                {"exec": "msgdriven"}, {"exec": "per_chare"},
+                                {"exec": "msgdriven", "hints": 4096}, {"exec": "msgdriven", "stencil": 5,
+                                                                       "n": (64, 1, 64)},
+                                {"exec": "msgdriven", "imbalance_pct": 10, "imbalance_max_extra": 2},
+                                {"exec": "per_chare"},
                                 {"exec": "fused", "hints": 4096},
                                 {"exec": "fused", "imbalance_pct": 10, "imbalance_max_extra": 2},
                                 {"exec": "fused", "tile": (128, 4, 8)}])
 def test_two_step_only_where_supported(kw):
     # other forms, the one-step hint, imbalance and tile shapes without a
     # two-step variant keep one step per pass
-    plan = od.host_plan(n=(64, 64, 64), odf=8, dtype="f64", **kw)
+    kw = dict(kw)
+    plan = od.host_plan(n=kw.pop("n", (64, 64, 64)), odf=8, dtype="f64", **kw)
     assert plan["steps_per_pass"] == 1
     assert plan["bytes_per_pass"] == plan["bytes_per_iter"]
 
 
 @pytest.mark.parametrize("exec_,hints", [("fused", 0), ("graph", 0), ("persistent", 0), ("persistent", 16),
-                                         ("persistent", 32), ("persistent", 8192)])
+                                         ("persistent", 32), ("persistent", 8192), ("msgdriven", 0),
+                                         ("msgdriven", 4 | 64), ("msgdriven", 128 | 1024)])
 def test_two_step_default_forms(exec_, hints):
     plan = od.host_plan(n=(64, 64, 64), odf=8, dtype="f64", exec=exec_, hints=hints)
     assert plan["steps_per_pass"] == 2
@@ -338,3 +343,43 @@ def test_two_step_octree_tiles_read_single_blocks(tile):
         for a, b in _two_step_boxes(o, t["extent"], n):
             ids = np.unique(own[a[2]:b[2], a[1]:b[1], a[0]:b[0]])
             assert len(ids) == 1, (t, a, b, ids)
+
+
+def _deps_brute(plan, n, reach):
+    """Every other tile owning a cell within L1 distance `reach` of a tile's
+    box (cells inside the domain), from a cell -> tile owner map."""
+    owner = np.full(n[::-1], -1, dtype=np.int64)   # [z, y, x]
+    boxes = []
+    for i, t in enumerate(plan["tiles"]):
+        co = plan["chares"][t["chare"]][0]
+        lo = [co[d] + t["origin"][d] for d in range(3)]
+        hi = [lo[d] + t["extent"][d] for d in range(3)]
+        owner[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = i
+        boxes.append((lo, hi))
+    assert (owner >= 0).all()
+    out = []
+    for i, (lo, hi) in enumerate(boxes):
+        a = [max(0, lo[d] - reach) for d in range(3)]
+        b = [min(n[d], hi[d] + reach) for d in range(3)]
+        z, y, x = np.meshgrid(np.arange(a[2], b[2]), np.arange(a[1], b[1]), np.arange(a[0], b[0]), indexing="ij")
+        dist = np.zeros(z.shape, dtype=np.int64)
+        for d, v in enumerate((x, y, z)):
+            dist += np.maximum(0, lo[d] - v) + np.maximum(0, v - (hi[d] - 1))
+        sub = owner[a[2]:b[2], a[1]:b[1], a[0]:b[0]]
+        got = set(int(v) for v in np.unique(sub[(dist >= 1) & (dist <= reach)]))
+        got.discard(i)
+        out.append(tuple(sorted(got)))
+    return out
+
+
+@pytest.mark.parametrize("n,odf,tile,hints,spp", [((64, 64, 64), 8, (16, 16, 8), 0, 2),
+                                                  ((70, 50, 45), 27, (32, 8, 8), 0, 2),
+                                                  ((40, 33, 29), 8, (16, 16, 4), 0, 2),
+                                                  ((70, 50, 45), 27, (32, 8, 8), 4096, 1)])
+def test_msgdriven_deps_reach_brute_force(n, odf, tile, hints, spp):
+    # the message-driven dependency lists are exactly the tiles a task reads
+    # (one cell out for single steps, two cells in L1 distance for two-step
+    # tasks), checked against a brute-force owner map
+    plan = od.host_plan(n=n, odf=odf, dtype="f64", exec="msgdriven", tile=tile, hints=hints)
+    assert plan["steps_per_pass"] == spp
+    assert plan["deps"] == _deps_brute(plan, n, spp)
