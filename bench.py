@@ -10,8 +10,9 @@ average launch time measured live with HIP events on the grid's stream),
 the measured HBM ceilings (copy, read-only, write-only), and, by default,
 every other part of the metric:
   odf_sweep        512^3 fp64 and fp32, ODF 8..4096: batched (graph-captured
-                   fused launches), batched persistent (one cooperative launch)
-                   and per-chare launches, each with its roofline fraction
+                   fused launches), batched persistent (one cooperative launch),
+                   message-driven (dependency-counting scheduler) and
+                   per-chare launches, each with its roofline fraction
   amr_octree_768   768^3 fp64 octree of uneven blocks, 500 iterations:
                    graph-captured and persistent, plus the multi-resolution
                    reading (ghost fill by injection / averaging)
@@ -214,7 +215,8 @@ def cpu_baseline(n, dtype, target_s=15.0, max_iters=200, chunk=10):
 def odf_sweep(n, iters, persistent=True):
     """Per dtype and ODF: graph-captured fused launches (tile autotuned),
     the persistent cooperative form (tile and schedule autotuned on its own
-    kernel), per-chare launches (the graph's tile).  Each
+    kernel), the message-driven form (the fused grid's tuned tile, z extent
+    at most 32), per-chare launches (the graph's tile).  Each
     batched form's roofline fraction divides the algorithmic bytes per
     iteration by its own kernel time per iteration (HIP events)."""
     rows = []
@@ -244,6 +246,14 @@ def odf_sweep(n, iters, persistent=True):
                             "persistent_step_bytes_frac": round(bp / q["launch_s"] / 1e9 / PEAK_HBM_GBPS, 4),
                             "persistent_us_per_iter": round(q["launch_s"] * 1e6, 2),
                             "persistent_grid_wgs": q["plan"]["grid_wgs"]})
+                m = grid_leg(n, odf, dtype, "msgdriven", iters, 2, 1)
+                gm = pass_gbps(m["plan"], m["launch_s"])
+                row.update({"msgdriven_tile": list(m["plan"]["tile"]),
+                            "msgdriven_steps_per_pass": m["plan"]["steps_per_pass"],
+                            "msgdriven_glups": round(m["glups"], 2),
+                            "msgdriven_hbm_gbps": round(gm, 1),
+                            "msgdriven_frac": round(gm / PEAK_HBM_GBPS, 4),
+                            "msgdriven_grid_wgs": m["plan"]["grid_wgs"]})
             pc_iters = 10 if odf <= 64 else (4 if odf <= 512 else 2)
             p = grid_leg(n, odf, dtype, "per_chare", pc_iters, 1, 1, tile=tile)
             row.update({"per_chare_glups": round(p["glups"], 3),

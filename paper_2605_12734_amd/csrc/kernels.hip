@@ -1694,8 +1694,19 @@ __global__ void __launch_bounds__((TX / V16<T>::N) * TY) OD_MSG_OCC k_msgdriven(
 // the dependency lists reach every tile within two cells (face slabs two
 // deep and the edge lines), so a tile still runs step k once everything it
 // reads has finished step k - 1 and nothing that reads it still needs k - 1.
+// Compiled for fewer waves than the one-step kernel: at 6 waves per SIMD
+// the scheduler's state and the two-step sweep spilled 124 bytes per lane
+// (512^3 fp64 ODF 4096, tile (32,16,32): 430 us per iteration); fp64 at 5
+// waves (40 bytes) took 289, at 4 (no spill) 309; fp32 at 4 waves 175
+// against 238 at 5 and 248 at 6.
+template <typename T>
+struct Msg2Waves {
+    static constexpr int value = sizeof(T) == 8 ? 5 : 4;
+};
+
 template <typename T, int TX, int TY>
-__global__ void __launch_bounds__((TX / V16<T>::N) * TY) OD_MSG_OCC k_msgdriven2(MsgArgs a) {
+__global__ void __launch_bounds__((TX / V16<T>::N) * TY) __attribute__((amdgpu_waves_per_eu(Msg2Waves<T>::value, 8)))
+k_msgdriven2(MsgArgs a) {
     using S = SW2<T, TX, TY>;
     __shared__ __align__(16) T lds[S::LDS];
     __shared__ double red[S::NT / 64];
