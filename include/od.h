@@ -142,16 +142,18 @@ typedef struct {
      * XCD group's tiles per workgroup;
      * bit 13 (OD_PERSISTENT): the fixed stride per workgroup, also where
      * counters are the default;
-     * bit 12 (OD_FUSED, OD_GRAPH, OD_PERSISTENT): one step per pass.  By
-     * default these forms run iterations in pairs where they can (blocks
-     * at one resolution, no imbalance, a tile shape with a two-step
-     * variant; OD_PERSISTENT with the 3D stencil, the fixed-stride or
-     * counter schedule, with or without the guided tail, and no
-     * timeline): one pass reads the field once and writes it two steps
-     * later, the first step kept on chip (the same values as two single
-     * sweeps, bit for bit); od_iterate(n) with odd n ends with a single
-     * sweep.  With explicit blocks the tiles are also cut so that every
-     * line of cells a pair reads lies in one block.
+     * bit 12 (OD_FUSED, OD_GRAPH, OD_PERSISTENT, OD_MSGDRIVEN): one step
+     * per pass.  By default these forms run iterations in pairs where they
+     * can (blocks at one resolution, no imbalance, a tile shape with a
+     * two-step variant; OD_PERSISTENT with the 3D stencil, the
+     * fixed-stride or counter schedule, with or without the guided tail,
+     * and no timeline; OD_MSGDRIVEN with the 3D stencil, each task then a
+     * pass of its tile, waiting for the tiles within two cells): one pass
+     * reads the field once and writes it two steps later, the first step
+     * kept on chip (the same values as two single sweeps, bit for bit);
+     * od_iterate(n) with odd n ends with a single sweep.  With explicit
+     * blocks the tiles are also cut so that every line of cells a pair
+     * reads lies in one block.
      * od_plan_info.steps_per_pass tells which is in use.
      * Bit 8 is reserved.  Other bits are ignored. */
     int32_t hints;
