@@ -58,6 +58,9 @@ od_config request_config(const od_request& r) {
     for (int i = 0; i < 6; ++i) c.bc[i] = r.bc[i];
     c.seed = r.seed;
     c.exec = OD_MSGDRIVEN;
+    // the serving kernel runs tasks of one step (a solve may stop at any
+    // step): its dependency lists reach one cell
+    c.hints = 4096;
     if (r.dtype == OD_F64) {
         c.tile[0] = kServeTx8;
         c.tile[1] = kServeTy8;

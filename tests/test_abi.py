@@ -136,3 +136,14 @@ def test_create_static_host_checks():
     assert L.od_create_static(ctypes.byref(big), None, ctypes.c_void_p(256), 1 << 40, ctypes.byref(h)) == -12
     assert b"static array holds" in L.od_last_error()
     assert not h.value
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n,odf", [(384, 1), (384, 8), (384, 64), (300, 27)])
+def test_largest_serving_requests_fit_a_slot(dtype, n, odf):
+    # the serving kernel runs tasks of one step: a request's dependency
+    # lists reach one cell, so the largest request sizes fit a slot's
+    # tile and dependency tables (checked on the host, no GPU)
+    from paper_2605_12734_amd.serving import request_bytes
+
+    assert request_bytes(n=n, dtype=dtype, odf=odf, tol=1e-6, max_iters=2000) > 0
