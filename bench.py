@@ -291,18 +291,22 @@ def amr_leg(iters=500, multires_only=False):
     # (finest leaves unit cells), resolution-change faces filled by
     # injection / face averaging before every sweep
     cell = [e[0] // 16 for _, e in blocks]
-    g = make_grid(768, blocks=blocks, dtype="f64", exec_="graph", cell=cell)
-    try:
-        plan = g.plan()
-        t = timed(g, iters, 1, 1)
-    finally:
-        g.close()
-    bp = plan["bytes_per_iter"]
-    out["multires_graph"] = {"cells": plan["interior"], "glups": round(plan["interior"] * iters / t["wall_s"] / 1e9, 2),
-                             "hbm_gbps": round(bp * iters / t["dev_s"] / 1e9, 1),
-                             "frac": round(bp * iters / t["dev_s"] / 1e9 / PEAK_HBM_GBPS, 4),
-                             "tile": list(plan["tile"]), "tiles": plan["ntiles"], "iters": iters}
-    log("amr: multires graph", out["multires_graph"])
+    # graph: the ghost fill and the sweep as two kernels per iteration;
+    # persistent: both in one cooperative launch, a barrier after each
+    for exec_ in ("graph", "persistent"):
+        g = make_grid(768, blocks=blocks, dtype="f64", exec_=exec_, cell=cell)
+        try:
+            plan = g.plan()
+            t = timed(g, iters, 1, 1)
+        finally:
+            g.close()
+        bp = plan["bytes_per_iter"]
+        key = "multires_" + exec_
+        out[key] = {"cells": plan["interior"], "glups": round(plan["interior"] * iters / t["wall_s"] / 1e9, 2),
+                    "hbm_gbps": round(bp * iters / t["dev_s"] / 1e9, 1),
+                    "frac": round(bp * iters / t["dev_s"] / 1e9 / PEAK_HBM_GBPS, 4),
+                    "tile": list(plan["tile"]), "tiles": plan["ntiles"], "iters": iters}
+        log("amr: multires", exec_, out[key])
     return out
 
 

@@ -176,9 +176,12 @@ typedef struct {
      * second tangential axis outer and the first inner (tangential axes in
      * x, y, z order) and divided by r*r.  Across such a face the finer
      * block's tangential origin and extent must be multiples of the coarser
-     * cell, else OD_EINVAL.  Supported with OD_FUSED and OD_GRAPH; the
-     * global od_read / od_write / od_read_points calls are refused, use
-     * od_read_block / od_write_block. */
+     * cell, else OD_EINVAL.  Supported with OD_FUSED and OD_GRAPH (the
+     * fill and the sweep as two launches per iteration) and OD_PERSISTENT
+     * (both in one cooperative launch per od_iterate call, a device-wide
+     * barrier after each; tiles from per-XCD counters, so hints bits 3, 5,
+     * 11 and 13 and imbalance are refused); the global od_read / od_write /
+     * od_read_points calls are refused, use od_read_block / od_write_block. */
     const int32_t* block_cell;
     /* Bound, in seconds, on every device-side wait of the persistent and
      * message-driven launches (barriers, ready queues); 0 = 10 s.  A wait

@@ -995,6 +995,155 @@ k_persistent2(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const 
     persist_cleanup(bar);
 }
 
+// Resolution-change ghost fill: one single-wave workgroup per rectangle.
+// A ghost cell takes R = r*r source values (r = 1: the coarser or equal
+// neighbour's cell; r > 1: the finer neighbour's r x r cells).  The wave
+// loads a batch of up to 256 source values with every lane (4 loads in
+// flight per lane; values of one cell are consecutive, so lanes read along
+// the face's first tangential axis), stages them in LDS, then each lane
+// takes every 64th ghost cell of the batch, sums its R values in the fixed
+// order (q2 outer, q1 inner) and stores the mean.  (Summing in each lane straight from memory serialised
+// the loads: r = 8 cells took 64 dependent loads each.  Batches of 1024
+// values were slower: fewer waves fit.)  x-normal faces read the source
+// chare's exported column (FillSeg::eoff, written by the sweep) instead of
+// one value per row of its storage.
+constexpr int kFillLanes = 64, kFillBatch = 256;
+
+// Orders one wave's LDS stores before its later loads (the staging values
+// of a fill batch are written and read by the same wave).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One rectangle of the fill by one wave (lane 0..63); vals: the wave's own
+// kFillBatch staging values in LDS.
+template <typename T>
+__device__ __forceinline__ void fill_segment(T* __restrict__ arena, const BlockDev* __restrict__ blocks,
+                                             const FillSeg& S, int parity, int lane, T* __restrict__ vals) {
+    {
+        const int d = S.d, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+        const BlockDev& N = blocks[S.src];
+        const int64_t eo = parity ? S.eoff[1] : S.eoff[0];
+        // x-normal faces read the neighbour's exported column when it has one
+        const int64_t nb = eo >= 0 ? eo
+                                   : (parity ? N.off[1] : N.off[0]) + (int64_t)S.lay * (d == 0 ? 1 : d == 1 ? N.py : N.pz);
+        const int64_t s1 = eo >= 0 ? 1 : (t1 == 0 ? 1 : N.py);
+        const int64_t s2 = eo >= 0 ? (int64_t)S.ey : (t2 == 1 ? N.py : N.pz);
+        const BlockDev& D = blocks[S.dst];
+        const int64_t ds1 = t1 == 0 ? 1 : D.py, ds2 = t2 == 1 ? D.py : D.pz;
+        const int32_t rr = S.hc >> S.lhn, r = rr > 1 ? rr : 1, R = r * r;
+        const int32_t cells = S.n1 * S.n2;
+        const int32_t cpb = kFillBatch / R;   // cells per batch (r <= 16)
+        for (int32_t cb = 0; cb < cells; cb += cpb) {
+            const int32_t nc = cells - cb < cpb ? cells - cb : cpb, nval = nc * R;
+            T v[kFillBatch / kFillLanes];
+#pragma unroll
+            for (int j = 0; j < kFillBatch / kFillLanes; ++j) {
+                // whole waves of loads past the batch are skipped (uniform);
+                // in the last one every lane loads a valid (clamped) value
+                if (j * kFillLanes < nval) {
+                    int32_t f = lane + j * kFillLanes;
+                    f = f < nval ? f : nval - 1;
+                    const int32_t cell = cb + f / R, q = f % R;
+                    const int32_t c1 = cell % S.n1, c2 = cell / S.n1;
+                    const int32_t i1 = ((S.r1 + c1 * S.hc) >> S.lhn) + q % r, i2 = ((S.r2 + c2 * S.hc) >> S.lhn) + q / r;
+                    v[j] = arena[nb + (int64_t)i1 * s1 + (int64_t)i2 * s2];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kFillBatch / kFillLanes; ++j)
+                if (lane + j * kFillLanes < nval) vals[lane + j * kFillLanes] = v[j];
+            wave_lds_sync();
+            for (int32_t k = lane; k < nc; k += kFillLanes) {
+                T sum = vals[k * R];
+                for (int32_t q = 1; q < R; ++q) sum = sum + vals[k * R + q];
+                const T m = R > 1 ? sum / (T)R : sum;
+                const int32_t cell = cb + k, c1 = cell % S.n1, c2 = cell / S.n1;
+                arena[D.off[0] + (int64_t)(S.a1 + c1) * ds1 + (int64_t)(S.a2 + c2) * ds2] = m;
+            }
+            wave_lds_sync();
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kFillLanes)
+k_amr_fill(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const FillSeg* __restrict__ segs,
+           int32_t nseg, int parity) {
+    __shared__ T vals[kFillBatch];
+    for (int32_t sg = blockIdx.x; sg < nseg; sg += gridDim.x)
+        fill_segment<T>(arena, blocks, segs[sg], parity, (int)threadIdx.x, vals);
+}
+
+// Persistent form of a multi-resolution grid: per iteration every wave of
+// the grid fills resolution-change ghost rectangles (rectangle w, w + W,
+// ... for global wave w of W; the host lists them by decreasing cost, so
+// each wave gets a similar share; claiming them from one counter measured
+// 2.7x slower, every wave contending for the one word), the grid meets at
+// the per-XCD barrier,
+// every workgroup sweeps tiles from its XCD group's counter (claimed as
+// each tile ends) and exports the tiles' boundary x-columns for the next
+// fill, and the grid meets again.  The fill stages its values in the
+// sweep's LDS planes (the barriers separate the two uses).  (Asking for 6
+// waves per SIMD, 80 VGPRs instead of the compiler's 87 and 5 waves,
+// measured slower: 768^3 octree, 16 cells per leaf edge, 269 against 245 us
+// per iteration.)
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__((TX / V16<T>::N) * TY)
+k_persistent_mr(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDev* __restrict__ tiles,
+                int32_t ntiles, int parity, int64_t iters, unsigned long long* __restrict__ res, int32_t nres,
+                unsigned int* bar, unsigned int* err, int64_t wait_ticks, int hints,
+                const FillSeg* __restrict__ segs, int32_t nseg, const XExpDev* __restrict__ xexp) {
+    using S = SW<T, TX, TY>;
+    constexpr int NW = S::NT / 64;
+    static_assert(S::LDS >= NW * kFillBatch, "each wave stages its fill batch in the sweep's LDS");
+    __shared__ __align__(16) T lds[S::LDS];
+    __shared__ T red[NW];
+    __shared__ int32_t s_idx;
+    __shared__ int s_xcd;
+    __shared__ unsigned int s_xwgs, s_nxcd;
+    const int ng = (gridDim.x >= 8 && gridDim.x % 8 == 0) ? 8 : 1;
+    const int xg = (int)(blockIdx.x % ng);
+    const int wave = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
+    if (!persist_register(bar, err, wait_ticks, &s_xcd, &s_xwgs, &s_nxcd)) return;
+    for (int64_t it = 0; it < iters; ++it) {
+        const int p = parity ^ (int)(it & 1);
+        if (blockIdx.x == 0)
+            for (int s = (int)threadIdx.x; s < nres; s += S::NT) res[2 * s + p] = 0ull;
+        for (int32_t sg = (int32_t)blockIdx.x * NW + wave; sg < nseg; sg += (int32_t)gridDim.x * NW)
+            fill_segment<T>(arena, blocks, segs[sg], p, lane, lds + wave * kFillBatch);
+        // the last arrival clears the tile counters of the next iteration
+        // (this iteration's were cleared one iteration ago, or at launch)
+        if (!xcd_barrier(bar, err, wait_ticks, tile_ctr(bar, (int)((it + 1) & 1), 0), s_xcd, s_xwgs, s_nxcd))
+            return;
+        unsigned int* ctr = tile_ctr(bar, (int)(it & 1), xg);
+        if (threadIdx.x == 0)
+            s_idx = (int32_t)__hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        int32_t idx = __builtin_amdgcn_readfirstlane(s_idx);
+        T r = 0;
+        int slot = -1;
+        for (;;) {
+            const int32_t ti = xg + ng * idx;
+            if (ti >= ntiles) break;
+            const TileDev& t = tiles[ti];
+            const T rr = t.nz > 0 ? sweep_tile<T, TX, TY, true>(arena, blocks, t, p, lds, hints, xexp) : (T)0;
+            if (slot >= 0 && slot != t.rslot) {
+                wg_residual<T, S::NT>(r, &res[2 * slot + (p ^ 1)], red);
+                r = 0;
+            }
+            slot = t.rslot;
+            r = rr > r ? rr : r;
+            idx = next_tile(ctr, &s_idx);
+        }
+        if (slot >= 0) wg_residual<T, S::NT>(r, &res[2 * slot + (p ^ 1)], red);
+        if (it + 1 < iters && !xcd_barrier(bar, err, wait_ticks, nullptr, s_xcd, s_xwgs, s_nxcd)) return;
+    }
+    persist_cleanup(bar);
+}
+
 // ---------------------------------------------------------------------------
 // message-driven schedulers
 
@@ -2094,6 +2243,7 @@ static std::string kernel_name(const char* base, int dtype_bytes, int tx, int ty
 static std::string coop_name(int dtype_bytes, int tx, int ty, int kind) {
     return kind == 1   ? kernel_name("k_msgdriven", dtype_bytes, tx, ty, nullptr)
            : kind == 5 ? kernel_name("k_msgdriven2", dtype_bytes, tx, ty, nullptr)
+           : kind == 6 ? kernel_name("k_persistent_mr", dtype_bytes, tx, ty, nullptr)
            : kind >= 3 ? kernel_name("k_persistent2", dtype_bytes, tx, ty, kind == 4 ? ", true" : ", false")
                        : kernel_name("k_persistent", dtype_bytes, tx, ty, kind == 2 ? ", true" : ", false");
 }
@@ -2112,7 +2262,7 @@ int persistent_max_grid(int dtype_bytes, int tx, int ty, int kind, int max_waves
     // faster at 5 waves per SIMD than at 6
     if (max_waves <= 0) max_waves = kind == 2 ? 5 : 8;
     const std::string name = coop_name(dtype_bytes, tx, ty, kind);
-    if (kind >= 3) {
+    if (kind >= 3 && kind <= 5) {
 #define OD_OCC2(T, TX, TY)                                                                            \
         if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                  \
             const hipError_t e = kind == 5                                                            \
@@ -2138,6 +2288,9 @@ int persistent_max_grid(int dtype_bytes, int tx, int ty, int kind, int max_waves
                                                            SW<T, TX, TY>::NT, 0)                      \
             : kind == 2                                                                               \
             ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent<T, TX, TY, true>,       \
+                                                           SW<T, TX, TY>::NT, 0)                      \
+            : kind == 6                                                                               \
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent_mr<T, TX, TY>,          \
                                                            SW<T, TX, TY>::NT, 0)                      \
             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_msgdriven<T, TX, TY>,              \
                                                            SW<T, TX, TY>::NT, 0);                     \
@@ -2165,6 +2318,26 @@ hipError_t launch_persistent(int dtype_bytes, int tx, int ty, hipStream_t st, in
         const void* fn = dyn ? reinterpret_cast<const void*>(k_persistent<T, TX, TY, true>)           \
                              : reinterpret_cast<const void*>(k_persistent<T, TX, TY, false>);         \
         return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(SW<T, TX, TY>::NT), args, 0, st);      \
+    }
+    OD_VARIANTS_F64(OD_LAUNCH)
+    OD_VARIANTS_F32(OD_LAUNCH)
+#undef OD_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_persistent_mr(int dtype_bytes, int tx, int ty, hipStream_t st, int grid, void* arena,
+                                const BlockDev* blocks, const TileDev* tiles, int32_t ntiles, int parity,
+                                int64_t iters, unsigned long long* res, int32_t nres, unsigned int* bar,
+                                unsigned int* err, int64_t wait_ticks, int hints, const FillSeg* segs, int32_t nseg,
+                                const XExpDev* xexp) {
+    if (iters <= 0) return hipSuccess;
+#define OD_LAUNCH(T, TX, TY)                                                                          \
+    if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                      \
+        T* ar = reinterpret_cast<T*>(arena);                                                          \
+        void* args[] = {&ar, &blocks, &tiles, &ntiles, &parity, &iters, &res, &nres, &bar, &err,      \
+                        &wait_ticks, &hints, &segs, &nseg, &xexp};                                    \
+        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_persistent_mr<T, TX, TY>), \
+                                          dim3(grid), dim3(SW<T, TX, TY>::NT), args, 0, st);          \
     }
     OD_VARIANTS_F64(OD_LAUNCH)
     OD_VARIANTS_F32(OD_LAUNCH)
@@ -2319,72 +2492,6 @@ __global__ void k_init_cells(GridDev g, const int32_t* __restrict__ ccell, int32
     }
 }
 
-// Resolution-change ghost fill: one single-wave workgroup per rectangle.
-// A ghost cell takes R = r*r source values (r = 1: the coarser or equal
-// neighbour's cell; r > 1: the finer neighbour's r x r cells).  The wave
-// loads a batch of up to 256 source values with every lane (4 loads in
-// flight per lane; values of one cell are consecutive, so lanes read along
-// the face's first tangential axis), stages them in LDS, then each lane
-// takes every 64th ghost cell of the batch, sums its R values in the fixed
-// order (q2 outer, q1 inner) and stores the mean.  (Summing in each lane straight from memory serialised
-// the loads: r = 8 cells took 64 dependent loads each.  Batches of 1024
-// values were slower: fewer waves fit.)  x-normal faces read the source
-// chare's exported column (FillSeg::eoff, written by the sweep) instead of
-// one value per row of its storage.
-constexpr int kFillLanes = 64, kFillBatch = 256;
-
-template <typename T>
-__global__ void __launch_bounds__(kFillLanes)
-k_amr_fill(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const FillSeg* __restrict__ segs,
-           int32_t nseg, int parity) {
-    __shared__ T vals[kFillBatch];
-    const int lane = (int)threadIdx.x;
-    for (int32_t sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
-        const FillSeg& S = segs[sg];
-        const int d = S.d, t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-        const BlockDev& N = blocks[S.src];
-        const int64_t eo = parity ? S.eoff[1] : S.eoff[0];
-        // x-normal faces read the neighbour's exported column when it has one
-        const int64_t nb = eo >= 0 ? eo
-                                   : (parity ? N.off[1] : N.off[0]) + (int64_t)S.lay * (d == 0 ? 1 : d == 1 ? N.py : N.pz);
-        const int64_t s1 = eo >= 0 ? 1 : (t1 == 0 ? 1 : N.py);
-        const int64_t s2 = eo >= 0 ? (int64_t)S.ey : (t2 == 1 ? N.py : N.pz);
-        const BlockDev& D = blocks[S.dst];
-        const int64_t ds1 = t1 == 0 ? 1 : D.py, ds2 = t2 == 1 ? D.py : D.pz;
-        const int32_t rr = S.hc >> S.lhn, r = rr > 1 ? rr : 1, R = r * r;
-        const int32_t cells = S.n1 * S.n2;
-        const int32_t cpb = kFillBatch / R;   // cells per batch (r <= 16)
-        for (int32_t cb = 0; cb < cells; cb += cpb) {
-            const int32_t nc = cells - cb < cpb ? cells - cb : cpb, nval = nc * R;
-            T v[kFillBatch / kFillLanes];
-#pragma unroll
-            for (int j = 0; j < kFillBatch / kFillLanes; ++j) {
-                // whole waves of loads past the batch are skipped (uniform);
-                // in the last one every lane loads a valid (clamped) value
-                if (j * kFillLanes < nval) {
-                    int32_t f = lane + j * kFillLanes;
-                    f = f < nval ? f : nval - 1;
-                    const int32_t cell = cb + f / R, q = f % R;
-                    const int32_t c1 = cell % S.n1, c2 = cell / S.n1;
-                    const int32_t i1 = ((S.r1 + c1 * S.hc) >> S.lhn) + q % r, i2 = ((S.r2 + c2 * S.hc) >> S.lhn) + q / r;
-                    v[j] = arena[nb + (int64_t)i1 * s1 + (int64_t)i2 * s2];
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < kFillBatch / kFillLanes; ++j)
-                if (lane + j * kFillLanes < nval) vals[lane + j * kFillLanes] = v[j];
-            __syncthreads();
-            for (int32_t k = lane; k < nc; k += kFillLanes) {
-                T sum = vals[k * R];
-                for (int32_t q = 1; q < R; ++q) sum = sum + vals[k * R + q];
-                const T m = R > 1 ? sum / (T)R : sum;
-                const int32_t cell = cb + k, c1 = cell % S.n1, c2 = cell / S.n1;
-                arena[D.off[0] + (int64_t)(S.a1 + c1) * ds1 + (int64_t)(S.a2 + c2) * ds2] = m;
-            }
-            __syncthreads();
-        }
-    }
-}
 
 template <typename T>
 __global__ void k_fill_pb(GridDev g, int32_t npb, const int32_t* pb_face, const int32_t* pb_block,

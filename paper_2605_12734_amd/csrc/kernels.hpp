@@ -104,6 +104,7 @@ int sweep_threads(int dtype_bytes, int tx, int ty);
 // the load-imbalance draw of this step (imb.heavy == 0: none).
 // xexp (may be null): multi-resolution x-column exports (XExpDev, per chare).
 struct XExpDev;
+struct FillSeg;
 hipError_t launch_sweep(int dtype_bytes, int tx, int ty, hipStream_t st, void* arena,
                         const BlockDev* blocks, const TileDev* tiles, int32_t ntiles, int parity,
                         unsigned long long* res, int32_t zero_lo, int32_t zero_hi,
@@ -139,6 +140,17 @@ bool sweep2_variant_ok(int dtype_bytes, int tx, int ty, bool flat = false);
 hipError_t launch_sweep2(int dtype_bytes, int tx, int ty, hipStream_t st, void* arena, const BlockDev* blocks,
                          const TileDev* tiles, const Tile2Dev* tiles2, int32_t ntiles, int parity,
                          unsigned long long* res, int32_t zero_lo, int32_t zero_hi, int hints);
+
+// Persistent form of a multi-resolution grid: `iters` iterations in one
+// cooperative launch, each the resolution-change ghost fill of the nseg
+// rectangles (from parity p), the per-XCD barrier, the sweep of every tile
+// (tiles from per-XCD-group counters; boundary x-columns exported through
+// xexp) and the barrier again; bar / err as launch_persistent.
+hipError_t launch_persistent_mr(int dtype_bytes, int tx, int ty, hipStream_t st, int grid, void* arena,
+                                const BlockDev* blocks, const TileDev* tiles, int32_t ntiles, int parity,
+                                int64_t iters, unsigned long long* res, int32_t nres, unsigned int* bar,
+                                unsigned int* err, int64_t wait_ticks, int hints, const FillSeg* segs, int32_t nseg,
+                                const XExpDev* xexp);
 
 // Persistent form of the two-step pass: `passes` passes (2 * passes steps)
 // in one cooperative launch of `grid` workgroups, the per-XCD barrier
@@ -194,7 +206,8 @@ int64_t device_wait_ticks(double seconds = 10.0);
 // Max co-resident workgroups of a cooperative kernel: kind 0 = persistent
 // with the static tile stride, 2 = persistent with tile counters (dyn),
 // 1 = message-driven, 3 / 4 = persistent two-step passes with the static
-// stride / with counters, 5 = message-driven two-step tasks; at most
+// stride / with counters, 5 = message-driven two-step tasks, 6 = persistent
+// multi-resolution (ghost fill and sweep per iteration); at most
 // max_waves waves per SIMD (0 = the default choice: 5 for kind 2, else as
 // many as the registers allow).
 int persistent_max_grid(int dtype_bytes, int tx, int ty, int kind, int max_waves = 0);

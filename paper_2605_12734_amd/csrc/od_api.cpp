@@ -376,8 +376,12 @@ std::string build_layout(const od_config& cfg, Grid& G) {
         return "imbalance_pct must be in [0,100] and imbalance_max_extra in [0,255]";
     if (!(cfg.wait_s >= 0.0) || cfg.wait_s > 3600.0) return "wait_s must be in [0, 3600] seconds";
     if (cfg.imbalance_pct > 0 && cfg.exec == OD_GRAPH) return "imbalance is not supported with OD_GRAPH";
-    if (p.multires && cfg.exec != OD_FUSED && cfg.exec != OD_GRAPH)
-        return "multi-resolution blocks are supported with OD_FUSED and OD_GRAPH";
+    if (p.multires && cfg.exec != OD_FUSED && cfg.exec != OD_GRAPH && cfg.exec != OD_PERSISTENT)
+        return "multi-resolution blocks are supported with OD_FUSED, OD_GRAPH and OD_PERSISTENT";
+    if (p.multires && cfg.exec == OD_PERSISTENT &&
+        ((cfg.hints & (kHintTimeline | 32 | 2048 | 8192)) || (cfg.imbalance_pct > 0 && cfg.imbalance_max_extra > 0)))
+        return "persistent multi-resolution grids take tiles from counters: no timeline, forced schedule or "
+               "imbalance";
     if (p.multires && cfg.stencil == 5) return "multi-resolution blocks need the 3D 7-point stencil";
     if (!p.regular) {
         // tile rows are loaded as 16-byte vectors: explicit blocks start on a
@@ -520,6 +524,15 @@ std::string build_layout(const od_config& cfg, Grid& G) {
     if (p.multires) {
         const int64_t reads = build_fill_segments(G);
         if (reads < 0) return "a block face borders cells more than 16 times finer (cell ratio across a face is limited to 16)";
+        // by decreasing cost (ghost cells times the source values each
+        // averages, plus its store): the persistent form deals rectangles to
+        // its waves with a fixed stride, so each gets a similar share
+        auto cost = [](const FillSeg& S) {
+            const int32_t rr = S.hc >> S.lhn, r = rr > 1 ? rr : 1;
+            return (int64_t)S.n1 * S.n2 * (r * r + 1);
+        };
+        std::stable_sort(G.segs_h.begin(), G.segs_h.end(),
+                         [&](const FillSeg& a, const FillSeg& b) { return cost(a) > cost(b); });
         // algorithmic ghost traffic: same-size faces read their neighbour
         // cells, resolution-change faces the neighbour cells their fill reads
         int64_t direct = 0;
@@ -1074,6 +1087,20 @@ od_status Grid::graph_run(int64_t n) {
 
 od_status Grid::persistent_run(int64_t n) {
     if (grid_wgs <= 0) return fail(OD_EHIP, "persistent kernel: no co-resident workgroups");
+    if (plan.multires) {
+        hipError_t e = launch_persistent_mr(s, plan.tile[0], plan.tile[1], st, grid_wgs, base,
+                                            reinterpret_cast<const BlockDev*>(cp(L.blocks)),
+                                            reinterpret_cast<const TileDev*>(cp(L.tiles)), (int32_t)tiles_h.size(),
+                                            parity, n, res_ptr(), 1, reinterpret_cast<unsigned int*>(cp(L.bar)),
+                                            reinterpret_cast<unsigned int*>(cp(L.err)),
+                                            device_wait_ticks(cfg.wait_s > 0 ? cfg.wait_s : 10.0), mode(),
+                                            reinterpret_cast<const FillSeg*>(cp(L.segs)), (int32_t)segs_h.size(),
+                                            xexp_dev());
+        if (e != hipSuccess) return fail(OD_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
+        parity ^= (int)(n & 1);
+        iters += n;
+        return OD_OK;
+    }
     if (two_step) {
         // n / 2 two-step passes in one launch, an odd last step as a single sweep
         const int64_t passes = n / 2;

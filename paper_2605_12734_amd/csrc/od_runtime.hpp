@@ -87,8 +87,9 @@ struct Grid {
     bool persistent_dyn() const { return sched() == 2 || sched() == 3; }
     // cooperative-kernel kind for persistent_max_grid
     int coop_kind() const {
-        return cfg.exec == OD_MSGDRIVEN ? (two_step ? 5 : 1)
-                                        : (two_step ? (persistent_dyn() ? 4 : 3) : (persistent_dyn() ? 2 : 0));
+        if (cfg.exec == OD_MSGDRIVEN) return two_step ? 5 : 1;
+        if (plan.multires) return 6;
+        return two_step ? (persistent_dyn() ? 4 : 3) : (persistent_dyn() ? 2 : 0);
     }
     std::vector<TileHost> base_tiles;   // the planner's tile list before schedule-specific cuts
     std::vector<MsgBufs> msg;

@@ -300,7 +300,9 @@ od_status autotune(Grid& G, int32_t iters, int32_t out_tile[3]) {
     // persistent schedules: fixed stride (1), counters (2), counters with a
     // guided tail (3), fixed runs (4); hints bits 4/5/11/13 fix the schedule
     std::vector<int32_t> scheds = {0};
-    if (pers) scheds = (G.cfg.hints & (48 | 2048 | 8192)) ? std::vector<int32_t>{0} : std::vector<int32_t>{1, 2, 3, 4};
+    // (multi-resolution grids always take tiles from counters)
+    if (pers) scheds = (G.cfg.hints & (48 | 2048 | 8192)) || G.plan.multires ? std::vector<int32_t>{0}
+                                                                            : std::vector<int32_t>{1, 2, 3, 4};
     // persistent candidates run real launches of 2 * iters iterations (the
     // barriers and counter resets are part of what is timed), so the grid's
     // state is saved first and restored after the search

@@ -67,16 +67,37 @@ def _ratio_8_octree():
 
 @pytest.mark.parametrize("layout", [_two_level, _three_level, _octree, _ratio_16, _ratio_8_octree])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("exec_", ["fused", "graph"])
+@pytest.mark.parametrize("exec_", ["fused", "graph", "persistent"])
 def test_multires_matches_oracle(layout, dtype, exec_):
     n, blocks, cell = layout()
     _compare(n, blocks, cell, dtype, exec_, 7)
 
 
 @pytest.mark.parametrize("tile", [(16, 8, 8), (32, 4, 16), (64, 8, 32)])
-def test_multires_tile_shapes(tile):
+@pytest.mark.parametrize("exec_", ["fused", "persistent"])
+def test_multires_tile_shapes(tile, exec_):
     n, blocks, cell = _three_level()
-    _compare(n, blocks, cell, "f64", "fused", 5, tile=tile)
+    _compare(n, blocks, cell, "f64", exec_, 5, tile=tile)
+
+
+def test_multires_persistent_resume_and_autotune():
+    # one cooperative launch per call (fill, barrier, sweep, barrier per
+    # iteration): calls of 1, 4 and 6 iterations on an autotuned grid
+    n, blocks, cell = _octree(n=128, root=64, min_edge=16, seed=7)
+    want = oracle.MLGrid(n, blocks, cell, np.float64, seed=12734)
+    r_want = want.jacobi(11)
+    g = od.Grid(n, blocks=blocks, cell=cell, dtype="f64", exec="persistent", hints=1)
+    try:
+        g.autotune(2)
+        for k in (1, 4, 6):
+            g.iterate(k)
+        r = g.residual()
+        assert g.iterations() == 11
+        for b in range(len(blocks)):
+            assert np.array_equal(g.read_block(b), want.interior(b)), b
+    finally:
+        g.close()
+    assert r == r_want
 
 
 def test_multires_bc_and_constant_field():
@@ -111,6 +132,7 @@ def test_multires_768_octree_full_size():
     tile = g.autotune(2)
     g.close()
     _compare(n, blocks, cell, "f64", "graph", 20, tile=tile)
+    _compare(n, blocks, cell, "f64", "persistent", 20, tile=tile)
 
 
 def test_global_io_refused_for_multires():

@@ -86,7 +86,7 @@ def test_unit_cells_plan_unchanged():
     ([((0, 0, 0), (16, 16, 16)), ((16, 0, 0), (16, 4, 16)), ((16, 4, 0), (16, 12, 16))], [8, 2, 2], "fused"),
     ([((0, 0, 0), (16, 16, 16)), ((16, 0, 0), (16, 16, 16))], [3, 1], "fused"),          # not a power of two
     ([((0, 0, 0), (16, 16, 16)), ((16, 0, 0), (16, 16, 16))], [2, 1], "msgdriven"),
-    ([((0, 0, 0), (16, 16, 16)), ((16, 0, 0), (16, 16, 16))], [2, 1], "persistent"),
+    ([((0, 0, 0), (16, 16, 16)), ((16, 0, 0), (16, 16, 16))], [2, 1], "per_chare"),
     ([((0, 0, 0), (12, 16, 16)), ((12, 0, 0), (20, 16, 16))], [8, 1], "fused"),          # origin not a multiple
     ([((0, 0, 0), (32, 32, 32)), ((32, 0, 0), (32, 32, 32))], [32, 1], "fused"),          # cell ratio 32 > 16
 ])
@@ -101,3 +101,19 @@ def test_cell_ratio_16_accepted():
     blocks = [((0, 0, 0), (32, 32, 32)), ((32, 0, 0), (32, 32, 32))]
     p = od.host_plan(n=(64, 32, 32), blocks=blocks, cell=[16, 1], dtype="f64", exec="fused")
     assert p["interior"] == 8 + 32 ** 3
+
+
+@pytest.mark.parametrize("kw,ok", [({}, True), ({"hints": 16}, True), ({"hints": 8}, False), ({"hints": 32}, False),
+                                   ({"hints": 2048}, False), ({"hints": 8192}, False),
+                                   ({"imbalance_pct": 10, "imbalance_max_extra": 2}, False)])
+def test_multires_persistent_forms(kw, ok):
+    # the persistent form of a multi-resolution grid fills and sweeps in one
+    # launch, taking tiles from counters: schedules that fix the tile order,
+    # the timeline and imbalance are refused; one step per pass
+    n, blocks, cell = _layouts()[0]
+    if ok:
+        p = od.host_plan(n=n, blocks=blocks, cell=cell, dtype="f64", exec="persistent", **kw)
+        assert p["steps_per_pass"] == 1
+    else:
+        with pytest.raises(od.ODError):
+            od.host_plan(n=n, blocks=blocks, cell=cell, dtype="f64", exec="persistent", **kw)
