@@ -2217,7 +2217,7 @@ constexpr int kLdsPerCu = 160 * 1024, kLdsGranule = 1280;
 // Co-resident workgroups per CU of a cooperative kernel: the occupancy
 // query `per` (exact for VGPRs), limited by the kernel's LDS in whole
 // granules and by what its scalar registers allow (both from what the
-// compiler recorded for this build; a kernel missing from the record is
+// compiler recorded when the library was compiled; a kernel missing from the record is
 // taken as 5 waves per SIMD), and by `max_waves` waves per SIMD (a
 // scheduling choice).  A cooperative grid larger than what is resident
 // would never complete its first device-wide barrier.

@@ -188,8 +188,8 @@ hipError_t launch_persistent(int dtype_bytes, int tx, int ty, hipStream_t st, in
 hipError_t launch_stamp_init(hipStream_t st, unsigned long long* stamps, int32_t n);
 // hints bit 3 (persistent form): record the timeline above.
 constexpr int kHintTimeline = 8;
-// Register usage of a kernel of this build (demangled name without the
-// return type and parameters); false if the build recorded none.
+// Register usage of a kernel of the compiled library (demangled name without the
+// return type and parameters); false if the compile recorded none.
 bool kernel_resources(const char* name, int* sgprs, int* vgprs, int* lds);
 // Waves per SIMD that a kernel's scalar registers allow on gfx950: residency
 // probes (256-thread workgroups holding their CU) held 8 waves at 78 SGPRs,
