@@ -1803,9 +1803,12 @@ __device__ __forceinline__ void serve_loop(const MsgArgs& a, SweepFn sweep, doub
 // compiler's choice).  The plain-grid kernel asks for 6: the compiler then
 // fits 80 VGPRs with a few spills instead of taking 93-97 (5 or 4 waves),
 // and the extra wave per SIMD measured 2 % faster (512^3 fp64 ODF 4096,
-// 277 -> 283 GLUP/s).
+// 277 -> 283 GLUP/s; measured again with the current scheduler: 270 at 5
+// waves, 290 at 6).  The serving kernel asks for 5: on its own it took 116 VGPRs and
+// 4 waves; at 5 (96 VGPRs, no scratch) a saturated stream of 64 mixed
+// requests ran 228.6 -> 236 GLUP/s (p50 4.28 -> 4.15 s at 1000 requests/s).
 #ifndef OD_SCHED_WAVES
-#define OD_SCHED_WAVES 0
+#define OD_SCHED_WAVES 5
 #endif
 #ifndef OD_MSG_WAVES
 #define OD_MSG_WAVES 6
