@@ -181,7 +181,7 @@ def test_bytes_per_pass_counts_two_step_reach():
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("exec_", ["fused", "graph", "persistent"])
+@pytest.mark.parametrize("exec_", ["fused", "graph", "persistent", "msgdriven"])
 @pytest.mark.parametrize("tile", [(16, 16, 8), (32, 16, 16), (32, 32, 32)])
 def test_uneven_octree_pairs(dtype, exec_, tile):
     # explicit blocks at one resolution: tiles are cut until every line of

@@ -383,3 +383,14 @@ def test_msgdriven_deps_reach_brute_force(n, odf, tile, hints, spp):
     plan = od.host_plan(n=n, odf=odf, dtype="f64", exec="msgdriven", tile=tile, hints=hints)
     assert plan["steps_per_pass"] == spp
     assert plan["deps"] == _deps_brute(plan, n, spp)
+
+
+@pytest.mark.parametrize("tile", [(16, 16, 8), (32, 16, 16)])
+def test_msgdriven_deps_reach_brute_force_octree(tile):
+    # explicit blocks at one resolution: the tiles are also cut so every
+    # line a pair reads lies in one block; the dependency lists still equal
+    # the tiles within two cells (L1) of each tile
+    blocks = workloads.octree_blocks(n=96, root=32, min_edge=8, p_refine=0.45, seed=11)
+    plan = od.host_plan(n=(96, 96, 96), blocks=blocks, dtype="f64", exec="msgdriven", tile=tile)
+    assert plan["steps_per_pass"] == 2
+    assert plan["deps"] == _deps_brute(plan, (96, 96, 96), 2)
