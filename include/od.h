@@ -144,8 +144,9 @@ typedef struct {
      * counters are the default;
      * bit 12 (OD_FUSED, OD_GRAPH, OD_PERSISTENT, OD_MSGDRIVEN): one step
      * per pass.  By default these forms run iterations in pairs where they
-     * can (blocks at one resolution, no imbalance, a tile shape with a
-     * two-step variant; OD_PERSISTENT with the 3D stencil, the
+     * can (blocks at one resolution, a tile shape with a two-step variant,
+     * under load imbalance the 3D stencil: a heavy chare's re-runs are
+     * one-step sweeps before its pass; OD_PERSISTENT with the 3D stencil, the
      * fixed-stride or counter schedule, with or without the guided tail,
      * and no timeline; OD_MSGDRIVEN with the 3D stencil, each task then a
      * pass of its tile, waiting for the tiles within two cells): one pass

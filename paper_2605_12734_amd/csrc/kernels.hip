@@ -938,18 +938,39 @@ k_persistent(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const T
     persist_cleanup(bar);
 }
 
-// Persistent form of the two-step pass (uniform work: blocks at one
-// resolution, no imbalance): `passes` passes of two steps each in one
-// cooperative launch, the same per-XCD barrier between passes as
-// k_persistent.  Workgroup w sweeps tiles w, w + G, ... of its XCD group,
-// or with DYN takes them one at a time from the group's counter as each
-// tile ends (next_tile).
-template <typename T, int TX, int TY, bool DYN>
+// Load imbalance in a two-step pass.  A chare drawn heavy at either step
+// of the pass re-runs its work extra(t) + extra(t + 1) times before the
+// pass: single sweeps from the pass's source parity into its own cells of
+// the other parity, the region the pass then overwrites.  Nothing reads
+// that region before the pass ends (the pass reads only its source
+// parity), so the result is the pair's, and each extra costs one one-step
+// sweep, as the re-runs of one-step sweeps do.  The one-step tile needs
+// fewer LDS values than the two-step tile with the same threads.
+template <typename T, int TX, int TY>
+__device__ __forceinline__ void imb_extra_sweeps(T* __restrict__ arena, const BlockDev* __restrict__ blocks,
+                                                 const TileDev& t, int parity, T* lds, const ImbDev& imb,
+                                                 int64_t step, int hints) {
+    static_assert(SW<T, TX, TY>::LDS <= SW2<T, TX, TY>::LDS && SW<T, TX, TY>::NT == SW2<T, TX, TY>::NT,
+                  "the one-step tile runs in the two-step tile's workgroup");
+    const int extra = imb_extra(imb, step, t.blk) + imb_extra(imb, step + 1, t.blk);
+    for (int e = 0; e < extra; ++e) (void)sweep_tile<T, TX, TY>(arena, blocks, t, parity, lds, hints);
+}
+
+// Persistent form of the two-step pass (blocks at one resolution):
+// `passes` passes of two steps each in one cooperative launch, the same
+// per-XCD barrier between passes as k_persistent.  Workgroup w sweeps
+// tiles w, w + G, ... of its XCD group, or with DYN takes them one at a
+// time from the group's counter as each tile ends (next_tile).  With IMB,
+// pass k covers steps iter_base + 2k and iter_base + 2k + 1 of the
+// imbalance draw imb (a variant of its own: without it the uniform pass
+// keeps its register allocation; the extra sweep's code raised its spill
+// from 44 to 60 bytes per lane in fp64).
+template <typename T, int TX, int TY, bool DYN, bool IMB>
 __global__ void __launch_bounds__((TX / V16<T>::N) * TY) __attribute__((amdgpu_waves_per_eu(6, 8)))
 k_persistent2(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDev* __restrict__ tiles,
               const Tile2Dev* __restrict__ tiles2, int32_t ntiles, int parity, int64_t passes,
               unsigned long long* __restrict__ res, int32_t nres, unsigned int* bar, unsigned int* err,
-              int64_t wait_ticks, int hints) {
+              int64_t wait_ticks, int hints, const ImbDev imb, int64_t iter_base) {
     using S = SW2<T, TX, TY>;
     __shared__ __align__(16) T lds[S::LDS];
     __shared__ T red[S::NT / 64];
@@ -977,6 +998,8 @@ k_persistent2(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const 
             const int32_t ti = xg + ng * idx;
             if (ti >= ntiles) break;
             const TileDev& t = tiles[ti];
+            if (IMB && t.nz > 0)
+                imb_extra_sweeps<T, TX, TY>(arena, blocks, t, p, lds, imb, iter_base + 2 * it, hints);
             const T rr = t.nz > 0 ? sweep2_tile<T, TX, TY>(arena, blocks, t, tiles2[ti], p, lds, hints) : (T)0;
             if (slot >= 0 && slot != t.rslot) {
                 wg_residual<T, S::NT>(r, &res[2 * slot + (p ^ 1)], red);
@@ -993,6 +1016,26 @@ k_persistent2(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const 
         }
     }
     persist_cleanup(bar);
+}
+
+// Fused two-step pass under load imbalance: k_sweep2 with each heavy
+// chare's extra sweeps first (imb_extra_sweeps; the pass covers steps
+// `step` and step + 1 of the draw).  A kernel of its own, so the pass of
+// uniform work keeps its code.
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__((TX / V16<T>::N) * TY)
+k_sweep2_imb(T* __restrict__ arena, const BlockDev* __restrict__ blocks, const TileDev* __restrict__ tiles,
+             const Tile2Dev* __restrict__ tiles2, int parity, unsigned long long* __restrict__ res, int zero_lo,
+             int zero_hi, int hints, const ImbDev imb, int64_t step) {
+    using S = SW2<T, TX, TY>;
+    __shared__ __align__(16) T lds[S::LDS];
+    __shared__ T red[S::NT / 64];
+    if (blockIdx.x == 0)
+        for (int s = zero_lo + (int)threadIdx.x; s < zero_hi; s += S::NT) res[2 * s + parity] = 0ull;
+    const TileDev& t = tiles[blockIdx.x];
+    imb_extra_sweeps<T, TX, TY>(arena, blocks, t, parity, lds, imb, step, hints);
+    const T r = sweep2_tile<T, TX, TY>(arena, blocks, t, tiles2[blockIdx.x], parity, lds, hints);
+    wg_residual<T, S::NT>(r, &res[2 * t.rslot + (parity ^ 1)], red);
 }
 
 // Resolution-change ghost fill: one single-wave workgroup per rectangle.
@@ -1832,7 +1875,7 @@ __global__ void __launch_bounds__((TX / V16<T>::N) * TY) OD_MSG_OCC k_msgdriven(
     T* arena = reinterpret_cast<T*>(a.arena);
     auto sweep = [&](int32_t gid, int32_t step) -> double {
         const TileDev& t = a.tiles[gid];
-        const int reps = 1 + imb_extra(a.imb, step, t.blk);
+        const int reps = 1 + imb_extra(a.imb, a.imb_base + step, t.blk);
         T r = 0;
         for (int rep = 0; rep < reps; ++rep) r = sweep_tile<T, TX, TY>(arena, a.blocks, t, step & 1, lds, a.hints);
         return (double)r;
@@ -1840,8 +1883,10 @@ __global__ void __launch_bounds__((TX / V16<T>::N) * TY) OD_MSG_OCC k_msgdriven(
     queue_loop<S::NT>(a, sweep, red);
 }
 
-// Message-driven tasks of two steps (grids at one resolution without
-// imbalance): the same scheduler, each task one two-step pass of its tile.
+// Message-driven tasks of two steps (grids at one resolution): the same
+// scheduler, each task one two-step pass of its tile (with IMB, scheduler
+// step k covers steps imb_base + 2k and imb_base + 2k + 1 of the
+// imbalance draw, as in k_persistent2).
 // A scheduler step is a pass (the field's parity flips once per step), and
 // the dependency lists reach every tile within two cells (face slabs two
 // deep and the edge lines), so a tile still runs step k once everything it
@@ -1856,7 +1901,7 @@ struct Msg2Waves {
     static constexpr int value = sizeof(T) == 8 ? 5 : 4;
 };
 
-template <typename T, int TX, int TY>
+template <typename T, int TX, int TY, bool IMB>
 __global__ void __launch_bounds__((TX / V16<T>::N) * TY) __attribute__((amdgpu_waves_per_eu(Msg2Waves<T>::value, 8)))
 k_msgdriven2(MsgArgs a) {
     using S = SW2<T, TX, TY>;
@@ -1864,7 +1909,11 @@ k_msgdriven2(MsgArgs a) {
     __shared__ double red[S::NT / 64];
     T* arena = reinterpret_cast<T*>(a.arena);
     auto sweep = [&](int32_t gid, int32_t step) -> double {
-        return (double)sweep2_tile<T, TX, TY>(arena, a.blocks, a.tiles[gid], a.tiles2[gid], step & 1, lds, a.hints);
+        const TileDev& t = a.tiles[gid];
+        if (IMB)
+            imb_extra_sweeps<T, TX, TY>(arena, a.blocks, t, step & 1, lds, a.imb, a.imb_base + 2 * (int64_t)step,
+                                        a.hints);
+        return (double)sweep2_tile<T, TX, TY>(arena, a.blocks, t, a.tiles2[gid], step & 1, lds, a.hints);
     };
     queue_loop<S::NT>(a, sweep, red);
 }
@@ -2175,9 +2224,11 @@ bool sweep2_variant_ok(int dtype_bytes, int tx, int ty, bool flat) {
 
 hipError_t launch_sweep2(int dtype_bytes, int tx, int ty, hipStream_t st, void* arena, const BlockDev* blocks,
                          const TileDev* tiles, const Tile2Dev* tiles2, int32_t ntiles, int parity,
-                         unsigned long long* res, int32_t zero_lo, int32_t zero_hi, int hints) {
+                         unsigned long long* res, int32_t zero_lo, int32_t zero_hi, int hints, const ImbDev& imb,
+                         int64_t step) {
     if (ntiles <= 0) return hipSuccess;
     if (hints & 0x100) {   // the 2D 5-point stencil
+        if (imb.heavy > 0) return hipErrorInvalidValue;
 #define OD_LAUNCH2D(T, TX)                                                                               \
         if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == 1) {                                      \
             hipLaunchKernelGGL((k_sweep2d<T, TX>), dim3(ntiles), dim3(SW2D<T, TX>::NT), 0, st,           \
@@ -2191,9 +2242,14 @@ hipError_t launch_sweep2(int dtype_bytes, int tx, int ty, hipStream_t st, void* 
     }
 #define OD_LAUNCH2(T, TX, TY)                                                                            \
     if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                         \
-        hipLaunchKernelGGL((k_sweep2<T, TX, TY>), dim3(ntiles), dim3(SW2<T, TX, TY>::NT), 0, st,        \
-                           reinterpret_cast<T*>(arena), blocks, tiles, tiles2, parity, res, zero_lo, zero_hi, \
-                           hints);                                                                       \
+        if (imb.heavy > 0)                                                                               \
+            hipLaunchKernelGGL((k_sweep2_imb<T, TX, TY>), dim3(ntiles), dim3(SW2<T, TX, TY>::NT), 0, st, \
+                               reinterpret_cast<T*>(arena), blocks, tiles, tiles2, parity, res, zero_lo,  \
+                               zero_hi, hints, imb, step);                                               \
+        else                                                                                             \
+            hipLaunchKernelGGL((k_sweep2<T, TX, TY>), dim3(ntiles), dim3(SW2<T, TX, TY>::NT), 0, st,    \
+                               reinterpret_cast<T*>(arena), blocks, tiles, tiles2, parity, res, zero_lo,  \
+                               zero_hi, hints);                                                          \
         return hipGetLastError();                                                                        \
     }
     OD_VARIANTS2_F64(OD_LAUNCH2)
@@ -2243,18 +2299,36 @@ static std::string kernel_name(const char* base, int dtype_bytes, int tx, int ty
            ", " + std::to_string(ty) + (extra ? extra : "") + ">";
 }
 
-static std::string coop_name(int dtype_bytes, int tx, int ty, int kind) {
+// imb: the load-imbalance variant of a two-step kernel (kinds 3 - 5)
+static std::string coop_name(int dtype_bytes, int tx, int ty, int kind, bool imb = false) {
+    const char* i2 = imb ? ", true" : ", false";
     return kind == 1   ? kernel_name("k_msgdriven", dtype_bytes, tx, ty, nullptr)
-           : kind == 5 ? kernel_name("k_msgdriven2", dtype_bytes, tx, ty, nullptr)
+           : kind == 5 ? kernel_name("k_msgdriven2", dtype_bytes, tx, ty, i2)
            : kind == 6 ? kernel_name("k_persistent_mr", dtype_bytes, tx, ty, nullptr)
-           : kind >= 3 ? kernel_name("k_persistent2", dtype_bytes, tx, ty, kind == 4 ? ", true" : ", false")
+           : kind >= 3 ? kernel_name("k_persistent2", dtype_bytes, tx, ty,
+                                     (std::string(kind == 4 ? ", true" : ", false") + i2).c_str())
                        : kernel_name("k_persistent", dtype_bytes, tx, ty, kind == 2 ? ", true" : ", false");
 }
 
-int coop_waves_limit(int dtype_bytes, int tx, int ty, int kind) {
-    const std::string name = coop_name(dtype_bytes, tx, ty, kind);
+static int sgpr_waves(const std::string& name) {
     int sg = 0;
     return kernel_resources(name.c_str(), &sg, nullptr, nullptr) ? waves_by_sgprs(sg) : 5;
+}
+
+// two-step kinds: the smaller of the uniform and imbalance variants, so a
+// grid sized for the kind fits either
+int coop_waves_limit(int dtype_bytes, int tx, int ty, int kind) {
+    const int w = sgpr_waves(coop_name(dtype_bytes, tx, ty, kind));
+    if (kind < 3 || kind > 5) return w;
+    const int wi = sgpr_waves(coop_name(dtype_bytes, tx, ty, kind, true));
+    return wi < w ? wi : w;
+}
+
+template <typename K>
+static int coop_cap(K kernel, int threads, const std::string& name, int max_waves) {
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess) return 0;
+    return coop_per_cu(per, threads, name.c_str(), max_waves);
 }
 
 int persistent_max_grid(int dtype_bytes, int tx, int ty, int kind, int max_waves) {
@@ -2266,18 +2340,18 @@ int persistent_max_grid(int dtype_bytes, int tx, int ty, int kind, int max_waves
     if (max_waves <= 0) max_waves = kind == 2 ? 5 : 8;
     const std::string name = coop_name(dtype_bytes, tx, ty, kind);
     if (kind >= 3 && kind <= 5) {
+        // the uniform and the load-imbalance variant: the smaller residency
+        const std::string name_i = coop_name(dtype_bytes, tx, ty, kind, true);
 #define OD_OCC2(T, TX, TY)                                                                            \
         if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                  \
-            const hipError_t e = kind == 5                                                            \
-                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_msgdriven2<T, TX, TY>,         \
-                                                               SW2<T, TX, TY>::NT, 0)                 \
-                : kind == 4                                                                           \
-                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent2<T, TX, TY, true>,  \
-                                                               SW2<T, TX, TY>::NT, 0)                 \
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persistent2<T, TX, TY, false>, \
-                                                               SW2<T, TX, TY>::NT, 0);                \
-            if (e != hipSuccess) return 0;                                                            \
-            return coop_per_cu(per, SW2<T, TX, TY>::NT, name.c_str(), max_waves) * ncu;              \
+            constexpr int NT = SW2<T, TX, TY>::NT;                                                    \
+            const int c0 = kind == 5 ? coop_cap(k_msgdriven2<T, TX, TY, false>, NT, name, max_waves)  \
+                           : kind == 4 ? coop_cap(k_persistent2<T, TX, TY, true, false>, NT, name, max_waves) \
+                           : coop_cap(k_persistent2<T, TX, TY, false, false>, NT, name, max_waves);   \
+            const int c1 = kind == 5 ? coop_cap(k_msgdriven2<T, TX, TY, true>, NT, name_i, max_waves) \
+                           : kind == 4 ? coop_cap(k_persistent2<T, TX, TY, true, true>, NT, name_i, max_waves) \
+                           : coop_cap(k_persistent2<T, TX, TY, false, true>, NT, name_i, max_waves);  \
+            return (c1 < c0 ? c1 : c0) * ncu;                                                         \
         }
         OD_VARIANTS2_F64(OD_OCC2)
         OD_VARIANTS2_F32(OD_OCC2)
@@ -2351,15 +2425,20 @@ hipError_t launch_persistent_mr(int dtype_bytes, int tx, int ty, hipStream_t st,
 hipError_t launch_persistent2(int dtype_bytes, int tx, int ty, hipStream_t st, int grid, void* arena,
                               const BlockDev* blocks, const TileDev* tiles, const Tile2Dev* tiles2, int32_t ntiles,
                               int parity, int64_t passes, unsigned long long* res, int32_t nres, unsigned int* bar,
-                              unsigned int* err, int hints, int64_t wait_ticks, int dyn) {
+                              unsigned int* err, int hints, int64_t wait_ticks, int dyn, const ImbDev& imb,
+                              int64_t iter_base) {
     if (passes <= 0) return hipSuccess;
+    ImbDev im = imb;
 #define OD_LAUNCH2(T, TX, TY)                                                                         \
     if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                      \
         T* ar = reinterpret_cast<T*>(arena);                                                          \
         void* args[] = {&ar, &blocks, &tiles, &tiles2, &ntiles, &parity, &passes, &res, &nres, &bar,  \
-                        &err, &wait_ticks, &hints};                                                   \
-        const void* fn = dyn ? reinterpret_cast<const void*>(k_persistent2<T, TX, TY, true>)          \
-                             : reinterpret_cast<const void*>(k_persistent2<T, TX, TY, false>);        \
+                        &err, &wait_ticks, &hints, &im, &iter_base};                                  \
+        const void* fn = imb.heavy > 0                                                                \
+            ? (dyn ? reinterpret_cast<const void*>(k_persistent2<T, TX, TY, true, true>)              \
+                   : reinterpret_cast<const void*>(k_persistent2<T, TX, TY, false, true>))            \
+            : (dyn ? reinterpret_cast<const void*>(k_persistent2<T, TX, TY, true, false>)             \
+                   : reinterpret_cast<const void*>(k_persistent2<T, TX, TY, false, false>));          \
         return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(SW2<T, TX, TY>::NT), args, 0, st);     \
     }
     OD_VARIANTS2_F64(OD_LAUNCH2)
@@ -2408,8 +2487,9 @@ hipError_t launch_msgdriven2(int dtype_bytes, int tx, int ty, hipStream_t st, in
 #define OD_LAUNCH2(T, TX, TY)                                                                         \
     if (dtype_bytes == (int)sizeof(T) && tx == TX && ty == TY) {                                      \
         void* args[] = {&ac};                                                                         \
-        return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_msgdriven2<T, TX, TY>),    \
-                                          dim3(grid), dim3(SW2<T, TX, TY>::NT), args, 0, st);         \
+        const void* fn = a.imb.heavy > 0 ? reinterpret_cast<const void*>(k_msgdriven2<T, TX, TY, true>) \
+                                         : reinterpret_cast<const void*>(k_msgdriven2<T, TX, TY, false>); \
+        return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(SW2<T, TX, TY>::NT), args, 0, st);     \
     }
     OD_VARIANTS2_F64(OD_LAUNCH2)
     OD_VARIANTS2_F32(OD_LAUNCH2)

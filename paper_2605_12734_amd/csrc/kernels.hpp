@@ -136,10 +136,13 @@ static_assert(sizeof(Tile2Dev) == 304, "Tile2Dev layout");
 bool sweep2_variant_ok(int dtype_bytes, int tx, int ty, bool flat = false);
 // Reads parity `parity`, writes the field two steps later into parity^1;
 // the residual (of the second step) and res zeroing as launch_sweep.
-// hints bit 8 (the 2D stencil) selects the row kernel.
+// hints bit 8 (the 2D stencil) selects the row kernel (no imbalance).
+// imb.heavy > 0: chares drawn heavy at step `step` or step + 1 first re-run
+// their sweep the drawn number of extra times (the result is unchanged).
 hipError_t launch_sweep2(int dtype_bytes, int tx, int ty, hipStream_t st, void* arena, const BlockDev* blocks,
                          const TileDev* tiles, const Tile2Dev* tiles2, int32_t ntiles, int parity,
-                         unsigned long long* res, int32_t zero_lo, int32_t zero_hi, int hints);
+                         unsigned long long* res, int32_t zero_lo, int32_t zero_hi, int hints, const ImbDev& imb,
+                         int64_t step);
 
 // Persistent form of a multi-resolution grid: `iters` iterations in one
 // cooperative launch, each the resolution-change ghost fill of the nseg
@@ -155,11 +158,13 @@ hipError_t launch_persistent_mr(int dtype_bytes, int tx, int ty, hipStream_t st,
 // Persistent form of the two-step pass: `passes` passes (2 * passes steps)
 // in one cooperative launch of `grid` workgroups, the per-XCD barrier
 // between passes; dyn != 0: tiles from per-XCD-group counters, else the
-// fixed stride; bar / err as launch_persistent.
+// fixed stride; bar / err as launch_persistent; pass k covers steps
+// iter_base + 2k and iter_base + 2k + 1 of the imbalance draw imb.
 hipError_t launch_persistent2(int dtype_bytes, int tx, int ty, hipStream_t st, int grid, void* arena,
                               const BlockDev* blocks, const TileDev* tiles, const Tile2Dev* tiles2, int32_t ntiles,
                               int parity, int64_t passes, unsigned long long* res, int32_t nres, unsigned int* bar,
-                              unsigned int* err, int hints, int64_t wait_ticks, int dyn);
+                              unsigned int* err, int hints, int64_t wait_ticks, int dyn, const ImbDev& imb,
+                              int64_t iter_base);
 
 // Persistent cooperative sweep: all `iters` iterations in one launch with a
 // device-wide barrier between them.  dyn != 0: workgroups take tiles from
@@ -233,6 +238,9 @@ struct MsgArgs {
     unsigned long long* res;    // plain grid: 2 slots (step parity); serving: 1 slot per solve
     unsigned int* err;
     ImbDev imb;                 // load-imbalance draw (heavy == 0: none)
+    // plain grids: scheduler step k draws the imbalance of step imb_base + k
+    // (one-step tasks) or imb_base + 2k and + 2k + 1 (two-step tasks)
+    int64_t imb_base;
     int64_t wait_ticks;         // bound on every device-side wait (wall-clock ticks)
     int32_t hints;              // od_config.hints (bit 2: schedule check, see kHintCheck)
     // plain grids: scheduler choice, bits 0-1 claim mode (0 = automatic,

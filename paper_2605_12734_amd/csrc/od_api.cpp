@@ -165,12 +165,12 @@ namespace {
 
 // Pairs of iterations in one pass need blocks at one resolution (every
 // line of cells around a tile in one block: so in a regular decomposition;
-// explicit blocks have their tiles split until it holds), no imbalance (a
-// re-run chare would have to repeat both steps), and a tile shape with a
-// two-step variant (3D tiles, or the 2D stencil's row tiles);
-// the persistent form also the 3D stencil, the fixed-stride or counter
+// explicit blocks have their tiles split until it holds) and a tile shape
+// with a two-step variant (3D tiles, or the 2D stencil's row tiles); the
+// persistent form also the 3D stencil, the fixed-stride or counter
 // schedule (with or without the guided tail) and no timeline; the
-// message-driven form the 3D stencil.
+// message-driven form the 3D stencil.  Under load imbalance a heavy
+// chare's extra runs are one-step sweeps before its pass (3D stencil only).
 bool two_step_possible(const Grid& G) {
     const od_config& cfg = G.cfg;
     const Plan& p = G.plan;
@@ -178,7 +178,7 @@ bool two_step_possible(const Grid& G) {
                       (cfg.exec == OD_PERSISTENT && cfg.stencil != 5 && G.sched() >= 1 && G.sched() <= 3 &&
                        !(cfg.hints & kHintTimeline)) ||
                       (cfg.exec == OD_MSGDRIVEN && cfg.stencil != 5);
-    return form && !(cfg.hints & 4096) && !p.multires && G.imb.heavy == 0;
+    return form && !(cfg.hints & 4096) && !p.multires && (G.imb.heavy == 0 || cfg.stencil != 5);
 }
 
 // Room for two-step descriptors: the forms that can pair steps under any
@@ -190,7 +190,7 @@ bool two_step_room(const Grid& G) {
                       (cfg.exec == OD_PERSISTENT && cfg.stencil != 5 && !(cfg.hints & (kHintTimeline | 2048))) ||
                       (cfg.exec == OD_MSGDRIVEN && cfg.stencil != 5);
     const bool imbalance = cfg.imbalance_pct > 0 && cfg.imbalance_max_extra > 0;
-    return form && !(cfg.hints & 4096) && !p.multires && !imbalance;
+    return form && !(cfg.hints & 4096) && !p.multires && (!imbalance || cfg.stencil != 5);
 }
 
 // Block and local coordinates of global cell (x, y, z) as a FaceDev: its
@@ -1021,11 +1021,11 @@ od_status Grid::fused_one(hipStream_t s2, int par, int64_t step) {
     return OD_OK;
 }
 
-od_status Grid::fused_two(hipStream_t s2, int par) {
+od_status Grid::fused_two(hipStream_t s2, int par, int64_t step) {
     hipError_t e = launch_sweep2(s, plan.tile[0], plan.tile[1], s2, base, reinterpret_cast<const BlockDev*>(cp(L.blocks)),
                                  reinterpret_cast<const TileDev*>(cp(L.tiles)),
                                  reinterpret_cast<const Tile2Dev*>(cp(L.tiles2)), (int32_t)tiles_h.size(), par,
-                                 res_ptr(), 0, 1, mode());
+                                 res_ptr(), 0, 1, mode(), imb, step);
     if (e != hipSuccess) return fail(OD_EHIP, std::string("two-step sweep launch: ") + hipGetErrorString(e));
     return OD_OK;
 }
@@ -1057,7 +1057,7 @@ od_status Grid::graph_run(int64_t n) {
             int par = parity;
             for (int64_t i = 0; i < m && os == OD_OK; par ^= 1) {
                 if (two_step && m - i >= 2) {
-                    os = fused_two(cap_st, par);
+                    os = fused_two(cap_st, par, iters + i);
                     i += 2;
                 } else {
                     os = fused_one(cap_st, par, iters + i);
@@ -1111,7 +1111,7 @@ od_status Grid::persistent_run(int64_t n) {
                                           parity, passes, res_ptr(), 1, reinterpret_cast<unsigned int*>(cp(L.bar)),
                                           reinterpret_cast<unsigned int*>(cp(L.err)), mode(),
                                           device_wait_ticks(cfg.wait_s > 0 ? cfg.wait_s : 10.0),
-                                          persistent_dyn() ? 1 : 0);
+                                          persistent_dyn() ? 1 : 0, imb, iters);
         if (e != hipSuccess) return fail(OD_EHIP, std::string("persistent launch: ") + hipGetErrorString(e));
         parity ^= (int)(passes & 1);
         iters += 2 * passes;
@@ -1183,6 +1183,9 @@ od_status Grid::msgdriven_launch(int64_t n, bool pairs) {
     a.res = res_ptr() + 2;   // slot (final step & 1) of this 2-slot pair
     a.err = reinterpret_cast<unsigned int*>(cp(L.err));
     a.imb = imb;
+    // scheduler step k of this launch is iteration iters + (k - flips) per
+    // step of a one-step task, two per two-step task
+    a.imb_base = pairs ? iters - 2 * flips : iters - flips;
     a.wait_ticks = device_wait_ticks(cfg.wait_s > 0 ? cfg.wait_s : 10.0);
     a.hints = mode();
     a.seed = cfg.seed;
@@ -1313,7 +1316,7 @@ od_status Grid::iterate(int64_t n) {
             msg_final = false;
             for (int64_t i = 0; i < n;) {
                 const int k = two_step && n - i >= 2 ? 2 : 1;
-                od_status os = k == 2 ? fused_two(st, parity) : fused_one(st, parity, iters);
+                od_status os = k == 2 ? fused_two(st, parity, iters) : fused_one(st, parity, iters);
                 if (os != OD_OK) return os;
                 parity ^= 1;
                 iters += k;

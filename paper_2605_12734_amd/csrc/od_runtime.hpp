@@ -153,7 +153,7 @@ struct Grid {
     od_status ensure_pinned(size_t bytes);
     unsigned long long* res_ptr();
     od_status fused_one(hipStream_t s2, int par, int64_t step);
-    od_status fused_two(hipStream_t s2, int par);   // two steps, parity par -> par ^ 1
+    od_status fused_two(hipStream_t s2, int par, int64_t step);   // steps step, step + 1: parity par -> par ^ 1
     od_status upload_tiles();                      // tile descriptors (and two-step lines) to the device
     int64_t bytes_per_pass() const;
     od_status graph_run(int64_t n);

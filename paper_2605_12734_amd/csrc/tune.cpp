@@ -335,7 +335,7 @@ od_status autotune(Grid& G, int32_t iters, int32_t out_tile[3]) {
                                      reinterpret_cast<const BlockDev*>(G.cp(G.L.blocks)),
                                      reinterpret_cast<const TileDev*>(G.cp(G.L.tiles)),
                                      reinterpret_cast<const Tile2Dev*>(G.cp(G.L.tiles2)), (int32_t)G.tiles_h.size(),
-                                     G.parity, G.res_ptr(), 0, 1, G.mode());
+                                     G.parity, G.res_ptr(), 0, 1, G.mode(), ImbDev{}, 0);
             return launch_sweep(G.s, G.plan.tile[0], G.plan.tile[1], G.st, G.base,
                                 reinterpret_cast<const BlockDev*>(G.cp(G.L.blocks)),
                                 reinterpret_cast<const TileDev*>(G.cp(G.L.tiles)), (int32_t)G.tiles_h.size(),

@@ -1,5 +1,5 @@
 """Two Jacobi steps per pass (the fused, graph, persistent and message-driven
-forms' default where blocks are at one resolution and there is no imbalance):
+forms' default where blocks are at one resolution, also under load imbalance):
 the pass reads the field once, keeps the first step on chip and writes the
 second.  Every case is compared with the CPU oracle bit for bit (0 ULP),
 with odd and even iteration counts (an odd count ends with a single sweep),
@@ -155,16 +155,39 @@ def test_persistent_pairs_then_single_steps_resume():
 
 
 def test_not_used_where_unsupported():
-    # imbalance, a forced persistent schedule and the message-driven and
-    # per-chare forms keep one step per pass
-    for kw in ({"exec": "fused", "imbalance_pct": 10, "imbalance_max_extra": 2},
-               {"exec": "persistent", "hints": 2048},
-               {"exec": "msgdriven", "imbalance_pct": 10, "imbalance_max_extra": 2}, {"exec": "per_chare"}):
+    # a forced persistent schedule, the one-step hint and the per-chare form
+    # keep one step per pass
+    for kw in ({"exec": "persistent", "hints": 2048}, {"exec": "msgdriven", "hints": 4096},
+               {"exec": "per_chare"}):
         g = od.Grid(64, odf=8, dtype="f64", **kw)
         try:
             assert g.plan()["steps_per_pass"] == 1
         finally:
             g.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("exec_,hints", [("fused", 1), ("persistent", 1), ("persistent", 1 | 8192),
+                                         ("persistent", 1 | 16), ("msgdriven", 1), ("msgdriven", 1 | 4)])
+def test_pairs_under_imbalance(dtype, exec_, hints):
+    # half the chares drawn heavy each step, 1-3 extra runs: a heavy chare's
+    # extra one-step sweeps write its own cells of the pass's output parity
+    # before the pass overwrites them; 9 iterations (four passes and a single
+    # step), then 4 more (the draw continues at step 9)
+    n, odf, seed = (70, 45, 38), 27, 5
+    want, _, r_w = oracle.solve(n, DT[dtype], seed=seed, iters=13)
+    g = od.Grid(n, odf=odf, dtype=dtype, exec=exec_, seed=seed, hints=hints, imbalance_pct=50,
+                imbalance_max_extra=3)
+    try:
+        assert g.plan()["steps_per_pass"] == 2
+        g.iterate(9)
+        g.iterate(4)
+        U, r = g.read(), g.residual()
+        assert g.iterations() == 13
+    finally:
+        g.close()
+    _same(U, want)
+    assert r == r_w
 
 
 def test_bytes_per_pass_counts_two_step_reach():

@@ -272,14 +272,14 @@ def test_two_step_pass_bytes_brute_force(n, odf, dtype):
 @pytest.mark.parametrize("kw", [{"exec": "persistent", "hints": 2048}, {"exec": "persistent", "hints": 8},
                                 {"exec": "msgdriven", "hints": 4096}, {"exec": "msgdriven", "stencil": 5,
                                                                        "n": (64, 1, 64)},
-                                {"exec": "msgdriven", "imbalance_pct": 10, "imbalance_max_extra": 2},
                                 {"exec": "per_chare"},
                                 {"exec": "fused", "hints": 4096},
-                                {"exec": "fused", "imbalance_pct": 10, "imbalance_max_extra": 2},
+                                {"exec": "fused", "stencil": 5, "n": (64, 1, 64), "imbalance_pct": 10,
+                                 "imbalance_max_extra": 2},
                                 {"exec": "fused", "tile": (128, 4, 8)}])
 def test_two_step_only_where_supported(kw):
-    # other forms, the one-step hint, imbalance and tile shapes without a
-    # two-step variant keep one step per pass
+    # other forms, the one-step hint, the 2D stencil under imbalance and
+    # tile shapes without a two-step variant keep one step per pass
     kw = dict(kw)
     plan = od.host_plan(n=kw.pop("n", (64, 64, 64)), odf=8, dtype="f64", **kw)
     assert plan["steps_per_pass"] == 1
@@ -292,6 +292,18 @@ def test_two_step_only_where_supported(kw):
 def test_two_step_default_forms(exec_, hints):
     plan = od.host_plan(n=(64, 64, 64), odf=8, dtype="f64", exec=exec_, hints=hints)
     assert plan["steps_per_pass"] == 2
+
+
+@pytest.mark.parametrize("exec_,hints", [("fused", 0), ("persistent", 0), ("persistent", 8192),
+                                         ("persistent", 16), ("msgdriven", 0)])
+def test_two_step_under_imbalance(exec_, hints):
+    # a heavy chare's extra runs are one-step sweeps before its pass, so the
+    # 3D stencil pairs steps under load imbalance too; the bytes of a pass
+    # count the pair alone (the extra runs are the imbalance's cost)
+    kw = dict(n=(64, 64, 64), odf=8, dtype="f64", exec=exec_, hints=hints)
+    a = od.host_plan(**kw)
+    b = od.host_plan(**kw, imbalance_pct=10, imbalance_max_extra=4)
+    assert b["steps_per_pass"] == 2 and b["bytes_per_pass"] == a["bytes_per_pass"]
 
 
 def _two_step_boxes(o, e, n):
