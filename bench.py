@@ -98,21 +98,22 @@ def msg_tile(tile):
     return (tile[0], tile[1], min(tile[2], 32))
 
 
-def msgdriven_tile(n, odf, dtype, fused_tile, iters=20):
+def msgdriven_tile(n, odf, dtype, fused_tile, iters=20, shapes=((32, 16, 32), (32, 32, 32)), **kw):
     """The message-driven grid's tile: its dependency lists are built for
     the tiles it is created with, so instead of retiling one grid, short
     runs on grids of a few shapes (the fused grid's tuned tile with z <= 32,
-    and (32,16,32) / (32,32,32)) pick the fastest, outside any timed run."""
+    then `shapes`) pick the fastest, outside any timed run; `kw` are further
+    grid settings (the imbalance draw)."""
     import paper_2605_12734_amd as od
 
     cands = []
-    for t in (msg_tile(fused_tile), (32, 16, 32), (32, 32, 32)):
+    for t in (msg_tile(fused_tile),) + tuple(tuple(x) for x in shapes):
         if t not in cands:
             cands.append(t)
     best, best_s = cands[0], float("inf")
     for t in cands:
         try:
-            g = od.Grid(n, odf=odf, dtype=dtype, exec="msgdriven", tile=t, hints=1)
+            g = od.Grid(n, odf=odf, dtype=dtype, exec="msgdriven", tile=t, hints=1, **kw)
         except od.ODError:
             continue
         try:
@@ -338,14 +339,21 @@ def amr_leg(iters=500, multires_only=False):
 
 
 def imbalance_leg(iters=1000, odfs=(8, 64, 512, 4096, 32768)):
+    """Each form with its own tile: the fused autotuner's (the persistent
+    form takes the same), and for the message-driven form the fastest of
+    short runs under the same imbalance (msgdriven_tile over the fused tile,
+    its z <= 32 cut, (32,16,32) and (64,16,64))."""
     rows = []
+    imb = {"imbalance_pct": 10, "imbalance_max_extra": 4}
     for odf in odfs:
         row = {"odf": odf, "block": 1024 // round(odf ** (1 / 3))}
-        tile = None
+        tile = mtile = None
         for exec_ in ("fused", "persistent", "msgdriven"):
+            if exec_ == "msgdriven":
+                mtile = msgdriven_tile(1024, odf, "f64", tile, iters=40,
+                                       shapes=(tuple(tile), (32, 16, 32), (64, 16, 64)), **imb)
             g = make_grid(1024, odf=odf, dtype="f64", exec_=exec_,
-                          tile=msg_tile(tile) if tile and exec_ == "msgdriven" else tile, imbalance_pct=10,
-                          imbalance_max_extra=4)
+                          tile=mtile if exec_ == "msgdriven" else tile, **imb)
             try:
                 tile = tile or g.plan()["tile"]
                 plan = g.plan()
@@ -355,7 +363,7 @@ def imbalance_leg(iters=1000, odfs=(8, 64, 512, 4096, 32768)):
             row[exec_ + "_glups"] = round(plan["interior"] * iters / t["wall_s"] / 1e9, 2)
             row[exec_ + "_s"] = round(t["wall_s"], 3)
         row["tile_bsp"] = list(tile)
-        row["tile_msgdriven"] = list(msg_tile(tile))
+        row["tile_msgdriven"] = list(mtile)
         row["msgdriven_vs_bsp_launches"] = round(row["msgdriven_glups"] / row["fused_glups"], 3)
         row["msgdriven_vs_bsp_barrier"] = round(row["msgdriven_glups"] / row["persistent_glups"], 3)
         log("imbalance:", row)
