@@ -98,16 +98,18 @@ def msg_tile(tile):
     return (tile[0], tile[1], min(tile[2], 32))
 
 
-def msgdriven_tile(n, odf, dtype, fused_tile, iters=20, shapes=((32, 16, 32), (32, 32, 32)), **kw):
+def msgdriven_tile(n, odf, dtype, fused_tile, iters=20,
+                   shapes=((32, 16, 32), (32, 32, 32), (64, 16, 64), (32, 32, 64)), **kw):
     """The message-driven grid's tile: its dependency lists are built for
     the tiles it is created with, so instead of retiling one grid, short
     runs on grids of a few shapes (the fused grid's tuned tile with z <= 32,
-    then `shapes`) pick the fastest, outside any timed run; `kw` are further
-    grid settings (the imbalance draw)."""
+    the tuned tile itself, then `shapes`) pick the fastest, outside any
+    timed run; `kw` are further grid settings (the imbalance draw).  Tasks
+    of two steps favour deeper tiles than tasks of one step did."""
     import paper_2605_12734_amd as od
 
     cands = []
-    for t in (msg_tile(fused_tile),) + tuple(tuple(x) for x in shapes):
+    for t in (msg_tile(fused_tile), tuple(fused_tile)) + tuple(tuple(x) for x in shapes):
         if t not in cands:
             cands.append(t)
     best, best_s = cands[0], float("inf")
@@ -350,8 +352,7 @@ def imbalance_leg(iters=1000, odfs=(8, 64, 512, 4096, 32768)):
         tile = mtile = None
         for exec_ in ("fused", "persistent", "msgdriven"):
             if exec_ == "msgdriven":
-                mtile = msgdriven_tile(1024, odf, "f64", tile, iters=40,
-                                       shapes=(tuple(tile), (32, 16, 32), (64, 16, 64)), **imb)
+                mtile = msgdriven_tile(1024, odf, "f64", tile, iters=40, shapes=((32, 16, 32), (64, 16, 64)), **imb)
             g = make_grid(1024, odf=odf, dtype="f64", exec_=exec_,
                           tile=mtile if exec_ == "msgdriven" else tile, **imb)
             try:
