@@ -111,7 +111,9 @@ typedef struct {
      * taken first in a pseudo-random order of chare ids drawn from
      * (seed, t), each re-run count drawn from SplitMix64 at (seed, t,
      * chare); od_extra_sweeps reports the draw.  A re-run recomputes the
-     * same values, so results do not change, only the time.  0 = off. */
+     * same values, so results do not change, only the time.  Where steps
+     * run in pairs, a chare re-runs extra(t) + extra(t + 1) one-step sweeps
+     * before the pass of steps t and t + 1.  0 = off. */
     int32_t imbalance_pct;
     int32_t imbalance_max_extra;
     /* Implementation hints, 0 = defaults; none of them changes a result.
